@@ -1,0 +1,253 @@
+"""FP64 CPU oracle (test infrastructure only).
+
+Thin ctypes wrapper over ``vls_oracle.c``.  Only the tests, the smoke check
+and the benchmark's CPU-baseline leg may import this package; the GPU library
+never does.  See ``vls_oracle.c`` for what is computed and the readings of
+the paper it takes.
+"""
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "vls_oracle.c")
+LIB = os.path.join(HERE, "libvls_oracle.so")
+
+C_M_PER_NS = 0.299792458
+PULSE_GAUSSIAN = 0
+PULSE_EQ3 = 1
+
+
+def build(force=True):
+    """Compile the oracle with gcc (OpenMP)."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class OrcScanner(ctypes.Structure):
+    _fields_ = [("divergence_rad", ctypes.c_double), ("pattern_extent", ctypes.c_double),
+                ("pulse_width_ns", ctypes.c_double), ("bin_ns", ctypes.c_double),
+                ("window_pre_ns", ctypes.c_double), ("peak_power_w", ctypes.c_double),
+                ("receiver_diameter_m", ctypes.c_double), ("efficiency", ctypes.c_double),
+                ("min_echo_abs", ctypes.c_double), ("min_echo_rel", ctypes.c_double),
+                ("n_subrays", ctypes.c_int32), ("beam_quality", ctypes.c_int32),
+                ("pulse_shape", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("max_returns", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        L.orc_ring_layout.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int]
+        L.orc_pattern_size.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_pattern.argtypes = [P, P, P, P, ctypes.c_int]
+        L.orc_subray_direction.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
+        L.orc_ray_triangle.argtypes = [P] * 8
+        L.orc_closest_hit.argtypes = [P, P, P, P, i64, P, P, P]
+        L.orc_closest_hit.restype = i64
+        L.orc_pulse_value.argtypes = [P, ctypes.c_double]
+        L.orc_pulse_value.restype = ctypes.c_double
+        L.orc_pulse_derivative.argtypes = [P, ctypes.c_double]
+        L.orc_pulse_derivative.restype = ctypes.c_double
+        L.orc_window_pre.argtypes = [P]
+        L.orc_window_pre.restype = ctypes.c_double
+        L.orc_peak_offset.argtypes = [P]
+        L.orc_peak_offset.restype = ctypes.c_double
+        L.orc_detect_peaks.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, P]
+        L.orc_attribute.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_double]
+        L.orc_simulate.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, i64, P] + [P] * 6 + [P] * 7 + [ctypes.c_int]
+        L.orc_gradient.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, P, P, P, ctypes.c_int]
+        L.orc_max_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def scanner_struct(sc):
+    """Plain scanner dict (see synth.configs.scanner) -> OrcScanner."""
+    shape = sc.get("pulse_shape", "gaussian")
+    return OrcScanner(divergence_rad=sc["divergence_rad"], pattern_extent=sc.get("pattern_extent", 1.0),
+                      pulse_width_ns=sc["pulse_width_ns"], bin_ns=sc["bin_ns"],
+                      window_pre_ns=sc.get("window_pre_ns", -1.0), peak_power_w=sc.get("peak_power_w", 1.0),
+                      receiver_diameter_m=sc.get("receiver_diameter_m", 1.0), efficiency=sc.get("efficiency", 1.0),
+                      min_echo_abs=sc.get("min_echo_abs", 0.0), min_echo_rel=sc.get("min_echo_rel", 1e-3),
+                      n_subrays=sc.get("n_subrays", 0), beam_quality=sc.get("beam_quality", 0),
+                      pulse_shape=PULSE_EQ3 if shape in ("eq3", PULSE_EQ3) else PULSE_GAUSSIAN,
+                      n_bins=sc["n_bins"], max_returns=sc.get("max_returns", 8), pad_=0)
+
+
+def ring_layout(n_subrays=0, beam_quality=0):
+    rc = np.zeros(256, np.int32)
+    n = lib().orc_ring_layout(n_subrays, beam_quality, _ptr(rc), 256)
+    if n < 0:
+        raise ValueError("bad pattern request")
+    return rc[:n].copy()
+
+
+def pattern_size(n_subrays=0, beam_quality=0):
+    return int(lib().orc_pattern_size(n_subrays, beam_quality))
+
+
+def pattern(sc):
+    """-> (alpha, phi, weight) float64 arrays of length S."""
+    st = scanner_struct(sc)
+    a = np.zeros(4096)
+    p = np.zeros(4096)
+    w = np.zeros(4096)
+    s = lib().orc_pattern(ctypes.byref(st), _ptr(a), _ptr(p), _ptr(w), 4096)
+    if s < 0:
+        raise ValueError("bad pattern request")
+    return a[:s].copy(), p[:s].copy(), w[:s].copy()
+
+
+def subray_directions(d, sc):
+    a, p, _ = pattern(sc)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.zeros((a.size, 3))
+    for k in range(a.size):
+        o = np.zeros(3)
+        lib().orc_subray_direction(_ptr(d), float(a[k]), float(p[k]), _ptr(o))
+        out[k] = o
+    return out
+
+
+def ray_triangle(O, d, a, b, c):
+    args = [np.ascontiguousarray(x, dtype=np.float64) for x in (O, d, a, b, c)]
+    t = np.zeros(1)
+    u = np.zeros(1)
+    v = np.zeros(1)
+    hit = lib().orc_ray_triangle(*[_ptr(x) for x in args], _ptr(t), _ptr(u), _ptr(v))
+    return bool(hit), float(t[0]), float(u[0]), float(v[0])
+
+
+def closest_hit(O, d, mesh):
+    O = np.ascontiguousarray(O, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    t = np.zeros(1)
+    u = np.zeros(1)
+    v = np.zeros(1)
+    h = lib().orc_closest_hit(_ptr(O), _ptr(d), _ptr(mesh.vertices), _ptr(mesh.triangles),
+                              mesh.n_triangles, _ptr(t), _ptr(u), _ptr(v))
+    return int(h), float(t[0]), float(u[0]), float(v[0])
+
+
+def pulse_value(sc, s):
+    st = scanner_struct(sc)
+    return float(lib().orc_pulse_value(ctypes.byref(st), float(s)))
+
+
+def pulse_derivative(sc, s):
+    st = scanner_struct(sc)
+    return float(lib().orc_pulse_derivative(ctypes.byref(st), float(s)))
+
+
+def window_pre(sc):
+    st = scanner_struct(sc)
+    return float(lib().orc_window_pre(ctypes.byref(st)))
+
+
+def peak_offset(sc):
+    st = scanner_struct(sc)
+    return float(lib().orc_peak_offset(ctypes.byref(st)))
+
+
+def detect_peaks(wf, thr_abs=0.0, thr_rel=1e-3, K=8):
+    wf = np.ascontiguousarray(wf, dtype=np.float64)
+    bins = np.zeros(64, np.int32)
+    n = lib().orc_detect_peaks(_ptr(wf), wf.size, float(thr_abs), float(thr_rel), int(K), _ptr(bins))
+    return bins[:n].copy()
+
+
+def attribute(sc, tri, R, P, tj):
+    """Index of the subray contributing most at time tj (ties: lowest index)."""
+    st = scanner_struct(sc)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    return int(lib().orc_attribute(ctypes.byref(st), _ptr(tri), _ptr(R), _ptr(P), tri.size, float(tj)))
+
+
+@dataclass
+class OracleResult:
+    sub_tri: np.ndarray
+    sub_range: np.ndarray
+    sub_cos: np.ndarray
+    sub_power: np.ndarray
+    sub_u: np.ndarray
+    sub_v: np.ndarray
+    waveform: np.ndarray
+    t0: np.ndarray
+    n_returns: np.ndarray
+    ret_range: np.ndarray
+    ret_amp: np.ndarray
+    ret_tri: np.ndarray
+    ret_bin: np.ndarray
+    S: int
+
+
+def simulate(mesh, pulses, sc, select=None, t0=None, threads=0, waveform=True):
+    """Forward over all pulses, or over the pulse indices in ``select``."""
+    mesh.checked()
+    st = scanner_struct(sc)
+    S = pattern_size(st.n_subrays, st.beam_quality)
+    if S <= 0:
+        raise ValueError("bad pattern request")
+    sel = None if select is None else np.ascontiguousarray(select, dtype=np.int64)
+    n = pulses.n if sel is None else sel.size
+    nb, K = st.n_bins, st.max_returns
+    r = OracleResult(np.zeros((n, S), np.int32), np.zeros((n, S)), np.zeros((n, S)), np.zeros((n, S)),
+                     np.zeros((n, S)), np.zeros((n, S)),
+                     np.zeros((n, nb)) if waveform else None, np.zeros(n), np.zeros(n, np.int32),
+                     np.zeros((n, K)), np.zeros((n, K)), np.zeros((n, K), np.int32), np.zeros((n, K), np.int32), S)
+    t0a = None if t0 is None else np.ascontiguousarray(t0, dtype=np.float64)
+    o = np.ascontiguousarray(pulses.origins, dtype=np.float64)
+    d = np.ascontiguousarray(pulses.directions, dtype=np.float32)
+    got = lib().orc_simulate(_ptr(mesh.vertices), mesh.n_vertices, _ptr(mesh.triangles), _ptr(mesh.reflectance),
+                             mesh.n_triangles, ctypes.byref(st), _ptr(o), _ptr(d), pulses.n,
+                             _ptr(sel), n, _ptr(t0a),
+                             _ptr(r.sub_tri), _ptr(r.sub_range), _ptr(r.sub_cos), _ptr(r.sub_power),
+                             _ptr(r.sub_u), _ptr(r.sub_v),
+                             _ptr(r.waveform), _ptr(r.t0), _ptr(r.n_returns), _ptr(r.ret_range), _ptr(r.ret_amp),
+                             _ptr(r.ret_tri), _ptr(r.ret_bin), int(threads))
+    if got != S:
+        raise RuntimeError("oracle simulate failed")
+    return r
+
+
+def gradient(mesh, pulses, sc, t0, grad_wf, threads=0):
+    """(grad_reflectance [T], grad_z [V]) of L with dL/dwf = grad_wf at fixed t0."""
+    st = scanner_struct(sc)
+    gr = np.zeros(mesh.n_triangles)
+    gz = np.zeros(mesh.n_vertices)
+    o = np.ascontiguousarray(pulses.origins, dtype=np.float64)
+    d = np.ascontiguousarray(pulses.directions, dtype=np.float32)
+    t0 = np.ascontiguousarray(t0, dtype=np.float64)
+    G = np.ascontiguousarray(grad_wf, dtype=np.float64)
+    got = lib().orc_gradient(_ptr(mesh.vertices), mesh.n_vertices, _ptr(mesh.triangles), _ptr(mesh.reflectance),
+                             mesh.n_triangles, ctypes.byref(st), _ptr(o), _ptr(d), pulses.n, _ptr(t0), _ptr(G),
+                             _ptr(gr), _ptr(gz), int(threads))
+    if got < 0:
+        raise RuntimeError("oracle gradient failed")
+    return gr, gz
+
+
+def max_threads():
+    return int(lib().orc_max_threads())

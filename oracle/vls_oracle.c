@@ -1,0 +1,540 @@
+/*
+ * FP64 CPU oracle for the virtual-laser-scanning hot path of HELIOS++
+ * (Winiwarter et al., "Virtual laser scanning with HELIOS++", arXiv 2101.09154).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file: it exists so that tests, the smoke check and the CPU
+ * baseline of the benchmark can check the GPU library against a plain,
+ * obviously correct definition.  It shares no code with the GPU library.
+ *
+ * What it computes, per pulse (origin O, direction d):
+ *   1. the subray pattern of the beam (Sec. 3.4: concentric rings, floor(2*pi*i)
+ *      subrays on ring i plus a central subray) with Gaussian beam weights
+ *      (Sec. 3.4, Eq. 1; far-field reading of Eq. 2);
+ *   2. each subray's closest hit by brute force over every triangle
+ *      (Sec. 3.4: a hit ends the subray; Sec. 5.1: minimum-distance
+ *      intersection) with the Moller-Trumbore (1997) test in FP64;
+ *   3. per-subray return power from the laser radar equation (Sec. 5.2, Eq. 7)
+ *      with a Lambertian extended-target cross-section;
+ *   4. the full waveform: the sum of the subrays' pulse shapes shifted by
+ *      their two-way travel times (Sec. 3.4, Eq. 3 or a Gaussian pulse),
+ *      sampled at the bin centres of a window that starts t_pre before the
+ *      first return;
+ *   5. local maxima of the summed waveform as discrete returns (Sec. 3.4);
+ *   6. the analytic gradient of a waveform loss with respect to per-triangle
+ *      reflectance and vertex heights (hit selection held fixed).
+ * Everything is FP64 with no truncation of the pulse support.
+ *
+ * Readings where the paper is silent or garbled:
+ *   - n_subrays that is not 1 + sum floor(2*pi*i): fill rings in order, the
+ *     last ring takes the remainder, evenly spaced;
+ *   - ring i of N sits at angle (i/N) * kappa * divergence/2 (divergence is
+ *     the full 1/e^2 angle); azimuths 2*pi*m/n_i, no per-ring offset;
+ *   - Eq. 2, far field: the beam radius at range R is R*tan(divergence/2), so
+ *     a subray at angle a has r/w = tan(a)/tan(divergence/2); weights are
+ *     normalised to sum 1;
+ *   - Eq. 7 with sigma = pi*rho*cos(theta)*R^2*beta^2 gives
+ *     P = P0 * w * (eta * D^2 / 4) * rho * cos(theta) / R^2, cos(theta) = |d.n|;
+ *   - two-way time tau = 2R/c; the window origin t0 = min tau - t_pre is not
+ *     snapped to a bin grid; bin j samples t0 + j*bin;
+ *   - a return is a bin j in [1, n-2] with wf[j] > wf[j-1], wf[j] >= wf[j+1]
+ *     and wf[j] >= max(thr_abs, thr_rel * max wf); the first K in time order;
+ *     its range is (c/2)(t0 + j*bin - s_peak) where s_peak is the pulse's own
+ *     peak offset; it is attributed to the subray contributing most at j
+ *     (ties: lowest subray index);
+ *   - equal hit distances go to the lowest triangle index; edges are
+ *     inclusive; only t > 0 counts.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_C_M_PER_NS 0.299792458 /* speed of light, Sec. 3.4: 299,792,458 m/s */
+#define ORC_PI 3.14159265358979323846
+
+enum { ORC_PULSE_GAUSSIAN = 0, ORC_PULSE_EQ3 = 1 };
+
+typedef struct {
+    double divergence_rad;      /* full angle at the 1/e^2 points */
+    double pattern_extent;      /* kappa: outer ring at kappa * divergence / 2 */
+    double pulse_width_ns;      /* Gaussian FWHM, or Eq. 3 pulse length (tau = L / 1.75) */
+    double bin_ns;
+    double window_pre_ns;       /* < 0: automatic (6 sigma for the Gaussian, 0 for Eq. 3) */
+    double peak_power_w;
+    double receiver_diameter_m;
+    double efficiency;
+    double min_echo_abs;
+    double min_echo_rel;
+    int32_t n_subrays;          /* > 0: ring-fill to this count */
+    int32_t beam_quality;       /* used when n_subrays == 0: rings 1..quality */
+    int32_t pulse_shape;
+    int32_t n_bins;
+    int32_t max_returns;
+    int32_t pad_;
+} orc_scanner;
+
+/* ------------------------------------------------------------------ pattern (Sec. 3.4, Fig. 6) */
+
+static int ring_capacity(int i) { return (int)floor(2.0 * ORC_PI * (double)i); }
+
+/* Number of subrays on each ring; returns the ring count N (0 for a single ray). */
+int orc_ring_layout(int n_subrays, int beam_quality, int32_t* ring_count, int max_rings)
+{
+    int n = 0;
+    if (n_subrays <= 0) {
+        if (beam_quality < 0) return -1;
+        for (int i = 1; i <= beam_quality; ++i) {
+            if (n >= max_rings) return -1;
+            ring_count[n++] = ring_capacity(i);
+        }
+        return n;
+    }
+    int left = n_subrays - 1;
+    for (int i = 1; left > 0; ++i) {
+        int m = ring_capacity(i);
+        if (m > left) m = left;
+        if (n >= max_rings) return -1;
+        ring_count[n++] = m;
+        left -= m;
+    }
+    return n;
+}
+
+int orc_pattern_size(int n_subrays, int beam_quality)
+{
+    int32_t rc[256];
+    int nr = orc_ring_layout(n_subrays, beam_quality, rc, 256);
+    if (nr < 0) return -1;
+    int s = 1;
+    for (int i = 0; i < nr; ++i) s += rc[i];
+    return s;
+}
+
+/* Subray k: angle from the beam axis alpha[k], azimuth phi[k], weight[k] (sum 1).
+ * Order: the central subray, then ring 1, ring 2, ...  Returns S, or -1. */
+int orc_pattern(const orc_scanner* sc, double* alpha, double* phi, double* weight, int cap)
+{
+    int32_t rc[256];
+    int nr = orc_ring_layout(sc->n_subrays, sc->beam_quality, rc, 256);
+    if (nr < 0) return -1;
+    int s = 1;
+    for (int i = 0; i < nr; ++i) s += rc[i];
+    if (s > cap) return -1;
+    double half = 0.5 * sc->divergence_rad;
+    double amax = sc->pattern_extent * half;
+    int k = 0;
+    alpha[k] = 0.0; phi[k] = 0.0; ++k;
+    for (int i = 1; i <= nr; ++i) {
+        int m = rc[i - 1];
+        for (int q = 0; q < m; ++q) {
+            alpha[k] = ((double)i / (double)nr) * amax;
+            phi[k] = 2.0 * ORC_PI * (double)q / (double)m;
+            ++k;
+        }
+    }
+    /* Eq. 1, I = I0 exp(-2 r^2 / w^2), with r/w = tan(alpha)/tan(divergence/2) */
+    double th = tan(half), sum = 0.0;
+    for (k = 0; k < s; ++k) {
+        double x = (th > 0.0) ? tan(alpha[k]) / th : 0.0;
+        weight[k] = exp(-2.0 * x * x);
+        sum += weight[k];
+    }
+    for (k = 0; k < s; ++k) weight[k] /= sum;
+    return s;
+}
+
+/* ------------------------------------------------------------------ subray directions */
+
+/* Orthonormal basis (u, v) perpendicular to unit n: Duff et al. 2017, "Building
+ * an orthonormal basis, revisited". */
+static void onb(const double n[3], double u[3], double v[3])
+{
+    double sgn = copysign(1.0, n[2]);
+    double a = -1.0 / (sgn + n[2]);
+    double b = n[0] * n[1] * a;
+    u[0] = 1.0 + sgn * n[0] * n[0] * a; u[1] = sgn * b; u[2] = -sgn * n[0];
+    v[0] = b; v[1] = sgn + n[1] * n[1] * a; v[2] = -n[1];
+}
+
+/* Direction of one subray: cos(a) d + sin(a) (cos(phi) u + sin(phi) v), d normalised first. */
+void orc_subray_direction(const double d_in[3], double alpha, double phi, double out[3])
+{
+    double len = sqrt(d_in[0] * d_in[0] + d_in[1] * d_in[1] + d_in[2] * d_in[2]);
+    double d[3] = { d_in[0] / len, d_in[1] / len, d_in[2] / len };
+    double u[3], v[3];
+    onb(d, u, v);
+    double ca = cos(alpha), sa = sin(alpha), cp = cos(phi), sp = sin(phi);
+    for (int i = 0; i < 3; ++i) out[i] = ca * d[i] + sa * (cp * u[i] + sp * v[i]);
+}
+
+/* ------------------------------------------------------------------ closest hit (Sec. 3.4, 5.1) */
+
+static void vload(const float* verts, int32_t idx, double out[3])
+{
+    out[0] = (double)verts[3 * (int64_t)idx + 0];
+    out[1] = (double)verts[3 * (int64_t)idx + 1];
+    out[2] = (double)verts[3 * (int64_t)idx + 2];
+}
+
+static void cross3(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Moller & Trumbore 1997, two-sided, inclusive edges.  1 on a hit with t > 0. */
+int orc_ray_triangle(const double O[3], const double d[3], const double a[3], const double b[3],
+                     const double c[3], double* t, double* u, double* v)
+{
+    double e1[3] = { b[0] - a[0], b[1] - a[1], b[2] - a[2] };
+    double e2[3] = { c[0] - a[0], c[1] - a[1], c[2] - a[2] };
+    double p[3];
+    cross3(d, e2, p);
+    double det = dot3(e1, p);
+    if (det == 0.0) return 0;
+    double inv = 1.0 / det;
+    double s[3] = { O[0] - a[0], O[1] - a[1], O[2] - a[2] };
+    double uu = dot3(s, p) * inv;
+    if (uu < 0.0 || uu > 1.0) return 0;
+    double q[3];
+    cross3(s, e1, q);
+    double vv = dot3(d, q) * inv;
+    if (vv < 0.0 || uu + vv > 1.0) return 0;
+    double tt = dot3(e2, q) * inv;
+    if (!(tt > 0.0)) return 0;
+    *t = tt; *u = uu; *v = vv;
+    return 1;
+}
+
+/* Closest hit over all triangles; ties on equal t go to the lowest index.  -1 = miss. */
+int64_t orc_closest_hit(const double O[3], const double d[3], const float* verts, const int32_t* tris,
+                        int64_t n_tri, double* t_out, double* u_out, double* v_out)
+{
+    int64_t best = -1;
+    double bt = INFINITY, bu = 0.0, bv = 0.0;
+    for (int64_t i = 0; i < n_tri; ++i) {
+        double a[3], b[3], c[3], t, u, v;
+        vload(verts, tris[3 * i + 0], a);
+        vload(verts, tris[3 * i + 1], b);
+        vload(verts, tris[3 * i + 2], c);
+        if (orc_ray_triangle(O, d, a, b, c, &t, &u, &v) && t < bt) {
+            best = i; bt = t; bu = u; bv = v;
+        }
+    }
+    *t_out = bt; *u_out = bu; *v_out = bv;
+    return best;
+}
+
+/* ------------------------------------------------------------------ pulse shape (Sec. 3.4, Eq. 3) */
+
+static double gauss_sigma(const orc_scanner* sc) { return sc->pulse_width_ns / (2.0 * sqrt(2.0 * log(2.0))); }
+static double eq3_tau(const orc_scanner* sc) { return sc->pulse_width_ns / 1.75; }
+
+/* Outgoing pulse at time offset s (ns): unit-peak Gaussian, or (s/tau)^2 exp(-s/tau). */
+double orc_pulse_value(const orc_scanner* sc, double s)
+{
+    if (sc->pulse_shape == ORC_PULSE_EQ3) {
+        double tau = eq3_tau(sc);
+        if (s <= 0.0) return 0.0;
+        double x = s / tau;
+        return x * x * exp(-x);
+    }
+    double sg = gauss_sigma(sc);
+    return exp(-s * s / (2.0 * sg * sg));
+}
+
+/* d/ds of the pulse */
+double orc_pulse_derivative(const orc_scanner* sc, double s)
+{
+    if (sc->pulse_shape == ORC_PULSE_EQ3) {
+        double tau = eq3_tau(sc);
+        if (s <= 0.0) return 0.0;
+        double x = s / tau;
+        return (2.0 * x - x * x) * exp(-x) / tau;
+    }
+    double sg = gauss_sigma(sc);
+    return -s / (sg * sg) * exp(-s * s / (2.0 * sg * sg));
+}
+
+double orc_window_pre(const orc_scanner* sc)
+{
+    if (sc->window_pre_ns >= 0.0) return sc->window_pre_ns;
+    return sc->pulse_shape == ORC_PULSE_EQ3 ? 0.0 : 6.0 * gauss_sigma(sc);
+}
+
+double orc_peak_offset(const orc_scanner* sc) { return sc->pulse_shape == ORC_PULSE_EQ3 ? 2.0 * eq3_tau(sc) : 0.0; }
+
+/* ------------------------------------------------------------------ returns (Sec. 3.4) */
+
+int orc_detect_peaks(const double* wf, int n, double thr_abs, double thr_rel, int K, int32_t* bins)
+{
+    double mx = 0.0;
+    for (int j = 0; j < n; ++j) if (wf[j] > mx) mx = wf[j];
+    double thr = thr_rel * mx;
+    if (thr_abs > thr) thr = thr_abs;
+    int cnt = 0;
+    for (int j = 1; j + 1 < n && cnt < K; ++j)
+        if (wf[j] > wf[j - 1] && wf[j] >= wf[j + 1] && wf[j] >= thr) bins[cnt++] = j;
+    return cnt;
+}
+
+/* The subray that contributes most to the waveform at time tj (the return's
+ * source, Fig. 4 caption: returns are traceable to objects); ties go to the
+ * lowest subray index.  -1 if no subray hit. */
+int orc_attribute(const orc_scanner* sc, const int32_t* tri, const double* R, const double* P, int S, double tj)
+{
+    double best = -1.0;
+    int bk = -1;
+    for (int k = 0; k < S; ++k) {
+        if (tri[k] < 0) continue;
+        double q = P[k] * orc_pulse_value(sc, tj - 2.0 * R[k] / ORC_C_M_PER_NS);
+        if (q > best) { best = q; bk = k; }
+    }
+    return bk;
+}
+
+/* ------------------------------------------------------------------ one pulse */
+
+static double power_const(const orc_scanner* sc)
+{
+    return sc->peak_power_w * sc->efficiency * sc->receiver_diameter_m * sc->receiver_diameter_m / 4.0;
+}
+
+typedef struct {
+    const float* verts; const int32_t* tris; const float* refl; int64_t n_tri;
+    const orc_scanner* sc; int S; const double* alpha; const double* phi; const double* w;
+} orc_ctx;
+
+/* Trace and shade the S subrays of one pulse. */
+static void trace_pulse(const orc_ctx* c, const double O[3], const float d32[3],
+                        int32_t* tri, double* R, double* cosang, double* P, double* U, double* V)
+{
+    double d[3] = { d32[0], d32[1], d32[2] };
+    double C = power_const(c->sc);
+    for (int k = 0; k < c->S; ++k) {
+        double dk[3], t, u, v;
+        orc_subray_direction(d, c->alpha[k], c->phi[k], dk);
+        int64_t h = orc_closest_hit(O, dk, c->verts, c->tris, c->n_tri, &t, &u, &v);
+        tri[k] = (int32_t)h;
+        if (h < 0) { R[k] = INFINITY; cosang[k] = 0.0; P[k] = 0.0; U[k] = V[k] = 0.0; continue; }
+        double a[3], b[3], cc[3], e1[3], e2[3], n[3];
+        vload(c->verts, c->tris[3 * h + 0], a);
+        vload(c->verts, c->tris[3 * h + 1], b);
+        vload(c->verts, c->tris[3 * h + 2], cc);
+        for (int i = 0; i < 3; ++i) { e1[i] = b[i] - a[i]; e2[i] = cc[i] - a[i]; }
+        cross3(e1, e2, n);
+        double ct = fabs(dot3(dk, n)) / sqrt(dot3(n, n));
+        R[k] = t; cosang[k] = ct; U[k] = u; V[k] = v;
+        /* Eq. 7 with a Lambertian extended-target cross-section */
+        P[k] = C * c->w[k] * (double)c->refl[h] * ct / (t * t);
+    }
+}
+
+/* Waveform + returns for one pulse from its traced subrays. */
+static void waveform_pulse(const orc_ctx* c, const int32_t* tri, const double* R, const double* P,
+                           const double* t0_in, double* wf, double* t0_out, int32_t* n_ret,
+                           double* ret_range, double* ret_amp, int32_t* ret_tri, int32_t* ret_bin)
+{
+    const orc_scanner* sc = c->sc;
+    int nb = sc->n_bins, K = sc->max_returns;
+    double tmin = INFINITY;
+    int any = 0;
+    for (int k = 0; k < c->S; ++k)
+        if (tri[k] >= 0) { any = 1; double tau = 2.0 * R[k] / ORC_C_M_PER_NS; if (tau < tmin) tmin = tau; }
+    double t0 = t0_in ? *t0_in : (any ? tmin - orc_window_pre(sc) : NAN);
+    *t0_out = t0;
+    for (int j = 0; j < nb; ++j) wf[j] = 0.0;
+    for (int r = 0; r < K; ++r) { ret_range[r] = 0.0; ret_amp[r] = 0.0; ret_tri[r] = -1; ret_bin[r] = -1; }
+    *n_ret = 0;
+    if (!any || isnan(t0)) return;
+    for (int j = 0; j < nb; ++j) {
+        double tj = t0 + (double)j * sc->bin_ns, acc = 0.0;
+        for (int k = 0; k < c->S; ++k)
+            if (tri[k] >= 0) acc += P[k] * orc_pulse_value(sc, tj - 2.0 * R[k] / ORC_C_M_PER_NS);
+        wf[j] = acc;
+    }
+    int32_t bins[64];
+    int cnt = orc_detect_peaks(wf, nb, sc->min_echo_abs, sc->min_echo_rel, K, bins);
+    *n_ret = cnt;
+    for (int r = 0; r < cnt; ++r) {
+        int j = bins[r];
+        double tj = t0 + (double)j * sc->bin_ns;
+        int bk = orc_attribute(sc, tri, R, P, c->S, tj);
+        ret_bin[r] = j;
+        ret_amp[r] = wf[j];
+        ret_range[r] = 0.5 * ORC_C_M_PER_NS * (tj - orc_peak_offset(sc));
+        ret_tri[r] = bk >= 0 ? tri[bk] : -1;
+    }
+}
+
+static int make_ctx(orc_ctx* c, const float* verts, const int32_t* tris, const float* refl, int64_t n_tri,
+                    const orc_scanner* sc, double* alpha, double* phi, double* w)
+{
+    c->verts = verts; c->tris = tris; c->refl = refl; c->n_tri = n_tri; c->sc = sc;
+    c->alpha = alpha; c->phi = phi; c->w = w;
+    c->S = orc_pattern(sc, alpha, phi, w, 4096);
+    if (c->S <= 0 || sc->n_bins < 3 || sc->max_returns < 1 || sc->max_returns > 64 || !(sc->bin_ns > 0.0)) return -1;
+    return 0;
+}
+
+/* Full forward over a selection of pulses (sel == NULL: all).  Output q belongs
+ * to pulse sel[q].  Per-subray arrays are [n_sel][S]; waveform [n_sel][n_bins];
+ * returns [n_sel][K].  t0_in (indexed by pulse, may be NULL) fixes the window
+ * origins.  Any per-subray output may be NULL.  Returns S, or -1. */
+int orc_simulate(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
+                 const orc_scanner* sc, const double* origins, const float* dirs, int64_t n_pulses,
+                 const int64_t* sel, int64_t n_sel, const double* t0_in,
+                 int32_t* sub_tri, double* sub_range, double* sub_cos, double* sub_power,
+                 double* sub_u, double* sub_v,
+                 double* wf, double* t0_out, int32_t* n_ret, double* ret_range, double* ret_amp,
+                 int32_t* ret_tri, int32_t* ret_bin, int n_threads)
+{
+    (void)n_vert;
+    double alpha[4096], phi[4096], w[4096];
+    orc_ctx c;
+    if (make_ctx(&c, verts, tris, refl, n_tri, sc, alpha, phi, w) < 0) return -1;
+    int S = c.S, nb = sc->n_bins, K = sc->max_returns;
+    int64_t n = sel ? n_sel : n_pulses;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel
+    {
+        int32_t* tri = (int32_t*)malloc(sizeof(int32_t) * S);
+        double* R = (double*)malloc(sizeof(double) * S * 5);
+        double *cs = R + S, *P = R + 2 * S, *U = R + 3 * S, *V = R + 4 * S;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < n; ++q) {
+            int64_t p = sel ? sel[q] : q;
+            trace_pulse(&c, origins + 3 * p, dirs + 3 * p, tri, R, cs, P, U, V);
+            for (int k = 0; k < S; ++k) {
+                if (sub_tri) sub_tri[q * S + k] = tri[k];
+                if (sub_range) sub_range[q * S + k] = R[k];
+                if (sub_cos) sub_cos[q * S + k] = cs[k];
+                if (sub_power) sub_power[q * S + k] = P[k];
+                if (sub_u) sub_u[q * S + k] = U[k];
+                if (sub_v) sub_v[q * S + k] = V[k];
+            }
+            if (wf) {
+                waveform_pulse(&c, tri, R, P, t0_in ? t0_in + p : NULL, wf + q * nb, t0_out + q, n_ret + q,
+                               ret_range + q * K, ret_amp + q * K, ret_tri + q * K, ret_bin + q * K);
+            }
+        }
+        free(tri);
+        free(R);
+    }
+    return S;
+}
+
+/* ------------------------------------------------------------------ gradient */
+
+/* Gradient of L(wf) for wf computed with fixed window origins t0[p], given
+ * G = dL/dwf [n_pulses][n_bins], with respect to reflectance [n_tri] and
+ * vertex heights z [n_vert].  Hit selection is recomputed by brute force at
+ * the current geometry and then held fixed.  Chain: P = C w rho cos/R^2,
+ * tau = 2R/c, R = n.(a-O)/(n.d) so dR/dv_i = b_i n/(n.d) (b_i = barycentric
+ * weight of vertex i at the hit), cos = |n.d|/|n|.  Accumulated per thread in
+ * thread order (deterministic for a fixed thread count). */
+int orc_gradient(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
+                 const orc_scanner* sc, const double* origins, const float* dirs, int64_t n_pulses,
+                 const double* t0, const double* grad_wf, double* grad_refl, double* grad_z, int n_threads)
+{
+    double alpha[4096], phi[4096], w[4096];
+    orc_ctx c;
+    if (make_ctx(&c, verts, tris, refl, n_tri, sc, alpha, phi, w) < 0) return -1;
+    int S = c.S, nb = sc->n_bins;
+    double C = power_const(sc);
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+    int nth = n_threads > 0 ? n_threads : omp_get_max_threads();
+#else
+    (void)n_threads;
+    int nth = 1;
+#endif
+    double* part = (double*)calloc((size_t)nth * (size_t)(n_tri + n_vert), sizeof(double));
+    if (!part) return -1;
+#pragma omp parallel num_threads(nth)
+    {
+#ifdef _OPENMP
+        int me = omp_get_thread_num();
+#else
+        int me = 0;
+#endif
+        double* gr = part + (size_t)me * (size_t)(n_tri + n_vert);
+        double* gz = gr + n_tri;
+        int32_t* tri = (int32_t*)malloc(sizeof(int32_t) * S);
+        double* R = (double*)malloc(sizeof(double) * S * 5);
+        double *cs = R + S, *P = R + 2 * S, *U = R + 3 * S, *V = R + 4 * S;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t p = 0; p < n_pulses; ++p) {
+            if (isnan(t0[p])) continue;
+            trace_pulse(&c, origins + 3 * p, dirs + 3 * p, tri, R, cs, P, U, V);
+            double dp[3] = { dirs[3 * p], dirs[3 * p + 1], dirs[3 * p + 2] };
+            const double* G = grad_wf + p * nb;
+            for (int k = 0; k < S; ++k) {
+                int32_t h = tri[k];
+                if (h < 0) continue;
+                double tau = 2.0 * R[k] / ORC_C_M_PER_NS, gP = 0.0, gD = 0.0;
+                for (int j = 0; j < nb; ++j) {
+                    double s = t0[p] + (double)j * sc->bin_ns - tau;
+                    gP += G[j] * orc_pulse_value(sc, s);
+                    gD += G[j] * orc_pulse_derivative(sc, s);
+                }
+                double gtau = -P[k] * gD;                   /* d wf_j / d tau = -P p'(s) */
+                double gR = gtau * 2.0 / ORC_C_M_PER_NS - gP * 2.0 * P[k] / R[k];
+                double base = C * w[k] / (R[k] * R[k]);
+                double gcos = gP * base * (double)refl[h];
+                gr[h] += gP * base * cs[k];
+                double dk[3], a[3], b[3], cc[3], e1[3], e2[3], n[3];
+                orc_subray_direction(dp, alpha[k], phi[k], dk);
+                vload(verts, tris[3 * h + 0], a);
+                vload(verts, tris[3 * h + 1], b);
+                vload(verts, tris[3 * h + 2], cc);
+                for (int i = 0; i < 3; ++i) { e1[i] = b[i] - a[i]; e2[i] = cc[i] - a[i]; }
+                cross3(e1, e2, n);
+                double nd = dot3(n, dk), nn = sqrt(dot3(n, n));
+                double bary[3] = { 1.0 - U[k] - V[k], U[k], V[k] };
+                for (int i = 0; i < 3; ++i) gz[tris[3 * h + i]] += gR * bary[i] * n[2] / nd;
+                /* cos = sgn(nd) nd/|n|: d cos/d n = sgn (d/|n| - nd n/|n|^3) */
+                double sg = nd >= 0.0 ? 1.0 : -1.0, gn[3];
+                for (int i = 0; i < 3; ++i) gn[i] = gcos * sg * (dk[i] / nn - nd * n[i] / (nn * nn * nn));
+                double d12[3] = { e1[0] - e2[0], e1[1] - e2[1], e1[2] - e2[2] }, r0[3], r1[3], r2[3];
+                cross3(d12, gn, r0);   /* dn = dv0 x (e1 - e2) */
+                cross3(e2, gn, r1);    /* dn = dv1 x e2        */
+                cross3(gn, e1, r2);    /* dn = e1 x dv2        */
+                gz[tris[3 * h + 0]] += r0[2];
+                gz[tris[3 * h + 1]] += r1[2];
+                gz[tris[3 * h + 2]] += r2[2];
+            }
+        }
+        free(tri);
+        free(R);
+    }
+    for (int64_t i = 0; i < n_tri; ++i) grad_refl[i] = 0.0;
+    for (int64_t i = 0; i < n_vert; ++i) grad_z[i] = 0.0;
+    for (int t = 0; t < nth; ++t) {
+        double* gr = part + (size_t)t * (size_t)(n_tri + n_vert);
+        for (int64_t i = 0; i < n_tri; ++i) grad_refl[i] += gr[i];
+        for (int64_t i = 0; i < n_vert; ++i) grad_z[i] += gr[n_tri + i];
+    }
+    free(part);
+    return S;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
