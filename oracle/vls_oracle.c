@@ -13,7 +13,9 @@
  *      (Sec. 3.4, Eq. 1; far-field reading of Eq. 2);
  *   2. each subray's closest hit by brute force over every triangle
  *      (Sec. 3.4: a hit ends the subray; Sec. 5.1: minimum-distance
- *      intersection) with the Moller-Trumbore (1997) test in FP64;
+ *      intersection) with the watertight test of Woop, Benthin & Wald (2013)
+ *      in FP64, so that no subray slips through a closed surface along a
+ *      shared edge;
  *   3. per-subray return power from the laser radar equation (Sec. 5.2, Eq. 7)
  *      with a Lambertian extended-target cross-section;
  *   4. the full waveform: the sum of the subrays' pulse shapes shifted by
@@ -189,27 +191,38 @@ static void cross3(const double a[3], const double b[3], double c[3])
 
 static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
-/* Moller & Trumbore 1997, two-sided, inclusive edges.  1 on a hit with t > 0. */
+/* Watertight ray/triangle test of Woop, Benthin & Wald (2013), in FP64,
+ * two-sided, inclusive edges.  The ray is sheared so that it runs along +z;
+ * the three 2-D edge functions of the projected triangle are then evaluated
+ * from the same operands for both triangles that share an edge, so a ray
+ * through a shared edge or vertex is never lost between them.  Returns 1 on a
+ * hit with t > 0, with the hit point (1-u-v) a + u b + v c. */
 int orc_ray_triangle(const double O[3], const double d[3], const double a[3], const double b[3],
                      const double c[3], double* t, double* u, double* v)
 {
-    double e1[3] = { b[0] - a[0], b[1] - a[1], b[2] - a[2] };
-    double e2[3] = { c[0] - a[0], c[1] - a[1], c[2] - a[2] };
-    double p[3];
-    cross3(d, e2, p);
-    double det = dot3(e1, p);
+    int kz = 0;
+    if (fabs(d[1]) > fabs(d[kz])) kz = 1;
+    if (fabs(d[2]) > fabs(d[kz])) kz = 2;
+    int kx = (kz + 1) % 3, ky = (kx + 1) % 3;
+    if (d[kz] < 0.0) { int tmp = kx; kx = ky; ky = tmp; }
+    if (d[kz] == 0.0) return 0;
+    double Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1.0 / d[kz];
+    double A[3] = { a[0] - O[0], a[1] - O[1], a[2] - O[2] };
+    double B[3] = { b[0] - O[0], b[1] - O[1], b[2] - O[2] };
+    double C[3] = { c[0] - O[0], c[1] - O[1], c[2] - O[2] };
+    double Ax = A[kx] - Sx * A[kz], Ay = A[ky] - Sy * A[kz];
+    double Bx = B[kx] - Sx * B[kz], By = B[ky] - Sy * B[kz];
+    double Cx = C[kx] - Sx * C[kz], Cy = C[ky] - Sy * C[kz];
+    double U = Cx * By - Cy * Bx;   /* edge b-c: weight of a */
+    double V = Ax * Cy - Ay * Cx;   /* edge c-a: weight of b */
+    double W = Bx * Ay - By * Ax;   /* edge a-b: weight of c */
+    if ((U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0)) return 0;
+    double det = U + V + W;
     if (det == 0.0) return 0;
-    double inv = 1.0 / det;
-    double s[3] = { O[0] - a[0], O[1] - a[1], O[2] - a[2] };
-    double uu = dot3(s, p) * inv;
-    if (uu < 0.0 || uu > 1.0) return 0;
-    double q[3];
-    cross3(s, e1, q);
-    double vv = dot3(d, q) * inv;
-    if (vv < 0.0 || uu + vv > 1.0) return 0;
-    double tt = dot3(e2, q) * inv;
+    double T = U * (Sz * A[kz]) + V * (Sz * B[kz]) + W * (Sz * C[kz]);
+    double tt = T / det;
     if (!(tt > 0.0)) return 0;
-    *t = tt; *u = uu; *v = vv;
+    *t = tt; *u = V / det; *v = W / det;
     return 1;
 }
 

@@ -124,3 +124,19 @@ def test_tilted_plane_range(orc):
         nf = np.cross(V[1] - V[0], V[2] - V[0])
         expect = ((V[0] - O) @ nf) / (D[k] @ nf)
         assert abs(r.sub_range[0, k] - expect) <= 1e-12 * expect
+
+
+def test_watertight_shared_edges_and_vertices(orc):
+    # Sec. 3.4: a subray that reaches a closed surface produces a return.  Rays
+    # along shared edges and through shared vertices of the terrain must hit.
+    mesh, pulses, sc = configs.small_tls()
+    for x in (17.0, 32.0, 40.0):
+        for y in (17.0, 32.0, 40.0):
+            for d in ((0.0, 0.0, -1.0), (0.6, 0.0, -0.8), (0.0, -0.6, -0.8), (0.6, 0.6, -0.52915026)):
+                h, t, u, v = orc.closest_hit((x, y, 10.0), d, mesh)
+                assert h >= 0, (x, y, d)
+    # the terrestrial grid looks along grid lines at azimuth 0, 90, 180, 270
+    # degrees; its steeper pulses land well inside the terrain
+    sel = np.concatenate([a * 100 + np.arange(0, 50) for a in (0, 25, 50, 75)])
+    r = orc.simulate(mesh, pulses.subset(sel), sc)
+    assert np.all(r.sub_tri >= 0)
