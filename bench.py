@@ -1,0 +1,197 @@
+"""Benchmark of the fused laser-scanning hot path on one GPU.
+
+Workload (default): the ALS scene with buildings -- a 1024x1024 fBm terrain at
+0.5 m plus 20,000 box buildings (2,333,058 triangles), 1,000,000 line-scanner
+pulses from 500 m above ground, 31 subrays per pulse, 512 bins of 0.5 ns, up
+to 8 returns.  One step = one fused launch: subrays, traversal, power,
+waveform write and returns for every pulse, inputs resident in HBM.
+
+Prints one JSON line.  The algorithmic bytes of a launch are measured by the
+library's traversal counters (64 B per node visit, 48 B per triangle test,
+4 B reflectance per hit, plus 36 B of pulse input and 4*n_bins + 8 + 4 + 16*K
+bytes of output per pulse).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2101_09154_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2101_09154_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_hash):
+    """HBM bytes per launch from the committed PMC summary, if it was taken on this source."""
+    path = os.path.join(ROOT, "profiles", "simulate_als_buildings_pmc.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic-json:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if not rec or rec.get("source_hash") != kernel_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(mesh, pulses, sc, target_s):
+    import oracle
+    threads = oracle.max_threads()
+    rng = np.random.default_rng(123)
+    probe = np.sort(rng.choice(pulses.n, 4, replace=False))
+    t = time.perf_counter()
+    oracle.simulate(mesh, pulses, sc, select=probe)
+    per = (time.perf_counter() - t) / probe.size
+    n = int(np.clip(target_s / max(per, 1e-6), 8, 20000))
+    sel = np.sort(rng.choice(pulses.n, n, replace=False))
+    t = time.perf_counter()
+    r = oracle.simulate(mesh, pulses, sc, select=sel)
+    dt = time.perf_counter() - t
+    return {"value": n * r.S / dt, "unit": "subrays/s", "cores": threads, "kind": "oracle",
+            "pulses_per_s": n / dt,
+            "sample": "%d seeded random pulses of the same workload (%d subrays), FP64 brute force over all "
+                      "%d triangles, %.1f s" % (n, n * r.S, mesh.n_triangles, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--block-waves", type=int, default=1)
+    ap.add_argument("--stack-lds", type=int, default=16)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (three times), to scale HBM counters")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the path has no multi-GPU form in this build "
+              "(pulses shard with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes}))
+        return
+    from synth import configs
+    import paper_2101_09154_amd as vp
+
+    log("generating scene and pulses")
+    mesh, pulses, sc = configs.als_buildings()
+    dev = torch.device("cuda", 0)
+    ctx = vp.Context(0)
+    ctx.set_launch_config(block_waves=args.block_waves, stack_lds=args.stack_lds)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    build_ms = (time.perf_counter() - t) * 1e3
+    stats = scene.stats()
+    log("scene built in %.1f ms: %s" % (build_ms, stats))
+    o = torch.from_numpy(pulses.origins).to(dev)
+    d = torch.from_numpy(pulses.directions).to(dev)
+    n = pulses.n
+    S = vp.n_subrays(sc)
+    K = sc["max_returns"]
+    nb = sc["n_bins"]
+    out = ctx.alloc_outputs(n, S, nb, K, dev, subrays=False)
+
+    log("traversal counters")
+    n_sub, visits, tests = ctx.trace_counts(scene, sc, o, d)
+    v_node = visits / n_sub
+    v_tri = tests / n_sub
+    hit_frac = None
+
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ctx.simulate(scene, sc, o, d, out=out)
+    torch.cuda.synchronize()
+    hit_frac = float((out["n_returns"] > 0).float().mean().item())
+    log("timing %d steps" % args.steps)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ctx.simulate(scene, sc, o, d, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = ev0.elapsed_time(ev1) / args.steps
+    sub_per_s = n * S / (ms * 1e-3)
+    pulse_per_s = n / (ms * 1e-3)
+
+    bytes_per_sub = 64.0 * v_node + 48.0 * v_tri + 4.0
+    bytes_per_pulse = S * bytes_per_sub + 36.0 + 4.0 * nb + 8.0 + 4.0 + 16.0 * K
+    alg_bytes = bytes_per_pulse * n
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    # bytes the launch must move at least once: the scene it reads, pulses in, outputs out
+    scene_bytes = 64.0 * max(mesh.n_triangles - 1, 1) + 48.0 * mesh.n_triangles + 4.0 * mesh.n_triangles
+    compulsory = scene_bytes + n * (36.0 + 4.0 * nb + 8.0 + 4.0 + 16.0 * K)
+    khash = source_hash()
+    traffic = measured_traffic(khash)
+
+    res = {
+        "metric": "subrays/s & pulses/s w/ full waveform, plain vs batched; bwd/fwd time ratio",
+        "value": sub_per_s,
+        "unit": "subrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "als_buildings: 1024x1024 fBm DTM at 0.5 m + 20,000 boxes (2,333,058 triangles), "
+                               "1,000,000 ALS pulses at 500 m AGL, 31 subrays, 512 x 0.5 ns bins, K=8",
+                   "pulses": n, "subrays_per_pulse": S, "n_bins": nb, "max_returns": K,
+                   "triangles": mesh.n_triangles, "parallelism": "single GPU",
+                   "launch": ctx.launch_config()},
+        "pulses_per_s": pulse_per_s,
+        "scene_build_ms": build_ms,
+        "scene_depth": stats["max_depth"],
+        "node_visits_per_subray": v_node,
+        "tri_tests_per_subray": v_tri,
+        "pulses_with_returns": hit_frac,
+        "wall_s_timed": wall,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": ms, "source_hash": khash,
+                     "compulsory_bytes_per_launch": compulsory,
+                     "compulsory_frac": compulsory / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline(mesh, pulses, sc, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

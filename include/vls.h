@@ -1,0 +1,286 @@
+/*
+ * vls.h - C ABI of the MI355X (gfx950) virtual-laser-scanning library.
+ *
+ * The library computes the data-parallel hot path of full-waveform virtual
+ * laser scanning as described for HELIOS++ (Winiwarter et al., "Virtual laser
+ * scanning with HELIOS++", arXiv 2101.09154):
+ *   - each pulse's beam is split into subrays on concentric rings (Sec. 3.4,
+ *     Fig. 6) weighted by the Gaussian beam profile (Sec. 3.4, Eq. 1);
+ *   - every subray is cast separately and stops at its first hit (Sec. 3.4),
+ *     found through an acceleration structure over the triangles (Sec. 5.1;
+ *     here a linear BVH instead of the paper's kD-tree);
+ *   - its return power follows the laser radar equation (Sec. 5.2, Eq. 7)
+ *     with incidence angle and per-triangle reflectance (Sec. 5.1);
+ *   - the returned waveform is the sum of the subrays' pulse shapes
+ *     (Sec. 3.4, Eq. 3, or a Gaussian pulse) shifted by their two-way travel
+ *     times, sampled in bins over a window of bounded length (Sec. 5.4);
+ *   - local maxima of the waveform become discrete returns (Sec. 3.4).
+ * Readings where the paper is silent are the library's documented
+ * conventions; they are listed next to each entry point.
+ *
+ * Conventions for every function:
+ *   - returns vls_status; VLS_OK == 0; nothing throws across the ABI;
+ *   - invalid arguments are detected before anything is enqueued;
+ *   - device work is enqueued on the caller's HIP stream (hipStream_t passed
+ *     as void*, NULL = the null stream) and is asynchronous unless stated;
+ *   - device faults surface at the next synchronising call, e.g. vls_synchronize;
+ *   - the caller owns every array it passes; the library owns contexts,
+ *     scenes and graphs, freed by their *_destroy call;
+ *   - a context (and everything created from it) is not thread-safe.
+ */
+#ifndef VLS_H
+#define VLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VLS_OK = 0,
+    VLS_ERR_INVALID_ARG = 1,   /* NULL where required, bad sizes or parameters         */
+    VLS_ERR_OUT_OF_MEMORY = 2, /* a device or host allocation failed                    */
+    VLS_ERR_DEVICE = 3,        /* a HIP runtime call or a kernel failed                  */
+    VLS_ERR_NOT_BUILT = 4,     /* reserved                                               */
+    VLS_ERR_UNSUPPORTED = 5,   /* valid request outside what this build handles          */
+    VLS_ERR_INTERNAL = 6       /* a C++ exception or an invariant failure inside the lib */
+} vls_status;
+
+enum { VLS_MEM_HOST = 0, VLS_MEM_DEVICE = 1 };
+enum { VLS_PULSE_GAUSSIAN = 0, VLS_PULSE_EQ3 = 1 };
+
+/* Limits of this build. */
+#define VLS_MAX_SUBRAYS 64      /* subrays per pulse (one wavefront)            */
+#define VLS_MAX_BINS 1024       /* waveform bins per pulse                       */
+#define VLS_MAX_RETURNS 16      /* returns kept per pulse                        */
+#define VLS_MAX_SCANNERS 64     /* scanner descriptions per batched call         */
+
+const char* vls_status_string(vls_status s);
+/* Detail of the last failure on the calling thread; valid until the next vls_* call there. */
+const char* vls_last_error(void);
+int32_t vls_version(void);
+
+typedef struct vls_context_s* vls_context;
+typedef struct vls_scene_s* vls_scene;
+typedef struct vls_graph_s* vls_graph;
+
+/* A context binds one HIP device and caches per-scanner subray tables and the
+ * launch configuration.  vls_context_create makes `hip_device` current. */
+vls_status vls_context_create(int32_t hip_device, vls_context* out);
+vls_status vls_context_destroy(vls_context ctx);
+
+/* ------------------------------------------------------------------ scenes */
+
+/* Triangle mesh (Sec. 5.1: a scene is a set of primitives, each with a material;
+ * here triangles with a reflectance in [0, 1]).
+ *   vertices    [n_vertices][3] float32, metres
+ *   triangles   [n_triangles][3] int32 vertex indices (validated on the host
+ *               only when memory == VLS_MEM_HOST)
+ *   reflectance [n_triangles] float32
+ *   memory      where the three arrays live: VLS_MEM_HOST or VLS_MEM_DEVICE.
+ * n_triangles may be 0 (every subray misses). */
+typedef struct {
+    const float* vertices;
+    const int32_t* triangles;
+    const float* reflectance;
+    int64_t n_vertices;
+    int64_t n_triangles;
+    int32_t memory;
+    int32_t reserved;
+} vls_mesh_desc;
+
+typedef struct {
+    int64_t n_vertices;
+    int64_t n_triangles;
+    int64_t n_internal_nodes;   /* n_triangles - 1 (binary LBVH, one triangle per leaf)   */
+    int64_t device_bytes;       /* bytes of device memory the scene holds                 */
+    int32_t max_depth;          /* deepest leaf (root = 0)                                */
+    int32_t max_supported_depth;
+    float bounds_lo[3];         /* vertex bounds                                          */
+    float bounds_hi[3];
+    float box_pad;              /* 0: node boxes are exact; traversal pads them per ray    */
+    float reserved;
+} vls_scene_stats;
+
+/* Copies the mesh to the device and builds the acceleration structure: Morton
+ * codes of triangle centroids (63 bits), radix sort, Karras (2012) binary
+ * radix tree, bottom-up boxes.  Enqueued on `stream`; returns after the build
+ * has finished (the call synchronises `stream`).  Input arrays are not kept. */
+vls_status vls_scene_create(vls_context ctx, const vls_mesh_desc* mesh, void* stream, vls_scene* out);
+
+/* New vertex positions (same count and triangles): leaf records and node boxes
+ * are refitted, the tree topology is kept.  `vertices_dev` is a device array
+ * [n_vertices][3] float32.  Asynchronous on `stream`. */
+vls_status vls_scene_update_vertices(vls_scene scene, const float* vertices_dev, void* stream);
+
+/* New per-triangle reflectance, device array [n_triangles] float32.  Asynchronous. */
+vls_status vls_scene_update_reflectance(vls_scene scene, const float* reflectance_dev, void* stream);
+
+/* Synchronous: statistics of the built scene. */
+vls_status vls_scene_stats_get(vls_scene scene, vls_scene_stats* out);
+
+/* Synchronous debug copy of the structure to host memory (any pointer may be NULL):
+ *   nodes      [n_internal_nodes][16] float32 words: left box lo.xyz hi.xyz,
+ *              right box lo.xyz hi.xyz, then left ref, right ref, parent, 0 as
+ *              int32 bits; a ref >= 0 is an internal node, ref < 0 is leaf ~ref
+ *   leaf_tri   [n_triangles] int32: original triangle index of each leaf
+ *   morton     [n_triangles] uint64: sorted Morton keys
+ *   root       the root ref (0, or ~0 for a one-triangle scene, or -1 if empty) */
+vls_status vls_scene_export(vls_scene scene, float* nodes, int32_t* leaf_tri, uint64_t* morton, int32_t* root);
+
+vls_status vls_scene_destroy(vls_scene scene);
+
+/* ------------------------------------------------------------------ scanner, pulses, outputs */
+
+/* Instrument description (Sec. 3.4 subrays and waveform, Sec. 5.2 radar
+ * equation, Sec. 5.4 bin size and window length).
+ *   divergence_rad     full beam divergence at the 1/e^2 points
+ *   n_subrays          1..64 subrays per pulse; 0 = use beam_quality.  Rings
+ *                      i = 1, 2, ... hold floor(2 pi i) subrays (Sec. 3.4); a
+ *                      count between ring totals fills rings in order and the
+ *                      last ring holds the remainder, evenly spaced
+ *   beam_quality       number of complete rings when n_subrays == 0
+ *   pattern_extent     kappa: ring i of N at angle (i/N) kappa divergence/2
+ *   pulse_shape        VLS_PULSE_GAUSSIAN (unit peak; width = FWHM) or
+ *                      VLS_PULSE_EQ3 ((s/tau)^2 exp(-s/tau), tau = width/1.75)
+ *   bin_ns, n_bins     the window samples t0 + j*bin_ns, j < n_bins (3..1024)
+ *   window_pre_ns      t0 = first two-way travel time - window_pre_ns;
+ *                      < 0 = automatic: 6 sigma (Gaussian) or 0 (Eq. 3)
+ *   peak_power_w, receiver_diameter_m, efficiency
+ *                      subray power P = peak * w_k * (eff * D^2 / 4) * rho * cos / R^2
+ *                      (Eq. 7 with a Lambertian extended target)
+ *   min_echo_abs, min_echo_rel
+ *                      a return needs wf >= max(abs, rel * max wf)
+ *   max_returns        K, 1..16 returns kept per pulse (the first K in time) */
+typedef struct {
+    double divergence_rad;
+    double pattern_extent;
+    double pulse_width_ns;
+    double bin_ns;
+    double window_pre_ns;
+    double peak_power_w;
+    double receiver_diameter_m;
+    double efficiency;
+    double min_echo_abs;
+    double min_echo_rel;
+    int32_t n_subrays;
+    int32_t beam_quality;
+    int32_t pulse_shape;
+    int32_t n_bins;
+    int32_t max_returns;
+    int32_t reserved;
+} vls_scanner_desc;
+
+/* Number of subrays the description yields (1..64), or an error for an
+ * invalid description.  Host only; enqueues nothing. */
+vls_status vls_scanner_subrays(const vls_scanner_desc* scanner, int32_t* n_subrays);
+
+/* Pulses (the beam origin and direction recorded with each waveform, Sec. 3.6).
+ *   origins        [n_pulses][3] float64, device
+ *   directions     [n_pulses][3] float32, device; normalised in FP64 by the
+ *                  library; a zero or non-finite direction makes every subray miss
+ *   window_t0_ns   [n_pulses] float64, device, or NULL: fixed window origins
+ *                  (NaN = no window; used to hold t0 fixed for gradients)
+ *   segment_offsets [n_segments+1] int64, HOST, or NULL: pulses of segment s
+ *                  are [off[s], off[s+1]); off[0] = 0, off[n] = n_pulses
+ *   segment_scanner [n_segments] int32, HOST: index into the scanner array
+ * Without segments every pulse uses scanners[0]. */
+typedef struct {
+    const double* origins;
+    const float* directions;
+    const double* window_t0_ns;
+    int64_t n_pulses;
+    const int64_t* segment_offsets;
+    const int32_t* segment_scanner;
+    int32_t n_segments;
+    int32_t reserved;
+} vls_pulse_batch;
+
+/* Outputs, all device arrays owned by the caller; any may be NULL unless a
+ * function needs it.  S_stride = the largest subray count of the scanners in
+ * the call; per-subray arrays are [n_pulses][S_stride] (unused tail entries of
+ * a pulse with fewer subrays are left untouched).
+ *   subray_tri      int32, hit triangle (original index) or -1 for a miss
+ *   subray_range    float64, metres (+inf for a miss)
+ *   subray_cos      float32, |cos| of the incidence angle (0 for a miss)
+ *   subray_power    float32, watts (0 for a miss)
+ *   waveform        [n_pulses][n_bins] float32
+ *   window_t0_ns    [n_pulses] float64 (NaN when no subray hit)
+ *   n_returns       [n_pulses] int32
+ *   ret_range       [n_pulses][K] float32 metres: (c/2)(t0 + j*bin - s_peak)
+ *   ret_amplitude   [n_pulses][K] float32, waveform value at the return's bin
+ *   ret_tri         [n_pulses][K] int32, triangle of the subray contributing
+ *                   most at that bin (lowest subray index on ties)
+ *   ret_bin         [n_pulses][K] int32
+ * Slots past n_returns hold range 0, amplitude 0, tri -1, bin -1. */
+typedef struct {
+    int32_t* subray_tri;
+    double* subray_range;
+    float* subray_cos;
+    float* subray_power;
+    float* waveform;
+    double* window_t0_ns;
+    int32_t* n_returns;
+    float* ret_range;
+    float* ret_amplitude;
+    int32_t* ret_tri;
+    int32_t* ret_bin;
+} vls_outputs;
+
+/* ------------------------------------------------------------------ the hot path */
+
+/* Subrays and closest hits only (Sec. 3.4 first hit; Sec. 5.1 minimum-distance
+ * intersection).  Writes subray_tri (required), subray_range, subray_cos,
+ * subray_power.  Ties on equal distance go to the lower triangle index;
+ * triangle edges are inclusive; only distances > 0 count. */
+vls_status vls_trace(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
+                     const vls_pulse_batch* pulses, const vls_outputs* out, void* stream);
+
+/* Waveform synthesis from traced subrays (Sec. 3.4, Eq. 3): reads subray_tri,
+ * subray_range, subray_power; writes waveform (required) and window_t0_ns. */
+vls_status vls_waveform(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners,
+                        const vls_pulse_batch* pulses, const vls_outputs* out, void* stream);
+
+/* Returns from waveforms (Sec. 3.4 local maxima): reads waveform and
+ * window_t0_ns; writes n_returns, ret_range, ret_amplitude, ret_bin (required)
+ * and ret_tri, which needs subray_tri, subray_range and subray_power (if they
+ * are NULL, ret_tri is -1). */
+vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners,
+                       const vls_pulse_batch* pulses, const vls_outputs* out, void* stream);
+
+/* The whole path fused in one launch: trace, power, waveform, returns.
+ * waveform may be NULL (returns are still found from the in-register
+ * waveform, Sec. 5.4: binning runs even when no waveform is written).
+ * With segments, one persistent launch covers every segment. */
+vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
+                        const vls_pulse_batch* pulses, const vls_outputs* out, void* stream);
+
+/* ------------------------------------------------------------------ launch configuration */
+
+typedef struct {
+    int32_t block_waves;       /* wavefronts per block: 1, 2, 4 (default 1)                     */
+    int32_t stack_lds;         /* traversal-stack entries per lane held in LDS: 4..32 (default 16);
+                                  deeper entries spill to per-lane scratch                        */
+    int32_t persistent_blocks; /* blocks of the persistent kernel; 0 = auto (CUs x occupancy)   */
+    int32_t reserved;
+} vls_launch_config;
+
+vls_status vls_set_launch_config(vls_context ctx, const vls_launch_config* cfg);
+vls_status vls_get_launch_config(vls_context ctx, vls_launch_config* cfg);
+
+/* Diagnostic, synchronous: traces the batch (nothing is written to outputs)
+ * and stores in counts[0..2] the number of subrays traced, internal-node
+ * visits and triangle tests of the traversal.  These give the algorithmic
+ * bytes of the path: 64 B per node visit and 48 B per triangle test. */
+vls_status vls_trace_counts(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
+                            const vls_pulse_batch* pulses, uint64_t* counts, void* stream);
+
+/* Synchronise `stream` and report any device error as VLS_ERR_DEVICE. */
+vls_status vls_synchronize(vls_context ctx, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VLS_H */

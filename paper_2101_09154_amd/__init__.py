@@ -1,0 +1,7 @@
+"""MI355X-native full-waveform virtual laser scanning (the hot path of HELIOS++,
+arXiv 2101.09154): HIP kernels for gfx950 behind the C ABI of include/vls.h,
+with a thin ctypes binding."""
+from . import vls
+from .vls import Context, Scene, VlsError, n_subrays, scanner_desc
+
+__all__ = ["vls", "Context", "Scene", "VlsError", "n_subrays", "scanner_desc"]

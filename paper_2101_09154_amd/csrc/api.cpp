@@ -1,0 +1,760 @@
+// Host runtime behind the C ABI declared in include/vls.h: argument
+// validation, per-scanner subray tables, scene lifecycle and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "vls.h"
+#include "vls_internal.h"
+
+using namespace vls;
+
+namespace {
+
+thread_local std::string g_err;
+
+vls_status fail(vls_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+vls_status hip_fail(hipError_t e, const char* what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? VLS_ERR_OUT_OF_MEMORY : VLS_ERR_DEVICE;
+}
+
+#define VLS_HIP(call, what)                            \
+    do {                                               \
+        hipError_t e__ = (call);                       \
+        if (e__ != hipSuccess) return hip_fail(e__, what); \
+    } while (0)
+
+// ------------------------------------------------------------------ subray table (Sec. 3.4)
+
+int ring_capacity(int i) { return (int)std::floor(2.0 * M_PI * (double)i); }
+
+// Ring sizes: complete rings 1..quality, or ring-fill to n_subrays.
+bool ring_sizes(int n_subrays, int quality, std::vector<int>& rings)
+{
+    rings.clear();
+    if (n_subrays <= 0) {
+        if (quality < 0 || quality > 64) return false;
+        for (int i = 1; i <= quality; ++i) rings.push_back(ring_capacity(i));
+        return true;
+    }
+    int left = n_subrays - 1;
+    for (int i = 1; left > 0; ++i) {
+        int m = std::min(ring_capacity(i), left);
+        rings.push_back(m);
+        left -= m;
+    }
+    return true;
+}
+
+// table[k] = {cos a, sin a, cos phi, sin phi, w}: central subray, then rings
+// outward; ring i of N at a = (i/N) kappa div/2, phi = 2 pi m / n_i; w from the
+// Gaussian beam profile (Eq. 1, far field: r/w = tan a / tan(div/2)), sum 1.
+int subray_table(const vls_scanner_desc& d, std::vector<double>& table)
+{
+    std::vector<int> rings;
+    if (!ring_sizes(d.n_subrays, d.beam_quality, rings)) return -1;
+    int S = 1;
+    for (int m : rings) S += m;
+    if (S > VLS_MAX_SUBRAYS) return -S;
+    const int N = (int)rings.size();
+    const double half = 0.5 * d.divergence_rad, th = std::tan(half);
+    std::vector<double> al(S), ph(S), w(S);
+    int k = 0;
+    al[k] = 0.0;
+    ph[k] = 0.0;
+    ++k;
+    for (int i = 1; i <= N; ++i)
+        for (int m = 0; m < rings[i - 1]; ++m, ++k) {
+            al[k] = ((double)i / (double)N) * (d.pattern_extent * half);
+            ph[k] = 2.0 * M_PI * (double)m / (double)rings[i - 1];
+        }
+    double sum = 0.0;
+    for (k = 0; k < S; ++k) {
+        double x = th > 0.0 ? std::tan(al[k]) / th : 0.0;
+        w[k] = std::exp(-2.0 * x * x);
+        sum += w[k];
+    }
+    table.resize(5 * (size_t)S);
+    for (k = 0; k < S; ++k) {
+        table[5 * k + 0] = std::cos(al[k]);
+        table[5 * k + 1] = std::sin(al[k]);
+        table[5 * k + 2] = std::cos(ph[k]);
+        table[5 * k + 3] = std::sin(ph[k]);
+        table[5 * k + 4] = w[k] / sum;
+    }
+    return S;
+}
+
+bool finite_pos(double x) { return x > 0.0 && std::isfinite(x); }
+
+vls_status check_scanner(const vls_scanner_desc& d, int idx)
+{
+    char b[160];
+    auto bad = [&](const char* what) {
+        snprintf(b, sizeof b, "scanner %d: %s", idx, what);
+        return fail(VLS_ERR_INVALID_ARG, b);
+    };
+    if (!(d.divergence_rad >= 0.0) || !std::isfinite(d.divergence_rad)) return bad("divergence_rad must be finite and >= 0");
+    if (!(d.pattern_extent >= 0.0) || !std::isfinite(d.pattern_extent)) return bad("pattern_extent must be finite and >= 0");
+    if (!finite_pos(d.pulse_width_ns)) return bad("pulse_width_ns must be > 0");
+    if (!finite_pos(d.bin_ns)) return bad("bin_ns must be > 0");
+    if (d.n_bins < 3 || d.n_bins > VLS_MAX_BINS) return bad("n_bins must be in [3, 1024]");
+    if (d.max_returns < 1 || d.max_returns > VLS_MAX_RETURNS) return bad("max_returns must be in [1, 16]");
+    if (d.pulse_shape != VLS_PULSE_GAUSSIAN && d.pulse_shape != VLS_PULSE_EQ3) return bad("unknown pulse_shape");
+    if (d.n_subrays < 0 || d.n_subrays > VLS_MAX_SUBRAYS) return bad("n_subrays must be in [0, 64]");
+    if (d.n_subrays == 0 && d.beam_quality < 0) return bad("beam_quality must be >= 0");
+    if (!std::isfinite(d.window_pre_ns)) return bad("window_pre_ns must be finite");
+    if (!std::isfinite(d.peak_power_w) || !std::isfinite(d.receiver_diameter_m) || !std::isfinite(d.efficiency))
+        return bad("radiometric constants must be finite");
+    if (!std::isfinite(d.min_echo_abs) || !std::isfinite(d.min_echo_rel)) return bad("echo thresholds must be finite");
+    std::vector<int> rings;
+    if (!ring_sizes(d.n_subrays, d.beam_quality, rings)) return bad("bad subray request");
+    int S = 1;
+    for (int m : rings) S += m;
+    if (S > VLS_MAX_SUBRAYS) {
+        snprintf(b, sizeof b, "scanner %d: %d subrays exceed %d (one wavefront per pulse)", idx, S, VLS_MAX_SUBRAYS);
+        return fail(VLS_ERR_UNSUPPORTED, b);
+    }
+    return VLS_OK;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ objects
+
+struct vls_context_s {
+    int device = 0;
+    LaunchCfg cfg;
+    std::map<std::string, double*> patterns;  // subray tables on the device
+    struct Batch {
+        std::vector<unsigned char> key;
+        unsigned char* dev = nullptr;
+        BatchDev bd;
+        int max_bins = 0;
+    };
+    std::vector<Batch> batches;  // uploaded segment tables, reused by content
+    ~vls_context_s()
+    {
+        (void)hipSetDevice(device);
+        for (auto& kv : patterns) (void)hipFree(kv.second);
+        for (auto& b : batches) (void)hipFree(b.dev);
+    }
+};
+
+struct vls_scene_s {
+    vls_context ctx = nullptr;
+    BvhBuffers b;
+    vls_scene_stats stats{};
+    int root = -1;
+    ~vls_scene_s()
+    {
+        (void)hipFree(b.nodes);
+        (void)hipFree(b.tris);
+        (void)hipFree(b.refl);
+        (void)hipFree(b.verts);
+        (void)hipFree(b.tri_idx);
+        (void)hipFree(b.leaf_parent);
+        (void)hipFree(b.node_parent);
+        (void)hipFree(b.leaf_tri);
+        (void)hipFree(b.morton);
+        (void)hipFree(b.flags);
+        (void)hipFree(b.bounds);
+    }
+};
+
+namespace {
+
+vls_status scanner_dev(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s)
+{
+    std::vector<double> table;
+    int S = subray_table(d, table);
+    if (S <= 0) return fail(VLS_ERR_UNSUPPORTED, "subray pattern too large");
+    char key[160];
+    snprintf(key, sizeof key, "%d|%a|%a", S, d.divergence_rad, d.pattern_extent);
+    double* dev = nullptr;
+    auto it = ctx->patterns.find(key);
+    if (it == ctx->patterns.end()) {
+        VLS_HIP(hipMalloc(&dev, sizeof(double) * table.size()), "pattern alloc");
+        hipError_t e = hipMemcpy(dev, table.data(), sizeof(double) * table.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(dev);
+            return hip_fail(e, "pattern upload");
+        }
+        ctx->patterns[key] = dev;
+    } else {
+        dev = it->second;
+    }
+    memset(&s, 0, sizeof s);
+    s.pattern = dev;
+    s.S = S;
+    s.P_w = kWave / S;
+    s.n_bins = d.n_bins;
+    s.K = d.max_returns;
+    s.shape = d.pulse_shape;
+    s.bin_ns = (float)d.bin_ns;
+    const double log2e = 1.4426950408889634;
+    if (d.pulse_shape == VLS_PULSE_GAUSSIAN) {
+        double sg = d.pulse_width_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+        s.neg_k = (float)(-log2e / (2.0 * sg * sg));
+        s.inv_tau = 0.0f;
+        s.cut_lo = (float)(8.0 * sg);
+        s.cut_hi = (float)(8.0 * sg);
+        s.t_pre = d.window_pre_ns < 0.0 ? 6.0 * sg : d.window_pre_ns;
+        s.s_peak = 0.0;
+    } else {
+        double tau = d.pulse_width_ns / 1.75;
+        s.neg_k = (float)(-log2e);
+        s.inv_tau = (float)(1.0 / tau);
+        s.cut_lo = 0.0f;
+        s.cut_hi = (float)(40.0 * tau);
+        s.t_pre = d.window_pre_ns < 0.0 ? 0.0 : d.window_pre_ns;
+        s.s_peak = 2.0 * tau;
+    }
+    s.power_c = d.peak_power_w * d.efficiency * d.receiver_diameter_m * d.receiver_diameter_m / 4.0;
+    s.thr_abs = d.min_echo_abs;
+    s.thr_rel = d.min_echo_rel;
+    return VLS_OK;
+}
+
+SceneDev scene_dev(vls_scene sc)
+{
+    SceneDev s;
+    s.nodes = sc->b.nodes;
+    s.tris = sc->b.tris;
+    s.refl = sc->b.refl;
+    s.bounds = sc->b.bounds;
+    s.root = sc->root;
+    s.n_tri = (int)sc->b.n_tri;
+    return s;
+}
+
+struct Prepared {
+    std::vector<ScannerDev> sc;
+    int S_stride = 1;
+    int n_bins = 0, K = 0;
+    bool same_layout = true;
+    std::vector<int64_t> off;   // segment offsets (or {0, n})
+    std::vector<int32_t> seg_sc;
+};
+
+vls_status prepare(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners, const vls_pulse_batch* pulses,
+                   Prepared& pr)
+{
+    if (!ctx) return fail(VLS_ERR_INVALID_ARG, "context is NULL");
+    if (!scanners || n_scanners < 1 || n_scanners > VLS_MAX_SCANNERS)
+        return fail(VLS_ERR_INVALID_ARG, "need 1..64 scanner descriptions");
+    if (!pulses) return fail(VLS_ERR_INVALID_ARG, "pulse batch is NULL");
+    if (pulses->n_pulses < 0) return fail(VLS_ERR_INVALID_ARG, "n_pulses < 0");
+    if (pulses->n_pulses > 0 && (!pulses->origins || !pulses->directions))
+        return fail(VLS_ERR_INVALID_ARG, "origins and directions are required");
+    if (!aligned(pulses->origins, 8) || !aligned(pulses->directions, 4) || !aligned(pulses->window_t0_ns, 8))
+        return fail(VLS_ERR_INVALID_ARG, "misaligned pulse arrays");
+    pr.sc.resize(n_scanners);
+    for (int i = 0; i < n_scanners; ++i) {
+        vls_status st = check_scanner(scanners[i], i);
+        if (st != VLS_OK) return st;
+        st = scanner_dev(ctx, scanners[i], pr.sc[i]);
+        if (st != VLS_OK) return st;
+    }
+    pr.n_bins = pr.sc[0].n_bins;
+    pr.K = pr.sc[0].K;
+    pr.S_stride = 1;
+    for (auto& s : pr.sc) {
+        pr.S_stride = std::max(pr.S_stride, s.S);
+        if (s.n_bins != pr.n_bins || s.K != pr.K) pr.same_layout = false;
+    }
+    const int64_t n = pulses->n_pulses;
+    if (pulses->n_segments > 0) {
+        if (!pulses->segment_offsets || !pulses->segment_scanner)
+            return fail(VLS_ERR_INVALID_ARG, "segments need host segment_offsets and segment_scanner");
+        if (!pr.same_layout)
+            return fail(VLS_ERR_INVALID_ARG, "scanners of one batch must share n_bins and max_returns");
+        const int ns = pulses->n_segments;
+        pr.off.assign(pulses->segment_offsets, pulses->segment_offsets + ns + 1);
+        pr.seg_sc.assign(pulses->segment_scanner, pulses->segment_scanner + ns);
+        if (pr.off[0] != 0 || pr.off[ns] != n) return fail(VLS_ERR_INVALID_ARG, "segment offsets must run from 0 to n_pulses");
+        for (int s = 0; s < ns; ++s) {
+            if (pr.off[s + 1] < pr.off[s]) return fail(VLS_ERR_INVALID_ARG, "segment offsets must not decrease");
+            if (pr.seg_sc[s] < 0 || pr.seg_sc[s] >= n_scanners)
+                return fail(VLS_ERR_INVALID_ARG, "segment scanner index out of range");
+        }
+    } else {
+        pr.off = {0, n};
+        pr.seg_sc = {0};
+    }
+    return VLS_OK;
+}
+
+vls_status check_scene(vls_context ctx, vls_scene scene)
+{
+    if (!scene) return fail(VLS_ERR_INVALID_ARG, "scene is NULL");
+    if (scene->ctx != ctx) return fail(VLS_ERR_INVALID_ARG, "scene belongs to another context");
+    int limit = ctx->cfg.stack_lds + kMaxSpill - 1;
+    if (scene->stats.max_depth > limit) {
+        char b[128];
+        snprintf(b, sizeof b, "scene depth %d exceeds the traversal stack (%d)", scene->stats.max_depth, limit);
+        return fail(VLS_ERR_UNSUPPORTED, b);
+    }
+    return VLS_OK;
+}
+
+OutDev out_dev(const vls_outputs* o, int stride)
+{
+    OutDev d;
+    memset(&d, 0, sizeof d);
+    d.sub_tri = o->subray_tri;
+    d.sub_range = o->subray_range;
+    d.sub_cos = o->subray_cos;
+    d.sub_power = o->subray_power;
+    d.sub_stride = stride;
+    d.wf = o->waveform;
+    d.t0 = o->window_t0_ns;
+    d.n_ret = o->n_returns;
+    d.ret_range = o->ret_range;
+    d.ret_amp = o->ret_amplitude;
+    d.ret_tri = o->ret_tri;
+    d.ret_bin = o->ret_bin;
+    return d;
+}
+
+vls_status check_outputs(const vls_outputs* o)
+{
+    if (!o) return fail(VLS_ERR_INVALID_ARG, "outputs are NULL");
+    if (!aligned(o->subray_tri, 4) || !aligned(o->subray_range, 8) || !aligned(o->subray_cos, 4) ||
+        !aligned(o->subray_power, 4) || !aligned(o->waveform, 4) || !aligned(o->window_t0_ns, 8) ||
+        !aligned(o->n_returns, 4) || !aligned(o->ret_range, 4) || !aligned(o->ret_amplitude, 4) ||
+        !aligned(o->ret_tri, 4) || !aligned(o->ret_bin, 4))
+        return fail(VLS_ERR_INVALID_ARG, "misaligned output array");
+    return VLS_OK;
+}
+
+PulsesDev pulses_dev(const vls_pulse_batch* p)
+{
+    PulsesDev d;
+    d.origins = p->origins;
+    d.dirs = p->directions;
+    d.t0_in = p->window_t0_ns;
+    d.n = p->n_pulses;
+    return d;
+}
+
+// Upload (or reuse) the device tables of a segmented batch.
+vls_status batch_tables(vls_context ctx, const Prepared& pr, vls_context_s::Batch*& out)
+{
+    const int ns = (int)pr.seg_sc.size();
+    std::vector<long long> tile_off(ns + 1), pulse_off(ns), pulse_end(ns);
+    std::vector<int> seg(ns);
+    tile_off[0] = 0;
+    for (int s = 0; s < ns; ++s) {
+        const ScannerDev& sc = pr.sc[pr.seg_sc[s]];
+        long long np = pr.off[s + 1] - pr.off[s];
+        tile_off[s + 1] = tile_off[s] + (np + sc.P_w - 1) / sc.P_w;
+        pulse_off[s] = pr.off[s];
+        pulse_end[s] = pr.off[s + 1];
+        seg[s] = pr.seg_sc[s];
+    }
+    // layout: tile_off | pulse_off | pulse_end | seg | scanners | counter
+    size_t o_tile = 0, o_po = o_tile + 8 * (ns + 1), o_pe = o_po + 8 * ns, o_seg = o_pe + 8 * ns;
+    size_t o_sc = (o_seg + 4 * ns + 63) / 64 * 64, o_ctr = o_sc + sizeof(ScannerDev) * pr.sc.size();
+    size_t bytes = o_ctr + 64;
+    std::vector<unsigned char> blob(bytes, 0);
+    memcpy(&blob[o_tile], tile_off.data(), 8 * (ns + 1));
+    memcpy(&blob[o_po], pulse_off.data(), 8 * ns);
+    memcpy(&blob[o_pe], pulse_end.data(), 8 * ns);
+    memcpy(&blob[o_seg], seg.data(), 4 * ns);
+    memcpy(&blob[o_sc], pr.sc.data(), sizeof(ScannerDev) * pr.sc.size());
+    for (auto& b : ctx->batches)
+        if (b.key == blob) {
+            out = &b;
+            return VLS_OK;
+        }
+    vls_context_s::Batch b;
+    VLS_HIP(hipMalloc(&b.dev, bytes), "batch table alloc");
+    hipError_t e = hipMemcpy(b.dev, blob.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(b.dev);
+        return hip_fail(e, "batch table upload");
+    }
+    b.key = std::move(blob);
+    b.bd.tile_off = reinterpret_cast<const long long*>(b.dev + o_tile);
+    b.bd.pulse_off = reinterpret_cast<const long long*>(b.dev + o_po);
+    b.bd.pulse_end = reinterpret_cast<const long long*>(b.dev + o_pe);
+    b.bd.seg_scanner = reinterpret_cast<const int*>(b.dev + o_seg);
+    b.bd.scanners = reinterpret_cast<const ScannerDev*>(b.dev + o_sc);
+    b.bd.counter = reinterpret_cast<unsigned long long*>(b.dev + o_ctr);
+    b.bd.n_seg = ns;
+    b.bd.n_tiles = tile_off[ns];
+    b.max_bins = pr.n_bins;
+    ctx->batches.push_back(std::move(b));
+    out = &ctx->batches.back();
+    return VLS_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI
+
+extern "C" {
+
+const char* vls_status_string(vls_status s)
+{
+    switch (s) {
+    case VLS_OK: return "ok";
+    case VLS_ERR_INVALID_ARG: return "invalid argument";
+    case VLS_ERR_OUT_OF_MEMORY: return "out of memory";
+    case VLS_ERR_DEVICE: return "device error";
+    case VLS_ERR_NOT_BUILT: return "not built";
+    case VLS_ERR_UNSUPPORTED: return "unsupported";
+    case VLS_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char* vls_last_error(void) { return g_err.c_str(); }
+
+int32_t vls_version(void) { return 1; }
+
+vls_status vls_scanner_subrays(const vls_scanner_desc* scanner, int32_t* n_subrays)
+{
+    if (!scanner || !n_subrays) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+    vls_status st = check_scanner(*scanner, 0);
+    if (st != VLS_OK) return st;
+    std::vector<double> table;
+    int S = subray_table(*scanner, table);
+    if (S <= 0) return fail(VLS_ERR_UNSUPPORTED, "subray pattern too large");
+    *n_subrays = S;
+    return VLS_OK;
+}
+
+vls_status vls_context_create(int32_t hip_device, vls_context* out)
+{
+    try {
+        if (!out) return fail(VLS_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        int n = 0;
+        VLS_HIP(hipGetDeviceCount(&n), "hipGetDeviceCount");
+        if (hip_device < 0 || hip_device >= n) return fail(VLS_ERR_INVALID_ARG, "no such HIP device");
+        VLS_HIP(hipSetDevice(hip_device), "hipSetDevice");
+        auto* c = new vls_context_s();
+        c->device = hip_device;
+        *out = c;
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
+vls_status vls_context_destroy(vls_context ctx)
+{
+    if (!ctx) return fail(VLS_ERR_INVALID_ARG, "context is NULL");
+    delete ctx;
+    return VLS_OK;
+}
+
+vls_status vls_set_launch_config(vls_context ctx, const vls_launch_config* cfg)
+{
+    if (!ctx || !cfg) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+    if (cfg->block_waves != 1 && cfg->block_waves != 2 && cfg->block_waves != 4)
+        return fail(VLS_ERR_INVALID_ARG, "block_waves must be 1, 2 or 4");
+    int r = cfg->stack_lds;
+    if (r < 4 || r > kMaxRing || (r & (r - 1)) != 0) return fail(VLS_ERR_INVALID_ARG, "stack_lds must be 4, 8, 16 or 32");
+    if (cfg->persistent_blocks < 0) return fail(VLS_ERR_INVALID_ARG, "persistent_blocks must be >= 0");
+    ctx->cfg.block_waves = cfg->block_waves;
+    ctx->cfg.stack_lds = r;
+    ctx->cfg.persistent_blocks = cfg->persistent_blocks;
+    return VLS_OK;
+}
+
+vls_status vls_get_launch_config(vls_context ctx, vls_launch_config* cfg)
+{
+    if (!ctx || !cfg) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+    cfg->block_waves = ctx->cfg.block_waves;
+    cfg->stack_lds = ctx->cfg.stack_lds;
+    cfg->persistent_blocks = ctx->cfg.persistent_blocks;
+    cfg->reserved = 0;
+    return VLS_OK;
+}
+
+vls_status vls_scene_create(vls_context ctx, const vls_mesh_desc* mesh, void* stream, vls_scene* out)
+{
+    try {
+        if (!ctx || !mesh || !out) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        const int64_t nv = mesh->n_vertices, nt = mesh->n_triangles;
+        if (nv < 0 || nt < 0) return fail(VLS_ERR_INVALID_ARG, "negative sizes");
+        if (nt > 0x3fffffff) return fail(VLS_ERR_UNSUPPORTED, "more than 2^30 triangles");
+        if (nt > 0 && (nv < 1 || !mesh->vertices || !mesh->triangles || !mesh->reflectance))
+            return fail(VLS_ERR_INVALID_ARG, "vertices, triangles and reflectance are required");
+        if (mesh->memory != VLS_MEM_HOST && mesh->memory != VLS_MEM_DEVICE)
+            return fail(VLS_ERR_INVALID_ARG, "memory must be VLS_MEM_HOST or VLS_MEM_DEVICE");
+        if (mesh->memory == VLS_MEM_HOST) {
+            for (int64_t i = 0; i < 3 * nt; ++i)
+                if (mesh->triangles[i] < 0 || mesh->triangles[i] >= nv)
+                    return fail(VLS_ERR_INVALID_ARG, "triangle vertex index out of range");
+            for (int64_t i = 0; i < 3 * nv; ++i)
+                if (!std::isfinite(mesh->vertices[i])) return fail(VLS_ERR_INVALID_ARG, "non-finite vertex");
+        }
+        VLS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+        hipStream_t s = (hipStream_t)stream;
+        std::unique_ptr<vls_scene_s> sc(new vls_scene_s());
+        sc->ctx = ctx;
+        BvhBuffers& b = sc->b;
+        b.n_tri = nt;
+        b.n_vert = nv;
+        const int64_t ni = std::max<int64_t>(nt - 1, 1);
+        const int64_t nt1 = std::max<int64_t>(nt, 1), nv1 = std::max<int64_t>(nv, 1);
+        int64_t bytes = 0;
+        auto alloc = [&](void** p, size_t n) -> hipError_t {
+            bytes += (int64_t)n;
+            return hipMalloc(p, n);
+        };
+        VLS_HIP(alloc((void**)&b.nodes, 64 * (size_t)ni), "scene alloc");
+        VLS_HIP(alloc((void**)&b.tris, 48 * (size_t)nt1), "scene alloc");
+        VLS_HIP(alloc((void**)&b.refl, 4 * (size_t)nt1), "scene alloc");
+        VLS_HIP(alloc((void**)&b.verts, 12 * (size_t)nv1), "scene alloc");
+        VLS_HIP(alloc((void**)&b.tri_idx, 12 * (size_t)nt1), "scene alloc");
+        VLS_HIP(alloc((void**)&b.leaf_parent, 4 * (size_t)nt1), "scene alloc");
+        VLS_HIP(alloc((void**)&b.node_parent, 4 * (size_t)ni), "scene alloc");
+        VLS_HIP(alloc((void**)&b.leaf_tri, 4 * (size_t)nt1), "scene alloc");
+        VLS_HIP(alloc((void**)&b.morton, 8 * (size_t)nt1), "scene alloc");
+        VLS_HIP(alloc((void**)&b.flags, 4 * (size_t)ni), "scene alloc");
+        VLS_HIP(alloc((void**)&b.bounds, 4 * 32), "scene alloc");
+        VLS_HIP(hipMemsetAsync(b.bounds, 0, 4 * 32, s), "scene init");
+        if (nt > 0) {
+            hipMemcpyKind kind = mesh->memory == VLS_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+            VLS_HIP(hipMemcpyAsync(b.verts, mesh->vertices, 12 * (size_t)nv, kind, s), "vertex copy");
+            VLS_HIP(hipMemcpyAsync(b.tri_idx, mesh->triangles, 12 * (size_t)nt, kind, s), "triangle copy");
+            VLS_HIP(hipMemcpyAsync(b.refl, mesh->reflectance, 4 * (size_t)nt, kind, s), "reflectance copy");
+            std::string err;
+            hipError_t e = bvh_build(b, s, err);
+            if (e != hipSuccess) return hip_fail(e, err.c_str());
+        }
+        VLS_HIP(hipStreamSynchronize(s), "scene build");
+        float host_bounds[16];
+        VLS_HIP(hipMemcpy(host_bounds, b.bounds, sizeof host_bounds, hipMemcpyDeviceToHost), "scene stats");
+        vls_scene_stats& st = sc->stats;
+        st.n_vertices = nv;
+        st.n_triangles = nt;
+        st.n_internal_nodes = nt > 0 ? nt - 1 : 0;
+        st.device_bytes = bytes;
+        unsigned depth;
+        memcpy(&depth, &host_bounds[13], 4);
+        st.max_depth = nt > 0 ? (int32_t)depth : 0;
+        st.max_supported_depth = ctx->cfg.stack_lds + kMaxSpill - 1;
+        for (int a = 0; a < 3; ++a) {
+            st.bounds_lo[a] = host_bounds[a];
+            st.bounds_hi[a] = host_bounds[3 + a];
+        }
+        st.box_pad = 0.0f;
+        sc->root = nt >= 2 ? 0 : (nt == 1 ? ~0 : -1);
+        *out = sc.release();
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
+vls_status vls_scene_update_vertices(vls_scene scene, const float* vertices_dev, void* stream)
+{
+    if (!scene || (!vertices_dev && scene->b.n_vert > 0)) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+    if (!aligned(vertices_dev, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned vertices");
+    hipStream_t s = (hipStream_t)stream;
+    if (scene->b.n_vert > 0)
+        VLS_HIP(hipMemcpyAsync(scene->b.verts, vertices_dev, 12 * (size_t)scene->b.n_vert, hipMemcpyDeviceToDevice, s),
+                "vertex copy");
+    VLS_HIP(bvh_update_vertices(scene->b, s), "refit");
+    return VLS_OK;
+}
+
+vls_status vls_scene_update_reflectance(vls_scene scene, const float* reflectance_dev, void* stream)
+{
+    if (!scene || (!reflectance_dev && scene->b.n_tri > 0)) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+    if (scene->b.n_tri > 0)
+        VLS_HIP(hipMemcpyAsync(scene->b.refl, reflectance_dev, 4 * (size_t)scene->b.n_tri, hipMemcpyDeviceToDevice,
+                               (hipStream_t)stream),
+                "reflectance copy");
+    return VLS_OK;
+}
+
+vls_status vls_scene_stats_get(vls_scene scene, vls_scene_stats* out)
+{
+    if (!scene || !out) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+    *out = scene->stats;
+    out->max_supported_depth = scene->ctx->cfg.stack_lds + kMaxSpill - 1;
+    return VLS_OK;
+}
+
+vls_status vls_scene_export(vls_scene scene, float* nodes, int32_t* leaf_tri, uint64_t* morton, int32_t* root)
+{
+    if (!scene) return fail(VLS_ERR_INVALID_ARG, "scene is NULL");
+    VLS_HIP(hipDeviceSynchronize(), "sync");
+    const int64_t nt = scene->b.n_tri;
+    if (nodes && nt > 1) VLS_HIP(hipMemcpy(nodes, scene->b.nodes, 64 * (size_t)(nt - 1), hipMemcpyDeviceToHost), "export");
+    if (leaf_tri && nt > 0) VLS_HIP(hipMemcpy(leaf_tri, scene->b.leaf_tri, 4 * (size_t)nt, hipMemcpyDeviceToHost), "export");
+    if (morton && nt > 0) VLS_HIP(hipMemcpy(morton, scene->b.morton, 8 * (size_t)nt, hipMemcpyDeviceToHost), "export");
+    if (root) *root = scene->root;
+    return VLS_OK;
+}
+
+vls_status vls_scene_destroy(vls_scene scene)
+{
+    if (!scene) return fail(VLS_ERR_INVALID_ARG, "scene is NULL");
+    delete scene;
+    return VLS_OK;
+}
+
+vls_status vls_trace(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
+                     const vls_pulse_batch* pulses, const vls_outputs* out, void* stream)
+{
+    try {
+        Prepared pr;
+        vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
+        if (st != VLS_OK) return st;
+        if ((st = check_scene(ctx, scene)) != VLS_OK) return st;
+        if ((st = check_outputs(out)) != VLS_OK) return st;
+        if (pulses->n_pulses > 0 && !out->subray_tri) return fail(VLS_ERR_INVALID_ARG, "subray_tri is required");
+        OutDev od = out_dev(out, pr.S_stride);
+        PulsesDev pd = pulses_dev(pulses);
+        SceneDev sd = scene_dev(scene);
+        for (size_t s = 0; s + 1 < pr.off.size(); ++s) {
+            hipError_t e = launch_simulate(sd, pr.sc[pr.seg_sc[s]], pd, od, pr.off[s], pr.off[s + 1] - pr.off[s], 0,
+                                           ctx->cfg, (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "trace launch");
+        }
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
+static vls_status wave_common(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners,
+                              const vls_pulse_batch* pulses, const vls_outputs* out, void* stream, int mode)
+{
+    try {
+        Prepared pr;
+        vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
+        if (st != VLS_OK) return st;
+        if ((st = check_outputs(out)) != VLS_OK) return st;
+        if (pulses->n_pulses > 0) {
+            if (mode == 0 && (!out->subray_tri || !out->subray_range || !out->subray_power || !out->waveform))
+                return fail(VLS_ERR_INVALID_ARG, "waveform needs subray_tri, subray_range, subray_power and waveform");
+            if (mode == 1 && (!out->waveform || !out->window_t0_ns || !out->n_returns || !out->ret_range ||
+                              !out->ret_amplitude || !out->ret_bin))
+                return fail(VLS_ERR_INVALID_ARG, "returns need waveform, window_t0_ns and the return arrays");
+        }
+        OutDev od = out_dev(out, pr.S_stride);
+        PulsesDev pd = pulses_dev(pulses);
+        for (size_t s = 0; s + 1 < pr.off.size(); ++s) {
+            hipError_t e = launch_waveform(pr.sc[pr.seg_sc[s]], pd, od, pr.off[s], pr.off[s + 1] - pr.off[s], mode,
+                                           ctx->cfg, (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "waveform launch");
+        }
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
+vls_status vls_waveform(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners,
+                        const vls_pulse_batch* pulses, const vls_outputs* out, void* stream)
+{
+    return wave_common(ctx, scanners, n_scanners, pulses, out, stream, 0);
+}
+
+vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners,
+                       const vls_pulse_batch* pulses, const vls_outputs* out, void* stream)
+{
+    return wave_common(ctx, scanners, n_scanners, pulses, out, stream, 1);
+}
+
+vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
+                        const vls_pulse_batch* pulses, const vls_outputs* out, void* stream)
+{
+    try {
+        Prepared pr;
+        vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
+        if (st != VLS_OK) return st;
+        if ((st = check_scene(ctx, scene)) != VLS_OK) return st;
+        if ((st = check_outputs(out)) != VLS_OK) return st;
+        if (pulses->n_pulses > 0 && (!out->n_returns || !out->ret_range || !out->ret_amplitude || !out->ret_bin))
+            return fail(VLS_ERR_INVALID_ARG, "simulate needs n_returns, ret_range, ret_amplitude and ret_bin");
+        if (pulses->n_pulses == 0) return VLS_OK;
+        OutDev od = out_dev(out, pr.S_stride);
+        PulsesDev pd = pulses_dev(pulses);
+        SceneDev sd = scene_dev(scene);
+        hipStream_t s = (hipStream_t)stream;
+        if (pulses->n_segments <= 0) {
+            hipError_t e = launch_simulate(sd, pr.sc[0], pd, od, 0, pulses->n_pulses, 1, ctx->cfg, s);
+            return e == hipSuccess ? VLS_OK : hip_fail(e, "simulate launch");
+        }
+        vls_context_s::Batch* bt = nullptr;
+        if ((st = batch_tables(ctx, pr, bt)) != VLS_OK) return st;
+        int blocks = ctx->cfg.persistent_blocks > 0 ? ctx->cfg.persistent_blocks
+                                                    : persistent_occupancy_blocks(pr.n_bins, ctx->cfg);
+        hipError_t e = launch_persistent(sd, bt->bd, pr.n_bins, pd, od, ctx->cfg, blocks, s);
+        return e == hipSuccess ? VLS_OK : hip_fail(e, "persistent launch");
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
+vls_status vls_trace_counts(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
+                            const vls_pulse_batch* pulses, uint64_t* counts, void* stream)
+{
+    try {
+        Prepared pr;
+        vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
+        if (st != VLS_OK) return st;
+        if ((st = check_scene(ctx, scene)) != VLS_OK) return st;
+        if (!counts) return fail(VLS_ERR_INVALID_ARG, "counts is NULL");
+        hipStream_t s = (hipStream_t)stream;
+        unsigned long long* dc = nullptr;
+        VLS_HIP(hipMalloc(&dc, 3 * sizeof(unsigned long long)), "counts alloc");
+        hipError_t e = launch_fill_u64(dc, 3, 0ull, s);
+        vls_outputs none;
+        memset(&none, 0, sizeof none);
+        OutDev od = out_dev(&none, pr.S_stride);
+        od.counts = dc;
+        PulsesDev pd = pulses_dev(pulses);
+        SceneDev sd = scene_dev(scene);
+        for (size_t g = 0; e == hipSuccess && g + 1 < pr.off.size(); ++g)
+            e = launch_simulate(sd, pr.sc[pr.seg_sc[g]], pd, od, pr.off[g], pr.off[g + 1] - pr.off[g], 2, ctx->cfg, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        unsigned long long h[3] = {0, 0, 0};
+        if (e == hipSuccess) e = hipMemcpy(h, dc, sizeof h, hipMemcpyDeviceToHost);
+        (void)hipFree(dc);
+        if (e != hipSuccess) return hip_fail(e, "trace counts");
+        for (int i = 0; i < 3; ++i) counts[i] = h[i];
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
+vls_status vls_synchronize(vls_context ctx, void* stream)
+{
+    if (!ctx) return fail(VLS_ERR_INVALID_ARG, "context is NULL");
+    VLS_HIP(hipStreamSynchronize((hipStream_t)stream), "synchronize");
+    VLS_HIP(hipGetLastError(), "device error");
+    return VLS_OK;
+}
+
+}  // extern "C"

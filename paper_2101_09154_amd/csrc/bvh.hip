@@ -1,0 +1,469 @@
+// Linear BVH over triangles for gfx950.
+//
+// The paper accelerates ray casting with a kD-tree searched recursively on the
+// CPU (Sec. 5.1).  Here the structure is a binary LBVH built entirely on the
+// GPU, one thread per triangle or node:
+//   1. vertex bounds and centroid bounds (ordered-integer atomics);
+//   2. 63-bit Morton codes of the centroids (21 bits per axis, one cell size);
+//   3. a stable LSD radix sort (8 bits per pass, 4096-key tiles, wave64
+//      ballot matching for stable in-tile ranks);
+//   4. the binary radix tree of Karras (2012), "Maximizing parallelism in the
+//      construction of BVHs, octrees, and k-d trees" (equal keys ordered by
+//      their sorted position);
+//   5. leaf records gathered in sorted order (48 B: three vertices + original id);
+//   6. child boxes written bottom-up into each parent, the second child to
+//      arrive continuing upward (device-scope acquire/release counters);
+//   7. the deepest leaf, which bounds the traversal stack.
+// Node boxes are exact FP32 bounds; the traversal pads them per ray.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "vls_internal.h"
+
+namespace vls {
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys
+constexpr int kScanThreads = 1024;
+
+__device__ __forceinline__ unsigned f2ord(float f)
+{
+    unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float ord2f(unsigned u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__global__ void k_fill_i32(int32_t* p, long long n, int32_t v)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u32(unsigned* p, long long n, unsigned v)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long long v)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ubounds[0..5] = vertex lo.xyz, hi.xyz; [6..11] = centroid lo.xyz, hi.xyz; [12] = max |coord|
+__global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ verts, const int32_t* __restrict__ tri,
+                                                long long n_tri, unsigned* __restrict__ ub)
+{
+    __shared__ unsigned s[13];
+    if (threadIdx.x < 13) s[threadIdx.x] = (threadIdx.x < 3 || (threadIdx.x >= 6 && threadIdx.x < 9)) ? 0xffffffffu : 0u;
+    __syncthreads();
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_tri) {
+        float c[3] = {0.f, 0.f, 0.f};
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        float mag = 0.f;
+        for (int q = 0; q < 3; ++q) {
+            long long v = tri[3 * i + q];
+            for (int a = 0; a < 3; ++a) {
+                float x = verts[3 * v + a];
+                lo[a] = fminf(lo[a], x);
+                hi[a] = fmaxf(hi[a], x);
+                c[a] += x;
+                mag = fmaxf(mag, fabsf(x));
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            c[a] *= (1.0f / 3.0f);
+            atomicMin(&s[a], f2ord(lo[a]));
+            atomicMax(&s[3 + a], f2ord(hi[a]));
+            atomicMin(&s[6 + a], f2ord(c[a]));
+            atomicMax(&s[9 + a], f2ord(c[a]));
+        }
+        atomicMax(&s[12], f2ord(mag));
+    }
+    __syncthreads();
+    if (threadIdx.x < 13) {
+        bool is_min = threadIdx.x < 3 || (threadIdx.x >= 6 && threadIdx.x < 9);
+        if (is_min) atomicMin(&ub[threadIdx.x], s[threadIdx.x]);
+        else atomicMax(&ub[threadIdx.x], s[threadIdx.x]);
+    }
+}
+
+__global__ void k_bounds_finish(const unsigned* __restrict__ ub, float* __restrict__ out)
+{
+    if (threadIdx.x < 13) out[threadIdx.x] = ord2f(ub[threadIdx.x]);
+}
+
+__device__ __forceinline__ unsigned long long spread3(unsigned long long x)
+{
+    x &= 0x1fffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ verts, const int32_t* __restrict__ tri,
+                                                long long n_tri, const float* __restrict__ bounds,
+                                                unsigned long long* __restrict__ keys, int32_t* __restrict__ vals)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tri) return;
+    unsigned long long q[3];
+    // one cell size for all axes (the longest centroid extent), so a flat
+    // scene's short axis does not get the same number of splits as the long ones
+    float ext = fmaxf(fmaxf(bounds[9] - bounds[6], bounds[10] - bounds[7]), bounds[11] - bounds[8]);
+    for (int a = 0; a < 3; ++a) {
+        float c = (verts[3 * (long long)tri[3 * i] + a] + verts[3 * (long long)tri[3 * i + 1] + a] +
+                   verts[3 * (long long)tri[3 * i + 2] + a]) * (1.0f / 3.0f);
+        float lo = bounds[6 + a];
+        float f = ext > 0.f ? (c - lo) / ext : 0.f;
+        f = fminf(fmaxf(f * 2097152.0f, 0.0f), 2097151.0f);
+        q[a] = (unsigned long long)f;
+    }
+    keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    vals[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------- radix sort
+
+__global__ __launch_bounds__(kSortThreads) void k_hist(const unsigned long long* __restrict__ keys, long long n,
+                                                       int shift, unsigned* __restrict__ hist, int n_tiles)
+{
+    __shared__ unsigned h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    long long base = (long long)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        long long idx = base + r * kSortThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(long long)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of `total` counts in one block (sizes here are <= 256 * tiles).
+__global__ __launch_bounds__(kScanThreads) void k_scan(unsigned* __restrict__ a, long long total)
+{
+    __shared__ unsigned s[kScanThreads];
+    long long chunk = (total + kScanThreads - 1) / kScanThreads;
+    long long b = threadIdx.x * chunk, e = b + chunk < total ? b + chunk : total;
+    unsigned sum = 0;
+    for (long long i = b; i < e; ++i) sum += a[i];
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        unsigned v = threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    unsigned run = s[threadIdx.x] - sum;
+    for (long long i = b; i < e; ++i) {
+        unsigned v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+__device__ __forceinline__ unsigned lanes_below(unsigned long long m)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_scatter(const unsigned long long* __restrict__ keys_in,
+                                                          const int32_t* __restrict__ vals_in,
+                                                          unsigned long long* __restrict__ keys_out,
+                                                          int32_t* __restrict__ vals_out, long long n, int shift,
+                                                          const unsigned* __restrict__ hist, int n_tiles)
+{
+    constexpr int W = kSortThreads / kWave;
+    __shared__ unsigned run[256];
+    __shared__ unsigned base[256];
+    __shared__ unsigned wc[W][256];
+    const int tid = threadIdx.x, w = tid / kWave;
+    run[tid] = 0;
+    base[tid] = hist[(long long)tid * n_tiles + blockIdx.x];
+    long long tile0 = (long long)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        long long idx = tile0 + r * kSortThreads + tid;
+        bool valid = idx < n;
+        unsigned long long key = valid ? keys_in[idx] : 0ull;
+        int32_t val = valid ? vals_in[idx] : 0;
+        unsigned d = (unsigned)(key >> shift) & 255u;
+        for (int q = 0; q < W; ++q) wc[q][tid] = 0;
+        unsigned long long m = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (d >> b) & 1u;
+            unsigned long long bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
+        unsigned rank = lanes_below(m);
+        __syncthreads();
+        if (valid && rank == 0) wc[w][d] = (unsigned)__popcll(m);
+        __syncthreads();
+        if (valid) {
+            unsigned pre = run[d];
+            for (int q = 0; q < w; ++q) pre += wc[q][d];
+            long long pos = (long long)base[d] + pre + rank;
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+        unsigned add = 0;
+        for (int q = 0; q < W; ++q) add += wc[q][tid];
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- hierarchy
+
+__device__ __forceinline__ int delta(const unsigned long long* __restrict__ k, long long n, long long i, long long j)
+{
+    if (j < 0 || j >= n) return -1;
+    unsigned long long a = k[i], b = k[j];
+    if (a == b) return 64 + __clzll((unsigned long long)(i ^ j));
+    return __clzll(a ^ b);
+}
+
+__device__ __forceinline__ float* node_words(float4* nodes, long long i) { return reinterpret_cast<float*>(nodes + 4 * i); }
+
+__global__ __launch_bounds__(256) void k_karras(const unsigned long long* __restrict__ k, long long n,
+                                                float4* __restrict__ nodes, int32_t* __restrict__ leaf_parent,
+                                                int32_t* __restrict__ node_parent)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int dir = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = delta(k, n, i, i - dir);
+    long long lmax = 2;
+    while (delta(k, n, i, i + lmax * dir) > dmin) lmax <<= 1;
+    long long l = 0;
+    for (long long t = lmax >> 1; t >= 1; t >>= 1)
+        if (delta(k, n, i, i + (l + t) * dir) > dmin) l += t;
+    long long j = i + l * dir;
+    int dnode = delta(k, n, i, j);
+    long long s = 0;
+    long long div = 2;
+    long long t;
+    do {
+        t = (l + div - 1) / div;
+        if (delta(k, n, i, i + (s + t) * dir) > dnode) s += t;
+        div <<= 1;
+    } while (t > 1);
+    long long gamma = i + s * dir + (dir < 0 ? -1 : 0);
+    long long lo = i < j ? i : j, hi = i < j ? j : i;
+    int left, right;
+    if (lo == gamma) { left = ~(int)gamma; leaf_parent[gamma] = (int32_t)i; }
+    else { left = (int)gamma; node_parent[gamma] = (int32_t)i; }
+    if (hi == gamma + 1) { right = ~(int)(gamma + 1); leaf_parent[gamma + 1] = (int32_t)i; }
+    else { right = (int)(gamma + 1); node_parent[gamma + 1] = (int32_t)i; }
+    float* w = node_words(nodes, i);
+    w[12] = __int_as_float(left);
+    w[13] = __int_as_float(right);
+    w[15] = 0.0f;
+    if (i == 0) node_parent[0] = -1;
+}
+
+__global__ __launch_bounds__(256) void k_parent_words(float4* __restrict__ nodes, const int32_t* __restrict__ node_parent,
+                                                      long long n_int)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_int) node_words(nodes, i)[14] = __int_as_float(node_parent[i]);
+}
+
+__global__ __launch_bounds__(256) void k_leaves(const float* __restrict__ verts, const int32_t* __restrict__ tri,
+                                                const int32_t* order, long long n,
+                                                float4* __restrict__ recs, int32_t* leaf_tri)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t o = order[i];
+    float v[3][3];
+    for (int q = 0; q < 3; ++q) {
+        long long vi = tri[3 * (long long)o + q];
+        v[q][0] = verts[3 * vi];
+        v[q][1] = verts[3 * vi + 1];
+        v[q][2] = verts[3 * vi + 2];
+    }
+    recs[3 * i + 0] = make_float4(v[0][0], v[0][1], v[0][2], __int_as_float(o));
+    recs[3 * i + 1] = make_float4(v[1][0], v[1][1], v[1][2], 0.0f);
+    recs[3 * i + 2] = make_float4(v[2][0], v[2][1], v[2][2], 0.0f);
+    if (leaf_tri) leaf_tri[i] = o;
+}
+
+__device__ __forceinline__ float ld_acq(const float* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bottom-up boxes: each leaf writes its box into its parent's slot; the second
+// child to arrive at a parent unions both slots and carries on upward.
+__global__ __launch_bounds__(256) void k_refit(const float4* __restrict__ recs, long long n, float4* nodes,
+                                               const int32_t* __restrict__ leaf_parent,
+                                               const int32_t* __restrict__ node_parent, int32_t* flags)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 a = recs[3 * i], b = recs[3 * i + 1], c = recs[3 * i + 2];
+    float box[6] = {fminf(fminf(a.x, b.x), c.x), fminf(fminf(a.y, b.y), c.y), fminf(fminf(a.z, b.z), c.z),
+                    fmaxf(fmaxf(a.x, b.x), c.x), fmaxf(fmaxf(a.y, b.y), c.y), fmaxf(fmaxf(a.z, b.z), c.z)};
+    int cur = ~(int)i;
+    int p = leaf_parent[i];
+    for (int guard = 0; p >= 0 && guard < 4096; ++guard) {
+        float* w = node_words(nodes, p);
+        int left = __float_as_int(w[12]);
+        int slot = (left == cur) ? 0 : 6;
+        for (int q = 0; q < 6; ++q)
+            __hip_atomic_store(&w[slot + q], box[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int old = __hip_atomic_fetch_add(&flags[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0) return;
+        int other = 6 - slot;
+        for (int q = 0; q < 3; ++q) box[q] = fminf(box[q], ld_acq(&w[other + q]));
+        for (int q = 3; q < 6; ++q) box[q] = fmaxf(box[q], ld_acq(&w[other + q]));
+        cur = p;
+        p = node_parent[p];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_depth(const int32_t* __restrict__ leaf_parent,
+                                               const int32_t* __restrict__ node_parent, long long n,
+                                               unsigned* __restrict__ depth)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int p = leaf_parent[i];
+    unsigned d = 0;
+    while (p >= 0 && d < 4096) {
+        ++d;
+        p = node_parent[p];
+    }
+    atomicMax(depth, d);
+}
+
+inline unsigned grid_for(long long n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+#define VLS_TRY(x)                         \
+    do {                                   \
+        hipError_t e_ = (x);               \
+        if (e_ != hipSuccess) return e_;   \
+    } while (0)
+
+static hipError_t bounds_pass(BvhBuffers& b, unsigned* ub, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(16), 0, stream, ub, 13ll, 0u);
+    // minima start at the largest ordered value
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(3), 0, stream, ub, 3ll, 0xffffffffu);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(3), 0, stream, ub + 6, 3ll, 0xffffffffu);
+    hipLaunchKernelGGL(k_bounds, dim3(grid_for(b.n_tri, 256)), dim3(256), 0, stream, b.verts, b.tri_idx, b.n_tri, ub);
+    hipLaunchKernelGGL(k_bounds_finish, dim3(1), dim3(64), 0, stream, ub, b.bounds);
+    return hipGetLastError();
+}
+
+hipError_t bvh_build(BvhBuffers& b, hipStream_t stream, std::string& err)
+{
+    const long long n = b.n_tri;
+    if (n == 0) return hipSuccess;
+    const int n_tiles = (int)((n + kSortTile - 1) / kSortTile);
+    unsigned long long* keys2 = nullptr;
+    int32_t *vals = nullptr, *vals2 = nullptr;
+    unsigned *hist = nullptr, *ub = nullptr;
+    hipError_t e = hipSuccess;
+    auto fail = [&](hipError_t x, const char* what) {
+        err = std::string(what) + ": " + hipGetErrorString(x);
+        return x;
+    };
+    do {
+        if ((e = hipMalloc(&keys2, sizeof(unsigned long long) * n)) != hipSuccess) { (void)fail(e, "alloc keys"); break; }
+        if ((e = hipMalloc(&vals, sizeof(int32_t) * n)) != hipSuccess) { (void)fail(e, "alloc vals"); break; }
+        if ((e = hipMalloc(&vals2, sizeof(int32_t) * n)) != hipSuccess) { (void)fail(e, "alloc vals"); break; }
+        if ((e = hipMalloc(&hist, sizeof(unsigned) * 256 * (size_t)n_tiles)) != hipSuccess) { (void)fail(e, "alloc hist"); break; }
+        if ((e = hipMalloc(&ub, sizeof(unsigned) * 16)) != hipSuccess) { (void)fail(e, "alloc bounds"); break; }
+        if ((e = bounds_pass(b, ub, stream)) != hipSuccess) { (void)fail(e, "bounds"); break; }
+        hipLaunchKernelGGL(k_morton, dim3(grid_for(n, 256)), dim3(256), 0, stream, b.verts, b.tri_idx, n, b.bounds,
+                           b.morton, vals);
+        unsigned long long *kin = b.morton, *kout = keys2;
+        int32_t *vin = vals, *vout = vals2;
+        for (int pass = 0; pass < 8; ++pass) {
+            int shift = 8 * pass;
+            hipLaunchKernelGGL(k_hist, dim3(n_tiles), dim3(kSortThreads), 0, stream, kin, n, shift, hist, n_tiles);
+            hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, stream, hist, 256ll * n_tiles);
+            hipLaunchKernelGGL(k_scatter, dim3(n_tiles), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n, shift,
+                               hist, n_tiles);
+            unsigned long long* tk = kin; kin = kout; kout = tk;
+            int32_t* tv = vin; vin = vout; vout = tv;
+        }
+        // 8 passes: the sorted data is back in b.morton / vals
+        if ((e = hipGetLastError()) != hipSuccess) { (void)fail(e, "sort"); break; }
+        if (n > 1) {
+            hipLaunchKernelGGL(k_karras, dim3(grid_for(n - 1, 256)), dim3(256), 0, stream, b.morton, n, b.nodes,
+                               b.leaf_parent, b.node_parent);
+            hipLaunchKernelGGL(k_parent_words, dim3(grid_for(n - 1, 256)), dim3(256), 0, stream, b.nodes,
+                               b.node_parent, n - 1);
+        } else {
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, b.leaf_parent, 1ll, -1);
+        }
+        hipLaunchKernelGGL(k_leaves, dim3(grid_for(n, 256)), dim3(256), 0, stream, b.verts, b.tri_idx, vals, n, b.tris,
+                           b.leaf_tri);
+        if ((e = hipGetLastError()) != hipSuccess) { (void)fail(e, "hierarchy"); break; }
+        if ((e = bvh_refit(b, stream)) != hipSuccess) { (void)fail(e, "refit"); break; }
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, stream, reinterpret_cast<unsigned*>(b.bounds + 13), 1ll, 0u);
+        hipLaunchKernelGGL(k_depth, dim3(grid_for(n, 256)), dim3(256), 0, stream, b.leaf_parent, b.node_parent, n,
+                           reinterpret_cast<unsigned*>(b.bounds + 13));
+        if ((e = hipGetLastError()) != hipSuccess) { (void)fail(e, "depth"); break; }
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) { (void)fail(e, "build"); break; }
+    } while (0);
+    (void)hipFree(keys2);
+    (void)hipFree(vals);
+    (void)hipFree(vals2);
+    (void)hipFree(hist);
+    (void)hipFree(ub);
+    return e;
+}
+
+hipError_t bvh_refit(BvhBuffers& b, hipStream_t stream)
+{
+    const long long n = b.n_tri;
+    if (n == 0) return hipSuccess;
+    unsigned* ub = reinterpret_cast<unsigned*>(b.bounds + 16);  // scratch words after the results
+    VLS_TRY(bounds_pass(b, ub, stream));
+    if (n > 1) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n - 1, 256)), dim3(256), 0, stream, b.flags, n - 1, 0);
+        hipLaunchKernelGGL(k_refit, dim3(grid_for(n, 256)), dim3(256), 0, stream, b.tris, n, b.nodes, b.leaf_parent,
+                           b.node_parent, b.flags);
+    }
+    return hipGetLastError();
+}
+
+// Leaf records from new vertices (same sorted order), then boxes.
+hipError_t bvh_update_vertices(BvhBuffers& b, hipStream_t stream)
+{
+    const long long n = b.n_tri;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_leaves, dim3(grid_for(n, 256)), dim3(256), 0, stream, b.verts, b.tri_idx, b.leaf_tri, n,
+                       b.tris, (int32_t*)nullptr);
+    VLS_TRY(hipGetLastError());
+    return bvh_refit(b, stream);
+}
+
+}  // namespace vls

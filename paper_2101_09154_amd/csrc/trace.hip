@@ -1,0 +1,678 @@
+// The fused hot path on gfx950: subrays -> closest hit -> return power ->
+// waveform -> returns, one wavefront per floor(64/S) pulses, one subray per lane.
+//
+// Subrays (Sec. 3.4, Fig. 6): the lane of subray k builds its direction in FP64
+// from the pulse direction and a per-scanner table (cos a, sin a, cos phi,
+// sin phi, weight) computed on the host:  d_k = cos a d + sin a (cos phi u +
+// sin phi v), (u, v) the orthonormal basis of Duff et al. (2017).
+//
+// Closest hit (Sec. 3.4: a hit ends the subray; Sec. 5.1: minimum-distance
+// intersection): LBVH traversal, near child first, boxes tested in FP32 against
+// a per-ray padding that covers the rounding of the FP32 ray, so no box that
+// holds the FP64 closest hit is culled.  Leaves are tested in FP64 with the
+// watertight test of Woop, Benthin & Wald (2013) (two-sided, inclusive edges,
+// t > 0), so no subray slips through a shared edge and hit selection is the
+// exact-arithmetic result up to FP64 rounding.  Equal distances go to the lower triangle index.  The
+// traversal stack is a per-lane ring in LDS that spills its oldest entries to
+// per-lane scratch when it is full.
+//
+// Power (Sec. 5.2, Eq. 7 with a Lambertian extended target):
+//   P_k = P0 w_k (eta D^2 / 4) rho cos(theta) / R^2,  cos(theta) = |d_k . n|.
+//
+// Waveform (Sec. 3.4, Eq. 3 or a Gaussian pulse): the window starts t_pre
+// before the pulse's first two-way travel time tau = 2R/c; lane l owns bins
+// l + 64 m; each bin sums P_k p(t0 + j bin - tau_k) over the pulse's subrays,
+// read from LDS, in fixed k order (deterministic).  Offsets are formed in FP64
+// and split into two FP32 parts so the FP32 pulse argument keeps FP64 accuracy.
+// Only chunks of 64 bins that some subray's pulse support reaches are summed.
+//
+// Returns (Sec. 3.4 local maxima): bin j in [1, n-2] is a return if
+// wf[j] > wf[j-1], wf[j] >= wf[j+1] and wf[j] >= max(abs, rel * max wf);
+// neighbours come through lane shuffles, a ballot gives each return its slot,
+// the first K in time order are kept, and each is attributed to the subray
+// contributing most at its bin (lowest subray index on ties).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "vls_internal.h"
+
+namespace vls {
+namespace {
+
+struct WaveLds {
+    double tau[kWave];
+    float hi[kWave];
+    float lo[kWave];
+    float pw[kWave];
+    int tri[kWave];
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_min_d(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max_f(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ unsigned lanes_below(unsigned long long m)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+struct Ray {
+    double O[3];
+    double D[3];
+    double Sx, Sy, Sz;  // shear of the watertight test: the ray runs along +kz
+    int kx, ky, kz;
+    float inv[3];
+    float oim[3];  // (O + pad) * inv : lower planes moved outward
+    float oip[3];  // (O - pad) * inv : upper planes moved outward
+};
+
+// Duff et al. 2017 orthonormal basis; FP64 subray direction; FP32 slab constants.
+// FP contraction is off wherever FP64 results decide a hit, so every product
+// and sum is rounded exactly as written.
+__device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const float* __restrict__ d32,
+                                          const double* __restrict__ pat, float scene_mag, Ray& r)
+{
+#pragma clang fp contract(off)
+    double dx = d32[0], dy = d32[1], dz = d32[2];
+    double len = sqrt(dx * dx + dy * dy + dz * dz);
+    if (!(len > 0.0) || !(len < INFINITY)) return false;
+    double n[3] = {dx / len, dy / len, dz / len};
+    double sgn = copysign(1.0, n[2]);
+    double a = -1.0 / (sgn + n[2]);
+    double b = n[0] * n[1] * a;
+    double u[3] = {1.0 + sgn * n[0] * n[0] * a, sgn * b, -sgn * n[0]};
+    double v[3] = {b, sgn + n[1] * n[1] * a, -n[1]};
+    double ca = pat[0], sa = pat[1], cp = pat[2], sp = pat[3];
+    double omax = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        r.D[i] = ca * n[i] + sa * (cp * u[i] + sp * v[i]);
+        r.O[i] = o[i];
+        omax = fmax(omax, fabs(o[i]));
+    }
+    if (!(omax < INFINITY)) return false;
+    int kz = 0;
+    if (fabs(r.D[1]) > fabs(r.D[kz])) kz = 1;
+    if (fabs(r.D[2]) > fabs(r.D[kz])) kz = 2;
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    if (r.D[kz] < 0.0) {
+        int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    r.Sx = r.D[kx] / r.D[kz];
+    r.Sy = r.D[ky] / r.D[kz];
+    r.Sz = 1.0 / r.D[kz];
+    // pad covers the FP32 rounding of origin, direction and slab arithmetic
+    double pad = (omax + (double)scene_mag + 1.0) * 1.9073486328125e-06;  // 2^-19
+    for (int i = 0; i < 3; ++i) {
+        float di = (float)r.D[i];
+        if (fabsf(di) < 1e-30f) di = copysignf(1e-30f, di);
+        float inv = 1.0f / di;
+        r.inv[i] = inv;
+        r.oim[i] = (float)(r.O[i] + pad) * inv;
+        r.oip[i] = (float)(r.O[i] - pad) * inv;
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool box_hit(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz,
+                                        float tcull, float& tn)
+{
+    float ax = fmaf(lx, r.inv[0], -r.oim[0]), bx = fmaf(hx, r.inv[0], -r.oip[0]);
+    float ay = fmaf(ly, r.inv[1], -r.oim[1]), by = fmaf(hy, r.inv[1], -r.oip[1]);
+    float az = fmaf(lz, r.inv[2], -r.oim[2]), bz = fmaf(hz, r.inv[2], -r.oip[2]);
+    float n0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+    float f0 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tcull));
+    tn = n0;
+    return n0 <= f0;
+}
+
+struct Hit {
+    double t;
+    int leaf;
+    int orig;
+};
+
+__device__ __forceinline__ double pick(double x, double y, double z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
+
+// Watertight ray/triangle test (Woop, Benthin & Wald 2013) in FP64, two-sided,
+// inclusive edges: the triangle is translated to the ray origin and sheared so
+// the ray runs along +kz; the 2-D edge functions U, V, W are then evaluated from
+// the same operands for both triangles of a shared edge, so no ray slips
+// between them.  t = T / det is formed only for candidates inside the triangle.
+__device__ __forceinline__ void leaf_test(const Ray& r, const float4* __restrict__ tris, int li, Hit& h, float& tcull)
+{
+#pragma clang fp contract(off)
+    float4 Pa = tris[3 * li], Pb = tris[3 * li + 1], Pc = tris[3 * li + 2];
+    int orig = __float_as_int(Pa.w);
+    double a0 = (double)Pa.x - r.O[0], a1 = (double)Pa.y - r.O[1], a2 = (double)Pa.z - r.O[2];
+    double b0 = (double)Pb.x - r.O[0], b1 = (double)Pb.y - r.O[1], b2 = (double)Pb.z - r.O[2];
+    double c0 = (double)Pc.x - r.O[0], c1 = (double)Pc.y - r.O[1], c2 = (double)Pc.z - r.O[2];
+    double Az = pick(a0, a1, a2, r.kz), Bz = pick(b0, b1, b2, r.kz), Cz = pick(c0, c1, c2, r.kz);
+    double Ax = pick(a0, a1, a2, r.kx) - r.Sx * Az, Ay = pick(a0, a1, a2, r.ky) - r.Sy * Az;
+    double Bx = pick(b0, b1, b2, r.kx) - r.Sx * Bz, By = pick(b0, b1, b2, r.ky) - r.Sy * Bz;
+    double Cx = pick(c0, c1, c2, r.kx) - r.Sx * Cz, Cy = pick(c0, c1, c2, r.ky) - r.Sy * Cz;
+    double U = Cx * By - Cy * Bx;
+    double V = Ax * Cy - Ay * Cx;
+    double W = Bx * Ay - By * Ax;
+    if ((U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0)) return;
+    double det = U + V + W;
+    if (det == 0.0) return;
+    double T = U * (r.Sz * Az) + V * (r.Sz * Bz) + W * (r.Sz * Cz);
+    double t = T / det;
+    if (!(t > 0.0)) return;
+    if (t < h.t || (t == h.t && orig < h.orig)) {
+        h.t = t;
+        h.orig = orig;
+        h.leaf = li;
+        float tf = (float)t;
+        if ((double)tf < t) tf = nextafterf(tf, INFINITY);
+        tcull = tf;
+    }
+}
+
+// Closest hit of one ray.  ring: this block's LDS ring, stride = blockDim.x.
+// COUNT: also count internal-node visits and triangle tests.
+template <bool COUNT>
+__device__ __forceinline__ Hit traverse(const SceneDev& scene, const Ray& r, int* __restrict__ ring, int ring_mask,
+                                        int& visits, int& tests)
+{
+    Hit h;
+    h.t = INFINITY;
+    h.leaf = -1;
+    h.orig = 0x7fffffff;
+    float tcull = INFINITY;
+    const int stride = blockDim.x;
+    int* my = ring + threadIdx.x;
+    int spill[kMaxSpill];
+    int sp = 0, nlow = 0;
+    int node = scene.root;
+    const float4* __restrict__ nodes = scene.nodes;
+    // a traversal visits each of the 2n-1 nodes at most once; the cap and the
+    // range checks only matter for a corrupted structure, which must not hang
+    // or read out of bounds
+    const int n_int = scene.n_tri - 1;
+    int budget = 2 * scene.n_tri + 64;
+    while (--budget > 0) {
+        if (node >= n_int || ~node >= scene.n_tri) break;
+        if (node >= 0) {
+            if (COUNT) ++visits;
+            const float4* nd = nodes + 4 * node;
+            float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+            float tl, tr;
+            bool hl = box_hit(r, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl);
+            bool hr = box_hit(r, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr);
+            int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
+            if (hl && hr) {
+                int nearc = (tl <= tr) ? cl : cr;
+                int farc = (tl <= tr) ? cr : cl;
+                if (sp - nlow > ring_mask) {
+                    // the host guarantees depth <= ring + kMaxSpill - 1; the guard keeps
+                    // a violated guarantee from writing past the array
+                    if (nlow < kMaxSpill) spill[nlow] = my[(nlow & ring_mask) * stride];
+                    ++nlow;
+                }
+                my[(sp & ring_mask) * stride] = farc;
+                ++sp;
+                node = nearc;
+                continue;
+            }
+            if (hl) { node = cl; continue; }
+            if (hr) { node = cr; continue; }
+        } else {
+            if (COUNT) ++tests;
+            leaf_test(r, scene.tris, ~node, h, tcull);
+        }
+        if (sp == 0) break;
+        --sp;
+        if (sp < nlow) {
+            node = sp < kMaxSpill ? spill[sp] : -1;
+            nlow = sp;
+        } else {
+            node = my[(sp & ring_mask) * stride];
+        }
+    }
+    return h;
+}
+
+__device__ __forceinline__ float pulse_shape(const ScannerDev& sc, float s)
+{
+    if (sc.shape == 0) return exp2f(s * s * sc.neg_k);
+    float x = s * sc.inv_tau;
+    return s > 0.0f ? x * x * exp2f(x * sc.neg_k) : 0.0f;
+}
+
+// Incidence and power of the chosen triangle (Sec. 5.2, Eq. 7):
+// cos = |d . n| / |n|, P = C w rho cos / R^2, all in FP64 as written.
+__device__ __forceinline__ void shade(const SceneDev& scene, const ScannerDev& sc, const Ray& r, const Hit& h,
+                                      double w, double& cosang, double& P)
+{
+#pragma clang fp contract(off)
+    float4 A = scene.tris[3 * h.leaf], B = scene.tris[3 * h.leaf + 1], C = scene.tris[3 * h.leaf + 2];
+    double e1x = (double)B.x - A.x, e1y = (double)B.y - A.y, e1z = (double)B.z - A.z;
+    double e2x = (double)C.x - A.x, e2y = (double)C.y - A.y, e2z = (double)C.z - A.z;
+    double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+    double c = fabs(r.D[0] * nx + r.D[1] * ny + r.D[2] * nz) / sqrt(nx * nx + ny * ny + nz * nz);
+    cosang = c;
+    P = sc.power_c * w * (double)scene.refl[h.orig] * c / (h.t * h.t);
+}
+
+// Trace one lane's subray: fills tri (original index or -1), R, cos, P.
+template <bool COUNT>
+__device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
+                                           long long p, int k, int* ring, int ring_mask,
+                                           int& tri, double& R, float& cosang, float& P, int& visits, int& tests)
+{
+    tri = -1;
+    R = INFINITY;
+    cosang = 0.0f;
+    P = 0.0f;
+    if (scene.n_tri <= 0) return;
+    const double* pat = sc.pattern + 5 * k;
+    Ray r;
+    if (!setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, pat, scene.bounds[12], r)) return;
+    Hit h = traverse<COUNT>(scene, r, ring, ring_mask, visits, tests);
+    if (h.leaf < 0) return;
+    double c, pw;
+    shade(scene, sc, r, h, pat[4], c, pw);
+    tri = h.orig;
+    R = h.t;
+    cosang = (float)c;
+    P = (float)pw;
+}
+
+// Waveform and/or returns of one pulse whose subrays sit in wl[k0 .. k0+S).
+// COMPUTE: synthesise wf from the subrays (else load wf and t0 from `out`).
+// RET: detect returns.  attrib: subray data present for return attribution.
+template <int MAXCH, bool COMPUTE, bool RET>
+__device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
+                                            long long p, int k0, WaveLds* wl, bool attrib)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int S = sc.S, nb = sc.n_bins, K = sc.K;
+    const bool mine = lane >= k0 && lane < k0 + S;
+    double t0;
+    bool any;
+    if (COMPUTE || attrib) {
+        double tmin = wave_min_d(mine ? wl->tau[lane] : INFINITY);
+        any = tmin < INFINITY;
+        if (COMPUTE) {
+            if (pulses.t0_in) t0 = pulses.t0_in[p];
+            else t0 = any ? tmin - sc.t_pre : (double)NAN;
+        } else {
+            t0 = out.t0[p];
+        }
+    } else {
+        t0 = out.t0[p];
+        any = true;
+    }
+    bool have = any && !isnan(t0);
+    float wf[MAXCH];
+    int bk[MAXCH];
+#pragma unroll
+    for (int c = 0; c < MAXCH; ++c) {
+        wf[c] = 0.0f;
+        bk[c] = -1;
+    }
+    if (!COMPUTE) {
+#pragma unroll
+        for (int c = 0; c < MAXCH; ++c) {
+            int j = c * kWave + lane;
+            if (j < nb) wf[c] = out.wf[p * nb + j];
+        }
+    }
+    // chunks of 64 bins that can hold a non-zero value (all of them for a loaded waveform)
+    int c_lo = 0, c_hi = MAXCH - 1;
+    if (have && (COMPUTE || attrib)) {
+        int jl = 0x7fffffff, jh = -0x7fffffff;
+        if (mine && wl->tri[lane] >= 0) {
+            double rel = wl->tau[lane] - t0;
+            float hi = (float)rel;
+            wl->hi[lane] = hi;
+            wl->lo[lane] = (float)(rel - (double)hi);
+            double a = ceil((rel - sc.cut_lo) / sc.bin_ns), b = floor((rel + sc.cut_hi) / sc.bin_ns);
+            jl = (int)fmax(fmin(a, 1e9), -1e9);
+            jh = (int)fmax(fmin(b, 1e9), -1e9);
+        }
+        wave_sync();
+        jl = max(wave_min_i(jl), 0);
+        jh = min(wave_max_i(jh), nb - 1);
+        if (COMPUTE) {
+            c_lo = jl >> 6;
+            c_hi = jl <= jh ? jh >> 6 : -1;
+        }
+#pragma unroll
+        for (int c = 0; c < MAXCH; ++c) {
+            const int cb = c * kWave;
+            if (cb < nb && cb <= jh && cb + kWave - 1 >= jl) {
+                int j = cb + lane;
+                double xd = (double)j * sc.bin_ns;
+                float xh = (float)xd, xl = (float)(xd - (double)xh);
+                float acc = 0.0f, best = -1.0f;
+                int bki = -1;
+                for (int kk = 0; kk < S; ++kk) {
+                    if (wl->tri[k0 + kk] < 0) continue;
+                    float s = (xh - wl->hi[k0 + kk]) + (xl - wl->lo[k0 + kk]);
+                    float val = wl->pw[k0 + kk] * pulse_shape(sc, s);
+                    acc += val;
+                    if (val > best) {
+                        best = val;
+                        bki = kk;
+                    }
+                }
+                if (COMPUTE && j < nb) wf[c] = acc;
+                bk[c] = bki;
+            }
+        }
+    }
+    if (COMPUTE) {
+        if (out.wf) {
+#pragma unroll
+            for (int c = 0; c < MAXCH; ++c) {
+                int j = c * kWave + lane;
+                if (j < nb) out.wf[p * nb + j] = wf[c];
+            }
+        }
+        if (lane == 0 && out.t0) out.t0[p] = t0;
+    }
+    if (!RET) return;
+    int count = 0;
+    if (have) {
+        float m = 0.0f;
+#pragma unroll
+        for (int c = 0; c < MAXCH; ++c)
+            if (c >= c_lo && c <= c_hi) m = fmaxf(m, wf[c]);
+        m = wave_max_f(m);
+        float thr = fmaxf((float)sc.thr_abs, (float)(sc.thr_rel * (double)m));
+#pragma unroll
+        for (int c = 0; c < MAXCH; ++c) {
+            if (c * kWave >= nb) break;
+            if (c < c_lo || c > c_hi) continue;  // all zero: no return can start here
+            float v = wf[c];
+            float left = __shfl_up(v, 1);
+            float right = __shfl_down(v, 1);
+            float prev = c > 0 ? __shfl(wf[c > 0 ? c - 1 : 0], 63) : 0.0f;
+            float next = c + 1 < MAXCH ? __shfl(wf[c + 1 < MAXCH ? c + 1 : c], 0) : 0.0f;
+            if (lane == 0) left = prev;
+            if (lane == kWave - 1) right = next;
+            int j = c * kWave + lane;
+            bool cand = j >= 1 && j <= nb - 2 && v > left && v >= right && v >= thr;
+            unsigned long long mk = __ballot(cand);
+            int slot = count + (int)lanes_below(mk);
+            if (cand && slot < K) {
+                long long o = p * K + slot;
+                out.ret_range[o] = (float)(0.5 * kCmPerNs * (t0 + (double)j * sc.bin_ns - sc.s_peak));
+                out.ret_amp[o] = v;
+                out.ret_bin[o] = j;
+                if (out.ret_tri) out.ret_tri[o] = (attrib && bk[c] >= 0) ? wl->tri[k0 + bk[c]] : -1;
+            }
+            count += __popcll(mk);
+        }
+    }
+    int nret = count < K ? count : K;
+    if (lane >= nret && lane < K) {
+        long long o = p * K + lane;
+        out.ret_range[o] = 0.0f;
+        out.ret_amp[o] = 0.0f;
+        out.ret_bin[o] = -1;
+        if (out.ret_tri) out.ret_tri[o] = -1;
+    }
+    if (lane == 0) out.n_ret[p] = nret;
+}
+
+// One wavefront: pulses [first, first + npw) of one scanner.
+// MODE 0: trace only.  MODE 1: trace + waveform + returns (fused).
+// MODE 2: trace only, adding subrays / node visits / triangle tests to out.counts.
+template <int MAXCH, int MODE>
+__device__ __forceinline__ void process_wave(const SceneDev& scene, const ScannerDev& sc,
+                                             const PulsesDev& pulses, const OutDev& out, long long first, int npw,
+                                             int* ring, int ring_mask, WaveLds* wl)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int S = sc.S;
+    const int pl = lane / S;
+    const int k = lane - pl * S;
+    const bool active = pl < npw;
+    int tri = -1;
+    double R = INFINITY;
+    float cs = 0.0f, P = 0.0f;
+    int visits = 0, tests = 0;
+    if (active) {
+        long long p = first + pl;
+        trace_lane<MODE == 2>(scene, sc, pulses, p, k, ring, ring_mask, tri, R, cs, P, visits, tests);
+        long long o = p * out.sub_stride + k;
+        if (out.sub_tri) out.sub_tri[o] = tri;
+        if (out.sub_range) out.sub_range[o] = R;
+        if (out.sub_cos) out.sub_cos[o] = cs;
+        if (out.sub_power) out.sub_power[o] = P;
+    }
+    if (MODE == 2) {
+        unsigned long long a = active ? 1ull : 0ull, v = (unsigned long long)visits, t = (unsigned long long)tests;
+        for (int o = 32; o > 0; o >>= 1) {
+            a += __shfl_xor(a, o);
+            v += __shfl_xor(v, o);
+            t += __shfl_xor(t, o);
+        }
+        if (lane == 0) {
+            atomicAdd(out.counts, a);
+            atomicAdd(out.counts + 1, v);
+            atomicAdd(out.counts + 2, t);
+        }
+        return;
+    }
+    if (MODE == 0) return;
+    wl->tau[lane] = (active && tri >= 0) ? 2.0 * R / kCmPerNs : (double)INFINITY;
+    wl->pw[lane] = P;
+    wl->tri[lane] = active ? tri : -1;
+    wave_sync();
+    for (int q = 0; q < npw; ++q) pulse_phase<MAXCH, true, true>(sc, pulses, out, first + q, q * S, wl, true);
+}
+
+template <int MAXCH, int MODE>
+__global__ __launch_bounds__(256) void k_simulate(SceneDev scene, ScannerDev sc, PulsesDev pulses,
+                                                  OutDev out, long long first, long long count, int ring_mask)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int waves = blockDim.x / kWave;
+    WaveLds* wl = reinterpret_cast<WaveLds*>(smem) + threadIdx.x / kWave;
+    int* ring = reinterpret_cast<int*>(smem + sizeof(WaveLds) * waves);
+    long long wave = (long long)blockIdx.x * waves + threadIdx.x / kWave;
+    long long p0 = wave * sc.P_w;
+    if (p0 >= count) return;
+    long long left = count - p0;
+    int npw = left < sc.P_w ? (int)left : sc.P_w;
+    process_wave<MAXCH, MODE>(scene, sc, pulses, out, first + p0, npw, ring, ring_mask, wl);
+}
+
+// Waveform from stored subrays (KIND 0) or returns from stored waveforms (KIND 1).
+template <int MAXCH, int KIND>
+__global__ __launch_bounds__(256) void k_wave(ScannerDev sc, PulsesDev pulses, OutDev out, long long first,
+                                              long long count)
+{
+    __shared__ WaveLds lds[4];
+    WaveLds* wl = lds + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int waves = blockDim.x / kWave;
+    long long wave = (long long)blockIdx.x * waves + threadIdx.x / kWave;
+    long long p0 = wave * sc.P_w;
+    if (p0 >= count) return;
+    long long left = count - p0;
+    int npw = left < sc.P_w ? (int)left : sc.P_w;
+    const int S = sc.S;
+    const int pl = lane / S, k = lane - pl * S;
+    bool attrib = KIND == 0 || (out.sub_tri && out.sub_range && out.sub_power);
+    if (attrib) {
+        int tri = -1;
+        double R = INFINITY;
+        float P = 0.0f;
+        if (pl < npw) {
+            long long o = (first + p0 + pl) * out.sub_stride + k;
+            tri = out.sub_tri[o];
+            if (tri >= 0) {
+                R = out.sub_range[o];
+                P = out.sub_power[o];
+            }
+        }
+        wl->tau[lane] = tri >= 0 ? 2.0 * R / kCmPerNs : (double)INFINITY;
+        wl->pw[lane] = P;
+        wl->tri[lane] = tri;
+        wave_sync();
+    }
+    for (int q = 0; q < npw; ++q) {
+        if (KIND == 0) pulse_phase<MAXCH, true, false>(sc, pulses, out, first + p0 + q, q * S, wl, true);
+        else pulse_phase<MAXCH, false, true>(sc, pulses, out, first + p0 + q, q * S, wl, attrib);
+    }
+}
+
+// Persistent batched kernel: wavefronts take wave-tiles from a global counter.
+template <int MAXCH>
+__global__ __launch_bounds__(256) void k_persistent(SceneDev scene, BatchDev batch, PulsesDev pulses,
+                                                    OutDev out, int ring_mask)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int waves = blockDim.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    WaveLds* wl = reinterpret_cast<WaveLds*>(smem) + threadIdx.x / kWave;
+    int* ring = reinterpret_cast<int*>(smem + sizeof(WaveLds) * waves);
+    while (true) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(batch.counter, 1ull);
+        long long tile = (long long)__shfl((long long)t, 0);
+        if (tile >= batch.n_tiles) break;
+        int lo = 0, hi = batch.n_seg - 1;
+        while (lo < hi) {  // last segment whose first tile <= tile
+            int mid = (lo + hi + 1) >> 1;
+            if (batch.tile_off[mid] <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const ScannerDev sc = batch.scanners[batch.seg_scanner[lo]];
+        long long p = batch.pulse_off[lo] + (tile - batch.tile_off[lo]) * sc.P_w;
+        long long left = batch.pulse_end[lo] - p;
+        int npw = left < sc.P_w ? (int)left : sc.P_w;
+        process_wave<MAXCH, 1>(scene, sc, pulses, out, p, npw, ring, ring_mask, wl);
+        wave_sync();
+    }
+}
+
+inline size_t sim_lds_bytes(int block, int ring) { return sizeof(WaveLds) * (block / kWave) + sizeof(int) * (size_t)ring * block; }
+
+}  // namespace
+
+hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
+                           long long first, long long count, int mode, const LaunchCfg& cfg, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    const int block = cfg.block_waves * kWave;
+    long long waves = (count + sc.P_w - 1) / sc.P_w;
+    unsigned grid = (unsigned)((waves + cfg.block_waves - 1) / cfg.block_waves);
+    size_t lds = sim_lds_bytes(block, cfg.stack_lds);
+    int mask = cfg.stack_lds - 1;
+    if (mode == 0) {
+        hipLaunchKernelGGL((k_simulate<4, 0>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out, first,
+                           count, mask);
+    } else if (mode == 2) {
+        hipLaunchKernelGGL((k_simulate<4, 2>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out, first,
+                           count, mask);
+    } else if (sc.n_bins <= 256) {
+        hipLaunchKernelGGL((k_simulate<4, 1>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out, first,
+                           count, mask);
+    } else if (sc.n_bins <= 512) {
+        hipLaunchKernelGGL((k_simulate<8, 1>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out, first,
+                           count, mask);
+    } else {
+        hipLaunchKernelGGL((k_simulate<16, 1>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out,
+                           first, count, mask);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_waveform(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out, long long first,
+                           long long count, int mode, const LaunchCfg& cfg, hipStream_t stream)
+{
+    (void)cfg;
+    if (count <= 0) return hipSuccess;
+    const int block = 4 * kWave;
+    long long waves = (count + sc.P_w - 1) / sc.P_w;
+    unsigned grid = (unsigned)((waves + 3) / 4);
+#define VLS_WAVE_LAUNCH(CH)                                                                                  \
+    do {                                                                                                     \
+        if (mode == 0)                                                                                       \
+            hipLaunchKernelGGL((k_wave<CH, 0>), dim3(grid), dim3(block), 0, stream, sc, pulses, out, first, count); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_wave<CH, 1>), dim3(grid), dim3(block), 0, stream, sc, pulses, out, first, count); \
+    } while (0)
+    if (sc.n_bins <= 256) VLS_WAVE_LAUNCH(4);
+    else if (sc.n_bins <= 512) VLS_WAVE_LAUNCH(8);
+    else VLS_WAVE_LAUNCH(16);
+#undef VLS_WAVE_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, const PulsesDev& pulses,
+                             const OutDev& out, const LaunchCfg& cfg, int blocks, hipStream_t stream)
+{
+    const int block = cfg.block_waves * kWave;
+    size_t lds = sim_lds_bytes(block, cfg.stack_lds);
+    int mask = cfg.stack_lds - 1;
+    hipError_t e = launch_fill_u64(batch.counter, 1, 0ull, stream);
+    if (e != hipSuccess) return e;
+    if (max_bins <= 256)
+        hipLaunchKernelGGL((k_persistent<4>), dim3(blocks), dim3(block), lds, stream, scene, batch, pulses, out, mask);
+    else if (max_bins <= 512)
+        hipLaunchKernelGGL((k_persistent<8>), dim3(blocks), dim3(block), lds, stream, scene, batch, pulses, out, mask);
+    else
+        hipLaunchKernelGGL((k_persistent<16>), dim3(blocks), dim3(block), lds, stream, scene, batch, pulses, out, mask);
+    return hipGetLastError();
+}
+
+int persistent_occupancy_blocks(int max_bins, const LaunchCfg& cfg)
+{
+    const int block = cfg.block_waves * kWave;
+    size_t lds = sim_lds_bytes(block, cfg.stack_lds);
+    int per_cu = 0;
+    hipError_t e;
+    if (max_bins <= 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<4>, block, lds);
+    else if (max_bins <= 512) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<8>, block, lds);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<16>, block, lds);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus < 1) cus = 1;
+    return per_cu * cus;
+}
+
+}  // namespace vls

@@ -1,0 +1,125 @@
+// Internal types shared by the library's HIP translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace vls {
+
+constexpr double kCmPerNs = 0.299792458;  // speed of light in m/ns (Sec. 3.4)
+constexpr int kWave = 64;                 // CDNA wavefront
+constexpr int kMaxSpill = 112;            // traversal-stack entries per lane beyond the LDS ring
+constexpr int kMaxRing = 32;
+
+// One scanner as the kernels see it (everything derived on the host in FP64).
+struct ScannerDev {
+    const double* pattern;  // [S][5]: cos a, sin a, cos phi, sin phi, weight
+    int S;                  // subrays per pulse
+    int P_w;                // pulses per wavefront = 64 / S
+    int n_bins;
+    int K;
+    int shape;              // 0 Gaussian, 1 Eq. 3
+    float bin_ns;
+    float neg_k;            // Gaussian: -log2(e) / (2 sigma^2); Eq. 3: -log2(e)
+    float inv_tau;          // Eq. 3: 1 / tau
+    float cut_lo;           // a subray contributes to bins with s in [-cut_lo, cut_hi] ns
+    float cut_hi;
+    float pad_;
+    double t_pre;           // window starts t_pre before the first echo
+    double s_peak;          // peak offset of the pulse shape (0 Gaussian, 2 tau Eq. 3)
+    double power_c;         // peak * eff * D^2 / 4
+    double thr_abs;
+    double thr_rel;
+};
+
+// Binary LBVH: node = 4 x float4 (64 B): left box lo.xyz hi.x | hi.yz, right lo.xy |
+// right lo.z hi.xyz | refs (left, right, parent, 0) as int bits.  A ref >= 0 is an
+// internal node; ref < 0 is leaf ~ref.  Leaf record = 3 x float4 (48 B):
+// v0.xyz + original triangle index (int bits) | v1.xyz + 0 | v2.xyz + 0.
+struct SceneDev {
+    const float4* nodes;
+    const float4* tris;
+    const float* refl;      // by original triangle index
+    const float* bounds;    // [13]: vertex lo.xyz hi.xyz, centroid lo.xyz hi.xyz, max |coordinate|
+    int root;
+    int n_tri;
+};
+
+struct PulsesDev {
+    const double* origins;
+    const float* dirs;
+    const double* t0_in;    // may be null
+    long long n;
+};
+
+struct OutDev {
+    int32_t* sub_tri;
+    double* sub_range;
+    float* sub_cos;
+    float* sub_power;
+    int sub_stride;
+    int pad_;
+    float* wf;
+    double* t0;
+    int32_t* n_ret;
+    float* ret_range;
+    float* ret_amp;
+    int32_t* ret_tri;
+    int32_t* ret_bin;
+    unsigned long long* counts;  // diagnostic: subrays, node visits, triangle tests (mode 2)
+};
+
+// Segmented batch for the persistent kernel.
+struct BatchDev {
+    const long long* tile_off;    // [n_seg+1] first wave-tile of each segment
+    const long long* pulse_off;   // [n_seg] first pulse of each segment
+    const long long* pulse_end;   // [n_seg]
+    const int* seg_scanner;       // [n_seg]
+    const ScannerDev* scanners;   // [n_scanners]
+    unsigned long long* counter;  // work counter (reset before each launch)
+    int n_seg;
+    int pad_;
+    long long n_tiles;
+};
+
+struct LaunchCfg {
+    int block_waves = 1;
+    int stack_lds = 16;
+    int persistent_blocks = 0;
+};
+
+// ---- host-side launchers (defined in the .hip files) ----
+// All return hipSuccess or the first HIP error; kernels are enqueued on `stream`.
+
+struct BvhBuffers {
+    float4* nodes = nullptr;      // [max(n_tri-1,1)][4]
+    float4* tris = nullptr;       // [n_tri][3]
+    float* refl = nullptr;        // [n_tri]
+    float* verts = nullptr;       // [n_vert][3]
+    int32_t* tri_idx = nullptr;   // [n_tri][3]
+    int32_t* leaf_parent = nullptr;   // [n_tri]
+    int32_t* node_parent = nullptr;   // [n_tri-1]
+    int32_t* leaf_tri = nullptr;      // [n_tri] original index per leaf
+    unsigned long long* morton = nullptr;  // [n_tri] sorted keys
+    int32_t* flags = nullptr;         // [n_tri-1]
+    float* bounds = nullptr;          // [32]: [0..12] as in SceneDev, [13] depth (uint bits), [16..28] scratch
+    int64_t n_tri = 0, n_vert = 0;
+};
+
+hipError_t bvh_build(BvhBuffers& b, hipStream_t stream, std::string& err);
+hipError_t bvh_refit(BvhBuffers& b, hipStream_t stream);
+hipError_t bvh_update_vertices(BvhBuffers& b, hipStream_t stream);
+
+hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
+                           const OutDev& out, long long first, long long count, int mode,
+                           const LaunchCfg& cfg, hipStream_t stream);
+hipError_t launch_waveform(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
+                           long long first, long long count, int mode, const LaunchCfg& cfg, hipStream_t stream);
+hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, const PulsesDev& pulses,
+                             const OutDev& out, const LaunchCfg& cfg, int blocks, hipStream_t stream);
+hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);
+int persistent_occupancy_blocks(int max_bins, const LaunchCfg& cfg);
+
+}  // namespace vls

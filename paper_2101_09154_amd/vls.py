@@ -1,0 +1,360 @@
+"""Python binding of the C ABI in include/vls.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libvls.so``; torch is used for
+device memory and streams.  If the library is missing, every entry point
+raises: there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvls.so")
+
+OK = 0
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "device error", 4: "not built",
+          5: "unsupported", 6: "internal error"}
+MEM_HOST = 0
+MEM_DEVICE = 1
+PULSE_GAUSSIAN = 0
+PULSE_EQ3 = 1
+
+
+class VlsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+P = ctypes.c_void_p
+i32 = ctypes.c_int32
+i64 = ctypes.c_int64
+f64 = ctypes.c_double
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("vertices", P), ("triangles", P), ("reflectance", P), ("n_vertices", i64),
+                ("n_triangles", i64), ("memory", i32), ("reserved", i32)]
+
+
+class SceneStats(ctypes.Structure):
+    _fields_ = [("n_vertices", i64), ("n_triangles", i64), ("n_internal_nodes", i64), ("device_bytes", i64),
+                ("max_depth", i32), ("max_supported_depth", i32), ("bounds_lo", ctypes.c_float * 3),
+                ("bounds_hi", ctypes.c_float * 3), ("box_pad", ctypes.c_float), ("reserved", ctypes.c_float)]
+
+
+class ScannerDesc(ctypes.Structure):
+    _fields_ = [("divergence_rad", f64), ("pattern_extent", f64), ("pulse_width_ns", f64), ("bin_ns", f64),
+                ("window_pre_ns", f64), ("peak_power_w", f64), ("receiver_diameter_m", f64),
+                ("efficiency", f64), ("min_echo_abs", f64), ("min_echo_rel", f64), ("n_subrays", i32),
+                ("beam_quality", i32), ("pulse_shape", i32), ("n_bins", i32), ("max_returns", i32),
+                ("reserved", i32)]
+
+
+class PulseBatch(ctypes.Structure):
+    _fields_ = [("origins", P), ("directions", P), ("window_t0_ns", P), ("n_pulses", i64),
+                ("segment_offsets", P), ("segment_scanner", P), ("n_segments", i32), ("reserved", i32)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("subray_tri", P), ("subray_range", P), ("subray_cos", P), ("subray_power", P),
+                ("waveform", P), ("window_t0_ns", P), ("n_returns", P), ("ret_range", P),
+                ("ret_amplitude", P), ("ret_tri", P), ("ret_bin", P)]
+
+
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("block_waves", i32), ("stack_lds", i32), ("persistent_blocks", i32), ("reserved", i32)]
+
+
+_lib = None
+
+_SIGS = {
+    "vls_status_string": ([i32], ctypes.c_char_p),
+    "vls_last_error": ([], ctypes.c_char_p),
+    "vls_version": ([], i32),
+    "vls_context_create": ([i32, P], i32),
+    "vls_context_destroy": ([P], i32),
+    "vls_scene_create": ([P, P, P, P], i32),
+    "vls_scene_update_vertices": ([P, P, P], i32),
+    "vls_scene_update_reflectance": ([P, P, P], i32),
+    "vls_scene_stats_get": ([P, P], i32),
+    "vls_scene_export": ([P, P, P, P, P], i32),
+    "vls_scene_destroy": ([P], i32),
+    "vls_scanner_subrays": ([P, P], i32),
+    "vls_trace": ([P, P, P, i32, P, P, P], i32),
+    "vls_waveform": ([P, P, i32, P, P, P], i32),
+    "vls_returns": ([P, P, i32, P, P, P], i32),
+    "vls_simulate": ([P, P, P, i32, P, P, P], i32),
+    "vls_set_launch_config": ([P, P], i32),
+    "vls_get_launch_config": ([P, P], i32),
+    "vls_synchronize": ([P, P], i32),
+    "vls_trace_counts": ([P, P, P, i32, P, P, P], i32),
+}
+
+
+def library_path():
+    return LIB_PATH
+
+
+def lib():
+    """Load libvls.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libvls.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_2101_09154_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def declared_symbols():
+    return sorted(_SIGS)
+
+
+def _check(status):
+    if status != OK:
+        raise VlsError(status, lib().vls_last_error().decode(errors="replace"))
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def scanner_desc(sc):
+    """Scanner dict (keys as in ScannerDesc; pulse_shape 'gaussian' or 'eq3') -> ScannerDesc."""
+    shape = sc.get("pulse_shape", "gaussian")
+    return ScannerDesc(divergence_rad=sc["divergence_rad"], pattern_extent=sc.get("pattern_extent", 1.0),
+                       pulse_width_ns=sc["pulse_width_ns"], bin_ns=sc["bin_ns"],
+                       window_pre_ns=sc.get("window_pre_ns", -1.0), peak_power_w=sc.get("peak_power_w", 1.0),
+                       receiver_diameter_m=sc.get("receiver_diameter_m", 1.0), efficiency=sc.get("efficiency", 1.0),
+                       min_echo_abs=sc.get("min_echo_abs", 0.0), min_echo_rel=sc.get("min_echo_rel", 1e-3),
+                       n_subrays=sc.get("n_subrays", 0), beam_quality=sc.get("beam_quality", 0),
+                       pulse_shape=PULSE_EQ3 if shape in ("eq3", PULSE_EQ3) else PULSE_GAUSSIAN,
+                       n_bins=sc["n_bins"], max_returns=sc.get("max_returns", 8), reserved=0)
+
+
+def n_subrays(sc):
+    d = scanner_desc(sc)
+    out = i32(0)
+    _check(lib().vls_scanner_subrays(ctypes.byref(d), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Scene:
+    def __init__(self, ctx, vertices, triangles, reflectance, stream=None):
+        self.ctx = ctx
+        self._h = P()
+        if isinstance(vertices, np.ndarray):
+            v = np.ascontiguousarray(vertices, dtype=np.float32)
+            t = np.ascontiguousarray(triangles, dtype=np.int32)
+            r = np.ascontiguousarray(reflectance, dtype=np.float32)
+            desc = MeshDesc(v.ctypes.data, t.ctypes.data, r.ctypes.data, v.shape[0], t.shape[0], MEM_HOST, 0)
+            keep = (v, t, r)
+        else:
+            v = _dev(vertices, torch.float32, name="vertices")
+            t = _dev(triangles, torch.int32, name="triangles")
+            r = _dev(reflectance, torch.float32, name="reflectance")
+            desc = MeshDesc(v.data_ptr(), t.data_ptr(), r.data_ptr(), v.shape[0], t.shape[0], MEM_DEVICE, 0)
+            keep = (v, t, r)
+        _check(lib().vls_scene_create(ctx._h, ctypes.byref(desc), _stream(stream), ctypes.byref(self._h)))
+        del keep
+        self.n_vertices = int(desc.n_vertices)
+        self.n_triangles = int(desc.n_triangles)
+
+    def stats(self):
+        s = SceneStats()
+        _check(lib().vls_scene_stats_get(self._h, ctypes.byref(s)))
+        return {f: (list(getattr(s, f)) if f.startswith("bounds") else getattr(s, f)) for f, _ in s._fields_}
+
+    def update_vertices(self, vertices, stream=None):
+        v = _dev(vertices, torch.float32, (self.n_vertices, 3), "vertices")
+        _check(lib().vls_scene_update_vertices(self._h, _ptr(v), _stream(stream)))
+
+    def update_reflectance(self, reflectance, stream=None):
+        r = _dev(reflectance, torch.float32, (self.n_triangles,), "reflectance")
+        _check(lib().vls_scene_update_reflectance(self._h, _ptr(r), _stream(stream)))
+
+    def export(self):
+        n = self.n_triangles
+        nodes = np.zeros((max(n - 1, 0), 16), np.float32)
+        leaf = np.zeros(n, np.int32)
+        mort = np.zeros(n, np.uint64)
+        root = i32(0)
+        _check(lib().vls_scene_export(self._h, nodes.ctypes.data if nodes.size else None,
+                                      leaf.ctypes.data if n else None, mort.ctypes.data if n else None,
+                                      ctypes.byref(root)))
+        return nodes, leaf, mort, int(root.value)
+
+    def close(self):
+        if self._h:
+            _check(lib().vls_scene_destroy(self._h))
+            self._h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    def __init__(self, device=0):
+        self.device = device
+        self._h = P()
+        _check(lib().vls_context_create(device, ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _check(lib().vls_context_destroy(self._h))
+            self._h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def scene(self, vertices, triangles, reflectance, stream=None):
+        return Scene(self, vertices, triangles, reflectance, stream)
+
+    def set_launch_config(self, block_waves=1, stack_lds=16, persistent_blocks=0):
+        c = LaunchConfig(block_waves, stack_lds, persistent_blocks, 0)
+        _check(lib().vls_set_launch_config(self._h, ctypes.byref(c)))
+
+    def launch_config(self):
+        c = LaunchConfig()
+        _check(lib().vls_get_launch_config(self._h, ctypes.byref(c)))
+        return {"block_waves": c.block_waves, "stack_lds": c.stack_lds, "persistent_blocks": c.persistent_blocks}
+
+    def synchronize(self, stream=None):
+        _check(lib().vls_synchronize(self._h, _stream(stream)))
+
+    # -------------------------------------------------------------- marshalling helpers
+    @staticmethod
+    def _scanners(scanners):
+        if isinstance(scanners, dict):
+            scanners = [scanners]
+        arr = (ScannerDesc * len(scanners))(*[scanner_desc(s) for s in scanners])
+        return arr, len(scanners)
+
+    @staticmethod
+    def _batch(origins, directions, t0=None, segment_offsets=None, segment_scanner=None):
+        n = origins.shape[0]
+        _dev(origins, torch.float64, (n, 3), "origins")
+        _dev(directions, torch.float32, (n, 3), "directions")
+        _dev(t0, torch.float64, (n,), "window_t0_ns")
+        keep = []
+        b = PulseBatch(origins.data_ptr(), directions.data_ptr(), None if t0 is None else t0.data_ptr(), n,
+                       None, None, 0, 0)
+        if segment_offsets is not None:
+            so = np.ascontiguousarray(segment_offsets, dtype=np.int64)
+            ss = np.ascontiguousarray(segment_scanner, dtype=np.int32)
+            keep += [so, ss]
+            b.segment_offsets = so.ctypes.data
+            b.segment_scanner = ss.ctypes.data
+            b.n_segments = ss.size
+        return b, keep
+
+    @staticmethod
+    def _outputs(d):
+        return Outputs(*[_ptr(d.get(k)) for k in ("subray_tri", "subray_range", "subray_cos", "subray_power",
+                                                   "waveform", "window_t0_ns", "n_returns", "ret_range",
+                                                   "ret_amplitude", "ret_tri", "ret_bin")])
+
+    @staticmethod
+    def alloc_outputs(n, S, n_bins, K, device, subrays=True, waveform=True, returns=True):
+        o = {}
+        dev = torch.device("cuda", device) if isinstance(device, int) else device
+        if subrays:
+            o["subray_tri"] = torch.empty((n, S), dtype=torch.int32, device=dev)
+            o["subray_range"] = torch.empty((n, S), dtype=torch.float64, device=dev)
+            o["subray_cos"] = torch.empty((n, S), dtype=torch.float32, device=dev)
+            o["subray_power"] = torch.empty((n, S), dtype=torch.float32, device=dev)
+        if waveform:
+            o["waveform"] = torch.empty((n, n_bins), dtype=torch.float32, device=dev)
+        o["window_t0_ns"] = torch.empty(n, dtype=torch.float64, device=dev)
+        if returns:
+            o["n_returns"] = torch.empty(n, dtype=torch.int32, device=dev)
+            o["ret_range"] = torch.empty((n, K), dtype=torch.float32, device=dev)
+            o["ret_amplitude"] = torch.empty((n, K), dtype=torch.float32, device=dev)
+            o["ret_tri"] = torch.empty((n, K), dtype=torch.int32, device=dev)
+            o["ret_bin"] = torch.empty((n, K), dtype=torch.int32, device=dev)
+        return o
+
+    # -------------------------------------------------------------- the hot path
+    def simulate(self, scene, scanners, origins, directions, *, t0=None, out=None, subrays=True, waveform=True,
+                 segment_offsets=None, segment_scanner=None, stream=None):
+        """Fused trace + power + waveform + returns; returns the output dict."""
+        scs = [scanners] if isinstance(scanners, dict) else list(scanners)
+        S = max(n_subrays(s) for s in scs)
+        if out is None:
+            out = self.alloc_outputs(origins.shape[0], S, scs[0]["n_bins"], scs[0].get("max_returns", 8),
+                                     origins.device, subrays=subrays, waveform=waveform)
+        arr, ns = self._scanners(scs)
+        b, keep = self._batch(origins, directions, t0, segment_offsets, segment_scanner)
+        o = self._outputs(out)
+        _check(lib().vls_simulate(self._h, scene._h, arr, ns, ctypes.byref(b), ctypes.byref(o), _stream(stream)))
+        return out
+
+    def trace(self, scene, scanners, origins, directions, *, out=None, segment_offsets=None, segment_scanner=None,
+              stream=None):
+        scs = [scanners] if isinstance(scanners, dict) else list(scanners)
+        S = max(n_subrays(s) for s in scs)
+        if out is None:
+            out = self.alloc_outputs(origins.shape[0], S, 3, 1, origins.device, waveform=False, returns=False)
+        arr, ns = self._scanners(scs)
+        b, keep = self._batch(origins, directions, None, segment_offsets, segment_scanner)
+        o = self._outputs(out)
+        _check(lib().vls_trace(self._h, scene._h, arr, ns, ctypes.byref(b), ctypes.byref(o), _stream(stream)))
+        return out
+
+    def waveform(self, scanners, origins, directions, out, *, t0=None, segment_offsets=None, segment_scanner=None,
+                 stream=None):
+        arr, ns = self._scanners(scanners)
+        b, keep = self._batch(origins, directions, t0, segment_offsets, segment_scanner)
+        o = self._outputs(out)
+        _check(lib().vls_waveform(self._h, arr, ns, ctypes.byref(b), ctypes.byref(o), _stream(stream)))
+        return out
+
+    def trace_counts(self, scene, scanners, origins, directions, *, segment_offsets=None, segment_scanner=None,
+                     stream=None):
+        """(subrays, node visits, triangle tests) of tracing the batch (synchronous)."""
+        arr, ns = self._scanners(scanners)
+        b, keep = self._batch(origins, directions, None, segment_offsets, segment_scanner)
+        c = (ctypes.c_uint64 * 3)()
+        _check(lib().vls_trace_counts(self._h, scene._h, arr, ns, ctypes.byref(b), c, _stream(stream)))
+        return int(c[0]), int(c[1]), int(c[2])
+
+    def returns(self, scanners, origins, directions, out, *, segment_offsets=None, segment_scanner=None,
+                stream=None):
+        arr, ns = self._scanners(scanners)
+        b, keep = self._batch(origins, directions, None, segment_offsets, segment_scanner)
+        o = self._outputs(out)
+        _check(lib().vls_returns(self._h, arr, ns, ctypes.byref(b), ctypes.byref(o), _stream(stream)))
+        return out

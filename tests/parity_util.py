@@ -1,0 +1,159 @@
+"""Comparison of GPU outputs with the oracle at the stated tolerances.
+
+Hit triangle ids: >= 99.99 % equal, and every mismatch excused: in FP64 the
+subray hits the GPU's triangle (when the GPU reports one) and the hit lies
+within 1e-6 (barycentric) of an edge of either triangle, or the two hit
+distances agree to 1e-6 relative (a depth tie).  A miss against a hit is
+excused only at an edge of the hit triangle.
+Range: <= 1e-4 m on equal ids.
+Waveform: per-pulse relative L2 <= 1e-5 for pulses whose ids all match;
+all-miss pulses are all zero.
+Returns: equal counts and bins except where the oracle's waveform has a near
+tie (|wf[j] - wf[j +- 1]| or |wf[j] - thr| <= 1e-5 max wf) at a differing bin.
+"""
+import numpy as np
+
+import oracle
+
+C = oracle.C_M_PER_NS
+EDGE = 1e-6
+RANGE_TOL = 1e-4
+WF_TOL = 1e-5
+ID_FRACTION = 0.9999
+
+
+def to_np(out):
+    return {k: v.detach().cpu().numpy() for k, v in out.items()}
+
+
+def _bary_min(O, d, mesh, tri):
+    """Plane hit of the ray on triangle `tri` in FP64 without any inside test:
+    (hit within 1e-6 of the triangle, t, smallest barycentric coordinate)."""
+    V = mesh.vertices[mesh.triangles[tri]].astype(np.float64)
+    e1 = V[1] - V[0]
+    e2 = V[2] - V[0]
+    n = np.cross(e1, e2)
+    dn = float(d @ n)
+    if dn == 0.0:
+        return False, np.inf, -np.inf
+    t = float((V[0] - O) @ n) / dn
+    X = O + t * d
+    nn = float(n @ n)
+    u = float(np.cross(X - V[0], e2) @ n) / nn
+    v = float(np.cross(e1, X - V[0]) @ n) / nn
+    b = min(u, v, 1.0 - u - v)
+    return (t > 0 and b >= -EDGE), t, b
+
+
+def check_hits(mesh, pulses, sc, sel, g, r, report):
+    """g: GPU dict (numpy) rows for the selected pulses; r: oracle result."""
+    S = r.S
+    gt = g["subray_tri"][:, :S]
+    eq = gt == r.sub_tri
+    frac = float(eq.mean())
+    report["id_fraction"] = frac
+    bad = np.argwhere(~eq)
+    unexcused = []
+    for q, k in bad:
+        p = sel[q]
+        O = pulses.origins[p].astype(np.float64)
+        d = oracle.subray_directions(pulses.directions[p].astype(np.float64), sc)[k]
+        go, oo = int(gt[q, k]), int(r.sub_tri[q, k])
+        ok = False
+        if go >= 0:
+            hg, tg, bg = _bary_min(O, d, mesh, go)
+            if hg:
+                if oo >= 0:
+                    ho, to, bo = _bary_min(O, d, mesh, oo)
+                    ok = bg <= EDGE or bo <= EDGE or abs(tg - to) <= 1e-6 * to
+                else:
+                    ok = bg <= EDGE
+        else:
+            ho, to, bo = _bary_min(O, d, mesh, oo)
+            ok = bo <= EDGE
+        if not ok:
+            unexcused.append((int(p), int(k), go, oo))
+    report["mismatches"] = int(bad.shape[0])
+    report["unexcused"] = unexcused
+    ranges = np.abs(g["subray_range"][:, :S] - r.sub_range)
+    m = eq & (r.sub_tri >= 0)
+    report["max_range_err"] = float(ranges[m].max()) if m.any() else 0.0
+    miss_ok = bool(np.all(np.isinf(g["subray_range"][:, :S][eq & (r.sub_tri < 0)])))
+    report["miss_ok"] = miss_ok
+    return frac >= ID_FRACTION and not unexcused and report["max_range_err"] <= RANGE_TOL and miss_ok
+
+
+def check_waveforms(g, r, report):
+    S = r.S
+    allmatch = np.all(g["subray_tri"][:, :S] == r.sub_tri, axis=1)
+    wf = g["waveform"].astype(np.float64)
+    nrm = np.linalg.norm(r.waveform, axis=1)
+    rel = np.linalg.norm(wf - r.waveform, axis=1) / np.where(nrm > 0, nrm, 1.0)
+    hit = nrm > 0
+    chk = allmatch & hit
+    report["wf_checked"] = int(chk.sum())
+    report["wf_worst"] = float(rel[chk].max()) if chk.any() else 0.0
+    zero = allmatch & ~hit
+    zero_ok = bool(np.all(wf[zero] == 0.0))
+    report["wf_zero_ok"] = zero_ok
+    t0ok = np.all(np.isnan(g["window_t0_ns"][zero]) == np.isnan(r.t0[zero]))
+    dt0 = np.abs(g["window_t0_ns"][chk] - r.t0[chk])
+    report["t0_max_err_ns"] = float(dt0.max()) if dt0.size else 0.0
+    return report["wf_worst"] <= WF_TOL and zero_ok and bool(t0ok) and report["t0_max_err_ns"] <= 1e-6
+
+
+def _near_tie(w, j, thr, scale):
+    eps = 1e-5 * scale
+    if j <= 0 or j >= w.size - 1:
+        return True
+    return abs(w[j] - w[j - 1]) <= eps or abs(w[j] - w[j + 1]) <= eps or abs(w[j] - thr) <= eps
+
+
+def check_returns(g, r, sc, report):
+    S = r.S
+    K = sc.get("max_returns", 8)
+    allmatch = np.all(g["subray_tri"][:, :S] == r.sub_tri, axis=1)
+    bad = []
+    tri_bad = []
+    for q in np.nonzero(allmatch)[0]:
+        ng, no = int(g["n_returns"][q]), int(r.n_returns[q])
+        bg = list(g["ret_bin"][q, :ng])
+        bo = list(r.ret_bin[q, :no])
+        w = r.waveform[q]
+        mx = w.max() if w.size else 0.0
+        thr = max(sc.get("min_echo_abs", 0.0), sc.get("min_echo_rel", 1e-3) * mx)
+        if bg != bo:
+            diff = set(bg) ^ set(bo)
+            if not all(_near_tie(w, j, thr, mx) for j in diff) and not (ng == K or no == K):
+                bad.append(int(q))
+            continue
+        if ng:
+            if np.max(np.abs(g["ret_range"][q, :ng] - r.ret_range[q, :ng])) > RANGE_TOL:
+                bad.append(int(q))
+            if np.max(np.abs(g["ret_amplitude"][q, :ng] - r.ret_amp[q, :ng])) > 1e-5 * mx:
+                bad.append(int(q))
+            for s in range(ng):
+                if g["ret_tri"][q, s] != r.ret_tri[q, s]:
+                    tri_bad.append((int(q), s))
+        if np.any(g["ret_bin"][q, ng:K] != -1) or np.any(g["ret_tri"][q, ng:K] != -1):
+            bad.append(int(q))
+    report["returns_bad"] = bad[:20]
+    report["returns_bad_n"] = len(bad)
+    report["ret_tri_mismatch"] = len(tri_bad)
+    return not bad, tri_bad
+
+
+def attribution_excused(mesh, pulses, sc, sel, g, r, tri_bad):
+    """A differing return attribution is excused when the GPU's triangle carries a
+    subray whose contribution at the bin is within 1e-5 of the largest."""
+    left = []
+    for q, s in tri_bad:
+        j = int(r.ret_bin[q, s])
+        tj = r.t0[q] + j * sc["bin_ns"]
+        contrib = np.array([r.sub_power[q, k] * oracle.pulse_value(sc, tj - 2 * r.sub_range[q, k] / C)
+                            if r.sub_tri[q, k] >= 0 else -1.0 for k in range(r.S)])
+        best = contrib.max()
+        cand = [k for k in range(r.S) if r.sub_tri[q, k] == g["ret_tri"][q, s]]
+        if not cand or max(contrib[k] for k in cand) < (1 - 1e-5) * best:
+            left.append((int(sel[q]), s))
+    return left

@@ -1,0 +1,302 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle.
+
+Tolerances and excuses are those of parity_util: hit ids >= 99.99 % equal with
+every mismatch at an edge or a depth tie, range <= 1e-4 m, waveform relative
+L2 <= 1e-5, returns equal except at near ties.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import configs
+from parity_util import (attribution_excused, check_hits, check_returns, check_waveforms, to_np)
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2101_09154_amd as vp
+    return vp.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_gpu(ctx, scene, pulses, sc, **kw):
+    o = _dev(pulses.origins)
+    d = _dev(pulses.directions)
+    out = ctx.simulate(scene, sc, o, d, **kw)
+    torch.cuda.synchronize()
+    return to_np(out)
+
+
+def compare(mesh, pulses, sc, g, sel=None, label=""):
+    sel = np.arange(pulses.n) if sel is None else np.asarray(sel)
+    r = oracle.simulate(mesh, pulses, sc, select=sel)
+    gs = {k: v[sel] for k, v in g.items()}
+    rep = {}
+    ok_h = check_hits(mesh, pulses, sc, sel, gs, r, rep)
+    ok_w = check_waveforms(gs, r, rep)
+    ok_r, tri_bad = check_returns(gs, r, sc, rep)
+    left = attribution_excused(mesh, pulses, sc, sel, gs, r, tri_bad)
+    rep["attribution_unexcused"] = left[:10]
+    say(label, rep)
+    assert ok_h, rep
+    assert ok_w, rep
+    assert ok_r, rep
+    assert not left, rep
+    return rep
+
+
+# ------------------------------------------------------------------ structure
+
+
+def _tri_soup(n, seed):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-50, 50, (n, 3))
+    v = c[:, None, :] + rng.normal(0, 1.0, (n, 3, 3))
+    v[: n // 10] = v[0]          # duplicates: equal centroids and Morton keys
+    v = v.reshape(-1, 3)
+    t = np.arange(3 * n).reshape(n, 3)
+    return synth.Mesh(v.astype(np.float32), t.astype(np.int32), rng.uniform(0.1, 0.6, n).astype(np.float32))
+
+
+@pytest.mark.parametrize("which", ["small_tls", "soup"])
+def test_lbvh_invariants(ctx, which):
+    mesh = configs.small_tls()[0] if which == "small_tls" else _tri_soup(5000, 3)
+    say("lbvh", which, mesh.n_triangles)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    nodes, leaf, mort, root = scene.export()
+    n = mesh.n_triangles
+    assert root == 0
+    assert np.array_equal(np.sort(leaf), np.arange(n))
+    assert np.all(mort[1:] >= mort[:-1])
+    refs = nodes[:, 12:14].view(np.int32)
+    parent = nodes[:, 14].view(np.int32)
+    boxes = nodes[:, :12].reshape(-1, 2, 6)
+    seen_leaf = np.zeros(n, int)
+    seen_node = np.zeros(n - 1, int)
+    tv = mesh.vertices[mesh.triangles].astype(np.float64)
+    stack = [(0, 0)]
+    depth = 0
+    while stack:
+        x, dx = stack.pop()
+        seen_node[x] += 1
+        for side in (0, 1):
+            c = int(refs[x, side])
+            b = boxes[x, side]
+            if c >= 0:
+                assert parent[c] == x
+                cb = boxes[c]
+                lo = np.minimum(cb[0, :3], cb[1, :3])
+                hi = np.maximum(cb[0, 3:], cb[1, 3:])
+                assert np.all(b[:3] <= lo) and np.all(b[3:] >= hi)
+                stack.append((c, dx + 1))
+            else:
+                li = ~c
+                seen_leaf[li] += 1
+                tri = tv[leaf[li]]
+                assert np.all(b[:3] <= tri.min(0)) and np.all(b[3:] >= tri.max(0))
+                depth = max(depth, dx + 1)
+    assert np.all(seen_leaf == 1) and np.all(seen_node == 1)
+    st = scene.stats()
+    assert st["max_depth"] == depth
+    assert st["n_triangles"] == n
+
+
+# ------------------------------------------------------------------ small_tls in full
+
+
+def test_small_tls_full(ctx):
+    mesh, pulses, sc = configs.small_tls()
+    say("small_tls full", pulses.n)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    g = run_gpu(ctx, scene, pulses, sc)
+    compare(mesh, pulses, sc, g, label="small_tls")
+
+
+# ------------------------------------------------------------------ edge cases
+
+
+def _plane_scene():
+    ground = synth.flat_quad(-200, 200, -200, 200, 0.0, 0.4)
+    occl = synth.flat_quad(-200, 0.0, -200, 200, 7.0, 0.3)
+    box = synth.flat_quad(10, 12, 10, 12, 3.0, 0.6)
+    return synth.merge_meshes([ground, occl, box])
+
+
+def _edge_pulses(n, seed=1):
+    rng = np.random.default_rng(seed)
+    o = np.stack([rng.uniform(-30, 30, n), rng.uniform(-30, 30, n), rng.uniform(40, 60, n)], 1)
+    d = np.stack([rng.uniform(-0.3, 0.3, n), rng.uniform(-0.3, 0.3, n), -np.ones(n)], 1)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d[5] = (0.2, 0.1, 1.0)          # points away: all subrays miss
+    d[6] = 0.0                      # zero direction: defined as a miss
+    return synth.Pulses(o, d.astype(np.float32))
+
+
+@pytest.mark.parametrize("case", [
+    dict(S=1), dict(S=7), dict(S=64), dict(S=0, beam_quality=4), dict(S=31, pulse_shape="eq3", pulse_width_ns=3.0),
+    dict(S=19, n_bins=100), dict(S=19, n_bins=1024, bin_ns=0.25), dict(S=31, max_returns=1),
+    dict(S=61, bin_ns=0.3, n_bins=333), dict(S=13, window_pre_ns=2.0),
+])
+def test_edge_cases(ctx, case):
+    case = dict(case)
+    S = case.pop("S")
+    sc = configs.scanner(4e-2, S, **case)   # wide beam: subrays straddle the occluder edge
+    mesh = _plane_scene()
+    pulses = _edge_pulses(203)               # ragged against every pulses-per-wave count
+    say("edge", S, case)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    g = run_gpu(ctx, scene, pulses, sc)
+    compare(mesh, pulses, sc, g, label="edge")
+    assert np.all(g["subray_tri"][6] == -1) and np.all(g["subray_tri"][5] == -1)
+    assert np.isnan(g["window_t0_ns"][5]) and g["n_returns"][5] == 0
+
+
+def test_empty_and_single_triangle(ctx):
+    sc = configs.scanner(1e-3, 19, n_bins=64)
+    pulses = _edge_pulses(10)
+    empty = synth.Mesh(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32), np.zeros(0, np.float32))
+    say("empty scene")
+    scene = ctx.scene(empty.vertices, empty.triangles, empty.reflectance)
+    g = run_gpu(ctx, scene, pulses, sc)
+    assert np.all(g["subray_tri"] == -1) and np.all(g["waveform"] == 0) and np.all(g["n_returns"] == 0)
+    one = synth.Mesh(np.array([[-100, -100, 0], [100, -100, 0], [0, 150, 0]], np.float32),
+                     np.array([[0, 1, 2]], np.int32), np.array([0.5], np.float32))
+    say("single triangle")
+    scene1 = ctx.scene(one.vertices, one.triangles, one.reflectance)
+    g1 = run_gpu(ctx, scene1, pulses, sc)
+    compare(one, pulses, sc, g1, label="single")
+    say("zero pulses")
+    z = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    out = ctx.simulate(scene1, sc, z, z.float())
+    torch.cuda.synchronize()
+    assert out["waveform"].shape == (0, 64)
+
+
+def test_fixed_window_origin(ctx):
+    mesh, pulses, sc = configs.small_tls()
+    sub = pulses.subset(np.arange(0, 10000, 53))
+    t0 = oracle.simulate(mesh, sub, sc).t0 - 3.25
+    t0[::7] = np.nan
+    say("fixed t0")
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    g = run_gpu(ctx, scene, sub, sc, t0=_dev(t0))
+    r = oracle.simulate(mesh, sub, sc, t0=t0)
+    rep = {}
+    assert check_hits(mesh, sub, sc, np.arange(sub.n), g, r, rep), rep
+    assert check_waveforms(g, r, rep), rep
+
+
+# ------------------------------------------------------------------ internal consistency
+
+
+def test_stack_spill_bitwise(ctx):
+    mesh, pulses, sc = configs.small_tls()
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    base = None
+    for ring, waves in ((16, 4), (4, 4), (8, 1), (32, 2)):
+        say("ring", ring, "waves", waves, "depth", scene.stats()["max_depth"])
+        ctx.set_launch_config(block_waves=waves, stack_lds=ring)
+        g = run_gpu(ctx, scene, pulses, sc)
+        if base is None:
+            base = g
+        else:
+            for k in base:
+                assert np.array_equal(base[k], g[k], equal_nan=True), k
+    ctx.set_launch_config()
+
+
+def test_split_entry_points_match_fused(ctx):
+    mesh, pulses, sc = configs.small_tls()
+    sc = dict(sc, max_returns=4)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    say("split vs fused")
+    fused = run_gpu(ctx, scene, pulses, sc)
+    o = _dev(pulses.origins)
+    d = _dev(pulses.directions)
+    out = ctx.trace(scene, sc, o, d)
+    n = pulses.n
+    extra = ctx.alloc_outputs(n, 19, sc["n_bins"], 4, o.device, subrays=False)
+    out.update(extra)
+    ctx.waveform(sc, o, d, out)
+    ctx.returns(sc, o, d, out)
+    torch.cuda.synchronize()
+    g = to_np(out)
+    for k in fused:
+        assert np.array_equal(fused[k], g[k], equal_nan=True), k
+
+
+# ------------------------------------------------------------------ batched
+
+
+def test_batched_matches_per_segment(ctx):
+    mesh, _, _ = configs.small_tls()
+    scs = [configs.scanner(0.3e-3, 19, n_bins=256), configs.scanner(0.5e-3, 31, n_bins=256),
+           configs.scanner(0.25e-3, 61, n_bins=256), configs.scanner(2e-3, 1, n_bins=256)]
+    parts = []
+    for i, (n_az, n_el) in enumerate([(37, 11), (5, 3), (1, 1), (64, 9), (13, 17), (0, 0), (7, 7)]):
+        if n_az == 0:
+            parts.append(synth.Pulses(np.zeros((0, 3)), np.zeros((0, 3), np.float32)))
+            continue
+        origin = (10.0 + 5 * i, 20.0 + 3 * i, 3.0)
+        parts.append(synth.tls_grid(origin, n_az, n_el, el_deg=(-40.0, 10.0)))
+    seg_sc = np.array([0, 1, 2, 3, 1, 0, 2], np.int32)
+    batch = synth.concat_pulses(parts, seg_sc)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    say("batched", batch.n, batch.segment_offsets)
+    o = _dev(batch.origins)
+    d = _dev(batch.directions)
+    gb = to_np(ctx.simulate(scene, scs, o, d, segment_offsets=batch.segment_offsets, segment_scanner=seg_sc))
+    torch.cuda.synchronize()
+    off = batch.segment_offsets
+    for s in range(len(parts)):
+        if off[s + 1] == off[s]:
+            continue
+        sc = scs[seg_sc[s]]
+        gs = to_np(ctx.simulate(scene, sc, o[off[s]:off[s + 1]], d[off[s]:off[s + 1]]))
+        S = gs["subray_tri"].shape[1]
+        for k in gs:
+            a = gb[k][off[s]:off[s + 1]]
+            if k.startswith("subray"):
+                a = a[:, :S]
+            assert np.array_equal(a, gs[k], equal_nan=True), (s, k)
+        sel = np.arange(parts[s].n)[:: max(1, parts[s].n // 40)]
+        compare(mesh, parts[s], sc, {k: v for k, v in gs.items()}, sel=sel, label="segment %d" % s)
+
+
+# ------------------------------------------------------------------ full-size workloads, sampled
+
+
+def test_als_buildings_sampled(ctx):
+    mesh, pulses, sc = configs.als_buildings()
+    say("als_buildings: scene", mesh.n_triangles, "pulses", pulses.n)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    say("als_buildings stats", scene.stats())
+    g = run_gpu(ctx, scene, pulses, sc)
+    rng = np.random.default_rng(11)
+    sel = np.sort(rng.choice(pulses.n, 48, replace=False))
+    # a few pulses at the swath edges (partial and total misses)
+    sel = np.unique(np.concatenate([sel, [0, 999, 500500, 999999]]))
+    compare(mesh, pulses, sc, g, sel=sel, label="als_buildings")
+    assert g["waveform"].shape == (pulses.n, 512)
+    # properties that hold at any size: returns sorted in time, inside the window
+    nr = g["n_returns"]
+    assert nr.min() >= 0 and nr.max() <= 8
+    has = nr > 1
+    rb = g["ret_bin"][has]
+    assert np.all((np.diff(rb[:, :2], axis=1) > 0))
