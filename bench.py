@@ -56,7 +56,7 @@ def cpu_baseline(mesh, pulses, sc, target_s):
     import oracle
     threads = oracle.max_threads()
     rng = np.random.default_rng(123)
-    probe = np.sort(rng.choice(pulses.n, 4, replace=False))
+    probe = np.sort(rng.choice(pulses.n, 2 * threads, replace=False))
     t = time.perf_counter()
     oracle.simulate(mesh, pulses, sc, select=probe)
     per = (time.perf_counter() - t) / probe.size
@@ -71,6 +71,115 @@ def cpu_baseline(mesh, pulses, sc, target_s):
                       "%d triangles, %.1f s" % (n, n * r.S, mesh.n_triangles, dt)}
 
 
+def time_ms(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_batched(ctx, scene, mesh, steps):
+    """256 terrestrial positions on the same scene: per-segment launches vs one
+    persistent launch vs a replayed HIP graph of it (autotuned)."""
+    import torch
+    from synth import configs
+    import paper_2101_09154_amd as vp
+    _, pulses, scs = configs.batched_tls(mesh=mesh)
+    off = pulses.segment_offsets
+    seg = pulses.segment_scanner
+    S = [vp.n_subrays(sc) for sc in scs]
+    n = pulses.n
+    subrays = int(sum((off[i + 1] - off[i]) * S[seg[i]] for i in range(seg.size)))
+    dev = torch.device("cuda", 0)
+    o = torch.from_numpy(pulses.origins).to(dev)
+    d = torch.from_numpy(pulses.directions).to(dev)
+    out = ctx.alloc_outputs(n, max(S), scs[0]["n_bins"], scs[0]["max_returns"], dev, subrays=False)
+    stream = torch.cuda.current_stream()
+    views = []
+    for i in range(seg.size):
+        a, b = int(off[i]), int(off[i + 1])
+        views.append((scs[seg[i]], o[a:b], d[a:b], {k: v[a:b] for k, v in out.items()}))
+
+    def per_segment():
+        for sc, oo, dd, oo_out in views:
+            ctx.simulate(scene, sc, oo, dd, out=oo_out)
+
+    kw = dict(segment_offsets=off, segment_scanner=seg)
+    cfg0 = ctx.launch_config()
+    t_seg = time_ms(per_segment, max(1, steps // 4), 1, stream)
+    t_pers = time_ms(lambda: ctx.simulate(scene, scs, o, d, out=out, **kw), steps, 1, stream)
+    tune = ctx.autotune(scene, scs, o, d, out, **kw)
+    t_tuned = time_ms(lambda: ctx.simulate(scene, scs, o, d, out=out, **kw), steps, 1, stream)
+    g = ctx.capture_graph(scene, scs, o, d, out, **kw)
+    t_graph = time_ms(lambda: g.launch(), steps, 1, stream)
+    cfg_tuned = ctx.launch_config()
+    g.close()
+    ctx.set_launch_config(**cfg0)
+    return {"workload": "batched_tls: %d positions on the als_buildings scene, %d pulses, %d subrays, "
+                        "scanners S=19/31/61, 256 x 1 ns bins" % (seg.size, n, subrays),
+            "pulses": n, "subrays": subrays,
+            "per_segment_launches_ms": t_seg, "persistent_ms": t_pers, "persistent_tuned_ms": t_tuned,
+            "graph_tuned_ms": t_graph, "subrays_per_s_graph": subrays / (t_graph * 1e-3),
+            "pulses_per_s_graph": n / (t_graph * 1e-3),
+            "subrays_per_s_per_segment": subrays / (t_seg * 1e-3),
+            "speedup_vs_per_segment": t_seg / t_graph, "tuned_launch": cfg_tuned, "autotune": tune}
+
+
+def bench_grad(ctx, steps):
+    """Differentiation workload: forward = new heights and reflectance into the
+    scene (refit) + fused forward with fixed window origins + L2 loss against a
+    perturbed target; backward = loss gradient + the adjoint kernel."""
+    import torch
+    from synth import configs
+    import paper_2101_09154_amd as vp
+    mesh, target, pulses, sc = configs.diff_als()
+    dev = torch.device("cuda", 0)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    tscene = ctx.scene(target.vertices, target.triangles, target.reflectance)
+    o = torch.from_numpy(pulses.origins).to(dev)
+    d = torch.from_numpy(pulses.directions).to(dev)
+    t0 = ctx.simulate(scene, sc, o, d)["window_t0_ns"].clone()
+    tgt = ctx.simulate(tscene, sc, o, d, t0=t0)["waveform"].clone()
+    base_xy = torch.from_numpy(mesh.vertices[:, :2].copy()).to(dev)
+    heights = torch.from_numpy(mesh.vertices[:, 2].copy()).to(dev).requires_grad_(True)
+    refl = torch.from_numpy(mesh.reflectance.copy()).to(dev).requires_grad_(True)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd = bwd = 0.0
+    for it in range(steps + 2):
+        heights.grad = None
+        refl.grad = None
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        wf = vp.WaveformFn.apply(refl, heights, ctx, scene, sc, o, d, t0, base_xy)
+        loss = ((wf - tgt) ** 2).sum()
+        ev[1].record(stream)
+        loss.backward()
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        if it >= 2:
+            fwd += ev[0].elapsed_time(ev[1])
+            bwd += ev[1].elapsed_time(ev[2])
+    fwd /= steps
+    bwd /= steps
+    S = vp.n_subrays(sc)
+    return {"workload": "diff_als: 256x256 value-noise DTM (130,050 triangles), 100,000 ALS pulses at 200 m, "
+                        "31 subrays, 512 x 0.5 ns bins; L2 loss to a target with heights +-0.2 m and "
+                        "reflectance +-0.05",
+            "forward_ms": fwd, "backward_ms": bwd, "bwd_fwd_ratio": bwd / fwd,
+            "forward_subrays_per_s": pulses.n * S / (fwd * 1e-3), "loss": float(loss.item()),
+            "grad_norm_reflectance": float(refl.grad.norm().item()),
+            "grad_norm_heights": float(heights.grad.norm().item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +189,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--block-waves", type=int, default=1)
     ap.add_argument("--stack-lds", type=int, default=16)
+    ap.add_argument("--only-plain", action="store_true", help="skip the batched and gradient workloads")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (three times), to scale HBM counters")
     args = ap.parse_args()
@@ -127,6 +238,10 @@ def main():
     hit_frac = None
 
     stream = torch.cuda.current_stream()
+    tune = None
+    if not args.no_tune:
+        log("autotune (plain)")
+        tune = ctx.autotune(scene, sc, o, d, out)
     for _ in range(args.warmup):
         ctx.simulate(scene, sc, o, d, out=out)
     torch.cuda.synchronize()
@@ -187,6 +302,12 @@ def main():
                      "compulsory_bytes_per_launch": compulsory,
                      "compulsory_frac": compulsory / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
+    res["autotune"] = tune
+    if not args.only_plain:
+        log("batched workload")
+        res["batched"] = bench_batched(ctx, scene, mesh, args.steps // 2 if args.steps > 2 else 1)
+        log("gradient workload")
+        res["gradient"] = bench_grad(ctx, max(args.steps // 2, 2))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(mesh, pulses, sc, args.cpu_seconds)

@@ -256,14 +256,34 @@ vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_
 vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
                         const vls_pulse_batch* pulses, const vls_outputs* out, void* stream);
 
+/* ------------------------------------------------------------------ adjoint */
+
+/* Gradient of a waveform loss L with respect to per-triangle reflectance and
+ * vertex heights (z), given G = dL/dwf.  Hit selection is held fixed (the
+ * forward's subray_tri), the window origins are the fixed window_t0_ns of
+ * `pulses` (required), and each subray's range, incidence and power are
+ * recomputed from the scene's current vertices and reflectance (Sec. 5.2,
+ * Eq. 7; Sec. 3.4, Eq. 3): dL/drho, and dL/dz through R = n.(a-O)/(n.d),
+ * cos = |n.d|/|n| and P = C w rho cos / R^2.
+ *   scanner            one description; no segments
+ *   subray_tri         [n_pulses][S] int32 device, from vls_simulate/vls_trace
+ *   grad_waveform      [n_pulses][n_bins] float32 device
+ *   grad_reflectance   [n_triangles] float32 device, overwritten (may be NULL)
+ *   grad_vertex_z      [n_vertices] float32 device, overwritten (may be NULL)
+ * Float atomics make the summation order, and so the last bits, vary between
+ * runs.  Asynchronous on `stream`. */
+vls_status vls_waveform_backward(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanner,
+                                 const vls_pulse_batch* pulses, const int32_t* subray_tri, const float* grad_waveform,
+                                 float* grad_reflectance, float* grad_vertex_z, void* stream);
+
 /* ------------------------------------------------------------------ launch configuration */
 
 typedef struct {
-    int32_t block_waves;       /* wavefronts per block: 1, 2, 4 (default 1)                     */
-    int32_t stack_lds;         /* traversal-stack entries per lane held in LDS: 4..32 (default 16);
-                                  deeper entries spill to per-lane scratch                        */
-    int32_t persistent_blocks; /* blocks of the persistent kernel; 0 = auto (CUs x occupancy)   */
-    int32_t reserved;
+    int32_t block_waves;       /* wavefronts per block: 1, 2, 4 (default 1)                      */
+    int32_t stack_lds;         /* traversal-stack entries per lane held in LDS: 4, 8, 16, 32
+                                  (default 16); deeper entries spill to per-lane scratch          */
+    int32_t persistent_blocks; /* blocks of the persistent kernel; 0 = auto (CUs x occupancy)    */
+    int32_t pack;              /* 0: floor(64/S) pulses per wavefront; 1: one pulse per wavefront */
 } vls_launch_config;
 
 vls_status vls_set_launch_config(vls_context ctx, const vls_launch_config* cfg);
@@ -275,6 +295,36 @@ vls_status vls_get_launch_config(vls_context ctx, vls_launch_config* cfg);
  * bytes of the path: 64 B per node visit and 48 B per triangle test. */
 vls_status vls_trace_counts(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
                             const vls_pulse_batch* pulses, uint64_t* counts, void* stream);
+
+/* ------------------------------------------------------------------ batched form: graphs and tuning */
+
+/* Captures the whole vls_simulate call (counter reset + launch) into a HIP
+ * graph on a private stream.  Every pointer in `pulses` and `out` is baked
+ * into the graph and must stay valid until vls_graph_destroy; the host
+ * segment arrays are copied at capture.  The launch configuration of `ctx` at
+ * capture time is used.  Replays of one graph must not overlap in time. */
+vls_status vls_graph_capture(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
+                             const vls_pulse_batch* pulses, const vls_outputs* out, vls_graph* graph);
+vls_status vls_graph_launch(vls_graph graph, void* stream);
+vls_status vls_graph_destroy(vls_graph graph);
+
+typedef struct {
+    vls_launch_config best;
+    double best_ms;            /* time of one vls_simulate call with `best`                 */
+    double default_ms;         /* time with the configuration the context had on entry      */
+    int32_t n_tried;           /* configurations timed (0 when taken from the cache)        */
+    int32_t from_cache;
+} vls_tune_result;
+
+/* Times vls_simulate on this batch for launch configurations (block shape,
+ * LDS stack depth, pulses per wavefront, persistent grid size) by coordinate
+ * descent with HIP events on `stream`, keeps the fastest in `ctx`, and appends
+ * it to `cache_path` (JSON lines, may be NULL) keyed by scene size, subray
+ * counts, bins, pulse count and segments.  A matching cache entry is used
+ * without timing.  Writes the outputs as vls_simulate does.  Synchronous. */
+vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
+                        const vls_pulse_batch* pulses, const vls_outputs* out, const char* cache_path, void* stream,
+                        vls_tune_result* result);
 
 /* Synchronise `stream` and report any device error as VLS_ERR_DEVICE. */
 vls_status vls_synchronize(vls_context ctx, void* stream);

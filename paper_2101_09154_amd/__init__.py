@@ -2,6 +2,7 @@
 arXiv 2101.09154): HIP kernels for gfx950 behind the C ABI of include/vls.h,
 with a thin ctypes binding."""
 from . import vls
+from .autograd import WaveformFn
 from .vls import Context, Scene, VlsError, n_subrays, scanner_desc
 
-__all__ = ["vls", "Context", "Scene", "VlsError", "n_subrays", "scanner_desc"]
+__all__ = ["vls", "WaveformFn", "Context", "Scene", "VlsError", "n_subrays", "scanner_desc"]

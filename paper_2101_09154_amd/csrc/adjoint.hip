@@ -1,0 +1,199 @@
+// Adjoint of the waveform with respect to per-triangle reflectance and vertex
+// heights, for a loss L(wf) whose gradient G = dL/dwf is given.
+//
+// Hit selection is discrete and held fixed: the subray's triangle comes from the
+// forward pass, and the window origin t0 is the forward's (a fixed input).  Per
+// subray the continuous state is recomputed rather than stored:
+//   R   = n.(a - O) / n.d            (range to the triangle's plane; n = e1 x e2)
+//   cos = |n.d| / |n|                (incidence, Sec. 5.2)
+//   P   = C w rho cos / R^2          (Eq. 7 with a Lambertian extended target)
+//   tau = 2 R / c                    (two-way travel time, Sec. 3.4)
+//   wf_j += P p(t0 + j bin - tau)    (Sec. 3.4, Eq. 3 or a Gaussian pulse)
+// so with gP = sum_j G_j p(s_j) and gD = sum_j G_j p'(s_j):
+//   dL/dtau = -P gD,   dL/dR = dL/dtau 2/c - gP 2P/R,
+//   dL/drho = gP C w cos / R^2,   dL/dcos = gP C w rho / R^2,
+//   dR/dv_i = b_i n / (n.d) (b_i: barycentric weight of vertex i at the hit),
+//   dcos/dn = sgn(n.d) (d/|n| - (n.d) n/|n|^3), with dn = dv0 x (e1 - e2),
+//   dn = dv1 x e2, dn = e1 x dv2 for moves of the three vertices.
+// Only the z (height) components of the vertex gradients are kept.  Lanes of a
+// wavefront that share a triangle are summed in the wavefront first, so each
+// (wavefront, triangle) pair issues one atomic per gradient entry.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "device_common.h"
+#include "vls_internal.h"
+
+namespace vls {
+namespace {
+
+using namespace dev;
+
+__device__ __forceinline__ float wave_sum_f(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+struct Grads {
+    double grho, gz[3];
+};
+
+// Gradient contributions of one subray that hit triangle `tri`.
+__device__ __forceinline__ bool subray_grads(const SceneDev& scene, const ScannerDev& sc, const Ray& r, int tri,
+                                             double w, double t0, const float* __restrict__ G, Grads& out)
+{
+#pragma clang fp contract(off)
+    const int32_t* ti = scene.tri_idx + 3 * (long long)tri;
+    const float* V = scene.verts;
+    double a[3], b[3], c[3];
+    for (int i = 0; i < 3; ++i) {
+        a[i] = V[3 * (long long)ti[0] + i];
+        b[i] = V[3 * (long long)ti[1] + i];
+        c[i] = V[3 * (long long)ti[2] + i];
+    }
+    double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    double nd = n[0] * r.D[0] + n[1] * r.D[1] + n[2] * r.D[2];
+    double nn = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+    if (nd == 0.0 || nn == 0.0) return false;
+    double R = (n[0] * (a[0] - r.O[0]) + n[1] * (a[1] - r.O[1]) + n[2] * (a[2] - r.O[2])) / nd;
+    if (!(R > 0.0)) return false;
+    double X[3] = {r.O[0] + R * r.D[0] - a[0], r.O[1] + R * r.D[1] - a[1], r.O[2] + R * r.D[2] - a[2]};
+    // barycentric weights of the hit point: X - a = u e1 + v e2
+    double xe2[3] = {X[1] * e2[2] - X[2] * e2[1], X[2] * e2[0] - X[0] * e2[2], X[0] * e2[1] - X[1] * e2[0]};
+    double e1x[3] = {e1[1] * X[2] - e1[2] * X[1], e1[2] * X[0] - e1[0] * X[2], e1[0] * X[1] - e1[1] * X[0]};
+    double u = (xe2[0] * n[0] + xe2[1] * n[1] + xe2[2] * n[2]) / nn;
+    double v = (e1x[0] * n[0] + e1x[1] * n[1] + e1x[2] * n[2]) / nn;
+    double bw[3] = {1.0 - u - v, u, v};
+    double len = sqrt(nn);
+    double cosv = fabs(nd) / len;
+    double rho = scene.refl[tri];
+    double base = sc.power_c * w / (R * R);
+    double P = base * rho * cosv;
+    double tau = 2.0 * R / kCmPerNs;
+    double rel = tau - t0;
+    // bins inside the pulse support around this echo
+    double lo = ceil((rel - sc.cut_lo) / sc.bin_ns), hi = floor((rel + sc.cut_hi) / sc.bin_ns);
+    int jl = (int)fmax(lo, 0.0), jh = (int)fmin(hi, (double)(sc.n_bins - 1));
+    float rh = (float)rel, rl = (float)(rel - (double)rh);
+    float gP = 0.0f, gD = 0.0f;
+    const float inv_s2 = -2.0f * sc.neg_k * 0.6931471805599453f;  // 1 / sigma^2 for the Gaussian
+    for (int j = jl; j <= jh; ++j) {
+        double xd = (double)j * sc.bin_ns;
+        float xh = (float)xd, xl = (float)(xd - (double)xh);
+        float s = (xh - rh) + (xl - rl);
+        float p, dp;
+        if (sc.shape == 0) {
+            p = exp2f(s * s * sc.neg_k);
+            dp = -s * inv_s2 * p;
+        } else {
+            float x = s * sc.inv_tau;
+            float e = s > 0.0f ? exp2f(x * sc.neg_k) : 0.0f;
+            p = x * x * e;
+            dp = (2.0f * x - x * x) * e * sc.inv_tau;
+        }
+        float g = G[j];
+        gP += g * p;
+        gD += g * dp;
+    }
+    double gtau = -P * (double)gD;
+    double gR = gtau * 2.0 / kCmPerNs - (double)gP * 2.0 * P / R;
+    double gcos = (double)gP * base * rho;
+    out.grho = (double)gP * base * cosv;
+    // through R: dR/dv_i = b_i n / n.d (z component)
+    for (int i = 0; i < 3; ++i) out.gz[i] = gR * bw[i] * n[2] / nd;
+    // through cos: gradient with respect to n, then to the vertices
+    double sg = nd >= 0.0 ? 1.0 : -1.0;
+    double gn[3];
+    for (int i = 0; i < 3; ++i) gn[i] = gcos * sg * (r.D[i] / len - nd * n[i] / (nn * len));
+    double d12[3] = {e1[0] - e2[0], e1[1] - e2[1], e1[2] - e2[2]};
+    out.gz[0] += d12[0] * gn[1] - d12[1] * gn[0];   // ((e1 - e2) x gn).z
+    out.gz[1] += e2[0] * gn[1] - e2[1] * gn[0];     // (e2 x gn).z
+    out.gz[2] += gn[0] * e1[1] - gn[1] * e1[0];     // (gn x e1).z
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float* p, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_backward(SceneDev scene, ScannerDev sc, PulsesDev pulses,
+                                                  const int32_t* __restrict__ sub_tri, int sub_stride,
+                                                  const float* __restrict__ grad_wf, float* grad_refl,
+                                                  float* grad_z, long long count)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int waves = blockDim.x / kWave;
+    long long wave = (long long)blockIdx.x * waves + threadIdx.x / kWave;
+    long long p0 = wave * sc.P_w;
+    if (p0 >= count) return;
+    long long left = count - p0;
+    const int npw = left < sc.P_w ? (int)left : sc.P_w;
+    const int S = sc.S;
+    const int pl = lane / S, k = lane - pl * S;
+    int tri = -1;
+    Grads g;
+    g.grho = g.gz[0] = g.gz[1] = g.gz[2] = 0.0;
+    if (pl < npw) {
+        long long p = p0 + pl;
+        int t = sub_tri[p * sub_stride + k];
+        double t0 = pulses.t0_in[p];
+        if (t >= 0 && t < scene.n_tri && !isnan(t0)) {
+            Ray r;
+            const double* pat = sc.pattern + 5 * k;
+            if (setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, pat, 0.0f, r) &&
+                subray_grads(scene, sc, r, t, pat[4], t0, grad_wf + p * sc.n_bins, g))
+                tri = t;
+        }
+    }
+    // sum the contributions of lanes that share a triangle, one atomic per entry
+    unsigned long long todo = __ballot(tri >= 0);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int t = __builtin_amdgcn_readlane(tri, leader);
+        const bool mine = tri == t;
+        todo &= ~__ballot(mine);
+        float sr = wave_sum_f(mine ? (float)g.grho : 0.0f);
+        float s0 = wave_sum_f(mine ? (float)g.gz[0] : 0.0f);
+        float s1 = wave_sum_f(mine ? (float)g.gz[1] : 0.0f);
+        float s2 = wave_sum_f(mine ? (float)g.gz[2] : 0.0f);
+        if (lane == leader) {
+            const int32_t* ti = scene.tri_idx + 3 * (long long)t;
+            if (grad_refl) unsafeAtomicAdd(grad_refl + t, sr);
+            if (grad_z) {
+                unsafeAtomicAdd(grad_z + ti[0], s0);
+                unsafeAtomicAdd(grad_z + ti[1], s1);
+                unsafeAtomicAdd(grad_z + ti[2], s2);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_backward(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
+                           const int32_t* sub_tri, int sub_stride, const float* grad_wf, float* grad_refl,
+                           float* grad_z, long long n_vert, const LaunchCfg& cfg, hipStream_t stream)
+{
+    if (grad_refl && scene.n_tri > 0)
+        hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((scene.n_tri + 255) / 256)), dim3(256), 0, stream, grad_refl,
+                           (long long)scene.n_tri);
+    if (grad_z && n_vert > 0)
+        hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n_vert + 255) / 256)), dim3(256), 0, stream, grad_z, n_vert);
+    if (pulses.n > 0 && scene.n_tri > 0) {
+        const int block = cfg.block_waves * kWave;
+        long long waves = (pulses.n + sc.P_w - 1) / sc.P_w;
+        unsigned grid = (unsigned)((waves + cfg.block_waves - 1) / cfg.block_waves);
+        hipLaunchKernelGGL(k_backward, dim3(grid), dim3(block), 0, stream, scene, sc, pulses, sub_tri, sub_stride,
+                           grad_wf, grad_refl, grad_z, pulses.n);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vls

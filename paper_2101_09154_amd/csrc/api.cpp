@@ -180,6 +180,19 @@ struct vls_scene_s {
     }
 };
 
+struct vls_graph_s {
+    vls_context ctx = nullptr;
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~vls_graph_s()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
+
 namespace {
 
 vls_status scanner_dev(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s)
@@ -205,7 +218,7 @@ vls_status scanner_dev(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s
     memset(&s, 0, sizeof s);
     s.pattern = dev;
     s.S = S;
-    s.P_w = kWave / S;
+    s.P_w = ctx->cfg.pack ? 1 : kWave / S;
     s.n_bins = d.n_bins;
     s.K = d.max_returns;
     s.shape = d.pulse_shape;
@@ -241,6 +254,8 @@ SceneDev scene_dev(vls_scene sc)
     s.tris = sc->b.tris;
     s.refl = sc->b.refl;
     s.bounds = sc->b.bounds;
+    s.verts = sc->b.verts;
+    s.tri_idx = sc->b.tri_idx;
     s.root = sc->root;
     s.n_tri = (int)sc->b.n_tri;
     return s;
@@ -477,9 +492,11 @@ vls_status vls_set_launch_config(vls_context ctx, const vls_launch_config* cfg)
     int r = cfg->stack_lds;
     if (r < 4 || r > kMaxRing || (r & (r - 1)) != 0) return fail(VLS_ERR_INVALID_ARG, "stack_lds must be 4, 8, 16 or 32");
     if (cfg->persistent_blocks < 0) return fail(VLS_ERR_INVALID_ARG, "persistent_blocks must be >= 0");
+    if (cfg->pack != 0 && cfg->pack != 1) return fail(VLS_ERR_INVALID_ARG, "pack must be 0 or 1");
     ctx->cfg.block_waves = cfg->block_waves;
     ctx->cfg.stack_lds = r;
     ctx->cfg.persistent_blocks = cfg->persistent_blocks;
+    ctx->cfg.pack = cfg->pack;
     return VLS_OK;
 }
 
@@ -489,7 +506,7 @@ vls_status vls_get_launch_config(vls_context ctx, vls_launch_config* cfg)
     cfg->block_waves = ctx->cfg.block_waves;
     cfg->stack_lds = ctx->cfg.stack_lds;
     cfg->persistent_blocks = ctx->cfg.persistent_blocks;
-    cfg->reserved = 0;
+    cfg->pack = ctx->cfg.pack;
     return VLS_OK;
 }
 
@@ -685,32 +702,49 @@ vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_
     return wave_common(ctx, scanners, n_scanners, pulses, out, stream, 1);
 }
 
+static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners,
+                                   int32_t n_scanners, const vls_pulse_batch* pulses, const vls_outputs* out,
+                                   Prepared& pr, vls_context_s::Batch*& bt, int& blocks)
+{
+    vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
+    if (st != VLS_OK) return st;
+    if ((st = check_scene(ctx, scene)) != VLS_OK) return st;
+    if ((st = check_outputs(out)) != VLS_OK) return st;
+    if (pulses->n_pulses > 0 && (!out->n_returns || !out->ret_range || !out->ret_amplitude || !out->ret_bin))
+        return fail(VLS_ERR_INVALID_ARG, "simulate needs n_returns, ret_range, ret_amplitude and ret_bin");
+    bt = nullptr;
+    blocks = 0;
+    if (pulses->n_pulses > 0 && pulses->n_segments > 0) {
+        if ((st = batch_tables(ctx, pr, bt)) != VLS_OK) return st;
+        blocks = ctx->cfg.persistent_blocks > 0 ? ctx->cfg.persistent_blocks
+                                                : persistent_occupancy_blocks(pr.n_bins, ctx->cfg);
+    }
+    return VLS_OK;
+}
+
+static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepared& pr, const vls_pulse_batch* pulses,
+                                   const vls_outputs* out, vls_context_s::Batch* bt, int blocks, hipStream_t s)
+{
+    if (pulses->n_pulses == 0) return VLS_OK;
+    OutDev od = out_dev(out, pr.S_stride);
+    PulsesDev pd = pulses_dev(pulses);
+    SceneDev sd = scene_dev(scene);
+    hipError_t e;
+    if (!bt) e = launch_simulate(sd, pr.sc[0], pd, od, 0, pulses->n_pulses, 1, ctx->cfg, s);
+    else e = launch_persistent(sd, bt->bd, pr.n_bins, pd, od, ctx->cfg, blocks, s);
+    return e == hipSuccess ? VLS_OK : hip_fail(e, "simulate launch");
+}
+
 vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
                         const vls_pulse_batch* pulses, const vls_outputs* out, void* stream)
 {
     try {
         Prepared pr;
-        vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
-        if (st != VLS_OK) return st;
-        if ((st = check_scene(ctx, scene)) != VLS_OK) return st;
-        if ((st = check_outputs(out)) != VLS_OK) return st;
-        if (pulses->n_pulses > 0 && (!out->n_returns || !out->ret_range || !out->ret_amplitude || !out->ret_bin))
-            return fail(VLS_ERR_INVALID_ARG, "simulate needs n_returns, ret_range, ret_amplitude and ret_bin");
-        if (pulses->n_pulses == 0) return VLS_OK;
-        OutDev od = out_dev(out, pr.S_stride);
-        PulsesDev pd = pulses_dev(pulses);
-        SceneDev sd = scene_dev(scene);
-        hipStream_t s = (hipStream_t)stream;
-        if (pulses->n_segments <= 0) {
-            hipError_t e = launch_simulate(sd, pr.sc[0], pd, od, 0, pulses->n_pulses, 1, ctx->cfg, s);
-            return e == hipSuccess ? VLS_OK : hip_fail(e, "simulate launch");
-        }
         vls_context_s::Batch* bt = nullptr;
-        if ((st = batch_tables(ctx, pr, bt)) != VLS_OK) return st;
-        int blocks = ctx->cfg.persistent_blocks > 0 ? ctx->cfg.persistent_blocks
-                                                    : persistent_occupancy_blocks(pr.n_bins, ctx->cfg);
-        hipError_t e = launch_persistent(sd, bt->bd, pr.n_bins, pd, od, ctx->cfg, blocks, s);
-        return e == hipSuccess ? VLS_OK : hip_fail(e, "persistent launch");
+        int blocks = 0;
+        vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, bt, blocks);
+        if (st != VLS_OK) return st;
+        return simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, (hipStream_t)stream);
     } catch (const std::exception& e) {
         return fail(VLS_ERR_INTERNAL, e.what());
     }
@@ -743,6 +777,216 @@ vls_status vls_trace_counts(vls_context ctx, vls_scene scene, const vls_scanner_
         (void)hipFree(dc);
         if (e != hipSuccess) return hip_fail(e, "trace counts");
         for (int i = 0; i < 3; ++i) counts[i] = h[i];
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
+vls_status vls_waveform_backward(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanner,
+                                 const vls_pulse_batch* pulses, const int32_t* subray_tri, const float* grad_waveform,
+                                 float* grad_reflectance, float* grad_vertex_z, void* stream)
+{
+    try {
+        Prepared pr;
+        vls_status st = prepare(ctx, scanner, 1, pulses, pr);
+        if (st != VLS_OK) return st;
+        if (!scene || scene->ctx != ctx) return fail(VLS_ERR_INVALID_ARG, "scene is NULL or of another context");
+        if (pulses->n_segments > 0) return fail(VLS_ERR_INVALID_ARG, "the adjoint takes one scanner and no segments");
+        if (pulses->n_pulses > 0 && (!pulses->window_t0_ns || !subray_tri || !grad_waveform))
+            return fail(VLS_ERR_INVALID_ARG, "the adjoint needs window_t0_ns, subray_tri and grad_waveform");
+        if (!grad_reflectance && !grad_vertex_z) return fail(VLS_ERR_INVALID_ARG, "no gradient requested");
+        if (!aligned(subray_tri, 4) || !aligned(grad_waveform, 4) || !aligned(grad_reflectance, 4) ||
+            !aligned(grad_vertex_z, 4))
+            return fail(VLS_ERR_INVALID_ARG, "misaligned array");
+        hipError_t e = launch_backward(scene_dev(scene), pr.sc[0], pulses_dev(pulses), subray_tri, pr.S_stride,
+                                       grad_waveform, grad_reflectance, grad_vertex_z, scene->b.n_vert, ctx->cfg,
+                                       (hipStream_t)stream);
+        return e == hipSuccess ? VLS_OK : hip_fail(e, "backward launch");
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
+vls_status vls_graph_capture(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
+                             const vls_pulse_batch* pulses, const vls_outputs* out, vls_graph* graph)
+{
+    try {
+        if (!graph) return fail(VLS_ERR_INVALID_ARG, "graph is NULL");
+        *graph = nullptr;
+        Prepared pr;
+        vls_context_s::Batch* bt = nullptr;
+        int blocks = 0;
+        vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, bt, blocks);
+        if (st != VLS_OK) return st;
+        std::unique_ptr<vls_graph_s> g(new vls_graph_s());
+        g->ctx = ctx;
+        VLS_HIP(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking), "capture stream");
+        VLS_HIP(hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal), "begin capture");
+        st = simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, g->cs);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(g->cs, &gr);
+        if (st != VLS_OK) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        g->graph = gr;
+        VLS_HIP(hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0), "graph instantiate");
+        *graph = g.release();
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
+vls_status vls_graph_launch(vls_graph graph, void* stream)
+{
+    if (!graph || !graph->exec) return fail(VLS_ERR_INVALID_ARG, "graph is NULL");
+    VLS_HIP(hipGraphLaunch(graph->exec, (hipStream_t)stream), "graph launch");
+    return VLS_OK;
+}
+
+vls_status vls_graph_destroy(vls_graph graph)
+{
+    if (!graph) return fail(VLS_ERR_INVALID_ARG, "graph is NULL");
+    delete graph;
+    return VLS_OK;
+}
+
+static std::string tune_key(vls_scene scene, const Prepared& pr, const vls_pulse_batch* pulses)
+{
+    int smin = 64, smax = 1;
+    for (auto& s : pr.sc) {
+        smin = std::min(smin, s.S);
+        smax = std::max(smax, s.S);
+    }
+    int bucket = 0;
+    for (int64_t n = pulses->n_pulses; n > 1; n >>= 1) ++bucket;
+    char b[200];
+    snprintf(b, sizeof b, "tri=%lld|S=%d-%d|bins=%d|pulses=2^%d|segments=%d", (long long)scene->b.n_tri, smin, smax,
+             pr.n_bins, bucket, pulses->n_segments > 0 ? pulses->n_segments : 0);
+    return b;
+}
+
+static bool tune_cache_find(const char* path, const std::string& key, vls_launch_config& c)
+{
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    std::string pat = "\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof line, f)) {
+        if (!strstr(line, pat.c_str())) continue;
+        vls_launch_config t{};
+        const char* p;
+        if ((p = strstr(line, "\"block_waves\": "))) t.block_waves = atoi(p + 15);
+        if ((p = strstr(line, "\"stack_lds\": "))) t.stack_lds = atoi(p + 13);
+        if ((p = strstr(line, "\"persistent_blocks\": "))) t.persistent_blocks = atoi(p + 21);
+        if ((p = strstr(line, "\"pack\": "))) t.pack = atoi(p + 8);
+        c = t;
+        found = true;
+    }
+    fclose(f);
+    return found;
+}
+
+vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
+                        const vls_pulse_batch* pulses, const vls_outputs* out, const char* cache_path, void* stream,
+                        vls_tune_result* result)
+{
+    try {
+        if (!result) return fail(VLS_ERR_INVALID_ARG, "result is NULL");
+        memset(result, 0, sizeof *result);
+        Prepared pr0;
+        vls_context_s::Batch* bt = nullptr;
+        int blocks = 0;
+        vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr0, bt, blocks);
+        if (st != VLS_OK) return st;
+        const std::string key = tune_key(scene, pr0, pulses);
+        hipStream_t s = (hipStream_t)stream;
+        const LaunchCfg entry = ctx->cfg;
+        hipEvent_t e0, e1;
+        VLS_HIP(hipEventCreate(&e0), "event");
+        VLS_HIP(hipEventCreate(&e1), "event");
+        auto timed = [&](const LaunchCfg& c, double& ms) -> vls_status {
+            ctx->cfg = c;
+            Prepared pr;
+            vls_context_s::Batch* b2 = nullptr;
+            int bl = 0;
+            vls_status r = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, b2, bl);
+            if (r != VLS_OK) return r;
+            if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s)) != VLS_OK) return r;
+            VLS_HIP(hipEventRecord(e0, s), "event");
+            for (int i = 0; i < 2; ++i)
+                if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s)) != VLS_OK) return r;
+            VLS_HIP(hipEventRecord(e1, s), "event");
+            VLS_HIP(hipEventSynchronize(e1), "event");
+            float f = 0.0f;
+            VLS_HIP(hipEventElapsedTime(&f, e0, e1), "event");
+            ms = f / 2.0;
+            return VLS_OK;
+        };
+        vls_launch_config cached{};
+        LaunchCfg best = entry;
+        double best_ms = 0.0;
+        if ((st = timed(entry, best_ms)) != VLS_OK) { ctx->cfg = entry; return st; }
+        result->default_ms = best_ms;
+        if (tune_cache_find(cache_path, key, cached)) {
+            LaunchCfg c;
+            c.block_waves = cached.block_waves;
+            c.stack_lds = cached.stack_lds;
+            c.persistent_blocks = cached.persistent_blocks;
+            c.pack = cached.pack;
+            double ms = 0.0;
+            if ((st = timed(c, ms)) != VLS_OK) { ctx->cfg = entry; return st; }
+            best = c;
+            best_ms = ms;
+            result->from_cache = 1;
+        } else {
+            int tried = 1;
+            const bool seg = pulses->n_segments > 0;
+            int auto_blocks = seg ? persistent_occupancy_blocks(pr0.n_bins, entry) : 0;
+            for (int dim = 0; dim < 4; ++dim) {
+                std::vector<LaunchCfg> cand;
+                for (int v = 0; v < 4; ++v) {
+                    LaunchCfg c = best;
+                    if (dim == 0) { if (v > 2) break; c.block_waves = 1 << v; }
+                    if (dim == 1) c.stack_lds = 4 << v;
+                    if (dim == 2) { if (v > 1) break; c.pack = v; }
+                    if (dim == 3) { if (!seg || v > 2) break; c.persistent_blocks = v == 0 ? 0 : (v == 1 ? auto_blocks / 2 : 2 * auto_blocks); }
+                    if (c.stack_lds + kMaxSpill - 1 < scene->stats.max_depth) continue;
+                    cand.push_back(c);
+                }
+                for (auto& c : cand) {
+                    if (c.block_waves == best.block_waves && c.stack_lds == best.stack_lds && c.pack == best.pack &&
+                        c.persistent_blocks == best.persistent_blocks)
+                        continue;
+                    double ms = 0.0;
+                    if ((st = timed(c, ms)) != VLS_OK) { ctx->cfg = entry; return st; }
+                    ++tried;
+                    if (ms < best_ms) { best_ms = ms; best = c; }
+                }
+            }
+            result->n_tried = tried;
+            if (cache_path) {
+                FILE* f = fopen(cache_path, "a");
+                if (f) {
+                    fprintf(f, "{\"key\": \"%s\", \"block_waves\": %d, \"stack_lds\": %d, \"persistent_blocks\": %d, \"pack\": %d, \"ms\": %.6f}\n",
+                            key.c_str(), best.block_waves, best.stack_lds, best.persistent_blocks, best.pack, best_ms);
+                    fclose(f);
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->cfg = best;
+        result->best.block_waves = best.block_waves;
+        result->best.stack_lds = best.stack_lds;
+        result->best.persistent_blocks = best.persistent_blocks;
+        result->best.pack = best.pack;
+        result->best_ms = best_ms;
         return VLS_OK;
     } catch (const std::exception& e) {
         return fail(VLS_ERR_INTERNAL, e.what());

@@ -1,0 +1,122 @@
+// Device helpers shared by the library's kernels (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "vls_internal.h"
+
+namespace vls {
+namespace dev {
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_min_d(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max_f(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ unsigned lanes_below(unsigned long long m)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+struct Ray {
+    double O[3];
+    double D[3];
+    double Sx, Sy, Sz;  // shear of the watertight test: the ray runs along +kz
+    int kx, ky, kz;
+    float inv[3];
+    float oim[3];  // (O + pad) * inv : lower planes moved outward
+    float oip[3];  // (O - pad) * inv : upper planes moved outward
+};
+
+// Duff et al. 2017 orthonormal basis; FP64 subray direction; FP32 slab constants.
+// FP contraction is off wherever FP64 results decide a hit, so every product
+// and sum is rounded exactly as written.
+__device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const float* __restrict__ d32,
+                                          const double* __restrict__ pat, float scene_mag, Ray& r)
+{
+#pragma clang fp contract(off)
+    double dx = d32[0], dy = d32[1], dz = d32[2];
+    double len = sqrt(dx * dx + dy * dy + dz * dz);
+    if (!(len > 0.0) || !(len < INFINITY)) return false;
+    double n[3] = {dx / len, dy / len, dz / len};
+    double sgn = copysign(1.0, n[2]);
+    double a = -1.0 / (sgn + n[2]);
+    double b = n[0] * n[1] * a;
+    double u[3] = {1.0 + sgn * n[0] * n[0] * a, sgn * b, -sgn * n[0]};
+    double v[3] = {b, sgn + n[1] * n[1] * a, -n[1]};
+    double ca = pat[0], sa = pat[1], cp = pat[2], sp = pat[3];
+    double omax = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        r.D[i] = ca * n[i] + sa * (cp * u[i] + sp * v[i]);
+        r.O[i] = o[i];
+        omax = fmax(omax, fabs(o[i]));
+    }
+    if (!(omax < INFINITY)) return false;
+    int kz = 0;
+    if (fabs(r.D[1]) > fabs(r.D[kz])) kz = 1;
+    if (fabs(r.D[2]) > fabs(r.D[kz])) kz = 2;
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    if (r.D[kz] < 0.0) {
+        int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    r.Sx = r.D[kx] / r.D[kz];
+    r.Sy = r.D[ky] / r.D[kz];
+    r.Sz = 1.0 / r.D[kz];
+    // pad covers the FP32 rounding of origin, direction and slab arithmetic
+    double pad = (omax + (double)scene_mag + 1.0) * 1.9073486328125e-06;  // 2^-19
+    for (int i = 0; i < 3; ++i) {
+        float di = (float)r.D[i];
+        if (fabsf(di) < 1e-30f) di = copysignf(1e-30f, di);
+        float inv = 1.0f / di;
+        r.inv[i] = inv;
+        r.oim[i] = (float)(r.O[i] + pad) * inv;
+        r.oip[i] = (float)(r.O[i] - pad) * inv;
+    }
+    return true;
+}
+
+__device__ __forceinline__ double pick(double x, double y, double z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
+
+__device__ __forceinline__ float pulse_shape(const ScannerDev& sc, float s)
+{
+    if (sc.shape == 0) return exp2f(s * s * sc.neg_k);
+    float x = s * sc.inv_tau;
+    return s > 0.0f ? x * x * exp2f(x * sc.neg_k) : 0.0f;
+}
+
+}  // namespace dev
+}  // namespace vls

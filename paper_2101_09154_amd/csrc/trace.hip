@@ -37,9 +37,12 @@
 #include <stdint.h>
 
 #include "vls_internal.h"
+#include "device_common.h"
 
 namespace vls {
 namespace {
+
+using namespace dev;
 
 struct WaveLds {
     double tau[kWave];
@@ -48,105 +51,6 @@ struct WaveLds {
     float pw[kWave];
     int tri[kWave];
 };
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ double wave_min_d(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ __forceinline__ float wave_max_f(float v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ __forceinline__ int wave_min_i(int v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ __forceinline__ int wave_max_i(int v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ __forceinline__ unsigned lanes_below(unsigned long long m)
-{
-    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
-
-struct Ray {
-    double O[3];
-    double D[3];
-    double Sx, Sy, Sz;  // shear of the watertight test: the ray runs along +kz
-    int kx, ky, kz;
-    float inv[3];
-    float oim[3];  // (O + pad) * inv : lower planes moved outward
-    float oip[3];  // (O - pad) * inv : upper planes moved outward
-};
-
-// Duff et al. 2017 orthonormal basis; FP64 subray direction; FP32 slab constants.
-// FP contraction is off wherever FP64 results decide a hit, so every product
-// and sum is rounded exactly as written.
-__device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const float* __restrict__ d32,
-                                          const double* __restrict__ pat, float scene_mag, Ray& r)
-{
-#pragma clang fp contract(off)
-    double dx = d32[0], dy = d32[1], dz = d32[2];
-    double len = sqrt(dx * dx + dy * dy + dz * dz);
-    if (!(len > 0.0) || !(len < INFINITY)) return false;
-    double n[3] = {dx / len, dy / len, dz / len};
-    double sgn = copysign(1.0, n[2]);
-    double a = -1.0 / (sgn + n[2]);
-    double b = n[0] * n[1] * a;
-    double u[3] = {1.0 + sgn * n[0] * n[0] * a, sgn * b, -sgn * n[0]};
-    double v[3] = {b, sgn + n[1] * n[1] * a, -n[1]};
-    double ca = pat[0], sa = pat[1], cp = pat[2], sp = pat[3];
-    double omax = 0.0;
-    for (int i = 0; i < 3; ++i) {
-        r.D[i] = ca * n[i] + sa * (cp * u[i] + sp * v[i]);
-        r.O[i] = o[i];
-        omax = fmax(omax, fabs(o[i]));
-    }
-    if (!(omax < INFINITY)) return false;
-    int kz = 0;
-    if (fabs(r.D[1]) > fabs(r.D[kz])) kz = 1;
-    if (fabs(r.D[2]) > fabs(r.D[kz])) kz = 2;
-    int kx = kz == 2 ? 0 : kz + 1;
-    int ky = kx == 2 ? 0 : kx + 1;
-    if (r.D[kz] < 0.0) {
-        int t = kx;
-        kx = ky;
-        ky = t;
-    }
-    r.kx = kx;
-    r.ky = ky;
-    r.kz = kz;
-    r.Sx = r.D[kx] / r.D[kz];
-    r.Sy = r.D[ky] / r.D[kz];
-    r.Sz = 1.0 / r.D[kz];
-    // pad covers the FP32 rounding of origin, direction and slab arithmetic
-    double pad = (omax + (double)scene_mag + 1.0) * 1.9073486328125e-06;  // 2^-19
-    for (int i = 0; i < 3; ++i) {
-        float di = (float)r.D[i];
-        if (fabsf(di) < 1e-30f) di = copysignf(1e-30f, di);
-        float inv = 1.0f / di;
-        r.inv[i] = inv;
-        r.oim[i] = (float)(r.O[i] + pad) * inv;
-        r.oip[i] = (float)(r.O[i] - pad) * inv;
-    }
-    return true;
-}
 
 __device__ __forceinline__ bool box_hit(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz,
                                         float tcull, float& tn)
@@ -165,8 +69,6 @@ struct Hit {
     int leaf;
     int orig;
 };
-
-__device__ __forceinline__ double pick(double x, double y, double z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
 
 // Watertight ray/triangle test (Woop, Benthin & Wald 2013) in FP64, two-sided,
 // inclusive edges: the triangle is translated to the ray origin and sheared so
@@ -266,13 +168,6 @@ __device__ __forceinline__ Hit traverse(const SceneDev& scene, const Ray& r, int
         }
     }
     return h;
-}
-
-__device__ __forceinline__ float pulse_shape(const ScannerDev& sc, float s)
-{
-    if (sc.shape == 0) return exp2f(s * s * sc.neg_k);
-    float x = s * sc.inv_tau;
-    return s > 0.0f ? x * x * exp2f(x * sc.neg_k) : 0.0f;
 }
 
 // Incidence and power of the chosen triangle (Sec. 5.2, Eq. 7):
@@ -501,8 +396,10 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     for (int q = 0; q < npw; ++q) pulse_phase<MAXCH, true, true>(sc, pulses, out, first + q, q * S, wl, true);
 }
 
+// Traversal is latency-bound: six wavefronts per SIMD (at most 80 VGPRs, a few
+// bytes of spills) measured faster than four or five without spills.
 template <int MAXCH, int MODE>
-__global__ __launch_bounds__(256) void k_simulate(SceneDev scene, ScannerDev sc, PulsesDev pulses,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_simulate(SceneDev scene, ScannerDev sc, PulsesDev pulses,
                                                   OutDev out, long long first, long long count, int ring_mask)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -557,9 +454,9 @@ __global__ __launch_bounds__(256) void k_wave(ScannerDev sc, PulsesDev pulses, O
     }
 }
 
-// Persistent batched kernel: wavefronts take wave-tiles from a global counter.
+// Persistent batched kernel: wavefronts take chunks of wave-tiles from a global counter.
 template <int MAXCH>
-__global__ __launch_bounds__(256) void k_persistent(SceneDev scene, BatchDev batch, PulsesDev pulses,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_persistent(SceneDev scene, BatchDev batch, PulsesDev pulses,
                                                     OutDev out, int ring_mask)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -567,23 +464,33 @@ __global__ __launch_bounds__(256) void k_persistent(SceneDev scene, BatchDev bat
     const int lane = threadIdx.x & (kWave - 1);
     WaveLds* wl = reinterpret_cast<WaveLds*>(smem) + threadIdx.x / kWave;
     int* ring = reinterpret_cast<int*>(smem + sizeof(WaveLds) * waves);
+    // Each wavefront takes `chunk` consecutive wave-tiles per counter update, so
+    // the single counter sees about n_tiles / chunk atomics instead of one per tile.
+    const long long chunk = batch.chunk;
     while (true) {
         unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(batch.counter, 1ull);
-        long long tile = (long long)__shfl((long long)t, 0);
-        if (tile >= batch.n_tiles) break;
+        if (lane == 0) t = atomicAdd(batch.counter, (unsigned long long)chunk);
+        // broadcast lane 0's value as a wave-uniform (scalar) value
+        const unsigned t_lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)t);
+        const unsigned t_hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(t >> 32));
+        const long long first = (long long)(((unsigned long long)t_hi << 32) | t_lo);
+        if (first >= batch.n_tiles) break;
+        const long long last = first + chunk < batch.n_tiles ? first + chunk : batch.n_tiles;
         int lo = 0, hi = batch.n_seg - 1;
-        while (lo < hi) {  // last segment whose first tile <= tile
+        while (lo < hi) {  // last segment whose first tile <= first
             int mid = (lo + hi + 1) >> 1;
-            if (batch.tile_off[mid] <= tile) lo = mid;
+            if (batch.tile_off[mid] <= first) lo = mid;
             else hi = mid - 1;
         }
-        const ScannerDev sc = batch.scanners[batch.seg_scanner[lo]];
-        long long p = batch.pulse_off[lo] + (tile - batch.tile_off[lo]) * sc.P_w;
-        long long left = batch.pulse_end[lo] - p;
-        int npw = left < sc.P_w ? (int)left : sc.P_w;
-        process_wave<MAXCH, 1>(scene, sc, pulses, out, p, npw, ring, ring_mask, wl);
-        wave_sync();
+        for (long long tile = first; tile < last; ++tile) {
+            while (lo + 1 < batch.n_seg && batch.tile_off[lo + 1] <= tile) ++lo;
+            const ScannerDev sc = batch.scanners[batch.seg_scanner[lo]];
+            long long p = batch.pulse_off[lo] + (tile - batch.tile_off[lo]) * sc.P_w;
+            long long left = batch.pulse_end[lo] - p;
+            int npw = left < sc.P_w ? (int)left : sc.P_w;
+            process_wave<MAXCH, 1>(scene, sc, pulses, out, p, npw, ring, ring_mask, wl);
+            wave_sync();
+        }
     }
 }
 
@@ -649,12 +556,16 @@ hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int m
     int mask = cfg.stack_lds - 1;
     hipError_t e = launch_fill_u64(batch.counter, 1, 0ull, stream);
     if (e != hipSuccess) return e;
+    BatchDev b = batch;
+    long long waves = (long long)blocks * cfg.block_waves;
+    long long ch = batch.n_tiles / (waves * 16 > 0 ? waves * 16 : 1);
+    b.chunk = (int)(ch < 1 ? 1 : (ch > 4096 ? 4096 : ch));
     if (max_bins <= 256)
-        hipLaunchKernelGGL((k_persistent<4>), dim3(blocks), dim3(block), lds, stream, scene, batch, pulses, out, mask);
+        hipLaunchKernelGGL((k_persistent<4>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask);
     else if (max_bins <= 512)
-        hipLaunchKernelGGL((k_persistent<8>), dim3(blocks), dim3(block), lds, stream, scene, batch, pulses, out, mask);
+        hipLaunchKernelGGL((k_persistent<8>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask);
     else
-        hipLaunchKernelGGL((k_persistent<16>), dim3(blocks), dim3(block), lds, stream, scene, batch, pulses, out, mask);
+        hipLaunchKernelGGL((k_persistent<16>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask);
     return hipGetLastError();
 }
 

@@ -43,6 +43,8 @@ struct SceneDev {
     const float4* tris;
     const float* refl;      // by original triangle index
     const float* bounds;    // [13]: vertex lo.xyz hi.xyz, centroid lo.xyz hi.xyz, max |coordinate|
+    const float* verts;     // [n_vert][3] current vertices (adjoint)
+    const int32_t* tri_idx; // [n_tri][3] vertex indices (adjoint)
     int root;
     int n_tri;
 };
@@ -80,7 +82,7 @@ struct BatchDev {
     const ScannerDev* scanners;   // [n_scanners]
     unsigned long long* counter;  // work counter (reset before each launch)
     int n_seg;
-    int pad_;
+    int chunk;                    // wave-tiles taken per counter update
     long long n_tiles;
 };
 
@@ -88,6 +90,7 @@ struct LaunchCfg {
     int block_waves = 1;
     int stack_lds = 16;
     int persistent_blocks = 0;
+    int pack = 0;  // 0: floor(64/S) pulses per wavefront; 1: one pulse per wavefront
 };
 
 // ---- host-side launchers (defined in the .hip files) ----
@@ -119,6 +122,9 @@ hipError_t launch_waveform(const ScannerDev& sc, const PulsesDev& pulses, const 
                            long long first, long long count, int mode, const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, const PulsesDev& pulses,
                              const OutDev& out, const LaunchCfg& cfg, int blocks, hipStream_t stream);
+hipError_t launch_backward(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
+                           const int32_t* sub_tri, int sub_stride, const float* grad_wf, float* grad_refl,
+                           float* grad_z, long long n_vert, const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);
 int persistent_occupancy_blocks(int max_bins, const LaunchCfg& cfg);
 

@@ -11,7 +11,8 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvls.so")
+# VLS_LIBRARY may point at another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("VLS_LIBRARY") or os.path.join(HERE, "libvls.so")
 
 OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "device error", 4: "not built",
@@ -65,7 +66,12 @@ class Outputs(ctypes.Structure):
 
 
 class LaunchConfig(ctypes.Structure):
-    _fields_ = [("block_waves", i32), ("stack_lds", i32), ("persistent_blocks", i32), ("reserved", i32)]
+    _fields_ = [("block_waves", i32), ("stack_lds", i32), ("persistent_blocks", i32), ("pack", i32)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", LaunchConfig), ("best_ms", f64), ("default_ms", f64), ("n_tried", i32),
+                ("from_cache", i32)]
 
 
 _lib = None
@@ -91,6 +97,11 @@ _SIGS = {
     "vls_get_launch_config": ([P, P], i32),
     "vls_synchronize": ([P, P], i32),
     "vls_trace_counts": ([P, P, P, i32, P, P, P], i32),
+    "vls_waveform_backward": ([P, P, P, P, P, P, P, P, P], i32),
+    "vls_graph_capture": ([P, P, P, i32, P, P, P], i32),
+    "vls_graph_launch": ([P, P], i32),
+    "vls_graph_destroy": ([P], i32),
+    "vls_autotune": ([P, P, P, i32, P, P, ctypes.c_char_p, P, P], i32),
 }
 
 
@@ -223,6 +234,26 @@ class Scene:
             pass
 
 
+class Graph:
+    def __init__(self):
+        self._h = P()
+        self._keep = None
+
+    def launch(self, stream=None):
+        _check(lib().vls_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            _check(lib().vls_graph_destroy(self._h))
+            self._h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     def __init__(self, device=0):
         self.device = device
@@ -243,14 +274,15 @@ class Context:
     def scene(self, vertices, triangles, reflectance, stream=None):
         return Scene(self, vertices, triangles, reflectance, stream)
 
-    def set_launch_config(self, block_waves=1, stack_lds=16, persistent_blocks=0):
-        c = LaunchConfig(block_waves, stack_lds, persistent_blocks, 0)
+    def set_launch_config(self, block_waves=1, stack_lds=16, persistent_blocks=0, pack=0):
+        c = LaunchConfig(block_waves, stack_lds, persistent_blocks, pack)
         _check(lib().vls_set_launch_config(self._h, ctypes.byref(c)))
 
     def launch_config(self):
         c = LaunchConfig()
         _check(lib().vls_get_launch_config(self._h, ctypes.byref(c)))
-        return {"block_waves": c.block_waves, "stack_lds": c.stack_lds, "persistent_blocks": c.persistent_blocks}
+        return {"block_waves": c.block_waves, "stack_lds": c.stack_lds, "persistent_blocks": c.persistent_blocks,
+                "pack": c.pack}
 
     def synchronize(self, stream=None):
         _check(lib().vls_synchronize(self._h, _stream(stream)))
@@ -341,6 +373,52 @@ class Context:
         o = self._outputs(out)
         _check(lib().vls_waveform(self._h, arr, ns, ctypes.byref(b), ctypes.byref(o), _stream(stream)))
         return out
+
+    def waveform_backward(self, scene, scanner, origins, directions, t0, subray_tri, grad_waveform, *,
+                          grad_reflectance=None, grad_z=None, stream=None):
+        """(grad_reflectance [n_tri], grad_z [n_vert]) of a waveform loss, hit selection and t0 fixed."""
+        n = origins.shape[0]
+        dev = origins.device
+        if grad_reflectance is None:
+            grad_reflectance = torch.empty(scene.n_triangles, dtype=torch.float32, device=dev)
+        if grad_z is None:
+            grad_z = torch.empty(scene.n_vertices, dtype=torch.float32, device=dev)
+        _dev(subray_tri, torch.int32, name="subray_tri")
+        _dev(grad_waveform, torch.float32, (n, scanner["n_bins"]), "grad_waveform")
+        _dev(grad_reflectance, torch.float32, (scene.n_triangles,), "grad_reflectance")
+        _dev(grad_z, torch.float32, (scene.n_vertices,), "grad_z")
+        d = scanner_desc(scanner)
+        b, keep = self._batch(origins, directions, t0)
+        _check(lib().vls_waveform_backward(self._h, scene._h, ctypes.byref(d), ctypes.byref(b), _ptr(subray_tri),
+                                           _ptr(grad_waveform), _ptr(grad_reflectance), _ptr(grad_z),
+                                           _stream(stream)))
+        return grad_reflectance, grad_z
+
+    def capture_graph(self, scene, scanners, origins, directions, out, *, t0=None, segment_offsets=None,
+                      segment_scanner=None):
+        """HIP graph of one simulate call; `out` and the inputs must outlive it."""
+        arr, ns = self._scanners(scanners)
+        b, keep = self._batch(origins, directions, t0, segment_offsets, segment_scanner)
+        o = self._outputs(out)
+        g = Graph()
+        _check(lib().vls_graph_capture(self._h, scene._h, arr, ns, ctypes.byref(b), ctypes.byref(o),
+                                       ctypes.byref(g._h)))
+        g._keep = (origins, directions, t0, out, scene)
+        return g
+
+    def autotune(self, scene, scanners, origins, directions, out, *, cache_path=None, segment_offsets=None,
+                 segment_scanner=None, stream=None):
+        arr, ns = self._scanners(scanners)
+        b, keep = self._batch(origins, directions, None, segment_offsets, segment_scanner)
+        o = self._outputs(out)
+        r = TuneResult()
+        _check(lib().vls_autotune(self._h, scene._h, arr, ns, ctypes.byref(b), ctypes.byref(o),
+                                  None if cache_path is None else cache_path.encode(), _stream(stream),
+                                  ctypes.byref(r)))
+        return {"best": {"block_waves": r.best.block_waves, "stack_lds": r.best.stack_lds,
+                         "persistent_blocks": r.best.persistent_blocks, "pack": r.best.pack},
+                "best_ms": r.best_ms, "default_ms": r.default_ms, "n_tried": r.n_tried,
+                "from_cache": bool(r.from_cache)}
 
     def trace_counts(self, scene, scanners, origins, directions, *, segment_offsets=None, segment_scanner=None,
                      stream=None):

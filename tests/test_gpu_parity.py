@@ -300,3 +300,190 @@ def test_als_buildings_sampled(ctx):
     has = nr > 1
     rb = g["ret_bin"][has]
     assert np.all((np.diff(rb[:, :2], axis=1) > 0))
+
+
+# ------------------------------------------------------------------ graphs and tuning
+
+
+def _small_batch():
+    mesh, _, _ = configs.small_tls()
+    scs = [configs.scanner(0.3e-3, 19, n_bins=256), configs.scanner(0.5e-3, 31, n_bins=256),
+           configs.scanner(0.25e-3, 61, n_bins=256)]
+    parts = [synth.tls_grid((8.0 + 9 * i, 12.0 + 7 * i, 3.0), 40 + 13 * i, 7 + i, el_deg=(-35.0, 15.0))
+             for i in range(6)]
+    seg_sc = (np.arange(6) % 3).astype(np.int32)
+    return mesh, scs, synth.concat_pulses(parts, seg_sc), seg_sc
+
+
+def _assert_batch_equal(a, b, batch, seg_sc, scs, what=""):
+    """Bitwise equality of two batched output sets on their valid entries (per-subray
+    slots past a pulse's own subray count are unspecified)."""
+    off = batch.segment_offsets
+    S = [len(oracle.pattern(sc)[0]) for sc in scs]
+    for k in a:
+        if k.startswith("subray"):
+            for s in range(seg_sc.size):
+                sl = slice(off[s], off[s + 1])
+                assert np.array_equal(a[k][sl, :S[seg_sc[s]]], b[k][sl, :S[seg_sc[s]]], equal_nan=True), (what, k, s)
+        else:
+            assert np.array_equal(a[k], b[k], equal_nan=True), (what, k)
+
+
+def test_graph_replays_match_eager(ctx):
+    mesh, scs, batch, seg_sc = _small_batch()
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = _dev(batch.origins)
+    d = _dev(batch.directions)
+    kw = dict(segment_offsets=batch.segment_offsets, segment_scanner=seg_sc)
+    say("graph: eager", batch.n)
+    eager = to_np(ctx.simulate(scene, scs, o, d, **kw))
+    out = ctx.alloc_outputs(batch.n, 61, 256, 8, o.device)
+    g = ctx.capture_graph(scene, scs, o, d, out, **kw)
+    for rep in range(4):
+        for v in out.values():
+            v.fill_(-7)
+        say("graph replay", rep)
+        g.launch()
+        torch.cuda.synchronize()
+        _assert_batch_equal(eager, to_np(out), batch, seg_sc, scs, rep)
+        # eager work of the program between replays
+        other = ctx.simulate(scene, scs[0], o[:100], d[:100])
+        torch.cuda.synchronize()
+        assert other["n_returns"].shape == (100,)
+    g.close()
+
+
+def test_autotune_and_cache(ctx, tmp_path):
+    mesh, scs, batch, seg_sc = _small_batch()
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = _dev(batch.origins)
+    d = _dev(batch.directions)
+    kw = dict(segment_offsets=batch.segment_offsets, segment_scanner=seg_sc)
+    ctx.set_launch_config()
+    eager = to_np(ctx.simulate(scene, scs, o, d, **kw))
+    out = ctx.alloc_outputs(batch.n, 61, 256, 8, o.device)
+    cache = str(tmp_path / "tune.jsonl")
+    say("autotune 1")
+    r1 = ctx.autotune(scene, scs, o, d, out, cache_path=cache, **kw)
+    say(r1)
+    assert not r1["from_cache"] and r1["n_tried"] >= 5 and r1["best_ms"] <= r1["default_ms"] * 1.5
+    assert ctx.launch_config() == r1["best"]
+    _assert_batch_equal(eager, to_np(out), batch, seg_sc, scs, "tuned")
+    say("autotune 2 (cache)")
+    ctx.set_launch_config()
+    r2 = ctx.autotune(scene, scs, o, d, out, cache_path=cache, **kw)
+    assert r2["from_cache"] and r2["best"] == r1["best"]
+    # packing one pulse per wavefront changes nothing but speed
+    ctx.set_launch_config(pack=1)
+    _assert_batch_equal(eager, to_np(ctx.simulate(scene, scs, o, d, **kw)), batch, seg_sc, scs, "pack")
+    ctx.set_launch_config()
+
+
+# ------------------------------------------------------------------ adjoint
+
+
+def _grad_case(n=48, lines=40, per_line=50):
+    mesh = configs.diff_scene(n=n)
+    target = configs.diff_target(mesh)
+    extent = mesh.info["extent"]
+    z = mesh.info["heights_mean"] + 120.0
+    y = 4.0 + (extent - 8.0) * np.arange(lines) / (lines - 1)
+    pulses = synth.als_lines(extent / 2, y, z, per_line, beta_deg=(-12.0, 12.0))
+    sc = configs.scanner(0.5e-3, 31, pulse_width_ns=4.0, bin_ns=0.5, n_bins=512)
+    return mesh, target, pulses, sc
+
+
+def _gpu_grad(ctx, mesh, pulses, sc, t0, G):
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = _dev(pulses.origins)
+    d = _dev(pulses.directions)
+    t0d = _dev(t0)
+    out = ctx.simulate(scene, sc, o, d, t0=t0d)
+    gr, gz = ctx.waveform_backward(scene, sc, o, d, t0d, out["subray_tri"], _dev(G.astype(np.float32)))
+    torch.cuda.synchronize()
+    return out, gr.cpu().numpy().astype(np.float64), gz.cpu().numpy().astype(np.float64)
+
+
+def test_adjoint_matches_oracle_gradient(ctx):
+    mesh, target, pulses, sc = _grad_case()
+    base = oracle.simulate(mesh, pulses, sc)
+    t0 = base.t0
+    tgt = oracle.simulate(target, pulses, sc, t0=t0).waveform
+    G = 2.0 * (base.waveform - tgt)
+    gr_o, gz_o = oracle.gradient(mesh, pulses, sc, t0, G)
+    say("adjoint vs oracle", mesh.n_triangles, pulses.n)
+    out, gr_g, gz_g = _gpu_grad(ctx, mesh, pulses, sc, t0, G)
+    assert np.array_equal(out["subray_tri"].cpu().numpy(), base.sub_tri)
+    er = np.linalg.norm(gr_g - gr_o) / np.linalg.norm(gr_o)
+    ez = np.linalg.norm(gz_g - gz_o) / np.linalg.norm(gz_o)
+    say("rel L2: reflectance %.2e heights %.2e" % (er, ez))
+    assert np.count_nonzero(gr_o) > 100 and np.count_nonzero(gz_o) > 100
+    assert er <= 1e-4 and ez <= 1e-4
+    # entries the oracle leaves at zero stay zero
+    assert np.all(gr_g[gr_o == 0] == 0) and np.all(gz_g[gz_o == 0] == 0)
+
+
+def test_adjoint_matches_finite_differences(ctx):
+    # central differences (h = 1e-3) of the FP64 oracle forward against the GPU adjoint
+    mesh, target, pulses, sc = _grad_case(n=16, lines=8, per_line=9)
+    sc = dict(sc, peak_power_w=1e4)
+    base = oracle.simulate(mesh, pulses, sc)
+    t0 = base.t0
+    tgt = oracle.simulate(target, pulses, sc, t0=t0).waveform
+    G = 2.0 * (base.waveform - tgt)
+    _, gr_g, gz_g = _gpu_grad(ctx, mesh, pulses, sc, t0, G)
+    h = 1e-3
+    scale = max(np.abs(gr_g).max(), np.abs(gz_g).max())
+    checked = 0
+    for v in np.argsort(-np.abs(gz_g))[:24]:
+        mp = synth.Mesh(mesh.vertices.copy(), mesh.triangles, mesh.reflectance)
+        mm = synth.Mesh(mesh.vertices.copy(), mesh.triangles, mesh.reflectance)
+        mp.vertices[v, 2] += np.float32(h)
+        mm.vertices[v, 2] -= np.float32(h)
+        rp = oracle.simulate(mp, pulses, sc, t0=t0)
+        rm = oracle.simulate(mm, pulses, sc, t0=t0)
+        if not (np.array_equal(rp.sub_tri, base.sub_tri) and np.array_equal(rm.sub_tri, base.sub_tri)):
+            continue
+        hh = (float(mp.vertices[v, 2]) - float(mm.vertices[v, 2])) / 2
+        fd = (np.sum((rp.waveform - tgt) ** 2) - np.sum((rm.waveform - tgt) ** 2)) / (2 * hh)
+        assert abs(fd - gz_g[v]) <= 2e-4 * abs(fd) + 1e-5 * scale, (v, fd, gz_g[v])
+        checked += 1
+    for t in np.argsort(-np.abs(gr_g))[:24]:
+        rp = mesh.reflectance.astype(np.float64).copy()
+        rm = rp.copy()
+        rp[t] += h
+        rm[t] -= h
+        lp = np.sum((oracle.simulate(synth.Mesh(mesh.vertices, mesh.triangles, rp.astype(np.float32)), pulses, sc,
+                                     t0=t0).waveform - tgt) ** 2)
+        lm = np.sum((oracle.simulate(synth.Mesh(mesh.vertices, mesh.triangles, rm.astype(np.float32)), pulses, sc,
+                                     t0=t0).waveform - tgt) ** 2)
+        hh = (float(np.float32(rp[t])) - float(np.float32(rm[t]))) / 2
+        fd = (lp - lm) / (2 * hh)
+        assert abs(fd - gr_g[t]) <= 2e-4 * abs(fd) + 1e-5 * scale, (t, fd, gr_g[t])
+        checked += 1
+    assert checked >= 36
+
+
+def test_autograd_function(ctx):
+    import paper_2101_09154_amd as vp
+    mesh, target, pulses, sc = _grad_case(n=32, lines=12, per_line=20)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = _dev(pulses.origins)
+    d = _dev(pulses.directions)
+    t0 = ctx.simulate(scene, sc, o, d)["window_t0_ns"].clone()
+    tscene = ctx.scene(target.vertices, target.triangles, target.reflectance)
+    tgt = ctx.simulate(tscene, sc, o, d, t0=t0)["waveform"].clone()
+    base_xy = _dev(mesh.vertices[:, :2])
+    heights = _dev(mesh.vertices[:, 2]).requires_grad_(True)
+    refl = _dev(mesh.reflectance).requires_grad_(True)
+    say("autograd")
+    wf = vp.WaveformFn.apply(refl, heights, ctx, scene, sc, o, d, t0, base_xy)
+    loss = ((wf - tgt) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    out = ctx.simulate(scene, sc, o, d, t0=t0)
+    gr, gz = ctx.waveform_backward(scene, sc, o, d, t0, out["subray_tri"], (2.0 * (out["waveform"] - tgt)).contiguous())
+    torch.cuda.synchronize()
+    assert torch.allclose(refl.grad, gr, rtol=1e-5, atol=1e-6 * float(gr.abs().max()))
+    assert torch.allclose(heights.grad, gz, rtol=1e-5, atol=1e-6 * float(gz.abs().max()))
+    assert float(refl.grad.abs().sum()) > 0 and float(heights.grad.abs().sum()) > 0
