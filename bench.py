@@ -233,7 +233,7 @@ def main():
 
     log("traversal counters")
     n_sub, visits, tests = ctx.trace_counts(scene, sc, o, d)
-    v_node = visits / n_sub
+    v_node = visits / n_sub   # node fetches per subray (the cone pass fetches once per pulse)
     v_tri = tests / n_sub
     hit_frac = None
 
@@ -261,9 +261,9 @@ def main():
     sub_per_s = n * S / (ms * 1e-3)
     pulse_per_s = n / (ms * 1e-3)
 
-    bytes_per_sub = 64.0 * v_node + 48.0 * v_tri + 4.0
-    bytes_per_pulse = S * bytes_per_sub + 36.0 + 4.0 * nb + 8.0 + 4.0 + 16.0 * K
-    alg_bytes = bytes_per_pulse * n
+    # node and triangle fetches the traversal makes, a reflectance per subray, and
+    # per pulse 36 B in and the waveform, t0, count and returns out
+    alg_bytes = 64.0 * visits + 48.0 * tests + 4.0 * n_sub + n * (36.0 + 4.0 * nb + 8.0 + 4.0 + 16.0 * K)
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     # bytes the launch must move at least once: the scene it reads, pulses in, outputs out
     scene_bytes = 64.0 * max(mesh.n_triangles - 1, 1) + 48.0 * mesh.n_triangles + 4.0 * mesh.n_triangles

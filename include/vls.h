@@ -284,6 +284,10 @@ typedef struct {
                                   (default 16); deeper entries spill to per-lane scratch          */
     int32_t persistent_blocks; /* blocks of the persistent kernel; 0 = auto (CUs x occupancy)    */
     int32_t pack;              /* 0: floor(64/S) pulses per wavefront; 1: one pulse per wavefront */
+    int32_t cone;              /* 1 (default): one cone traversal per pulse collects the triangles
+                                  its subrays can hit (same results, less work); 0: every subray
+                                  traverses the LBVH on its own                                    */
+    int32_t reserved;
 } vls_launch_config;
 
 vls_status vls_set_launch_config(vls_context ctx, const vls_launch_config* cfg);

@@ -151,9 +151,12 @@ struct vls_context_s {
         int max_bins = 0;
     };
     std::vector<Batch> batches;  // uploaded segment tables, reused by content
+    int* cand = nullptr;         // cone-pass candidate lists, grown on demand
+    long long cand_pulses = 0;
     ~vls_context_s()
     {
         (void)hipSetDevice(device);
+        (void)hipFree(cand);
         for (auto& kv : patterns) (void)hipFree(kv.second);
         for (auto& b : batches) (void)hipFree(b.dev);
     }
@@ -185,11 +188,13 @@ struct vls_graph_s {
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int* cand = nullptr;
     ~vls_graph_s()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cs) (void)hipStreamDestroy(cs);
+        (void)hipFree(cand);
     }
 };
 
@@ -242,6 +247,7 @@ vls_status scanner_dev(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s
         s.s_peak = 2.0 * tau;
     }
     s.power_c = d.peak_power_w * d.efficiency * d.receiver_diameter_m * d.receiver_diameter_m / 4.0;
+    s.tan_max = S > 1 ? std::tan(d.pattern_extent * 0.5 * d.divergence_rad) : 0.0;
     s.thr_abs = d.min_echo_abs;
     s.thr_rel = d.min_echo_rel;
     return VLS_OK;
@@ -368,6 +374,7 @@ PulsesDev pulses_dev(const vls_pulse_batch* p)
     d.dirs = p->directions;
     d.t0_in = p->window_t0_ns;
     d.n = p->n_pulses;
+    d.cand = nullptr;
     return d;
 }
 
@@ -421,6 +428,26 @@ vls_status batch_tables(vls_context ctx, const Prepared& pr, vls_context_s::Batc
     ctx->batches.push_back(std::move(b));
     out = &ctx->batches.back();
     return VLS_OK;
+}
+
+// Candidate workspace for n pulses (allocated outside any capture).
+vls_status cone_workspace(vls_context ctx, long long n)
+{
+    if (!ctx->cfg.cone || n <= ctx->cand_pulses) return VLS_OK;
+    VLS_HIP(hipDeviceSynchronize(), "workspace sync");
+    (void)hipFree(ctx->cand);
+    ctx->cand = nullptr;
+    ctx->cand_pulses = 0;
+    VLS_HIP(hipMalloc(&ctx->cand, sizeof(int) * (size_t)(kCandMax + 1) * (size_t)n), "candidate workspace");
+    ctx->cand_pulses = n;
+    return VLS_OK;
+}
+
+double max_tan(const Prepared& pr)
+{
+    double t = 0.0;
+    for (auto& s : pr.sc) t = std::max(t, s.tan_max);
+    return t;
 }
 
 }  // namespace
@@ -493,10 +520,12 @@ vls_status vls_set_launch_config(vls_context ctx, const vls_launch_config* cfg)
     if (r < 4 || r > kMaxRing || (r & (r - 1)) != 0) return fail(VLS_ERR_INVALID_ARG, "stack_lds must be 4, 8, 16 or 32");
     if (cfg->persistent_blocks < 0) return fail(VLS_ERR_INVALID_ARG, "persistent_blocks must be >= 0");
     if (cfg->pack != 0 && cfg->pack != 1) return fail(VLS_ERR_INVALID_ARG, "pack must be 0 or 1");
+    if (cfg->cone != 0 && cfg->cone != 1) return fail(VLS_ERR_INVALID_ARG, "cone must be 0 or 1");
     ctx->cfg.block_waves = cfg->block_waves;
     ctx->cfg.stack_lds = r;
     ctx->cfg.persistent_blocks = cfg->persistent_blocks;
     ctx->cfg.pack = cfg->pack;
+    ctx->cfg.cone = cfg->cone;
     return VLS_OK;
 }
 
@@ -507,6 +536,8 @@ vls_status vls_get_launch_config(vls_context ctx, vls_launch_config* cfg)
     cfg->stack_lds = ctx->cfg.stack_lds;
     cfg->persistent_blocks = ctx->cfg.persistent_blocks;
     cfg->pack = ctx->cfg.pack;
+    cfg->cone = ctx->cfg.cone;
+    cfg->reserved = 0;
     return VLS_OK;
 }
 
@@ -648,9 +679,16 @@ vls_status vls_trace(vls_context ctx, vls_scene scene, const vls_scanner_desc* s
         if ((st = check_scene(ctx, scene)) != VLS_OK) return st;
         if ((st = check_outputs(out)) != VLS_OK) return st;
         if (pulses->n_pulses > 0 && !out->subray_tri) return fail(VLS_ERR_INVALID_ARG, "subray_tri is required");
+        if ((st = cone_workspace(ctx, pulses->n_pulses)) != VLS_OK) return st;
         OutDev od = out_dev(out, pr.S_stride);
         PulsesDev pd = pulses_dev(pulses);
         SceneDev sd = scene_dev(scene);
+        if (ctx->cfg.cone && pulses->n_pulses > 0) {
+            hipError_t e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, pulses->n_pulses, ctx->cfg, nullptr,
+                                       (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "cone launch");
+            pd.cand = ctx->cand;
+        }
         for (size_t s = 0; s + 1 < pr.off.size(); ++s) {
             hipError_t e = launch_simulate(sd, pr.sc[pr.seg_sc[s]], pd, od, pr.off[s], pr.off[s + 1] - pr.off[s], 0,
                                            ctx->cfg, (hipStream_t)stream);
@@ -714,6 +752,7 @@ static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_s
         return fail(VLS_ERR_INVALID_ARG, "simulate needs n_returns, ret_range, ret_amplitude and ret_bin");
     bt = nullptr;
     blocks = 0;
+    if ((st = cone_workspace(ctx, pulses->n_pulses)) != VLS_OK) return st;
     if (pulses->n_pulses > 0 && pulses->n_segments > 0) {
         if ((st = batch_tables(ctx, pr, bt)) != VLS_OK) return st;
         blocks = ctx->cfg.persistent_blocks > 0 ? ctx->cfg.persistent_blocks
@@ -722,14 +761,21 @@ static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_s
     return VLS_OK;
 }
 
+// cand: candidate workspace of at least n_pulses entries (the context's, or a graph's own)
 static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepared& pr, const vls_pulse_batch* pulses,
-                                   const vls_outputs* out, vls_context_s::Batch* bt, int blocks, hipStream_t s)
+                                   const vls_outputs* out, vls_context_s::Batch* bt, int blocks, hipStream_t s,
+                                   int* cand)
 {
     if (pulses->n_pulses == 0) return VLS_OK;
     OutDev od = out_dev(out, pr.S_stride);
     PulsesDev pd = pulses_dev(pulses);
     SceneDev sd = scene_dev(scene);
     hipError_t e;
+    if (ctx->cfg.cone) {
+        e = launch_cone(sd, max_tan(pr), pd, cand, 0, pulses->n_pulses, ctx->cfg, nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "cone launch");
+        pd.cand = cand;
+    }
     if (!bt) e = launch_simulate(sd, pr.sc[0], pd, od, 0, pulses->n_pulses, 1, ctx->cfg, s);
     else e = launch_persistent(sd, bt->bd, pr.n_bins, pd, od, ctx->cfg, blocks, s);
     return e == hipSuccess ? VLS_OK : hip_fail(e, "simulate launch");
@@ -744,7 +790,7 @@ vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc
         int blocks = 0;
         vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, bt, blocks);
         if (st != VLS_OK) return st;
-        return simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, (hipStream_t)stream);
+        return simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, (hipStream_t)stream, ctx->cand);
     } catch (const std::exception& e) {
         return fail(VLS_ERR_INTERNAL, e.what());
     }
@@ -769,6 +815,14 @@ vls_status vls_trace_counts(vls_context ctx, vls_scene scene, const vls_scanner_
         od.counts = dc;
         PulsesDev pd = pulses_dev(pulses);
         SceneDev sd = scene_dev(scene);
+        if ((st = cone_workspace(ctx, pulses->n_pulses)) != VLS_OK) {
+            (void)hipFree(dc);
+            return st;
+        }
+        if (e == hipSuccess && ctx->cfg.cone && pulses->n_pulses > 0) {
+            e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, pulses->n_pulses, ctx->cfg, dc, s);
+            pd.cand = ctx->cand;
+        }
         for (size_t g = 0; e == hipSuccess && g + 1 < pr.off.size(); ++g)
             e = launch_simulate(sd, pr.sc[pr.seg_sc[g]], pd, od, pr.off[g], pr.off[g + 1] - pr.off[g], 2, ctx->cfg, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -821,9 +875,13 @@ vls_status vls_graph_capture(vls_context ctx, vls_scene scene, const vls_scanner
         if (st != VLS_OK) return st;
         std::unique_ptr<vls_graph_s> g(new vls_graph_s());
         g->ctx = ctx;
+        // the graph owns its candidate workspace: the context's may be reallocated later
+        if (ctx->cfg.cone && pulses->n_pulses > 0)
+            VLS_HIP(hipMalloc(&g->cand, sizeof(int) * (size_t)(kCandMax + 1) * (size_t)pulses->n_pulses),
+                    "graph workspace");
         VLS_HIP(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking), "capture stream");
         VLS_HIP(hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal), "begin capture");
-        st = simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, g->cs);
+        st = simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, g->cs, g->cand);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(g->cs, &gr);
         if (st != VLS_OK) {
@@ -885,6 +943,7 @@ static bool tune_cache_find(const char* path, const std::string& key, vls_launch
         if ((p = strstr(line, "\"stack_lds\": "))) t.stack_lds = atoi(p + 13);
         if ((p = strstr(line, "\"persistent_blocks\": "))) t.persistent_blocks = atoi(p + 21);
         if ((p = strstr(line, "\"pack\": "))) t.pack = atoi(p + 8);
+        if ((p = strstr(line, "\"cone\": "))) t.cone = atoi(p + 8);
         c = t;
         found = true;
     }
@@ -917,10 +976,10 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             int bl = 0;
             vls_status r = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, b2, bl);
             if (r != VLS_OK) return r;
-            if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s)) != VLS_OK) return r;
+            if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s, ctx->cand)) != VLS_OK) return r;
             VLS_HIP(hipEventRecord(e0, s), "event");
             for (int i = 0; i < 2; ++i)
-                if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s)) != VLS_OK) return r;
+                if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s, ctx->cand)) != VLS_OK) return r;
             VLS_HIP(hipEventRecord(e1, s), "event");
             VLS_HIP(hipEventSynchronize(e1), "event");
             float f = 0.0f;
@@ -939,6 +998,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             c.stack_lds = cached.stack_lds;
             c.persistent_blocks = cached.persistent_blocks;
             c.pack = cached.pack;
+            c.cone = cached.cone;
             double ms = 0.0;
             if ((st = timed(c, ms)) != VLS_OK) { ctx->cfg = entry; return st; }
             best = c;
@@ -948,7 +1008,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             int tried = 1;
             const bool seg = pulses->n_segments > 0;
             int auto_blocks = seg ? persistent_occupancy_blocks(pr0.n_bins, entry) : 0;
-            for (int dim = 0; dim < 4; ++dim) {
+            for (int dim = 0; dim < 5; ++dim) {
                 std::vector<LaunchCfg> cand;
                 for (int v = 0; v < 4; ++v) {
                     LaunchCfg c = best;
@@ -956,12 +1016,13 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
                     if (dim == 1) c.stack_lds = 4 << v;
                     if (dim == 2) { if (v > 1) break; c.pack = v; }
                     if (dim == 3) { if (!seg || v > 2) break; c.persistent_blocks = v == 0 ? 0 : (v == 1 ? auto_blocks / 2 : 2 * auto_blocks); }
+                    if (dim == 4) { if (v > 1) break; c.cone = v; }
                     if (c.stack_lds + kMaxSpill - 1 < scene->stats.max_depth) continue;
                     cand.push_back(c);
                 }
                 for (auto& c : cand) {
                     if (c.block_waves == best.block_waves && c.stack_lds == best.stack_lds && c.pack == best.pack &&
-                        c.persistent_blocks == best.persistent_blocks)
+                        c.persistent_blocks == best.persistent_blocks && c.cone == best.cone)
                         continue;
                     double ms = 0.0;
                     if ((st = timed(c, ms)) != VLS_OK) { ctx->cfg = entry; return st; }
@@ -973,8 +1034,9 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             if (cache_path) {
                 FILE* f = fopen(cache_path, "a");
                 if (f) {
-                    fprintf(f, "{\"key\": \"%s\", \"block_waves\": %d, \"stack_lds\": %d, \"persistent_blocks\": %d, \"pack\": %d, \"ms\": %.6f}\n",
-                            key.c_str(), best.block_waves, best.stack_lds, best.persistent_blocks, best.pack, best_ms);
+                    fprintf(f, "{\"key\": \"%s\", \"block_waves\": %d, \"stack_lds\": %d, \"persistent_blocks\": %d, \"pack\": %d, \"cone\": %d, \"ms\": %.6f}\n",
+                            key.c_str(), best.block_waves, best.stack_lds, best.persistent_blocks, best.pack, best.cone,
+                            best_ms);
                     fclose(f);
                 }
             }
@@ -986,6 +1048,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
         result->best.stack_lds = best.stack_lds;
         result->best.persistent_blocks = best.persistent_blocks;
         result->best.pack = best.pack;
+        result->best.cone = best.cone;
         result->best_ms = best_ms;
         return VLS_OK;
     } catch (const std::exception& e) {

@@ -199,7 +199,20 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
     const double* pat = sc.pattern + 5 * k;
     Ray r;
     if (!setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, pat, scene.bounds[12], r)) return;
-    Hit h = traverse<COUNT>(scene, r, ring, ring_mask, visits, tests);
+    Hit h;
+    const int* cand = pulses.cand ? pulses.cand + p * (kCandMax + 1) : nullptr;
+    const int nc = cand ? cand[0] : -1;
+    if (nc >= 0) {
+        // the cone pass found every triangle any subray of this pulse can hit
+        h.t = INFINITY;
+        h.leaf = -1;
+        h.orig = 0x7fffffff;
+        float tcull = INFINITY;
+        for (int i = 0; i < nc; ++i) leaf_test(r, scene.tris, cand[1 + i], h, tcull);
+        if (COUNT) tests += nc;
+    } else {
+        h = traverse<COUNT>(scene, r, ring, ring_mask, visits, tests);
+    }
     if (h.leaf < 0) return;
     double c, pw;
     shade(scene, sc, r, h, pat[4], c, pw);

@@ -12,6 +12,7 @@ constexpr double kCmPerNs = 0.299792458;  // speed of light in m/ns (Sec. 3.4)
 constexpr int kWave = 64;                 // CDNA wavefront
 constexpr int kMaxSpill = 112;            // traversal-stack entries per lane beyond the LDS ring
 constexpr int kMaxRing = 32;
+constexpr int kCandMax = 15;             // candidate leaves kept per pulse by the cone pass
 
 // One scanner as the kernels see it (everything derived on the host in FP64).
 struct ScannerDev {
@@ -32,6 +33,7 @@ struct ScannerDev {
     double power_c;         // peak * eff * D^2 / 4
     double thr_abs;
     double thr_rel;
+    double tan_max;         // tan of the largest subray angle (outer ring)
 };
 
 // Binary LBVH: node = 4 x float4 (64 B): left box lo.xyz hi.x | hi.yz, right lo.xy |
@@ -54,6 +56,8 @@ struct PulsesDev {
     const float* dirs;
     const double* t0_in;    // may be null
     long long n;
+    const int* cand;        // [n][kCandMax + 1] candidate leaves from the cone pass, or null:
+                            // entry 0 = count (-1 = overflow, use full traversal), then leaf ids
 };
 
 struct OutDev {
@@ -91,6 +95,7 @@ struct LaunchCfg {
     int stack_lds = 16;
     int persistent_blocks = 0;
     int pack = 0;  // 0: floor(64/S) pulses per wavefront; 1: one pulse per wavefront
+    int cone = 1;  // 1: one cone traversal per pulse collects candidate triangles for its subrays
 };
 
 // ---- host-side launchers (defined in the .hip files) ----
@@ -125,6 +130,11 @@ hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int m
 hipError_t launch_backward(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
                            const int32_t* sub_tri, int sub_stride, const float* grad_wf, float* grad_refl,
                            float* grad_z, long long n_vert, const LaunchCfg& cfg, hipStream_t stream);
+// Cone pass: pulses [first, first + count), cone slope tan_max (largest over the
+// scanners in use).  Writes cand[p * (kCandMax + 1) ...]; counts (optional)
+// accumulates node visits into counts[1].
+hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
+                       long long count, const LaunchCfg& cfg, unsigned long long* counts, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);
 int persistent_occupancy_blocks(int max_bins, const LaunchCfg& cfg);
 

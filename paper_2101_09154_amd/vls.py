@@ -66,7 +66,8 @@ class Outputs(ctypes.Structure):
 
 
 class LaunchConfig(ctypes.Structure):
-    _fields_ = [("block_waves", i32), ("stack_lds", i32), ("persistent_blocks", i32), ("pack", i32)]
+    _fields_ = [("block_waves", i32), ("stack_lds", i32), ("persistent_blocks", i32), ("pack", i32),
+                ("cone", i32), ("reserved", i32)]
 
 
 class TuneResult(ctypes.Structure):
@@ -274,15 +275,15 @@ class Context:
     def scene(self, vertices, triangles, reflectance, stream=None):
         return Scene(self, vertices, triangles, reflectance, stream)
 
-    def set_launch_config(self, block_waves=1, stack_lds=16, persistent_blocks=0, pack=0):
-        c = LaunchConfig(block_waves, stack_lds, persistent_blocks, pack)
+    def set_launch_config(self, block_waves=1, stack_lds=16, persistent_blocks=0, pack=0, cone=1):
+        c = LaunchConfig(block_waves, stack_lds, persistent_blocks, pack, cone, 0)
         _check(lib().vls_set_launch_config(self._h, ctypes.byref(c)))
 
     def launch_config(self):
         c = LaunchConfig()
         _check(lib().vls_get_launch_config(self._h, ctypes.byref(c)))
         return {"block_waves": c.block_waves, "stack_lds": c.stack_lds, "persistent_blocks": c.persistent_blocks,
-                "pack": c.pack}
+                "pack": c.pack, "cone": c.cone}
 
     def synchronize(self, stream=None):
         _check(lib().vls_synchronize(self._h, _stream(stream)))
@@ -416,7 +417,8 @@ class Context:
                                   None if cache_path is None else cache_path.encode(), _stream(stream),
                                   ctypes.byref(r)))
         return {"best": {"block_waves": r.best.block_waves, "stack_lds": r.best.stack_lds,
-                         "persistent_blocks": r.best.persistent_blocks, "pack": r.best.pack},
+                         "persistent_blocks": r.best.persistent_blocks, "pack": r.best.pack,
+                         "cone": r.best.cone},
                 "best_ms": r.best_ms, "default_ms": r.default_ms, "n_tried": r.n_tried,
                 "from_cache": bool(r.from_cache)}
 

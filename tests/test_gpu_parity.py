@@ -206,12 +206,14 @@ def test_fixed_window_origin(ctx):
 
 
 def test_stack_spill_bitwise(ctx):
+    # LDS stack sizes (4 forces scratch spills), block shapes and the cone pass
+    # change nothing but speed
     mesh, pulses, sc = configs.small_tls()
     scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
     base = None
-    for ring, waves in ((16, 4), (4, 4), (8, 1), (32, 2)):
-        say("ring", ring, "waves", waves, "depth", scene.stats()["max_depth"])
-        ctx.set_launch_config(block_waves=waves, stack_lds=ring)
+    for ring, waves, cone in ((16, 4, 1), (16, 4, 0), (4, 4, 1), (4, 1, 0), (8, 1, 1), (32, 2, 0)):
+        say("ring", ring, "waves", waves, "cone", cone, "depth", scene.stats()["max_depth"])
+        ctx.set_launch_config(block_waves=waves, stack_lds=ring, cone=cone)
         g = run_gpu(ctx, scene, pulses, sc)
         if base is None:
             base = g
@@ -487,3 +489,113 @@ def test_autograd_function(ctx):
     assert torch.allclose(refl.grad, gr, rtol=1e-5, atol=1e-6 * float(gr.abs().max()))
     assert torch.allclose(heights.grad, gz, rtol=1e-5, atol=1e-6 * float(gz.abs().max()))
     assert float(refl.grad.abs().sum()) > 0 and float(heights.grad.abs().sum()) > 0
+
+
+# ------------------------------------------------------------------ more full-size workloads, sampled
+
+
+def _rows(out, sel):
+    idx = torch.from_numpy(np.asarray(sel, dtype=np.int64)).cuda()
+    return {k: v.index_select(0, idx).cpu().numpy() for k, v in out.items()}
+
+
+def test_uls_trees_sampled(ctx):
+    mesh, pulses, sc = configs.uls_trees()
+    say("uls_trees: scene", mesh.n_triangles, "pulses", pulses.n)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    say("uls_trees stats", scene.stats())
+    o = _dev(pulses.origins)
+    d = _dev(pulses.directions)
+    out = ctx.simulate(scene, sc, o, d)
+    torch.cuda.synchronize()
+    # pulses whose beam axis lands inside the terrain, where the trees are
+    rng = np.random.default_rng(5)
+    x_land = pulses.origins[:, 0] - pulses.directions[:, 0] / pulses.directions[:, 2] * 60.0
+    inside = np.nonzero((x_land > 10) & (x_land < 190))[0]
+    sel = np.sort(rng.choice(inside, 12, replace=False))
+    g = _rows(out, sel)
+    sub = pulses.subset(sel)
+    rep = compare(mesh, sub, sc, g, label="uls_trees")
+    nr = out["n_returns"].cpu().numpy()
+    say("returns per pulse histogram", np.bincount(nr, minlength=9))
+    assert nr.max() <= 8 and (nr >= 2).mean() > 0.01
+
+
+def test_batched_full_sampled(ctx):
+    mesh = configs.als_scene()
+    _, pulses, scs = configs.batched_tls(mesh=mesh)
+    say("batched_tls:", pulses.n, "pulses")
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = _dev(pulses.origins)
+    d = _dev(pulses.directions)
+    off, seg = pulses.segment_offsets, pulses.segment_scanner
+    out = ctx.simulate(scene, scs, o, d, segment_offsets=off, segment_scanner=seg, subrays=False)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    for typ in range(3):
+        segs = np.nonzero(seg == typ)[0]
+        s = int(rng.choice(segs))
+        a, b = int(off[s]), int(off[s + 1])
+        # the segment alone, through the plain launch: bitwise equal
+        alone = ctx.simulate(scene, scs[typ], o[a:b], d[a:b])
+        torch.cuda.synchronize()
+        for k in out:
+            assert torch.equal(out[k][a:b].nan_to_num(-1), alone[k].nan_to_num(-1)), (s, k)
+        sel = np.sort(rng.choice(np.arange(a, b), 3, replace=False))
+        g = _rows(alone, sel - a)
+        compare(mesh, pulses.subset(sel), scs[typ], g, label="batched segment %d" % s)
+
+
+def test_gradient_full_sampled(ctx):
+    mesh, target, pulses, sc = configs.diff_als()
+    say("diff_als:", mesh.n_triangles, pulses.n)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = _dev(pulses.origins)
+    d = _dev(pulses.directions)
+    rng = np.random.default_rng(2)
+    sel = np.sort(rng.choice(pulses.n, 300, replace=False))
+    sub = pulses.subset(sel)
+    base = oracle.simulate(mesh, sub, sc)
+    t0_all = ctx.simulate(scene, sc, o, d)["window_t0_ns"].cpu().numpy()
+    t0_all[sel] = base.t0
+    tgt = oracle.simulate(target, sub, sc, t0=base.t0).waveform
+    Gs = 2.0 * (base.waveform - tgt)
+    gr_o, gz_o = oracle.gradient(mesh, sub, sc, base.t0, Gs)
+    # full-size launch; only the sampled pulses carry a loss gradient
+    G = torch.zeros((pulses.n, sc["n_bins"]), dtype=torch.float32, device="cuda")
+    G[torch.from_numpy(sel).cuda()] = _dev(Gs.astype(np.float32))
+    t0d = _dev(t0_all)
+    out = ctx.simulate(scene, sc, o, d, t0=t0d)
+    gr, gz = ctx.waveform_backward(scene, sc, o, d, t0d, out["subray_tri"], G)
+    torch.cuda.synchronize()
+    assert np.array_equal(out["subray_tri"].cpu().numpy()[sel], base.sub_tri)
+    gr = gr.cpu().numpy().astype(np.float64)
+    gz = gz.cpu().numpy().astype(np.float64)
+    er = np.linalg.norm(gr - gr_o) / np.linalg.norm(gr_o)
+    ez = np.linalg.norm(gz - gz_o) / np.linalg.norm(gz_o)
+    say("full-size gradient rel L2: reflectance %.2e heights %.2e" % (er, ez))
+    assert er <= 1e-4 and ez <= 1e-4
+
+
+def test_cone_pass_bitwise_on_buildings(ctx):
+    # ALS over buildings (few candidates per pulse) and terrestrial pulses through
+    # dense buildings (candidate overflow -> per-subray traversal): same bits
+    mesh = configs.als_scene()
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    _, als, sc = configs.als_buildings(mesh=mesh, n_lines=40, per_line=1000)
+    _, tls, scs = configs.batched_tls(mesh=mesh, n_positions=6, count_range=(2000, 4000))
+    for pulses, scn, kw in ((als, sc, {}), (tls, scs, dict(segment_offsets=tls.segment_offsets,
+                                                          segment_scanner=tls.segment_scanner))):
+        o = _dev(pulses.origins)
+        d = _dev(pulses.directions)
+        res = []
+        for cone in (1, 0):
+            ctx.set_launch_config(cone=cone)
+            say("cone", cone, pulses.n)
+            res.append(to_np(ctx.simulate(scene, scn, o, d, **kw)))
+        for k in res[0]:
+            a, b = res[0][k], res[1][k]
+            if k.startswith("subray") and kw:
+                continue
+            assert np.array_equal(a, b, equal_nan=True), k
+    ctx.set_launch_config()
