@@ -31,12 +31,6 @@ namespace {
 
 using namespace dev;
 
-__device__ __forceinline__ float wave_sum_f(float v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 struct Grads {
     double grho, gz[3];
 };

@@ -228,6 +228,7 @@ vls_status scanner_dev(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s
     s.K = d.max_returns;
     s.shape = d.pulse_shape;
     s.bin_ns = (float)d.bin_ns;
+    s.inv_bin = (float)(1.0 / d.bin_ns);
     const double log2e = 1.4426950408889634;
     if (d.pulse_shape == VLS_PULSE_GAUSSIAN) {
         double sg = d.pulse_width_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));

@@ -156,8 +156,10 @@ __global__ __launch_bounds__(256) void k_cone(SceneDev scene, double tana, Pulse
         if (scene.n_tri > 0 && setup_cone(pulses.origins + 3 * p, pulses.dirs + 3 * p, tana, scene.bounds[12], c)) {
             float tcull = INFINITY;
             const int stride = blockDim.x;
-            int* my = reinterpret_cast<int*>(smem) + threadIdx.x;
-            int spill[kMaxSpill];
+            // stack entries carry their entry distance, so nodes pushed before a
+            // cull distance was known are dropped when popped
+            int2* my = reinterpret_cast<int2*>(smem) + threadIdx.x;
+            int2 spill[kMaxSpill];
             int sp = 0, nlow = 0;
             int node = scene.root;
             const int n_int = scene.n_tri - 1;
@@ -173,8 +175,9 @@ __global__ __launch_bounds__(256) void k_cone(SceneDev scene, double tana, Pulse
                     bool hr = cone_box(c, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr);
                     int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
                     if (hl && hr) {
-                        int nearc = (tl <= tr) ? cl : cr;
-                        int farc = (tl <= tr) ? cr : cl;
+                        const bool lfirst = tl <= tr;
+                        int nearc = lfirst ? cl : cr;
+                        int2 farc = make_int2(lfirst ? cr : cl, __float_as_int(lfirst ? tr : tl));
                         if (sp - nlow > ring_mask) {
                             if (nlow < kMaxSpill) spill[nlow] = my[(nlow & ring_mask) * stride];
                             ++nlow;
@@ -200,14 +203,24 @@ __global__ __launch_bounds__(256) void k_cone(SceneDev scene, double tana, Pulse
                         tcull = fminf(tcull, tf);
                     }
                 }
-                if (sp == 0) break;
-                --sp;
-                if (sp < nlow) {
-                    node = sp < kMaxSpill ? spill[sp] : -1;
-                    nlow = sp;
-                } else {
-                    node = my[(sp & ring_mask) * stride];
+                // pop the next node that can still hold a closest hit
+                bool found = false;
+                while (sp > 0) {
+                    --sp;
+                    int2 e;
+                    if (sp < nlow) {
+                        e = sp < kMaxSpill ? spill[sp] : make_int2(-1, 0);
+                        nlow = sp;
+                    } else {
+                        e = my[(sp & ring_mask) * stride];
+                    }
+                    if (__int_as_float(e.y) <= tcull) {
+                        node = e.x;
+                        found = true;
+                        break;
+                    }
                 }
+                if (!found) break;
             }
             if (budget <= 0) n = -1;
         }
@@ -228,7 +241,7 @@ hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& p
     if (count <= 0) return hipSuccess;
     const int block = 64 * cfg.block_waves;
     unsigned grid = (unsigned)((count + block - 1) / block);
-    size_t lds = sizeof(int) * (size_t)cfg.stack_lds * block;
+    size_t lds = sizeof(int2) * (size_t)cfg.stack_lds * block;
     int mask = cfg.stack_lds - 1;
     if (counts)
         hipLaunchKernelGGL(k_cone<true>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, first,

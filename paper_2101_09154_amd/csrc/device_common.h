@@ -17,29 +17,79 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ double wave_min_d(double v)
+// Whole-wavefront reductions with DPP (data-parallel primitives): pairs and
+// quads, half-rows and rows by mirroring, then row broadcasts of lanes 15 and
+// 31; lane 63 ends with the result, which readlane makes wave-uniform.  Every
+// lane must be active.  Each step is one DPP move plus the operation.
+#define VLS_DPP_STEPS(STEP) STEP(0xB1, 0xF) STEP(0x4E, 0xF) STEP(0x141, 0xF) STEP(0x140, 0xF) STEP(0x142, 0xA) STEP(0x143, 0xC)
+
+__device__ __forceinline__ int wave_bcast63_i(int v) { return __builtin_amdgcn_readlane(v, 63); }
+
+__device__ __forceinline__ float wave_min_f(float v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
+    const int id = __float_as_int(INFINITY);
+#define VLS_STEP(C, M) v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(id, __float_as_int(v), C, M, 0xF, false)));
+    VLS_DPP_STEPS(VLS_STEP)
+#undef VLS_STEP
+    return __int_as_float(wave_bcast63_i(__float_as_int(v)));
 }
 
 __device__ __forceinline__ float wave_max_f(float v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return v;
+    const int id = __float_as_int(-INFINITY);
+#define VLS_STEP(C, M) v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(id, __float_as_int(v), C, M, 0xF, false)));
+    VLS_DPP_STEPS(VLS_STEP)
+#undef VLS_STEP
+    return __int_as_float(wave_bcast63_i(__float_as_int(v)));
+}
+
+__device__ __forceinline__ float wave_sum_f(float v)
+{
+#define VLS_STEP(C, M) v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), C, M, 0xF, false));
+    VLS_DPP_STEPS(VLS_STEP)
+#undef VLS_STEP
+    return __int_as_float(wave_bcast63_i(__float_as_int(v)));
 }
 
 __device__ __forceinline__ int wave_min_i(int v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
+#define VLS_STEP(C, M) v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, C, M, 0xF, false));
+    VLS_DPP_STEPS(VLS_STEP)
+#undef VLS_STEP
+    return wave_bcast63_i(v);
 }
 
 __device__ __forceinline__ int wave_max_i(int v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
+#define VLS_STEP(C, M) v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, C, M, 0xF, false));
+    VLS_DPP_STEPS(VLS_STEP)
+#undef VLS_STEP
+    return wave_bcast63_i(v);
 }
+
+__device__ __forceinline__ double wave_min_d(double v)
+{
+    const int id_lo = __double2loint(INFINITY), id_hi = __double2hiint(INFINITY);
+#define VLS_STEP(C, M)                                                                         \
+    v = fmin(v, __hiloint2double(__builtin_amdgcn_update_dpp(id_hi, __double2hiint(v), C, M, 0xF, false), \
+                                 __builtin_amdgcn_update_dpp(id_lo, __double2loint(v), C, M, 0xF, false)));
+    VLS_DPP_STEPS(VLS_STEP)
+#undef VLS_STEP
+    return __hiloint2double(wave_bcast63_i(__double2hiint(v)), wave_bcast63_i(__double2loint(v)));
+}
+
+// Value of lane l - 1 (lane 0 gets `edge`) and of lane l + 1 (lane 63 gets `edge`).
+__device__ __forceinline__ float lane_prev_f(float v, float edge)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float lane_next_f(float v, float edge)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float lane_read_f(float v, int lane) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane)); }
 
 __device__ __forceinline__ unsigned lanes_below(unsigned long long m)
 {
@@ -111,11 +161,14 @@ __device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const fl
 
 __device__ __forceinline__ double pick(double x, double y, double z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
 
+// Outgoing pulse at offset s (ns): unit-peak Gaussian, or Eq. 3 (s/tau)^2 exp(-s/tau).
+// exp2 is the hardware instruction: results below 2^-126 flush to zero, far under
+// any bin that matters.
 __device__ __forceinline__ float pulse_shape(const ScannerDev& sc, float s)
 {
-    if (sc.shape == 0) return exp2f(s * s * sc.neg_k);
+    if (sc.shape == 0) return __builtin_amdgcn_exp2f(s * s * sc.neg_k);
     float x = s * sc.inv_tau;
-    return s > 0.0f ? x * x * exp2f(x * sc.neg_k) : 0.0f;
+    return s > 0.0f ? x * x * __builtin_amdgcn_exp2f(x * sc.neg_k) : 0.0f;
 }
 
 }  // namespace dev

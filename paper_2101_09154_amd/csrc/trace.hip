@@ -44,12 +44,11 @@ namespace {
 
 using namespace dev;
 
+// Per-wavefront LDS: the subrays' waveform inputs, and the candidate triangles of
+// the wavefront's pulses staged by one parallel load (slot = pulse * 16 + candidate).
 struct WaveLds {
-    double tau[kWave];
-    float hi[kWave];
-    float lo[kWave];
-    float pw[kWave];
-    int tri[kWave];
+    float4 sub[kWave];   // (offset hi, offset lo, power, triangle as int bits) per subray lane
+    float4 rec[3][kWave];
 };
 
 __device__ __forceinline__ bool box_hit(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz,
@@ -75,10 +74,9 @@ struct Hit {
 // the ray runs along +kz; the 2-D edge functions U, V, W are then evaluated from
 // the same operands for both triangles of a shared edge, so no ray slips
 // between them.  t = T / det is formed only for candidates inside the triangle.
-__device__ __forceinline__ void leaf_test(const Ray& r, const float4* __restrict__ tris, int li, Hit& h, float& tcull)
+__device__ __forceinline__ bool leaf_test_rec(const Ray& r, float4 Pa, float4 Pb, float4 Pc, Hit& h, float& tcull)
 {
 #pragma clang fp contract(off)
-    float4 Pa = tris[3 * li], Pb = tris[3 * li + 1], Pc = tris[3 * li + 2];
     int orig = __float_as_int(Pa.w);
     double a0 = (double)Pa.x - r.O[0], a1 = (double)Pa.y - r.O[1], a2 = (double)Pa.z - r.O[2];
     double b0 = (double)Pb.x - r.O[0], b1 = (double)Pb.y - r.O[1], b2 = (double)Pb.z - r.O[2];
@@ -90,20 +88,26 @@ __device__ __forceinline__ void leaf_test(const Ray& r, const float4* __restrict
     double U = Cx * By - Cy * Bx;
     double V = Ax * Cy - Ay * Cx;
     double W = Bx * Ay - By * Ax;
-    if ((U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0)) return;
+    if ((U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0)) return false;
     double det = U + V + W;
-    if (det == 0.0) return;
+    if (det == 0.0) return false;
     double T = U * (r.Sz * Az) + V * (r.Sz * Bz) + W * (r.Sz * Cz);
     double t = T / det;
-    if (!(t > 0.0)) return;
+    if (!(t > 0.0)) return false;
     if (t < h.t || (t == h.t && orig < h.orig)) {
         h.t = t;
         h.orig = orig;
-        h.leaf = li;
         float tf = (float)t;
         if ((double)tf < t) tf = nextafterf(tf, INFINITY);
         tcull = tf;
+        return true;
     }
+    return false;
+}
+
+__device__ __forceinline__ void leaf_test(const Ray& r, const float4* __restrict__ tris, int li, Hit& h, float& tcull)
+{
+    if (leaf_test_rec(r, tris[3 * li], tris[3 * li + 1], tris[3 * li + 2], h, tcull)) h.leaf = li;
 }
 
 // Closest hit of one ray.  ring: this block's LDS ring, stride = blockDim.x.
@@ -173,10 +177,9 @@ __device__ __forceinline__ Hit traverse(const SceneDev& scene, const Ray& r, int
 // Incidence and power of the chosen triangle (Sec. 5.2, Eq. 7):
 // cos = |d . n| / |n|, P = C w rho cos / R^2, all in FP64 as written.
 __device__ __forceinline__ void shade(const SceneDev& scene, const ScannerDev& sc, const Ray& r, const Hit& h,
-                                      double w, double& cosang, double& P)
+                                      float4 A, float4 B, float4 C, double w, double& cosang, double& P)
 {
 #pragma clang fp contract(off)
-    float4 A = scene.tris[3 * h.leaf], B = scene.tris[3 * h.leaf + 1], C = scene.tris[3 * h.leaf + 2];
     double e1x = (double)B.x - A.x, e1y = (double)B.y - A.y, e1z = (double)B.z - A.z;
     double e2x = (double)C.x - A.x, e2y = (double)C.y - A.y, e2z = (double)C.z - A.z;
     double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
@@ -186,10 +189,12 @@ __device__ __forceinline__ void shade(const SceneDev& scene, const ScannerDev& s
 }
 
 // Trace one lane's subray: fills tri (original index or -1), R, cos, P.
+// staged: the pulse's candidate records sit in wl->rec slots [q * 16, q * 16 + nc).
 template <bool COUNT>
 __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
-                                           long long p, int k, int* ring, int ring_mask,
-                                           int& tri, double& R, float& cosang, float& P, int& visits, int& tests)
+                                           long long p, int k, int q, bool staged, const WaveLds* wl, int* ring,
+                                           int ring_mask, int& tri, double& R, float& cosang, float& P, int& visits,
+                                           int& tests)
 {
     tri = -1;
     R = INFINITY;
@@ -200,42 +205,69 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
     Ray r;
     if (!setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, pat, scene.bounds[12], r)) return;
     Hit h;
-    const int* cand = pulses.cand ? pulses.cand + p * (kCandMax + 1) : nullptr;
-    const int nc = cand ? cand[0] : -1;
+    h.t = INFINITY;
+    h.leaf = -1;
+    h.orig = 0x7fffffff;
+    const int nc = pulses.cand ? pulses.cand[p * (kCandMax + 1)] : -1;
+    float4 A, B, C;
     if (nc >= 0) {
         // the cone pass found every triangle any subray of this pulse can hit
-        h.t = INFINITY;
-        h.leaf = -1;
-        h.orig = 0x7fffffff;
         float tcull = INFINITY;
-        for (int i = 0; i < nc; ++i) leaf_test(r, scene.tris, cand[1 + i], h, tcull);
+        if (staged) {
+            int best = -1;
+            for (int i = 0; i < nc; ++i) {
+                const int slot = q * 16 + i;
+                if (leaf_test_rec(r, wl->rec[0][slot], wl->rec[1][slot], wl->rec[2][slot], h, tcull)) best = slot;
+            }
+            if (best >= 0) {
+                h.leaf = best;
+                A = wl->rec[0][best];
+                B = wl->rec[1][best];
+                C = wl->rec[2][best];
+            }
+        } else {
+            const int* cand = pulses.cand + p * (kCandMax + 1);
+            for (int i = 0; i < nc; ++i) leaf_test(r, scene.tris, cand[1 + i], h, tcull);
+            if (h.leaf >= 0) {
+                A = scene.tris[3 * h.leaf];
+                B = scene.tris[3 * h.leaf + 1];
+                C = scene.tris[3 * h.leaf + 2];
+            }
+        }
         if (COUNT) tests += nc;
     } else {
         h = traverse<COUNT>(scene, r, ring, ring_mask, visits, tests);
+        if (h.leaf >= 0) {
+            A = scene.tris[3 * h.leaf];
+            B = scene.tris[3 * h.leaf + 1];
+            C = scene.tris[3 * h.leaf + 2];
+        }
     }
     if (h.leaf < 0) return;
     double c, pw;
-    shade(scene, sc, r, h, pat[4], c, pw);
+    shade(scene, sc, r, h, A, B, C, pat[4], c, pw);
     tri = h.orig;
     R = h.t;
     cosang = (float)c;
     P = (float)pw;
 }
 
-// Waveform and/or returns of one pulse whose subrays sit in wl[k0 .. k0+S).
+// Waveform and/or returns of one pulse whose subrays are lanes [k0, k0 + S).
+// Each lane passes its own subray (tau = 2R/c, power, triangle; tri < 0: miss).
 // COMPUTE: synthesise wf from the subrays (else load wf and t0 from `out`).
 // RET: detect returns.  attrib: subray data present for return attribution.
 template <int MAXCH, bool COMPUTE, bool RET>
 __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
-                                            long long p, int k0, WaveLds* wl, bool attrib)
+                                            long long p, int k0, WaveLds* wl, bool attrib, double my_tau,
+                                            float my_pw, int my_tri)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int S = sc.S, nb = sc.n_bins, K = sc.K;
-    const bool mine = lane >= k0 && lane < k0 + S;
+    const bool mine = lane >= k0 && lane < k0 + S && my_tri >= 0;
     double t0;
     bool any;
     if (COMPUTE || attrib) {
-        double tmin = wave_min_d(mine ? wl->tau[lane] : INFINITY);
+        double tmin = wave_min_d(mine ? my_tau : INFINITY);
         any = tmin < INFINITY;
         if (COMPUTE) {
             if (pulses.t0_in) t0 = pulses.t0_in[p];
@@ -266,14 +298,17 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
     int c_lo = 0, c_hi = MAXCH - 1;
     if (have && (COMPUTE || attrib)) {
         int jl = 0x7fffffff, jh = -0x7fffffff;
-        if (mine && wl->tri[lane] >= 0) {
-            double rel = wl->tau[lane] - t0;
-            float hi = (float)rel;
-            wl->hi[lane] = hi;
-            wl->lo[lane] = (float)(rel - (double)hi);
-            double a = ceil((rel - sc.cut_lo) / sc.bin_ns), b = floor((rel + sc.cut_hi) / sc.bin_ns);
-            jl = (int)fmax(fmin(a, 1e9), -1e9);
-            jh = (int)fmax(fmin(b, 1e9), -1e9);
+        if (lane >= k0 && lane < k0 + S) {
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+            if (mine) {
+                double rel = my_tau - t0;
+                float hi = (float)rel;
+                v = make_float4(hi, (float)(rel - (double)hi), my_pw, __int_as_float(my_tri));
+                // support of this echo in bins, widened by one bin against rounding
+                jl = (int)fmaxf(floorf((hi - sc.cut_lo) * sc.inv_bin) - 1.0f, -1e9f);
+                jh = (int)fminf(ceilf((hi + sc.cut_hi) * sc.inv_bin) + 1.0f, 1e9f);
+            }
+            wl->sub[lane] = v;
         }
         wave_sync();
         jl = max(wave_min_i(jl), 0);
@@ -292,9 +327,10 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
                 float acc = 0.0f, best = -1.0f;
                 int bki = -1;
                 for (int kk = 0; kk < S; ++kk) {
-                    if (wl->tri[k0 + kk] < 0) continue;
-                    float s = (xh - wl->hi[k0 + kk]) + (xl - wl->lo[k0 + kk]);
-                    float val = wl->pw[k0 + kk] * pulse_shape(sc, s);
+                    const float4 u = wl->sub[k0 + kk];
+                    if (__float_as_int(u.w) < 0) continue;
+                    float s = (xh - u.x) + (xl - u.y);
+                    float val = u.z * pulse_shape(sc, s);
                     acc += val;
                     if (val > best) {
                         best = val;
@@ -330,12 +366,11 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
             if (c * kWave >= nb) break;
             if (c < c_lo || c > c_hi) continue;  // all zero: no return can start here
             float v = wf[c];
-            float left = __shfl_up(v, 1);
-            float right = __shfl_down(v, 1);
-            float prev = c > 0 ? __shfl(wf[c > 0 ? c - 1 : 0], 63) : 0.0f;
-            float next = c + 1 < MAXCH ? __shfl(wf[c + 1 < MAXCH ? c + 1 : c], 0) : 0.0f;
-            if (lane == 0) left = prev;
-            if (lane == kWave - 1) right = next;
+            // neighbours: lane shifts, with the adjacent chunk's edge lane at the ends
+            float prev = c > 0 ? lane_read_f(wf[c > 0 ? c - 1 : 0], 63) : 0.0f;
+            float next = c + 1 < MAXCH ? lane_read_f(wf[c + 1 < MAXCH ? c + 1 : c], 0) : 0.0f;
+            float left = lane_prev_f(v, prev);
+            float right = lane_next_f(v, next);
             int j = c * kWave + lane;
             bool cand = j >= 1 && j <= nb - 2 && v > left && v >= right && v >= thr;
             unsigned long long mk = __ballot(cand);
@@ -345,7 +380,8 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
                 out.ret_range[o] = (float)(0.5 * kCmPerNs * (t0 + (double)j * sc.bin_ns - sc.s_peak));
                 out.ret_amp[o] = v;
                 out.ret_bin[o] = j;
-                if (out.ret_tri) out.ret_tri[o] = (attrib && bk[c] >= 0) ? wl->tri[k0 + bk[c]] : -1;
+                if (out.ret_tri)
+                    out.ret_tri[o] = (attrib && bk[c] >= 0) ? __float_as_int(wl->sub[k0 + bk[c]].w) : -1;
             }
             count += __popcll(mk);
         }
@@ -374,13 +410,27 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     const int pl = lane / S;
     const int k = lane - pl * S;
     const bool active = pl < npw;
+    // stage the candidate triangles of up to 4 pulses with one load per lane
+    const bool staged = pulses.cand && sc.P_w <= 4;
+    if (staged) {
+        const int q = lane >> 4, c = lane & 15;
+        int nq = -1;
+        if (q < npw) nq = pulses.cand[(first + q) * (kCandMax + 1)];
+        if (c < nq) {
+            const int li = pulses.cand[(first + q) * (kCandMax + 1) + 1 + c];
+            wl->rec[0][lane] = scene.tris[3 * li];
+            wl->rec[1][lane] = scene.tris[3 * li + 1];
+            wl->rec[2][lane] = scene.tris[3 * li + 2];
+        }
+        wave_sync();
+    }
     int tri = -1;
     double R = INFINITY;
     float cs = 0.0f, P = 0.0f;
     int visits = 0, tests = 0;
     if (active) {
         long long p = first + pl;
-        trace_lane<MODE == 2>(scene, sc, pulses, p, k, ring, ring_mask, tri, R, cs, P, visits, tests);
+        trace_lane<MODE == 2>(scene, sc, pulses, p, k, pl, staged, wl, ring, ring_mask, tri, R, cs, P, visits, tests);
         long long o = p * out.sub_stride + k;
         if (out.sub_tri) out.sub_tri[o] = tri;
         if (out.sub_range) out.sub_range[o] = R;
@@ -402,15 +452,10 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
         return;
     }
     if (MODE == 0) return;
-    wl->tau[lane] = (active && tri >= 0) ? 2.0 * R / kCmPerNs : (double)INFINITY;
-    wl->pw[lane] = P;
-    wl->tri[lane] = active ? tri : -1;
-    wave_sync();
-    for (int q = 0; q < npw; ++q) pulse_phase<MAXCH, true, true>(sc, pulses, out, first + q, q * S, wl, true);
+    const double tau = (active && tri >= 0) ? 2.0 * R / kCmPerNs : (double)INFINITY;
+    for (int q = 0; q < npw; ++q) pulse_phase<MAXCH, true, true>(sc, pulses, out, first + q, q * S, wl, true, tau, P, tri);
 }
 
-// Traversal is latency-bound: six wavefronts per SIMD (at most 80 VGPRs, a few
-// bytes of spills) measured faster than four or five without spills.
 template <int MAXCH, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_simulate(SceneDev scene, ScannerDev sc, PulsesDev pulses,
                                                   OutDev out, long long first, long long count, int ring_mask)
@@ -444,26 +489,21 @@ __global__ __launch_bounds__(256) void k_wave(ScannerDev sc, PulsesDev pulses, O
     const int S = sc.S;
     const int pl = lane / S, k = lane - pl * S;
     bool attrib = KIND == 0 || (out.sub_tri && out.sub_range && out.sub_power);
-    if (attrib) {
-        int tri = -1;
-        double R = INFINITY;
-        float P = 0.0f;
-        if (pl < npw) {
-            long long o = (first + p0 + pl) * out.sub_stride + k;
-            tri = out.sub_tri[o];
-            if (tri >= 0) {
-                R = out.sub_range[o];
-                P = out.sub_power[o];
-            }
+    int tri = -1;
+    double R = INFINITY;
+    float P = 0.0f;
+    if (attrib && pl < npw) {
+        long long o = (first + p0 + pl) * out.sub_stride + k;
+        tri = out.sub_tri[o];
+        if (tri >= 0) {
+            R = out.sub_range[o];
+            P = out.sub_power[o];
         }
-        wl->tau[lane] = tri >= 0 ? 2.0 * R / kCmPerNs : (double)INFINITY;
-        wl->pw[lane] = P;
-        wl->tri[lane] = tri;
-        wave_sync();
     }
+    const double tau = tri >= 0 ? 2.0 * R / kCmPerNs : (double)INFINITY;
     for (int q = 0; q < npw; ++q) {
-        if (KIND == 0) pulse_phase<MAXCH, true, false>(sc, pulses, out, first + p0 + q, q * S, wl, true);
-        else pulse_phase<MAXCH, false, true>(sc, pulses, out, first + p0 + q, q * S, wl, attrib);
+        if (KIND == 0) pulse_phase<MAXCH, true, false>(sc, pulses, out, first + p0 + q, q * S, wl, true, tau, P, tri);
+        else pulse_phase<MAXCH, false, true>(sc, pulses, out, first + p0 + q, q * S, wl, attrib, tau, P, tri);
     }
 }
 
@@ -507,7 +547,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     }
 }
 
-inline size_t sim_lds_bytes(int block, int ring) { return sizeof(WaveLds) * (block / kWave) + sizeof(int) * (size_t)ring * block; }
+inline size_t sim_lds_bytes(int block, int ring)
+{
+    return sizeof(WaveLds) * (block / kWave) + sizeof(int) * (size_t)ring * block;
+}
 
 }  // namespace
 

@@ -27,7 +27,7 @@ struct ScannerDev {
     float inv_tau;          // Eq. 3: 1 / tau
     float cut_lo;           // a subray contributes to bins with s in [-cut_lo, cut_hi] ns
     float cut_hi;
-    float pad_;
+    float inv_bin;          // 1 / bin_ns
     double t_pre;           // window starts t_pre before the first echo
     double s_peak;          // peak offset of the pulse shape (0 Gaussian, 2 tau Eq. 3)
     double power_c;         // peak * eff * D^2 / 4
