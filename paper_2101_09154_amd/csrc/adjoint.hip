@@ -82,11 +82,11 @@ __device__ __forceinline__ bool subray_grads(const SceneDev& scene, const Scanne
         float s = (xh - rh) + (xl - rl);
         float p, dp;
         if (sc.shape == 0) {
-            p = exp2f(s * s * sc.neg_k);
+            p = __builtin_amdgcn_exp2f(s * s * sc.neg_k);
             dp = -s * inv_s2 * p;
         } else {
             float x = s * sc.inv_tau;
-            float e = s > 0.0f ? exp2f(x * sc.neg_k) : 0.0f;
+            float e = s > 0.0f ? __builtin_amdgcn_exp2f(x * sc.neg_k) : 0.0f;
             p = x * x * e;
             dp = (2.0f * x - x * x) * e * sc.inv_tau;
         }

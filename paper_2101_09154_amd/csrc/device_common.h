@@ -133,13 +133,11 @@ __device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const fl
     int kz = 0;
     if (fabs(r.D[1]) > fabs(r.D[kz])) kz = 1;
     if (fabs(r.D[2]) > fabs(r.D[kz])) kz = 2;
+    // kx, ky follow kz cyclically.  The winding-preserving swap of kx and ky for a
+    // negative D[kz] is left out: the test is two-sided, and the swap would only
+    // negate U, V, W, det and T exactly, leaving every decision and t unchanged.
     int kx = kz == 2 ? 0 : kz + 1;
     int ky = kx == 2 ? 0 : kx + 1;
-    if (r.D[kz] < 0.0) {
-        int t = kx;
-        kx = ky;
-        ky = t;
-    }
     r.kx = kx;
     r.ky = ky;
     r.kz = kz;
@@ -159,14 +157,14 @@ __device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const fl
     return true;
 }
 
-__device__ __forceinline__ double pick(double x, double y, double z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
 
-// Outgoing pulse at offset s (ns): unit-peak Gaussian, or Eq. 3 (s/tau)^2 exp(-s/tau).
-// exp2 is the hardware instruction: results below 2^-126 flush to zero, far under
-// any bin that matters.
+// Outgoing pulse at offset s (ns): unit-peak Gaussian (SHAPE 0), or Eq. 3
+// (s/tau)^2 exp(-s/tau) (SHAPE 1).  exp2 is the hardware instruction: results
+// below 2^-126 flush to zero, far under any bin that matters.
+template <int SHAPE>
 __device__ __forceinline__ float pulse_shape(const ScannerDev& sc, float s)
 {
-    if (sc.shape == 0) return __builtin_amdgcn_exp2f(s * s * sc.neg_k);
+    if (SHAPE == 0) return __builtin_amdgcn_exp2f(s * s * sc.neg_k);
     float x = s * sc.inv_tau;
     return s > 0.0f ? x * x * __builtin_amdgcn_exp2f(x * sc.neg_k) : 0.0f;
 }

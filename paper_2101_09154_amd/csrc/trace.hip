@@ -74,17 +74,20 @@ struct Hit {
 // the ray runs along +kz; the 2-D edge functions U, V, W are then evaluated from
 // the same operands for both triangles of a shared edge, so no ray slips
 // between them.  t = T / det is formed only for candidates inside the triangle.
-__device__ __forceinline__ bool leaf_test_rec(const Ray& r, float4 Pa, float4 Pb, float4 Pc, Hit& h, float& tcull)
+__device__ __forceinline__ double comp(float4 v, int k) { return k == 0 ? (double)v.x : (k == 1 ? (double)v.y : (double)v.z); }
+
+// KZ: the ray's dominant axis; kx = KZ + 1, ky = KZ + 2 (mod 3) with static indices.
+template <int KZ>
+__device__ __forceinline__ bool leaf_test_kz(const Ray& r, float4 Pa, float4 Pb, float4 Pc, Hit& h, float& tcull)
 {
 #pragma clang fp contract(off)
+    constexpr int KX = KZ == 2 ? 0 : KZ + 1;
+    constexpr int KY = KX == 2 ? 0 : KX + 1;
     int orig = __float_as_int(Pa.w);
-    double a0 = (double)Pa.x - r.O[0], a1 = (double)Pa.y - r.O[1], a2 = (double)Pa.z - r.O[2];
-    double b0 = (double)Pb.x - r.O[0], b1 = (double)Pb.y - r.O[1], b2 = (double)Pb.z - r.O[2];
-    double c0 = (double)Pc.x - r.O[0], c1 = (double)Pc.y - r.O[1], c2 = (double)Pc.z - r.O[2];
-    double Az = pick(a0, a1, a2, r.kz), Bz = pick(b0, b1, b2, r.kz), Cz = pick(c0, c1, c2, r.kz);
-    double Ax = pick(a0, a1, a2, r.kx) - r.Sx * Az, Ay = pick(a0, a1, a2, r.ky) - r.Sy * Az;
-    double Bx = pick(b0, b1, b2, r.kx) - r.Sx * Bz, By = pick(b0, b1, b2, r.ky) - r.Sy * Bz;
-    double Cx = pick(c0, c1, c2, r.kx) - r.Sx * Cz, Cy = pick(c0, c1, c2, r.ky) - r.Sy * Cz;
+    double Az = comp(Pa, KZ) - r.O[KZ], Bz = comp(Pb, KZ) - r.O[KZ], Cz = comp(Pc, KZ) - r.O[KZ];
+    double Ax = (comp(Pa, KX) - r.O[KX]) - r.Sx * Az, Ay = (comp(Pa, KY) - r.O[KY]) - r.Sy * Az;
+    double Bx = (comp(Pb, KX) - r.O[KX]) - r.Sx * Bz, By = (comp(Pb, KY) - r.O[KY]) - r.Sy * Bz;
+    double Cx = (comp(Pc, KX) - r.O[KX]) - r.Sx * Cz, Cy = (comp(Pc, KY) - r.O[KY]) - r.Sy * Cz;
     double U = Cx * By - Cy * Bx;
     double V = Ax * Cy - Ay * Cx;
     double W = Bx * Ay - By * Ax;
@@ -103,6 +106,13 @@ __device__ __forceinline__ bool leaf_test_rec(const Ray& r, float4 Pa, float4 Pb
         return true;
     }
     return false;
+}
+
+__device__ __forceinline__ bool leaf_test_rec(const Ray& r, float4 Pa, float4 Pb, float4 Pc, Hit& h, float& tcull)
+{
+    if (r.kz == 2) return leaf_test_kz<2>(r, Pa, Pb, Pc, h, tcull);
+    if (r.kz == 1) return leaf_test_kz<1>(r, Pa, Pb, Pc, h, tcull);
+    return leaf_test_kz<0>(r, Pa, Pb, Pc, h, tcull);
 }
 
 __device__ __forceinline__ void leaf_test(const Ray& r, const float4* __restrict__ tris, int li, Hit& h, float& tcull)
@@ -256,7 +266,7 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
 // Each lane passes its own subray (tau = 2R/c, power, triangle; tri < 0: miss).
 // COMPUTE: synthesise wf from the subrays (else load wf and t0 from `out`).
 // RET: detect returns.  attrib: subray data present for return attribution.
-template <int MAXCH, bool COMPUTE, bool RET>
+template <int MAXCH, bool COMPUTE, bool RET, int SHAPE>
 __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
                                             long long p, int k0, WaveLds* wl, bool attrib, double my_tau,
                                             float my_pw, int my_tri)
@@ -299,7 +309,7 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
     if (have && (COMPUTE || attrib)) {
         int jl = 0x7fffffff, jh = -0x7fffffff;
         if (lane >= k0 && lane < k0 + S) {
-            float4 v = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));  // a miss
             if (mine) {
                 double rel = my_tau - t0;
                 float hi = (float)rel;
@@ -326,11 +336,13 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
                 float xh = (float)xd, xl = (float)(xd - (double)xh);
                 float acc = 0.0f, best = -1.0f;
                 int bki = -1;
+                // a missed subray carries power 0 and offset 0: it adds exactly 0
+                // and never becomes the strict maximum of a bin with a hit
+#pragma unroll 4
                 for (int kk = 0; kk < S; ++kk) {
                     const float4 u = wl->sub[k0 + kk];
-                    if (__float_as_int(u.w) < 0) continue;
                     float s = (xh - u.x) + (xl - u.y);
-                    float val = u.z * pulse_shape(sc, s);
+                    float val = u.z * pulse_shape<SHAPE>(sc, s);
                     acc += val;
                     if (val > best) {
                         best = val;
@@ -453,7 +465,13 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     }
     if (MODE == 0) return;
     const double tau = (active && tri >= 0) ? 2.0 * R / kCmPerNs : (double)INFINITY;
-    for (int q = 0; q < npw; ++q) pulse_phase<MAXCH, true, true>(sc, pulses, out, first + q, q * S, wl, true, tau, P, tri);
+    if (sc.shape == 0) {
+        for (int q = 0; q < npw; ++q)
+            pulse_phase<MAXCH, true, true, 0>(sc, pulses, out, first + q, q * S, wl, true, tau, P, tri);
+    } else {
+        for (int q = 0; q < npw; ++q)
+            pulse_phase<MAXCH, true, true, 1>(sc, pulses, out, first + q, q * S, wl, true, tau, P, tri);
+    }
 }
 
 template <int MAXCH, int MODE>
@@ -502,8 +520,14 @@ __global__ __launch_bounds__(256) void k_wave(ScannerDev sc, PulsesDev pulses, O
     }
     const double tau = tri >= 0 ? 2.0 * R / kCmPerNs : (double)INFINITY;
     for (int q = 0; q < npw; ++q) {
-        if (KIND == 0) pulse_phase<MAXCH, true, false>(sc, pulses, out, first + p0 + q, q * S, wl, true, tau, P, tri);
-        else pulse_phase<MAXCH, false, true>(sc, pulses, out, first + p0 + q, q * S, wl, attrib, tau, P, tri);
+        const long long p = first + p0 + q;
+        if (KIND == 0) {
+            if (sc.shape == 0) pulse_phase<MAXCH, true, false, 0>(sc, pulses, out, p, q * S, wl, true, tau, P, tri);
+            else pulse_phase<MAXCH, true, false, 1>(sc, pulses, out, p, q * S, wl, true, tau, P, tri);
+        } else {
+            if (sc.shape == 0) pulse_phase<MAXCH, false, true, 0>(sc, pulses, out, p, q * S, wl, attrib, tau, P, tri);
+            else pulse_phase<MAXCH, false, true, 1>(sc, pulses, out, p, q * S, wl, attrib, tau, P, tri);
+        }
     }
 }
 
