@@ -330,6 +330,14 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
                         const vls_pulse_batch* pulses, const vls_outputs* out, const char* cache_path, void* stream,
                         vls_tune_result* result);
 
+/* Diagnostic: runs only the cone pass (the per-pulse traversal that collects
+ * the triangles a pulse's subrays can hit) into `candidates`, a device array
+ * [n_pulses][16] int32: entry 0 is the count (-1 when more than 15 triangles
+ * were reached and the subrays traverse on their own), then the original
+ * triangle indices.  Asynchronous on `stream`. */
+vls_status vls_cone_candidates(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners,
+                               int32_t n_scanners, const vls_pulse_batch* pulses, int32_t* candidates, void* stream);
+
 /* Synchronise `stream` and report any device error as VLS_ERR_DEVICE. */
 vls_status vls_synchronize(vls_context ctx, void* stream);
 

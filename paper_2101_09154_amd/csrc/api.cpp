@@ -1057,6 +1057,30 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
     }
 }
 
+vls_status vls_cone_candidates(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners,
+                               int32_t n_scanners, const vls_pulse_batch* pulses, int32_t* candidates, void* stream)
+{
+    try {
+        Prepared pr;
+        vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
+        if (st != VLS_OK) return st;
+        if ((st = check_scene(ctx, scene)) != VLS_OK) return st;
+        if (pulses->n_pulses > 0 && !candidates) return fail(VLS_ERR_INVALID_ARG, "candidates is NULL");
+        if (!aligned(candidates, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned candidates");
+        hipStream_t s = (hipStream_t)stream;
+        hipError_t e = launch_cone(scene_dev(scene), max_tan(pr), pulses_dev(pulses), candidates, 0, pulses->n_pulses,
+                                   ctx->cfg, nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "cone launch");
+        if (pulses->n_pulses > 0) {
+            e = launch_leaf_to_orig(scene->b.leaf_tri, candidates, pulses->n_pulses, s);
+            if (e != hipSuccess) return hip_fail(e, "candidate ids");
+        }
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
 vls_status vls_synchronize(vls_context ctx, void* stream)
 {
     if (!ctx) return fail(VLS_ERR_INVALID_ARG, "context is NULL");

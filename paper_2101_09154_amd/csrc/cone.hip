@@ -233,7 +233,24 @@ __global__ __launch_bounds__(256) void k_cone(SceneDev scene, double tana, Pulse
     }
 }
 
+__global__ __launch_bounds__(256) void k_leaf_to_orig(const int32_t* __restrict__ leaf_tri, int* __restrict__ cand,
+                                                      long long n)
+{
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int* c = cand + p * (kCandMax + 1);
+    int cnt = c[0];
+    for (int i = 0; i < cnt && i < kCandMax; ++i) c[1 + i] = leaf_tri[c[1 + i]];
+}
+
 }  // namespace
+
+hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_pulses, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_leaf_to_orig, dim3((unsigned)((n_pulses + 255) / 256)), dim3(256), 0, stream, leaf_tri, cand,
+                       n_pulses);
+    return hipGetLastError();
+}
 
 hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
                        long long count, const LaunchCfg& cfg, unsigned long long* counts, hipStream_t stream)

@@ -135,6 +135,8 @@ hipError_t launch_backward(const SceneDev& scene, const ScannerDev& sc, const Pu
 // accumulates node visits into counts[1].
 hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
                        long long count, const LaunchCfg& cfg, unsigned long long* counts, hipStream_t stream);
+// Candidate lists hold leaf indices; rewrite them as original triangle indices.
+hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_pulses, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);
 int persistent_occupancy_blocks(int max_bins, const LaunchCfg& cfg);
 

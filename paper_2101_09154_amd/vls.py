@@ -100,6 +100,7 @@ _SIGS = {
     "vls_trace_counts": ([P, P, P, i32, P, P, P], i32),
     "vls_waveform_backward": ([P, P, P, P, P, P, P, P, P], i32),
     "vls_graph_capture": ([P, P, P, i32, P, P, P], i32),
+    "vls_cone_candidates": ([P, P, P, i32, P, P, P], i32),
     "vls_graph_launch": ([P, P], i32),
     "vls_graph_destroy": ([P], i32),
     "vls_autotune": ([P, P, P, i32, P, P, ctypes.c_char_p, P, P], i32),
@@ -421,6 +422,17 @@ class Context:
                          "cone": r.best.cone},
                 "best_ms": r.best_ms, "default_ms": r.default_ms, "n_tried": r.n_tried,
                 "from_cache": bool(r.from_cache)}
+
+    def cone_candidates(self, scene, scanners, origins, directions, *, out=None, segment_offsets=None,
+                        segment_scanner=None, stream=None):
+        """[n, 16] int32: candidate count (-1 = overflow) then original triangle ids, per pulse."""
+        n = origins.shape[0]
+        if out is None:
+            out = torch.empty((n, 16), dtype=torch.int32, device=origins.device)
+        arr, ns = self._scanners(scanners)
+        b, keep = self._batch(origins, directions, None, segment_offsets, segment_scanner)
+        _check(lib().vls_cone_candidates(self._h, scene._h, arr, ns, ctypes.byref(b), _ptr(out), _stream(stream)))
+        return out
 
     def trace_counts(self, scene, scanners, origins, directions, *, segment_offsets=None, segment_scanner=None,
                      stream=None):

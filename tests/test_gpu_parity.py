@@ -599,3 +599,26 @@ def test_cone_pass_bitwise_on_buildings(ctx):
                 continue
             assert np.array_equal(a, b, equal_nan=True), k
     ctx.set_launch_config()
+
+
+def test_cone_candidates_contain_every_hit(ctx):
+    # the candidate list of a pulse holds the closest-hit triangle of every one
+    # of its subrays (found here by per-subray traversal), unless it overflowed
+    mesh = configs.als_scene()
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    _, als, sc = configs.als_buildings(mesh=mesh, n_lines=30, per_line=1000)
+    _, tls, scs = configs.batched_tls(mesh=mesh, n_positions=3, count_range=(3000, 5000))
+    for pulses, scn in ((als, sc), (tls.subset(np.arange(tls.segment_offsets[1])), scs[0])):
+        o = _dev(pulses.origins)
+        d = _dev(pulses.directions)
+        cand = ctx.cone_candidates(scene, scn, o, d).cpu().numpy()
+        ctx.set_launch_config(cone=0)
+        hits = ctx.trace(scene, scn, o, d)["subray_tri"].cpu().numpy()
+        ctx.set_launch_config()
+        ok = cand[:, 0] >= 0
+        say("cone candidates: %d pulses, %.4f listed, mean %.2f candidates" %
+            (pulses.n, ok.mean(), cand[ok, 0].mean()))
+        for q in np.nonzero(ok)[0]:
+            listed = set(cand[q, 1:1 + cand[q, 0]])
+            for t in hits[q]:
+                assert t < 0 or t in listed, (q, t, listed)
