@@ -71,13 +71,13 @@ __device__ __forceinline__ bool subray_grads(const SceneDev& scene, const Scanne
     double tau = 2.0 * R / kCmPerNs;
     double rel = tau - t0;
     // bins inside the pulse support around this echo
-    double lo = ceil((rel - sc.cut_lo) / sc.bin_ns), hi = floor((rel + sc.cut_hi) / sc.bin_ns);
+    double lo = ceil((rel - sc.cut_lo) / sc.bin_d), hi = floor((rel + sc.cut_hi) / sc.bin_d);
     int jl = (int)fmax(lo, 0.0), jh = (int)fmin(hi, (double)(sc.n_bins - 1));
     float rh = (float)rel, rl = (float)(rel - (double)rh);
     float gP = 0.0f, gD = 0.0f;
     const float inv_s2 = -2.0f * sc.neg_k * 0.6931471805599453f;  // 1 / sigma^2 for the Gaussian
     for (int j = jl; j <= jh; ++j) {
-        double xd = (double)j * sc.bin_ns;
+        double xd = (double)j * sc.bin_d;
         float xh = (float)xd, xl = (float)(xd - (double)xh);
         float s = (xh - rh) + (xl - rl);
         float p, dp;

@@ -228,22 +228,25 @@ vls_status scanner_dev(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s
     s.K = d.max_returns;
     s.shape = d.pulse_shape;
     s.bin_ns = (float)d.bin_ns;
+    s.bin_d = d.bin_ns;
     s.inv_bin = (float)(1.0 / d.bin_ns);
     const double log2e = 1.4426950408889634;
     if (d.pulse_shape == VLS_PULSE_GAUSSIAN) {
         double sg = d.pulse_width_ns / (2.0 * std::sqrt(2.0 * std::log(2.0)));
         s.neg_k = (float)(-log2e / (2.0 * sg * sg));
         s.inv_tau = 0.0f;
-        s.cut_lo = (float)(8.0 * sg);
-        s.cut_hi = (float)(8.0 * sg);
+        // beyond 6.5 sigma the pulse is below 1e-9 of its peak
+        s.cut_lo = (float)(6.5 * sg);
+        s.cut_hi = (float)(6.5 * sg);
         s.t_pre = d.window_pre_ns < 0.0 ? 6.0 * sg : d.window_pre_ns;
         s.s_peak = 0.0;
     } else {
         double tau = d.pulse_width_ns / 1.75;
         s.neg_k = (float)(-log2e);
         s.inv_tau = (float)(1.0 / tau);
+        // beyond 29 tau, (s/tau)^2 exp(-s/tau) is below 1e-9 of its peak 4 exp(-2)
         s.cut_lo = 0.0f;
-        s.cut_hi = (float)(40.0 * tau);
+        s.cut_hi = (float)(29.0 * tau);
         s.t_pre = d.window_pre_ns < 0.0 ? 0.0 : d.window_pre_ns;
         s.s_peak = 2.0 * tau;
     }

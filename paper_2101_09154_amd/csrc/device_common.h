@@ -131,19 +131,26 @@ __device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const fl
     }
     if (!(omax < INFINITY)) return false;
     int kz = 0;
-    if (fabs(r.D[1]) > fabs(r.D[kz])) kz = 1;
-    if (fabs(r.D[2]) > fabs(r.D[kz])) kz = 2;
+    double dmax = fabs(r.D[0]);
+    if (fabs(r.D[1]) > dmax) {
+        kz = 1;
+        dmax = fabs(r.D[1]);
+    }
+    if (fabs(r.D[2]) > dmax) kz = 2;
     // kx, ky follow kz cyclically.  The winding-preserving swap of kx and ky for a
     // negative D[kz] is left out: the test is two-sided, and the swap would only
     // negate U, V, W, det and T exactly, leaving every decision and t unchanged.
-    int kx = kz == 2 ? 0 : kz + 1;
-    int ky = kx == 2 ? 0 : kx + 1;
-    r.kx = kx;
-    r.ky = ky;
+    // components picked by selects, not by a run-time array index (which would
+    // place the array in scratch memory)
+    const double az = kz == 0 ? r.D[0] : (kz == 1 ? r.D[1] : r.D[2]);
+    const double ax = kz == 0 ? r.D[1] : (kz == 1 ? r.D[2] : r.D[0]);
+    const double ay = kz == 0 ? r.D[2] : (kz == 1 ? r.D[0] : r.D[1]);
+    r.kx = kz == 2 ? 0 : kz + 1;
+    r.ky = kz == 0 ? 2 : kz - 1;
     r.kz = kz;
-    r.Sx = r.D[kx] / r.D[kz];
-    r.Sy = r.D[ky] / r.D[kz];
-    r.Sz = 1.0 / r.D[kz];
+    r.Sx = ax / az;
+    r.Sy = ay / az;
+    r.Sz = 1.0 / az;
     // pad covers the FP32 rounding of origin, direction and slab arithmetic
     double pad = (omax + (double)scene_mag + 1.0) * 1.9073486328125e-06;  // 2^-19
     for (int i = 0; i < 3; ++i) {

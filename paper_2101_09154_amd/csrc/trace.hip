@@ -262,10 +262,32 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
     P = (float)pw;
 }
 
+// Contribution of one echo to a bin: offsets are taken from the centre bin jc of
+// the bin's chunk, so x = (l - 32) bin (lane l) and the echo offset
+// r = (tau - t0) - jc bin (FP64, split into FP32 hi + lo) are both small, and
+// s = (x - hi) - lo keeps FP64 accuracy in FP32 arithmetic.
+__device__ __forceinline__ void echo_offset(const ScannerDev& sc, double rel, int jc, float& hi, float& lo)
+{
+    const double r = rel - (double)jc * sc.bin_d;
+    hi = (float)r;
+    lo = (float)(r - (double)hi);
+}
+
+template <int SHAPE>
+__device__ __forceinline__ float echo_value(const ScannerDev& sc, float x, float hi, float lo, float pw)
+{
+    return pw * pulse_shape<SHAPE>(sc, (x - hi) - lo);
+}
+
 // Waveform and/or returns of one pulse whose subrays are lanes [k0, k0 + S).
 // Each lane passes its own subray (tau = 2R/c, power, triangle; tri < 0: miss).
 // COMPUTE: synthesise wf from the subrays (else load wf and t0 from `out`).
 // RET: detect returns.  attrib: subray data present for return attribution.
+//
+// A synthesised waveform is non-zero only on the support [jl, jh] of its echoes,
+// so it is computed as nch chunks of 64 bins starting at jb = jl (lane l of chunk
+// c owns bin jb + 64 c + l); a loaded one as the aligned chunks of the whole row.
+// Bins outside the chunks are zero.
 template <int MAXCH, bool COMPUTE, bool RET, int SHAPE>
 __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
                                             long long p, int k0, WaveLds* wl, bool attrib, double my_tau,
@@ -273,7 +295,8 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int S = sc.S, nb = sc.n_bins, K = sc.K;
-    const bool mine = lane >= k0 && lane < k0 + S && my_tri >= 0;
+    const bool sub_lane = lane >= k0 && lane < k0 + S;
+    const bool mine = sub_lane && my_tri >= 0;
     double t0;
     bool any;
     if (COMPUTE || attrib) {
@@ -289,111 +312,123 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
         t0 = out.t0[p];
         any = true;
     }
-    bool have = any && !isnan(t0);
-    float wf[MAXCH];
-    int bk[MAXCH];
-#pragma unroll
-    for (int c = 0; c < MAXCH; ++c) {
-        wf[c] = 0.0f;
-        bk[c] = -1;
-    }
+    const bool have = any && !isnan(t0);
+    const double rel = my_tau - t0;  // used on `mine` lanes only
+    const float x = (float)((double)(lane - 32) * sc.bin_d);
+    int jb = 0, nch = 0;
     if (!COMPUTE) {
+        nch = (nb + kWave - 1) / kWave;
+    } else if (have) {
+        // support of the echoes in bins, widened by one bin against rounding
+        int jl = 0x7fffffff, jh = -0x7fffffff;
+        if (mine) {
+            float hi = (float)rel;
+            jl = (int)fmaxf(floorf((hi - sc.cut_lo) * sc.inv_bin) - 1.0f, -1e9f);
+            jh = (int)fminf(ceilf((hi + sc.cut_hi) * sc.inv_bin) + 1.0f, 1e9f);
+        }
+        jl = max(wave_min_i(jl), 0);
+        jh = min(wave_max_i(jh), nb - 1);
+        if (jl <= jh) {
+            jb = jl;
+            nch = ((jh - jl) >> 6) + 1;
+        }
+    }
+    float wf[MAXCH];
+#pragma unroll
+    for (int c = 0; c < MAXCH; ++c) wf[c] = 0.0f;
+    if (COMPUTE) {
+#pragma unroll
+        for (int c = 0; c < MAXCH; ++c) {
+            if (c >= nch) continue;
+            if (sub_lane) {
+                // a missed subray carries power 0 and offset 0: it adds exactly 0
+                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (mine) {
+                    echo_offset(sc, rel, jb + c * kWave + 32, v.x, v.y);
+                    v.z = my_pw;
+                }
+                wl->sub[lane] = v;
+            }
+            wave_sync();
+            float acc = 0.0f;
+#pragma unroll 4
+            for (int kk = 0; kk < S; ++kk) {
+                const float4 u = wl->sub[k0 + kk];
+                acc = fmaf(u.z, pulse_shape<SHAPE>(sc, (x - u.x) - u.y), acc);
+            }
+            wf[c] = jb + c * kWave + lane < nb ? acc : 0.0f;
+            wave_sync();
+        }
+        if (out.wf) {
+            float* row = out.wf + p * nb;
+            const int jend = jb + nch * kWave;
+#pragma unroll
+            for (int m = 0; m < MAXCH; ++m) {
+                const int j = m * kWave + lane;
+                if (j < nb && (j < jb || j >= jend)) row[j] = 0.0f;
+            }
+#pragma unroll
+            for (int c = 0; c < MAXCH; ++c) {
+                const int j = jb + c * kWave + lane;
+                if (c < nch && j < nb) row[j] = wf[c];
+            }
+        }
+        if (lane == 0 && out.t0) out.t0[p] = t0;
+    } else {
 #pragma unroll
         for (int c = 0; c < MAXCH; ++c) {
             int j = c * kWave + lane;
             if (j < nb) wf[c] = out.wf[p * nb + j];
         }
     }
-    // chunks of 64 bins that can hold a non-zero value (all of them for a loaded waveform)
-    int c_lo = 0, c_hi = MAXCH - 1;
-    if (have && (COMPUTE || attrib)) {
-        int jl = 0x7fffffff, jh = -0x7fffffff;
-        if (lane >= k0 && lane < k0 + S) {
-            float4 v = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));  // a miss
-            if (mine) {
-                double rel = my_tau - t0;
-                float hi = (float)rel;
-                v = make_float4(hi, (float)(rel - (double)hi), my_pw, __int_as_float(my_tri));
-                // support of this echo in bins, widened by one bin against rounding
-                jl = (int)fmaxf(floorf((hi - sc.cut_lo) * sc.inv_bin) - 1.0f, -1e9f);
-                jh = (int)fminf(ceilf((hi + sc.cut_hi) * sc.inv_bin) + 1.0f, 1e9f);
-            }
-            wl->sub[lane] = v;
-        }
-        wave_sync();
-        jl = max(wave_min_i(jl), 0);
-        jh = min(wave_max_i(jh), nb - 1);
-        if (COMPUTE) {
-            c_lo = jl >> 6;
-            c_hi = jl <= jh ? jh >> 6 : -1;
-        }
-#pragma unroll
-        for (int c = 0; c < MAXCH; ++c) {
-            const int cb = c * kWave;
-            if (cb < nb && cb <= jh && cb + kWave - 1 >= jl) {
-                int j = cb + lane;
-                double xd = (double)j * sc.bin_ns;
-                float xh = (float)xd, xl = (float)(xd - (double)xh);
-                float acc = 0.0f, best = -1.0f;
-                int bki = -1;
-                // a missed subray carries power 0 and offset 0: it adds exactly 0
-                // and never becomes the strict maximum of a bin with a hit
-#pragma unroll 4
-                for (int kk = 0; kk < S; ++kk) {
-                    const float4 u = wl->sub[k0 + kk];
-                    float s = (xh - u.x) + (xl - u.y);
-                    float val = u.z * pulse_shape<SHAPE>(sc, s);
-                    acc += val;
-                    if (val > best) {
-                        best = val;
-                        bki = kk;
-                    }
-                }
-                if (COMPUTE && j < nb) wf[c] = acc;
-                bk[c] = bki;
-            }
-        }
-    }
-    if (COMPUTE) {
-        if (out.wf) {
-#pragma unroll
-            for (int c = 0; c < MAXCH; ++c) {
-                int j = c * kWave + lane;
-                if (j < nb) out.wf[p * nb + j] = wf[c];
-            }
-        }
-        if (lane == 0 && out.t0) out.t0[p] = t0;
-    }
     if (!RET) return;
     int count = 0;
-    if (have) {
+    if (have && nch > 0) {
         float m = 0.0f;
 #pragma unroll
         for (int c = 0; c < MAXCH; ++c)
-            if (c >= c_lo && c <= c_hi) m = fmaxf(m, wf[c]);
+            if (c < nch) m = fmaxf(m, wf[c]);
         m = wave_max_f(m);
         float thr = fmaxf((float)sc.thr_abs, (float)(sc.thr_rel * (double)m));
 #pragma unroll
         for (int c = 0; c < MAXCH; ++c) {
-            if (c * kWave >= nb) break;
-            if (c < c_lo || c > c_hi) continue;  // all zero: no return can start here
+            if (c >= nch || count >= K) continue;
             float v = wf[c];
-            // neighbours: lane shifts, with the adjacent chunk's edge lane at the ends
+            // neighbours: lane shifts, with the adjacent chunk's edge lane at the
+            // chunk ends; beyond the first and last chunk the waveform is zero
             float prev = c > 0 ? lane_read_f(wf[c > 0 ? c - 1 : 0], 63) : 0.0f;
-            float next = c + 1 < MAXCH ? lane_read_f(wf[c + 1 < MAXCH ? c + 1 : c], 0) : 0.0f;
+            float next = c + 1 < MAXCH && c + 1 < nch ? lane_read_f(wf[c + 1 < MAXCH ? c + 1 : c], 0) : 0.0f;
             float left = lane_prev_f(v, prev);
             float right = lane_next_f(v, next);
-            int j = c * kWave + lane;
+            const int j = jb + c * kWave + lane;
             bool cand = j >= 1 && j <= nb - 2 && v > left && v >= right && v >= thr;
             unsigned long long mk = __ballot(cand);
+            int rt = -1;
+            if (attrib && out.ret_tri) {
+                // each kept return goes to the subray contributing most at its bin
+                // (lowest subray index on ties); subray lanes evaluate their own echo
+                float hi = 0.0f, lo = 0.0f;
+                if (mine) echo_offset(sc, rel, jb + c * kWave + 32, hi, lo);
+                unsigned long long todo = mk;
+                for (int s = count; todo && s < K; ++s) {
+                    const int b = __ffsll((long long)todo) - 1;
+                    todo &= todo - 1;
+                    const float xb = (float)((double)(b - 32) * sc.bin_d);
+                    const float val = mine ? echo_value<SHAPE>(sc, xb, hi, lo, my_pw) : -1.0f;
+                    const float best = wave_max_f(val);
+                    const unsigned long long w = __ballot(mine && val == best);
+                    int t = -1;
+                    if (w) t = __builtin_amdgcn_readlane(my_tri, __ffsll((long long)w) - 1);
+                    if (lane == b) rt = t;
+                }
+            }
             int slot = count + (int)lanes_below(mk);
             if (cand && slot < K) {
                 long long o = p * K + slot;
-                out.ret_range[o] = (float)(0.5 * kCmPerNs * (t0 + (double)j * sc.bin_ns - sc.s_peak));
+                out.ret_range[o] = (float)(0.5 * kCmPerNs * (t0 + (double)j * sc.bin_d - sc.s_peak));
                 out.ret_amp[o] = v;
                 out.ret_bin[o] = j;
-                if (out.ret_tri)
-                    out.ret_tri[o] = (attrib && bk[c] >= 0) ? __float_as_int(wl->sub[k0 + bk[c]].w) : -1;
+                if (out.ret_tri) out.ret_tri[o] = rt;
             }
             count += __popcll(mk);
         }

@@ -23,6 +23,7 @@ struct ScannerDev {
     int K;
     int shape;              // 0 Gaussian, 1 Eq. 3
     float bin_ns;
+    double bin_d;           // bin width in FP64 (bin times t0 + j bin)
     float neg_k;            // Gaussian: -log2(e) / (2 sigma^2); Eq. 3: -log2(e)
     float inv_tau;          // Eq. 3: 1 / tau
     float cut_lo;           // a subray contributes to bins with s in [-cut_lo, cut_hi] ns
