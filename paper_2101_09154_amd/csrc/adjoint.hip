@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_backward(SceneDev scene, ScannerDev sc,
         if (t >= 0 && t < scene.n_tri && !isnan(t0)) {
             Ray r;
             const double* pat = sc.pattern + 5 * k;
-            if (setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, pat, 0.0f, r) &&
+            if (setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, pat, r) &&
                 subray_grads(scene, sc, r, t, pat[4], t0, grad_wf + p * sc.n_bins, g))
                 tri = t;
         }

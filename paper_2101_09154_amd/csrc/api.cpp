@@ -280,6 +280,16 @@ struct Prepared {
     std::vector<int32_t> seg_sc;
 };
 
+// Largest pulses-per-wavefront among the scanners whose candidates are staged in
+// LDS (those with at most 4 pulses per wavefront), or 0.
+int staged_pw(const Prepared& pr)
+{
+    int m = 0;
+    for (const auto& s : pr.sc)
+        if (s.P_w <= 4) m = std::max(m, s.P_w);
+    return m;
+}
+
 vls_status prepare(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners, const vls_pulse_batch* pulses,
                    Prepared& pr)
 {
@@ -760,7 +770,7 @@ static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_s
     if (pulses->n_pulses > 0 && pulses->n_segments > 0) {
         if ((st = batch_tables(ctx, pr, bt)) != VLS_OK) return st;
         blocks = ctx->cfg.persistent_blocks > 0 ? ctx->cfg.persistent_blocks
-                                                : persistent_occupancy_blocks(pr.n_bins, ctx->cfg);
+                                                : persistent_occupancy_blocks(pr.n_bins, staged_pw(pr), ctx->cfg);
     }
     return VLS_OK;
 }
@@ -781,7 +791,7 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
         pd.cand = cand;
     }
     if (!bt) e = launch_simulate(sd, pr.sc[0], pd, od, 0, pulses->n_pulses, 1, ctx->cfg, s);
-    else e = launch_persistent(sd, bt->bd, pr.n_bins, pd, od, ctx->cfg, blocks, s);
+    else e = launch_persistent(sd, bt->bd, pr.n_bins, staged_pw(pr), pd, od, ctx->cfg, blocks, s);
     return e == hipSuccess ? VLS_OK : hip_fail(e, "simulate launch");
 }
 
@@ -1011,7 +1021,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
         } else {
             int tried = 1;
             const bool seg = pulses->n_segments > 0;
-            int auto_blocks = seg ? persistent_occupancy_blocks(pr0.n_bins, entry) : 0;
+            int auto_blocks = seg ? persistent_occupancy_blocks(pr0.n_bins, staged_pw(pr0), entry) : 0;
             for (int dim = 0; dim < 5; ++dim) {
                 std::vector<LaunchCfg> cand;
                 for (int v = 0; v < 4; ++v) {

@@ -100,17 +100,23 @@ struct Ray {
     double O[3];
     double D[3];
     double Sx, Sy, Sz;  // shear of the watertight test: the ray runs along +kz
-    int kx, ky, kz;
+    int kz;
+    float d32[3];       // direction rounded to FP32 (shading)
+};
+
+// FP32 slab constants of the box test, padded outward against the rounding of
+// the FP32 ray.
+struct RayBox {
     float inv[3];
     float oim[3];  // (O + pad) * inv : lower planes moved outward
     float oip[3];  // (O - pad) * inv : upper planes moved outward
 };
 
-// Duff et al. 2017 orthonormal basis; FP64 subray direction; FP32 slab constants.
+// Duff et al. 2017 orthonormal basis; FP64 subray direction and shear.
 // FP contraction is off wherever FP64 results decide a hit, so every product
 // and sum is rounded exactly as written.
 __device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const float* __restrict__ d32,
-                                          const double* __restrict__ pat, float scene_mag, Ray& r)
+                                          const double* __restrict__ pat, Ray& r)
 {
 #pragma clang fp contract(off)
     double dx = d32[0], dy = d32[1], dz = d32[2];
@@ -127,6 +133,7 @@ __device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const fl
     for (int i = 0; i < 3; ++i) {
         r.D[i] = ca * n[i] + sa * (cp * u[i] + sp * v[i]);
         r.O[i] = o[i];
+        r.d32[i] = (float)r.D[i];
         omax = fmax(omax, fabs(o[i]));
     }
     if (!(omax < INFINITY)) return false;
@@ -140,30 +147,32 @@ __device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const fl
     // kx, ky follow kz cyclically.  The winding-preserving swap of kx and ky for a
     // negative D[kz] is left out: the test is two-sided, and the swap would only
     // negate U, V, W, det and T exactly, leaving every decision and t unchanged.
-    // components picked by selects, not by a run-time array index (which would
-    // place the array in scratch memory)
+    // Components are picked by selects, not by a run-time array index (which
+    // would place the array in scratch memory).
     const double az = kz == 0 ? r.D[0] : (kz == 1 ? r.D[1] : r.D[2]);
     const double ax = kz == 0 ? r.D[1] : (kz == 1 ? r.D[2] : r.D[0]);
     const double ay = kz == 0 ? r.D[2] : (kz == 1 ? r.D[0] : r.D[1]);
-    r.kx = kz == 2 ? 0 : kz + 1;
-    r.ky = kz == 0 ? 2 : kz - 1;
     r.kz = kz;
     r.Sx = ax / az;
     r.Sy = ay / az;
     r.Sz = 1.0 / az;
-    // pad covers the FP32 rounding of origin, direction and slab arithmetic
-    double pad = (omax + (double)scene_mag + 1.0) * 1.9073486328125e-06;  // 2^-19
-    for (int i = 0; i < 3; ++i) {
-        float di = (float)r.D[i];
-        if (fabsf(di) < 1e-30f) di = copysignf(1e-30f, di);
-        float inv = 1.0f / di;
-        r.inv[i] = inv;
-        r.oim[i] = (float)(r.O[i] + pad) * inv;
-        r.oip[i] = (float)(r.O[i] - pad) * inv;
-    }
     return true;
 }
 
+// pad covers the FP32 rounding of origin, direction and slab arithmetic
+__device__ __forceinline__ void setup_box(const Ray& r, float scene_mag, RayBox& b)
+{
+    double omax = fmax(fmax(fabs(r.O[0]), fabs(r.O[1])), fabs(r.O[2]));
+    double pad = (omax + (double)scene_mag + 1.0) * 1.9073486328125e-06;  // 2^-19
+    for (int i = 0; i < 3; ++i) {
+        float di = r.d32[i];
+        if (fabsf(di) < 1e-30f) di = copysignf(1e-30f, di);
+        float inv = 1.0f / di;
+        b.inv[i] = inv;
+        b.oim[i] = (float)(r.O[i] + pad) * inv;
+        b.oip[i] = (float)(r.O[i] - pad) * inv;
+    }
+}
 
 // Outgoing pulse at offset s (ns): unit-peak Gaussian (SHAPE 0), or Eq. 3
 // (s/tau)^2 exp(-s/tau) (SHAPE 1).  exp2 is the hardware instruction: results

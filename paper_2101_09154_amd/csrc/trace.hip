@@ -44,14 +44,24 @@ namespace {
 
 using namespace dev;
 
-// Per-wavefront LDS: the subrays' waveform inputs, and the candidate triangles of
-// the wavefront's pulses staged by one parallel load (slot = pulse * 16 + candidate).
-struct WaveLds {
-    float4 sub[kWave];   // (offset hi, offset lo, power, triangle as int bits) per subray lane
-    float4 rec[3][kWave];
+// A candidate triangle staged for the subrays of one pulse: its vertices
+// translated to the pulse origin in FP64 (the first step of the watertight test,
+// shared by all subrays of the pulse), its original index and its leaf.
+struct CandRec {
+    double a[3], b[3], c[3];
+    int orig;
+    int leaf;
 };
 
-__device__ __forceinline__ bool box_hit(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz,
+// Per-wavefront LDS, used in turn by the two phases: the staged candidates of the
+// wavefront's pulses (slot = pulse * 16 + candidate) while tracing, then the
+// subrays' waveform inputs (offset hi, offset lo, power, unused) per lane.
+__host__ __device__ constexpr int wave_lds_bytes(int staged_pw)
+{
+    return staged_pw * 16 * (int)sizeof(CandRec) > kWave * 16 ? staged_pw * 16 * (int)sizeof(CandRec) : kWave * 16;
+}
+
+__device__ __forceinline__ bool box_hit(const RayBox& r, float lx, float ly, float lz, float hx, float hy, float hz,
                                         float tcull, float& tn)
 {
     float ax = fmaf(lx, r.inv[0], -r.oim[0]), bx = fmaf(hx, r.inv[0], -r.oip[0]);
@@ -70,54 +80,79 @@ struct Hit {
 };
 
 // Watertight ray/triangle test (Woop, Benthin & Wald 2013) in FP64, two-sided,
-// inclusive edges: the triangle is translated to the ray origin and sheared so
-// the ray runs along +kz; the 2-D edge functions U, V, W are then evaluated from
-// the same operands for both triangles of a shared edge, so no ray slips
-// between them.  t = T / det is formed only for candidates inside the triangle.
-__device__ __forceinline__ double comp(float4 v, int k) { return k == 0 ? (double)v.x : (k == 1 ? (double)v.y : (double)v.z); }
-
-// KZ: the ray's dominant axis; kx = KZ + 1, ky = KZ + 2 (mod 3) with static indices.
+// inclusive edges, on vertices already translated to the ray origin: the
+// triangle is sheared so the ray runs along +kz; the 2-D edge functions U, V, W
+// are then evaluated from the same operands for both triangles of a shared edge,
+// so no ray slips between them.  Returns t = T / det for a hit with t > 0, else
+// a value that is not > 0 (NaN or <= 0).
 template <int KZ>
-__device__ __forceinline__ bool leaf_test_kz(const Ray& r, float4 Pa, float4 Pb, float4 Pc, Hit& h, float& tcull)
+__device__ __forceinline__ double woop_t(const Ray& r, const double* a, const double* b, const double* c)
 {
 #pragma clang fp contract(off)
     constexpr int KX = KZ == 2 ? 0 : KZ + 1;
     constexpr int KY = KX == 2 ? 0 : KX + 1;
-    int orig = __float_as_int(Pa.w);
-    double Az = comp(Pa, KZ) - r.O[KZ], Bz = comp(Pb, KZ) - r.O[KZ], Cz = comp(Pc, KZ) - r.O[KZ];
-    double Ax = (comp(Pa, KX) - r.O[KX]) - r.Sx * Az, Ay = (comp(Pa, KY) - r.O[KY]) - r.Sy * Az;
-    double Bx = (comp(Pb, KX) - r.O[KX]) - r.Sx * Bz, By = (comp(Pb, KY) - r.O[KY]) - r.Sy * Bz;
-    double Cx = (comp(Pc, KX) - r.O[KX]) - r.Sx * Cz, Cy = (comp(Pc, KY) - r.O[KY]) - r.Sy * Cz;
-    double U = Cx * By - Cy * Bx;
-    double V = Ax * Cy - Ay * Cx;
-    double W = Bx * Ay - By * Ax;
-    if ((U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0)) return false;
-    double det = U + V + W;
-    if (det == 0.0) return false;
-    double T = U * (r.Sz * Az) + V * (r.Sz * Bz) + W * (r.Sz * Cz);
-    double t = T / det;
-    if (!(t > 0.0)) return false;
-    if (t < h.t || (t == h.t && orig < h.orig)) {
-        h.t = t;
-        h.orig = orig;
-        float tf = (float)t;
-        if ((double)tf < t) tf = nextafterf(tf, INFINITY);
-        tcull = tf;
-        return true;
+    const double Az = a[KZ], Bz = b[KZ], Cz = c[KZ];
+    const double Ax = a[KX] - r.Sx * Az, Ay = a[KY] - r.Sy * Az;
+    const double Bx = b[KX] - r.Sx * Bz, By = b[KY] - r.Sy * Bz;
+    const double Cx = c[KX] - r.Sx * Cz, Cy = c[KY] - r.Sy * Cz;
+    const double U = Cx * By - Cy * Bx;
+    const double V = Ax * Cy - Ay * Cx;
+    const double W = Bx * Ay - By * Ax;
+    const bool out = (U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0);
+    const double det = U + V + W;
+    const double T = U * (r.Sz * Az) + V * (r.Sz * Bz) + W * (r.Sz * Cz);
+    const double t = T / det;
+    return (out || det == 0.0) ? -1.0 : t;
+}
+
+// Closest-hit update: smaller t wins, equal t goes to the lower original index.
+__device__ __forceinline__ bool closer(double t, int orig, const Hit& h)
+{
+    return t > 0.0 && (t < h.t || (t == h.t && orig < h.orig));
+}
+
+__device__ __forceinline__ void translate(const Ray& r, float4 P, double* v)
+{
+    v[0] = (double)P.x - r.O[0];
+    v[1] = (double)P.y - r.O[1];
+    v[2] = (double)P.z - r.O[2];
+}
+
+// Test of a triangle read from the leaf records (global memory); sets h.leaf.
+__device__ __forceinline__ bool leaf_test(const Ray& r, const float4* __restrict__ tris, int li, Hit& h)
+{
+    const float4 P0 = tris[3 * li], P1 = tris[3 * li + 1], P2 = tris[3 * li + 2];
+    double a[3], b[3], c[3];
+    translate(r, P0, a);
+    translate(r, P1, b);
+    translate(r, P2, c);
+    const double t = r.kz == 2 ? woop_t<2>(r, a, b, c) : (r.kz == 1 ? woop_t<1>(r, a, b, c) : woop_t<0>(r, a, b, c));
+    const int orig = __float_as_int(P0.w);
+    if (!closer(t, orig, h)) return false;
+    h.t = t;
+    h.orig = orig;
+    h.leaf = li;
+    return true;
+}
+
+// The staged candidates [0, nc) of the lane's pulse (records from slot base on);
+// KZ: the dominant axis of every active lane.  Returns the winning slot or -1.
+template <int KZ>
+__device__ __forceinline__ int cand_loop(const Ray& r, const CandRec* __restrict__ rec, int nc, Hit& h)
+{
+    int best = -1;
+    for (int i = 0; i < nc; ++i) {
+        const CandRec& c = rec[i];
+        double a[3] = {c.a[0], c.a[1], c.a[2]}, b[3] = {c.b[0], c.b[1], c.b[2]}, e[3] = {c.c[0], c.c[1], c.c[2]};
+        const double t = woop_t<KZ>(r, a, b, e);
+        const int orig = c.orig;
+        if (closer(t, orig, h)) {
+            h.t = t;
+            h.orig = orig;
+            best = i;
+        }
     }
-    return false;
-}
-
-__device__ __forceinline__ bool leaf_test_rec(const Ray& r, float4 Pa, float4 Pb, float4 Pc, Hit& h, float& tcull)
-{
-    if (r.kz == 2) return leaf_test_kz<2>(r, Pa, Pb, Pc, h, tcull);
-    if (r.kz == 1) return leaf_test_kz<1>(r, Pa, Pb, Pc, h, tcull);
-    return leaf_test_kz<0>(r, Pa, Pb, Pc, h, tcull);
-}
-
-__device__ __forceinline__ void leaf_test(const Ray& r, const float4* __restrict__ tris, int li, Hit& h, float& tcull)
-{
-    if (leaf_test_rec(r, tris[3 * li], tris[3 * li + 1], tris[3 * li + 2], h, tcull)) h.leaf = li;
+    return best;
 }
 
 // Closest hit of one ray.  ring: this block's LDS ring, stride = blockDim.x.
@@ -130,6 +165,8 @@ __device__ __forceinline__ Hit traverse(const SceneDev& scene, const Ray& r, int
     h.t = INFINITY;
     h.leaf = -1;
     h.orig = 0x7fffffff;
+    RayBox rb;
+    setup_box(r, scene.bounds[12], rb);
     float tcull = INFINITY;
     const int stride = blockDim.x;
     int* my = ring + threadIdx.x;
@@ -149,8 +186,8 @@ __device__ __forceinline__ Hit traverse(const SceneDev& scene, const Ray& r, int
             const float4* nd = nodes + 4 * node;
             float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
             float tl, tr;
-            bool hl = box_hit(r, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl);
-            bool hr = box_hit(r, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr);
+            bool hl = box_hit(rb, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl);
+            bool hr = box_hit(rb, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr);
             int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
             if (hl && hr) {
                 int nearc = (tl <= tr) ? cl : cr;
@@ -170,7 +207,12 @@ __device__ __forceinline__ Hit traverse(const SceneDev& scene, const Ray& r, int
             if (hr) { node = cr; continue; }
         } else {
             if (COUNT) ++tests;
-            leaf_test(r, scene.tris, ~node, h, tcull);
+            if (leaf_test(r, scene.tris, ~node, h)) {
+                // boxes beyond the closest hit so far cannot hold a closer one
+                float tf = (float)h.t;
+                if ((double)tf < h.t) tf = nextafterf(tf, INFINITY);
+                tcull = tf;
+            }
         }
         if (sp == 0) break;
         --sp;
@@ -184,25 +226,26 @@ __device__ __forceinline__ Hit traverse(const SceneDev& scene, const Ray& r, int
     return h;
 }
 
-// Incidence and power of the chosen triangle (Sec. 5.2, Eq. 7):
-// cos = |d . n| / |n|, P = C w rho cos / R^2, all in FP64 as written.
-__device__ __forceinline__ void shade(const SceneDev& scene, const ScannerDev& sc, const Ray& r, const Hit& h,
-                                      float4 A, float4 B, float4 C, double w, double& cosang, double& P)
+// Incidence and power of the chosen triangle (Sec. 5.2, Eq. 7) in FP32, from
+// its translated FP64 vertices: cos = |d . n| / |n|, P = C w rho cos / R^2.
+__device__ __forceinline__ void shade(const Ray& r, const double* a, const double* b, const double* c, double t,
+                                      float cw, float rho, float& cosang, float& P)
 {
-#pragma clang fp contract(off)
-    double e1x = (double)B.x - A.x, e1y = (double)B.y - A.y, e1z = (double)B.z - A.z;
-    double e2x = (double)C.x - A.x, e2y = (double)C.y - A.y, e2z = (double)C.z - A.z;
-    double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
-    double c = fabs(r.D[0] * nx + r.D[1] * ny + r.D[2] * nz) / sqrt(nx * nx + ny * ny + nz * nz);
-    cosang = c;
-    P = sc.power_c * w * (double)scene.refl[h.orig] * c / (h.t * h.t);
+    const float e1x = (float)(b[0] - a[0]), e1y = (float)(b[1] - a[1]), e1z = (float)(b[2] - a[2]);
+    const float e2x = (float)(c[0] - a[0]), e2y = (float)(c[1] - a[1]), e2z = (float)(c[2] - a[2]);
+    const float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+    const float nn = nx * nx + ny * ny + nz * nz;
+    const float cs = nn > 0.0f ? fabsf(r.d32[0] * nx + r.d32[1] * ny + r.d32[2] * nz) / sqrtf(nn) : 0.0f;
+    const float R = (float)t;
+    cosang = cs;
+    P = cw * rho * cs / (R * R);
 }
 
 // Trace one lane's subray: fills tri (original index or -1), R, cos, P.
-// staged: the pulse's candidate records sit in wl->rec slots [q * 16, q * 16 + nc).
+// staged: the pulse's candidate records sit in rec[q * 16, q * 16 + nc).
 template <bool COUNT>
 __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
-                                           long long p, int k, int q, bool staged, const WaveLds* wl, int* ring,
+                                           long long p, int k, int q, bool staged, const CandRec* rec, int* ring,
                                            int ring_mask, int& tri, double& R, float& cosang, float& P, int& visits,
                                            int& tests)
 {
@@ -213,53 +256,53 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
     if (scene.n_tri <= 0) return;
     const double* pat = sc.pattern + 5 * k;
     Ray r;
-    if (!setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, pat, scene.bounds[12], r)) return;
+    if (!setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, pat, r)) return;
     Hit h;
     h.t = INFINITY;
     h.leaf = -1;
     h.orig = 0x7fffffff;
     const int nc = pulses.cand ? pulses.cand[p * (kCandMax + 1)] : -1;
-    float4 A, B, C;
-    if (nc >= 0) {
-        // the cone pass found every triangle any subray of this pulse can hit
-        float tcull = INFINITY;
-        if (staged) {
-            int best = -1;
-            for (int i = 0; i < nc; ++i) {
-                const int slot = q * 16 + i;
-                if (leaf_test_rec(r, wl->rec[0][slot], wl->rec[1][slot], wl->rec[2][slot], h, tcull)) best = slot;
-            }
-            if (best >= 0) {
-                h.leaf = best;
-                A = wl->rec[0][best];
-                B = wl->rec[1][best];
-                C = wl->rec[2][best];
-            }
+    double a[3], b[3], c[3];
+    if (nc >= 0 && staged) {
+        // the cone pass found every triangle any subray of this pulse can hit;
+        // the dominant axis is the same for the whole wavefront almost always, so
+        // the test is specialised for it behind a uniform branch
+        const CandRec* mine = rec + q * 16;
+        const int kz0 = __builtin_amdgcn_readfirstlane(r.kz);
+        int best;
+        if (__ballot(r.kz != kz0) == 0) {
+            if (kz0 == 2) best = cand_loop<2>(r, mine, nc, h);
+            else if (kz0 == 1) best = cand_loop<1>(r, mine, nc, h);
+            else best = cand_loop<0>(r, mine, nc, h);
         } else {
-            const int* cand = pulses.cand + p * (kCandMax + 1);
-            for (int i = 0; i < nc; ++i) leaf_test(r, scene.tris, cand[1 + i], h, tcull);
-            if (h.leaf >= 0) {
-                A = scene.tris[3 * h.leaf];
-                B = scene.tris[3 * h.leaf + 1];
-                C = scene.tris[3 * h.leaf + 2];
-            }
+            if (r.kz == 2) best = cand_loop<2>(r, mine, nc, h);
+            else if (r.kz == 1) best = cand_loop<1>(r, mine, nc, h);
+            else best = cand_loop<0>(r, mine, nc, h);
         }
         if (COUNT) tests += nc;
-    } else {
-        h = traverse<COUNT>(scene, r, ring, ring_mask, visits, tests);
-        if (h.leaf >= 0) {
-            A = scene.tris[3 * h.leaf];
-            B = scene.tris[3 * h.leaf + 1];
-            C = scene.tris[3 * h.leaf + 2];
+        if (best < 0) return;
+        const CandRec& w = mine[best];
+        for (int i = 0; i < 3; ++i) {
+            a[i] = w.a[i];
+            b[i] = w.b[i];
+            c[i] = w.c[i];
         }
+    } else {
+        if (nc >= 0) {
+            const int* cand = pulses.cand + p * (kCandMax + 1);
+            for (int i = 0; i < nc; ++i) leaf_test(r, scene.tris, cand[1 + i], h);
+            if (COUNT) tests += nc;
+        } else {
+            h = traverse<COUNT>(scene, r, ring, ring_mask, visits, tests);
+        }
+        if (h.leaf < 0) return;
+        translate(r, scene.tris[3 * h.leaf], a);
+        translate(r, scene.tris[3 * h.leaf + 1], b);
+        translate(r, scene.tris[3 * h.leaf + 2], c);
     }
-    if (h.leaf < 0) return;
-    double c, pw;
-    shade(scene, sc, r, h, A, B, C, pat[4], c, pw);
+    shade(r, a, b, c, h.t, (float)(sc.power_c * pat[4]), scene.refl[h.orig], cosang, P);
     tri = h.orig;
     R = h.t;
-    cosang = (float)c;
-    P = (float)pw;
 }
 
 // Contribution of one echo to a bin: offsets are taken from the centre bin jc of
@@ -290,7 +333,7 @@ __device__ __forceinline__ float echo_value(const ScannerDev& sc, float x, float
 // Bins outside the chunks are zero.
 template <int MAXCH, bool COMPUTE, bool RET, int SHAPE>
 __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
-                                            long long p, int k0, WaveLds* wl, bool attrib, double my_tau,
+                                            long long p, int k0, float4* sub, bool attrib, double my_tau,
                                             float my_pw, int my_tri)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -347,13 +390,13 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
                     echo_offset(sc, rel, jb + c * kWave + 32, v.x, v.y);
                     v.z = my_pw;
                 }
-                wl->sub[lane] = v;
+                sub[lane] = v;
             }
             wave_sync();
             float acc = 0.0f;
 #pragma unroll 4
             for (int kk = 0; kk < S; ++kk) {
-                const float4 u = wl->sub[k0 + kk];
+                const float4 u = sub[k0 + kk];
                 acc = fmaf(u.z, pulse_shape<SHAPE>(sc, (x - u.x) - u.y), acc);
             }
             wf[c] = jb + c * kWave + lane < nb ? acc : 0.0f;
@@ -450,14 +493,16 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
 template <int MAXCH, int MODE>
 __device__ __forceinline__ void process_wave(const SceneDev& scene, const ScannerDev& sc,
                                              const PulsesDev& pulses, const OutDev& out, long long first, int npw,
-                                             int* ring, int ring_mask, WaveLds* wl)
+                                             int* ring, int ring_mask, unsigned char* wl)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int S = sc.S;
     const int pl = lane / S;
     const int k = lane - pl * S;
     const bool active = pl < npw;
-    // stage the candidate triangles of up to 4 pulses with one load per lane
+    // stage the candidate triangles of up to 4 pulses, one per lane, translated
+    // to their pulse's origin
+    CandRec* rec = reinterpret_cast<CandRec*>(wl);
     const bool staged = pulses.cand && sc.P_w <= 4;
     if (staged) {
         const int q = lane >> 4, c = lane & 15;
@@ -465,9 +510,20 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
         if (q < npw) nq = pulses.cand[(first + q) * (kCandMax + 1)];
         if (c < nq) {
             const int li = pulses.cand[(first + q) * (kCandMax + 1) + 1 + c];
-            wl->rec[0][lane] = scene.tris[3 * li];
-            wl->rec[1][lane] = scene.tris[3 * li + 1];
-            wl->rec[2][lane] = scene.tris[3 * li + 2];
+            const double* o = pulses.origins + 3 * (first + q);
+            const float4 P0 = scene.tris[3 * li], P1 = scene.tris[3 * li + 1], P2 = scene.tris[3 * li + 2];
+            CandRec& w = rec[lane];
+            w.a[0] = (double)P0.x - o[0];
+            w.a[1] = (double)P0.y - o[1];
+            w.a[2] = (double)P0.z - o[2];
+            w.b[0] = (double)P1.x - o[0];
+            w.b[1] = (double)P1.y - o[1];
+            w.b[2] = (double)P1.z - o[2];
+            w.c[0] = (double)P2.x - o[0];
+            w.c[1] = (double)P2.y - o[1];
+            w.c[2] = (double)P2.z - o[2];
+            w.orig = __float_as_int(P0.w);
+            w.leaf = li;
         }
         wave_sync();
     }
@@ -477,7 +533,7 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     int visits = 0, tests = 0;
     if (active) {
         long long p = first + pl;
-        trace_lane<MODE == 2>(scene, sc, pulses, p, k, pl, staged, wl, ring, ring_mask, tri, R, cs, P, visits, tests);
+        trace_lane<MODE == 2>(scene, sc, pulses, p, k, pl, staged, rec, ring, ring_mask, tri, R, cs, P, visits, tests);
         long long o = p * out.sub_stride + k;
         if (out.sub_tri) out.sub_tri[o] = tri;
         if (out.sub_range) out.sub_range[o] = R;
@@ -500,23 +556,27 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     }
     if (MODE == 0) return;
     const double tau = (active && tri >= 0) ? 2.0 * R / kCmPerNs : (double)INFINITY;
+    // the staged records are dead: the same LDS now carries the waveform inputs
+    wave_sync();
+    float4* sub = reinterpret_cast<float4*>(wl);
     if (sc.shape == 0) {
         for (int q = 0; q < npw; ++q)
-            pulse_phase<MAXCH, true, true, 0>(sc, pulses, out, first + q, q * S, wl, true, tau, P, tri);
+            pulse_phase<MAXCH, true, true, 0>(sc, pulses, out, first + q, q * S, sub, true, tau, P, tri);
     } else {
         for (int q = 0; q < npw; ++q)
-            pulse_phase<MAXCH, true, true, 1>(sc, pulses, out, first + q, q * S, wl, true, tau, P, tri);
+            pulse_phase<MAXCH, true, true, 1>(sc, pulses, out, first + q, q * S, sub, true, tau, P, tri);
     }
 }
 
 template <int MAXCH, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_simulate(SceneDev scene, ScannerDev sc, PulsesDev pulses,
-                                                  OutDev out, long long first, long long count, int ring_mask)
+                                                  OutDev out, long long first, long long count, int ring_mask,
+                                                  int wl_bytes)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int waves = blockDim.x / kWave;
-    WaveLds* wl = reinterpret_cast<WaveLds*>(smem) + threadIdx.x / kWave;
-    int* ring = reinterpret_cast<int*>(smem + sizeof(WaveLds) * waves);
+    unsigned char* wl = smem + (threadIdx.x / kWave) * wl_bytes;
+    int* ring = reinterpret_cast<int*>(smem + wl_bytes * waves);
     long long wave = (long long)blockIdx.x * waves + threadIdx.x / kWave;
     long long p0 = wave * sc.P_w;
     if (p0 >= count) return;
@@ -530,8 +590,8 @@ template <int MAXCH, int KIND>
 __global__ __launch_bounds__(256) void k_wave(ScannerDev sc, PulsesDev pulses, OutDev out, long long first,
                                               long long count)
 {
-    __shared__ WaveLds lds[4];
-    WaveLds* wl = lds + threadIdx.x / kWave;
+    __shared__ float4 lds[4][kWave];
+    float4* sub = lds[threadIdx.x / kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int waves = blockDim.x / kWave;
     long long wave = (long long)blockIdx.x * waves + threadIdx.x / kWave;
@@ -557,11 +617,11 @@ __global__ __launch_bounds__(256) void k_wave(ScannerDev sc, PulsesDev pulses, O
     for (int q = 0; q < npw; ++q) {
         const long long p = first + p0 + q;
         if (KIND == 0) {
-            if (sc.shape == 0) pulse_phase<MAXCH, true, false, 0>(sc, pulses, out, p, q * S, wl, true, tau, P, tri);
-            else pulse_phase<MAXCH, true, false, 1>(sc, pulses, out, p, q * S, wl, true, tau, P, tri);
+            if (sc.shape == 0) pulse_phase<MAXCH, true, false, 0>(sc, pulses, out, p, q * S, sub, true, tau, P, tri);
+            else pulse_phase<MAXCH, true, false, 1>(sc, pulses, out, p, q * S, sub, true, tau, P, tri);
         } else {
-            if (sc.shape == 0) pulse_phase<MAXCH, false, true, 0>(sc, pulses, out, p, q * S, wl, attrib, tau, P, tri);
-            else pulse_phase<MAXCH, false, true, 1>(sc, pulses, out, p, q * S, wl, attrib, tau, P, tri);
+            if (sc.shape == 0) pulse_phase<MAXCH, false, true, 0>(sc, pulses, out, p, q * S, sub, attrib, tau, P, tri);
+            else pulse_phase<MAXCH, false, true, 1>(sc, pulses, out, p, q * S, sub, attrib, tau, P, tri);
         }
     }
 }
@@ -569,13 +629,13 @@ __global__ __launch_bounds__(256) void k_wave(ScannerDev sc, PulsesDev pulses, O
 // Persistent batched kernel: wavefronts take chunks of wave-tiles from a global counter.
 template <int MAXCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_persistent(SceneDev scene, BatchDev batch, PulsesDev pulses,
-                                                    OutDev out, int ring_mask)
+                                                    OutDev out, int ring_mask, int wl_bytes)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int waves = blockDim.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
-    WaveLds* wl = reinterpret_cast<WaveLds*>(smem) + threadIdx.x / kWave;
-    int* ring = reinterpret_cast<int*>(smem + sizeof(WaveLds) * waves);
+    unsigned char* wl = smem + (threadIdx.x / kWave) * wl_bytes;
+    int* ring = reinterpret_cast<int*>(smem + wl_bytes * waves);
     // Each wavefront takes `chunk` consecutive wave-tiles per counter update, so
     // the single counter sees about n_tiles / chunk atomics instead of one per tile.
     const long long chunk = batch.chunk;
@@ -606,9 +666,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     }
 }
 
-inline size_t sim_lds_bytes(int block, int ring)
+inline size_t sim_lds_bytes(int block, int ring, int wl_bytes)
 {
-    return sizeof(WaveLds) * (block / kWave) + sizeof(int) * (size_t)ring * block;
+    return (size_t)wl_bytes * (block / kWave) + sizeof(int) * (size_t)ring * block;
 }
 
 }  // namespace
@@ -620,24 +680,18 @@ hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const Pu
     const int block = cfg.block_waves * kWave;
     long long waves = (count + sc.P_w - 1) / sc.P_w;
     unsigned grid = (unsigned)((waves + cfg.block_waves - 1) / cfg.block_waves);
-    size_t lds = sim_lds_bytes(block, cfg.stack_lds);
+    const int wl = wave_lds_bytes(pulses.cand && sc.P_w <= 4 ? sc.P_w : 0);
+    size_t lds = sim_lds_bytes(block, cfg.stack_lds, wl);
     int mask = cfg.stack_lds - 1;
-    if (mode == 0) {
-        hipLaunchKernelGGL((k_simulate<4, 0>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out, first,
-                           count, mask);
-    } else if (mode == 2) {
-        hipLaunchKernelGGL((k_simulate<4, 2>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out, first,
-                           count, mask);
-    } else if (sc.n_bins <= 256) {
-        hipLaunchKernelGGL((k_simulate<4, 1>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out, first,
-                           count, mask);
-    } else if (sc.n_bins <= 512) {
-        hipLaunchKernelGGL((k_simulate<8, 1>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out, first,
-                           count, mask);
-    } else {
-        hipLaunchKernelGGL((k_simulate<16, 1>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out,
-                           first, count, mask);
-    }
+#define VLS_SIM_LAUNCH(CH, MODE)                                                                              \
+    hipLaunchKernelGGL((k_simulate<CH, MODE>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out, first, \
+                       count, mask, wl)
+    if (mode == 0) VLS_SIM_LAUNCH(4, 0);
+    else if (mode == 2) VLS_SIM_LAUNCH(4, 2);
+    else if (sc.n_bins <= 256) VLS_SIM_LAUNCH(4, 1);
+    else if (sc.n_bins <= 512) VLS_SIM_LAUNCH(8, 1);
+    else VLS_SIM_LAUNCH(16, 1);
+#undef VLS_SIM_LAUNCH
     return hipGetLastError();
 }
 
@@ -663,11 +717,13 @@ hipError_t launch_waveform(const ScannerDev& sc, const PulsesDev& pulses, const 
     return hipGetLastError();
 }
 
-hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, const PulsesDev& pulses,
-                             const OutDev& out, const LaunchCfg& cfg, int blocks, hipStream_t stream)
+hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, int staged_pw,
+                             const PulsesDev& pulses, const OutDev& out, const LaunchCfg& cfg, int blocks,
+                             hipStream_t stream)
 {
     const int block = cfg.block_waves * kWave;
-    size_t lds = sim_lds_bytes(block, cfg.stack_lds);
+    const int wl = wave_lds_bytes(pulses.cand ? staged_pw : 0);
+    size_t lds = sim_lds_bytes(block, cfg.stack_lds, wl);
     int mask = cfg.stack_lds - 1;
     hipError_t e = launch_fill_u64(batch.counter, 1, 0ull, stream);
     if (e != hipSuccess) return e;
@@ -676,18 +732,21 @@ hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int m
     long long ch = batch.n_tiles / (waves * 16 > 0 ? waves * 16 : 1);
     b.chunk = (int)(ch < 1 ? 1 : (ch > 4096 ? 4096 : ch));
     if (max_bins <= 256)
-        hipLaunchKernelGGL((k_persistent<4>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask);
+        hipLaunchKernelGGL((k_persistent<4>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask,
+                           wl);
     else if (max_bins <= 512)
-        hipLaunchKernelGGL((k_persistent<8>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask);
+        hipLaunchKernelGGL((k_persistent<8>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask,
+                           wl);
     else
-        hipLaunchKernelGGL((k_persistent<16>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask);
+        hipLaunchKernelGGL((k_persistent<16>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask,
+                           wl);
     return hipGetLastError();
 }
 
-int persistent_occupancy_blocks(int max_bins, const LaunchCfg& cfg)
+int persistent_occupancy_blocks(int max_bins, int staged_pw, const LaunchCfg& cfg)
 {
     const int block = cfg.block_waves * kWave;
-    size_t lds = sim_lds_bytes(block, cfg.stack_lds);
+    size_t lds = sim_lds_bytes(block, cfg.stack_lds, wave_lds_bytes(cfg.cone ? staged_pw : 0));
     int per_cu = 0;
     hipError_t e;
     if (max_bins <= 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<4>, block, lds);

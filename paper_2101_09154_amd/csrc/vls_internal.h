@@ -126,8 +126,11 @@ hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const Pu
                            const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_waveform(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
                            long long first, long long count, int mode, const LaunchCfg& cfg, hipStream_t stream);
-hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, const PulsesDev& pulses,
-                             const OutDev& out, const LaunchCfg& cfg, int blocks, hipStream_t stream);
+// staged_pw: the largest pulses-per-wavefront <= 4 among the batch's scanners (0 if
+// none): it sizes the LDS that stages candidate triangles.
+hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, int staged_pw,
+                             const PulsesDev& pulses, const OutDev& out, const LaunchCfg& cfg, int blocks,
+                             hipStream_t stream);
 hipError_t launch_backward(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
                            const int32_t* sub_tri, int sub_stride, const float* grad_wf, float* grad_refl,
                            float* grad_z, long long n_vert, const LaunchCfg& cfg, hipStream_t stream);
@@ -139,6 +142,6 @@ hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& p
 // Candidate lists hold leaf indices; rewrite them as original triangle indices.
 hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_pulses, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);
-int persistent_occupancy_blocks(int max_bins, const LaunchCfg& cfg);
+int persistent_occupancy_blocks(int max_bins, int staged_pw, const LaunchCfg& cfg);
 
 }  // namespace vls
