@@ -9,10 +9,10 @@ waveform write and returns for every pulse, inputs resident in HBM.
 Prints one JSON line.  A step is two launches: the cone pass (one traversal
 per pulse collecting candidate triangles) and the fused kernel (subray tests,
 power, waveform, returns).  The roofline is reported for the fused kernel, the
-dominant one, with its algorithmic bytes: per pulse 36 B in, the 64 B candidate
-list, 48 B per staged candidate triangle and 4*n_bins + 8 + 4 + 16*K B out,
-plus 4 B of reflectance per subray; the cone pass is reported beside it with
-64 B per node visit.  Node visits and triangle tests are counted by the
+dominant one, with its algorithmic bytes: per pulse 36 B in, the candidate
+count (4 B), 52 B per candidate (its id and its 48 B leaf record) and
+4*n_bins + 8 + 4 + 16*K B out, plus 4 B of reflectance per subray; the cone
+pass is reported beside it with 64 B per node visit.  Node visits and triangle tests are counted by the
 library (vls_trace_counts).
 """
 import argparse
@@ -267,16 +267,16 @@ def main():
 
     # time the cone pass alone (HIP events on the same stream); the fused kernel
     # is the rest of the step
-    cand_buf = torch.empty((n, 16), dtype=torch.int32, device=dev)
+    cand_buf = torch.empty((n, vp.vls.MAX_CANDIDATES + 1), dtype=torch.int32, device=dev)
     cone_ms = time_ms(lambda: ctx.cone_candidates(scene, sc, o, d, out=cand_buf), args.steps, 1, stream)
     sim_ms = ms - cone_ms
     per_pulse_io = 36.0 + 4.0 * nb + 8.0 + 4.0 + 16.0 * K
     cand_per_pulse = tests / n_sub   # every subray tests its pulse's candidates
-    # fused kernel: pulse in, candidate list (16 ints) and the staged candidate
+    # fused kernel: pulse in, candidate count and ids and the candidate
     # triangles (48 B each) per pulse, a reflectance per subray, outputs out
-    sim_bytes = n * (per_pulse_io + 64.0 + 48.0 * cand_per_pulse) + 4.0 * n_sub
+    sim_bytes = n * (per_pulse_io + 4.0 + 52.0 * cand_per_pulse) + 4.0 * n_sub
     # cone pass: 64 B per node visit, 48 B per leaf reached, pulse in, list out
-    cone_bytes = 64.0 * visits + n * (36.0 + 64.0 + 48.0 * cand_per_pulse)
+    cone_bytes = 64.0 * visits + n * (36.0 + 4.0 + 52.0 * cand_per_pulse)
     alg_bytes = sim_bytes + cone_bytes
     achieved = sim_bytes / (sim_ms * 1e-3) / 1e9
     # bytes the whole step must move at least once: the scene, pulses in, outputs out

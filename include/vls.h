@@ -55,6 +55,7 @@ enum { VLS_PULSE_GAUSSIAN = 0, VLS_PULSE_EQ3 = 1 };
 #define VLS_MAX_BINS 1024       /* waveform bins per pulse                       */
 #define VLS_MAX_RETURNS 16      /* returns kept per pulse                        */
 #define VLS_MAX_SCANNERS 64     /* scanner descriptions per batched call         */
+#define VLS_MAX_CANDIDATES 63   /* triangles the cone pass lists per pulse       */
 
 const char* vls_status_string(vls_status s);
 /* Detail of the last failure on the calling thread; valid until the next vls_* call there. */
@@ -332,9 +333,9 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
 
 /* Diagnostic: runs only the cone pass (the per-pulse traversal that collects
  * the triangles a pulse's subrays can hit) into `candidates`, a device array
- * [n_pulses][16] int32: entry 0 is the count (-1 when more than 15 triangles
- * were reached and the subrays traverse on their own), then the original
- * triangle indices.  Asynchronous on `stream`. */
+ * [n_pulses][VLS_MAX_CANDIDATES + 1] int32: entry 0 is the count (-1 when more
+ * than VLS_MAX_CANDIDATES triangles were reached and the subrays traverse on
+ * their own), then the original triangle indices.  Asynchronous on `stream`. */
 vls_status vls_cone_candidates(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners,
                                int32_t n_scanners, const vls_pulse_batch* pulses, int32_t* candidates, void* stream);
 

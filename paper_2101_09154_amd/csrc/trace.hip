@@ -58,7 +58,8 @@ struct CandRec {
 // subrays' waveform inputs (offset hi, offset lo, power, unused) per lane.
 __host__ __device__ constexpr int wave_lds_bytes(int staged_pw)
 {
-    return staged_pw * 16 * (int)sizeof(CandRec) > kWave * 16 ? staged_pw * 16 * (int)sizeof(CandRec) : kWave * 16;
+    return staged_pw * kCandStaged * (int)sizeof(CandRec) > kWave * 16 ? staged_pw * kCandStaged * (int)sizeof(CandRec)
+                                                                       : kWave * 16;
 }
 
 __device__ __forceinline__ bool box_hit(const RayBox& r, float lx, float ly, float lz, float hx, float hy, float hz,
@@ -242,7 +243,7 @@ __device__ __forceinline__ void shade(const Ray& r, const double* a, const doubl
 }
 
 // Trace one lane's subray: fills tri (original index or -1), R, cos, P.
-// staged: the pulse's candidate records sit in rec[q * 16, q * 16 + nc).
+// staged: the pulse's first candidate records sit in rec[q * 16, q * 16 + min(nc, 16)).
 template <bool COUNT>
 __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
                                            long long p, int k, int q, bool staged, const CandRec* rec, int* ring,
@@ -266,26 +267,36 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
     if (nc >= 0 && staged) {
         // the cone pass found every triangle any subray of this pulse can hit;
         // the dominant axis is the same for the whole wavefront almost always, so
-        // the test is specialised for it behind a uniform branch
-        const CandRec* mine = rec + q * 16;
+        // the test of the staged ones is specialised for it behind a uniform branch
+        const CandRec* mine = rec + q * kCandStaged;
+        const int ns = nc < kCandStaged ? nc : kCandStaged;
         const int kz0 = __builtin_amdgcn_readfirstlane(r.kz);
         int best;
         if (__ballot(r.kz != kz0) == 0) {
-            if (kz0 == 2) best = cand_loop<2>(r, mine, nc, h);
-            else if (kz0 == 1) best = cand_loop<1>(r, mine, nc, h);
-            else best = cand_loop<0>(r, mine, nc, h);
+            if (kz0 == 2) best = cand_loop<2>(r, mine, ns, h);
+            else if (kz0 == 1) best = cand_loop<1>(r, mine, ns, h);
+            else best = cand_loop<0>(r, mine, ns, h);
         } else {
-            if (r.kz == 2) best = cand_loop<2>(r, mine, nc, h);
-            else if (r.kz == 1) best = cand_loop<1>(r, mine, nc, h);
-            else best = cand_loop<0>(r, mine, nc, h);
+            if (r.kz == 2) best = cand_loop<2>(r, mine, ns, h);
+            else if (r.kz == 1) best = cand_loop<1>(r, mine, ns, h);
+            else best = cand_loop<0>(r, mine, ns, h);
         }
+        // candidates beyond the staged ones come from the leaf records
+        const int* cand = pulses.cand + p * (kCandMax + 1);
+        for (int i = ns; i < nc; ++i) leaf_test(r, scene.tris, cand[1 + i], h);
         if (COUNT) tests += nc;
-        if (best < 0) return;
-        const CandRec& w = mine[best];
-        for (int i = 0; i < 3; ++i) {
-            a[i] = w.a[i];
-            b[i] = w.b[i];
-            c[i] = w.c[i];
+        if (h.leaf >= 0) {
+            translate(r, scene.tris[3 * h.leaf], a);
+            translate(r, scene.tris[3 * h.leaf + 1], b);
+            translate(r, scene.tris[3 * h.leaf + 2], c);
+        } else {
+            if (best < 0) return;
+            const CandRec& w = mine[best];
+            for (int i = 0; i < 3; ++i) {
+                a[i] = w.a[i];
+                b[i] = w.b[i];
+                c[i] = w.c[i];
+            }
         }
     } else {
         if (nc >= 0) {
@@ -500,12 +511,12 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     const int pl = lane / S;
     const int k = lane - pl * S;
     const bool active = pl < npw;
-    // stage the candidate triangles of up to 4 pulses, one per lane, translated
-    // to their pulse's origin
+    // stage the first 16 candidate triangles of up to 4 pulses, one per lane,
+    // translated to their pulse's origin
     CandRec* rec = reinterpret_cast<CandRec*>(wl);
     const bool staged = pulses.cand && sc.P_w <= 4;
     if (staged) {
-        const int q = lane >> 4, c = lane & 15;
+        const int q = lane / kCandStaged, c = lane % kCandStaged;
         int nq = -1;
         if (q < npw) nq = pulses.cand[(first + q) * (kCandMax + 1)];
         if (c < nq) {

@@ -12,7 +12,8 @@ constexpr double kCmPerNs = 0.299792458;  // speed of light in m/ns (Sec. 3.4)
 constexpr int kWave = 64;                 // CDNA wavefront
 constexpr int kMaxSpill = 112;            // traversal-stack entries per lane beyond the LDS ring
 constexpr int kMaxRing = 32;
-constexpr int kCandMax = 15;             // candidate leaves kept per pulse by the cone pass
+constexpr int kCandMax = 63;             // candidate leaves kept per pulse by the cone pass
+constexpr int kCandStaged = 16;          // of which the first ones are staged in LDS by the fused kernel
 
 // One scanner as the kernels see it (everything derived on the host in FP64).
 struct ScannerDev {

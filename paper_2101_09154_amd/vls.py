@@ -18,6 +18,7 @@ OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "device error", 4: "not built",
           5: "unsupported", 6: "internal error"}
 MEM_HOST = 0
+MAX_CANDIDATES = 63  # VLS_MAX_CANDIDATES: triangles the cone pass lists per pulse
 MEM_DEVICE = 1
 PULSE_GAUSSIAN = 0
 PULSE_EQ3 = 1
@@ -425,10 +426,11 @@ class Context:
 
     def cone_candidates(self, scene, scanners, origins, directions, *, out=None, segment_offsets=None,
                         segment_scanner=None, stream=None):
-        """[n, 16] int32: candidate count (-1 = overflow) then original triangle ids, per pulse."""
+        """[n, MAX_CANDIDATES + 1] int32: candidate count (-1 = overflow) then original
+        triangle ids, per pulse."""
         n = origins.shape[0]
         if out is None:
-            out = torch.empty((n, 16), dtype=torch.int32, device=origins.device)
+            out = torch.empty((n, MAX_CANDIDATES + 1), dtype=torch.int32, device=origins.device)
         arr, ns = self._scanners(scanners)
         b, keep = self._batch(origins, directions, None, segment_offsets, segment_scanner)
         _check(lib().vls_cone_candidates(self._h, scene._h, arr, ns, ctypes.byref(b), _ptr(out), _stream(stream)))
