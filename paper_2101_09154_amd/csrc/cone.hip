@@ -35,7 +35,7 @@ struct Cone {
     double U[3];  // tan(a_max) u
     double V[3];  // tan(a_max) v
     float i1[3], i2[3], c1[3], c2[3];
-    unsigned pos;  // bit a: d_a + k > 0; bit 3 + a: d_a - k > 0
+    bool mixed;   // some axis has d_a - k < 0 < d_a + k
 };
 
 __device__ __forceinline__ bool setup_cone(const double* __restrict__ o, const float* __restrict__ d32, double tana,
@@ -63,14 +63,13 @@ __device__ __forceinline__ bool setup_cone(const double* __restrict__ o, const f
     double pad = (omax + (double)scene_mag + 1.0) * 1.9073486328125e-06;  // 2^-19, as for subrays
     // slope: tan(a_max), the FP32 rounding of the axis (~2^-23 rad) and slack
     float k = (float)(tana * (1.0 + 1e-6) + 4e-7);
-    c.pos = 0;
+    c.mixed = false;
     for (int i = 0; i < 3; ++i) {
         float da = (float)n[i];
         float s1 = da + k, s2 = da - k;
         if (s1 == 0.0f) s1 = 1e-30f;
         if (s2 == 0.0f) s2 = -1e-30f;
-        if (s1 > 0.0f) c.pos |= 1u << i;
-        if (s2 > 0.0f) c.pos |= 8u << i;
+        if (s1 > 0.0f && s2 < 0.0f) c.mixed = true;
         c.i1[i] = 1.0f / s1;
         c.i2[i] = 1.0f / s2;
         c.c1[i] = (float)(c.O[i] + pad) * c.i1[i];
@@ -79,64 +78,151 @@ __device__ __forceinline__ bool setup_cone(const double* __restrict__ o, const f
     return true;
 }
 
+// Interval of axial distances over which the cone can lie inside the slab
+// [lo, hi] of one axis.  tA is where the side of slope d + k crosses lo, tB where
+// the side of slope d - k crosses hi.  When both slopes have one sign, the
+// interval is [tA, tB] (positive) or [tB, tA] (negative); an ordering the other
+// way round only occurs for an interval that ends before t = 0, which the caller
+// rejects anyway, so min and max give it.  MIXED (slopes of both signs): the
+// interval is [max(tA, tB), inf).
+template <bool MIXED>
 __device__ __forceinline__ void cone_axis(const Cone& c, int a, float lo, float hi, float& lower, float& upper)
 {
-    float tA = fmaf(lo, c.i1[a], -c.c1[a]);  // lower plane, slope d_a + k
-    float tB = fmaf(hi, c.i2[a], -c.c2[a]);  // upper plane, slope d_a - k
-    bool p1 = (c.pos >> a) & 1u, p2 = (c.pos >> (3 + a)) & 1u;
-    lower = p1 ? (p2 ? tA : fmaxf(tA, tB)) : tB;
-    upper = p2 ? tB : (p1 ? INFINITY : tA);
+    const float tA = fmaf(lo, c.i1[a], -c.c1[a]);
+    const float tB = fmaf(hi, c.i2[a], -c.c2[a]);
+    if (!MIXED) {
+        lower = fminf(tA, tB);
+        upper = fmaxf(tA, tB);
+    } else {
+        const bool p1 = c.i1[a] > 0.0f, p2 = c.i2[a] > 0.0f;
+        const float mn = fminf(tA, tB), mx = fmaxf(tA, tB);
+        lower = (p1 && !p2) ? mx : mn;
+        upper = (p1 && !p2) ? INFINITY : mx;
+    }
 }
 
+template <bool MIXED>
 __device__ __forceinline__ bool cone_box(const Cone& c, float lx, float ly, float lz, float hx, float hy, float hz,
                                          float tcull, float& tn)
 {
     float l0, u0, l1, u1, l2, u2;
-    cone_axis(c, 0, lx, hx, l0, u0);
-    cone_axis(c, 1, ly, hy, l1, u1);
-    cone_axis(c, 2, lz, hz, l2, u2);
+    cone_axis<MIXED>(c, 0, lx, hx, l0, u0);
+    cone_axis<MIXED>(c, 1, ly, hy, l1, u1);
+    cone_axis<MIXED>(c, 2, lz, hz, l2, u2);
     float n0 = fmaxf(fmaxf(l0, l1), fmaxf(l2, 0.0f));
     float f0 = fminf(fminf(u0, u1), fminf(u2, tcull));
     tn = n0;
     return n0 <= f0;
 }
 
-// Moller-Trumbore in FP64 for one corner ray, requiring a margin inside all
-// three edges (a sufficient condition only: a miss here just means no cull).
-__device__ __forceinline__ bool corner_inside(const double O[3], const double d[3], const double a[3],
-                                              const double e1[3], const double e2[3], double& t)
-{
-    double p[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
-    double det = e1[0] * p[0] + e1[1] * p[1] + e1[2] * p[2];
-    if (det == 0.0) return false;
-    double inv = 1.0 / det;
-    double s[3] = {O[0] - a[0], O[1] - a[1], O[2] - a[2]};
-    double u = (s[0] * p[0] + s[1] * p[1] + s[2] * p[2]) * inv;
-    double q[3] = {s[1] * e1[2] - s[2] * e1[1], s[2] * e1[0] - s[0] * e1[2], s[0] * e1[1] - s[1] * e1[0]};
-    double v = (d[0] * q[0] + d[1] * q[1] + d[2] * q[2]) * inv;
-    t = (e2[0] * q[0] + e2[1] * q[1] + e2[2] * q[2]) * inv;
-    const double m = 1e-9;
-    return u > m && v > m && u + v < 1.0 - m && t > 0.0;
-}
-
 // Largest axial distance at which the whole pyramid around the cone meets the
-// triangle, or +inf if some corner ray misses it.
+// triangle, or +inf if some corner ray misses it.  Each corner ray O + t d,
+// d = D +- U +- V, is tested with Moller-Trumbore in FP64 and must pass inside
+// all three edges with a margin (a sufficient condition only: a miss just means
+// no cull).  The terms that do not depend on d (s = O - a, q = s x e1 and
+// e2 . q) are shared by the four corners, and u, v are compared unnormalised.
 __device__ __forceinline__ double cover_distance(const Cone& c, const float4* __restrict__ tris, int li)
 {
-    float4 A = tris[3 * li], B = tris[3 * li + 1], C = tris[3 * li + 2];
-    double a[3] = {A.x, A.y, A.z};
-    double e1[3] = {(double)B.x - A.x, (double)B.y - A.y, (double)B.z - A.z};
-    double e2[3] = {(double)C.x - A.x, (double)C.y - A.y, (double)C.z - A.z};
-    double tmax = 0.0;
-    for (int q = 0; q < 4; ++q) {
-        double su = (q & 1) ? 1.0 : -1.0, sv = (q & 2) ? 1.0 : -1.0;
-        double d[3] = {c.D[0] + su * c.U[0] + sv * c.V[0], c.D[1] + su * c.U[1] + sv * c.V[1],
-                       c.D[2] + su * c.U[2] + sv * c.V[2]};
-        double t;
-        if (!corner_inside(c.O, d, a, e1, e2, t)) return INFINITY;
-        tmax = fmax(tmax, t);
+    const float4 A = tris[3 * li], B = tris[3 * li + 1], C = tris[3 * li + 2];
+    const double e1[3] = {(double)B.x - A.x, (double)B.y - A.y, (double)B.z - A.z};
+    const double e2[3] = {(double)C.x - A.x, (double)C.y - A.y, (double)C.z - A.z};
+    const double s3[3] = {c.O[0] - A.x, c.O[1] - A.y, c.O[2] - A.z};
+    const double q[3] = {s3[1] * e1[2] - s3[2] * e1[1], s3[2] * e1[0] - s3[0] * e1[2], s3[0] * e1[1] - s3[1] * e1[0]};
+    const double tn = e2[0] * q[0] + e2[1] * q[1] + e2[2] * q[2];
+    const double m = 1e-9;
+    double dmin = INFINITY;  // smallest |det| over the corners (largest t = tn / det)
+    for (int k = 0; k < 4; ++k) {
+        const double su = (k & 1) ? 1.0 : -1.0, sv = (k & 2) ? 1.0 : -1.0;
+        const double d[3] = {c.D[0] + su * c.U[0] + sv * c.V[0], c.D[1] + su * c.U[1] + sv * c.V[1],
+                             c.D[2] + su * c.U[2] + sv * c.V[2]};
+        const double pv[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+        double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+        double un = s3[0] * pv[0] + s3[1] * pv[1] + s3[2] * pv[2];
+        double vn = d[0] * q[0] + d[1] * q[1] + d[2] * q[2];
+        double t = tn;
+        if (det < 0.0) {  // same tests with det > 0
+            det = -det;
+            un = -un;
+            vn = -vn;
+            t = -t;
+        }
+        if (!(det > 0.0 && un > m * det && vn > m * det && un + vn < (1.0 - m) * det && t > 0.0)) return INFINITY;
+        dmin = fmin(dmin, det);
     }
-    return tmax * (1.0 + 1e-9) + 1e-9;
+    return (fabs(tn) / dmin) * (1.0 + 1e-9) + 1e-9;
+}
+
+// One lane's cone traversal: writes the candidate leaves to out[1..] and returns
+// their count (-1: more than kCandMax, or a corrupted structure).
+template <bool COUNT, bool MIXED>
+__device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, int* __restrict__ out, int2* my,
+                                         int ring_mask, int& visits)
+{
+    int n = 0;
+    float tcull = INFINITY;
+    const int stride = blockDim.x;
+    // stack entries carry their entry distance, so nodes pushed before a cull
+    // distance was known are dropped when popped
+    int2 spill[kMaxSpill];
+    int sp = 0, nlow = 0;
+    int node = scene.root;
+    const int n_int = scene.n_tri - 1;
+    int budget = 2 * scene.n_tri + 64;
+    while (--budget > 0) {
+        if (node >= n_int || ~node >= scene.n_tri) return -1;
+        if (node >= 0) {
+            if (COUNT) ++visits;
+            const float4* nd = scene.nodes + 4 * node;
+            float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+            float tl, tr;
+            bool hl = cone_box<MIXED>(c, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl);
+            bool hr = cone_box<MIXED>(c, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr);
+            int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
+            if (hl || hr) {
+                // descend into the near child; with both hit, the far one is pushed
+                const bool lfirst = hl && (!hr || tl <= tr);
+                node = lfirst ? cl : cr;
+                if (hl && hr) {
+                    if (sp - nlow > ring_mask) {
+                        if (nlow < kMaxSpill) spill[nlow] = my[(nlow & ring_mask) * stride];
+                        ++nlow;
+                    }
+                    my[(sp & ring_mask) * stride] = make_int2(lfirst ? cr : cl, __float_as_int(lfirst ? tr : tl));
+                    ++sp;
+                }
+                continue;
+            }
+        } else {
+            if (n == kCandMax) return -1;  // too many: the subrays traverse on their own
+            out[1 + n] = ~node;
+            ++n;
+            double tc = cover_distance(c, scene.tris, ~node);
+            if (tc < INFINITY) {
+                float tf = (float)tc;
+                if ((double)tf < tc) tf = nextafterf(tf, INFINITY);
+                tcull = fminf(tcull, tf);
+            }
+        }
+        // pop the next node that can still hold a closest hit
+        bool found = false;
+        while (sp > 0) {
+            --sp;
+            int2 e;
+            if (sp < nlow) {
+                e = sp < kMaxSpill ? spill[sp] : make_int2(-1, 0);
+                nlow = sp;
+            } else {
+                e = my[(sp & ring_mask) * stride];
+            }
+            if (__int_as_float(e.y) <= tcull) {
+                node = e.x;
+                found = true;
+                break;
+            }
+        }
+        if (!found) return n;
+    }
+    return -1;
 }
 
 template <bool COUNT>
@@ -149,83 +235,19 @@ __global__ __launch_bounds__(256) void k_cone(SceneDev scene, double tana, Pulse
     const bool active = i < count;
     const long long p = first + i;
     int visits = 0;
-    if (active) {
-        int* out = cand + p * (kCandMax + 1);
-        int n = 0;
-        Cone c;
-        if (scene.n_tri > 0 && setup_cone(pulses.origins + 3 * p, pulses.dirs + 3 * p, tana, scene.bounds[12], c)) {
-            float tcull = INFINITY;
-            const int stride = blockDim.x;
-            // stack entries carry their entry distance, so nodes pushed before a
-            // cull distance was known are dropped when popped
-            int2* my = reinterpret_cast<int2*>(smem) + threadIdx.x;
-            int2 spill[kMaxSpill];
-            int sp = 0, nlow = 0;
-            int node = scene.root;
-            const int n_int = scene.n_tri - 1;
-            int budget = 2 * scene.n_tri + 64;
-            while (--budget > 0) {
-                if (node >= n_int || ~node >= scene.n_tri) break;
-                if (node >= 0) {
-                    if (COUNT) ++visits;
-                    const float4* nd = scene.nodes + 4 * node;
-                    float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
-                    float tl, tr;
-                    bool hl = cone_box(c, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl);
-                    bool hr = cone_box(c, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr);
-                    int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
-                    if (hl && hr) {
-                        const bool lfirst = tl <= tr;
-                        int nearc = lfirst ? cl : cr;
-                        int2 farc = make_int2(lfirst ? cr : cl, __float_as_int(lfirst ? tr : tl));
-                        if (sp - nlow > ring_mask) {
-                            if (nlow < kMaxSpill) spill[nlow] = my[(nlow & ring_mask) * stride];
-                            ++nlow;
-                        }
-                        my[(sp & ring_mask) * stride] = farc;
-                        ++sp;
-                        node = nearc;
-                        continue;
-                    }
-                    if (hl) { node = cl; continue; }
-                    if (hr) { node = cr; continue; }
-                } else {
-                    if (n == kCandMax) {  // too many: the subrays traverse on their own
-                        n = -1;
-                        break;
-                    }
-                    out[1 + n] = ~node;
-                    ++n;
-                    double tc = cover_distance(c, scene.tris, ~node);
-                    if (tc < INFINITY) {
-                        float tf = (float)tc;
-                        if ((double)tf < tc) tf = nextafterf(tf, INFINITY);
-                        tcull = fminf(tcull, tf);
-                    }
-                }
-                // pop the next node that can still hold a closest hit
-                bool found = false;
-                while (sp > 0) {
-                    --sp;
-                    int2 e;
-                    if (sp < nlow) {
-                        e = sp < kMaxSpill ? spill[sp] : make_int2(-1, 0);
-                        nlow = sp;
-                    } else {
-                        e = my[(sp & ring_mask) * stride];
-                    }
-                    if (__int_as_float(e.y) <= tcull) {
-                        node = e.x;
-                        found = true;
-                        break;
-                    }
-                }
-                if (!found) break;
-            }
-            if (budget <= 0) n = -1;
-        }
-        out[0] = n;
+    Cone c;
+    const bool ok = active && scene.n_tri > 0 &&
+                    setup_cone(pulses.origins + 3 * p, pulses.dirs + 3 * p, tana, scene.bounds[12], c);
+    int n = 0;
+    int* out = cand + p * (kCandMax + 1);
+    int2* my = reinterpret_cast<int2*>(smem) + threadIdx.x;
+    // the cheaper slab test serves every wavefront without a mixed-sign axis
+    if (__ballot(ok && c.mixed) == 0) {
+        if (ok) n = cone_walk<COUNT, false>(scene, c, out, my, ring_mask, visits);
+    } else {
+        if (ok) n = cone_walk<COUNT, true>(scene, c, out, my, ring_mask, visits);
     }
+    if (active) out[0] = n;
     if (COUNT) {
         unsigned long long v = (unsigned long long)visits;
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
