@@ -31,9 +31,13 @@ namespace {
 
 struct Cone {
     double O[3];
-    double D[3];
-    double U[3];  // tan(a_max) u
-    double V[3];  // tan(a_max) v
+    // axis and the pyramid's half-width vectors (1 + 1e-3) tan(a_max) u, v in
+    // FP32: the widening (2.5e-7 rad at the largest beams here) covers the FP32
+    // rounding of the corner directions (~1e-7 rad), so the pyramid of the
+    // rounded corners still contains every subray
+    float D[3];
+    float U[3];
+    float V[3];
     float i1[3], i2[3], c1[3], c2[3];
     bool mixed;   // some axis has d_a - k < 0 < d_a + k
 };
@@ -52,11 +56,12 @@ __device__ __forceinline__ bool setup_cone(const double* __restrict__ o, const f
     double u[3] = {1.0 + sgn * n[0] * n[0] * a, sgn * b, -sgn * n[0]};
     double v[3] = {b, sgn + n[1] * n[1] * a, -n[1]};
     double omax = 0.0;
+    const double w = tana * (1.0 + 1e-3);
     for (int i = 0; i < 3; ++i) {
         c.O[i] = o[i];
-        c.D[i] = n[i];
-        c.U[i] = tana * u[i];
-        c.V[i] = tana * v[i];
+        c.D[i] = (float)n[i];
+        c.U[i] = (float)(w * u[i]);
+        c.V[i] = (float)(w * v[i]);
         omax = fmax(omax, fabs(o[i]));
     }
     if (!(omax < INFINITY)) return false;
@@ -117,10 +122,12 @@ __device__ __forceinline__ bool cone_box(const Cone& c, float lx, float ly, floa
 
 // Largest axial distance at which the whole pyramid around the cone meets the
 // triangle, or +inf if some corner ray misses it.  Each corner ray O + t d,
-// d = D +- U +- V, is tested with Moller-Trumbore in FP64 and must pass inside
-// all three edges with a margin (a sufficient condition only: a miss just means
-// no cull).  The terms that do not depend on d (s = O - a, q = s x e1 and
-// e2 . q) are shared by the four corners, and u, v are compared unnormalised.
+// d = D +- U +- V, must hit the triangle inside all three edges with a margin
+// (Moller-Trumbore in FP64; a sufficient condition only: a miss just means no
+// cull).  With s = O - a, n = e1 x e2, w = e2 x s and q = s x e1, the
+// unnormalised determinant and barycentrics are triple products:
+// det = -d . n, u det = d . w, v det = d . q, t det = e2 . q, so each corner
+// costs three dot products.
 __device__ __forceinline__ double cover_distance(const Cone& c, const float4* __restrict__ tris, int li)
 {
     const float4 A = tris[3 * li], B = tris[3 * li + 1], C = tris[3 * li + 2];
@@ -128,16 +135,18 @@ __device__ __forceinline__ double cover_distance(const Cone& c, const float4* __
     const double e2[3] = {(double)C.x - A.x, (double)C.y - A.y, (double)C.z - A.z};
     const double s3[3] = {c.O[0] - A.x, c.O[1] - A.y, c.O[2] - A.z};
     const double q[3] = {s3[1] * e1[2] - s3[2] * e1[1], s3[2] * e1[0] - s3[0] * e1[2], s3[0] * e1[1] - s3[1] * e1[0]};
+    const double w[3] = {e2[1] * s3[2] - e2[2] * s3[1], e2[2] * s3[0] - e2[0] * s3[2], e2[0] * s3[1] - e2[1] * s3[0]};
+    const double nv[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
     const double tn = e2[0] * q[0] + e2[1] * q[1] + e2[2] * q[2];
     const double m = 1e-9;
     double dmin = INFINITY;  // smallest |det| over the corners (largest t = tn / det)
     for (int k = 0; k < 4; ++k) {
-        const double su = (k & 1) ? 1.0 : -1.0, sv = (k & 2) ? 1.0 : -1.0;
-        const double d[3] = {c.D[0] + su * c.U[0] + sv * c.V[0], c.D[1] + su * c.U[1] + sv * c.V[1],
-                             c.D[2] + su * c.U[2] + sv * c.V[2]};
-        const double pv[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
-        double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
-        double un = s3[0] * pv[0] + s3[1] * pv[1] + s3[2] * pv[2];
+        const float su = (k & 1) ? 1.0f : -1.0f, sv = (k & 2) ? 1.0f : -1.0f;
+        const double d[3] = {(double)fmaf(sv, c.V[0], fmaf(su, c.U[0], c.D[0])),
+                             (double)fmaf(sv, c.V[1], fmaf(su, c.U[1], c.D[1])),
+                             (double)fmaf(sv, c.V[2], fmaf(su, c.U[2], c.D[2]))};
+        double det = -(d[0] * nv[0] + d[1] * nv[1] + d[2] * nv[2]);
+        double un = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
         double vn = d[0] * q[0] + d[1] * q[1] + d[2] * q[2];
         double t = tn;
         if (det < 0.0) {  // same tests with det > 0
@@ -226,7 +235,7 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
 }
 
 template <bool COUNT>
-__global__ __launch_bounds__(256) void k_cone(SceneDev scene, double tana, PulsesDev pulses, int* __restrict__ cand,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_cone(SceneDev scene, double tana, PulsesDev pulses, int* __restrict__ cand,
                                               long long first, long long count, int ring_mask,
                                               unsigned long long* counts)
 {
