@@ -339,6 +339,23 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
 vls_status vls_cone_candidates(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners,
                                int32_t n_scanners, const vls_pulse_batch* pulses, int32_t* candidates, void* stream);
 
+/* Kernel timing for measurement (no passage of the paper: it instruments the
+ * calls above).  While enabled, every eager vls_simulate call records a pair of
+ * HIP events on its stream around the cone pass and around the fused (or
+ * persistent) kernel; nothing is recorded while the stream is being captured
+ * into a graph.  vls_profile_read waits for the recorded events, returns the
+ * summed elapsed times and launch counts since the previous read, and clears
+ * them.  The events are owned by the context.  Errors: VLS_ERR_INVALID_ARG for
+ * NULL arguments; a failed event call returns VLS_ERR_DEVICE. */
+typedef struct {
+    double cone_ms;          /* summed over the recorded cone passes          */
+    double fused_ms;         /* summed over the recorded fused kernels        */
+    int64_t cone_launches;
+    int64_t fused_launches;
+} vls_profile;
+vls_status vls_profile_enable(vls_context ctx, int32_t enable);
+vls_status vls_profile_read(vls_context ctx, vls_profile* out);
+
 /* Synchronise `stream` and report any device error as VLS_ERR_DEVICE. */
 vls_status vls_synchronize(vls_context ctx, void* stream);
 

@@ -153,9 +153,18 @@ struct vls_context_s {
     std::vector<Batch> batches;  // uploaded segment tables, reused by content
     int* cand = nullptr;         // cone-pass candidate lists, grown on demand
     long long cand_pulses = 0;
+    // kernel timing (vls_profile_*): event pairs recorded around the cone pass
+    // and the fused kernel of eager vls_simulate calls, and a pool of spares
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_cone, prof_fused, prof_pool;
     ~vls_context_s()
     {
         (void)hipSetDevice(device);
+        for (auto* v : {&prof_cone, &prof_fused, &prof_pool})
+            for (auto& e : *v) {
+                (void)hipEventDestroy(e.first);
+                (void)hipEventDestroy(e.second);
+            }
         (void)hipFree(cand);
         for (auto& kv : patterns) (void)hipFree(kv.second);
         for (auto& b : batches) (void)hipFree(b.dev);
@@ -775,6 +784,35 @@ static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_s
     return VLS_OK;
 }
 
+// Timing events: take a pair from the pool (or create one) and record its start.
+static hipError_t prof_begin(vls_context ctx, hipStream_t s, std::pair<hipEvent_t, hipEvent_t>& ev)
+{
+    hipError_t e;
+    if (!ctx->prof_pool.empty()) {
+        ev = ctx->prof_pool.back();
+        ctx->prof_pool.pop_back();
+    } else {
+        if ((e = hipEventCreate(&ev.first)) != hipSuccess) return e;
+        if ((e = hipEventCreate(&ev.second)) != hipSuccess) {
+            (void)hipEventDestroy(ev.first);
+            return e;
+        }
+    }
+    return hipEventRecord(ev.first, s);
+}
+
+static hipError_t prof_end(vls_context ctx, hipStream_t s, std::pair<hipEvent_t, hipEvent_t>& ev,
+                           std::vector<std::pair<hipEvent_t, hipEvent_t>>& into)
+{
+    hipError_t e = hipEventRecord(ev.second, s);
+    if (e != hipSuccess) {
+        ctx->prof_pool.push_back(ev);
+        return e;
+    }
+    into.push_back(ev);
+    return hipSuccess;
+}
+
 // cand: candidate workspace of at least n_pulses entries (the context's, or a graph's own)
 static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepared& pr, const vls_pulse_batch* pulses,
                                    const vls_outputs* out, vls_context_s::Batch* bt, int blocks, hipStream_t s,
@@ -785,14 +823,24 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
     PulsesDev pd = pulses_dev(pulses);
     SceneDev sd = scene_dev(scene);
     hipError_t e;
+    // timing events only on eager calls (not while a graph is being captured)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (ctx->prof && hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
+    const bool prof = ctx->prof && cap == hipStreamCaptureStatusNone;
+    std::pair<hipEvent_t, hipEvent_t> ev{};
     if (ctx->cfg.cone) {
+        if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
         e = launch_cone(sd, max_tan(pr), pd, cand, 0, pulses->n_pulses, ctx->cfg, nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "cone launch");
+        if (prof && (e = prof_end(ctx, s, ev, ctx->prof_cone)) != hipSuccess) return hip_fail(e, "timing event");
         pd.cand = cand;
     }
+    if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
     if (!bt) e = launch_simulate(sd, pr.sc[0], pd, od, 0, pulses->n_pulses, 1, ctx->cfg, s);
     else e = launch_persistent(sd, bt->bd, pr.n_bins, staged_pw(pr), pd, od, ctx->cfg, blocks, s);
-    return e == hipSuccess ? VLS_OK : hip_fail(e, "simulate launch");
+    if (e != hipSuccess) return hip_fail(e, "simulate launch");
+    if (prof && (e = prof_end(ctx, s, ev, ctx->prof_fused)) != hipSuccess) return hip_fail(e, "timing event");
+    return VLS_OK;
 }
 
 vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
@@ -1100,6 +1148,36 @@ vls_status vls_synchronize(vls_context ctx, void* stream)
     VLS_HIP(hipStreamSynchronize((hipStream_t)stream), "synchronize");
     VLS_HIP(hipGetLastError(), "device error");
     return VLS_OK;
+}
+
+vls_status vls_profile_enable(vls_context ctx, int32_t enable)
+{
+    if (!ctx) return fail(VLS_ERR_INVALID_ARG, "context is NULL");
+    ctx->prof = enable != 0;
+    return VLS_OK;
+}
+
+vls_status vls_profile_read(vls_context ctx, vls_profile* out)
+{
+    if (!ctx || !out) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+    VLS_HIP(hipSetDevice(ctx->device), "set device");
+    *out = vls_profile{};
+    vls_status st = VLS_OK;
+    auto drain = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double& ms, int64_t& n) {
+        for (auto& e : v) {
+            float t = 0.0f;
+            hipError_t r = hipEventSynchronize(e.second);
+            if (r == hipSuccess) r = hipEventElapsedTime(&t, e.first, e.second);
+            if (r != hipSuccess && st == VLS_OK) st = hip_fail(r, "timing event");
+            ms += t;
+            ++n;
+            ctx->prof_pool.push_back(e);
+        }
+        v.clear();
+    };
+    drain(ctx->prof_cone, out->cone_ms, out->cone_launches);
+    drain(ctx->prof_fused, out->fused_ms, out->fused_launches);
+    return st;
 }
 
 }  // extern "C"

@@ -246,18 +246,16 @@ __device__ __forceinline__ void shade(const Ray& r, const double* a, const doubl
 // staged: the pulse's first candidate records sit in rec[q * 16, q * 16 + min(nc, 16)).
 template <bool COUNT>
 __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
-                                           long long p, int k, int q, bool staged, const CandRec* rec, int* ring,
-                                           int ring_mask, int& tri, double& R, float& cosang, float& P, int& visits,
-                                           int& tests)
+                                           long long p, int k, int q, const Ray& r, bool ray_ok, bool staged,
+                                           const CandRec* rec, int* ring, int ring_mask, int& tri, double& R,
+                                           float& cosang, float& P, int& visits, int& tests)
 {
     tri = -1;
     R = INFINITY;
     cosang = 0.0f;
     P = 0.0f;
-    if (scene.n_tri <= 0) return;
+    if (scene.n_tri <= 0 || !ray_ok) return;
     const double* pat = sc.pattern + 5 * k;
-    Ray r;
-    if (!setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, pat, r)) return;
     Hit h;
     h.t = INFINITY;
     h.leaf = -1;
@@ -513,16 +511,28 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     const bool active = pl < npw;
     // stage the first 16 candidate triangles of up to 4 pulses, one per lane,
     // translated to their pulse's origin
+    // The loads are issued first and the subray setup runs while they are in
+    // flight: the count and the ids share a row, and the record loads use an id
+    // clamped into range, so they need not wait for the count.
     CandRec* rec = reinterpret_cast<CandRec*>(wl);
     const bool staged = pulses.cand && sc.P_w <= 4;
+    const int sq = lane / kCandStaged, sc16 = lane % kCandStaged;
+    int nq = -1, li = 0;
+    float4 P0, P1, P2;
+    if (staged && sq < npw && scene.n_tri > 0) {
+        const int* row = pulses.cand + (first + sq) * (kCandMax + 1);
+        nq = row[0];
+        li = min(max(row[1 + sc16], 0), scene.n_tri - 1);
+        P0 = scene.tris[3 * li];
+        P1 = scene.tris[3 * li + 1];
+        P2 = scene.tris[3 * li + 2];
+    }
+    Ray r;
+    const bool ray_ok = active && setup_ray(pulses.origins + 3 * (first + pl), pulses.dirs + 3 * (first + pl),
+                                            sc.pattern + 5 * k, r);
     if (staged) {
-        const int q = lane / kCandStaged, c = lane % kCandStaged;
-        int nq = -1;
-        if (q < npw) nq = pulses.cand[(first + q) * (kCandMax + 1)];
-        if (c < nq) {
-            const int li = pulses.cand[(first + q) * (kCandMax + 1) + 1 + c];
-            const double* o = pulses.origins + 3 * (first + q);
-            const float4 P0 = scene.tris[3 * li], P1 = scene.tris[3 * li + 1], P2 = scene.tris[3 * li + 2];
+        if (sc16 < nq) {
+            const double* o = pulses.origins + 3 * (first + sq);
             CandRec& w = rec[lane];
             w.a[0] = (double)P0.x - o[0];
             w.a[1] = (double)P0.y - o[1];
@@ -544,7 +554,8 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     int visits = 0, tests = 0;
     if (active) {
         long long p = first + pl;
-        trace_lane<MODE == 2>(scene, sc, pulses, p, k, pl, staged, rec, ring, ring_mask, tri, R, cs, P, visits, tests);
+        trace_lane<MODE == 2>(scene, sc, pulses, p, k, pl, r, ray_ok, staged, rec, ring, ring_mask, tri, R, cs, P, visits,
+                              tests);
         long long o = p * out.sub_stride + k;
         if (out.sub_tri) out.sub_tri[o] = tri;
         if (out.sub_range) out.sub_range[o] = R;

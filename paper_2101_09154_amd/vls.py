@@ -71,6 +71,11 @@ class LaunchConfig(ctypes.Structure):
                 ("cone", i32), ("reserved", i32)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("cone_ms", f64), ("fused_ms", f64), ("cone_launches", ctypes.c_int64),
+                ("fused_launches", ctypes.c_int64)]
+
+
 class TuneResult(ctypes.Structure):
     _fields_ = [("best", LaunchConfig), ("best_ms", f64), ("default_ms", f64), ("n_tried", i32),
                 ("from_cache", i32)]
@@ -105,6 +110,8 @@ _SIGS = {
     "vls_graph_launch": ([P, P], i32),
     "vls_graph_destroy": ([P], i32),
     "vls_autotune": ([P, P, P, i32, P, P, ctypes.c_char_p, P, P], i32),
+    "vls_profile_enable": ([P, i32], i32),
+    "vls_profile_read": ([P, P], i32),
 }
 
 
@@ -435,6 +442,18 @@ class Context:
         b, keep = self._batch(origins, directions, None, segment_offsets, segment_scanner)
         _check(lib().vls_cone_candidates(self._h, scene._h, arr, ns, ctypes.byref(b), _ptr(out), _stream(stream)))
         return out
+
+    def profile(self, enable=True):
+        """Record HIP events around the cone pass and the fused kernel of each
+        eager simulate call (see profile_read)."""
+        _check(lib().vls_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """Summed kernel times (ms) and launch counts since the last read (waits for them)."""
+        p = Profile()
+        _check(lib().vls_profile_read(self._h, ctypes.byref(p)))
+        return {"cone_ms": p.cone_ms, "fused_ms": p.fused_ms, "cone_launches": int(p.cone_launches),
+                "fused_launches": int(p.fused_launches)}
 
     def trace_counts(self, scene, scanners, origins, directions, *, segment_offsets=None, segment_scanner=None,
                      stream=None):

@@ -355,6 +355,35 @@ def test_graph_replays_match_eager(ctx):
     g.close()
 
 
+def test_kernel_timing_events(ctx):
+    # the library's per-kernel events: two eager calls give two timed launches of
+    # each kernel, results are unchanged, a graph capture records nothing, and a
+    # read clears the totals
+    mesh, scs, batch, seg_sc = _small_batch()
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = _dev(batch.origins)
+    d = _dev(batch.directions)
+    kw = dict(segment_offsets=batch.segment_offsets, segment_scanner=seg_sc)
+    ctx.set_launch_config()
+    ref = to_np(ctx.simulate(scene, scs, o, d, **kw))
+    ctx.profile(True)
+    a = to_np(ctx.simulate(scene, scs, o, d, **kw))
+    out = ctx.alloc_outputs(batch.n, 61, 256, 8, o.device)
+    g = ctx.capture_graph(scene, scs, o, d, out, **kw)
+    g.launch()
+    torch.cuda.synchronize()
+    b = to_np(ctx.simulate(scene, scs, o, d, **kw))
+    p = ctx.profile_read()
+    ctx.profile(False)
+    g.close()
+    say("kernel timing", p)
+    assert p["cone_launches"] == 2 and p["fused_launches"] == 2
+    assert p["cone_ms"] > 0.0 and p["fused_ms"] > 0.0
+    assert ctx.profile_read() == {"cone_ms": 0.0, "fused_ms": 0.0, "cone_launches": 0, "fused_launches": 0}
+    _assert_batch_equal(ref, a, batch, seg_sc, scs, 0)
+    _assert_batch_equal(ref, b, batch, seg_sc, scs, 1)
+
+
 def test_autotune_and_cache(ctx, tmp_path):
     mesh, scs, batch, seg_sc = _small_batch()
     scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
