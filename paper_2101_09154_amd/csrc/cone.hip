@@ -163,6 +163,13 @@ __device__ __forceinline__ double cover_distance(const Cone& c, const float4* __
 
 // One lane's cone traversal: writes the candidate leaves to out[1..] and returns
 // their count (-1: more than kCandMax, or a corrupted structure).
+//
+// A leaf is recorded and the walk moves on at once; the cover test (the
+// expensive part, and only an aid to culling) runs on a lane's first untested
+// leaf in batches, when a quarter of the wavefront's walking lanes (or 16) have
+// one waiting, so that the wavefront does not pay for it in every step in which
+// some lane sits at a leaf.  A later or skipped cover test only culls less; the
+// list still holds every leaf the cone reaches before the cull that applies.
 template <bool COUNT, bool MIXED>
 __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, int* __restrict__ out, int2* my,
                                          int ring_mask, int& visits)
@@ -177,17 +184,22 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
     int node = scene.root;
     const int n_int = scene.n_tri - 1;
     int budget = 2 * scene.n_tri + 64;
-    while (--budget > 0) {
-        if (node >= n_int || ~node >= scene.n_tri) return -1;
-        if (node >= 0) {
-            if (COUNT) ++visits;
-            const float4* nd = scene.nodes + 4 * node;
-            float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
-            float tl, tr;
-            bool hl = cone_box<MIXED>(c, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl);
-            bool hr = cone_box<MIXED>(c, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr);
-            int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
-            if (hl || hr) {
+    bool busy = true;
+    int pend = -1;  // first recorded leaf not yet cover-tested
+    while (true) {
+        if (busy) {
+            bool pop = false;
+            if (--budget <= 0 || node >= n_int || ~node >= scene.n_tri) {
+                n = -1;
+                busy = false;
+            } else if (node >= 0) {
+                if (COUNT) ++visits;
+                const float4* nd = scene.nodes + 4 * node;
+                float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+                float tl, tr;
+                bool hl = cone_box<MIXED>(c, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl);
+                bool hr = cone_box<MIXED>(c, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr);
+                int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
                 // descend into the near child; with both hit, the far one is pushed
                 const bool lfirst = hl && (!hr || tl <= tr);
                 node = lfirst ? cl : cr;
@@ -199,39 +211,53 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
                     my[(sp & ring_mask) * stride] = make_int2(lfirst ? cr : cl, __float_as_int(lfirst ? tr : tl));
                     ++sp;
                 }
-                continue;
-            }
-        } else {
-            if (n == kCandMax) return -1;  // too many: the subrays traverse on their own
-            out[1 + n] = ~node;
-            ++n;
-            double tc = cover_distance(c, scene.tris, ~node);
-            if (tc < INFINITY) {
-                float tf = (float)tc;
-                if ((double)tf < tc) tf = nextafterf(tf, INFINITY);
-                tcull = fminf(tcull, tf);
-            }
-        }
-        // pop the next node that can still hold a closest hit
-        bool found = false;
-        while (sp > 0) {
-            --sp;
-            int2 e;
-            if (sp < nlow) {
-                e = sp < kMaxSpill ? spill[sp] : make_int2(-1, 0);
-                nlow = sp;
+                pop = !hl && !hr;
+            } else if (n == kCandMax) {  // too many: the subrays traverse on their own
+                n = -1;
+                busy = false;
             } else {
-                e = my[(sp & ring_mask) * stride];
+                out[1 + n] = ~node;
+                ++n;
+                if (pend < 0) pend = ~node;
+                pop = true;
             }
-            if (__int_as_float(e.y) <= tcull) {
-                node = e.x;
-                found = true;
-                break;
+            if (pop) {
+                // pop the next node that can still hold a closest hit
+                busy = false;
+                while (sp > 0) {
+                    --sp;
+                    int2 e;
+                    if (sp < nlow) {
+                        e = sp < kMaxSpill ? spill[sp] : make_int2(-1, 0);
+                        nlow = sp;
+                    } else {
+                        e = my[(sp & ring_mask) * stride];
+                    }
+                    if (__int_as_float(e.y) <= tcull) {
+                        node = e.x;
+                        busy = true;
+                        break;
+                    }
+                }
             }
         }
-        if (!found) return n;
+        const unsigned long long walking = __ballot(busy);
+        if (walking == 0) break;
+        const unsigned long long waiting = __ballot(busy && pend >= 0);
+        const int nw = __popcll(waiting);
+        if (nw >= 16 || 4 * nw >= __popcll(walking)) {
+            if (busy && pend >= 0) {
+                double tc = cover_distance(c, scene.tris, pend);
+                if (tc < INFINITY) {
+                    float tf = (float)tc;
+                    if ((double)tf < tc) tf = nextafterf(tf, INFINITY);
+                    tcull = fminf(tcull, tf);
+                }
+                pend = -1;
+            }
+        }
     }
-    return -1;
+    return n;
 }
 
 template <bool COUNT>
