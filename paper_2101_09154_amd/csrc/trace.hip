@@ -349,10 +349,10 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
     const int S = sc.S, nb = sc.n_bins, K = sc.K;
     const bool sub_lane = lane >= k0 && lane < k0 + S;
     const bool mine = sub_lane && my_tri >= 0;
-    double t0;
+    double t0, tmin = INFINITY;
     bool any;
     if (COMPUTE || attrib) {
-        double tmin = wave_min_d(mine ? my_tau : INFINITY);
+        tmin = wave_min_d(mine ? my_tau : INFINITY);
         any = tmin < INFINITY;
         if (COMPUTE) {
             if (pulses.t0_in) t0 = pulses.t0_in[p];
@@ -371,18 +371,17 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
     if (!COMPUTE) {
         nch = (nb + kWave - 1) / kWave;
     } else if (have) {
-        // support of the echoes in bins, widened by one bin against rounding
-        int jl = 0x7fffffff, jh = -0x7fffffff;
-        if (mine) {
-            float hi = (float)rel;
-            jl = (int)fmaxf(floorf((hi - sc.cut_lo) * sc.inv_bin) - 1.0f, -1e9f);
-            jh = (int)fminf(ceilf((hi + sc.cut_hi) * sc.inv_bin) + 1.0f, 1e9f);
-        }
-        jl = max(wave_min_i(jl), 0);
-        jh = min(wave_max_i(jh), nb - 1);
+        // support of the echoes in bins, widened by one bin against rounding: it
+        // starts at the earliest echo (tmin) and ends at the latest (the largest
+        // offset); the window starts there, rounded down to a multiple of 4 bins
+        // (the bins it adds are computed like the others)
+        const float lo = (float)(tmin - t0);
+        const float hi = wave_max_f(mine ? (float)rel : -INFINITY);
+        const int jl = (int)fminf(fmaxf(floorf((lo - sc.cut_lo) * sc.inv_bin) - 1.0f, 0.0f), 1e9f);
+        const int jh = (int)fminf(fmaxf(ceilf((hi + sc.cut_hi) * sc.inv_bin) + 1.0f, -1.0f), (float)(nb - 1));
         if (jl <= jh) {
-            jb = jl;
-            nch = ((jh - jl) >> 6) + 1;
+            jb = jl & ~3;
+            nch = ((jh - jb) >> 6) + 1;
         }
     }
     float wf[MAXCH];
@@ -414,10 +413,21 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
         if (out.wf) {
             float* row = out.wf + p * nb;
             const int jend = jb + nch * kWave;
+            if ((nb & 3) == 0 && (reinterpret_cast<unsigned long long>(out.wf) & 15) == 0) {
+                // zeros outside the chunks, four bins per lane (jb and jend are
+                // multiples of 4, and the row start is 16-byte aligned)
+                float4* row4 = reinterpret_cast<float4*>(row);
 #pragma unroll
-            for (int m = 0; m < MAXCH; ++m) {
-                const int j = m * kWave + lane;
-                if (j < nb && (j < jb || j >= jend)) row[j] = 0.0f;
+                for (int m = 0; m < (MAXCH + 3) / 4; ++m) {
+                    const int g = m * kWave + lane, j = 4 * g;
+                    if (j < nb && (j < jb || j >= jend)) row4[g] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < MAXCH; ++m) {
+                    const int j = m * kWave + lane;
+                    if (j < nb && (j < jb || j >= jend)) row[j] = 0.0f;
+                }
             }
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
