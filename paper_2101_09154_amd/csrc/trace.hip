@@ -314,6 +314,16 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
     R = h.t;
 }
 
+// Waveform rows are written once and not read back by the kernel: streaming
+// (non-temporal) stores keep them from displacing the scene in the caches.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void stream_store(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void stream_zero4(float4* p)
+{
+    const vf4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+    __builtin_nontemporal_store(z, reinterpret_cast<vf4*>(p));
+}
+
 // Contribution of one echo to a bin: offsets are taken from the centre bin jc of
 // the bin's chunk, so x = (l - 32) bin (lane l) and the echo offset
 // r = (tau - t0) - jc bin (FP64, split into FP32 hi + lo) are both small, and
@@ -420,19 +430,19 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
 #pragma unroll
                 for (int m = 0; m < (MAXCH + 3) / 4; ++m) {
                     const int g = m * kWave + lane, j = 4 * g;
-                    if (j < nb && (j < jb || j >= jend)) row4[g] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (j < nb && (j < jb || j >= jend)) stream_zero4(&row4[g]);
                 }
             } else {
 #pragma unroll
                 for (int m = 0; m < MAXCH; ++m) {
                     const int j = m * kWave + lane;
-                    if (j < nb && (j < jb || j >= jend)) row[j] = 0.0f;
+                    if (j < nb && (j < jb || j >= jend)) stream_store(&row[j], 0.0f);
                 }
             }
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
                 const int j = jb + c * kWave + lane;
-                if (c < nch && j < nb) row[j] = wf[c];
+                if (c < nch && j < nb) stream_store(&row[j], wf[c]);
             }
         }
         if (lane == 0 && out.t0) out.t0[p] = t0;
