@@ -179,6 +179,7 @@ struct vls_scene_s {
     ~vls_scene_s()
     {
         (void)hipFree(b.nodes);
+        (void)hipFree(b.nodes4);
         (void)hipFree(b.tris);
         (void)hipFree(b.refl);
         (void)hipFree(b.verts);
@@ -270,6 +271,7 @@ SceneDev scene_dev(vls_scene sc)
 {
     SceneDev s;
     s.nodes = sc->b.nodes;
+    s.nodes4 = sc->b.nodes4;
     s.tris = sc->b.tris;
     s.refl = sc->b.refl;
     s.bounds = sc->b.bounds;
@@ -598,6 +600,7 @@ vls_status vls_scene_create(vls_context ctx, const vls_mesh_desc* mesh, void* st
             return hipMalloc(p, n);
         };
         VLS_HIP(alloc((void**)&b.nodes, 64 * (size_t)ni), "scene alloc");
+        VLS_HIP(alloc((void**)&b.nodes4, 128 * (size_t)ni), "scene alloc");
         VLS_HIP(alloc((void**)&b.tris, 48 * (size_t)nt1), "scene alloc");
         VLS_HIP(alloc((void**)&b.refl, 4 * (size_t)nt1), "scene alloc");
         VLS_HIP(alloc((void**)&b.verts, 12 * (size_t)nv1), "scene alloc");

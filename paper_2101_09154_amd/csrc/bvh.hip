@@ -337,6 +337,44 @@ __global__ __launch_bounds__(256) void k_refit(const float4* __restrict__ recs, 
     }
 }
 
+// Four-wide view of the binary tree for the cone pass.  Record b (8 x float4)
+// holds, for binary node b, the boxes and refs of its grandchildren -- or of a
+// child itself when that child is a leaf -- so one fetch covers two levels:
+// words [4q .. 4q+3] of float4 q = 0..5 are lo.x, lo.y, lo.z, hi.x, hi.y, hi.z of
+// slots 0..3; float4 6 holds the four refs as int bits (>= 0: record of an
+// internal node, < 0: leaf ~ref, kEmpty4: unused slot).  A child's box contains
+// its children's boxes, so testing the grandchildren alone loses nothing.
+__global__ __launch_bounds__(256) void k_collapse4(const float4* __restrict__ nodes, long long n_int,
+                                                   float4* __restrict__ nodes4)
+{
+    long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_int) return;
+    const float* w = reinterpret_cast<const float*>(nodes + 4 * b);
+    float box[6][4];
+    int ref[4];
+    for (int side = 0; side < 2; ++side) {
+        const int c = __float_as_int(w[12 + side]);
+        const float* cb = w + 6 * side;
+        if (c >= 0 && c < n_int) {
+            const float* wc = reinterpret_cast<const float*>(nodes + 4 * (long long)c);
+            for (int h = 0; h < 2; ++h) {
+                for (int q = 0; q < 6; ++q) box[q][2 * side + h] = wc[6 * h + q];
+                ref[2 * side + h] = __float_as_int(wc[12 + h]);
+            }
+        } else {
+            for (int q = 0; q < 6; ++q) box[q][2 * side] = cb[q];
+            ref[2 * side] = c;
+            for (int q = 0; q < 3; ++q) box[q][2 * side + 1] = INFINITY;
+            for (int q = 3; q < 6; ++q) box[q][2 * side + 1] = -INFINITY;
+            ref[2 * side + 1] = kEmpty4;
+        }
+    }
+    float4* o = nodes4 + 8 * b;
+    for (int q = 0; q < 6; ++q) o[q] = make_float4(box[q][0], box[q][1], box[q][2], box[q][3]);
+    o[6] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]), __int_as_float(ref[3]));
+    o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 __global__ __launch_bounds__(256) void k_depth(const int32_t* __restrict__ leaf_parent,
                                                const int32_t* __restrict__ node_parent, long long n,
                                                unsigned* __restrict__ depth)
@@ -451,6 +489,9 @@ hipError_t bvh_refit(BvhBuffers& b, hipStream_t stream)
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n - 1, 256)), dim3(256), 0, stream, b.flags, n - 1, 0);
         hipLaunchKernelGGL(k_refit, dim3(grid_for(n, 256)), dim3(256), 0, stream, b.tris, n, b.nodes, b.leaf_parent,
                            b.node_parent, b.flags);
+        if (b.nodes4)
+            hipLaunchKernelGGL(k_collapse4, dim3(grid_for(n - 1, 256)), dim3(256), 0, stream, b.nodes, n - 1,
+                               b.nodes4);
     }
     return hipGetLastError();
 }

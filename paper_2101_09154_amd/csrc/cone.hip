@@ -193,25 +193,37 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
                 n = -1;
                 busy = false;
             } else if (node >= 0) {
+                // a four-wide record: the node's grandchildren (or leaf children)
                 if (COUNT) ++visits;
-                const float4* nd = scene.nodes + 4 * node;
-                float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
-                float tl, tr;
-                bool hl = cone_box<MIXED>(c, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl);
-                bool hr = cone_box<MIXED>(c, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr);
-                int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
-                // descend into the near child; with both hit, the far one is pushed
-                const bool lfirst = hl && (!hr || tl <= tr);
-                node = lfirst ? cl : cr;
-                if (hl && hr) {
-                    if (sp - nlow > ring_mask) {
-                        if (nlow < kMaxSpill) spill[nlow] = my[(nlow & ring_mask) * stride];
-                        ++nlow;
+                const float4* nd = scene.nodes4 + 8 * node;
+                const float4 LX = nd[0], LY = nd[1], LZ = nd[2], HX = nd[3], HY = nd[4], HZ = nd[5], RF = nd[6];
+                float t[4];
+                int r[4] = {__float_as_int(RF.x), __float_as_int(RF.y), __float_as_int(RF.z), __float_as_int(RF.w)};
+                t[0] = cone_box<MIXED>(c, LX.x, LY.x, LZ.x, HX.x, HY.x, HZ.x, tcull, t[0]) && r[0] != kEmpty4 ? t[0] : INFINITY;
+                t[1] = cone_box<MIXED>(c, LX.y, LY.y, LZ.y, HX.y, HY.y, HZ.y, tcull, t[1]) && r[1] != kEmpty4 ? t[1] : INFINITY;
+                t[2] = cone_box<MIXED>(c, LX.z, LY.z, LZ.z, HX.z, HY.z, HZ.z, tcull, t[2]) && r[2] != kEmpty4 ? t[2] : INFINITY;
+                t[3] = cone_box<MIXED>(c, LX.w, LY.w, LZ.w, HX.w, HY.w, HZ.w, tcull, t[3]) && r[3] != kEmpty4 ? t[3] : INFINITY;
+                // nearest first: sort the four (distance, ref) pairs, misses (inf) last
+#define VLS_CX(a, b)                                  \
+    if (t[b] < t[a]) {                                \
+        const float tt = t[a]; t[a] = t[b]; t[b] = tt; \
+        const int rr = r[a]; r[a] = r[b]; r[b] = rr;   \
+    }
+                VLS_CX(0, 1) VLS_CX(2, 3) VLS_CX(0, 2) VLS_CX(1, 3) VLS_CX(1, 2)
+#undef VLS_CX
+                node = r[0];
+                pop = !(t[0] < INFINITY);
+                // the others are pushed farthest first, so the nearer ones pop first
+                for (int q = 3; q >= 1; --q) {
+                    if (t[q] < INFINITY) {
+                        if (sp - nlow > ring_mask) {
+                            if (nlow < kMaxSpill) spill[nlow] = my[(nlow & ring_mask) * stride];
+                            ++nlow;
+                        }
+                        my[(sp & ring_mask) * stride] = make_int2(r[q], __float_as_int(t[q]));
+                        ++sp;
                     }
-                    my[(sp & ring_mask) * stride] = make_int2(lfirst ? cr : cl, __float_as_int(lfirst ? tr : tl));
-                    ++sp;
                 }
-                pop = !hl && !hr;
             } else if (n == kCandMax) {  // too many: the subrays traverse on their own
                 n = -1;
                 busy = false;

@@ -13,6 +13,7 @@ constexpr int kWave = 64;                 // CDNA wavefront
 constexpr int kMaxSpill = 112;            // traversal-stack entries per lane beyond the LDS ring
 constexpr int kMaxRing = 32;
 constexpr int kCandMax = 63;             // candidate leaves kept per pulse by the cone pass
+constexpr int kEmpty4 = 0x7fffffff;       // unused slot of a four-wide record
 constexpr int kCandStaged = 16;          // of which the first ones are staged in LDS by the fused kernel
 
 // One scanner as the kernels see it (everything derived on the host in FP64).
@@ -44,6 +45,7 @@ struct ScannerDev {
 // v0.xyz + original triangle index (int bits) | v1.xyz + 0 | v2.xyz + 0.
 struct SceneDev {
     const float4* nodes;
+    const float4* nodes4;   // [n_tri-1][8]: four-wide records (grandchildren of each node)
     const float4* tris;
     const float* refl;      // by original triangle index
     const float* bounds;    // [13]: vertex lo.xyz hi.xyz, centroid lo.xyz hi.xyz, max |coordinate|
@@ -105,6 +107,7 @@ struct LaunchCfg {
 
 struct BvhBuffers {
     float4* nodes = nullptr;      // [max(n_tri-1,1)][4]
+    float4* nodes4 = nullptr;     // [max(n_tri-1,1)][8] four-wide records, rebuilt with every refit
     float4* tris = nullptr;       // [n_tri][3]
     float* refl = nullptr;        // [n_tri]
     float* verts = nullptr;       // [n_vert][3]
