@@ -359,6 +359,12 @@ vls_status check_scene(vls_context ctx, vls_scene scene)
         snprintf(b, sizeof b, "scene depth %d exceeds the traversal stack (%d)", scene->stats.max_depth, limit);
         return fail(VLS_ERR_UNSUPPORTED, b);
     }
+    // the cone pass pushes up to three entries per four-wide level
+    if (ctx->cfg.cone && 3 * ((scene->stats.max_depth + 1) / 2) > kConeRing + kMaxSpill - 1) {
+        char b[128];
+        snprintf(b, sizeof b, "scene depth %d exceeds the cone-pass stack; use cone = 0", scene->stats.max_depth);
+        return fail(VLS_ERR_UNSUPPORTED, b);
+    }
     return VLS_OK;
 }
 

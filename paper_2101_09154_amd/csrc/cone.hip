@@ -273,7 +273,7 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
 }
 
 template <bool COUNT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_cone(SceneDev scene, double tana, PulsesDev pulses, int* __restrict__ cand,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_cone(SceneDev scene, double tana, PulsesDev pulses, int* __restrict__ cand,
                                               long long first, long long count, int ring_mask,
                                               unsigned long long* counts)
 {
@@ -327,8 +327,10 @@ hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& p
     if (count <= 0) return hipSuccess;
     const int block = 64 * cfg.block_waves;
     unsigned grid = (unsigned)((count + block - 1) / block);
-    size_t lds = sizeof(int2) * (size_t)cfg.stack_lds * block;
-    int mask = cfg.stack_lds - 1;
+    // the cone pass keeps its own ring depth: a four-wide visit can push three
+    // entries, and 16 entries per lane still fit 4 wavefronts per SIMD
+    size_t lds = sizeof(int2) * (size_t)kConeRing * block;
+    int mask = kConeRing - 1;
     if (counts)
         hipLaunchKernelGGL(k_cone<true>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, first,
                            count, mask, counts);

@@ -14,6 +14,7 @@ constexpr int kMaxSpill = 112;            // traversal-stack entries per lane be
 constexpr int kMaxRing = 32;
 constexpr int kCandMax = 63;             // candidate leaves kept per pulse by the cone pass
 constexpr int kEmpty4 = 0x7fffffff;       // unused slot of a four-wide record
+constexpr int kConeRing = 16;            // LDS stack entries per lane of the cone pass
 constexpr int kCandStaged = 16;          // of which the first ones are staged in LDS by the fused kernel
 
 // One scanner as the kernels see it (everything derived on the host in FP64).
