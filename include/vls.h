@@ -97,7 +97,10 @@ typedef struct {
     int64_t n_internal_nodes;   /* n_triangles - 1 (binary LBVH, one triangle per leaf)   */
     int64_t device_bytes;       /* bytes of device memory the scene holds                 */
     int32_t max_depth;          /* deepest leaf (root = 0)                                */
-    int32_t max_supported_depth;
+    int32_t max_supported_depth;/* deepest tree the per-subray traversal stack holds (the
+                                   LDS ring plus 112 scratch entries); tracing a deeper
+                                   scene returns VLS_ERR_UNSUPPORTED, and so does a scene
+                                   deeper than 84 with the cone pass on                    */
     float bounds_lo[3];         /* vertex bounds                                          */
     float bounds_hi[3];
     float box_pad;              /* 0: node boxes are exact; traversal pads them per ray    */
@@ -106,7 +109,8 @@ typedef struct {
 
 /* Copies the mesh to the device and builds the acceleration structure: Morton
  * codes of triangle centroids (63 bits), radix sort, Karras (2012) binary
- * radix tree, bottom-up boxes.  Enqueued on `stream`; returns after the build
+ * radix tree, bottom-up boxes, and a four-wide view of the tree (each node's
+ * grandchildren) for the cone pass.  Enqueued on `stream`; returns after the build
  * has finished (the call synchronises `stream`).  Input arrays are not kept. */
 vls_status vls_scene_create(vls_context ctx, const vls_mesh_desc* mesh, void* stream, vls_scene* out);
 
