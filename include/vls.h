@@ -345,8 +345,9 @@ vls_status vls_cone_candidates(vls_context ctx, vls_scene scene, const vls_scann
 
 /* Kernel timing for measurement (no passage of the paper: it instruments the
  * calls above).  While enabled, every eager vls_simulate call records a pair of
- * HIP events on its stream around the cone pass and around the fused (or
- * persistent) kernel; nothing is recorded while the stream is being captured
+ * HIP events on its stream around the cone pass, around the packet walk of the
+ * pulses whose candidate list overflowed, and around the fused (or persistent)
+ * kernel; nothing is recorded while the stream is being captured
  * into a graph.  vls_profile_read waits for the recorded events, returns the
  * summed elapsed times and launch counts since the previous read, and clears
  * them.  The events are owned by the context.  Errors: VLS_ERR_INVALID_ARG for
@@ -356,6 +357,9 @@ typedef struct {
     double fused_ms;         /* summed over the recorded fused kernels        */
     int64_t cone_launches;
     int64_t fused_launches;
+    double packet_ms;        /* summed over the recorded packet walks (pulses
+                                whose candidate list overflowed)              */
+    int64_t packet_launches;
 } vls_profile;
 vls_status vls_profile_enable(vls_context ctx, int32_t enable);
 vls_status vls_profile_read(vls_context ctx, vls_profile* out);

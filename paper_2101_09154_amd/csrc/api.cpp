@@ -156,11 +156,11 @@ struct vls_context_s {
     // kernel timing (vls_profile_*): event pairs recorded around the cone pass
     // and the fused kernel of eager vls_simulate calls, and a pool of spares
     bool prof = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_cone, prof_fused, prof_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_cone, prof_packets, prof_fused, prof_pool;
     ~vls_context_s()
     {
         (void)hipSetDevice(device);
-        for (auto* v : {&prof_cone, &prof_fused, &prof_pool})
+        for (auto* v : {&prof_cone, &prof_packets, &prof_fused, &prof_pool})
             for (auto& e : *v) {
                 (void)hipEventDestroy(e.first);
                 (void)hipEventDestroy(e.second);
@@ -469,7 +469,7 @@ vls_status cone_workspace(vls_context ctx, long long n)
     (void)hipFree(ctx->cand);
     ctx->cand = nullptr;
     ctx->cand_pulses = 0;
-    VLS_HIP(hipMalloc(&ctx->cand, sizeof(int) * (size_t)(kCandMax + 1) * (size_t)n), "candidate workspace");
+    VLS_HIP(hipMalloc(&ctx->cand, sizeof(int) * cone_ws_ints(n)), "candidate workspace");
     ctx->cand_pulses = n;
     return VLS_OK;
 }
@@ -716,9 +716,17 @@ vls_status vls_trace(vls_context ctx, vls_scene scene, const vls_scanner_desc* s
         PulsesDev pd = pulses_dev(pulses);
         SceneDev sd = scene_dev(scene);
         if (ctx->cfg.cone && pulses->n_pulses > 0) {
-            hipError_t e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, pulses->n_pulses, ctx->cfg, nullptr,
+            vls_context_s::Batch* bt = nullptr;
+            if (pr.seg_sc.size() > 1 && (st = batch_tables(ctx, pr, bt)) != VLS_OK) return st;
+            const long long n = pulses->n_pulses;
+            int* list = cone_ws_list(ctx->cand, n);
+            unsigned long long* ctr = cone_ws_ctr(ctx->cand, n);
+            hipError_t e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, n, ctx->cfg, nullptr, list, ctr,
                                        (hipStream_t)stream);
             if (e != hipSuccess) return hip_fail(e, "cone launch");
+            e = launch_packets(sd, pr.sc[0], bt ? bt->bd : BatchDev{}, pd, ctx->cand, list, ctr, 0,
+                               (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "packet launch");
             pd.cand = ctx->cand;
         }
         for (size_t s = 0; s + 1 < pr.off.size(); ++s) {
@@ -839,9 +847,17 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
     std::pair<hipEvent_t, hipEvent_t> ev{};
     if (ctx->cfg.cone) {
         if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
-        e = launch_cone(sd, max_tan(pr), pd, cand, 0, pulses->n_pulses, ctx->cfg, nullptr, s);
+        const long long n = pulses->n_pulses;
+        int* list = cone_ws_list(cand, n);
+        unsigned long long* ctr = cone_ws_ctr(cand, n);
+        e = launch_cone(sd, max_tan(pr), pd, cand, 0, n, ctx->cfg, nullptr, list, ctr, s);
         if (e != hipSuccess) return hip_fail(e, "cone launch");
         if (prof && (e = prof_end(ctx, s, ev, ctx->prof_cone)) != hipSuccess) return hip_fail(e, "timing event");
+        // pulses whose candidate list overflowed: one wavefront walks each pulse's subrays together
+        if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
+        e = launch_packets(sd, pr.sc[0], bt ? bt->bd : BatchDev{}, pd, cand, list, ctr, 0, s);
+        if (e != hipSuccess) return hip_fail(e, "packet launch");
+        if (prof && (e = prof_end(ctx, s, ev, ctx->prof_packets)) != hipSuccess) return hip_fail(e, "timing event");
         pd.cand = cand;
     }
     if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
@@ -891,7 +907,7 @@ vls_status vls_trace_counts(vls_context ctx, vls_scene scene, const vls_scanner_
             return st;
         }
         if (e == hipSuccess && ctx->cfg.cone && pulses->n_pulses > 0) {
-            e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, pulses->n_pulses, ctx->cfg, dc, s);
+            e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, pulses->n_pulses, ctx->cfg, dc, nullptr, nullptr, s);
             pd.cand = ctx->cand;
         }
         for (size_t g = 0; e == hipSuccess && g + 1 < pr.off.size(); ++g)
@@ -948,8 +964,7 @@ vls_status vls_graph_capture(vls_context ctx, vls_scene scene, const vls_scanner
         g->ctx = ctx;
         // the graph owns its candidate workspace: the context's may be reallocated later
         if (ctx->cfg.cone && pulses->n_pulses > 0)
-            VLS_HIP(hipMalloc(&g->cand, sizeof(int) * (size_t)(kCandMax + 1) * (size_t)pulses->n_pulses),
-                    "graph workspace");
+            VLS_HIP(hipMalloc(&g->cand, sizeof(int) * cone_ws_ints(pulses->n_pulses)), "graph workspace");
         VLS_HIP(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking), "capture stream");
         VLS_HIP(hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal), "begin capture");
         st = simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, g->cs, g->cand);
@@ -1139,7 +1154,7 @@ vls_status vls_cone_candidates(vls_context ctx, vls_scene scene, const vls_scann
         if (!aligned(candidates, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned candidates");
         hipStream_t s = (hipStream_t)stream;
         hipError_t e = launch_cone(scene_dev(scene), max_tan(pr), pulses_dev(pulses), candidates, 0, pulses->n_pulses,
-                                   ctx->cfg, nullptr, s);
+                                   ctx->cfg, nullptr, nullptr, nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "cone launch");
         if (pulses->n_pulses > 0) {
             e = launch_leaf_to_orig(scene->b.leaf_tri, candidates, pulses->n_pulses, s);
@@ -1185,6 +1200,7 @@ vls_status vls_profile_read(vls_context ctx, vls_profile* out)
         v.clear();
     };
     drain(ctx->prof_cone, out->cone_ms, out->cone_launches);
+    drain(ctx->prof_packets, out->packet_ms, out->packet_launches);
     drain(ctx->prof_fused, out->fused_ms, out->fused_launches);
     return st;
 }

@@ -275,7 +275,7 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
 template <bool COUNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_cone(SceneDev scene, double tana, PulsesDev pulses, int* __restrict__ cand,
                                               long long first, long long count, int ring_mask,
-                                              unsigned long long* counts)
+                                              unsigned long long* counts, int* ovf_list, unsigned long long* ovf_ctr)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -295,6 +295,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (ok) n = cone_walk<COUNT, true>(scene, c, out, my, ring_mask, visits);
     }
     if (active) out[0] = n;
+    if (ovf_list) {
+        // overflowed pulses go to the list, one counter update per wavefront
+        const unsigned long long m = __ballot(active && n < 0);
+        if (m) {
+            const int lane = threadIdx.x & (kWave - 1);
+            const int leader = __ffsll((long long)m) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(ovf_ctr, (unsigned long long)__popcll(m));
+            const unsigned b_lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)base, leader);
+            const unsigned b_hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(base >> 32), leader);
+            const unsigned long long b = ((unsigned long long)b_hi << 32) | b_lo;
+            if (active && n < 0) ovf_list[b + dev::lanes_below(m)] = (int)i;
+        }
+    }
     if (COUNT) {
         unsigned long long v = (unsigned long long)visits;
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -322,8 +336,13 @@ hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_p
 }
 
 hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
-                       long long count, const LaunchCfg& cfg, unsigned long long* counts, hipStream_t stream)
+                       long long count, const LaunchCfg& cfg, unsigned long long* counts, int* ovf_list,
+                       unsigned long long* ovf_ctr, hipStream_t stream)
 {
+    if (ovf_list) {
+        hipError_t e = launch_fill_u64(ovf_ctr, 2, 0ull, stream);
+        if (e != hipSuccess) return e;
+    }
     if (count <= 0) return hipSuccess;
     const int block = 64 * cfg.block_waves;
     unsigned grid = (unsigned)((count + block - 1) / block);
@@ -333,10 +352,10 @@ hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& p
     int mask = kConeRing - 1;
     if (counts)
         hipLaunchKernelGGL(k_cone<true>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, first,
-                           count, mask, counts);
+                           count, mask, counts, ovf_list, ovf_ctr);
     else
         hipLaunchKernelGGL(k_cone<false>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, first,
-                           count, mask, counts);
+                           count, mask, counts, ovf_list, ovf_ctr);
     return hipGetLastError();
 }
 

@@ -227,6 +227,86 @@ __device__ __forceinline__ Hit traverse(const SceneDev& scene, const Ray& r, int
     return h;
 }
 
+// Closest hits of the subrays of one pulse (the lanes with `on`), found by one
+// walk of the wavefront over the four-wide records: the pulse's subrays are
+// nearly parallel, so they share most of their path.  Each lane tests the
+// children's boxes with its own padded FP32 ray and its own closest-hit
+// distance; a child is entered when any lane's test passes, nearest first by
+// the first lane's entry distance; every lane tests the leaves with its own
+// FP64 watertight test.  Control flow and the stack are uniform: the stack sits
+// in the wavefront's part of the LDS ring (entry e at word (e / 64) * stride +
+// e % 64 of the wavefront's base), `cap` entries.  The host guarantees that
+// 3 * ceil(depth / 2) <= cap.
+template <bool COUNT>
+__device__ __forceinline__ void packet_walk(const SceneDev& scene, const Ray& r, bool on, Hit& h,
+                                            int* __restrict__ ring, int cap, int& visits, int& tests)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int stride = blockDim.x;
+    int* st = ring + (threadIdx.x - lane);
+    RayBox rb;
+    setup_box(r, scene.bounds[12], rb);
+    float tcull = INFINITY;
+    const unsigned long long onm = __ballot(on);
+    const int leader = __ffsll((long long)onm) - 1;
+    const int n_int = scene.n_tri - 1;
+    int node = scene.root;
+    int sp = 0;
+    for (int guard = 2 * scene.n_tri + 64; guard > 0; --guard) {
+        if (node >= 0) {
+            if (node >= n_int) break;  // only a corrupted structure gets here
+            if (COUNT && on) ++visits;
+            const float4* nd = scene.nodes4 + 8 * node;
+            const float4 LX = nd[0], LY = nd[1], LZ = nd[2], HX = nd[3], HY = nd[4], HZ = nd[5], RF = nd[6];
+            int rf[4] = {__float_as_int(RF.x), __float_as_int(RF.y), __float_as_int(RF.z), __float_as_int(RF.w)};
+            float t[4];
+            bool hit[4];
+            hit[0] = on && rf[0] != kEmpty4 && box_hit(rb, LX.x, LY.x, LZ.x, HX.x, HY.x, HZ.x, tcull, t[0]);
+            hit[1] = on && rf[1] != kEmpty4 && box_hit(rb, LX.y, LY.y, LZ.y, HX.y, HY.y, HZ.y, tcull, t[1]);
+            hit[2] = on && rf[2] != kEmpty4 && box_hit(rb, LX.z, LY.z, LZ.z, HX.z, HY.z, HZ.z, tcull, t[2]);
+            hit[3] = on && rf[3] != kEmpty4 && box_hit(rb, LX.w, LY.w, LZ.w, HX.w, HY.w, HZ.w, tcull, t[3]);
+            // uniform keys: the leader's entry distance, 3e38 when only other
+            // lanes enter the child, inf when none does
+            float key[4];
+            for (int i = 0; i < 4; ++i) {
+                const float lt = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hit[i] ? t[i] : 3e38f), leader));
+                key[i] = __ballot(hit[i]) ? lt : INFINITY;
+            }
+#define VLS_CX(a, b)                                            \
+    if (key[b] < key[a]) {                                      \
+        const float kt = key[a]; key[a] = key[b]; key[b] = kt; \
+        const int rr = rf[a]; rf[a] = rf[b]; rf[b] = rr;       \
+    }
+            VLS_CX(0, 1) VLS_CX(2, 3) VLS_CX(0, 2) VLS_CX(1, 3) VLS_CX(1, 2)
+#undef VLS_CX
+            for (int q = 3; q >= 1; --q) {
+                if (key[q] < INFINITY && sp < cap) {
+                    if (lane == 0) st[(sp >> 6) * stride + (sp & 63)] = rf[q];
+                    ++sp;
+                }
+            }
+            if (key[0] < INFINITY) {
+                node = rf[0];
+                continue;
+            }
+        } else {
+            if (~node >= scene.n_tri) break;  // only a corrupted structure gets here
+            if (on) {
+                if (COUNT) ++tests;
+                if (leaf_test(r, scene.tris, ~node, h)) {
+                    // boxes beyond the closest hit so far cannot hold a closer one
+                    float tf = (float)h.t;
+                    if ((double)tf < h.t) tf = nextafterf(tf, INFINITY);
+                    tcull = tf;
+                }
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        node = __builtin_amdgcn_readfirstlane(st[(sp >> 6) * stride + (sp & 63)]);
+    }
+}
+
 // Incidence and power of the chosen triangle (Sec. 5.2, Eq. 7) in FP32, from
 // its translated FP64 vertices: cos = |d . n| / |n|, P = C w rho cos / R^2.
 __device__ __forceinline__ void shade(const Ray& r, const double* a, const double* b, const double* c, double t,
@@ -297,10 +377,21 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
             }
         }
     } else {
-        if (nc >= 0) {
-            const int* cand = pulses.cand + p * (kCandMax + 1);
-            for (int i = 0; i < nc; ++i) leaf_test(r, scene.tris, cand[1 + i], h);
-            if (COUNT) tests += nc;
+        if (nc >= 0 || nc <= kWalked) {
+            // the pulse's candidates, or the one leaf a packet walk found for
+            // this subray (-1: none)
+            const int* ids = pulses.cand + p * (kCandMax + 1) + 1;
+            int cnt = nc, last = -1;
+            if (nc <= kWalked) {
+                cnt = 1;
+                if (k < kCandMax) ids += k;
+                else last = kWalked - 1 - nc;
+            }
+            for (int i = 0; i < cnt; ++i) {
+                const int li = last >= 0 ? last : ids[i];
+                if (li >= 0 && li < scene.n_tri) leaf_test(r, scene.tris, li, h);
+            }
+            if (COUNT) tests += cnt;
         } else {
             h = traverse<COUNT>(scene, r, ring, ring_mask, visits, tests);
         }
@@ -574,8 +665,8 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     int visits = 0, tests = 0;
     if (active) {
         long long p = first + pl;
-        trace_lane<MODE == 2>(scene, sc, pulses, p, k, pl, r, ray_ok, staged, rec, ring, ring_mask, tri, R, cs, P, visits,
-                              tests);
+        trace_lane<MODE == 2>(scene, sc, pulses, p, k, pl, r, ray_ok, staged, rec, ring, ring_mask, tri, R, cs, P,
+                              visits, tests);
         long long o = p * out.sub_stride + k;
         if (out.sub_tri) out.sub_tri[o] = tri;
         if (out.sub_range) out.sub_range[o] = R;
@@ -708,6 +799,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     }
 }
 
+// Pulses with more candidates than a list holds: one wavefront per pulse walks
+// the tree with all of the pulse's subrays as a packet and writes each subray's
+// closest leaf (or -1) into the pulse's candidate row, with a count word of
+// kWalked or below; the fused kernel then tests that one leaf per subray.
+// `list` holds the pulses (indices from `first`) and ctr[0] their number, both
+// written by the cone pass; past one pulse per wavefront of the grid, the
+// wavefronts take pulses from ctr[1] until the list is done.  Scanners: sc0, or per segment of `batch` when batch.n_seg > 0.
+// The stack holds kPacketCap entries: three per four-wide level, which the
+// scene check bounds the same way as the cone pass's stack.
+__global__ __launch_bounds__(256) void k_packets(SceneDev scene, ScannerDev sc0, BatchDev batch, PulsesDev pulses,
+                                                 int* __restrict__ cand, const int* __restrict__ list,
+                                                 unsigned long long* ctr, long long first)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & (kWave - 1);
+    int* stack = reinterpret_cast<int*>(smem);  // kPacketCap entries per wavefront, interleaved
+    const unsigned long long n = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the first pulse of each wavefront is its index in the grid; later ones come
+    // from the counter, so wavefronts without work never touch it
+    const unsigned long long n_waves = (unsigned long long)gridDim.x * (blockDim.x / kWave);
+    unsigned long long i = (unsigned long long)blockIdx.x * (blockDim.x / kWave) +
+                           (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    int visits = 0, tests = 0;
+    while (i < n) {
+        const long long p = first + list[i];
+        const ScannerDev* scp = &sc0;
+        if (batch.n_seg > 0) {
+            int lo = 0, hi = batch.n_seg - 1;
+            while (lo < hi) {  // last segment whose first pulse <= p
+                const int mid = (lo + hi + 1) >> 1;
+                if (batch.pulse_off[mid] <= p) lo = mid;
+                else hi = mid - 1;
+            }
+            scp = batch.scanners + batch.seg_scanner[lo];
+        }
+        const int S = scp->S;
+        Ray r;
+        const bool on = lane < S && setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, scp->pattern + 5 * lane, r);
+        Hit h;
+        h.t = INFINITY;
+        h.leaf = -1;
+        h.orig = 0x7fffffff;
+        if (__ballot(on)) packet_walk<false>(scene, r, on, h, stack, kPacketCap, visits, tests);
+        // the row holds kCandMax leaves; with 64 subrays the last one is folded
+        // into the count word: kWalked - 1 - leaf (kWalked itself when it is -1)
+        int* row = cand + p * (kCandMax + 1);
+        const int last = __builtin_amdgcn_readlane(h.leaf, kWave - 1);
+        if (lane < S && lane < kCandMax) row[1 + lane] = h.leaf;
+        if (lane == 0) row[0] = kWalked - 1 - (S > kCandMax ? last : -1);
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(ctr + 1, 1ull);
+        const unsigned t_lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)t);
+        const unsigned t_hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(t >> 32));
+        i = n_waves + (((unsigned long long)t_hi << 32) | t_lo);
+    }
+}
+
 inline size_t sim_lds_bytes(int block, int ring, int wl_bytes)
 {
     return (size_t)wl_bytes * (block / kWave) + sizeof(int) * (size_t)ring * block;
@@ -734,6 +882,24 @@ hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const Pu
     else if (sc.n_bins <= 512) VLS_SIM_LAUNCH(8, 1);
     else VLS_SIM_LAUNCH(16, 1);
 #undef VLS_SIM_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_packets(const SceneDev& scene, const ScannerDev& sc0, const BatchDev& batch, const PulsesDev& pulses,
+                          int* cand, const int* ovf_list, unsigned long long* ovf_ctr, long long first,
+                          hipStream_t stream)
+{
+    if (scene.n_tri <= 0) return hipSuccess;
+    // a fixed grid: the wavefronts find the number of pulses to walk on the device
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    const int block = 4 * kWave;
+    const unsigned grid = (unsigned)(cus > 0 ? 4 * cus : 1024);
+    const size_t lds = sizeof(int) * (size_t)kPacketCap * block / kWave;
+    hipLaunchKernelGGL(k_packets, dim3(grid), dim3(block), lds, stream, scene, sc0, batch, pulses, cand, ovf_list,
+                       ovf_ctr, first);
     return hipGetLastError();
 }
 

@@ -15,6 +15,17 @@ constexpr int kMaxRing = 32;
 constexpr int kCandMax = 63;             // candidate leaves kept per pulse by the cone pass
 constexpr int kEmpty4 = 0x7fffffff;       // unused slot of a four-wide record
 constexpr int kConeRing = 16;            // LDS stack entries per lane of the cone pass
+constexpr int kWalked = -2;              // count word <= kWalked: the row holds one leaf per subray
+constexpr int kPacketCap = 128;          // stack entries of a packet walk (3 per four-wide level)
+
+// Cone-pass workspace for n pulses: candidate rows [n][kCandMax + 1], then the
+// list of pulses that overflowed [n], then two counters (overflow count, work).
+inline size_t cone_ws_ints(long long n) { return (size_t)(kCandMax + 1) * n + n + (n & 1) + 4; }
+inline int* cone_ws_list(int* ws, long long n) { return ws + (size_t)(kCandMax + 1) * n; }
+inline unsigned long long* cone_ws_ctr(int* ws, long long n)
+{
+    return reinterpret_cast<unsigned long long*>(ws + (size_t)(kCandMax + 1) * n + n + (n & 1));
+}
 constexpr int kCandStaged = 16;          // of which the first ones are staged in LDS by the fused kernel
 
 // One scanner as the kernels see it (everything derived on the host in FP64).
@@ -62,7 +73,8 @@ struct PulsesDev {
     const double* t0_in;    // may be null
     long long n;
     const int* cand;        // [n][kCandMax + 1] candidate leaves from the cone pass, or null:
-                            // entry 0 = count (-1 = overflow, use full traversal), then leaf ids
+                            // entry 0 = count (-1 = overflow, use full traversal; <= kWalked:
+                            // one leaf per subray from a packet walk), then leaf ids
 };
 
 struct OutDev {
@@ -142,8 +154,17 @@ hipError_t launch_backward(const SceneDev& scene, const ScannerDev& sc, const Pu
 // Cone pass: pulses [first, first + count), cone slope tan_max (largest over the
 // scanners in use).  Writes cand[p * (kCandMax + 1) ...]; counts (optional)
 // accumulates node visits into counts[1].
+// ovf_list / ovf_ctr (optional): pulses whose list overflows are appended to
+// ovf_list (indices from `first`) and counted in ovf_ctr[0]; both counters are
+// reset first.
 hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
-                       long long count, const LaunchCfg& cfg, unsigned long long* counts, hipStream_t stream);
+                       long long count, const LaunchCfg& cfg, unsigned long long* counts, int* ovf_list,
+                       unsigned long long* ovf_ctr, hipStream_t stream);
+// Packet walks of the overflowed pulses (see k_packets); batch.n_seg == 0: every
+// pulse uses sc0.
+hipError_t launch_packets(const SceneDev& scene, const ScannerDev& sc0, const BatchDev& batch, const PulsesDev& pulses,
+                          int* cand, const int* ovf_list, unsigned long long* ovf_ctr, long long first,
+                          hipStream_t stream);
 // Candidate lists hold leaf indices; rewrite them as original triangle indices.
 hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_pulses, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);

@@ -73,7 +73,7 @@ class LaunchConfig(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("cone_ms", f64), ("fused_ms", f64), ("cone_launches", ctypes.c_int64),
-                ("fused_launches", ctypes.c_int64)]
+                ("fused_launches", ctypes.c_int64), ("packet_ms", f64), ("packet_launches", ctypes.c_int64)]
 
 
 class TuneResult(ctypes.Structure):
@@ -452,8 +452,9 @@ class Context:
         """Summed kernel times (ms) and launch counts since the last read (waits for them)."""
         p = Profile()
         _check(lib().vls_profile_read(self._h, ctypes.byref(p)))
-        return {"cone_ms": p.cone_ms, "fused_ms": p.fused_ms, "cone_launches": int(p.cone_launches),
-                "fused_launches": int(p.fused_launches)}
+        return {"cone_ms": p.cone_ms, "fused_ms": p.fused_ms, "packet_ms": p.packet_ms,
+                "cone_launches": int(p.cone_launches), "fused_launches": int(p.fused_launches),
+                "packet_launches": int(p.packet_launches)}
 
     def trace_counts(self, scene, scanners, origins, directions, *, segment_offsets=None, segment_scanner=None,
                      stream=None):

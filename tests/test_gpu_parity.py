@@ -377,9 +377,10 @@ def test_kernel_timing_events(ctx):
     ctx.profile(False)
     g.close()
     say("kernel timing", p)
-    assert p["cone_launches"] == 2 and p["fused_launches"] == 2
-    assert p["cone_ms"] > 0.0 and p["fused_ms"] > 0.0
-    assert ctx.profile_read() == {"cone_ms": 0.0, "fused_ms": 0.0, "cone_launches": 0, "fused_launches": 0}
+    assert p["cone_launches"] == 2 and p["fused_launches"] == 2 and p["packet_launches"] == 2
+    assert p["cone_ms"] > 0.0 and p["fused_ms"] > 0.0 and p["packet_ms"] > 0.0
+    assert ctx.profile_read() == {"cone_ms": 0.0, "fused_ms": 0.0, "packet_ms": 0.0, "cone_launches": 0,
+                                  "fused_launches": 0, "packet_launches": 0}
     _assert_batch_equal(ref, a, batch, seg_sc, scs, 0)
     _assert_batch_equal(ref, b, batch, seg_sc, scs, 1)
 
@@ -628,6 +629,32 @@ def test_cone_pass_bitwise_on_buildings(ctx):
                 continue
             assert np.array_equal(a, b, equal_nan=True), k
     ctx.set_launch_config()
+
+
+@pytest.mark.parametrize("S", [61, 64])
+def test_packet_walk_bitwise_on_trees(ctx, S):
+    # vegetation overflows many candidate lists: those pulses are walked as
+    # packets (64 subrays: the last subray's leaf sits in the count word); every
+    # output must equal per-subray traversal with the cone pass off
+    mesh = configs.uls_scene()
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    _, pulses, sc = configs.uls_trees(mesh=mesh, strips=2, n_lines=12, per_line=500)
+    sc = dict(sc, n_subrays=S, divergence_rad=1.0e-3)
+    o = _dev(pulses.origins)
+    d = _dev(pulses.directions)
+    cand = ctx.cone_candidates(scene, sc, o, d).cpu().numpy()
+    ovf = (cand[:, 0] < 0).mean()
+    say("packet walk: S", S, "pulses", pulses.n, "overflowed %.3f" % ovf)
+    assert ovf > 0.05
+    res = []
+    for cone in (1, 0):
+        ctx.set_launch_config(cone=cone)
+        r = to_np(ctx.simulate(scene, sc, o, d))
+        r.update({"trace_" + k: v for k, v in to_np(ctx.trace(scene, sc, o, d)).items()})
+        res.append(r)
+    ctx.set_launch_config()
+    for k in res[0]:
+        assert np.array_equal(res[0][k], res[1][k], equal_nan=True), k
 
 
 def test_cone_candidates_contain_every_hit(ctx):
