@@ -3,16 +3,18 @@
 Workload (default): the ALS scene with buildings -- a 1024x1024 fBm terrain at
 0.5 m plus 20,000 box buildings (2,333,058 triangles), 1,000,000 line-scanner
 pulses from 500 m above ground, 31 subrays per pulse, 512 bins of 0.5 ns, up
-to 8 returns.  One step = one fused launch: subrays, traversal, power,
-waveform write and returns for every pulse, inputs resident in HBM.
+to 8 returns.  One step: subrays, traversal, power, waveform write and
+returns for every pulse, inputs resident in HBM.
 
-Prints one JSON line.  A step is two launches: the cone pass (one traversal
-per pulse collecting candidate triangles) and the fused kernel (subray tests,
-power, waveform, returns).  The roofline is reported for the fused kernel, the
-dominant one, with its algorithmic bytes: per pulse 36 B in, the candidate
-count (4 B), 52 B per candidate (its id and its 48 B leaf record) and
-4*n_bins + 8 + 4 + 16*K B out, plus 4 B of reflectance per subray; the cone
-pass is reported beside it with 64 B per node visit.  Node visits and triangle tests are counted by the
+Prints one JSON line.  A step is three launches: the cone pass (one traversal
+per pulse collecting candidate triangles), the packet walk of the pulses whose
+candidate list overflowed (one wavefront per pulse; few on this workload) and
+the fused kernel (subray tests, power, waveform, returns).  The roofline is
+reported for the fused kernel, the dominant one, with its algorithmic bytes:
+per pulse 36 B in, the candidate count (4 B), 52 B per candidate (its id and
+its 48 B leaf record) and 4*n_bins + 8 + 4 + 16*K B out, plus 4 B of
+reflectance per subray; the cone pass is reported beside it with 112 B per
+four-wide record visited.  Record visits and triangle tests are counted by the
 library (vls_trace_counts).
 """
 import argparse
@@ -273,14 +275,16 @@ def main():
     prof = ctx.profile_read()
     ctx.profile(False)
     cone_ms = prof["cone_ms"] / max(prof["cone_launches"], 1)
+    packet_ms = prof["packet_ms"] / max(prof["packet_launches"], 1)
     sim_ms = prof["fused_ms"] / max(prof["fused_launches"], 1)
     per_pulse_io = 36.0 + 4.0 * nb + 8.0 + 4.0 + 16.0 * K
     cand_per_pulse = tests / n_sub   # every subray tests its pulse's candidates
     # fused kernel: pulse in, candidate count and ids and the candidate
     # triangles (48 B each) per pulse, a reflectance per subray, outputs out
     sim_bytes = n * (per_pulse_io + 4.0 + 52.0 * cand_per_pulse) + 4.0 * n_sub
-    # cone pass: 64 B per node visit, 48 B per leaf reached, pulse in, list out
-    cone_bytes = 64.0 * visits + n * (36.0 + 4.0 + 52.0 * cand_per_pulse)
+    # cone pass: 112 B per four-wide record visited (six coordinate rows and the
+    # refs), 48 B per leaf reached, pulse in, list out
+    cone_bytes = 112.0 * visits + n * (36.0 + 4.0 + 52.0 * cand_per_pulse)
     alg_bytes = sim_bytes + cone_bytes
     achieved = sim_bytes / (sim_ms * 1e-3) / 1e9
     # bytes the whole step must move at least once: the scene, pulses in, outputs out
@@ -322,6 +326,7 @@ def main():
                      "source_hash": khash,
                      "cone_pass": {"kernel_ms": cone_ms, "algorithmic_bytes_per_launch": cone_bytes,
                                    "achieved": cone_bytes / (cone_ms * 1e-3) / 1e9},
+                     "packet_walk": {"kernel_ms": packet_ms},
                      "timing": "HIP events recorded by the library on the launch stream around each kernel, "
                                "mean of %d launches" % prof["fused_launches"],
                      "step": {"ms": ms, "algorithmic_bytes": alg_bytes,

@@ -102,8 +102,10 @@ __device__ __forceinline__ double woop_t(const Ray& r, const double* a, const do
     const bool out = (U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0);
     const double det = U + V + W;
     const double T = U * (r.Sz * Az) + V * (r.Sz * Bz) + W * (r.Sz * Cz);
-    const double t = T / det;
-    return (out || det == 0.0) ? -1.0 : t;
+    // the division only where some lane can hit (most candidates miss every lane)
+    double t = -1.0;
+    if (!out && det != 0.0) t = T / det;
+    return t;
 }
 
 // Closest-hit update: smaller t wins, equal t goes to the lower original index.
