@@ -37,10 +37,13 @@ def log(*a):
 
 
 def source_hash():
+    """Hash of the device code (the .hip sources and the headers they include)."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2101_09154_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_2101_09154_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2101_09154_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -326,8 +326,10 @@ typedef struct {
 } vls_tune_result;
 
 /* Times vls_simulate on this batch for launch configurations (block shape,
- * LDS stack depth, pulses per wavefront, persistent grid size) by coordinate
- * descent with HIP events on `stream`, keeps the fastest in `ctx`, and appends
+ * LDS stack depth, pulses per wavefront, persistent grid size, cone pass on or
+ * off) by coordinate descent with HIP events on `stream` (a configuration's
+ * time: the fastest of three pairs of calls after one warm-up call), keeps the
+ * fastest in `ctx`, and appends
  * it to `cache_path` (JSON lines, may be NULL) keyed by scene size, subray
  * counts, bins, pulse count and segments.  A matching cache entry is used
  * without timing.  Writes the outputs as vls_simulate does.  Synchronous. */
