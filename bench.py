@@ -290,8 +290,10 @@ def main():
     cone_bytes = 112.0 * visits + n * (36.0 + 4.0 + 52.0 * cand_per_pulse)
     alg_bytes = sim_bytes + cone_bytes
     achieved = sim_bytes / (sim_ms * 1e-3) / 1e9
-    # bytes the whole step must move at least once: the scene, pulses in, outputs out
-    scene_bytes = 64.0 * max(mesh.n_triangles - 1, 1) + 48.0 * mesh.n_triangles + 4.0 * mesh.n_triangles
+    # bytes the whole step must move at least once: the scene as the step reads it
+    # (112 B of each four-wide record, the leaf records, reflectances), pulses in,
+    # outputs out
+    scene_bytes = 112.0 * max(mesh.n_triangles - 1, 1) + 48.0 * mesh.n_triangles + 4.0 * mesh.n_triangles
     compulsory = scene_bytes + n * per_pulse_io
     khash = source_hash()
     traffic = measured_traffic(khash)
