@@ -109,9 +109,13 @@ typedef struct {
 
 /* Copies the mesh to the device and builds the acceleration structure: Morton
  * codes of triangle centroids (63 bits), radix sort, Karras (2012) binary
- * radix tree, bottom-up boxes, and a four-wide view of the tree (each node's
- * grandchildren) for the cone pass.  Enqueued on `stream`; returns after the build
- * has finished (the call synchronises `stream`).  Input arrays are not kept. */
+ * radix tree, boxes computed one tree depth at a time from the deepest, and a
+ * four-wide view of the tree (each node's grandchildren) for the cone pass.
+ * Enqueued on `stream`; returns after the build has finished (the call
+ * synchronises `stream`).  Input arrays are not kept.  The copied indices and
+ * coordinates are checked on the device first (host or device input alike):
+ * an index outside [0, n_vertices) or a non-finite coordinate returns
+ * VLS_ERR_INVALID_ARG and builds nothing. */
 vls_status vls_scene_create(vls_context ctx, const vls_mesh_desc* mesh, void* stream, vls_scene* out);
 
 /* New vertex positions (same count and triangles): leaf records and node boxes

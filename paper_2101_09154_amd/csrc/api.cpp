@@ -188,7 +188,8 @@ struct vls_scene_s {
         (void)hipFree(b.node_parent);
         (void)hipFree(b.leaf_tri);
         (void)hipFree(b.morton);
-        (void)hipFree(b.flags);
+        (void)hipFree(b.node_depth);
+        (void)hipFree(b.level_order);
         (void)hipFree(b.bounds);
     }
 };
@@ -584,13 +585,6 @@ vls_status vls_scene_create(vls_context ctx, const vls_mesh_desc* mesh, void* st
             return fail(VLS_ERR_INVALID_ARG, "vertices, triangles and reflectance are required");
         if (mesh->memory != VLS_MEM_HOST && mesh->memory != VLS_MEM_DEVICE)
             return fail(VLS_ERR_INVALID_ARG, "memory must be VLS_MEM_HOST or VLS_MEM_DEVICE");
-        if (mesh->memory == VLS_MEM_HOST) {
-            for (int64_t i = 0; i < 3 * nt; ++i)
-                if (mesh->triangles[i] < 0 || mesh->triangles[i] >= nv)
-                    return fail(VLS_ERR_INVALID_ARG, "triangle vertex index out of range");
-            for (int64_t i = 0; i < 3 * nv; ++i)
-                if (!std::isfinite(mesh->vertices[i])) return fail(VLS_ERR_INVALID_ARG, "non-finite vertex");
-        }
         VLS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
         hipStream_t s = (hipStream_t)stream;
         std::unique_ptr<vls_scene_s> sc(new vls_scene_s());
@@ -615,7 +609,8 @@ vls_status vls_scene_create(vls_context ctx, const vls_mesh_desc* mesh, void* st
         VLS_HIP(alloc((void**)&b.node_parent, 4 * (size_t)ni), "scene alloc");
         VLS_HIP(alloc((void**)&b.leaf_tri, 4 * (size_t)nt1), "scene alloc");
         VLS_HIP(alloc((void**)&b.morton, 8 * (size_t)nt1), "scene alloc");
-        VLS_HIP(alloc((void**)&b.flags, 4 * (size_t)ni), "scene alloc");
+        VLS_HIP(alloc((void**)&b.node_depth, 4 * (size_t)ni), "scene alloc");
+        VLS_HIP(alloc((void**)&b.level_order, 4 * (size_t)ni), "scene alloc");
         VLS_HIP(alloc((void**)&b.bounds, 4 * 32), "scene alloc");
         VLS_HIP(hipMemsetAsync(b.bounds, 0, 4 * 32, s), "scene init");
         if (nt > 0) {
@@ -623,6 +618,12 @@ vls_status vls_scene_create(vls_context ctx, const vls_mesh_desc* mesh, void* st
             VLS_HIP(hipMemcpyAsync(b.verts, mesh->vertices, 12 * (size_t)nv, kind, s), "vertex copy");
             VLS_HIP(hipMemcpyAsync(b.tri_idx, mesh->triangles, 12 * (size_t)nt, kind, s), "triangle copy");
             VLS_HIP(hipMemcpyAsync(b.refl, mesh->reflectance, 4 * (size_t)nt, kind, s), "reflectance copy");
+            // indices and coordinates are checked on the device, before the build
+            // reads vertices through the indices
+            unsigned bad = 0;
+            VLS_HIP(mesh_check(b, s, bad), "mesh check");
+            if (bad & 1u) return fail(VLS_ERR_INVALID_ARG, "triangle vertex index out of range");
+            if (bad & 2u) return fail(VLS_ERR_INVALID_ARG, "non-finite vertex");
             std::string err;
             hipError_t e = bvh_build(b, s, err);
             if (e != hipSuccess) return hip_fail(e, err.c_str());

@@ -3,6 +3,7 @@
 // The paper accelerates ray casting with a kD-tree searched recursively on the
 // CPU (Sec. 5.1).  Here the structure is a binary LBVH built entirely on the
 // GPU, one thread per triangle or node:
+//   0. a check of the copied mesh (indices in range, finite coordinates);
 //   1. vertex bounds and centroid bounds (ordered-integer atomics);
 //   2. 63-bit Morton codes of the centroids (21 bits per axis, one cell size);
 //   3. a stable LSD radix sort (8 bits per pass, 4096-key tiles, wave64
@@ -11,11 +12,20 @@
 //      construction of BVHs, octrees, and k-d trees" (equal keys ordered by
 //      their sorted position);
 //   5. leaf records gathered in sorted order (48 B: three vertices + original id);
-//   6. child boxes written bottom-up into each parent, the second child to
-//      arrive continuing upward (device-scope acquire/release counters);
-//   7. the deepest leaf, which bounds the traversal stack.
-// Node boxes are exact FP32 bounds; the traversal pads them per ray.
+//   6. internal nodes grouped by depth (a per-block LDS histogram, then one
+//      global slot grab per block and depth); the deepest internal node's
+//      depth + 1 is the deepest leaf, which bounds the traversal stack;
+//   7. child boxes, one launch per depth, deepest first: a child's box is its
+//      triangle's or the union of the boxes the child holds, written one launch
+//      earlier.  A bottom-up pass with per-node arrival counters needs an
+//      agent-scope release and acquire per node, and on a chip whose L2s are
+//      per XCD those cost far more than the few dozen launches;
+//   8. the four-wide view for the cone pass.
+// Node boxes are exact FP32 bounds; the traversal pads them per ray.  A refit
+// (new vertex positions, same tree) repeats 7 and 8.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include <stdint.h>
 
@@ -303,37 +313,84 @@ __global__ __launch_bounds__(256) void k_leaves(const float* __restrict__ verts,
     if (leaf_tri) leaf_tri[i] = o;
 }
 
-__device__ __forceinline__ float ld_acq(const float* p)
+// Depth of every internal node (steps up to the root), and a histogram of the
+// depths (capped at kMaxLevel, which only a corrupted structure reaches).
+__global__ __launch_bounds__(256) void k_node_depth(const int32_t* __restrict__ node_parent, long long n_int,
+                                                    int32_t* __restrict__ depth, unsigned* __restrict__ hist)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __shared__ unsigned h[kMaxLevel + 1];
+    for (int q = threadIdx.x; q <= kMaxLevel; q += blockDim.x) h[q] = 0;
+    __syncthreads();
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_int) {
+        int d = 0;
+        for (int p = node_parent[i]; p >= 0 && d < kMaxLevel; p = node_parent[p]) ++d;
+        depth[i] = d;
+        atomicAdd(&h[d], 1u);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q <= kMaxLevel; q += blockDim.x)
+        if (h[q]) atomicAdd(&hist[q], h[q]);
 }
 
-// Bottom-up boxes: each leaf writes its box into its parent's slot; the second
-// child to arrive at a parent unions both slots and carries on upward.
-__global__ __launch_bounds__(256) void k_refit(const float4* __restrict__ recs, long long n, float4* nodes,
-                                               const int32_t* __restrict__ leaf_parent,
-                                               const int32_t* __restrict__ node_parent, int32_t* flags)
+// Internal nodes grouped by depth: cursor[d] starts at the first slot of depth
+// d in `order` (the order within a depth does not matter).  Each block counts
+// its nodes per depth in LDS and takes its slots with one global atomic per
+// depth it holds; depths are < n_levels.
+__global__ __launch_bounds__(256) void k_level_scatter(const int32_t* __restrict__ depth, long long n_int,
+                                                       int n_levels, unsigned* __restrict__ cursor,
+                                                       int32_t* __restrict__ order)
+{
+    __shared__ unsigned cnt[kMaxLevel + 1];
+    __shared__ unsigned base[kMaxLevel + 1];
+    for (int q = threadIdx.x; q < n_levels; q += blockDim.x) cnt[q] = 0;
+    __syncthreads();
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int d = -1;
+    unsigned local = 0;
+    if (i < n_int) {
+        d = depth[i];
+        if (d >= 0 && d < n_levels) local = atomicAdd(&cnt[d], 1u);
+        else d = -1;  // only a corrupted structure gets here
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n_levels; q += blockDim.x)
+        if (cnt[q]) base[q] = atomicAdd(&cursor[q], cnt[q]);
+    __syncthreads();
+    if (d >= 0) order[base[d] + local] = (int32_t)i;
+}
+
+// Boxes of one depth of internal nodes: a child's box is its triangle's (leaf)
+// or the union of the two boxes the child node holds, written one launch
+// earlier (children are one level deeper).
+__global__ __launch_bounds__(256) void k_refit_level(const float4* __restrict__ recs, float4* nodes,
+                                                     const int32_t* __restrict__ order, long long count,
+                                                     long long n_int, long long n)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float4 a = recs[3 * i], b = recs[3 * i + 1], c = recs[3 * i + 2];
-    float box[6] = {fminf(fminf(a.x, b.x), c.x), fminf(fminf(a.y, b.y), c.y), fminf(fminf(a.z, b.z), c.z),
-                    fmaxf(fmaxf(a.x, b.x), c.x), fmaxf(fmaxf(a.y, b.y), c.y), fmaxf(fmaxf(a.z, b.z), c.z)};
-    int cur = ~(int)i;
-    int p = leaf_parent[i];
-    for (int guard = 0; p >= 0 && guard < 4096; ++guard) {
-        float* w = node_words(nodes, p);
-        int left = __float_as_int(w[12]);
-        int slot = (left == cur) ? 0 : 6;
-        for (int q = 0; q < 6; ++q)
-            __hip_atomic_store(&w[slot + q], box[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int old = __hip_atomic_fetch_add(&flags[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0) return;
-        int other = 6 - slot;
-        for (int q = 0; q < 3; ++q) box[q] = fminf(box[q], ld_acq(&w[other + q]));
-        for (int q = 3; q < 6; ++q) box[q] = fmaxf(box[q], ld_acq(&w[other + q]));
-        cur = p;
-        p = node_parent[p];
+    if (i >= count) return;
+    const int p = order[i];
+    float* w = node_words(nodes, p);
+    for (int side = 0; side < 2; ++side) {
+        const int c = __float_as_int(w[12 + side]);
+        float box[6];
+        if (c < 0) {
+            const long long li = ~(long long)c;
+            if (li >= n) continue;  // only a corrupted structure gets here
+            const float4 a = recs[3 * li], b = recs[3 * li + 1], d = recs[3 * li + 2];
+            box[0] = fminf(fminf(a.x, b.x), d.x);
+            box[1] = fminf(fminf(a.y, b.y), d.y);
+            box[2] = fminf(fminf(a.z, b.z), d.z);
+            box[3] = fmaxf(fmaxf(a.x, b.x), d.x);
+            box[4] = fmaxf(fmaxf(a.y, b.y), d.y);
+            box[5] = fmaxf(fmaxf(a.z, b.z), d.z);
+        } else {
+            if (c >= n_int) continue;  // only a corrupted structure gets here
+            const float* wc = node_words(nodes, c);
+            for (int q = 0; q < 3; ++q) box[q] = fminf(wc[q], wc[6 + q]);
+            for (int q = 3; q < 6; ++q) box[q] = fmaxf(wc[q], wc[6 + q]);
+        }
+        for (int q = 0; q < 6; ++q) w[6 * side + q] = box[q];
     }
 }
 
@@ -375,19 +432,23 @@ __global__ __launch_bounds__(256) void k_collapse4(const float4* __restrict__ no
     o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-__global__ __launch_bounds__(256) void k_depth(const int32_t* __restrict__ leaf_parent,
-                                               const int32_t* __restrict__ node_parent, long long n,
-                                               unsigned* __restrict__ depth)
+// Checked before anything reads vertices through the indices: bit 0 marks an
+// index outside [0, nv), bit 1 a non-finite vertex coordinate.
+__global__ __launch_bounds__(256) void k_check_mesh(const float* __restrict__ verts, long long nv,
+                                                    const int32_t* __restrict__ tri, long long nt,
+                                                    unsigned* __restrict__ bad)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int p = leaf_parent[i];
-    unsigned d = 0;
-    while (p >= 0 && d < 4096) {
-        ++d;
-        p = node_parent[p];
+    const long long n3 = 3 * (nv > nt ? nv : nt);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n3;
+         i += (long long)gridDim.x * blockDim.x) {
+        unsigned f = 0;
+        if (i < 3 * nt) {
+            const int32_t v = tri[i];
+            if (v < 0 || v >= nv) f |= 1u;
+        }
+        if (i < 3 * nv && !isfinite(verts[i])) f |= 2u;
+        if (f) atomicOr(bad, f);
     }
-    atomicMax(depth, d);
 }
 
 inline unsigned grid_for(long long n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -418,6 +479,20 @@ static hipError_t bounds_pass(BvhBuffers& b, unsigned* ub, hipStream_t stream)
     return hipGetLastError();
 }
 
+hipError_t mesh_check(const BvhBuffers& b, hipStream_t stream, unsigned& bad)
+{
+    bad = 0;
+    if (b.n_tri == 0 && b.n_vert == 0) return hipSuccess;
+    unsigned* flag = reinterpret_cast<unsigned*>(b.bounds + 30);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, flag, 1ll, 0u);
+    const long long n3 = 3 * std::max(b.n_tri, b.n_vert);
+    hipLaunchKernelGGL(k_check_mesh, dim3(std::min(grid_for(n3, 256), 4096u)), dim3(256), 0, stream, b.verts,
+                       (long long)b.n_vert, b.tri_idx, (long long)b.n_tri, flag);
+    VLS_TRY(hipGetLastError());
+    VLS_TRY(hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, stream));
+    return hipStreamSynchronize(stream);
+}
+
 hipError_t bvh_build(BvhBuffers& b, hipStream_t stream, std::string& err)
 {
     const long long n = b.n_tri;
@@ -425,7 +500,8 @@ hipError_t bvh_build(BvhBuffers& b, hipStream_t stream, std::string& err)
     const int n_tiles = (int)((n + kSortTile - 1) / kSortTile);
     unsigned long long* keys2 = nullptr;
     int32_t *vals = nullptr, *vals2 = nullptr;
-    unsigned *hist = nullptr, *ub = nullptr;
+    unsigned *hist = nullptr, *ub = nullptr, *lv = nullptr;
+    std::vector<unsigned> cur;  // level cursors: the copy to the device reads them until the final synchronisation
     hipError_t e = hipSuccess;
     auto fail = [&](hipError_t x, const char* what) {
         err = std::string(what) + ": " + hipGetErrorString(x);
@@ -464,10 +540,37 @@ hipError_t bvh_build(BvhBuffers& b, hipStream_t stream, std::string& err)
         hipLaunchKernelGGL(k_leaves, dim3(grid_for(n, 256)), dim3(256), 0, stream, b.verts, b.tri_idx, vals, n, b.tris,
                            b.leaf_tri);
         if ((e = hipGetLastError()) != hipSuccess) { (void)fail(e, "hierarchy"); break; }
+        b.level_off.assign(1, 0);
+        if (n > 1) {
+            // internal nodes grouped by depth, for the refit's one launch per depth
+            const long long ni = n - 1;
+            if ((e = hipMalloc(&lv, sizeof(unsigned) * 2 * (kMaxLevel + 1))) != hipSuccess) { (void)fail(e, "alloc levels"); break; }
+            hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(kMaxLevel + 1, 256)), dim3(256), 0, stream, lv,
+                               (long long)kMaxLevel + 1, 0u);
+            hipLaunchKernelGGL(k_node_depth, dim3(grid_for(ni, 256)), dim3(256), 0, stream, b.node_parent, ni,
+                               b.node_depth, lv);
+            std::vector<unsigned> h(kMaxLevel + 1);
+            if ((e = hipMemcpyAsync(h.data(), lv, sizeof(unsigned) * h.size(), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+                (e = hipStreamSynchronize(stream)) != hipSuccess) { (void)fail(e, "levels"); break; }
+            int top = kMaxLevel;
+            while (top > 0 && h[top] == 0) --top;
+            cur.assign(top + 1, 0u);
+            b.level_off.assign(top + 2, 0);
+            for (int d = 0; d <= top; ++d) {
+                cur[d] = (unsigned)b.level_off[d];
+                b.level_off[d + 1] = b.level_off[d] + h[d];
+            }
+            if ((e = hipMemcpyAsync(lv + kMaxLevel + 1, cur.data(), sizeof(unsigned) * cur.size(),
+                                    hipMemcpyHostToDevice, stream)) != hipSuccess) { (void)fail(e, "levels"); break; }
+            hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(ni, 256)), dim3(256), 0, stream, b.node_depth, ni,
+                               top + 1, lv + kMaxLevel + 1, b.level_order);
+            if ((e = hipGetLastError()) != hipSuccess) { (void)fail(e, "levels"); break; }
+        }
+        // the deepest leaves hang below the deepest internal nodes
+        const unsigned leaf_depth = n > 1 ? (unsigned)b.level_off.size() - 1 : 0u;
         if ((e = bvh_refit(b, stream)) != hipSuccess) { (void)fail(e, "refit"); break; }
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, stream, reinterpret_cast<unsigned*>(b.bounds + 13), 1ll, 0u);
-        hipLaunchKernelGGL(k_depth, dim3(grid_for(n, 256)), dim3(256), 0, stream, b.leaf_parent, b.node_parent, n,
-                           reinterpret_cast<unsigned*>(b.bounds + 13));
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, stream, reinterpret_cast<unsigned*>(b.bounds + 13), 1ll,
+                           leaf_depth);
         if ((e = hipGetLastError()) != hipSuccess) { (void)fail(e, "depth"); break; }
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) { (void)fail(e, "build"); break; }
     } while (0);
@@ -476,6 +579,7 @@ hipError_t bvh_build(BvhBuffers& b, hipStream_t stream, std::string& err)
     (void)hipFree(vals2);
     (void)hipFree(hist);
     (void)hipFree(ub);
+    (void)hipFree(lv);
     return e;
 }
 
@@ -486,9 +590,13 @@ hipError_t bvh_refit(BvhBuffers& b, hipStream_t stream)
     unsigned* ub = reinterpret_cast<unsigned*>(b.bounds + 16);  // scratch words after the results
     VLS_TRY(bounds_pass(b, ub, stream));
     if (n > 1) {
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n - 1, 256)), dim3(256), 0, stream, b.flags, n - 1, 0);
-        hipLaunchKernelGGL(k_refit, dim3(grid_for(n, 256)), dim3(256), 0, stream, b.tris, n, b.nodes, b.leaf_parent,
-                           b.node_parent, b.flags);
+        // one launch per depth, deepest first (the levels come from the build)
+        for (size_t d = b.level_off.size() - 1; d-- > 0;) {
+            const long long lo = b.level_off[d], cnt = b.level_off[d + 1] - lo;
+            if (cnt > 0)
+                hipLaunchKernelGGL(k_refit_level, dim3(grid_for(cnt, 256)), dim3(256), 0, stream, b.tris, b.nodes,
+                                   b.level_order + lo, cnt, n - 1, n);
+        }
         if (b.nodes4)
             hipLaunchKernelGGL(k_collapse4, dim3(grid_for(n - 1, 256)), dim3(256), 0, stream, b.nodes, n - 1,
                                b.nodes4);

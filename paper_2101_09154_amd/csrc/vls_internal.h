@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 namespace vls {
 
@@ -26,6 +27,7 @@ inline unsigned long long* cone_ws_ctr(int* ws, long long n)
 {
     return reinterpret_cast<unsigned long long*>(ws + (size_t)(kCandMax + 1) * n + n + (n & 1));
 }
+constexpr int kMaxLevel = 4096;          // depth cap of the build's level lists
 constexpr int kCandStaged = 16;          // of which the first ones are staged in LDS by the fused kernel
 
 // One scanner as the kernels see it (everything derived on the host in FP64).
@@ -129,11 +131,16 @@ struct BvhBuffers {
     int32_t* node_parent = nullptr;   // [n_tri-1]
     int32_t* leaf_tri = nullptr;      // [n_tri] original index per leaf
     unsigned long long* morton = nullptr;  // [n_tri] sorted keys
-    int32_t* flags = nullptr;         // [n_tri-1]
+    int32_t* node_depth = nullptr;    // [n_tri-1] steps from the root
+    int32_t* level_order = nullptr;   // [n_tri-1] internal nodes by depth, shallowest first
+    std::vector<long long> level_off; // depth d occupies level_order[level_off[d], level_off[d + 1])
     float* bounds = nullptr;          // [32]: [0..12] as in SceneDev, [13] depth (uint bits), [16..28] scratch
     int64_t n_tri = 0, n_vert = 0;
 };
 
+// Device check of a copied mesh (indices in range, finite vertices): bad gets bit
+// 0 for an index out of range, bit 1 for a non-finite coordinate.  Synchronises.
+hipError_t mesh_check(const BvhBuffers& b, hipStream_t stream, unsigned& bad);
 hipError_t bvh_build(BvhBuffers& b, hipStream_t stream, std::string& err);
 hipError_t bvh_refit(BvhBuffers& b, hipStream_t stream);
 hipError_t bvh_update_vertices(BvhBuffers& b, hipStream_t stream);

@@ -74,11 +74,18 @@ def _tri_soup(n, seed):
     return synth.Mesh(v.astype(np.float32), t.astype(np.int32), rng.uniform(0.1, 0.6, n).astype(np.float32))
 
 
-@pytest.mark.parametrize("which", ["small_tls", "soup"])
+@pytest.mark.parametrize("which", ["small_tls", "soup", "soup_refit"])
 def test_lbvh_invariants(ctx, which):
     mesh = configs.small_tls()[0] if which == "small_tls" else _tri_soup(5000, 3)
     say("lbvh", which, mesh.n_triangles)
     scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    if which == "soup_refit":
+        # new vertex positions keep the tree and refit its boxes level by level
+        rng = np.random.default_rng(11)
+        moved = (mesh.vertices + rng.normal(0.0, 2.0, mesh.vertices.shape)).astype(np.float32)
+        scene.update_vertices(torch.from_numpy(moved).cuda())
+        torch.cuda.synchronize()
+        mesh = synth.Mesh(moved, mesh.triangles, mesh.reflectance)
     nodes, leaf, mort, root = scene.export()
     n = mesh.n_triangles
     assert root == 0
@@ -186,6 +193,28 @@ def test_empty_and_single_triangle(ctx):
     out = ctx.simulate(scene1, sc, z, z.float())
     torch.cuda.synchronize()
     assert out["waveform"].shape == (0, 64)
+
+
+def test_mesh_checked_on_device(ctx):
+    import paper_2101_09154_amd as vp
+    # indices out of range and non-finite coordinates are refused before the
+    # build reads vertices through the indices, for host and device input
+    v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], np.float32)
+    t = np.array([[0, 1, 2], [1, 3, 2]], np.int32)
+    r = np.array([0.5, 0.5], np.float32)
+    for bad_t, bad_v, what in ((np.array([[0, 1, 2], [1, 4, 2]], np.int32), v, "index"),
+                               (np.array([[0, 1, -1], [1, 3, 2]], np.int32), v, "index"),
+                               (t, np.where(np.arange(12).reshape(4, 3) == 7, np.nan, v).astype(np.float32), "vertex")):
+        for dev in (False, True):
+            say("mesh check", what, "device" if dev else "host")
+            args = (bad_v, bad_t, r)
+            if dev:
+                args = tuple(torch.from_numpy(a).cuda() for a in args)
+            with pytest.raises(vp.VlsError, match="out of range" if what == "index" else "non-finite"):
+                ctx.scene(*args)
+    # the context still works
+    scene = ctx.scene(v, t, r)
+    assert scene.stats()["n_triangles"] == 2
 
 
 def test_fixed_window_origin(ctx):
