@@ -406,6 +406,7 @@ PulsesDev pulses_dev(const vls_pulse_batch* p)
     d.dirs = p->directions;
     d.t0_in = p->window_t0_ns;
     d.n = p->n_pulses;
+    d.basis = nullptr;
     d.cand = nullptr;
     return d;
 }
@@ -722,13 +723,15 @@ vls_status vls_trace(vls_context ctx, vls_scene scene, const vls_scanner_desc* s
             const long long n = pulses->n_pulses;
             int* list = cone_ws_list(ctx->cand, n);
             unsigned long long* ctr = cone_ws_ctr(ctx->cand, n);
-            hipError_t e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, n, ctx->cfg, nullptr, list, ctr,
+            double* basis = cone_ws_basis(ctx->cand, n);
+            hipError_t e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, n, ctx->cfg, nullptr, list, ctr, basis,
                                        (hipStream_t)stream);
             if (e != hipSuccess) return hip_fail(e, "cone launch");
             e = launch_packets(sd, pr.sc[0], bt ? bt->bd : BatchDev{}, pd, ctx->cand, list, ctr, 0,
                                (hipStream_t)stream);
             if (e != hipSuccess) return hip_fail(e, "packet launch");
             pd.cand = ctx->cand;
+            pd.basis = basis;
         }
         for (size_t s = 0; s + 1 < pr.off.size(); ++s) {
             hipError_t e = launch_simulate(sd, pr.sc[pr.seg_sc[s]], pd, od, pr.off[s], pr.off[s + 1] - pr.off[s], 0,
@@ -851,7 +854,8 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
         const long long n = pulses->n_pulses;
         int* list = cone_ws_list(cand, n);
         unsigned long long* ctr = cone_ws_ctr(cand, n);
-        e = launch_cone(sd, max_tan(pr), pd, cand, 0, n, ctx->cfg, nullptr, list, ctr, s);
+        double* basis = cone_ws_basis(cand, n);
+        e = launch_cone(sd, max_tan(pr), pd, cand, 0, n, ctx->cfg, nullptr, list, ctr, basis, s);
         if (e != hipSuccess) return hip_fail(e, "cone launch");
         if (prof && (e = prof_end(ctx, s, ev, ctx->prof_cone)) != hipSuccess) return hip_fail(e, "timing event");
         // pulses whose candidate list overflowed: one wavefront walks each pulse's subrays together
@@ -860,6 +864,7 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
         if (e != hipSuccess) return hip_fail(e, "packet launch");
         if (prof && (e = prof_end(ctx, s, ev, ctx->prof_packets)) != hipSuccess) return hip_fail(e, "timing event");
         pd.cand = cand;
+        pd.basis = basis;
     }
     if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
     if (!bt) e = launch_simulate(sd, pr.sc[0], pd, od, 0, pulses->n_pulses, 1, ctx->cfg, s);
@@ -908,8 +913,11 @@ vls_status vls_trace_counts(vls_context ctx, vls_scene scene, const vls_scanner_
             return st;
         }
         if (e == hipSuccess && ctx->cfg.cone && pulses->n_pulses > 0) {
-            e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, pulses->n_pulses, ctx->cfg, dc, nullptr, nullptr, s);
+            double* basis = cone_ws_basis(ctx->cand, pulses->n_pulses);
+            e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, pulses->n_pulses, ctx->cfg, dc, nullptr, nullptr, basis,
+                            s);
             pd.cand = ctx->cand;
+            pd.basis = basis;
         }
         for (size_t g = 0; e == hipSuccess && g + 1 < pr.off.size(); ++g)
             e = launch_simulate(sd, pr.sc[pr.seg_sc[g]], pd, od, pr.off[g], pr.off[g + 1] - pr.off[g], 2, ctx->cfg, s);
@@ -1160,7 +1168,7 @@ vls_status vls_cone_candidates(vls_context ctx, vls_scene scene, const vls_scann
         if (!aligned(candidates, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned candidates");
         hipStream_t s = (hipStream_t)stream;
         hipError_t e = launch_cone(scene_dev(scene), max_tan(pr), pulses_dev(pulses), candidates, 0, pulses->n_pulses,
-                                   ctx->cfg, nullptr, nullptr, nullptr, s);
+                                   ctx->cfg, nullptr, nullptr, nullptr, nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "cone launch");
         if (pulses->n_pulses > 0) {
             e = launch_leaf_to_orig(scene->b.leaf_tri, candidates, pulses->n_pulses, s);

@@ -76,28 +76,51 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ verts,
     if (threadIdx.x < 13) s[threadIdx.x] = (threadIdx.x < 3 || (threadIdx.x >= 6 && threadIdx.x < 9)) ? 0xffffffffu : 0u;
     __syncthreads();
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // per lane: vertex lo/hi, centroid lo/hi, largest |coordinate| (identities
+    // on lanes past the end), reduced over the wavefront before the atomics
+    float r[13];
+    for (int a = 0; a < 3; ++a) {
+        r[a] = INFINITY;
+        r[3 + a] = -INFINITY;
+        r[6 + a] = INFINITY;
+        r[9 + a] = -INFINITY;
+    }
+    r[12] = 0.0f;
     if (i < n_tri) {
         float c[3] = {0.f, 0.f, 0.f};
-        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        float mag = 0.f;
         for (int q = 0; q < 3; ++q) {
             long long v = tri[3 * i + q];
             for (int a = 0; a < 3; ++a) {
                 float x = verts[3 * v + a];
-                lo[a] = fminf(lo[a], x);
-                hi[a] = fmaxf(hi[a], x);
+                r[a] = fminf(r[a], x);
+                r[3 + a] = fmaxf(r[3 + a], x);
                 c[a] += x;
-                mag = fmaxf(mag, fabsf(x));
+                r[12] = fmaxf(r[12], fabsf(x));
             }
         }
         for (int a = 0; a < 3; ++a) {
             c[a] *= (1.0f / 3.0f);
-            atomicMin(&s[a], f2ord(lo[a]));
-            atomicMax(&s[3 + a], f2ord(hi[a]));
-            atomicMin(&s[6 + a], f2ord(c[a]));
-            atomicMax(&s[9 + a], f2ord(c[a]));
+            r[6 + a] = c[a];
+            r[9 + a] = c[a];
         }
-        atomicMax(&s[12], f2ord(mag));
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        for (int a = 0; a < 3; ++a) {
+            r[a] = fminf(r[a], __shfl_xor(r[a], off));
+            r[3 + a] = fmaxf(r[3 + a], __shfl_xor(r[3 + a], off));
+            r[6 + a] = fminf(r[6 + a], __shfl_xor(r[6 + a], off));
+            r[9 + a] = fmaxf(r[9 + a], __shfl_xor(r[9 + a], off));
+        }
+        r[12] = fmaxf(r[12], __shfl_xor(r[12], off));
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&s[a], f2ord(r[a]));
+            atomicMax(&s[3 + a], f2ord(r[3 + a]));
+            atomicMin(&s[6 + a], f2ord(r[6 + a]));
+            atomicMax(&s[9 + a], f2ord(r[9 + a]));
+        }
+        atomicMax(&s[12], f2ord(r[12]));
     }
     __syncthreads();
     if (threadIdx.x < 13) {
@@ -162,27 +185,44 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const unsigned long long*
     hist[(long long)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of `total` counts in one block (sizes here are <= 256 * tiles).
+// Exclusive scan of `total` counts in one block (sizes here are <= 256 * tiles):
+// tiles of 4 * kScanThreads consecutive counts, four per thread, read and
+// written coalesced; wavefront scans by lane shifts, then one scan of the
+// wavefront sums, and a carry from tile to tile.
 __global__ __launch_bounds__(kScanThreads) void k_scan(unsigned* __restrict__ a, long long total)
 {
-    __shared__ unsigned s[kScanThreads];
-    long long chunk = (total + kScanThreads - 1) / kScanThreads;
-    long long b = threadIdx.x * chunk, e = b + chunk < total ? b + chunk : total;
-    unsigned sum = 0;
-    for (long long i = b; i < e; ++i) sum += a[i];
-    s[threadIdx.x] = sum;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        unsigned v = threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
+    constexpr int W = kScanThreads / kWave;
+    __shared__ unsigned wsum[W];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    unsigned carry = 0;
+    for (long long base = 0; base < total; base += 4 * kScanThreads) {
+        const long long i0 = base + 4 * (long long)threadIdx.x;
+        unsigned v[4];
+        for (int q = 0; q < 4; ++q) v[q] = i0 + q < total ? a[i0 + q] : 0u;
+        const unsigned t = v[0] + v[1] + v[2] + v[3];
+        unsigned x = t;  // inclusive scan over the wavefront
+        for (int off = 1; off < kWave; off <<= 1) {
+            const unsigned y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == kWave - 1) wsum[w] = x;
         __syncthreads();
-        s[threadIdx.x] += v;
+        if (w == 0) {
+            unsigned ws = lane < W ? wsum[lane] : 0u;
+            for (int off = 1; off < W; off <<= 1) {
+                const unsigned y = __shfl_up(ws, off);
+                if (lane >= off) ws += y;
+            }
+            if (lane < W) wsum[lane] = ws;
+        }
         __syncthreads();
-    }
-    unsigned run = s[threadIdx.x] - sum;
-    for (long long i = b; i < e; ++i) {
-        unsigned v = a[i];
-        a[i] = run;
-        run += v;
+        unsigned run = carry + (w > 0 ? wsum[w - 1] : 0u) + x - t;
+        for (int q = 0; q < 4; ++q) {
+            if (i0 + q < total) a[i0 + q] = run;
+            run += v[q];
+        }
+        carry += wsum[W - 1];
+        __syncthreads();
     }
 }
 

@@ -42,17 +42,15 @@ struct Cone {
     bool mixed;   // some axis has d_a - k < 0 < d_a + k
 };
 
-__device__ __forceinline__ bool setup_cone(const double* __restrict__ o, const float* __restrict__ d32, double tana,
+// The pulse's cone from its basis (the subrays' own basis, computed the same
+// way; see pulse_basis).
+__device__ __forceinline__ bool setup_cone(const double* __restrict__ o, const dev::Basis& B, double tana,
                                            float scene_mag, Cone& c)
 {
 #pragma clang fp contract(off)
-    double dx = d32[0], dy = d32[1], dz = d32[2];
-    double len = sqrt(dx * dx + dy * dy + dz * dz);
-    if (!(len > 0.0) || !(len < INFINITY)) return false;
-    double n[3] = {dx / len, dy / len, dz / len};
+    const double* n = B.n;
+    const double a = B.a, b = B.b;
     double sgn = copysign(1.0, n[2]);
-    double a = -1.0 / (sgn + n[2]);
-    double b = n[0] * n[1] * a;
     double u[3] = {1.0 + sgn * n[0] * n[0] * a, sgn * b, -sgn * n[0]};
     double v[3] = {b, sgn + n[1] * n[1] * a, -n[1]};
     double omax = 0.0;
@@ -275,7 +273,8 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
 template <bool COUNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_cone(SceneDev scene, double tana, PulsesDev pulses, int* __restrict__ cand,
                                               long long first, long long count, int ring_mask,
-                                              unsigned long long* counts, int* ovf_list, unsigned long long* ovf_ctr)
+                                              unsigned long long* counts, int* ovf_list, unsigned long long* ovf_ctr,
+                                              double* basis_out)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -283,8 +282,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const long long p = first + i;
     int visits = 0;
     Cone c;
-    const bool ok = active && scene.n_tri > 0 &&
-                    setup_cone(pulses.origins + 3 * p, pulses.dirs + 3 * p, tana, scene.bounds[12], c);
+    dev::Basis B;
+    const bool bok = active && dev::pulse_basis(pulses.dirs + 3 * p, B);
+    if (basis_out && active) {
+        // the pulse's basis for the fused kernel (n_x NaN: no valid direction)
+        double* w = basis_out + 5 * p;
+        w[0] = bok ? B.n[0] : (double)NAN;
+        w[1] = bok ? B.n[1] : 0.0;
+        w[2] = bok ? B.n[2] : 0.0;
+        w[3] = bok ? B.a : 0.0;
+        w[4] = bok ? B.b : 0.0;
+    }
+    const bool ok = bok && scene.n_tri > 0 && setup_cone(pulses.origins + 3 * p, B, tana, scene.bounds[12], c);
     int n = 0;
     int* out = cand + p * (kCandMax + 1);
     int2* my = reinterpret_cast<int2*>(smem) + threadIdx.x;
@@ -337,7 +346,7 @@ hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_p
 
 hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
                        long long count, const LaunchCfg& cfg, unsigned long long* counts, int* ovf_list,
-                       unsigned long long* ovf_ctr, hipStream_t stream)
+                       unsigned long long* ovf_ctr, double* basis_out, hipStream_t stream)
 {
     if (ovf_list) {
         hipError_t e = launch_fill_u64(ovf_ctr, 2, 0ull, stream);
@@ -352,10 +361,10 @@ hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& p
     int mask = kConeRing - 1;
     if (counts)
         hipLaunchKernelGGL(k_cone<true>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, first,
-                           count, mask, counts, ovf_list, ovf_ctr);
+                           count, mask, counts, ovf_list, ovf_ctr, basis_out);
     else
         hipLaunchKernelGGL(k_cone<false>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, first,
-                           count, mask, counts, ovf_list, ovf_ctr);
+                           count, mask, counts, ovf_list, ovf_ctr, basis_out);
     return hipGetLastError();
 }
 

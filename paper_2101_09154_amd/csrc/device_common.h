@@ -115,17 +115,41 @@ struct RayBox {
 // Duff et al. 2017 orthonormal basis; FP64 subray direction and shear.
 // FP contraction is off wherever FP64 results decide a hit, so every product
 // and sum is rounded exactly as written.
-__device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const float* __restrict__ d32,
-                                          const double* __restrict__ pat, Ray& r)
+//
+// The pulse's part: the unit axis n and the two scalars a, b from which the
+// basis vectors u, v follow (with s = sign of n_z):
+//   u = (1 + s n_x^2 a, s b, -s n_x),  v = (b, s + n_y^2 a, -n_y).
+// False for a zero or non-finite direction.  The cone pass computes it once
+// per pulse and hands it to the fused kernel in this layout.
+struct Basis {
+    double n[3];
+    double a, b;
+};
+
+__device__ __forceinline__ bool pulse_basis(const float* __restrict__ d32, Basis& B)
 {
 #pragma clang fp contract(off)
     double dx = d32[0], dy = d32[1], dz = d32[2];
     double len = sqrt(dx * dx + dy * dy + dz * dz);
     if (!(len > 0.0) || !(len < INFINITY)) return false;
-    double n[3] = {dx / len, dy / len, dz / len};
+    B.n[0] = dx / len;
+    B.n[1] = dy / len;
+    B.n[2] = dz / len;
+    double sgn = copysign(1.0, B.n[2]);
+    B.a = -1.0 / (sgn + B.n[2]);
+    B.b = B.n[0] * B.n[1] * B.a;
+    return true;
+}
+
+// The subray's part: direction from the pattern entry (cos a, sin a, cos phi,
+// sin phi), dominant axis and shear.  False for a non-finite origin.
+__device__ __forceinline__ bool setup_ray_b(const double* __restrict__ o, const Basis& B,
+                                            const double* __restrict__ pat, Ray& r)
+{
+#pragma clang fp contract(off)
+    const double* n = B.n;
+    const double a = B.a, b = B.b;
     double sgn = copysign(1.0, n[2]);
-    double a = -1.0 / (sgn + n[2]);
-    double b = n[0] * n[1] * a;
     double u[3] = {1.0 + sgn * n[0] * n[0] * a, sgn * b, -sgn * n[0]};
     double v[3] = {b, sgn + n[1] * n[1] * a, -n[1]};
     double ca = pat[0], sa = pat[1], cp = pat[2], sp = pat[3];
@@ -157,6 +181,25 @@ __device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const fl
     r.Sy = ay / az;
     r.Sz = 1.0 / az;
     return true;
+}
+
+__device__ __forceinline__ bool setup_ray(const double* __restrict__ o, const float* __restrict__ d32,
+                                          const double* __restrict__ pat, Ray& r)
+{
+    Basis B;
+    return pulse_basis(d32, B) && setup_ray_b(o, B, pat, r);
+}
+
+// A basis stored by the cone pass ([5] doubles: n, a, b; n_x NaN for a pulse
+// whose direction is zero or non-finite).
+__device__ __forceinline__ bool load_basis(const double* __restrict__ stored, Basis& B)
+{
+    B.n[0] = stored[0];
+    B.n[1] = stored[1];
+    B.n[2] = stored[2];
+    B.a = stored[3];
+    B.b = stored[4];
+    return !isnan(B.n[0]);
 }
 
 // pad covers the FP32 rounding of origin, direction and slab arithmetic

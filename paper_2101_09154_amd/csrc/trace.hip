@@ -641,8 +641,12 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
         P2 = scene.tris[3 * li + 2];
     }
     Ray r;
-    const bool ray_ok = active && setup_ray(pulses.origins + 3 * (first + pl), pulses.dirs + 3 * (first + pl),
-                                            sc.pattern + 5 * k, r);
+    // the pulse's basis comes from the cone pass when it ran (same values)
+    Basis B;
+    const bool ray_ok = active &&
+                        (pulses.basis ? load_basis(pulses.basis + 5 * (first + pl), B)
+                                      : pulse_basis(pulses.dirs + 3 * (first + pl), B)) &&
+                        setup_ray_b(pulses.origins + 3 * (first + pl), B, sc.pattern + 5 * k, r);
     if (staged) {
         if (sc16 < nq) {
             const double* o = pulses.origins + 3 * (first + sq);

@@ -20,12 +20,17 @@ constexpr int kWalked = -2;              // count word <= kWalked: the row holds
 constexpr int kPacketCap = 128;          // stack entries of a packet walk (3 per four-wide level)
 
 // Cone-pass workspace for n pulses: candidate rows [n][kCandMax + 1], then the
-// list of pulses that overflowed [n], then two counters (overflow count, work).
-inline size_t cone_ws_ints(long long n) { return (size_t)(kCandMax + 1) * n + n + (n & 1) + 4; }
+// list of pulses that overflowed [n], then two counters (overflow count, work),
+// then each pulse's basis [n][5] doubles (see dev::Basis).
+inline size_t cone_ws_ints(long long n) { return (size_t)(kCandMax + 1) * n + n + (n & 1) + 4 + 10 * (size_t)n; }
 inline int* cone_ws_list(int* ws, long long n) { return ws + (size_t)(kCandMax + 1) * n; }
 inline unsigned long long* cone_ws_ctr(int* ws, long long n)
 {
     return reinterpret_cast<unsigned long long*>(ws + (size_t)(kCandMax + 1) * n + n + (n & 1));
+}
+inline double* cone_ws_basis(int* ws, long long n)
+{
+    return reinterpret_cast<double*>(ws + (size_t)(kCandMax + 1) * n + n + (n & 1) + 4);
 }
 constexpr int kMaxLevel = 4096;          // depth cap of the build's level lists
 constexpr int kCandStaged = 16;          // of which the first ones are staged in LDS by the fused kernel
@@ -74,6 +79,7 @@ struct PulsesDev {
     const float* dirs;
     const double* t0_in;    // may be null
     long long n;
+    const double* basis;    // [n][5] each pulse's basis from the cone pass (n, a, b), or null
     const int* cand;        // [n][kCandMax + 1] candidate leaves from the cone pass, or null:
                             // entry 0 = count (-1 = overflow, use full traversal; <= kWalked:
                             // one leaf per subray from a packet walk), then leaf ids
@@ -164,9 +170,10 @@ hipError_t launch_backward(const SceneDev& scene, const ScannerDev& sc, const Pu
 // ovf_list / ovf_ctr (optional): pulses whose list overflows are appended to
 // ovf_list (indices from `first`) and counted in ovf_ctr[0]; both counters are
 // reset first.
+// basis_out (optional): each pulse's basis, [p][5] doubles.
 hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
                        long long count, const LaunchCfg& cfg, unsigned long long* counts, int* ovf_list,
-                       unsigned long long* ovf_ctr, hipStream_t stream);
+                       unsigned long long* ovf_ctr, double* basis_out, hipStream_t stream);
 // Packet walks of the overflowed pulses (see k_packets); batch.n_seg == 0: every
 // pulse uses sc0.
 hipError_t launch_packets(const SceneDev& scene, const ScannerDev& sc0, const BatchDev& batch, const PulsesDev& pulses,
