@@ -69,6 +69,9 @@ def lib():
         L.orc_peak_offset.argtypes = [P]
         L.orc_peak_offset.restype = ctypes.c_double
         L.orc_detect_peaks.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, P]
+        L.orc_echo_width_bins.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_double, P]
+        L.orc_echo_width_bins.restype = ctypes.c_double
+        L.orc_echo_width.argtypes = [P, P, ctypes.c_int, P, ctypes.c_int, P]
         L.orc_attribute.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_double]
         L.orc_simulate.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, i64, P] + [P] * 6 + [P] * 7 + [ctypes.c_int]
         L.orc_gradient.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, P, P, P, ctypes.c_int]
@@ -174,6 +177,25 @@ def detect_peaks(wf, thr_abs=0.0, thr_rel=1e-3, K=8):
     bins = np.zeros(64, np.int32)
     n = lib().orc_detect_peaks(_ptr(wf), wf.size, float(thr_abs), float(thr_rel), int(K), _ptr(bins))
     return bins[:n].copy()
+
+
+def echo_width_bins(wf, j, s0):
+    """Gaussian fit to the lobe of the return at bin j (Sec. 3.4 echo width):
+    (width in bins or NaN, fitted (A, mu, s))."""
+    wf = np.ascontiguousarray(wf, dtype=np.float64)
+    p = np.zeros(3)
+    w = lib().orc_echo_width_bins(_ptr(wf), wf.size, int(j), float(s0), _ptr(p))
+    return w, p
+
+
+def echo_width(sc, wf, bins):
+    """Echo widths (ns) of the returns `bins` of one waveform."""
+    st = scanner_struct(sc)
+    wf = np.ascontiguousarray(wf, dtype=np.float64)
+    bins = np.ascontiguousarray(bins, dtype=np.int32)
+    out = np.zeros(max(bins.size, 1))
+    lib().orc_echo_width(ctypes.byref(st), _ptr(wf), wf.size, _ptr(bins), bins.size, _ptr(out))
+    return out[:bins.size].copy()
 
 
 def attribute(sc, tri, R, P, tj):

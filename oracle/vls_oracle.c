@@ -24,7 +24,10 @@
  *      first return;
  *   5. local maxima of the summed waveform as discrete returns (Sec. 3.4);
  *   6. the analytic gradient of a waveform loss with respect to per-triangle
- *      reflectance and vertex heights (hit selection held fixed).
+ *      reflectance and vertex heights (hit selection held fixed);
+ *   7. optionally, the width of each return: a Gaussian fitted by non-linear
+ *      least squares to the waveform around the return (Sec. 3.4; its cost is
+ *      discussed in Sec. 3.6).
  * Everything is FP64 with no truncation of the pulse support.
  *
  * Readings where the paper is silent or garbled:
@@ -45,7 +48,9 @@
  *     peak offset; it is attributed to the subray contributing most at j
  *     (ties: lowest subray index);
  *   - equal hit distances go to the lowest triangle index; edges are
- *     inclusive; only t > 0 counts.
+ *     inclusive; only t > 0 counts;
+ *   - echo width (the paper names neither the samples nor the solver): see
+ *     the comment above orc_echo_width.
  */
 #include <math.h>
 #include <stdint.h>
@@ -541,6 +546,143 @@ int orc_gradient(const float* verts, int64_t n_vert, const int32_t* tris, const 
     }
     free(part);
     return S;
+}
+
+/* ------------------------------------------------------------------ echo width (Sec. 3.4, optional) */
+
+/* The paper fits a Gaussian to the waveform of each return by non-linear least
+ * squares and reports its standard deviation as the echo width; the return's
+ * position stays the local maximum.  Readings taken where it says no more:
+ *   samples  the return's lobe: from the return bin j outward while the
+ *            waveform keeps falling strictly, at most ORC_EW_HALF bins to each
+ *            side and within the waveform;
+ *   model    g(x) = A exp(-(x - mu)^2 / (2 s^2)), x = bin index - j;
+ *   start    the Gaussian through bins j-1, j, j+1 (a parabola through the
+ *            logarithms) when those three lie in the lobe, are positive and
+ *            curve downward; otherwise A = wf[j], mu = 0, s = s0 (the pulse's
+ *            own standard deviation in bins);
+ *   solver   Levenberg-Marquardt: solve (J'J + lambda diag(J'J)) delta = J'r
+ *            for the residuals r = wf - g; accept p + delta if it lowers the
+ *            sum of squares (lambda / 10), else keep p (lambda * 10); lambda
+ *            starts at 1e-3; exactly ORC_EW_ITERS iterations;
+ *   result   |s| times the bin width, in ns; NaN for a lobe of fewer than
+ *            three bins, a singular system at the start, or a fit that ends
+ *            with A <= 0 or a non-finite s. */
+#define ORC_EW_HALF 31
+#define ORC_EW_ITERS 12
+
+/* Sum of squared residuals, and J'J (upper triangle: 00 01 02 11 12 22) and
+ * J'r at p = (A, mu, s) over the samples (x[i], y[i]). */
+static double ew_normal(const double* x, const double* y, int m, const double p[3], double H[6], double g[3])
+{
+    double c = 0.0;
+    for (int q = 0; q < 6; ++q) H[q] = 0.0;
+    for (int q = 0; q < 3; ++q) g[q] = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double d = x[i] - p[1];
+        double e = exp(-d * d / (2.0 * p[2] * p[2]));
+        double r = y[i] - p[0] * e;
+        double J[3] = {e, p[0] * e * d / (p[2] * p[2]), p[0] * e * d * d / (p[2] * p[2] * p[2])};
+        c += r * r;
+        H[0] += J[0] * J[0];
+        H[1] += J[0] * J[1];
+        H[2] += J[0] * J[2];
+        H[3] += J[1] * J[1];
+        H[4] += J[1] * J[2];
+        H[5] += J[2] * J[2];
+        for (int q = 0; q < 3; ++q) g[q] += J[q] * r;
+    }
+    return c;
+}
+
+static double ew_cost(const double* x, const double* y, int m, const double p[3])
+{
+    double c = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double d = x[i] - p[1];
+        double r = y[i] - p[0] * exp(-d * d / (2.0 * p[2] * p[2]));
+        c += r * r;
+    }
+    return c;
+}
+
+/* Solves the symmetric 3x3 system M delta = g (M from its upper triangle) by
+ * Cramer's rule; 0 if it is singular. */
+static int ew_solve(const double M[6], const double g[3], double delta[3])
+{
+    double a = M[0], b = M[1], c = M[2], d = M[3], e = M[4], f = M[5];
+    double det = a * (d * f - e * e) - b * (b * f - e * c) + c * (b * e - d * c);
+    if (!(det != 0.0) || !isfinite(det)) return 0;
+    delta[0] = (g[0] * (d * f - e * e) - b * (g[1] * f - e * g[2]) + c * (g[1] * e - d * g[2])) / det;
+    delta[1] = (a * (g[1] * f - e * g[2]) - g[0] * (b * f - e * c) + c * (b * g[2] - g[1] * c)) / det;
+    delta[2] = (a * (d * g[2] - g[1] * e) - b * (b * g[2] - g[1] * c) + g[0] * (b * e - d * c)) / det;
+    return 1;
+}
+
+/* Echo width of the return at bin j of the waveform wf[0..n-1]; s0: the start
+ * width in bins; returns the width in bins (NaN: no fit).  p_out (optional)
+ * receives the fitted (A, mu, s). */
+double orc_echo_width_bins(const double* wf, int n, int j, double s0, double* p_out)
+{
+    if (p_out) p_out[0] = p_out[1] = p_out[2] = NAN;
+    if (j < 0 || j >= n) return NAN;
+    int L = j, R = j;
+    while (L > 0 && j - L < ORC_EW_HALF && wf[L - 1] < wf[L]) --L;
+    while (R < n - 1 && R - j < ORC_EW_HALF && wf[R + 1] < wf[R]) ++R;
+    int m = R - L + 1;
+    if (m < 3) return NAN;
+    double x[2 * ORC_EW_HALF + 1], y[2 * ORC_EW_HALF + 1];
+    for (int i = 0; i < m; ++i) {
+        x[i] = (double)(L + i - j);
+        y[i] = wf[L + i];
+    }
+    double p[3] = {wf[j], 0.0, s0};
+    if (L <= j - 1 && R >= j + 1 && wf[j - 1] > 0.0 && wf[j] > 0.0 && wf[j + 1] > 0.0) {
+        double lm = log(wf[j - 1]), l0 = log(wf[j]), lp = log(wf[j + 1]);
+        double c2 = lm - 2.0 * l0 + lp;  /* twice the quadratic coefficient */
+        if (c2 < 0.0) {
+            double s2 = -1.0 / c2;
+            double mu = 0.5 * (lp - lm) * s2;
+            p[0] = exp(l0 + mu * mu / (2.0 * s2));
+            p[1] = mu;
+            p[2] = sqrt(s2);
+        }
+    }
+    double H[6], g[3];
+    double cost = ew_normal(x, y, m, p, H, g);
+    double lambda = 1e-3;
+    for (int it = 0; it < ORC_EW_ITERS; ++it) {
+        double M[6] = {H[0] * (1.0 + lambda), H[1], H[2], H[3] * (1.0 + lambda), H[4], H[5] * (1.0 + lambda)};
+        double delta[3];
+        if (!ew_solve(M, g, delta)) break;
+        double q[3] = {p[0] + delta[0], p[1] + delta[1], p[2] + delta[2]};
+        double cq = ew_cost(x, y, m, q);
+        if (cq < cost) {
+            p[0] = q[0];
+            p[1] = q[1];
+            p[2] = q[2];
+            cost = ew_normal(x, y, m, p, H, g);
+            lambda *= 0.1;
+        } else {
+            lambda *= 10.0;
+        }
+    }
+    if (p_out) {
+        p_out[0] = p[0];
+        p_out[1] = p[1];
+        p_out[2] = p[2];
+    }
+    if (!(p[0] > 0.0) || !isfinite(p[2]) || p[2] == 0.0) return NAN;
+    return fabs(p[2]);
+}
+
+/* Widths (ns) of the returns bins[0..k-1] of one waveform; the start width is
+ * the pulse's own standard deviation (for Eq. 3, that of a Gaussian of the same
+ * FWHM-like length). */
+void orc_echo_width(const orc_scanner* sc, const double* wf, int n, const int32_t* bins, int k, double* width_ns)
+{
+    double s0 = gauss_sigma(sc) / sc->bin_ns;
+    for (int i = 0; i < k; ++i) width_ns[i] = orc_echo_width_bins(wf, n, bins[i], s0, NULL) * sc->bin_ns;
 }
 
 int orc_max_threads(void)
