@@ -347,6 +347,24 @@ def main():
                               "compulsory_bytes": compulsory,
                               "compulsory_frac": compulsory / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}},
     }
+    # echo width (Sec. 3.4, optional): a Gaussian fitted to each kept return
+    log("echo width")
+    width = torch.empty((n, K), dtype=torch.float32, device=dev)
+    ctx.echo_width(sc, o, d, out, width=width)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.echo_width(sc, o, d, out, width=width)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ew_ms = e0.elapsed_time(e1) / args.steps
+    n_ret = int(out["n_returns"].sum().item())
+    res["echo_width"] = {"ms": ew_ms, "returns": n_ret, "returns_per_s": n_ret / (ew_ms * 1e-3),
+                         "fitted": int(torch.isfinite(width).sum().item()),
+                         "step_with_echo_width_over_step": (ms + ew_ms) / ms,
+                         "paper_runtime_factor": 1.3}
     res["autotune"] = tune
     if not args.only_plain:
         log("batched workload")

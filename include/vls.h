@@ -76,8 +76,8 @@ vls_status vls_context_destroy(vls_context ctx);
 /* Triangle mesh (Sec. 5.1: a scene is a set of primitives, each with a material;
  * here triangles with a reflectance in [0, 1]).
  *   vertices    [n_vertices][3] float32, metres
- *   triangles   [n_triangles][3] int32 vertex indices (validated on the host
- *               only when memory == VLS_MEM_HOST)
+ *   triangles   [n_triangles][3] int32 vertex indices (checked on the device
+ *               by vls_scene_create)
  *   reflectance [n_triangles] float32
  *   memory      where the three arrays live: VLS_MEM_HOST or VLS_MEM_DEVICE.
  * n_triangles may be 0 (every subray misses). */
@@ -257,6 +257,27 @@ vls_status vls_waveform(vls_context ctx, const vls_scanner_desc* scanners, int32
  * are NULL, ret_tri is -1). */
 vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners,
                        const vls_pulse_batch* pulses, const vls_outputs* out, void* stream);
+
+/* Echo width (Sec. 3.4: an optional Gaussian fitted by non-linear least squares
+ * to the waveform of each return, whose standard deviation is the return's
+ * width; the return's position stays the local maximum).  For every kept
+ * return of every pulse, the samples are the return's lobe: from the return's
+ * bin outward while the waveform keeps falling strictly, at most 31 bins to each
+ * side.  The model A exp(-(x - mu)^2 / (2 s^2)) starts from the Gaussian
+ * through the return's bin and its two neighbours (when they lie in the lobe,
+ * are positive and curve downward), else from the bin's value and the pulse's
+ * own standard deviation, and is fitted by 12 Levenberg-Marquardt iterations in
+ * FP32.
+ *   reads    out->waveform, out->n_returns, out->ret_bin (as vls_simulate or
+ *            vls_returns wrote them; the other output arrays are not used)
+ *   width_ns device array [n_pulses][K] float32: |s| in ns for the kept
+ *            returns, NaN where no fit exists (a lobe of fewer than three bins,
+ *            a fit ending with A <= 0) and for the slots past n_returns.
+ * The context keeps a workspace of n_pulses * K ints, grown on demand.  Enqueued
+ * on `stream`.  Errors: VLS_ERR_INVALID_ARG for missing arrays, as vls_returns
+ * for the scanners and the batch. */
+vls_status vls_echo_width(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners,
+                          const vls_pulse_batch* pulses, const vls_outputs* out, float* width_ns, void* stream);
 
 /* The whole path fused in one launch: trace, power, waveform, returns.
  * waveform may be NULL (returns are still found from the in-register

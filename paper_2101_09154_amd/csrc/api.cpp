@@ -153,6 +153,8 @@ struct vls_context_s {
     std::vector<Batch> batches;  // uploaded segment tables, reused by content
     int* cand = nullptr;         // cone-pass candidate lists, grown on demand
     long long cand_pulses = 0;
+    int* ew = nullptr;           // echo-width list of returns + counter, grown on demand
+    long long ew_entries = 0;
     // kernel timing (vls_profile_*): event pairs recorded around the cone pass
     // and the fused kernel of eager vls_simulate calls, and a pool of spares
     bool prof = false;
@@ -166,6 +168,7 @@ struct vls_context_s {
                 (void)hipEventDestroy(e.second);
             }
         (void)hipFree(cand);
+        (void)hipFree(ew);
         for (auto& kv : patterns) (void)hipFree(kv.second);
         for (auto& b : batches) (void)hipFree(b.dev);
     }
@@ -782,6 +785,45 @@ vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_
                        const vls_pulse_batch* pulses, const vls_outputs* out, void* stream)
 {
     return wave_common(ctx, scanners, n_scanners, pulses, out, stream, 1);
+}
+
+vls_status vls_echo_width(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners,
+                          const vls_pulse_batch* pulses, const vls_outputs* out, float* width_ns, void* stream)
+{
+    try {
+        Prepared pr;
+        vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
+        if (st != VLS_OK) return st;
+        if ((st = check_outputs(out)) != VLS_OK) return st;
+        const long long n = pulses->n_pulses;
+        if (n == 0) return VLS_OK;
+        if (!out->waveform || !out->n_returns || !out->ret_bin || !width_ns)
+            return fail(VLS_ERR_INVALID_ARG, "echo width needs waveform, n_returns, ret_bin and width_ns");
+        if (!aligned(width_ns, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned width_ns");
+        // workspace: one list entry per return slot, then a 64-bit counter
+        const long long entries = n * (long long)pr.K;
+        if (entries > ctx->ew_entries) {
+            (void)hipFree(ctx->ew);
+            ctx->ew = nullptr;
+            ctx->ew_entries = 0;
+            VLS_HIP(hipMalloc(&ctx->ew, sizeof(int) * (size_t)(entries + (entries & 1) + 2)), "echo-width workspace");
+            ctx->ew_entries = entries;
+        }
+        unsigned long long* ctr = reinterpret_cast<unsigned long long*>(ctx->ew + entries + (entries & 1));
+        for (size_t g = 0; g + 1 < pr.off.size(); ++g) {
+            const vls_scanner_desc& d = scanners[pr.seg_sc[g]];
+            // start width: the pulse's standard deviation (for Eq. 3 that of a
+            // Gaussian of the same width parameter), in bins
+            const float s0 = (float)(d.pulse_width_ns / (2.0 * std::sqrt(2.0 * std::log(2.0))) / d.bin_ns);
+            hipError_t e = launch_echo_width(pr.sc[pr.seg_sc[g]], out->waveform, out->n_returns, out->ret_bin, s0,
+                                             pr.off[g], pr.off[g + 1] - pr.off[g], ctx->ew, ctr, width_ns,
+                                             (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "echo-width launch");
+        }
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
 }
 
 static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners,

@@ -179,6 +179,11 @@ hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& p
 hipError_t launch_packets(const SceneDev& scene, const ScannerDev& sc0, const BatchDev& batch, const PulsesDev& pulses,
                           int* cand, const int* ovf_list, unsigned long long* ovf_ctr, long long first,
                           hipStream_t stream);
+// Echo width of the kept returns of pulses [first, first + count) (see echo.hip):
+// list / list_ctr: workspace of count * K ints and one 64-bit counter.
+hipError_t launch_echo_width(const ScannerDev& sc, const float* wf, const int32_t* n_ret, const int32_t* ret_bin,
+                             float s0_bins, long long first, long long count, int* list,
+                             unsigned long long* list_ctr, float* width, hipStream_t stream);
 // Candidate lists hold leaf indices; rewrite them as original triangle indices.
 hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_pulses, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);

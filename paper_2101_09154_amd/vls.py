@@ -99,6 +99,7 @@ _SIGS = {
     "vls_trace": ([P, P, P, i32, P, P, P], i32),
     "vls_waveform": ([P, P, i32, P, P, P], i32),
     "vls_returns": ([P, P, i32, P, P, P], i32),
+    "vls_echo_width": ([P, P, i32, P, P, P, P], i32),
     "vls_simulate": ([P, P, P, i32, P, P, P], i32),
     "vls_set_launch_config": ([P, P], i32),
     "vls_get_launch_config": ([P, P], i32),
@@ -472,3 +473,19 @@ class Context:
         o = self._outputs(out)
         _check(lib().vls_returns(self._h, arr, ns, ctypes.byref(b), ctypes.byref(o), _stream(stream)))
         return out
+
+    def echo_width(self, scanners, origins, directions, out, *, width=None, segment_offsets=None,
+                   segment_scanner=None, stream=None):
+        """Echo width (ns) of every kept return in `out` (waveform, n_returns and ret_bin
+        as written by simulate or returns): float32 [n, K], NaN where there is none."""
+        arr, ns = self._scanners(scanners)
+        b, keep = self._batch(origins, directions, None, segment_offsets, segment_scanner)
+        o = self._outputs(out)
+        n = origins.shape[0]
+        K = out["ret_bin"].shape[1] if out.get("ret_bin") is not None else 1
+        if width is None:
+            width = torch.empty((n, K), dtype=torch.float32, device=origins.device)
+        _dev(width, torch.float32, (n, K), "width")
+        _check(lib().vls_echo_width(self._h, arr, ns, ctypes.byref(b), ctypes.byref(o), _ptr(width),
+                                    _stream(stream)))
+        return width

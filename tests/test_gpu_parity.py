@@ -686,6 +686,89 @@ def test_packet_walk_bitwise_on_trees(ctx, S):
         assert np.array_equal(res[0][k], res[1][k], equal_nan=True), k
 
 
+# ------------------------------------------------------------------ echo width (Sec. 3.4, optional)
+
+# FP32 fit against the FP64 one on the same waveform: sums over <= 63 bins
+# (<= 63 * 2^-24 ~ 4e-6 relative in J'J and J'r) through a 3x3 system whose
+# condition number reaches ~100 on skewed (Eq. 3) lobes -> ~4e-4
+EW_RTOL = 5e-4
+
+
+def _check_echo_width(sc_list, seg_of, g, w, label):
+    """Compare the GPU widths w [n, K] with the oracle's on the GPU's own waveform
+    and return bins (the fit alone is under test here)."""
+    n, K = w.shape
+    worst = 0.0
+    checked = 0
+    where = None
+    for i in range(n):
+        sc = sc_list[seg_of[i]]
+        nr = int(g["n_returns"][i])
+        assert np.all(np.isnan(w[i, nr:])), (label, i)
+        if nr == 0:
+            continue
+        ref = oracle.echo_width(sc, g["waveform"][i].astype(np.float64), g["ret_bin"][i, :nr])
+        both_nan = np.isnan(ref) & np.isnan(w[i, :nr])
+        assert np.array_equal(np.isnan(ref), np.isnan(w[i, :nr])), (label, i, ref, w[i, :nr])
+        ok = ~both_nan
+        if ok.any():
+            rel = np.abs(w[i, :nr][ok] - ref[ok]) / ref[ok]
+            if float(rel.max()) > worst:
+                worst = float(rel.max())
+                k = int(np.nonzero(ok)[0][np.argmax(rel)])
+                j = int(g["ret_bin"][i, k])
+                where = (i, k, j, float(ref[k]), float(w[i, k]), g["waveform"][i, max(j - 32, 0):j + 33].tolist())
+            checked += int(ok.sum())
+    say("echo width %s: %d returns, worst rel %.2e" % (label, checked, worst))
+    assert checked > 0 and worst <= EW_RTOL, (label, worst, where)
+    return worst
+
+
+@pytest.mark.parametrize("case", ["small_tls", "eq3_k1_ragged"])
+def test_echo_width_matches_oracle(ctx, case):
+    mesh, pulses, sc = configs.small_tls()
+    if case == "eq3_k1_ragged":
+        sc = dict(sc, pulse_shape="eq3", pulse_width_ns=3.0, max_returns=1, n_bins=100)
+        pulses = pulses.subset(np.arange(0, pulses.n, 7))
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = _dev(pulses.origins)
+    d = _dev(pulses.directions)
+    out = ctx.simulate(scene, sc, o, d)
+    w = ctx.echo_width(sc, o, d, out)
+    torch.cuda.synchronize()
+    _check_echo_width([sc], np.zeros(pulses.n, int), to_np(out), w.cpu().numpy(), case)
+
+
+def test_echo_width_batched_and_full_size(ctx):
+    # segments with different scanners (bin widths), and the ALS workload at
+    # full size on sampled pulses
+    mesh, scs, batch, seg_sc = _small_batch()
+    scs = [dict(scs[0], bin_ns=0.5), dict(scs[1], bin_ns=1.0), dict(scs[2], bin_ns=0.7)]
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = _dev(batch.origins)
+    d = _dev(batch.directions)
+    kw = dict(segment_offsets=batch.segment_offsets, segment_scanner=batch.segment_scanner)
+    out = ctx.simulate(scene, scs, o, d, **kw)
+    w = ctx.echo_width(scs, o, d, out, **kw)
+    torch.cuda.synchronize()
+    seg_of = np.repeat(np.asarray(batch.segment_scanner), np.diff(np.asarray(batch.segment_offsets)))
+    _check_echo_width(scs, seg_of, to_np(out), w.cpu().numpy(), "batched")
+
+    mesh, pulses, sc = configs.als_buildings()
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = _dev(pulses.origins)
+    d = _dev(pulses.directions)
+    out = ctx.simulate(scene, sc, o, d)
+    w = ctx.echo_width(sc, o, d, out)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    sel = np.sort(rng.choice(pulses.n, 400, replace=False))
+    g = _rows(out, sel)
+    ws = w.index_select(0, torch.from_numpy(sel).cuda()).cpu().numpy()
+    _check_echo_width([sc], np.zeros(sel.size, int), g, ws, "als_buildings")
+    assert np.all(np.isnan(w.cpu().numpy()[out["n_returns"].cpu().numpy() == 0]))
+
+
 def test_cone_candidates_contain_every_hit(ctx):
     # the candidate list of a pulse holds the closest-hit triangle of every one
     # of its subrays (found here by per-subray traversal), unless it overflowed
