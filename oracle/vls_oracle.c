@@ -554,17 +554,20 @@ int orc_gradient(const float* verts, int64_t n_vert, const int32_t* tris, const 
  * squares and reports its standard deviation as the echo width; the return's
  * position stays the local maximum.  Readings taken where it says no more:
  *   samples  the return's lobe: from the return bin j outward while the
- *            waveform keeps falling strictly, at most ORC_EW_HALF bins to each
- *            side and within the waveform;
+ *            waveform keeps falling strictly and stays at or above 2^-10 of
+ *            wf[j] (the tails below carry next to nothing), at most ORC_EW_HALF
+ *            bins to each side and within the waveform;
  *   model    g(x) = A exp(-(x - mu)^2 / (2 s^2)), x = bin index - j;
  *   start    the Gaussian through bins j-1, j, j+1 (a parabola through the
  *            logarithms) when those three lie in the lobe, are positive and
  *            curve downward; otherwise A = wf[j], mu = 0, s = s0 (the pulse's
  *            own standard deviation in bins);
  *   solver   Levenberg-Marquardt: solve (J'J + lambda diag(J'J)) delta = J'r
- *            for the residuals r = wf - g; accept p + delta if it lowers the
- *            sum of squares (lambda / 10), else keep p (lambda * 10); lambda
- *            starts at 1e-3; exactly ORC_EW_ITERS iterations;
+ *            for the residuals r = wf - g; accept p + delta if its centre lies
+ *            within the lobe's length of j, its |s| is at most twice the number
+ *            of lobe bins, and it lowers the sum of squares (lambda / 10); else
+ *            keep p (lambda * 10); lambda starts at 1e-3; exactly ORC_EW_ITERS
+ *            iterations;
  *   result   |s| times the bin width, in ns; NaN for a lobe of fewer than
  *            three bins, a singular system at the start, or a fit that ends
  *            with A <= 0 or a non-finite s. */
@@ -627,8 +630,8 @@ double orc_echo_width_bins(const double* wf, int n, int j, double s0, double* p_
     if (p_out) p_out[0] = p_out[1] = p_out[2] = NAN;
     if (j < 0 || j >= n) return NAN;
     int L = j, R = j;
-    while (L > 0 && j - L < ORC_EW_HALF && wf[L - 1] < wf[L]) --L;
-    while (R < n - 1 && R - j < ORC_EW_HALF && wf[R + 1] < wf[R]) ++R;
+    while (L > 0 && j - L < ORC_EW_HALF && wf[L - 1] < wf[L] && 1024.0 * wf[L - 1] >= wf[j]) --L;
+    while (R < n - 1 && R - j < ORC_EW_HALF && wf[R + 1] < wf[R] && 1024.0 * wf[R + 1] >= wf[j]) ++R;
     int m = R - L + 1;
     if (m < 3) return NAN;
     double x[2 * ORC_EW_HALF + 1], y[2 * ORC_EW_HALF + 1];
@@ -656,7 +659,10 @@ double orc_echo_width_bins(const double* wf, int n, int j, double s0, double* p_
         double delta[3];
         if (!ew_solve(M, g, delta)) break;
         double q[3] = {p[0] + delta[0], p[1] + delta[1], p[2] + delta[2]};
-        double cq = ew_cost(x, y, m, q);
+        /* a trial centre outside the lobe or a width beyond twice its length
+         * counts as rejected: it heads for the flat (infinitely wide) limit */
+        int inside = fabs(q[1]) <= (double)(R - L) && fabs(q[2]) <= 2.0 * (double)m;
+        double cq = inside ? ew_cost(x, y, m, q) : INFINITY;
         if (cq < cost) {
             p[0] = q[0];
             p[1] = q[1];

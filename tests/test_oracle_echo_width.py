@@ -15,13 +15,14 @@ HALF = 31  # lobe half-width cap, in bins
 
 def _lobe(wf, j):
     """The samples the fit must use: from j outward while the waveform keeps
-    falling strictly, at most HALF bins to each side (written here from the
-    reading, independently of the oracle)."""
+    falling strictly and stays at or above 2^-10 of wf[j], at most HALF bins to
+    each side (written here from the reading, independently of the oracle)."""
+    floor = wf[j] / 1024.0
     L = j
-    while L > 0 and j - L < HALF and wf[L - 1] < wf[L]:
+    while L > 0 and j - L < HALF and wf[L - 1] < wf[L] and wf[L - 1] >= floor:
         L -= 1
     R = j
-    while R < len(wf) - 1 and R - j < HALF and wf[R + 1] < wf[R]:
+    while R < len(wf) - 1 and R - j < HALF and wf[R + 1] < wf[R] and wf[R + 1] >= floor:
         R += 1
     return np.arange(L, R + 1)
 
@@ -45,7 +46,8 @@ def _gauss(x, A, mu, s):
 @pytest.mark.parametrize("A,mu,s", [(2.5, 0.3, 3.1), (1e-3, -0.45, 0.8), (7.0, 0.1, 12.0), (1.0, 0.0, 40.0)])
 def test_exact_gaussian_recovered(orc, A, mu, s):
     # noise-free Gaussian samples: the least-squares optimum is the generator
-    # itself (cost 0), also when the lobe is cut at 31 bins (s = 40)
+    # itself (cost 0), also when the lobe is cut at 31 bins (s = 40) or at
+    # 2^-10 of the peak (the others)
     x = np.arange(160, dtype=np.float64)
     j = 80
     wf = _gauss(x, A, j + mu, s)
@@ -105,6 +107,35 @@ def test_each_return_uses_its_own_lobe(orc):
     assert orc.echo_width_bins(both, 120, 4.0)[0] == pytest.approx(5.5, rel=1e-9)
 
 
+def test_lobe_floor(orc):
+    # bins below 2^-10 of the return bin's value are left out: a pedestal far
+    # below the echo does not widen it
+    x = np.arange(200, dtype=np.float64)
+    wf = _gauss(x, 1.0, 100.0, 3.0) + 2e-4 * _gauss(x, 1.0, 100.0, 60.0)
+    L, R = _lobe(wf, 100)[[0, -1]]
+    assert R - L + 1 < 2 * HALF + 1 and wf[L] >= wf[100] / 1024 and wf[L - 1] < wf[100] / 1024
+    w, _ = orc.echo_width_bins(wf, 100, 4.0)
+    idx = _lobe(wf, 100)
+    ref = _scipy_fit(wf, 100, np.array([1.0, 0.0, 3.0]))
+    assert abs(w - ref[2]) <= 1e-6 * ref[2]
+
+
+@pytest.mark.parametrize("side", [-1, 1])
+def test_lobe_stops_at_a_plateau(orc, side):
+    # the lobe ends where the waveform stops falling strictly: two equal bins
+    # on one flank end it there, and the fit uses only the bins before them
+    x = np.arange(128, dtype=np.float64)
+    wf = _gauss(x, 1.0, 64.2, 3.0) + 0.3 * _gauss(x, 1.0, 64.0 + side * 9.0, 4.0)
+    j = int(np.argmax(wf))
+    k = j + side * 4
+    wf[k + side] = wf[k]          # a plateau four bins out
+    idx = _lobe(wf, j)
+    assert (idx[0] if side < 0 else idx[-1]) == k
+    w, p = orc.echo_width_bins(wf, j, 3.0)
+    ref = _scipy_fit(wf, j, p)
+    assert abs(w - ref[2]) <= 1e-6 * ref[2], (w, ref)
+
+
 def test_no_fit_cases(orc):
     # a lobe of two bins (a dip before the peak, a plateau after it) has no fit
     wf = np.zeros(16)
@@ -112,7 +143,7 @@ def test_no_fit_cases(orc):
     w, _ = orc.echo_width_bins(wf, 4, 2.0)
     assert np.isnan(w)
     # three bins do: the Gaussian through them
-    wf[2] = 0.0
+    wf[2] = 0.01
     w3, p3 = orc.echo_width_bins(wf, 4, 2.0)
     assert np.isfinite(w3) and p3[0] > 0.0
     # out of range
