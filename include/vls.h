@@ -262,12 +262,14 @@ vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_
  * to the waveform of each return, whose standard deviation is the return's
  * width; the return's position stays the local maximum).  For every kept
  * return of every pulse, the samples are the return's lobe: from the return's
- * bin outward while the waveform keeps falling strictly, at most 31 bins to each
- * side.  The model A exp(-(x - mu)^2 / (2 s^2)) starts from the Gaussian
- * through the return's bin and its two neighbours (when they lie in the lobe,
- * are positive and curve downward), else from the bin's value and the pulse's
- * own standard deviation, and is fitted by 12 Levenberg-Marquardt iterations in
- * FP32.
+ * bin outward while the waveform keeps falling strictly and stays at or above
+ * 2^-10 of the return bin's value, at most 31 bins to each side.  The model
+ * A exp(-(x - mu)^2 / (2 s^2)) starts from the Gaussian through the return's
+ * bin and its two neighbours (when they lie in the lobe, are positive and curve
+ * downward), else from the bin's value and the pulse's own standard deviation,
+ * and is fitted by 12 Levenberg-Marquardt iterations in FP32 (trial points
+ * centred farther out than the lobe is long, or wider than twice its bins,
+ * count as rejected).
  *   reads    out->waveform, out->n_returns, out->ret_bin (as vls_simulate or
  *            vls_returns wrote them; the other output arrays are not used)
  *   width_ns device array [n_pulses][K] float32: |s| in ns for the kept

@@ -4,17 +4,20 @@
 // maximum.  Sec. 3.6 notes the fit's cost).
 //
 // The samples are the return's lobe: from the return bin j outward while the
-// waveform keeps falling strictly, at most kEwHalf bins to each side.  The model
+// waveform keeps falling strictly and stays at or above 2^-10 of wf[j] (a
+// power-of-two scale, so FP32 and FP64 decide it alike), at most kEwHalf bins to
+// each side.  The model
 // A exp(-(x - mu)^2 / (2 s^2)), x = bin - j, starts from the Gaussian through
 // bins j-1, j, j+1 (a parabola through their logarithms) when those lie in the
 // lobe, are positive and curve downward, else from A = wf[j], mu = 0 and the
 // pulse's own standard deviation; Levenberg-Marquardt with Marquardt's scaling
 // then runs exactly kEwIters iterations (damping 1e-3 at the start, / 10 on an
-// accepted step, * 10 on a rejected one).  Width = |s| bin in ns; NaN for a lobe
+// accepted step, * 10 on a rejected one; a trial centre farther from j than the
+// lobe is long, or a width beyond twice the lobe's bins, counts as rejected).  Width = |s| bin in ns; NaN for a lobe
 // of fewer than three bins or a fit that ends with A <= 0 or a non-finite s.
 //
 // Two launches: k_ew_list lists every kept (pulse, return) pair (one atomic per
-// wavefront) and writes NaN to every slot; k_ew_fit gives each lane one listed
+// block of 1024 pulses) and writes NaN to every slot; k_ew_fit gives each lane one listed
 // return, so every lane of a wavefront has a fit to do.  A lane caches the
 // 2 kEwHalf + 1 bins around its return in LDS, bin-major ([bin][lane]), so the
 // lanes of a wavefront read consecutive words, and runs the fit in FP32; each
@@ -35,37 +38,51 @@ constexpr int kEwHalf = 31;
 constexpr int kEwSpan = 2 * kEwHalf + 1;
 constexpr int kEwIters = 12;
 
+constexpr int kEwListThreads = 1024;
+
 // Lists the kept returns of pulses [first, first + count): entry = p * K + k.
-// list_ctr[0] counts them (reset by the launcher).  Every width slot of these
-// pulses is set to NaN; the fit overwrites the listed ones.
-__global__ __launch_bounds__(256) void k_ew_list(const int32_t* __restrict__ n_ret, int K, long long first,
-                                                 long long count, int* __restrict__ list,
-                                                 unsigned long long* list_ctr, float* __restrict__ width)
+// list_ctr[0] counts them (reset by the launcher); each block takes its slots
+// with one atomic.  Every width slot of these pulses is set to NaN (coalesced);
+// the fit overwrites the listed ones.
+__global__ __launch_bounds__(kEwListThreads) void k_ew_list(const int32_t* __restrict__ n_ret, int K,
+                                                            long long first, long long count,
+                                                            int* __restrict__ list, unsigned long long* list_ctr,
+                                                            float* __restrict__ width)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & (kWave - 1);
-    const bool active = i < count;
-    const long long p = first + i;
+    constexpr int W = kEwListThreads / kWave;
+    __shared__ int wsum[W];
+    __shared__ unsigned long long block_base;
+    const long long b0 = (long long)blockIdx.x * kEwListThreads;
+    const long long i = b0 + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const long long nb = count - b0 < kEwListThreads ? count - b0 : kEwListThreads;
+    for (long long q = threadIdx.x; q < nb * K; q += kEwListThreads) width[(first + b0) * K + q] = NAN;
     int nr = 0;
-    if (active) {
-        nr = n_ret[p];
+    if (i < count) {
+        nr = n_ret[first + i];
         nr = nr < 0 ? 0 : (nr > K ? K : nr);
-        for (int k = 0; k < K; ++k) width[p * K + k] = NAN;
     }
-    // exclusive prefix of nr over the wavefront, one atomic for its total
+    // prefix of nr over the wavefront, then over the block's wavefront totals
     int incl = nr;
     for (int off = 1; off < kWave; off <<= 1) {
         const int y = __shfl_up(incl, off);
         if (lane >= off) incl += y;
     }
-    const int total = __shfl(incl, kWave - 1);
-    if (total == 0) return;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(list_ctr, (unsigned long long)total);
-    const unsigned b_lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)base);
-    const unsigned b_hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(base >> 32));
-    const unsigned long long b = ((unsigned long long)b_hi << 32) | b_lo;
-    for (int k = 0; k < nr; ++k) list[b + (incl - nr) + k] = (int)(p * K + k);
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+        int t = lane < W ? wsum[lane] : 0;
+        for (int off = 1; off < W; off <<= 1) {
+            const int y = __shfl_up(t, off);
+            if (lane >= off) t += y;
+        }
+        if (lane < W) wsum[lane] = t;
+        if (lane == W - 1) block_base = t > 0 ? atomicAdd(list_ctr, (unsigned long long)t) : 0ull;
+    }
+    __syncthreads();
+    const unsigned long long base = block_base + (unsigned long long)(w > 0 ? wsum[w - 1] : 0) + (incl - nr);
+    const long long p = first + i;
+    for (int k = 0; k < nr; ++k) list[base + k] = (int)(p * K + k);
 }
 
 // Residual sum, normal equations J'J (upper triangle 00 01 02 11 12 22) and J'r
@@ -129,8 +146,9 @@ __global__ __launch_bounds__(kWave) void k_ew_fit(const float* __restrict__ wf, 
         }
         int L = kEwHalf, R = kEwHalf;
         if (ok) {
-            while (L > 0 && buf[L - 1][lane] < buf[L][lane]) --L;
-            while (R < kEwSpan - 1 && buf[R + 1][lane] < buf[R][lane]) ++R;
+            const float top = buf[kEwHalf][lane];
+            while (L > 0 && buf[L - 1][lane] < buf[L][lane] && 1024.0f * buf[L - 1][lane] >= top) --L;
+            while (R < kEwSpan - 1 && buf[R + 1][lane] < buf[R][lane] && 1024.0f * buf[R + 1][lane] >= top) ++R;
         }
         // the fit runs on the lobe divided by the return bin's value: least
         // squares is equivariant under that scaling (A scales, mu and s do not),
@@ -169,8 +187,10 @@ __global__ __launch_bounds__(kWave) void k_ew_fit(const float* __restrict__ wf, 
                 const float d1 = (a * (g[1] * f - ee * g[2]) - g[0] * m1 + cc * (b * g[2] - g[1] * cc)) * id;
                 const float d2 = (a * (d * g[2] - g[1] * ee) - b * (b * g[2] - g[1] * cc) + g[0] * m2) * id;
                 const float tA = A + d0, tmu = mu + d1, ts = s + d2;
+                const bool inside = fabsf(tmu) <= (float)(R - L) && fabsf(ts) <= 2.0f * (float)(R - L + 1);
                 float Ht[6], gt[3];
-                const float ct = ew_pass(buf, lane, L, R, inv, tA, tmu, ts, Ht, gt);
+                float ct = INFINITY;
+                if (inside) ct = ew_pass(buf, lane, L, R, inv, tA, tmu, ts, Ht, gt);
                 if (ct < cost) {
                     A = tA;
                     mu = tmu;
@@ -199,8 +219,8 @@ hipError_t launch_echo_width(const ScannerDev& sc, const float* wf, const int32_
     if (count <= 0) return hipSuccess;
     hipError_t e = launch_fill_u64(list_ctr, 1, 0ull, stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ew_list, dim3(grid_for(count, 256)), dim3(256), 0, stream, n_ret, sc.K, first, count, list,
-                       list_ctr, width);
+    hipLaunchKernelGGL(k_ew_list, dim3(grid_for(count, kEwListThreads)), dim3(kEwListThreads), 0, stream, n_ret, sc.K,
+                       first, count, list, list_ctr, width);
     int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
