@@ -31,6 +31,16 @@ def build(force=True):
     return LIB
 
 
+class OrcSurvey(ctypes.Structure):
+    _fields_ = [("waypoints", ctypes.c_void_p), ("n_waypoints", ctypes.c_int32), ("deflector", ctypes.c_int32),
+                ("speed", ctypes.c_double), ("prf", ctypes.c_double), ("scan_freq", ctypes.c_double),
+                ("scan_angle", ctypes.c_double), ("n_fibres", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("t0", ctypes.c_double), ("noise_sigma", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+DEFLECTORS = {"polygon": 0, "swing": 1, "conic": 2, "fibre": 3}
+
+
 class OrcScanner(ctypes.Structure):
     _fields_ = [("divergence_rad", ctypes.c_double), ("pattern_extent", ctypes.c_double),
                 ("pulse_width_ns", ctypes.c_double), ("bin_ns", ctypes.c_double),
@@ -72,6 +82,9 @@ def lib():
         L.orc_echo_width_bins.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_double, P]
         L.orc_echo_width_bins.restype = ctypes.c_double
         L.orc_echo_width.argtypes = [P, P, ctypes.c_int, P, ctypes.c_int, P]
+        L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_splitmix64.restype = ctypes.c_uint64
+        L.orc_generate_pulses.argtypes = [P, i64, i64, P, P]
         L.orc_attribute.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_double]
         L.orc_simulate.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, i64, P] + [P] * 6 + [P] * 7 + [ctypes.c_int]
         L.orc_gradient.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, P, P, P, ctypes.c_int]
@@ -196,6 +209,26 @@ def echo_width(sc, wf, bins):
     out = np.zeros(max(bins.size, 1))
     lib().orc_echo_width(ctypes.byref(st), _ptr(wf), wf.size, _ptr(bins), bins.size, _ptr(out))
     return out[:bins.size].copy()
+
+
+def splitmix64(seed, c):
+    """Output number c of the SplitMix64 sequence seeded with `seed`."""
+    return int(lib().orc_splitmix64(int(seed) & 0xFFFFFFFFFFFFFFFF, int(c)))
+
+
+def generate_pulses(sv, first, count):
+    """Pulses [first, first + count) of a survey (Sec. 3.2-3.3 readings):
+    origins and unit directions, both float64 [count, 3]."""
+    wp = np.ascontiguousarray(sv["waypoints"], dtype=np.float64).reshape(-1, 3)
+    st = OrcSurvey(wp.ctypes.data, wp.shape[0], DEFLECTORS[sv.get("deflector", "polygon")],
+                   float(sv.get("speed_mps", 0.0)), float(sv["pulse_rate_hz"]), float(sv.get("scan_freq_hz", 0.0)),
+                   float(sv.get("scan_angle_rad", 0.0)), int(sv.get("n_fibres", 0)), 0, float(sv.get("t0", 0.0)),
+                   float(sv.get("platform_noise_m", 0.0)), int(sv.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF)
+    o = np.zeros((count, 3))
+    d = np.zeros((count, 3))
+    if lib().orc_generate_pulses(ctypes.byref(st), int(first), int(count), _ptr(o), _ptr(d)) != 0:
+        raise ValueError("invalid survey")
+    return o, d
 
 
 def attribute(sc, tri, R, P, tj):

@@ -27,7 +27,10 @@
  *      reflectance and vertex heights (hit selection held fixed);
  *   7. optionally, the width of each return: a Gaussian fitted by non-linear
  *      least squares to the waveform around the return (Sec. 3.4; its cost is
- *      discussed in Sec. 3.6).
+ *      discussed in Sec. 3.6);
+ *   8. pulses generated from a survey: a LinearPath or static platform (Sec.
+ *      3.2) carrying one of the four scan deflectors of Sec. 3.3, with optional
+ *      platform position noise from a counter-based SplitMix64.
  * Everything is FP64 with no truncation of the pulse support.
  *
  * Readings where the paper is silent or garbled:
@@ -689,6 +692,132 @@ void orc_echo_width(const orc_scanner* sc, const double* wf, int n, const int32_
 {
     double s0 = gauss_sigma(sc) / sc->bin_ns;
     for (int i = 0; i < k; ++i) width_ns[i] = orc_echo_width_bins(wf, n, bins[i], s0, NULL) * sc->bin_ns;
+}
+
+/* ------------------------------------------------------------------ pulse generation (Sec. 3.2, 3.3) */
+
+/* The paper names the platforms and deflectors and describes their patterns
+ * (Sec. 3.2: a LinearPath platform moves at constant speed from one waypoint to
+ * the next and always faces the next one; Sec. 3.3, Fig. 7: a polygon mirror
+ * gives parallel lines of even density, a fibre array a similar pattern from
+ * fixed directions, a swinging mirror a zig-zag denser at its extremes, a
+ * slanted rotating (Palmer) mirror a cone at a constant angle off nadir) but no
+ * formulas.  Readings taken here:
+ *   time     pulse k leaves at t_k = t0 + k / prf;
+ *   path     the platform covers the polyline of waypoints at `speed` from
+ *            the first waypoint at t = 0 and stays at the last one afterwards;
+ *            it is level and its heading (yaw) is that of the current leg's
+ *            horizontal direction (one waypoint: static, heading +x);
+ *   frame    platform x forward, y left, z up; world = Rz(yaw) * platform;
+ *   polygon  across-track angle a = -A + 2A frac(f t) (a sawtooth);
+ *   swing    a = A sin(2 pi f t);
+ *   fibre    a = -A + 2A (k mod N) / (N - 1), N fibres fired in turn;
+ *            for these three the direction is (0, sin a, -cos a);
+ *   conic    (sin A cos p, sin A sin p, -cos A), p = 2 pi frac(f t);
+ *   noise    the origin gets independent N(0, sigma^2) offsets per axis:
+ *            Box-Muller on uniforms u = ((x >> 11) + 1) 2^-53 of SplitMix64
+ *            output number c = 6k + 2 axis (+1) of the sequence seeded with
+ *            `seed` (Steele, Lea & Flood 2014: output c mixes seed + (c + 1)
+ *            times 0x9E3779B97F4A7C15). */
+enum { ORC_DEFLECT_POLYGON = 0, ORC_DEFLECT_SWING = 1, ORC_DEFLECT_CONIC = 2, ORC_DEFLECT_FIBRE = 3 };
+
+typedef struct {
+    const double* waypoints; /* [n][3] */
+    int32_t n_waypoints;
+    int32_t deflector;
+    double speed;            /* m/s */
+    double prf;              /* pulses per second */
+    double scan_freq;        /* lines (polygon), oscillations (swing), revolutions (conic) per second */
+    double scan_angle;       /* A: half the line's angle, or the cone's angle off nadir (rad) */
+    int32_t n_fibres;
+    int32_t pad_;
+    double t0;
+    double noise_sigma;      /* m */
+    uint64_t seed;
+} orc_survey;
+
+uint64_t orc_splitmix64(uint64_t seed, uint64_t c)
+{
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double sm_uniform(uint64_t seed, uint64_t c)
+{
+    return (double)((orc_splitmix64(seed, c) >> 11) + 1) * (1.0 / 9007199254740992.0);
+}
+
+/* Pulses [first, first + count): origins [count][3], directions [count][3]
+ * (unit, FP64).  Returns 0, or -1 for an invalid survey. */
+int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, double* origins, double* dirs)
+{
+    int nw = sv->n_waypoints;
+    if (nw < 1 || !(sv->prf > 0.0)) return -1;
+    if (sv->deflector == ORC_DEFLECT_FIBRE && sv->n_fibres < 2) return -1;
+    double* cum = (double*)malloc(sizeof(double) * (size_t)nw);
+    cum[0] = 0.0;
+    for (int i = 1; i < nw; ++i) {
+        const double* a = sv->waypoints + 3 * (i - 1);
+        const double* b = sv->waypoints + 3 * i;
+        double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+        cum[i] = cum[i - 1] + sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    for (int64_t q = 0; q < count; ++q) {
+        int64_t k = first + q;
+        double t = sv->t0 + (double)k / sv->prf;
+        /* position along the path and heading of the current leg */
+        double pos[3] = {sv->waypoints[0], sv->waypoints[1], sv->waypoints[2]};
+        double yaw = 0.0;
+        if (nw >= 2) {
+            double sdist = sv->speed * t;
+            int leg = 0;
+            while (leg + 2 < nw && cum[leg + 1] <= sdist) ++leg;
+            const double* a = sv->waypoints + 3 * leg;
+            const double* b = sv->waypoints + 3 * (leg + 1);
+            double len = cum[leg + 1] - cum[leg];
+            double f = len > 0.0 ? (sdist - cum[leg]) / len : 0.0;
+            if (f < 0.0) f = 0.0;
+            if (f > 1.0) f = 1.0;
+            for (int i = 0; i < 3; ++i) pos[i] = a[i] + f * (b[i] - a[i]);
+            yaw = atan2(b[1] - a[1], b[0] - a[0]);
+        }
+        if (sv->noise_sigma > 0.0) {
+            for (int ax = 0; ax < 3; ++ax) {
+                uint64_t c = 6 * (uint64_t)k + 2 * (uint64_t)ax;
+                double u1 = sm_uniform(sv->seed, c), u2 = sm_uniform(sv->seed, c + 1);
+                pos[ax] += sv->noise_sigma * sqrt(-2.0 * log(u1)) * cos(2.0 * ORC_PI * u2);
+            }
+        }
+        /* direction in the platform frame */
+        double A = sv->scan_angle, d[3];
+        double ph = sv->scan_freq * t;
+        ph -= floor(ph);
+        if (sv->deflector == ORC_DEFLECT_CONIC) {
+            double p = 2.0 * ORC_PI * ph;
+            d[0] = sin(A) * cos(p);
+            d[1] = sin(A) * sin(p);
+            d[2] = -cos(A);
+        } else {
+            double ang;
+            if (sv->deflector == ORC_DEFLECT_POLYGON) ang = -A + 2.0 * A * ph;
+            else if (sv->deflector == ORC_DEFLECT_SWING) ang = A * sin(2.0 * ORC_PI * sv->scan_freq * t);
+            else ang = -A + 2.0 * A * (double)(k % sv->n_fibres) / (double)(sv->n_fibres - 1);
+            d[0] = 0.0;
+            d[1] = sin(ang);
+            d[2] = -cos(ang);
+        }
+        double cy = cos(yaw), sy = sin(yaw);
+        double* o = origins + 3 * q;
+        double* w = dirs + 3 * q;
+        for (int i = 0; i < 3; ++i) o[i] = pos[i];
+        w[0] = cy * d[0] - sy * d[1];
+        w[1] = sy * d[0] + cy * d[1];
+        w[2] = d[2];
+    }
+    free(cum);
+    return 0;
 }
 
 int orc_max_threads(void)
