@@ -20,6 +20,7 @@ library (vls_trace_counts).
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -365,6 +366,40 @@ def main():
                          "fitted": int(torch.isfinite(width).sum().item()),
                          "step_with_echo_width_over_step": (ms + ew_ms) / ms,
                          "paper_runtime_factor": 1.3}
+    # pulses generated on the device from a survey (Sec. 3.2, 3.3): a flight
+    # line 500 m above the terrain with a polygon mirror of +-30 deg, 1,000 pulses
+    # per line, as many pulses as the workload; then one step on them
+    log("pulse generation")
+    ext = mesh.info["extent"]
+    z = mesh.info["heights_mean"] + 500.0
+    survey = dict(waypoints=[[0.05 * ext, 0.5 * ext, z], [0.95 * ext, 0.5 * ext, z]], deflector="polygon",
+                  speed_mps=60.0, pulse_rate_hz=1.0e6, scan_freq_hz=1.0e3, scan_angle_rad=math.radians(30.0),
+                  platform_noise_m=0.02, seed=2021)
+    go = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    gd = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    ctx.generate_pulses(survey, 0, n, origins=go, directions=gd)
+    ctx.simulate(scene, sc, go, gd, out=out)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.generate_pulses(survey, 0, n, origins=go, directions=gd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gen_ms = e0.elapsed_time(e1) / args.steps
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.generate_pulses(survey, 0, n, origins=go, directions=gd)
+        ctx.simulate(scene, sc, go, gd, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gstep_ms = e0.elapsed_time(e1) / args.steps
+    res["pulse_generation"] = {"survey": "LinearPath 500 m above mean ground across the scene, polygon mirror "
+                                         "+-30 deg, 1e6 pulses/s, 1e3 lines/s, platform noise 2 cm",
+                               "ms": gen_ms, "pulses_per_s": n / (gen_ms * 1e-3),
+                               "bytes_written_per_pulse": 36,
+                               "achieved_GBps": 36.0 * n / (gen_ms * 1e-3) / 1e9,
+                               "step_with_generation_ms": gstep_ms,
+                               "subrays_per_s_with_generation": n * S / (gstep_ms * 1e-3)}
     res["autotune"] = tune
     if not args.only_plain:
         log("batched workload")

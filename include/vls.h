@@ -258,6 +258,55 @@ vls_status vls_waveform(vls_context ctx, const vls_scanner_desc* scanners, int32
 vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners,
                        const vls_pulse_batch* pulses, const vls_outputs* out, void* stream);
 
+/* ------------------------------------------------------------------ surveys */
+
+/* Scan deflectors (Sec. 3.3, Fig. 7). */
+enum { VLS_DEFLECT_POLYGON = 0, VLS_DEFLECT_SWING = 1, VLS_DEFLECT_CONIC = 2, VLS_DEFLECT_FIBRE = 3 };
+
+/* A survey: a platform (Sec. 3.2) carrying a scanner with a deflector (Sec.
+ * 3.3).  The paper gives the platforms' and deflectors' behaviour but no
+ * formulas; the model:
+ *   pulse k leaves at t = t0_s + k / pulse_rate_hz;
+ *   LinearPath platform (n_waypoints >= 2): covers the polyline at speed_mps
+ *   from the first waypoint at t = 0, level, facing the current leg's
+ *   horizontal direction, and stays at the last waypoint afterwards; one
+ *   waypoint: static, facing +x;
+ *   platform frame x forward, y left, z up; with A = scan_angle_rad and
+ *   f = scan_freq_hz the beam points along (0, sin a, -cos a) with
+ *     POLYGON a = -A + 2A frac(f t)        (parallel lines, even density)
+ *     SWING   a = A sin(2 pi f t)          (zig-zag, denser at the extremes)
+ *     FIBRE   a = -A + 2A (k mod n_fibres) / (n_fibres - 1)
+ *   or, CONIC (Palmer), along (sin A cos p, sin A sin p, -cos A), p = 2 pi frac(f t);
+ *   platform_noise_m > 0 adds independent N(0, sigma^2) offsets per axis to
+ *   each origin, from SplitMix64 (Steele, Lea & Flood 2014) outputs
+ *   6k + 2 axis and 6k + 2 axis + 1 of the sequence seeded with `seed`
+ *   (Box-Muller), so any range of pulses can be generated on its own.
+ * waypoints: [n_waypoints][3] float64 in host memory, finite, consecutive ones
+ * distinct; copied (the library caches one device table per distinct survey). */
+typedef struct {
+    const double* waypoints;
+    int32_t n_waypoints;
+    int32_t deflector;
+    double speed_mps;
+    double pulse_rate_hz;
+    double scan_freq_hz;
+    double scan_angle_rad;
+    int32_t n_fibres;
+    int32_t reserved;
+    double t0_s;
+    double platform_noise_m;
+    uint64_t seed;
+} vls_survey_desc;
+
+/* Pulses [first, first + count) of a survey, on the device, in the layout
+ * vls_simulate takes: origins [count][3] float64, directions [count][3]
+ * float32 (unit), both device arrays.  Enqueued on `stream` (the first call
+ * with a new survey uploads its table synchronously).  Errors:
+ * VLS_ERR_INVALID_ARG for an invalid survey, a negative range or missing or
+ * misaligned outputs. */
+vls_status vls_generate_pulses(vls_context ctx, const vls_survey_desc* survey, int64_t first, int64_t count,
+                               double* origins, float* directions, void* stream);
+
 /* Echo width (Sec. 3.4: an optional Gaussian fitted by non-linear least squares
  * to the waveform of each return, whose standard deviation is the return's
  * width; the return's position stays the local maximum).  For every kept

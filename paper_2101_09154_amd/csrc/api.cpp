@@ -155,6 +155,11 @@ struct vls_context_s {
     long long cand_pulses = 0;
     int* ew = nullptr;           // echo-width list of returns + counter, grown on demand
     long long ew_entries = 0;
+    struct SurveyTab {
+        std::vector<double> key;   // the host table it was made from
+        double* dev = nullptr;
+    };
+    std::vector<SurveyTab> surveys;  // device waypoint tables, one per distinct survey
     // kernel timing (vls_profile_*): event pairs recorded around the cone pass
     // and the fused kernel of eager vls_simulate calls, and a pool of spares
     bool prof = false;
@@ -169,6 +174,7 @@ struct vls_context_s {
             }
         (void)hipFree(cand);
         (void)hipFree(ew);
+        for (auto& t : surveys) (void)hipFree(t.dev);
         for (auto& kv : patterns) (void)hipFree(kv.second);
         for (auto& b : batches) (void)hipFree(b.dev);
     }
@@ -785,6 +791,88 @@ vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_
                        const vls_pulse_batch* pulses, const vls_outputs* out, void* stream)
 {
     return wave_common(ctx, scanners, n_scanners, pulses, out, stream, 1);
+}
+
+vls_status vls_generate_pulses(vls_context ctx, const vls_survey_desc* sv, int64_t first, int64_t count,
+                               double* origins, float* directions, void* stream)
+{
+    try {
+        if (!ctx || !sv) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+        if (count < 0 || first < 0) return fail(VLS_ERR_INVALID_ARG, "negative pulse range");
+        if (sv->n_waypoints < 1 || !sv->waypoints) return fail(VLS_ERR_INVALID_ARG, "need at least one waypoint");
+        if (sv->deflector < VLS_DEFLECT_POLYGON || sv->deflector > VLS_DEFLECT_FIBRE)
+            return fail(VLS_ERR_INVALID_ARG, "unknown deflector");
+        if (!(sv->pulse_rate_hz > 0.0) || !std::isfinite(sv->pulse_rate_hz))
+            return fail(VLS_ERR_INVALID_ARG, "pulse_rate_hz must be positive");
+        if (!(sv->speed_mps >= 0.0) || !std::isfinite(sv->speed_mps) || !std::isfinite(sv->scan_freq_hz) ||
+            !std::isfinite(sv->scan_angle_rad) || !std::isfinite(sv->t0_s) || !(sv->platform_noise_m >= 0.0) ||
+            !std::isfinite(sv->platform_noise_m))
+            return fail(VLS_ERR_INVALID_ARG, "survey parameters must be finite (speed and noise >= 0)");
+        if (sv->deflector == VLS_DEFLECT_FIBRE && sv->n_fibres < 2)
+            return fail(VLS_ERR_INVALID_ARG, "a fibre array needs at least two fibres");
+        if (count == 0) return VLS_OK;
+        if (!origins || !directions) return fail(VLS_ERR_INVALID_ARG, "origins and directions are required");
+        if (!aligned(origins, 8) || !aligned(directions, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned output");
+        // per-waypoint table: position, cumulative length, cos and sin of the
+        // heading of the leg that starts there (host FP64)
+        const int nw = sv->n_waypoints;
+        std::vector<double> tab(6 * (size_t)nw);
+        double cum = 0.0;
+        for (int i = 0; i < nw; ++i) {
+            const double* a = sv->waypoints + 3 * i;
+            for (int c = 0; c < 3; ++c) {
+                if (!std::isfinite(a[c])) return fail(VLS_ERR_INVALID_ARG, "non-finite waypoint");
+                tab[6 * i + c] = a[c];
+            }
+            if (i > 0) {
+                const double* p = sv->waypoints + 3 * (i - 1);
+                const double dx = a[0] - p[0], dy = a[1] - p[1], dz = a[2] - p[2];
+                const double len = std::sqrt(dx * dx + dy * dy + dz * dz);
+                if (!(len > 0.0)) return fail(VLS_ERR_INVALID_ARG, "consecutive waypoints coincide");
+                cum = cum + len;
+            }
+            tab[6 * i + 3] = cum;
+            double yaw = 0.0;
+            if (i + 1 < nw) {
+                const double* b = sv->waypoints + 3 * (i + 1);
+                yaw = std::atan2(b[1] - a[1], b[0] - a[0]);
+            }
+            tab[6 * i + 4] = nw >= 2 ? std::cos(yaw) : 1.0;
+            tab[6 * i + 5] = nw >= 2 ? std::sin(yaw) : 0.0;
+        }
+        double* dtab = nullptr;
+        for (auto& t : ctx->surveys)
+            if (t.key == tab) dtab = t.dev;
+        if (!dtab) {
+            vls_context_s::SurveyTab t;
+            VLS_HIP(hipMalloc(&t.dev, sizeof(double) * tab.size()), "survey table");
+            hipError_t e = hipMemcpy(t.dev, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(t.dev);
+                return hip_fail(e, "survey table upload");
+            }
+            t.key = tab;
+            dtab = t.dev;
+            ctx->surveys.push_back(std::move(t));
+        }
+        SurveyDev d;
+        d.n_wp = nw;
+        d.deflector = sv->deflector;
+        d.n_fibres = sv->n_fibres;
+        d.pad_ = 0;
+        d.speed = sv->speed_mps;
+        d.prf = sv->pulse_rate_hz;
+        d.freq = sv->scan_freq_hz;
+        d.angle = sv->scan_angle_rad;
+        d.t0 = sv->t0_s;
+        d.noise = sv->platform_noise_m;
+        d.seed = sv->seed;
+        hipError_t e = launch_generate(d, dtab, first, count, origins, directions, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "pulse generation launch");
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
 }
 
 vls_status vls_echo_width(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners,

@@ -1,0 +1,124 @@
+// Pulses generated on the GPU from a survey (Sec. 3.2 platforms, Sec. 3.3 scan
+// deflectors), so that a scan needs no host arrays of origins and directions.
+//
+// The paper describes the platforms and deflectors and their patterns but gives
+// no formulas; the model here: pulse k leaves at t = t0 + k / prf; a LinearPath
+// platform covers its polyline of waypoints at constant speed from t = 0, stays
+// level, faces the current leg's horizontal direction, and stays at the last
+// waypoint afterwards (one waypoint: static, facing +x).  In the platform frame
+// (x forward, y left, z up) the beam points, for an across-track angle a, along
+// (0, sin a, -cos a), with a = -A + 2A frac(f t) (polygon mirror: parallel lines
+// of even density), A sin(2 pi f t) (swinging mirror: a zig-zag, denser at the
+// extremes) or -A + 2A (k mod N) / (N - 1) (fibre array: N fixed directions
+// fired in turn); a Palmer (conic) scanner points along (sin A cos p,
+// sin A sin p, -cos A), p = 2 pi frac(f t).  Platform noise adds independent
+// N(0, sigma^2) offsets per axis to the origin: Box-Muller on uniforms
+// ((x >> 11) + 1) 2^-53 of SplitMix64 (Steele, Lea & Flood 2014) outputs
+// number 6k + 2 axis and 6k + 2 axis + 1 of the sequence seeded with the
+// survey's seed, so any pulse can be generated on its own.
+//
+// One thread per pulse; all arithmetic in FP64, directions stored as FP32.  The
+// per-leg table (waypoint, cumulative length, cos and sin of the heading) is
+// computed on the host.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "vls_internal.h"
+
+namespace vls {
+namespace {
+
+__device__ __forceinline__ uint64_t sm64(uint64_t seed, uint64_t c)
+{
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double sm_uniform(uint64_t seed, uint64_t c)
+{
+    return (double)((sm64(seed, c) >> 11) + 1) * (1.0 / 9007199254740992.0);
+}
+
+// tab: per waypoint i, [x, y, z, cumulative length, cos yaw, sin yaw] of the
+// leg that starts there (the last entry's yaw is unused).
+__global__ __launch_bounds__(256) void k_generate(SurveyDev sv, const double* __restrict__ tab, long long first,
+                                                  long long count, double* __restrict__ origins,
+                                                  float* __restrict__ dirs)
+{
+#pragma clang fp contract(off)
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const long long k = first + q;
+    const double t = sv.t0 + (double)k / sv.prf;
+    double pos[3] = {tab[0], tab[1], tab[2]};
+    double cy = 1.0, sy = 0.0;
+    if (sv.n_wp >= 2) {
+        const double sd = sv.speed * t;
+        // the last leg whose start lies at or before sd (the first leg before it)
+        int lo = 0, hi = sv.n_wp - 2;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[6 * mid + 3] <= sd) lo = mid;
+            else hi = mid - 1;
+        }
+        const double* a = tab + 6 * lo;
+        const double* b = tab + 6 * (lo + 1);
+        const double len = b[3] - a[3];
+        double f = len > 0.0 ? (sd - a[3]) / len : 0.0;
+        if (f < 0.0) f = 0.0;
+        if (f > 1.0) f = 1.0;
+        for (int i = 0; i < 3; ++i) pos[i] = a[i] + f * (b[i] - a[i]);
+        cy = a[4];
+        sy = a[5];
+    }
+    if (sv.noise > 0.0) {
+        for (int ax = 0; ax < 3; ++ax) {
+            const uint64_t c = 6 * (uint64_t)k + 2 * (uint64_t)ax;
+            const double u1 = sm_uniform(sv.seed, c), u2 = sm_uniform(sv.seed, c + 1);
+            pos[ax] += sv.noise * sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+        }
+    }
+    const double A = sv.angle;
+    double ph = sv.freq * t;
+    ph -= floor(ph);
+    double d0, d1, d2;
+    if (sv.deflector == 2) {
+        const double p = 2.0 * M_PI * ph;
+        d0 = sin(A) * cos(p);
+        d1 = sin(A) * sin(p);
+        d2 = -cos(A);
+    } else {
+        double ang;
+        if (sv.deflector == 0) ang = -A + 2.0 * A * ph;
+        else if (sv.deflector == 1) ang = A * sin(2.0 * M_PI * sv.freq * t);
+        else ang = -A + 2.0 * A * (double)(k % sv.n_fibres) / (double)(sv.n_fibres - 1);
+        d0 = 0.0;
+        d1 = sin(ang);
+        d2 = -cos(ang);
+    }
+    double* o = origins + 3 * q;
+    float* w = dirs + 3 * q;
+    o[0] = pos[0];
+    o[1] = pos[1];
+    o[2] = pos[2];
+    w[0] = (float)(cy * d0 - sy * d1);
+    w[1] = (float)(sy * d0 + cy * d1);
+    w[2] = (float)d2;
+}
+
+}  // namespace
+
+hipError_t launch_generate(const SurveyDev& sv, const double* tab, long long first, long long count,
+                           double* origins, float* dirs, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_generate, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream, sv, tab, first,
+                       count, origins, dirs);
+    return hipGetLastError();
+}
+
+}  // namespace vls

@@ -115,6 +115,16 @@ struct BatchDev {
     long long n_tiles;
 };
 
+// A survey as the pulse generator sees it (see survey.hip).
+struct SurveyDev {
+    int n_wp;
+    int deflector;   // 0 polygon, 1 swing, 2 conic, 3 fibre
+    int n_fibres;
+    int pad_;
+    double speed, prf, freq, angle, t0, noise;
+    uint64_t seed;
+};
+
 struct LaunchCfg {
     int block_waves = 1;
     int stack_lds = 16;
@@ -184,6 +194,9 @@ hipError_t launch_packets(const SceneDev& scene, const ScannerDev& sc0, const Ba
 hipError_t launch_echo_width(const ScannerDev& sc, const float* wf, const int32_t* n_ret, const int32_t* ret_bin,
                              float s0_bins, long long first, long long count, int* list,
                              unsigned long long* list_ctr, float* width, hipStream_t stream);
+// Pulses [first, first + count) of a survey; tab: per-waypoint table (see survey.hip).
+hipError_t launch_generate(const SurveyDev& sv, const double* tab, long long first, long long count,
+                           double* origins, float* dirs, hipStream_t stream);
 // Candidate lists hold leaf indices; rewrite them as original triangle indices.
 hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_pulses, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);

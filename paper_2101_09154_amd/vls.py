@@ -71,6 +71,15 @@ class LaunchConfig(ctypes.Structure):
                 ("cone", i32), ("reserved", i32)]
 
 
+class SurveyDesc(ctypes.Structure):
+    _fields_ = [("waypoints", P), ("n_waypoints", i32), ("deflector", i32), ("speed_mps", f64),
+                ("pulse_rate_hz", f64), ("scan_freq_hz", f64), ("scan_angle_rad", f64), ("n_fibres", i32),
+                ("reserved", i32), ("t0_s", f64), ("platform_noise_m", f64), ("seed", ctypes.c_uint64)]
+
+
+DEFLECTORS = {"polygon": 0, "swing": 1, "conic": 2, "fibre": 3}
+
+
 class Profile(ctypes.Structure):
     _fields_ = [("cone_ms", f64), ("fused_ms", f64), ("cone_launches", ctypes.c_int64),
                 ("fused_launches", ctypes.c_int64), ("packet_ms", f64), ("packet_launches", ctypes.c_int64)]
@@ -100,6 +109,7 @@ _SIGS = {
     "vls_waveform": ([P, P, i32, P, P, P], i32),
     "vls_returns": ([P, P, i32, P, P, P], i32),
     "vls_echo_width": ([P, P, i32, P, P, P, P], i32),
+    "vls_generate_pulses": ([P, P, ctypes.c_int64, ctypes.c_int64, P, P, P], i32),
     "vls_simulate": ([P, P, P, i32, P, P, P], i32),
     "vls_set_launch_config": ([P, P], i32),
     "vls_get_launch_config": ([P, P], i32),
@@ -473,6 +483,28 @@ class Context:
         o = self._outputs(out)
         _check(lib().vls_returns(self._h, arr, ns, ctypes.byref(b), ctypes.byref(o), _stream(stream)))
         return out
+
+    def generate_pulses(self, survey, first, count, *, origins=None, directions=None, device=0, stream=None):
+        """Pulses [first, first + count) of a survey (dict: waypoints, deflector, speed_mps,
+        pulse_rate_hz, scan_freq_hz, scan_angle_rad, n_fibres, t0_s, platform_noise_m, seed)
+        generated on the device: (origins float64 [count, 3], directions float32 [count, 3])."""
+        wp = np.ascontiguousarray(survey["waypoints"], dtype=np.float64).reshape(-1, 3)
+        desc = SurveyDesc(wp.ctypes.data, wp.shape[0], DEFLECTORS[survey.get("deflector", "polygon")],
+                          float(survey.get("speed_mps", 0.0)), float(survey["pulse_rate_hz"]),
+                          float(survey.get("scan_freq_hz", 0.0)), float(survey.get("scan_angle_rad", 0.0)),
+                          int(survey.get("n_fibres", 0)), 0, float(survey.get("t0_s", 0.0)),
+                          float(survey.get("platform_noise_m", 0.0)), int(survey.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF)
+        dev = torch.device("cuda", device) if isinstance(device, int) else device
+        if origins is None:
+            origins = torch.empty((count, 3), dtype=torch.float64, device=dev)
+        if directions is None:
+            directions = torch.empty((count, 3), dtype=torch.float32, device=dev)
+        _dev(origins, torch.float64, (count, 3), "origins")
+        _dev(directions, torch.float32, (count, 3), "directions")
+        _check(lib().vls_generate_pulses(self._h, ctypes.byref(desc), int(first), int(count), _ptr(origins),
+                                         _ptr(directions), _stream(stream)))
+        del wp
+        return origins, directions
 
     def echo_width(self, scanners, origins, directions, out, *, width=None, segment_offsets=None,
                    segment_scanner=None, stream=None):

@@ -769,6 +769,50 @@ def test_echo_width_batched_and_full_size(ctx):
     assert np.all(np.isnan(w.cpu().numpy()[out["n_returns"].cpu().numpy() == 0]))
 
 
+# ------------------------------------------------------------------ pulses from a survey (Sec. 3.2, 3.3)
+
+_WP = [[2.0, 3.0, 40.0], [60.0, 5.0, 42.0], [30.0, 58.0, 45.0], [5.0, 20.0, 40.0]]
+
+
+@pytest.mark.parametrize("deflector,noise,static", [("polygon", 0.0, False), ("swing", 0.0, False),
+                                                    ("conic", 0.03, False), ("fibre", 0.0, True),
+                                                    ("polygon", 0.05, True)])
+def test_generated_pulses_match_oracle(ctx, deflector, noise, static):
+    sv = dict(waypoints=_WP[:1] if static else _WP, deflector=deflector, speed_mps=25.0, pulse_rate_hz=4000.0,
+              scan_freq_hz=37.0, scan_angle_rad=0.45, n_fibres=9, t0_s=0.125, platform_noise_m=noise, seed=77)
+    first, count = 1234, 30001              # ragged, and past the end of the path
+    o, d = ctx.generate_pulses(sv, first, count)
+    torch.cuda.synchronize()
+    ro, rd = oracle.generate_pulses(dict(sv, t0=sv["t0_s"]), first, count)
+    o = o.cpu().numpy()
+    d = d.cpu().numpy().astype(np.float64)
+    say("generated", deflector, noise, static, "max |do| %.2e max |dd| %.2e"
+        % (np.abs(o - ro).max(), np.abs(d - rd).max()))
+    # FP64 both sides: only the device's sin, cos and log differ in the last bits
+    assert np.abs(o - ro).max() <= 1e-9
+    assert np.abs(d - rd).max() <= 2e-7          # FP32 directions
+    assert np.allclose(np.linalg.norm(d, axis=1), 1.0, atol=3e-7)
+
+
+def test_simulate_on_generated_pulses(ctx):
+    # an airborne survey over the small terrain, generated on the device and
+    # simulated there; the oracle simulates the same pulses
+    mesh, _, sc = configs.small_tls()
+    sv = dict(waypoints=[[4.0, 8.0, 120.0], [60.0, 8.0, 120.0], [60.0, 40.0, 120.0], [4.0, 40.0, 120.0]],
+              deflector="polygon", speed_mps=30.0, pulse_rate_hz=2000.0, scan_freq_hz=40.0, scan_angle_rad=0.3,
+              platform_noise_m=0.02, seed=5)
+    sc = dict(sc, n_subrays=31, divergence_rad=0.5e-3, n_bins=256, bin_ns=0.5)
+    o, d = ctx.generate_pulses(sv, 0, 6000)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    out = ctx.simulate(scene, sc, o, d)
+    torch.cuda.synchronize()
+    pulses = synth.Pulses(o.cpu().numpy(), d.cpu().numpy())
+    g = to_np(out)
+    sel = np.arange(0, pulses.n, 13)
+    rep = compare(mesh, pulses.subset(sel), sc, {k: v[sel] for k, v in g.items()}, label="generated")
+    assert (g["n_returns"] > 0).mean() > 0.3
+
+
 def test_cone_candidates_contain_every_hit(ctx):
     # the candidate list of a pulse holds the closest-hit triangle of every one
     # of its subrays (found here by per-subray traversal), unless it overflowed
