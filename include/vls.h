@@ -55,7 +55,7 @@ enum { VLS_PULSE_GAUSSIAN = 0, VLS_PULSE_EQ3 = 1 };
 #define VLS_MAX_BINS 1024       /* waveform bins per pulse                       */
 #define VLS_MAX_RETURNS 16      /* returns kept per pulse                        */
 #define VLS_MAX_SCANNERS 64     /* scanner descriptions per batched call         */
-#define VLS_MAX_CANDIDATES 63   /* triangles the cone pass lists per pulse       */
+#define VLS_MAX_CANDIDATES 255  /* triangles the cone pass lists per pulse       */
 
 const char* vls_status_string(vls_status s);
 /* Detail of the last failure on the calling thread; valid until the next vls_* call there. */

@@ -16,7 +16,7 @@
 // one triangle strictly inside it, every subray (its direction lies inside that
 // pyramid) hits that triangle, at an axial distance no larger than the largest
 // corner distance; nodes that start beyond it cannot hold a closest hit.
-// A pulse with more than kCandMax (63) candidates is marked for full per-subray
+// A pulse with more than kCandMax (255) candidates is marked for full per-subray
 // traversal.
 #include <hip/hip_runtime.h>
 

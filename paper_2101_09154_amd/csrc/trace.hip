@@ -379,18 +379,17 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
             }
         }
     } else {
-        if (nc >= 0 || nc <= kWalked) {
+        if (nc >= 0 || nc == kWalked) {
             // the pulse's candidates, or the one leaf a packet walk found for
             // this subray (-1: none)
             const int* ids = pulses.cand + p * (kCandMax + 1) + 1;
-            int cnt = nc, last = -1;
-            if (nc <= kWalked) {
+            int cnt = nc;
+            if (nc == kWalked) {
                 cnt = 1;
-                if (k < kCandMax) ids += k;
-                else last = kWalked - 1 - nc;
+                ids += k;
             }
             for (int i = 0; i < cnt; ++i) {
-                const int li = last >= 0 ? last : ids[i];
+                const int li = ids[i];
                 if (li >= 0 && li < scene.n_tri) leaf_test(r, scene.tris, li, h);
             }
             if (COUNT) tests += cnt;
@@ -807,8 +806,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 
 // Pulses with more candidates than a list holds: one wavefront per pulse walks
 // the tree with all of the pulse's subrays as a packet and writes each subray's
-// closest leaf (or -1) into the pulse's candidate row, with a count word of
-// kWalked or below; the fused kernel then tests that one leaf per subray.
+// closest leaf (or -1) into the pulse's candidate row, with the count word
+// kWalked; the fused kernel then tests that one leaf per subray.
 // `list` holds the pulses (indices from `first`) and ctr[0] their number, both
 // written by the cone pass; past one pulse per wavefront of the grid, the
 // wavefronts take pulses from ctr[1] until the list is done.  Scanners: sc0, or per segment of `batch` when batch.n_seg > 0.
@@ -848,12 +847,9 @@ __global__ __launch_bounds__(256) void k_packets(SceneDev scene, ScannerDev sc0,
         h.leaf = -1;
         h.orig = 0x7fffffff;
         if (__ballot(on)) packet_walk<false>(scene, r, on, h, stack, kPacketCap, visits, tests);
-        // the row holds kCandMax leaves; with 64 subrays the last one is folded
-        // into the count word: kWalked - 1 - leaf (kWalked itself when it is -1)
         int* row = cand + p * (kCandMax + 1);
-        const int last = __builtin_amdgcn_readlane(h.leaf, kWave - 1);
-        if (lane < S && lane < kCandMax) row[1 + lane] = h.leaf;
-        if (lane == 0) row[0] = kWalked - 1 - (S > kCandMax ? last : -1);
+        if (lane < S) row[1 + lane] = h.leaf;
+        if (lane == 0) row[0] = kWalked;
         unsigned long long t = 0;
         if (lane == 0) t = atomicAdd(ctr + 1, 1ull);
         const unsigned t_lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)t);

@@ -13,10 +13,11 @@ constexpr double kCmPerNs = 0.299792458;  // speed of light in m/ns (Sec. 3.4)
 constexpr int kWave = 64;                 // CDNA wavefront
 constexpr int kMaxSpill = 112;            // traversal-stack entries per lane beyond the LDS ring
 constexpr int kMaxRing = 32;
-constexpr int kCandMax = 63;             // candidate leaves kept per pulse by the cone pass
+constexpr int kCandMax = 255;            // candidate leaves kept per pulse by the cone pass
+static_assert(kCandMax >= kWave, "a packet walk writes one leaf per subray into the row");
 constexpr int kEmpty4 = 0x7fffffff;       // unused slot of a four-wide record
 constexpr int kConeRing = 16;            // LDS stack entries per lane of the cone pass
-constexpr int kWalked = -2;              // count word <= kWalked: the row holds one leaf per subray
+constexpr int kWalked = -2;              // count word kWalked: the row holds one leaf per subray
 constexpr int kPacketCap = 128;          // stack entries of a packet walk (3 per four-wide level)
 
 // Cone-pass workspace for n pulses: candidate rows [n][kCandMax + 1], then the
@@ -81,7 +82,7 @@ struct PulsesDev {
     long long n;
     const double* basis;    // [n][5] each pulse's basis from the cone pass (n, a, b), or null
     const int* cand;        // [n][kCandMax + 1] candidate leaves from the cone pass, or null:
-                            // entry 0 = count (-1 = overflow, use full traversal; <= kWalked:
+                            // entry 0 = count (-1 = overflow, use full traversal; kWalked:
                             // one leaf per subray from a packet walk), then leaf ids
 };
 

@@ -18,7 +18,7 @@ OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "device error", 4: "not built",
           5: "unsupported", 6: "internal error"}
 MEM_HOST = 0
-MAX_CANDIDATES = 63  # VLS_MAX_CANDIDATES: triangles the cone pass lists per pulse
+MAX_CANDIDATES = 255  # VLS_MAX_CANDIDATES: triangles the cone pass lists per pulse
 MEM_DEVICE = 1
 PULSE_GAUSSIAN = 0
 PULSE_EQ3 = 1

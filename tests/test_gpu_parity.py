@@ -662,19 +662,19 @@ def test_cone_pass_bitwise_on_buildings(ctx):
 
 @pytest.mark.parametrize("S", [61, 64])
 def test_packet_walk_bitwise_on_trees(ctx, S):
-    # vegetation overflows many candidate lists: those pulses are walked as
-    # packets (64 subrays: the last subray's leaf sits in the count word); every
+    # vegetation with a wide beam overflows many candidate lists: those pulses
+    # are walked as packets (64 subrays: every lane's leaf in the row); every
     # output must equal per-subray traversal with the cone pass off
     mesh = configs.uls_scene()
     scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
     _, pulses, sc = configs.uls_trees(mesh=mesh, strips=2, n_lines=12, per_line=500)
-    sc = dict(sc, n_subrays=S, divergence_rad=1.0e-3)
+    sc = dict(sc, n_subrays=S, divergence_rad=6.0e-3)
     o = _dev(pulses.origins)
     d = _dev(pulses.directions)
     cand = ctx.cone_candidates(scene, sc, o, d).cpu().numpy()
     ovf = (cand[:, 0] < 0).mean()
     say("packet walk: S", S, "pulses", pulses.n, "overflowed %.3f" % ovf)
-    assert ovf > 0.05
+    assert ovf > 0.02
     res = []
     for cone in (1, 0):
         ctx.set_launch_config(cone=cone)
