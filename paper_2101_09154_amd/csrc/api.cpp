@@ -301,13 +301,12 @@ struct Prepared {
     std::vector<int32_t> seg_sc;
 };
 
-// Largest pulses-per-wavefront among the scanners whose candidates are staged in
-// LDS (those with at most 4 pulses per wavefront), or 0.
-int staged_pw(const Prepared& pr)
+// The most candidate records any of the scanners stages in LDS per wavefront
+// (pulses per wavefront times staged_per_pulse), or 0.
+int staged_slots(const Prepared& pr)
 {
     int m = 0;
-    for (const auto& s : pr.sc)
-        if (s.P_w <= 4) m = std::max(m, s.P_w);
+    for (const auto& s : pr.sc) m = std::max(m, s.P_w * staged_per_pulse(s.P_w));
     return m;
 }
 
@@ -930,7 +929,7 @@ static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_s
     if (pulses->n_pulses > 0 && pulses->n_segments > 0) {
         if ((st = batch_tables(ctx, pr, bt)) != VLS_OK) return st;
         blocks = ctx->cfg.persistent_blocks > 0 ? ctx->cfg.persistent_blocks
-                                                : persistent_occupancy_blocks(pr.n_bins, staged_pw(pr), ctx->cfg);
+                                                : persistent_occupancy_blocks(pr.n_bins, staged_slots(pr), ctx->cfg);
     }
     return VLS_OK;
 }
@@ -998,7 +997,7 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
     }
     if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
     if (!bt) e = launch_simulate(sd, pr.sc[0], pd, od, 0, pulses->n_pulses, 1, ctx->cfg, s);
-    else e = launch_persistent(sd, bt->bd, pr.n_bins, staged_pw(pr), pd, od, ctx->cfg, blocks, s);
+    else e = launch_persistent(sd, bt->bd, pr.n_bins, staged_slots(pr), pd, od, ctx->cfg, blocks, s);
     if (e != hipSuccess) return hip_fail(e, "simulate launch");
     if (prof && (e = prof_end(ctx, s, ev, ctx->prof_fused)) != hipSuccess) return hip_fail(e, "timing event");
     return VLS_OK;
@@ -1237,7 +1236,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
         } else {
             int tried = 1;
             const bool seg = pulses->n_segments > 0;
-            int auto_blocks = seg ? persistent_occupancy_blocks(pr0.n_bins, staged_pw(pr0), entry) : 0;
+            int auto_blocks = seg ? persistent_occupancy_blocks(pr0.n_bins, staged_slots(pr0), entry) : 0;
             for (int dim = 0; dim < 5; ++dim) {
                 std::vector<LaunchCfg> cand;
                 for (int v = 0; v < 4; ++v) {

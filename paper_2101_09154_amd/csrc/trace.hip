@@ -54,12 +54,11 @@ struct CandRec {
 };
 
 // Per-wavefront LDS, used in turn by the two phases: the staged candidates of the
-// wavefront's pulses (slot = pulse * 16 + candidate) while tracing, then the
-// subrays' waveform inputs (offset hi, offset lo, power, unused) per lane.
-__host__ __device__ constexpr int wave_lds_bytes(int staged_pw)
+// wavefront's pulses (slot = pulse * staged_per_pulse + candidate) while tracing,
+// then the subrays' waveform inputs (offset hi, offset lo, power, unused) per lane.
+__host__ __device__ constexpr int wave_lds_bytes(int staged_slots)
 {
-    return staged_pw * kCandStaged * (int)sizeof(CandRec) > kWave * 16 ? staged_pw * kCandStaged * (int)sizeof(CandRec)
-                                                                       : kWave * 16;
+    return staged_slots * (int)sizeof(CandRec) > kWave * 16 ? staged_slots * (int)sizeof(CandRec) : kWave * 16;
 }
 
 __device__ __forceinline__ bool box_hit(const RayBox& r, float lx, float ly, float lz, float hx, float hy, float hz,
@@ -348,8 +347,9 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
         // the cone pass found every triangle any subray of this pulse can hit;
         // the dominant axis is the same for the whole wavefront almost always, so
         // the test of the staged ones is specialised for it behind a uniform branch
-        const CandRec* mine = rec + q * kCandStaged;
-        const int ns = nc < kCandStaged ? nc : kCandStaged;
+        const int per = staged_per_pulse(sc.P_w);
+        const CandRec* mine = rec + q * per;
+        const int ns = nc < per ? nc : per;
         const int kz0 = __builtin_amdgcn_readfirstlane(r.kz);
         int best;
         if (__ballot(r.kz != kz0) == 0) {
@@ -621,14 +621,17 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     const int pl = lane / S;
     const int k = lane - pl * S;
     const bool active = pl < npw;
-    // stage the first 16 candidate triangles of up to 4 pulses, one per lane,
-    // translated to their pulse's origin
+    // stage the first candidate triangles of up to 4 pulses, one per lane (64 for
+    // one pulse per wavefront, else 16 per pulse), translated to their pulse's
+    // origin
     // The loads are issued first and the subray setup runs while they are in
     // flight: the count and the ids share a row, and the record loads use an id
     // clamped into range, so they need not wait for the count.
     CandRec* rec = reinterpret_cast<CandRec*>(wl);
     const bool staged = pulses.cand && sc.P_w <= 4;
-    const int sq = lane / kCandStaged, sc16 = lane % kCandStaged;
+    // staged_per_pulse is 64 or 16: a shift, not a division
+    const int per_shift = staged && sc.P_w == 1 ? 6 : 4;
+    const int sq = lane >> per_shift, sc16 = lane & ((1 << per_shift) - 1);
     int nq = -1, li = 0;
     float4 P0, P1, P2;
     if (staged && sq < npw && scene.n_tri > 0) {
@@ -872,7 +875,7 @@ hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const Pu
     const int block = cfg.block_waves * kWave;
     long long waves = (count + sc.P_w - 1) / sc.P_w;
     unsigned grid = (unsigned)((waves + cfg.block_waves - 1) / cfg.block_waves);
-    const int wl = wave_lds_bytes(pulses.cand && sc.P_w <= 4 ? sc.P_w : 0);
+    const int wl = wave_lds_bytes(pulses.cand ? sc.P_w * staged_per_pulse(sc.P_w) : 0);
     size_t lds = sim_lds_bytes(block, cfg.stack_lds, wl);
     int mask = cfg.stack_lds - 1;
 #define VLS_SIM_LAUNCH(CH, MODE)                                                                              \
@@ -927,12 +930,12 @@ hipError_t launch_waveform(const ScannerDev& sc, const PulsesDev& pulses, const 
     return hipGetLastError();
 }
 
-hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, int staged_pw,
+hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, int staged_slots,
                              const PulsesDev& pulses, const OutDev& out, const LaunchCfg& cfg, int blocks,
                              hipStream_t stream)
 {
     const int block = cfg.block_waves * kWave;
-    const int wl = wave_lds_bytes(pulses.cand ? staged_pw : 0);
+    const int wl = wave_lds_bytes(pulses.cand ? staged_slots : 0);
     size_t lds = sim_lds_bytes(block, cfg.stack_lds, wl);
     int mask = cfg.stack_lds - 1;
     hipError_t e = launch_fill_u64(batch.counter, 1, 0ull, stream);
@@ -953,10 +956,10 @@ hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int m
     return hipGetLastError();
 }
 
-int persistent_occupancy_blocks(int max_bins, int staged_pw, const LaunchCfg& cfg)
+int persistent_occupancy_blocks(int max_bins, int staged_slots, const LaunchCfg& cfg)
 {
     const int block = cfg.block_waves * kWave;
-    size_t lds = sim_lds_bytes(block, cfg.stack_lds, wave_lds_bytes(cfg.cone ? staged_pw : 0));
+    size_t lds = sim_lds_bytes(block, cfg.stack_lds, wave_lds_bytes(cfg.cone ? staged_slots : 0));
     int per_cu = 0;
     hipError_t e;
     if (max_bins <= 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<4>, block, lds);

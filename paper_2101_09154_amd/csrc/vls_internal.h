@@ -35,6 +35,13 @@ inline double* cone_ws_basis(int* ws, long long n)
 }
 constexpr int kMaxLevel = 4096;          // depth cap of the build's level lists
 constexpr int kCandStaged = 16;          // of which the first ones are staged in LDS by the fused kernel
+// Candidates staged per pulse: one per lane of the wavefront, so 64 for one pulse
+// per wavefront, 16 for two to four (0 beyond: nothing staged).  The fused kernel
+// relies on both being powers of two.
+__host__ __device__ constexpr int staged_per_pulse(int pulses_per_wave)
+{
+    return pulses_per_wave == 1 ? kWave : (pulses_per_wave <= 4 ? kCandStaged : 0);
+}
 
 // One scanner as the kernels see it (everything derived on the host in FP64).
 struct ScannerDev {
@@ -167,9 +174,9 @@ hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const Pu
                            const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_waveform(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
                            long long first, long long count, int mode, const LaunchCfg& cfg, hipStream_t stream);
-// staged_pw: the largest pulses-per-wavefront <= 4 among the batch's scanners (0 if
-// none): it sizes the LDS that stages candidate triangles.
-hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, int staged_pw,
+// staged_slots: the most candidate records any of the batch's scanners stages per
+// wavefront (pulses per wavefront * staged_per_pulse): it sizes that LDS.
+hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, int staged_slots,
                              const PulsesDev& pulses, const OutDev& out, const LaunchCfg& cfg, int blocks,
                              hipStream_t stream);
 hipError_t launch_backward(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
@@ -201,6 +208,6 @@ hipError_t launch_generate(const SurveyDev& sv, const double* tab, long long fir
 // Candidate lists hold leaf indices; rewrite them as original triangle indices.
 hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_pulses, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);
-int persistent_occupancy_blocks(int max_bins, int staged_pw, const LaunchCfg& cfg);
+int persistent_occupancy_blocks(int max_bins, int staged_slots, const LaunchCfg& cfg);
 
 }  // namespace vls
