@@ -325,10 +325,10 @@ __device__ __forceinline__ void shade(const Ray& r, const double* a, const doubl
 
 // Trace one lane's subray: fills tri (original index or -1), R, cos, P.
 // staged: the pulse's first candidate records sit in rec[q * 16, q * 16 + min(nc, 16)).
-template <bool COUNT>
+template <bool COUNT, bool CHUNK>
 __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
                                            long long p, int k, int q, const Ray& r, bool ray_ok, bool staged,
-                                           const CandRec* rec, int* ring, int ring_mask, int& tri, double& R,
+                                           CandRec* rec, int* ring, int ring_mask, int& tri, double& R,
                                            float& cosang, float& P, int& visits, int& tests)
 {
     tri = -1;
@@ -361,10 +361,49 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
             else if (r.kz == 1) best = cand_loop<1>(r, mine, ns, h);
             else best = cand_loop<0>(r, mine, ns, h);
         }
-        // candidates beyond the staged ones come from the leaf records
         const int* cand = pulses.cand + p * (kCandMax + 1);
-        for (int i = ns; i < nc; ++i) leaf_test(r, scene.tris, cand[1 + i], h);
-        if (COUNT) tests += nc;
+        if (CHUNK && sc.P_w == 1 && nc > ns) {
+            // one pulse per wavefront: the rest are staged in chunks of 64 as
+            // well, each triangle loaded and translated once for the pulse by the
+            // subray lanes (all of them take this branch together, k = 0..S-1)
+            int best_leaf = best >= 0 ? mine[best].leaf : -1;
+            const double* o = pulses.origins + 3 * p;
+            for (int base = ns; base < nc; base += kWave) {
+                const int m = nc - base < kWave ? nc - base : kWave;
+                wave_sync();  // the previous chunk has been read
+                for (int j = k; j < m; j += sc.S) {
+                    const int li = min(max(cand[1 + base + j], 0), scene.n_tri - 1);
+                    const float4 P0 = scene.tris[3 * li], P1 = scene.tris[3 * li + 1], P2 = scene.tris[3 * li + 2];
+                    CandRec& w = rec[j];
+                    w.a[0] = (double)P0.x - o[0];
+                    w.a[1] = (double)P0.y - o[1];
+                    w.a[2] = (double)P0.z - o[2];
+                    w.b[0] = (double)P1.x - o[0];
+                    w.b[1] = (double)P1.y - o[1];
+                    w.b[2] = (double)P1.z - o[2];
+                    w.c[0] = (double)P2.x - o[0];
+                    w.c[1] = (double)P2.y - o[1];
+                    w.c[2] = (double)P2.z - o[2];
+                    w.orig = __float_as_int(P0.w);
+                    w.leaf = li;
+                }
+                wave_sync();
+                int b2;
+                if (r.kz == 2) b2 = cand_loop<2>(r, rec, m, h);
+                else if (r.kz == 1) b2 = cand_loop<1>(r, rec, m, h);
+                else b2 = cand_loop<0>(r, rec, m, h);
+                if (b2 >= 0) best_leaf = rec[b2].leaf;
+            }
+            if (COUNT) tests += nc;
+            if (best_leaf < 0) return;
+            // the winner's vertices come again from its leaf record below (the
+            // same FP64 translation as when it was staged)
+            h.leaf = best_leaf;
+        } else {
+            // candidates beyond the staged ones come from the leaf records
+            for (int i = ns; i < nc; ++i) leaf_test(r, scene.tris, cand[1 + i], h);
+            if (COUNT) tests += nc;
+        }
         if (h.leaf >= 0) {
             translate(r, scene.tris[3 * h.leaf], a);
             translate(r, scene.tris[3 * h.leaf + 1], b);
@@ -611,7 +650,9 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
 // One wavefront: pulses [first, first + npw) of one scanner.
 // MODE 0: trace only.  MODE 1: trace + waveform + returns (fused).
 // MODE 2: trace only, adding subrays / node visits / triangle tests to out.counts.
-template <int MAXCH, int MODE>
+// CHUNK: a launch for a scanner with one pulse per wavefront, which stages long
+// candidate lists in chunks (kept out of the other launches' code).
+template <int MAXCH, int MODE, bool CHUNK = false>
 __device__ __forceinline__ void process_wave(const SceneDev& scene, const ScannerDev& sc,
                                              const PulsesDev& pulses, const OutDev& out, long long first, int npw,
                                              int* ring, int ring_mask, unsigned char* wl)
@@ -673,7 +714,7 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     int visits = 0, tests = 0;
     if (active) {
         long long p = first + pl;
-        trace_lane<MODE == 2>(scene, sc, pulses, p, k, pl, r, ray_ok, staged, rec, ring, ring_mask, tri, R, cs, P,
+        trace_lane<MODE == 2, CHUNK>(scene, sc, pulses, p, k, pl, r, ray_ok, staged, rec, ring, ring_mask, tri, R, cs, P,
                               visits, tests);
         long long o = p * out.sub_stride + k;
         if (out.sub_tri) out.sub_tri[o] = tri;
@@ -709,7 +750,7 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     }
 }
 
-template <int MAXCH, int MODE>
+template <int MAXCH, int MODE, bool CHUNK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_simulate(SceneDev scene, ScannerDev sc, PulsesDev pulses,
                                                   OutDev out, long long first, long long count, int ring_mask,
                                                   int wl_bytes)
@@ -723,7 +764,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     if (p0 >= count) return;
     long long left = count - p0;
     int npw = left < sc.P_w ? (int)left : sc.P_w;
-    process_wave<MAXCH, MODE>(scene, sc, pulses, out, first + p0, npw, ring, ring_mask, wl);
+    process_wave<MAXCH, MODE, CHUNK>(scene, sc, pulses, out, first + p0, npw, ring, ring_mask, wl);
 }
 
 // Waveform from stored subrays (KIND 0) or returns from stored waveforms (KIND 1).
@@ -879,8 +920,14 @@ hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const Pu
     size_t lds = sim_lds_bytes(block, cfg.stack_lds, wl);
     int mask = cfg.stack_lds - 1;
 #define VLS_SIM_LAUNCH(CH, MODE)                                                                              \
-    hipLaunchKernelGGL((k_simulate<CH, MODE>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, out, first, \
-                       count, mask, wl)
+    do {                                                                                                     \
+        if (sc.P_w == 1 && MODE != 2)                                                                        \
+            hipLaunchKernelGGL((k_simulate<CH, MODE, true>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, \
+                               out, first, count, mask, wl);                                                 \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_simulate<CH, MODE, false>), dim3(grid), dim3(block), lds, stream, scene, sc,  \
+                               pulses, out, first, count, mask, wl);                                         \
+    } while (0)
     if (mode == 0) VLS_SIM_LAUNCH(4, 0);
     else if (mode == 2) VLS_SIM_LAUNCH(4, 2);
     else if (sc.n_bins <= 256) VLS_SIM_LAUNCH(4, 1);
