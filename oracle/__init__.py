@@ -41,6 +41,23 @@ class OrcSurvey(ctypes.Structure):
 DEFLECTORS = {"polygon": 0, "swing": 1, "conic": 2, "fibre": 3}
 
 
+class OrcVoxels(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("size", ctypes.c_double), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("n_lut", ctypes.c_int32),
+                ("pad", ctypes.c_void_p), ("lut", ctypes.c_void_p), ("seed", ctypes.c_uint64)]
+
+
+def voxel_struct(vox):
+    """ctypes view of a voxel grid dict (origin, size, pad [nz, ny, nx], lut [n, 2], seed); the arrays
+    are kept alive in the returned tuple."""
+    pad = np.ascontiguousarray(vox["pad"], dtype=np.float32)
+    lut = np.ascontiguousarray(vox["lut"], dtype=np.float64).reshape(-1, 2)
+    nz, ny, nx = pad.shape
+    st = OrcVoxels((ctypes.c_double * 3)(*[float(x) for x in vox["origin"]]), float(vox["size"]), nx, ny, nz,
+                   lut.shape[0], pad.ctypes.data, lut.ctypes.data, int(vox.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF)
+    return st, (pad, lut)
+
+
 class OrcScanner(ctypes.Structure):
     _fields_ = [("divergence_rad", ctypes.c_double), ("pattern_extent", ctypes.c_double),
                 ("pulse_width_ns", ctypes.c_double), ("bin_ns", ctypes.c_double),
@@ -88,6 +105,11 @@ def lib():
         L.orc_attribute.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_double]
         L.orc_simulate.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, i64, P] + [P] * 6 + [P] * 7 + [ctypes.c_int]
         L.orc_gradient.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, P, P, P, ctypes.c_int]
+        L.orc_simulate_vox.argtypes = L.orc_simulate.argtypes + [P]
+        L.orc_lut_g.argtypes = [P, ctypes.c_double]
+        L.orc_lut_g.restype = ctypes.c_double
+        L.orc_voxel_hit.argtypes = [P, P, P, ctypes.c_double, ctypes.c_uint64, P, P]
+        L.orc_voxel_hit.restype = i64
         L.orc_max_threads.argtypes = []
         _lib = L
     return _lib
@@ -258,8 +280,9 @@ class OracleResult:
     S: int
 
 
-def simulate(mesh, pulses, sc, select=None, t0=None, threads=0, waveform=True):
-    """Forward over all pulses, or over the pulse indices in ``select``."""
+def simulate(mesh, pulses, sc, select=None, t0=None, threads=0, waveform=True, voxels=None):
+    """Forward over all pulses, or over the pulse indices in ``select``; ``voxels``: an
+    optional transmissive voxel grid (see voxel_struct)."""
     mesh.checked()
     st = scanner_struct(sc)
     S = pattern_size(st.n_subrays, st.beam_quality)
@@ -275,16 +298,39 @@ def simulate(mesh, pulses, sc, select=None, t0=None, threads=0, waveform=True):
     t0a = None if t0 is None else np.ascontiguousarray(t0, dtype=np.float64)
     o = np.ascontiguousarray(pulses.origins, dtype=np.float64)
     d = np.ascontiguousarray(pulses.directions, dtype=np.float32)
-    got = lib().orc_simulate(_ptr(mesh.vertices), mesh.n_vertices, _ptr(mesh.triangles), _ptr(mesh.reflectance),
-                             mesh.n_triangles, ctypes.byref(st), _ptr(o), _ptr(d), pulses.n,
-                             _ptr(sel), n, _ptr(t0a),
-                             _ptr(r.sub_tri), _ptr(r.sub_range), _ptr(r.sub_cos), _ptr(r.sub_power),
-                             _ptr(r.sub_u), _ptr(r.sub_v),
-                             _ptr(r.waveform), _ptr(r.t0), _ptr(r.n_returns), _ptr(r.ret_range), _ptr(r.ret_amp),
-                             _ptr(r.ret_tri), _ptr(r.ret_bin), int(threads))
+    vst, keep = voxel_struct(voxels) if voxels is not None else (None, None)
+    got = lib().orc_simulate_vox(_ptr(mesh.vertices), mesh.n_vertices, _ptr(mesh.triangles), _ptr(mesh.reflectance),
+                                 mesh.n_triangles, ctypes.byref(st), _ptr(o), _ptr(d), pulses.n,
+                                 _ptr(sel), n, _ptr(t0a),
+                                 _ptr(r.sub_tri), _ptr(r.sub_range), _ptr(r.sub_cos), _ptr(r.sub_power),
+                                 _ptr(r.sub_u), _ptr(r.sub_v),
+                                 _ptr(r.waveform), _ptr(r.t0), _ptr(r.n_returns), _ptr(r.ret_range), _ptr(r.ret_amp),
+                                 _ptr(r.ret_tri), _ptr(r.ret_bin), int(threads),
+                                 ctypes.byref(vst) if vst is not None else None)
+    del keep
     if got != S:
         raise RuntimeError("oracle simulate failed")
     return r
+
+
+def lut_g(voxels, vz):
+    """The leaf-angle table's value at vertical component |vz|."""
+    vst, keep = voxel_struct(voxels)
+    return lib().orc_lut_g(ctypes.byref(vst), float(vz))
+
+
+def voxel_hit(voxels, O, d, t_limit, pulse, subray):
+    """(voxel index or -1, hit distance, sigma) of one ray through the grid."""
+    vst, keep = voxel_struct(voxels)
+    O = np.ascontiguousarray(O, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    n_vox = int(np.asarray(voxels["pad"]).size)
+    c0 = ((int(pulse) * 64 + int(subray)) * n_vox) & 0xFFFFFFFFFFFFFFFF
+    t = ctypes.c_double(0.0)
+    sg = ctypes.c_double(0.0)
+    vi = lib().orc_voxel_hit(ctypes.byref(vst), _ptr(O), _ptr(d), float(t_limit), c0, ctypes.byref(t),
+                             ctypes.byref(sg))
+    return int(vi), t.value, sg.value
 
 
 def gradient(mesh, pulses, sc, t0, grad_wf, threads=0):

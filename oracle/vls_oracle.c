@@ -30,7 +30,11 @@
  *      discussed in Sec. 3.6);
  *   8. pulses generated from a survey: a LinearPath or static platform (Sec.
  *      3.2) carrying one of the four scan deflectors of Sec. 3.3, with optional
- *      platform position noise from a counter-based SplitMix64.
+ *      platform position noise from a counter-based SplitMix64;
+ *   9. optionally, transmissive voxels (Sec. 3.5.4, Sec. 5.2): a subray crossing
+ *      a voxel of plant area density PAD stops in it at a random depth drawn
+ *      from the extinction coefficient (Eq. 5 through a leaf-angle table, Eq. 6),
+ *      with the echo power of Eq. 8.
  * Everything is FP64 with no truncation of the pulse support.
  *
  * Readings where the paper is silent or garbled:
@@ -328,13 +332,137 @@ static double power_const(const orc_scanner* sc)
     return sc->peak_power_w * sc->efficiency * sc->receiver_diameter_m * sc->receiver_diameter_m / 4.0;
 }
 
+/* Transmissive voxels (Sec. 3.5.4, Sec. 5.2).  Readings taken:
+ *   grid     one axis-aligned grid of cubes of side `size` from `origin`,
+ *            nx * ny * nz voxels, PAD per voxel (index ix + nx (iy + ny iz));
+ *   sigma    Eq. 5's integral is what the leaf-angle table tabulates (Table 2:
+ *            hit probability against the beam's horizontal and vertical
+ *            components, obtained by numerical integration); a beam's
+ *            horizontal component is sqrt(1 - v_z^2), so the table is a function
+ *            of |v_z|: sigma = PAD * g(|v_z|), g linear between the table's rows
+ *            (sorted by vertical component) and held at its ends;
+ *   depth    Eq. 6: s = -ln(u) / sigma with u uniform in (0, 1]: u =
+ *            ((x >> 11) + 1) 2^-53 of SplitMix64 output number
+ *            (pulse * 64 + subray) * n_voxels + voxel of the sequence seeded with
+ *            `seed`, one draw per voxel a subray crosses;
+ *   stop     Sec. 5.2: the subray stops in the voxel when s is at most the length
+ *            it travels inside the voxel (Sec. 3.5.4 words the comparison the
+ *            other way round; Sec. 5.2 and the physics of extinction agree);
+ *            sigma = 0 lets it through;
+ *   walk     the voxels are visited in order along the subray (Amanatides & Woo
+ *            1987) in FP64; the nearest of the first stopping voxel and the
+ *            closest triangle is the hit (Sec. 5.1: consecutive intersections
+ *            along the ray);
+ *   power    Eq. 8 with the proportionality taken as equality:
+ *            P = eta * sigma * P0 w D^2 / (4 pi R^4 beta^2), beta the full
+ *            divergence, R the hit distance; cos is reported as 1;
+ *   id       a voxel hit is reported as triangle id n_tri + voxel index. */
+typedef struct {
+    double origin[3];
+    double size;
+    int32_t nx, ny, nz, n_lut;
+    const float* pad;        /* [nz][ny][nx] */
+    const double* lut;       /* [n_lut][2]: vertical component, g */
+    uint64_t seed;
+} orc_voxels;
+
 typedef struct {
     const float* verts; const int32_t* tris; const float* refl; int64_t n_tri;
     const orc_scanner* sc; int S; const double* alpha; const double* phi; const double* w;
+    const orc_voxels* vox;   /* NULL: no voxels */
 } orc_ctx;
 
+uint64_t orc_splitmix64(uint64_t seed, uint64_t c);
+
+double orc_lut_g(const orc_voxels* v, double vz)
+{
+    double a = fabs(vz);
+    const double* t = v->lut;
+    int n = v->n_lut;
+    if (a <= t[0]) return t[1];
+    if (a >= t[2 * (n - 1)]) return t[2 * (n - 1) + 1];
+    int i = 0;
+    while (i + 2 < n && t[2 * (i + 1)] <= a) ++i;
+    double f = (a - t[2 * i]) / (t[2 * (i + 1)] - t[2 * i]);
+    return t[2 * i + 1] + f * (t[2 * (i + 1) + 1] - t[2 * i + 1]);
+}
+
+/* The first voxel that stops the ray O + t d (d unit) before t_limit: returns
+ * its index (or -1) and sets *t_hit and *sigma.  `counter0` = (pulse * 64 +
+ * subray) * n_voxels addresses the draws. */
+int64_t orc_voxel_hit(const orc_voxels* v, const double O[3], const double d[3], double t_limit,
+                      uint64_t counter0, double* t_hit, double* sigma)
+{
+    const int n[3] = {v->nx, v->ny, v->nz};
+    double t_in = 0.0, t_out = t_limit;
+    for (int a = 0; a < 3; ++a) {
+        double lo = v->origin[a], hi = v->origin[a] + v->size * (double)n[a];
+        if (d[a] == 0.0) {
+            if (O[a] < lo || O[a] > hi) return -1;
+            continue;
+        }
+        double t1 = (lo - O[a]) / d[a], t2 = (hi - O[a]) / d[a];
+        if (t1 > t2) { double tt = t1; t1 = t2; t2 = tt; }
+        if (t1 > t_in) t_in = t1;
+        if (t2 < t_out) t_out = t2;
+    }
+    if (!(t_in < t_out)) return -1;
+    int idx[3], step[3];
+    double tmax[3], tdel[3];
+    for (int a = 0; a < 3; ++a) {
+        /* the entry voxel; a point on a boundary belongs to the voxel the ray
+         * moves into */
+        double pa = O[a] + t_in * d[a];
+        double q = (pa - v->origin[a]) / v->size;
+        double f = d[a] < 0.0 ? ceil(q) - 1.0 : floor(q);
+        int i = (int)f;
+        if (f < 0.0) i = 0;
+        if (f > (double)(n[a] - 1)) i = n[a] - 1;
+        idx[a] = i;
+        if (d[a] > 0.0) {
+            step[a] = 1;
+            tmax[a] = (v->origin[a] + v->size * (double)(i + 1) - O[a]) / d[a];
+            tdel[a] = v->size / d[a];
+        } else if (d[a] < 0.0) {
+            step[a] = -1;
+            tmax[a] = (v->origin[a] + v->size * (double)i - O[a]) / d[a];
+            tdel[a] = -v->size / d[a];
+        } else {
+            step[a] = 0;
+            tmax[a] = INFINITY;
+            tdel[a] = INFINITY;
+        }
+    }
+    const double g = orc_lut_g(v, d[2]);
+    double t = t_in;
+    while (t < t_out) {
+        int ax = 0;
+        if (tmax[1] < tmax[ax]) ax = 1;
+        if (tmax[2] < tmax[ax]) ax = 2;
+        double t_exit = tmax[ax] < t_out ? tmax[ax] : t_out;
+        if (t_exit < t) t_exit = t;  /* rounding never walks backwards */
+        int64_t vi = (int64_t)idx[0] + (int64_t)v->nx * ((int64_t)idx[1] + (int64_t)v->ny * (int64_t)idx[2]);
+        double sg = (double)v->pad[vi] * g;
+        if (sg > 0.0) {
+            double u = (double)((orc_splitmix64(v->seed, counter0 + (uint64_t)vi) >> 11) + 1) *
+                       (1.0 / 9007199254740992.0);
+            double sd = -log(u) / sg;
+            if (sd <= t_exit - t) {
+                *t_hit = t + sd;
+                *sigma = sg;
+                return vi;
+            }
+        }
+        t = t_exit;
+        idx[ax] += step[ax];
+        if (idx[ax] < 0 || idx[ax] >= n[ax]) break;
+        tmax[ax] += tdel[ax];
+    }
+    return -1;
+}
+
 /* Trace and shade the S subrays of one pulse. */
-static void trace_pulse(const orc_ctx* c, const double O[3], const float d32[3],
+static void trace_pulse(const orc_ctx* c, int64_t pulse, const double O[3], const float d32[3],
                         int32_t* tri, double* R, double* cosang, double* P, double* U, double* V)
 {
     double d[3] = { d32[0], d32[1], d32[2] };
@@ -343,6 +471,24 @@ static void trace_pulse(const orc_ctx* c, const double O[3], const float d32[3],
         double dk[3], t, u, v;
         orc_subray_direction(d, c->alpha[k], c->phi[k], dk);
         int64_t h = orc_closest_hit(O, dk, c->verts, c->tris, c->n_tri, &t, &u, &v);
+        if (c->vox) {
+            double tv, sg;
+            uint64_t c0 = ((uint64_t)pulse * 64 + (uint64_t)k) *
+                          (uint64_t)((int64_t)c->vox->nx * c->vox->ny * c->vox->nz);
+            int64_t vi = orc_voxel_hit(c->vox, O, dk, h >= 0 ? t : INFINITY, c0, &tv, &sg);
+            if (vi >= 0) {
+                /* Eq. 8, proportionality taken as equality */
+                double beta = c->sc->divergence_rad;
+                double Dm = c->sc->receiver_diameter_m;
+                tri[k] = (int32_t)(c->n_tri + vi);
+                R[k] = tv;
+                cosang[k] = 1.0;
+                U[k] = V[k] = 0.0;
+                P[k] = c->sc->efficiency * sg * c->sc->peak_power_w * c->w[k] * Dm * Dm /
+                       (4.0 * ORC_PI * tv * tv * tv * tv * beta * beta);
+                continue;
+            }
+        }
         tri[k] = (int32_t)h;
         if (h < 0) { R[k] = INFINITY; cosang[k] = 0.0; P[k] = 0.0; U[k] = V[k] = 0.0; continue; }
         double a[3], b[3], cc[3], e1[3], e2[3], n[3];
@@ -400,6 +546,7 @@ static int make_ctx(orc_ctx* c, const float* verts, const int32_t* tris, const f
 {
     c->verts = verts; c->tris = tris; c->refl = refl; c->n_tri = n_tri; c->sc = sc;
     c->alpha = alpha; c->phi = phi; c->w = w;
+    c->vox = NULL;
     c->S = orc_pattern(sc, alpha, phi, w, 4096);
     if (c->S <= 0 || sc->n_bins < 3 || sc->max_returns < 1 || sc->max_returns > 64 || !(sc->bin_ns > 0.0)) return -1;
     return 0;
@@ -409,18 +556,20 @@ static int make_ctx(orc_ctx* c, const float* verts, const int32_t* tris, const f
  * to pulse sel[q].  Per-subray arrays are [n_sel][S]; waveform [n_sel][n_bins];
  * returns [n_sel][K].  t0_in (indexed by pulse, may be NULL) fixes the window
  * origins.  Any per-subray output may be NULL.  Returns S, or -1. */
-int orc_simulate(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
-                 const orc_scanner* sc, const double* origins, const float* dirs, int64_t n_pulses,
-                 const int64_t* sel, int64_t n_sel, const double* t0_in,
-                 int32_t* sub_tri, double* sub_range, double* sub_cos, double* sub_power,
-                 double* sub_u, double* sub_v,
-                 double* wf, double* t0_out, int32_t* n_ret, double* ret_range, double* ret_amp,
-                 int32_t* ret_tri, int32_t* ret_bin, int n_threads)
+/* The same with transmissive voxels (vox may be NULL). */
+int orc_simulate_vox(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
+                     const orc_scanner* sc, const double* origins, const float* dirs, int64_t n_pulses,
+                     const int64_t* sel, int64_t n_sel, const double* t0_in,
+                     int32_t* sub_tri, double* sub_range, double* sub_cos, double* sub_power,
+                     double* sub_u, double* sub_v,
+                     double* wf, double* t0_out, int32_t* n_ret, double* ret_range, double* ret_amp,
+                     int32_t* ret_tri, int32_t* ret_bin, int n_threads, const orc_voxels* vox)
 {
     (void)n_vert;
     double alpha[4096], phi[4096], w[4096];
     orc_ctx c;
     if (make_ctx(&c, verts, tris, refl, n_tri, sc, alpha, phi, w) < 0) return -1;
+    c.vox = vox;
     int S = c.S, nb = sc->n_bins, K = sc->max_returns;
     int64_t n = sel ? n_sel : n_pulses;
 #ifdef _OPENMP
@@ -436,7 +585,7 @@ int orc_simulate(const float* verts, int64_t n_vert, const int32_t* tris, const 
 #pragma omp for schedule(dynamic, 1)
         for (int64_t q = 0; q < n; ++q) {
             int64_t p = sel ? sel[q] : q;
-            trace_pulse(&c, origins + 3 * p, dirs + 3 * p, tri, R, cs, P, U, V);
+            trace_pulse(&c, p, origins + 3 * p, dirs + 3 * p, tri, R, cs, P, U, V);
             for (int k = 0; k < S; ++k) {
                 if (sub_tri) sub_tri[q * S + k] = tri[k];
                 if (sub_range) sub_range[q * S + k] = R[k];
@@ -454,6 +603,19 @@ int orc_simulate(const float* verts, int64_t n_vert, const int32_t* tris, const 
         free(R);
     }
     return S;
+}
+
+int orc_simulate(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
+                 const orc_scanner* sc, const double* origins, const float* dirs, int64_t n_pulses,
+                 const int64_t* sel, int64_t n_sel, const double* t0_in,
+                 int32_t* sub_tri, double* sub_range, double* sub_cos, double* sub_power,
+                 double* sub_u, double* sub_v,
+                 double* wf, double* t0_out, int32_t* n_ret, double* ret_range, double* ret_amp,
+                 int32_t* ret_tri, int32_t* ret_bin, int n_threads)
+{
+    return orc_simulate_vox(verts, n_vert, tris, refl, n_tri, sc, origins, dirs, n_pulses, sel, n_sel, t0_in, sub_tri,
+                            sub_range, sub_cos, sub_power, sub_u, sub_v, wf, t0_out, n_ret, ret_range, ret_amp,
+                            ret_tri, ret_bin, n_threads, NULL);
 }
 
 /* ------------------------------------------------------------------ gradient */
@@ -498,7 +660,7 @@ int orc_gradient(const float* verts, int64_t n_vert, const int32_t* tris, const 
 #pragma omp for schedule(dynamic, 1)
         for (int64_t p = 0; p < n_pulses; ++p) {
             if (isnan(t0[p])) continue;
-            trace_pulse(&c, origins + 3 * p, dirs + 3 * p, tri, R, cs, P, U, V);
+            trace_pulse(&c, p, origins + 3 * p, dirs + 3 * p, tri, R, cs, P, U, V);
             double dp[3] = { dirs[3 * p], dirs[3 * p + 1], dirs[3 * p + 2] };
             const double* G = grad_wf + p * nb;
             for (int k = 0; k < S; ++k) {
