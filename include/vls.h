@@ -126,6 +126,52 @@ vls_status vls_scene_update_vertices(vls_scene scene, const float* vertices_dev,
 /* New per-triangle reflectance, device array [n_triangles] float32.  Asynchronous. */
 vls_status vls_scene_update_reflectance(vls_scene scene, const float* reflectance_dev, void* stream);
 
+/* A transmissive voxel grid (Sec. 3.5.4, Sec. 5.2): vegetation given as plant
+ * area density (PAD, m^2/m^3) per voxel of an axis-aligned grid of cubes of
+ * side voxel_size_m whose lowest corner is `origin`; voxel (ix, iy, iz) has
+ * index ix + nx (iy + ny iz).  Model (the paper gives the equations; the
+ * choices where it leaves room are stated here):
+ *   sigma   = PAD * g(|v_z|), v the subray's unit direction; `lut` is the
+ *             leaf-angle table (Table 2: hit probability against the beam's
+ *             vertical component, whose horizontal component follows), rows of
+ *             (vertical component, g), strictly increasing in the first; g is
+ *             linear between rows and held beyond the first and last (Eq. 5's
+ *             integral is what the table tabulates);
+ *   depth   s = -ln(u) / sigma (Eq. 6), u uniform in (0, 1] from SplitMix64
+ *             (Steele, Lea & Flood 2014) output number
+ *             (pulse * 64 + subray) * (nx ny nz) + voxel of the sequence seeded
+ *             with `seed`: u = ((x >> 11) + 1) 2^-53, one draw per voxel the
+ *             subray crosses; `pulse` is the index in the call's pulse batch;
+ *   stop    the subray stops in a voxel when s is at most the length it
+ *             travels inside the voxel (Sec. 5.2), at s past its entry, and
+ *             passes on otherwise (sigma = 0: always); voxels are visited in
+ *             order along the subray (Amanatides & Woo 1987; Sec. 5.1's
+ *             consecutive intersections without an epsilon step) and the nearer
+ *             of the first stop and the closest triangle is the hit (a voxel
+ *             stop at the triangle's distance wins);
+ *   echo    subray_tri = n_triangles + voxel index, subray_cos = 1,
+ *             subray_power = eta sigma P0 w D^2 / (4 pi R^4 beta^2) (Eq. 8 with
+ *             the proportionality taken as equality; beta the full divergence,
+ *             which must then be > 0); waveforms and returns take voxel echoes
+ *             like triangle echoes, and ret_tri reports their ids alike.
+ * pad [nz][ny][nx] float32 and lut [n_lut][2] float64 are HOST arrays, checked
+ * (finite, PAD >= 0, g >= 0) and copied; the call synchronises `stream`.
+ * n_triangles + nx ny nz must stay below 2^31.  A scene takes one grid, once
+ * (a second call returns VLS_ERR_INVALID_ARG); graphs captured before the call
+ * keep tracing without it.  vls_waveform_backward treats voxel echoes as
+ * constants (they depend on neither reflectance nor vertices). */
+typedef struct {
+    double origin[3];
+    double voxel_size_m;
+    int32_t nx, ny, nz;
+    int32_t n_lut;
+    const float* pad;
+    const double* lut;
+    uint64_t seed;
+} vls_voxel_desc;
+
+vls_status vls_scene_set_voxels(vls_scene scene, const vls_voxel_desc* voxels, void* stream);
+
 /* Synchronous: statistics of the built scene. */
 vls_status vls_scene_stats_get(vls_scene scene, vls_scene_stats* out);
 

@@ -106,6 +106,7 @@ def lib():
         L.orc_simulate.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, i64, P] + [P] * 6 + [P] * 7 + [ctypes.c_int]
         L.orc_gradient.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, P, P, P, ctypes.c_int]
         L.orc_simulate_vox.argtypes = L.orc_simulate.argtypes + [P]
+        L.orc_gradient_vox.argtypes = L.orc_gradient.argtypes + [P]
         L.orc_lut_g.argtypes = [P, ctypes.c_double]
         L.orc_lut_g.restype = ctypes.c_double
         L.orc_voxel_hit.argtypes = [P, P, P, ctypes.c_double, ctypes.c_uint64, P, P]
@@ -333,18 +334,22 @@ def voxel_hit(voxels, O, d, t_limit, pulse, subray):
     return int(vi), t.value, sg.value
 
 
-def gradient(mesh, pulses, sc, t0, grad_wf, threads=0):
-    """(grad_reflectance [T], grad_z [V]) of L with dL/dwf = grad_wf at fixed t0."""
+def gradient(mesh, pulses, sc, t0, grad_wf, threads=0, voxels=None):
+    """(grad_reflectance [T], grad_z [V]) of L with dL/dwf = grad_wf at fixed t0; ``voxels``: an
+    optional transmissive voxel grid (its echoes are constants)."""
     st = scanner_struct(sc)
+    vst, keep = voxel_struct(voxels) if voxels is not None else (None, None)
     gr = np.zeros(mesh.n_triangles)
     gz = np.zeros(mesh.n_vertices)
     o = np.ascontiguousarray(pulses.origins, dtype=np.float64)
     d = np.ascontiguousarray(pulses.directions, dtype=np.float32)
     t0 = np.ascontiguousarray(t0, dtype=np.float64)
     G = np.ascontiguousarray(grad_wf, dtype=np.float64)
-    got = lib().orc_gradient(_ptr(mesh.vertices), mesh.n_vertices, _ptr(mesh.triangles), _ptr(mesh.reflectance),
-                             mesh.n_triangles, ctypes.byref(st), _ptr(o), _ptr(d), pulses.n, _ptr(t0), _ptr(G),
-                             _ptr(gr), _ptr(gz), int(threads))
+    got = lib().orc_gradient_vox(_ptr(mesh.vertices), mesh.n_vertices, _ptr(mesh.triangles),
+                                 _ptr(mesh.reflectance), mesh.n_triangles, ctypes.byref(st), _ptr(o), _ptr(d),
+                                 pulses.n, _ptr(t0), _ptr(G), _ptr(gr), _ptr(gz), int(threads),
+                                 ctypes.byref(vst) if vst is not None else None)
+    del keep
     if got < 0:
         raise RuntimeError("oracle gradient failed")
     return gr, gz

@@ -395,6 +395,8 @@ int64_t orc_voxel_hit(const orc_voxels* v, const double O[3], const double d[3],
 {
     const int n[3] = {v->nx, v->ny, v->nz};
     double t_in = 0.0, t_out = t_limit;
+    for (int a = 0; a < 3; ++a)  /* a subray that is not finite meets nothing */
+        if (!isfinite(O[a]) || !isfinite(d[a])) return -1;
     for (int a = 0; a < 3; ++a) {
         double lo = v->origin[a], hi = v->origin[a] + v->size * (double)n[a];
         if (d[a] == 0.0) {
@@ -627,13 +629,17 @@ int orc_simulate(const float* verts, int64_t n_vert, const int32_t* tris, const 
  * tau = 2R/c, R = n.(a-O)/(n.d) so dR/dv_i = b_i n/(n.d) (b_i = barycentric
  * weight of vertex i at the hit), cos = |n.d|/|n|.  Accumulated per thread in
  * thread order (deterministic for a fixed thread count). */
-int orc_gradient(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
-                 const orc_scanner* sc, const double* origins, const float* dirs, int64_t n_pulses,
-                 const double* t0, const double* grad_wf, double* grad_refl, double* grad_z, int n_threads)
+/* The same with transmissive voxels (vox may be NULL): a subray that a voxel
+ * stops carries no triangle and so adds nothing to either gradient. */
+int orc_gradient_vox(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
+                     const orc_scanner* sc, const double* origins, const float* dirs, int64_t n_pulses,
+                     const double* t0, const double* grad_wf, double* grad_refl, double* grad_z, int n_threads,
+                     const orc_voxels* vox)
 {
     double alpha[4096], phi[4096], w[4096];
     orc_ctx c;
     if (make_ctx(&c, verts, tris, refl, n_tri, sc, alpha, phi, w) < 0) return -1;
+    c.vox = vox;
     int S = c.S, nb = sc->n_bins;
     double C = power_const(sc);
 #ifdef _OPENMP
@@ -665,7 +671,7 @@ int orc_gradient(const float* verts, int64_t n_vert, const int32_t* tris, const 
             const double* G = grad_wf + p * nb;
             for (int k = 0; k < S; ++k) {
                 int32_t h = tri[k];
-                if (h < 0) continue;
+                if (h < 0 || h >= n_tri) continue;
                 double tau = 2.0 * R[k] / ORC_C_M_PER_NS, gP = 0.0, gD = 0.0;
                 for (int j = 0; j < nb; ++j) {
                     double s = t0[p] + (double)j * sc->bin_ns - tau;
@@ -711,6 +717,14 @@ int orc_gradient(const float* verts, int64_t n_vert, const int32_t* tris, const 
     }
     free(part);
     return S;
+}
+
+int orc_gradient(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
+                 const orc_scanner* sc, const double* origins, const float* dirs, int64_t n_pulses,
+                 const double* t0, const double* grad_wf, double* grad_refl, double* grad_z, int n_threads)
+{
+    return orc_gradient_vox(verts, n_vert, tris, refl, n_tri, sc, origins, dirs, n_pulses, t0, grad_wf, grad_refl,
+                            grad_z, n_threads, NULL);
 }
 
 /* ------------------------------------------------------------------ echo width (Sec. 3.4, optional) */

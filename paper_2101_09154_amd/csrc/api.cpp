@@ -185,8 +185,11 @@ struct vls_scene_s {
     BvhBuffers b;
     vls_scene_stats stats{};
     int root = -1;
+    VoxDev vox{};              // transmissive voxel grid (n_vox == 0: none); arrays owned here
     ~vls_scene_s()
     {
+        (void)hipFree(const_cast<float*>(vox.pad));
+        (void)hipFree(const_cast<double*>(vox.lut));
         (void)hipFree(b.nodes);
         (void)hipFree(b.nodes4);
         (void)hipFree(b.tris);
@@ -271,6 +274,7 @@ vls_status scanner_dev(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s
         s.s_peak = 2.0 * tau;
     }
     s.power_c = d.peak_power_w * d.efficiency * d.receiver_diameter_m * d.receiver_diameter_m / 4.0;
+    s.vox_c = s.power_c / (M_PI * d.divergence_rad * d.divergence_rad);
     s.tan_max = S > 1 ? std::tan(d.pattern_extent * 0.5 * d.divergence_rad) : 0.0;
     s.thr_abs = d.min_echo_abs;
     s.thr_rel = d.min_echo_rel;
@@ -289,6 +293,7 @@ SceneDev scene_dev(vls_scene sc)
     s.tri_idx = sc->b.tri_idx;
     s.root = sc->root;
     s.n_tri = (int)sc->b.n_tri;
+    s.vox = sc->vox;
     return s;
 }
 
@@ -358,10 +363,14 @@ vls_status prepare(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_
     return VLS_OK;
 }
 
-vls_status check_scene(vls_context ctx, vls_scene scene)
+vls_status check_scene(vls_context ctx, vls_scene scene, const Prepared& pr)
 {
     if (!scene) return fail(VLS_ERR_INVALID_ARG, "scene is NULL");
     if (scene->ctx != ctx) return fail(VLS_ERR_INVALID_ARG, "scene belongs to another context");
+    if (scene->vox.n_vox > 0)
+        for (const auto& s : pr.sc)
+            if (!(s.vox_c < INFINITY))
+                return fail(VLS_ERR_INVALID_ARG, "a scene with voxels needs scanners of divergence > 0 (Eq. 8)");
     int limit = ctx->cfg.stack_lds + kMaxSpill - 1;
     if (scene->stats.max_depth > limit) {
         char b[128];
@@ -684,6 +693,66 @@ vls_status vls_scene_update_reflectance(vls_scene scene, const float* reflectanc
     return VLS_OK;
 }
 
+vls_status vls_scene_set_voxels(vls_scene scene, const vls_voxel_desc* v, void* stream)
+{
+    try {
+        if (!scene || !v) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+        if (scene->vox.n_vox > 0) return fail(VLS_ERR_INVALID_ARG, "the scene already has a voxel grid");
+        if (!v->pad || !v->lut) return fail(VLS_ERR_INVALID_ARG, "pad and lut are required");
+        if (v->nx < 1 || v->ny < 1 || v->nz < 1) return fail(VLS_ERR_INVALID_ARG, "grid dimensions must be >= 1");
+        const int64_t n_vox = (int64_t)v->nx * v->ny * v->nz;
+        if (n_vox > (int64_t)0x7fffffff - scene->b.n_tri)
+            return fail(VLS_ERR_UNSUPPORTED, "n_triangles + voxels must stay below 2^31");
+        if (!(v->voxel_size_m > 0.0) || !std::isfinite(v->voxel_size_m))
+            return fail(VLS_ERR_INVALID_ARG, "voxel_size_m must be finite and > 0");
+        const int dims[3] = {v->nx, v->ny, v->nz};
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(v->origin[a]) || !std::isfinite(v->origin[a] + v->voxel_size_m * dims[a]))
+                return fail(VLS_ERR_INVALID_ARG, "grid corners must be finite");
+        if (v->n_lut < 1) return fail(VLS_ERR_INVALID_ARG, "the leaf-angle table needs a row");
+        for (int i = 0; i < v->n_lut; ++i) {
+            const double x = v->lut[2 * i], g = v->lut[2 * i + 1];
+            if (!std::isfinite(x) || !std::isfinite(g) || g < 0.0)
+                return fail(VLS_ERR_INVALID_ARG, "table rows must be finite with g >= 0");
+            if (i > 0 && !(x > v->lut[2 * i - 2]))
+                return fail(VLS_ERR_INVALID_ARG, "table rows must have strictly increasing vertical components");
+        }
+        for (int64_t i = 0; i < n_vox; ++i)
+            if (!(v->pad[i] >= 0.0f) || !std::isfinite(v->pad[i]))
+                return fail(VLS_ERR_INVALID_ARG, "plant area density must be finite and >= 0");
+        VLS_HIP(hipSetDevice(scene->ctx->device), "hipSetDevice");
+        hipStream_t s = (hipStream_t)stream;
+        float* pad = nullptr;
+        double* lut = nullptr;
+        VLS_HIP(hipMalloc(&pad, sizeof(float) * (size_t)n_vox), "voxel alloc");
+        hipError_t e = hipMalloc(&lut, sizeof(double) * 2 * (size_t)v->n_lut);
+        if (e == hipSuccess) e = hipMemcpyAsync(pad, v->pad, sizeof(float) * (size_t)n_vox, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(lut, v->lut, sizeof(double) * 2 * (size_t)v->n_lut, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            (void)hipFree(pad);
+            (void)hipFree(lut);
+            return hip_fail(e, "voxel upload");
+        }
+        VoxDev& d = scene->vox;
+        d.pad = pad;
+        d.lut = lut;
+        for (int a = 0; a < 3; ++a) d.origin[a] = v->origin[a];
+        d.size = v->voxel_size_m;
+        d.nx = v->nx;
+        d.ny = v->ny;
+        d.nz = v->nz;
+        d.n_lut = v->n_lut;
+        d.seed = v->seed;
+        d.n_vox = n_vox;
+        scene->stats.device_bytes += (int64_t)(sizeof(float) * n_vox + sizeof(double) * 2 * v->n_lut);
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
 vls_status vls_scene_stats_get(vls_scene scene, vls_scene_stats* out)
 {
     if (!scene || !out) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
@@ -718,7 +787,7 @@ vls_status vls_trace(vls_context ctx, vls_scene scene, const vls_scanner_desc* s
         Prepared pr;
         vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
         if (st != VLS_OK) return st;
-        if ((st = check_scene(ctx, scene)) != VLS_OK) return st;
+        if ((st = check_scene(ctx, scene, pr)) != VLS_OK) return st;
         if ((st = check_outputs(out)) != VLS_OK) return st;
         if (pulses->n_pulses > 0 && !out->subray_tri) return fail(VLS_ERR_INVALID_ARG, "subray_tri is required");
         if ((st = cone_workspace(ctx, pulses->n_pulses)) != VLS_OK) return st;
@@ -919,7 +988,7 @@ static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_s
 {
     vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
     if (st != VLS_OK) return st;
-    if ((st = check_scene(ctx, scene)) != VLS_OK) return st;
+    if ((st = check_scene(ctx, scene, pr)) != VLS_OK) return st;
     if ((st = check_outputs(out)) != VLS_OK) return st;
     if (pulses->n_pulses > 0 && (!out->n_returns || !out->ret_range || !out->ret_amplitude || !out->ret_bin))
         return fail(VLS_ERR_INVALID_ARG, "simulate needs n_returns, ret_range, ret_amplitude and ret_bin");
@@ -929,7 +998,7 @@ static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_s
     if (pulses->n_pulses > 0 && pulses->n_segments > 0) {
         if ((st = batch_tables(ctx, pr, bt)) != VLS_OK) return st;
         blocks = ctx->cfg.persistent_blocks > 0 ? ctx->cfg.persistent_blocks
-                                                : persistent_occupancy_blocks(pr.n_bins, staged_slots(pr), ctx->cfg);
+                                                : persistent_occupancy_blocks(pr.n_bins, staged_slots(pr), scene->vox.n_vox > 0, ctx->cfg);
     }
     return VLS_OK;
 }
@@ -1025,7 +1094,7 @@ vls_status vls_trace_counts(vls_context ctx, vls_scene scene, const vls_scanner_
         Prepared pr;
         vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
         if (st != VLS_OK) return st;
-        if ((st = check_scene(ctx, scene)) != VLS_OK) return st;
+        if ((st = check_scene(ctx, scene, pr)) != VLS_OK) return st;
         if (!counts) return fail(VLS_ERR_INVALID_ARG, "counts is NULL");
         hipStream_t s = (hipStream_t)stream;
         unsigned long long* dc = nullptr;
@@ -1236,7 +1305,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
         } else {
             int tried = 1;
             const bool seg = pulses->n_segments > 0;
-            int auto_blocks = seg ? persistent_occupancy_blocks(pr0.n_bins, staged_slots(pr0), entry) : 0;
+            int auto_blocks = seg ? persistent_occupancy_blocks(pr0.n_bins, staged_slots(pr0), scene->vox.n_vox > 0, entry) : 0;
             for (int dim = 0; dim < 5; ++dim) {
                 std::vector<LaunchCfg> cand;
                 for (int v = 0; v < 4; ++v) {
@@ -1292,7 +1361,7 @@ vls_status vls_cone_candidates(vls_context ctx, vls_scene scene, const vls_scann
         Prepared pr;
         vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
         if (st != VLS_OK) return st;
-        if ((st = check_scene(ctx, scene)) != VLS_OK) return st;
+        if ((st = check_scene(ctx, scene, pr)) != VLS_OK) return st;
         if (pulses->n_pulses > 0 && !candidates) return fail(VLS_ERR_INVALID_ARG, "candidates is NULL");
         if (!aligned(candidates, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned candidates");
         hipStream_t s = (hipStream_t)stream;

@@ -217,6 +217,23 @@ __device__ __forceinline__ void setup_box(const Ray& r, float scene_mag, RayBox&
     }
 }
 
+// Output number c of the SplitMix64 sequence seeded with `seed` (Steele, Lea &
+// Flood 2014): the state after c + 1 steps of the Weyl increment, mixed.  Any
+// output is reached directly, so parallel draws need no shared state.
+__device__ __forceinline__ uint64_t sm64(uint64_t seed, uint64_t c)
+{
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// A uniform number in (0, 1]: ((x >> 11) + 1) 2^-53 of output c.
+__device__ __forceinline__ double sm_uniform(uint64_t seed, uint64_t c)
+{
+    return (double)((sm64(seed, c) >> 11) + 1) * (1.0 / 9007199254740992.0);
+}
+
 // Outgoing pulse at offset s (ns): unit-peak Gaussian (SHAPE 0), or Eq. 3
 // (s/tau)^2 exp(-s/tau) (SHAPE 1).  exp2 is the hardware instruction: results
 // below 2^-126 flush to zero, far under any bin that matters.

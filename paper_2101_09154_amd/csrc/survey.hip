@@ -25,23 +25,12 @@
 #include <math.h>
 #include <stdint.h>
 
-#include "vls_internal.h"
+#include "device_common.h"
 
 namespace vls {
 namespace {
 
-__device__ __forceinline__ uint64_t sm64(uint64_t seed, uint64_t c)
-{
-    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ double sm_uniform(uint64_t seed, uint64_t c)
-{
-    return (double)((sm64(seed, c) >> 11) + 1) * (1.0 / 9007199254740992.0);
-}
+using dev::sm_uniform;
 
 // tab: per waypoint i, [x, y, z, cumulative length, cos yaw, sin yaw] of the
 // leg that starts there (the last entry's yaw is unused).

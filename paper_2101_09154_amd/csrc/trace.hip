@@ -38,6 +38,7 @@
 
 #include "vls_internal.h"
 #include "device_common.h"
+#include "voxels.h"
 
 namespace vls {
 namespace {
@@ -652,7 +653,7 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
 // MODE 2: trace only, adding subrays / node visits / triangle tests to out.counts.
 // CHUNK: a launch for a scanner with one pulse per wavefront, which stages long
 // candidate lists in chunks (kept out of the other launches' code).
-template <int MAXCH, int MODE, bool CHUNK = false>
+template <int MAXCH, int MODE, bool CHUNK, bool VOX>
 __device__ __forceinline__ void process_wave(const SceneDev& scene, const ScannerDev& sc,
                                              const PulsesDev& pulses, const OutDev& out, long long first, int npw,
                                              int* ring, int ring_mask, unsigned char* wl)
@@ -716,6 +717,21 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
         long long p = first + pl;
         trace_lane<MODE == 2, CHUNK>(scene, sc, pulses, p, k, pl, r, ray_ok, staged, rec, ring, ring_mask, tri, R, cs, P,
                               visits, tests);
+        if (VOX && ray_ok) {
+            // a voxel that stops the subray before its closest triangle takes the
+            // echo: id n_tri + voxel, cos 1, power by Eq. 8 (proportionality as
+            // equality): P = power_c w sigma / (pi beta^2 R^4)
+            double tv, sg;
+            const uint64_t c0 = ((uint64_t)p * kWave + (uint64_t)k) * (uint64_t)scene.vox.n_vox;
+            const long long vi = voxel_stop(scene.vox, r.O, r.D, tri >= 0 ? R : (double)INFINITY, c0, tv, sg);
+            if (vi >= 0) {
+                tri = scene.n_tri + (int)vi;
+                R = tv;
+                cs = 1.0f;
+                const double R2 = tv * tv;
+                P = (float)(sc.vox_c * sc.pattern[5 * k + 4] * sg / (R2 * R2));
+            }
+        }
         long long o = p * out.sub_stride + k;
         if (out.sub_tri) out.sub_tri[o] = tri;
         if (out.sub_range) out.sub_range[o] = R;
@@ -750,7 +766,7 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     }
 }
 
-template <int MAXCH, int MODE, bool CHUNK>
+template <int MAXCH, int MODE, bool CHUNK, bool VOX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_simulate(SceneDev scene, ScannerDev sc, PulsesDev pulses,
                                                   OutDev out, long long first, long long count, int ring_mask,
                                                   int wl_bytes)
@@ -764,7 +780,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     if (p0 >= count) return;
     long long left = count - p0;
     int npw = left < sc.P_w ? (int)left : sc.P_w;
-    process_wave<MAXCH, MODE, CHUNK>(scene, sc, pulses, out, first + p0, npw, ring, ring_mask, wl);
+    process_wave<MAXCH, MODE, CHUNK, VOX>(scene, sc, pulses, out, first + p0, npw, ring, ring_mask, wl);
 }
 
 // Waveform from stored subrays (KIND 0) or returns from stored waveforms (KIND 1).
@@ -809,7 +825,7 @@ __global__ __launch_bounds__(256) void k_wave(ScannerDev sc, PulsesDev pulses, O
 }
 
 // Persistent batched kernel: wavefronts take chunks of wave-tiles from a global counter.
-template <int MAXCH>
+template <int MAXCH, bool VOX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_persistent(SceneDev scene, BatchDev batch, PulsesDev pulses,
                                                     OutDev out, int ring_mask, int wl_bytes)
 {
@@ -842,7 +858,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
             long long p = batch.pulse_off[lo] + (tile - batch.tile_off[lo]) * sc.P_w;
             long long left = batch.pulse_end[lo] - p;
             int npw = left < sc.P_w ? (int)left : sc.P_w;
-            process_wave<MAXCH, 1>(scene, sc, pulses, out, p, npw, ring, ring_mask, wl);
+            process_wave<MAXCH, 1, false, VOX>(scene, sc, pulses, out, p, npw, ring, ring_mask, wl);
             wave_sync();
         }
     }
@@ -919,14 +935,21 @@ hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const Pu
     const int wl = wave_lds_bytes(pulses.cand ? sc.P_w * staged_per_pulse(sc.P_w) : 0);
     size_t lds = sim_lds_bytes(block, cfg.stack_lds, wl);
     int mask = cfg.stack_lds - 1;
-#define VLS_SIM_LAUNCH(CH, MODE)                                                                              \
+    // separate instantiations for scenes with voxels keep the others' code unchanged
+    const bool vox = scene.vox.n_vox > 0;
+#define VLS_SIM_LAUNCH_V(CH, MODE, VOX)                                                                       \
     do {                                                                                                     \
         if (sc.P_w == 1 && MODE != 2)                                                                        \
-            hipLaunchKernelGGL((k_simulate<CH, MODE, true>), dim3(grid), dim3(block), lds, stream, scene, sc, pulses, \
-                               out, first, count, mask, wl);                                                 \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_simulate<CH, MODE, false>), dim3(grid), dim3(block), lds, stream, scene, sc,  \
+            hipLaunchKernelGGL((k_simulate<CH, MODE, true, VOX>), dim3(grid), dim3(block), lds, stream, scene, sc, \
                                pulses, out, first, count, mask, wl);                                         \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_simulate<CH, MODE, false, VOX>), dim3(grid), dim3(block), lds, stream, scene, sc, \
+                               pulses, out, first, count, mask, wl);                                         \
+    } while (0)
+#define VLS_SIM_LAUNCH(CH, MODE)               \
+    do {                                       \
+        if (vox) VLS_SIM_LAUNCH_V(CH, MODE, true);  \
+        else VLS_SIM_LAUNCH_V(CH, MODE, false);     \
     } while (0)
     if (mode == 0) VLS_SIM_LAUNCH(4, 0);
     else if (mode == 2) VLS_SIM_LAUNCH(4, 2);
@@ -934,6 +957,7 @@ hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const Pu
     else if (sc.n_bins <= 512) VLS_SIM_LAUNCH(8, 1);
     else VLS_SIM_LAUNCH(16, 1);
 #undef VLS_SIM_LAUNCH
+#undef VLS_SIM_LAUNCH_V
     return hipGetLastError();
 }
 
@@ -991,27 +1015,38 @@ hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int m
     long long waves = (long long)blocks * cfg.block_waves;
     long long ch = batch.n_tiles / (waves * 16 > 0 ? waves * 16 : 1);
     b.chunk = (int)(ch < 1 ? 1 : (ch > 4096 ? 4096 : ch));
-    if (max_bins <= 256)
-        hipLaunchKernelGGL((k_persistent<4>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask,
-                           wl);
-    else if (max_bins <= 512)
-        hipLaunchKernelGGL((k_persistent<8>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask,
-                           wl);
-    else
-        hipLaunchKernelGGL((k_persistent<16>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask,
-                           wl);
+#define VLS_PERSISTENT(CH, VOX)                                                                                \
+    hipLaunchKernelGGL((k_persistent<CH, VOX>), dim3(blocks), dim3(block), lds, stream, scene, b, pulses, out, mask, wl)
+    const bool vox = scene.vox.n_vox > 0;
+    if (max_bins <= 256) {
+        if (vox) VLS_PERSISTENT(4, true);
+        else VLS_PERSISTENT(4, false);
+    } else if (max_bins <= 512) {
+        if (vox) VLS_PERSISTENT(8, true);
+        else VLS_PERSISTENT(8, false);
+    } else {
+        if (vox) VLS_PERSISTENT(16, true);
+        else VLS_PERSISTENT(16, false);
+    }
+#undef VLS_PERSISTENT
     return hipGetLastError();
 }
 
-int persistent_occupancy_blocks(int max_bins, int staged_slots, const LaunchCfg& cfg)
+int persistent_occupancy_blocks(int max_bins, int staged_slots, bool vox, const LaunchCfg& cfg)
 {
     const int block = cfg.block_waves * kWave;
     size_t lds = sim_lds_bytes(block, cfg.stack_lds, wave_lds_bytes(cfg.cone ? staged_slots : 0));
     int per_cu = 0;
     hipError_t e;
-    if (max_bins <= 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<4>, block, lds);
-    else if (max_bins <= 512) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<8>, block, lds);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<16>, block, lds);
+    if (max_bins <= 256)
+        e = vox ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<4, true>, block, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<4, false>, block, lds);
+    else if (max_bins <= 512)
+        e = vox ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<8, true>, block, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<8, false>, block, lds);
+    else
+        e = vox ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<16, true>, block, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<16, false>, block, lds);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);

@@ -64,6 +64,18 @@ struct ScannerDev {
     double thr_abs;
     double thr_rel;
     double tan_max;         // tan of the largest subray angle (outer ring)
+    double vox_c;           // voxel echoes (Eq. 8): power_c / (pi beta^2), beta the full divergence
+};
+
+// A transmissive voxel grid (see voxels.h); n_vox == 0: none.
+struct VoxDev {
+    const float* pad;       // [nz][ny][nx] plant area density
+    const double* lut;      // [n_lut][2]: vertical component (strictly increasing), g
+    double origin[3];
+    double size;            // voxel side
+    int nx, ny, nz, n_lut;
+    unsigned long long seed;
+    long long n_vox;        // nx * ny * nz
 };
 
 // Binary LBVH: node = 4 x float4 (64 B): left box lo.xyz hi.x | hi.yz, right lo.xy |
@@ -80,6 +92,7 @@ struct SceneDev {
     const int32_t* tri_idx; // [n_tri][3] vertex indices (adjoint)
     int root;
     int n_tri;
+    VoxDev vox;
 };
 
 struct PulsesDev {
@@ -208,6 +221,6 @@ hipError_t launch_generate(const SurveyDev& sv, const double* tab, long long fir
 // Candidate lists hold leaf indices; rewrite them as original triangle indices.
 hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_pulses, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);
-int persistent_occupancy_blocks(int max_bins, int staged_slots, const LaunchCfg& cfg);
+int persistent_occupancy_blocks(int max_bins, int staged_slots, bool vox, const LaunchCfg& cfg);
 
 }  // namespace vls

@@ -47,6 +47,11 @@ class SceneStats(ctypes.Structure):
                 ("bounds_hi", ctypes.c_float * 3), ("box_pad", ctypes.c_float), ("reserved", ctypes.c_float)]
 
 
+class VoxelDesc(ctypes.Structure):
+    _fields_ = [("origin", f64 * 3), ("voxel_size_m", f64), ("nx", i32), ("ny", i32), ("nz", i32), ("n_lut", i32),
+                ("pad", P), ("lut", P), ("seed", ctypes.c_uint64)]
+
+
 class ScannerDesc(ctypes.Structure):
     _fields_ = [("divergence_rad", f64), ("pattern_extent", f64), ("pulse_width_ns", f64), ("bin_ns", f64),
                 ("window_pre_ns", f64), ("peak_power_w", f64), ("receiver_diameter_m", f64),
@@ -101,6 +106,7 @@ _SIGS = {
     "vls_scene_create": ([P, P, P, P], i32),
     "vls_scene_update_vertices": ([P, P, P], i32),
     "vls_scene_update_reflectance": ([P, P, P], i32),
+    "vls_scene_set_voxels": ([P, P, P], i32),
     "vls_scene_stats_get": ([P, P], i32),
     "vls_scene_export": ([P, P, P, P, P], i32),
     "vls_scene_destroy": ([P], i32),
@@ -231,6 +237,19 @@ class Scene:
     def update_reflectance(self, reflectance, stream=None):
         r = _dev(reflectance, torch.float32, (self.n_triangles,), "reflectance")
         _check(lib().vls_scene_update_reflectance(self._h, _ptr(r), _stream(stream)))
+
+    def set_voxels(self, origin, voxel_size_m, pad, lut, seed=0, stream=None):
+        """A transmissive voxel grid: pad [nz, ny, nx] plant area density, lut [n, 2] rows of the
+        leaf-angle table (vertical component, g); host arrays, copied."""
+        pad = np.ascontiguousarray(pad, dtype=np.float32)
+        lut = np.ascontiguousarray(lut, dtype=np.float64).reshape(-1, 2)
+        if pad.ndim != 3:
+            raise ValueError("pad must be [nz, ny, nx]")
+        nz, ny, nx = pad.shape
+        desc = VoxelDesc((f64 * 3)(*[float(x) for x in origin]), float(voxel_size_m), nx, ny, nz, lut.shape[0],
+                         pad.ctypes.data, lut.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF)
+        _check(lib().vls_scene_set_voxels(self._h, ctypes.byref(desc), _stream(stream)))
+        self.n_voxels = int(pad.size)
 
     def export(self):
         n = self.n_triangles

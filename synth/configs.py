@@ -1,4 +1,4 @@
-"""The five synthetic workloads, as (scene, pulses, scanner) recipes.
+"""The six synthetic workloads, as (scene, pulses, scanner) recipes.
 
   small_tls      64x64 value-noise DTM at 1 m (7,938 triangles); terrestrial
                  scanner, 100x100 az/el grid; 19 subrays; 256 x 1 ns bins.
@@ -7,6 +7,10 @@
                  31 subrays; 512 x 0.5 ns bins.
   uls_trees      200x200 m fBm DTM at 0.5 m + 2,000 procedural trees
                  (~9.95M triangles); 60 m AGL, 2M pulses; 61 subrays; 8 returns.
+  uls_voxels     the uls_trees terrain and flight; trunks and branches as
+                 triangles (5,952,000), crowns as 0.5 m transmissive voxels of
+                 plant area density 0.2-1.6 m^2/m^3 per crown (summed where
+                 crowns overlap); Table 2's printed rows.
   batched_tls    the als_buildings scene; 256 terrestrial positions with
                  log-uniform pulse counts in [1k, 200k]; three scanner types.
   diff_als       the small_tls noise field on 256x256 vertices (130,050
@@ -17,7 +21,8 @@ A scanner is a plain dict of instrument parameters (no method arithmetic).
 import numpy as np
 
 from .rng import stream_uniform, uniform01
-from .scenes import value_noise_field, dtm_mesh, add_boxes, merge_meshes, ground_height, procedural_trees
+from .scenes import (value_noise_field, dtm_mesh, add_boxes, merge_meshes, ground_height, procedural_trees,
+                     tree_layout, crown_voxels)
 from .pulses import tls_grid, als_lines, concat_pulses
 
 
@@ -113,6 +118,31 @@ def uls_trees(seed=ULS_SEED, strips=4, n_lines=500, per_line=1000, mesh=None):
     pulses = Pulses(o, d, info={"kind": "uls"})
     sc = scanner(0.25e-3, 61, pulse_width_ns=4.0, bin_ns=0.5, n_bins=512, max_returns=8)
     return mesh, pulses, sc
+
+
+# ---------------------------------------------------------------- uls_voxels
+# The rows of the leaf-angle table the paper prints (Table 2, erectophile):
+# (vertical component of the beam, hit probability g).  Its middle rows are
+# elided there; between the printed rows the table is taken as linear.
+TABLE2_ROWS = [[0.0, 0.424413], [0.025180, 0.424682], [0.050345, 0.425489], [0.999955, 0.848789],
+               [1.0, 0.848822]]
+
+
+def uls_voxels(seed=ULS_SEED, strips=4, n_lines=500, per_line=1000, voxel_size=0.5):
+    """The uls_trees terrain and flight, with woody trees (trunks and branches as
+    triangles) whose crowns are transmissive voxels of plant area density."""
+    x = np.arange(401, dtype=np.float64) * 0.5
+    X, Y = np.meshgrid(x, x)
+    h = value_noise_field(X, Y, seed=seed, octaves=5, base_wavelength=64.0, amplitude=5.0)
+    dtm = dtm_mesh(h, 0.5, refl_seed=seed)
+    wood = procedural_trees(h, 0.5, 2000, seed=seed, extent=200.0, leaves=0)
+    mesh = merge_meshes([dtm, wood])
+    mesh.info.update(kind="uls_voxels", heights_mean=float(h.mean()), extent=200.0)
+    lay = tree_layout(h, 0.5, 2000, seed=seed, extent=200.0)
+    origin, pad = crown_voxels(lay, seed=seed, extent=200.0, voxel_size=voxel_size)
+    voxels = dict(origin=list(origin), size=float(voxel_size), pad=pad, lut=TABLE2_ROWS, seed=seed)
+    _, pulses, sc = uls_trees(seed, strips, n_lines, per_line, mesh=mesh)
+    return mesh, voxels, pulses, sc
 
 
 # ---------------------------------------------------------------- batched_tls

@@ -240,6 +240,51 @@ def _poisson_positions(n, extent, min_dist, seed, margin=5.0):
     return np.array(pts)
 
 
+def tree_layout(heights, spacing, n_trees, *, seed, extent, min_dist=3.0):
+    """Positions, ground heights, heights and crown ellipsoids (horizontal
+    semi-axis ca, vertical cc, centre height cz) of the procedural trees."""
+    pos = _poisson_positions(n_trees, extent, min_dist, seed)
+    tid = np.arange(n_trees)
+    gz = ground_height(heights, spacing, pos[:, 0], pos[:, 1])
+    H = 10.0 + 15.0 * uniform01(seed, 40, tid)
+    ca = 2.0 + 2.0 * uniform01(seed, 45, tid)
+    cc = 0.3 * H
+    cz = gz + 0.7 * H
+    return dict(pos=pos, gz=gz, H=H, ca=ca, cc=cc, cz=cz)
+
+
+def crown_voxels(layout, *, seed, extent, voxel_size=0.5, pad_range=(0.4, 1.6)):
+    """Plant area density (m^2/m^3) of the crowns on a grid over [0, extent]^2
+    and the crowns' height range: each tree adds pad_tree (0.5 + 0.5 u) to the
+    voxels whose centre lies in its crown ellipsoid, pad_tree uniform in
+    ``pad_range`` per tree and u uniform per voxel.  Returns (origin, pad
+    [nz, ny, nx] float32)."""
+    pos, ca, cc, cz = layout["pos"], layout["ca"], layout["cc"], layout["cz"]
+    n = pos.shape[0]
+    z0 = np.floor((cz - cc).min() / voxel_size) * voxel_size
+    z1 = (cz + cc).max()
+    nx = ny = int(np.ceil(extent / voxel_size))
+    nz = int(np.ceil((z1 - z0) / voxel_size))
+    vary = 0.5 + 0.5 * stream_uniform(seed, 54, nx * ny * nz).reshape(nz, ny, nx)
+    pad_tree = pad_range[0] + (pad_range[1] - pad_range[0]) * uniform01(seed, 53, np.arange(n))
+    pad = np.zeros((nz, ny, nx), np.float64)
+    cx = (np.arange(nx) + 0.5) * voxel_size
+    czs = z0 + (np.arange(nz) + 0.5) * voxel_size
+    for t in range(n):
+        i0 = max(int((pos[t, 0] - ca[t]) / voxel_size), 0)
+        i1 = min(int((pos[t, 0] + ca[t]) / voxel_size) + 1, nx)
+        j0 = max(int((pos[t, 1] - ca[t]) / voxel_size), 0)
+        j1 = min(int((pos[t, 1] + ca[t]) / voxel_size) + 1, ny)
+        k0 = max(int((cz[t] - cc[t] - z0) / voxel_size), 0)
+        k1 = min(int((cz[t] + cc[t] - z0) / voxel_size) + 1, nz)
+        X = ((cx[i0:i1] - pos[t, 0]) / ca[t]) ** 2
+        Y = ((cx[j0:j1] - pos[t, 1]) / ca[t]) ** 2
+        Z = ((czs[k0:k1] - cz[t]) / cc[t]) ** 2
+        inside = (Z[:, None, None] + Y[None, :, None] + X[None, None, :]) <= 1.0
+        pad[k0:k1, j0:j1, i0:i1] += np.where(inside, pad_tree[t] * vary[k0:k1, j0:j1, i0:i1], 0.0)
+    return (0.0, 0.0, float(z0)), pad.astype(np.float32)
+
+
 def procedural_trees(heights, spacing, n_trees, *, seed, extent, min_dist=3.0,
                      trunk_segments=8, facets=16, branches=40, branch_segments=2,
                      leaves=2000, leaf_size=0.05, refl_range=(0.1, 0.6)):
@@ -250,11 +295,10 @@ def procedural_trees(heights, spacing, n_trees, *, seed, extent, min_dist=3.0,
     of the trunk, ``leaves`` equilateral triangles of side ``leaf_size`` placed
     uniformly in a crown ellipsoid with isotropic normals.
     """
-    pos = _poisson_positions(n_trees, extent, min_dist, seed)
+    lay = tree_layout(heights, spacing, n_trees, seed=seed, extent=extent, min_dist=min_dist)
+    pos, gz, H = lay["pos"], lay["gz"], lay["H"]
     n = n_trees
     tid = np.arange(n)
-    gz = ground_height(heights, spacing, pos[:, 0], pos[:, 1])
-    H = 10.0 + 15.0 * uniform01(seed, 40, tid)
     r_base = 0.12 + 0.012 * H
     r_top = 0.25 * r_base
     # trunk frusta
@@ -285,9 +329,7 @@ def procedural_trees(heights, spacing, n_trees, *, seed, extent, min_dist=3.0,
     # leaves: uniform in the crown ellipsoid, isotropic normals
     lid = np.arange(n * leaves)
     tree_of_l = lid // leaves
-    ca = 2.0 + 2.0 * uniform01(seed, 45, tid)
-    cc = 0.3 * H
-    cz = gz + 0.7 * H
+    ca, cc, cz = lay["ca"], lay["cc"], lay["cz"]
     # uniform point in the unit ball by radius cube-root + direction
     u1 = uniform01(seed, 46, lid)
     u2 = uniform01(seed, 47, lid)

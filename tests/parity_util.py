@@ -4,7 +4,9 @@ Hit triangle ids: >= 99.99 % equal, and every mismatch excused: in FP64 the
 subray hits the GPU's triangle (when the GPU reports one) and the hit lies
 within 1e-6 (barycentric) of an edge of either triangle, or the two hit
 distances agree to 1e-6 relative (a depth tie).  A miss against a hit is
-excused only at an edge of the hit triangle.
+excused only at an edge of the hit triangle.  A voxel echo (id >= n_triangles)
+against anything else is excused only where the two distances agree to 1e-6
+relative; equal voxel echoes carry Eq. 8's power to 1e-6 relative and cos 1.
 Range: <= 1e-4 m on equal ids.
 Waveform: per-pulse relative L2 <= 1e-5 for pulses whose ids all match;
 all-miss pulses are all zero.
@@ -48,6 +50,7 @@ def _bary_min(O, d, mesh, tri):
 def check_hits(mesh, pulses, sc, sel, g, r, report):
     """g: GPU dict (numpy) rows for the selected pulses; r: oracle result."""
     S = r.S
+    nt = mesh.n_triangles
     gt = g["subray_tri"][:, :S]
     eq = gt == r.sub_tri
     frac = float(eq.mean())
@@ -56,9 +59,16 @@ def check_hits(mesh, pulses, sc, sel, g, r, report):
     unexcused = []
     for q, k in bad:
         p = sel[q]
+        go, oo = int(gt[q, k]), int(r.sub_tri[q, k])
+        if go >= nt or oo >= nt:
+            # a voxel echo (id >= n_triangles) against anything else: excused
+            # only where the two distances tie
+            rg, ro = float(g["subray_range"][q, k]), float(r.sub_range[q, k])
+            if not (np.isfinite(rg) and np.isfinite(ro) and abs(rg - ro) <= 1e-6 * ro):
+                unexcused.append((int(p), int(k), go, oo))
+            continue
         O = pulses.origins[p].astype(np.float64)
         d = oracle.subray_directions(pulses.directions[p].astype(np.float64), sc)[k]
-        go, oo = int(gt[q, k]), int(r.sub_tri[q, k])
         ok = False
         if go >= 0:
             hg, tg, bg = _bary_min(O, d, mesh, go)
@@ -80,7 +90,16 @@ def check_hits(mesh, pulses, sc, sel, g, r, report):
     report["max_range_err"] = float(ranges[m].max()) if m.any() else 0.0
     miss_ok = bool(np.all(np.isinf(g["subray_range"][:, :S][eq & (r.sub_tri < 0)])))
     report["miss_ok"] = miss_ok
-    return frac >= ID_FRACTION and not unexcused and report["max_range_err"] <= RANGE_TOL and miss_ok
+    power_ok = True
+    vm = eq & (r.sub_tri >= nt)
+    if vm.any() and "subray_power" in g:
+        # voxel echoes: Eq. 8's power, rounded once to FP32 by the GPU
+        rel = np.abs(g["subray_power"][:, :S][vm] - r.sub_power[vm]) / r.sub_power[vm]
+        report["voxel_echoes"] = int(vm.sum())
+        report["voxel_power_rel_err"] = float(rel.max())
+        power_ok = report["voxel_power_rel_err"] <= 1e-6 and bool(np.all(g["subray_cos"][:, :S][vm] == 1.0))
+    return (frac >= ID_FRACTION and not unexcused and report["max_range_err"] <= RANGE_TOL and miss_ok
+            and power_ok)
 
 
 def check_waveforms(g, r, report):

@@ -160,3 +160,55 @@ def test_voxel_echo_power_and_ids(orc):
     assert np.array_equal(r.sub_tri, r2.sub_tri)
     r3 = orc.simulate(plane, pulses, sc, voxels=dict(vox, seed=12))
     assert not np.array_equal(r.sub_tri, r3.sub_tri)
+
+
+def test_degenerate_rays_and_grids(orc):
+    vox = _grid(np.full((2, 2, 2), 3.0, np.float32))
+    # a ray that is not finite meets nothing
+    for O, d in [([np.nan, 0.5, 0.5], [1.0, 0.0, 0.0]), ([-1.0, 0.5, 0.5], [np.nan, 0.0, 0.0]),
+                 ([-1.0, 0.5, np.inf], [1.0, 0.0, 0.0])]:
+        assert orc.voxel_hit(vox, O, d, math.inf, 0, 0)[0] == -1
+    # a ray parallel to a face outside the grid, a ray pointing away, and one
+    # starting beyond its far side meet nothing
+    assert orc.voxel_hit(vox, [-1.0, 2.5, 0.5], [1.0, 0.0, 0.0], math.inf, 0, 0)[0] == -1
+    assert orc.voxel_hit(vox, [-1.0, 0.5, 0.5], [-1.0, 0.0, 0.0], math.inf, 0, 0)[0] == -1
+    assert orc.voxel_hit(vox, [3.0, 0.5, 0.5], [1.0, 0.0, 0.0], math.inf, 0, 0)[0] == -1
+    # a ray starting inside stops at depths measured from its origin
+    ts = [orc.voxel_hit(vox, [0.5, 0.5, 0.5], [1.0, 0.0, 0.0], math.inf, p, 0) for p in range(4000)]
+    t = np.array([x[1] for x in ts if x[0] >= 0])
+    sigma = 3.0 * 0.5
+    assert abs(np.mean(np.array([x[0] for x in ts]) < 0) - math.exp(-1.5 * sigma)) < 0.02
+    assert t.min() >= 0.0 and t.max() <= 1.5
+
+
+def test_voxel_gradient_is_the_triangles_alone(orc):
+    # voxel echoes depend on neither reflectance nor heights: with a grid that
+    # stops every subray the gradient vanishes; with an empty one it is the
+    # gradient without voxels
+    mesh = synth.flat_quad(-50.0, 50.0, -50.0, 50.0, 0.0, reflectance=0.5)
+    sc = configs.scanner(2e-3, 19, n_bins=128, bin_ns=0.5)
+    o = np.tile([[0.3, -0.2, 30.0]], (6, 1))
+    d = np.tile([[0.05, 0.02, -1.0]], (6, 1)).astype(np.float32)
+    pulses = synth.Pulses(o, d)
+    base = orc.simulate(mesh, pulses, sc)
+    G = np.random.default_rng(1).normal(size=base.waveform.shape)
+    gr0, gz0 = orc.gradient(mesh, pulses, sc, base.t0, G, threads=1)
+    assert np.abs(gr0).max() > 0
+    empty = _grid(np.zeros((2, 2, 2), np.float32), size=4.0, origin=(-4.0, -4.0, 10.0))
+    gr1, gz1 = orc.gradient(mesh, pulses, sc, base.t0, G, threads=1, voxels=empty)
+    assert np.array_equal(gr0, gr1) and np.array_equal(gz0, gz1)
+    wall = _grid(np.full((2, 2, 2), 1e9, np.float32), size=4.0, origin=(-4.0, -4.0, 10.0))
+    assert (orc.simulate(mesh, pulses, sc, voxels=wall).sub_tri >= mesh.n_triangles).all()
+    gr2, gz2 = orc.gradient(mesh, pulses, sc, base.t0, G, voxels=wall)
+    assert not gr2.any() and not gz2.any()
+
+
+def test_voxel_forest_workload():
+    mesh, vox, pulses, sc = configs.uls_voxels(n_lines=2, per_line=10)
+    pad = vox["pad"]
+    nz, ny, nx = pad.shape
+    assert (nx, ny) == (400, 400) and vox["size"] == 0.5
+    assert pad.dtype == np.float32 and pad.min() >= 0.0 and 0.05 < (pad > 0).mean() < 0.8
+    # the grid is tight around the crowns: they reach its lowest and highest layers
+    assert pad[0].any() and pad[-1].any()
+    assert mesh.n_triangles + pad.size < 2**31
