@@ -190,6 +190,44 @@ def bench_grad(ctx, steps):
             "grad_norm_heights": float(heights.grad.norm().item())}
 
 
+def bench_voxels(ctx, steps):
+    """Transmissive voxels (Sec. 3.5.4, Sec. 5.2): the uls_voxels forest, crowns
+    as a voxel grid of plant area density over woody trees and terrain."""
+    import torch
+    from synth import configs
+    import paper_2101_09154_amd as vp
+    mesh, vox, pulses, sc = configs.uls_voxels()
+    dev = torch.device("cuda", 0)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    scene.set_voxels(vox["origin"], vox["size"], vox["pad"], vox["lut"], vox["seed"])
+    o = torch.from_numpy(pulses.origins).to(dev)
+    d = torch.from_numpy(pulses.directions).to(dev)
+    n = pulses.n
+    S = vp.n_subrays(sc)
+    out = ctx.alloc_outputs(n, S, sc["n_bins"], sc["max_returns"], dev)
+    stream = torch.cuda.current_stream()
+    ctx.simulate(scene, sc, o, d, out=out)
+    torch.cuda.synchronize()
+    vfrac = float((out["subray_tri"] >= mesh.n_triangles).float().mean().item())
+    ms = time_ms(lambda: ctx.simulate(scene, sc, o, d, out=out), steps, 1, stream)
+    ctx.profile(True)
+    for _ in range(steps):
+        ctx.simulate(scene, sc, o, d, out=out)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    nz, ny, nx = vox["pad"].shape
+    res = {"workload": "uls_voxels: uls_trees terrain and flight (2,000,000 pulses, 61 subrays, 512 x 0.5 ns bins), "
+                       "trunks and branches as %d triangles, crowns as %d x %d x %d voxels of 0.5 m"
+                       % (mesh.n_triangles, nx, ny, nz),
+           "ms": ms, "subrays_per_s": n * S / (ms * 1e-3), "pulses_per_s": n / (ms * 1e-3),
+           "voxel_echo_fraction": vfrac,
+           "fused_ms": prof["fused_ms"] / max(prof["fused_launches"], 1),
+           "cone_ms": prof["cone_ms"] / max(prof["cone_launches"], 1),
+           "packet_ms": prof["packet_ms"] / max(prof["packet_launches"], 1)}
+    scene.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,6 +445,8 @@ def main():
         res["batched"] = bench_batched(ctx, scene, mesh, args.steps // 2 if args.steps > 2 else 1)
         log("gradient workload")
         res["gradient"] = bench_grad(ctx, max(args.steps // 2, 2))
+        log("voxel workload")
+        res["voxels"] = bench_voxels(ctx, max(args.steps // 2, 2))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(mesh, pulses, sc, args.cpu_seconds)
