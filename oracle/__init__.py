@@ -26,7 +26,8 @@ def build(force=True):
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", tmp, SRC, "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", tmp,
+                           SRC, "-lm"])
     os.replace(tmp, LIB)
     return LIB
 
@@ -111,6 +112,7 @@ def lib():
         L.orc_lut_g.restype = ctypes.c_double
         L.orc_voxel_hit.argtypes = [P, P, P, ctypes.c_double, ctypes.c_uint64, P, P]
         L.orc_voxel_hit.restype = i64
+        L.orc_instance_vertices.argtypes = [P, i64, P, P]
         L.orc_max_threads.argtypes = []
         _lib = L
     return _lib
@@ -353,6 +355,28 @@ def gradient(mesh, pulses, sc, t0, grad_wf, threads=0, voxels=None):
     if got < 0:
         raise RuntimeError("oracle gradient failed")
     return gr, gz
+
+
+def instance_mesh(parts, instances):
+    """The scene of parts placed by affine maps (Sec. 3.5, Sec. 5.1): instance i of part p
+    contributes part p's triangles with vertices A x + t (``instances``: (part, affine 3 x 4)),
+    in instance order; reflectance is the part's."""
+    from synth import Mesh
+    vs, ts, rs = [], [], []
+    off = 0
+    for part, aff in instances:
+        m = parts[part]
+        a = np.ascontiguousarray(aff, dtype=np.float64).reshape(3, 4)
+        v = np.ascontiguousarray(m.vertices, dtype=np.float32)
+        w = np.empty_like(v)
+        if v.shape[0]:
+            lib().orc_instance_vertices(_ptr(v), v.shape[0], _ptr(a), _ptr(w))
+        vs.append(w)
+        ts.append(m.triangles.astype(np.int64) + off)
+        rs.append(m.reflectance)
+        off += v.shape[0]
+    cat = lambda xs, shape, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(shape, dt)
+    return Mesh(cat(vs, (0, 3), np.float32), cat(ts, (0, 3), np.int32), cat(rs, (0,), np.float32))
 
 
 def max_threads():

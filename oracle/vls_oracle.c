@@ -34,7 +34,10 @@
  *   9. optionally, transmissive voxels (Sec. 3.5.4, Sec. 5.2): a subray crossing
  *      a voxel of plant area density PAD stops in it at a random depth drawn
  *      from the extinction coefficient (Eq. 5 through a leaf-angle table, Eq. 6),
- *      with the echo power of Eq. 8.
+ *      with the echo power of Eq. 8;
+ *  10. scene parts placed by affine maps (Sec. 3.5: a part loaded several
+ *      times and moved by transforms; Sec. 5.1: primitives rotate, scale and
+ *      translate): each instance's vertices mapped to the scene's frame.
  * Everything is FP64 with no truncation of the pulse support.
  *
  * Readings where the paper is silent or garbled:
@@ -994,6 +997,24 @@ int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, doub
     }
     free(cum);
     return 0;
+}
+
+/* Scene parts (Sec. 3.5, Sec. 5.1): instance vertices x -> A x + t with A and t
+ * the rows [A_i0 A_i1 A_i2 t_i] of `affine` (row-major 3 x 4), evaluated in
+ * FP64 in that order and rounded once to FP32. */
+void orc_instance_vertices(const float* v, int64_t nv, const double affine[12], float* out)
+{
+    for (int64_t q = 0; q < nv; ++q) {
+        double x = v[3 * q], y = v[3 * q + 1], z = v[3 * q + 2];
+        for (int i = 0; i < 3; ++i) {
+            const double* r = affine + 4 * i;
+            double w = r[0] * x;
+            w = w + r[1] * y;
+            w = w + r[2] * z;
+            w = w + r[3];
+            out[3 * q + i] = (float)w;
+        }
+    }
 }
 
 int orc_max_threads(void)
