@@ -118,6 +118,34 @@ typedef struct {
  * VLS_ERR_INVALID_ARG and builds nothing. */
 vls_status vls_scene_create(vls_context ctx, const vls_mesh_desc* mesh, void* stream, vls_scene* out);
 
+/* One placement of a scene part (Sec. 3.5: a part may be loaded several times
+ * and moved by transforms; Sec. 5.1: primitives rotate, scale and translate):
+ * the part's vertices x map to A x + t, affine = the rows [A_i0 A_i1 A_i2 t_i],
+ * i = 0..2 (row-major 3 x 4, float64, finite; any invertible or singular A). */
+typedef struct {
+    int32_t part;
+    int32_t reserved;
+    double affine[12];
+} vls_instance_desc;
+
+/* A scene of parts placed by instances.  Instance j contributes its part's
+ * triangles with vertices evaluated in FP64 as ((A_i0 x + A_i1 y) + A_i2 z) +
+ * t_i and rounded once to FP32, vertex indices offset by the instance's first
+ * vertex, and the part's reflectance.  Instances are laid out in order: the
+ * scene's triangle ids of instance j are [T_j, T_j + n_triangles of its part)
+ * with T_j the triangles of the instances before it (vertices likewise), so a
+ * hit id names its instance and its triangle in the part.  The result is then
+ * built and traced exactly as vls_scene_create's (one LBVH over the placed
+ * triangles; the device holds every placed copy).  Parts: as for
+ * vls_scene_create, each with its own memory kind; a part index outside
+ * [0, n_parts), a non-finite map, a part's vertex index outside its own
+ * vertices or a non-finite placed vertex returns VLS_ERR_INVALID_ARG.  More
+ * than 2^30 placed triangles or 2^31 placed vertices: VLS_ERR_UNSUPPORTED.
+ * Synchronises `stream`. */
+vls_status vls_scene_create_instanced(vls_context ctx, const vls_mesh_desc* parts, int32_t n_parts,
+                                      const vls_instance_desc* instances, int32_t n_instances, void* stream,
+                                      vls_scene* out);
+
 /* New vertex positions (same count and triangles): leaf records and node boxes
  * are refitted, the tree topology is kept.  `vertices_dev` is a device array
  * [n_vertices][3] float32.  Asynchronous on `stream`. */

@@ -671,6 +671,130 @@ vls_status vls_scene_create(vls_context ctx, const vls_mesh_desc* mesh, void* st
     }
 }
 
+vls_status vls_scene_create_instanced(vls_context ctx, const vls_mesh_desc* parts, int32_t n_parts,
+                                      const vls_instance_desc* instances, int32_t n_instances, void* stream,
+                                      vls_scene* out)
+{
+    // device buffers of this call, freed on return (after the stream has finished with them)
+    struct Temp {
+        std::vector<void*> p;
+        ~Temp()
+        {
+            for (void* q : p) (void)hipFree(q);
+        }
+        hipError_t alloc(void** q, size_t n)
+        {
+            hipError_t e = hipMalloc(q, n < 4 ? 4 : n);
+            if (e == hipSuccess) p.push_back(*q);
+            return e;
+        }
+    } tmp;
+    try {
+        if (!ctx || !out || (n_parts > 0 && !parts) || (n_instances > 0 && !instances))
+            return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        if (n_parts < 0 || n_instances < 0) return fail(VLS_ERR_INVALID_ARG, "negative counts");
+        for (int p = 0; p < n_parts; ++p) {
+            const vls_mesh_desc& m = parts[p];
+            if (m.n_vertices < 0 || m.n_triangles < 0) return fail(VLS_ERR_INVALID_ARG, "negative part sizes");
+            if ((m.n_vertices > 0 && !m.vertices) ||
+                (m.n_triangles > 0 && (!m.triangles || !m.reflectance || m.n_vertices < 1)))
+                return fail(VLS_ERR_INVALID_ARG, "a part lacks vertices, triangles or reflectance");
+            if (m.memory != VLS_MEM_HOST && m.memory != VLS_MEM_DEVICE)
+                return fail(VLS_ERR_INVALID_ARG, "memory must be VLS_MEM_HOST or VLS_MEM_DEVICE");
+        }
+        int64_t V = 0, T = 0;
+        std::vector<std::vector<int>> of_part(n_parts);
+        for (int j = 0; j < n_instances; ++j) {
+            const vls_instance_desc& d = instances[j];
+            if (d.part < 0 || d.part >= n_parts) return fail(VLS_ERR_INVALID_ARG, "instance part index out of range");
+            for (int i = 0; i < 12; ++i)
+                if (!std::isfinite(d.affine[i])) return fail(VLS_ERR_INVALID_ARG, "non-finite instance map");
+            of_part[d.part].push_back(j);
+            V += parts[d.part].n_vertices;
+            T += parts[d.part].n_triangles;
+            if (T > 0x3fffffff || V > 0x7fffffff) return fail(VLS_ERR_UNSUPPORTED, "more than 2^30 triangles or 2^31 vertices");
+        }
+        // first vertex and triangle of each instance, in instance order
+        std::vector<long long> voff(n_instances), toff(n_instances);
+        for (long long j = 0, v = 0, t = 0; j < n_instances; ++j) {
+            voff[j] = v;
+            toff[j] = t;
+            v += parts[instances[j].part].n_vertices;
+            t += parts[instances[j].part].n_triangles;
+        }
+        VLS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+        hipStream_t s = (hipStream_t)stream;
+        float *wv = nullptr, *wr = nullptr;
+        int32_t* wt = nullptr;
+        unsigned* bad = nullptr;
+        VLS_HIP(tmp.alloc((void**)&wv, 12 * (size_t)V), "instance alloc");
+        VLS_HIP(tmp.alloc((void**)&wt, 12 * (size_t)T), "instance alloc");
+        VLS_HIP(tmp.alloc((void**)&wr, 4 * (size_t)T), "instance alloc");
+        VLS_HIP(tmp.alloc((void**)&bad, 4), "instance alloc");
+        VLS_HIP(hipMemsetAsync(bad, 0, 4, s), "instance init");
+        for (int p = 0; p < n_parts; ++p) {
+            const std::vector<int>& js = of_part[p];
+            const vls_mesh_desc& m = parts[p];
+            if (js.empty() || (m.n_vertices == 0 && m.n_triangles == 0)) continue;
+            const float* pv = m.vertices;
+            const int32_t* pt = m.triangles;
+            const float* pr = m.reflectance;
+            if (m.memory == VLS_MEM_HOST) {
+                float *dv = nullptr, *dr = nullptr;
+                int32_t* dt = nullptr;
+                VLS_HIP(tmp.alloc((void**)&dv, 12 * (size_t)m.n_vertices), "part alloc");
+                VLS_HIP(tmp.alloc((void**)&dt, 12 * (size_t)m.n_triangles), "part alloc");
+                VLS_HIP(tmp.alloc((void**)&dr, 4 * (size_t)m.n_triangles), "part alloc");
+                if (m.n_vertices > 0)
+                    VLS_HIP(hipMemcpyAsync(dv, pv, 12 * (size_t)m.n_vertices, hipMemcpyHostToDevice, s), "part copy");
+                if (m.n_triangles > 0) {
+                    VLS_HIP(hipMemcpyAsync(dt, pt, 12 * (size_t)m.n_triangles, hipMemcpyHostToDevice, s), "part copy");
+                    VLS_HIP(hipMemcpyAsync(dr, pr, 4 * (size_t)m.n_triangles, hipMemcpyHostToDevice, s), "part copy");
+                }
+                pv = dv;
+                pt = dt;
+                pr = dr;
+            }
+            const size_t k = js.size();
+            std::vector<double> aff(12 * k);
+            std::vector<long long> off(2 * k);
+            for (size_t q = 0; q < k; ++q) {
+                memcpy(&aff[12 * q], instances[js[q]].affine, 12 * sizeof(double));
+                off[q] = voff[js[q]];
+                off[k + q] = toff[js[q]];
+            }
+            double* daff = nullptr;
+            long long* doff = nullptr;
+            VLS_HIP(tmp.alloc((void**)&daff, sizeof(double) * aff.size()), "instance table");
+            VLS_HIP(tmp.alloc((void**)&doff, sizeof(long long) * off.size()), "instance table");
+            VLS_HIP(hipMemcpyAsync(daff, aff.data(), sizeof(double) * aff.size(), hipMemcpyHostToDevice, s),
+                    "instance table");
+            VLS_HIP(hipMemcpyAsync(doff, off.data(), sizeof(long long) * off.size(), hipMemcpyHostToDevice, s),
+                    "instance table");
+            // the host tables must outlive the copies
+            VLS_HIP(hipStreamSynchronize(s), "instance table");
+            VLS_HIP(launch_instances(pv, pt, pr, m.n_vertices, m.n_triangles, daff, doff, doff + k, (long long)k, wv,
+                                     wt, wr, bad, s),
+                    "instance expansion");
+        }
+        unsigned hbad = 0;
+        VLS_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s), "instance check");
+        VLS_HIP(hipStreamSynchronize(s), "instance expansion");
+        if (hbad) return fail(VLS_ERR_INVALID_ARG, "triangle vertex index out of range in a part");
+        vls_mesh_desc world{};
+        world.vertices = wv;
+        world.triangles = wt;
+        world.reflectance = wr;
+        world.n_vertices = V;
+        world.n_triangles = T;
+        world.memory = VLS_MEM_DEVICE;
+        return vls_scene_create(ctx, &world, stream, out);
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
 vls_status vls_scene_update_vertices(vls_scene scene, const float* vertices_dev, void* stream)
 {
     if (!scene || (!vertices_dev && scene->b.n_vert > 0)) return fail(VLS_ERR_INVALID_ARG, "NULL argument");

@@ -218,6 +218,12 @@ hipError_t launch_echo_width(const ScannerDev& sc, const float* wf, const int32_
 // Pulses [first, first + count) of a survey; tab: per-waypoint table (see survey.hip).
 hipError_t launch_generate(const SurveyDev& sv, const double* tab, long long first, long long count,
                            double* origins, float* dirs, hipStream_t stream);
+// Scene parts (see instance.hip): the k instances of one part, aff [k][12] rows
+// (A_i0, A_i1, A_i2, t_i), voff / toff [k] each instance's first scene vertex and
+// triangle; *bad gets bit 0 for a part's vertex index out of range.
+hipError_t launch_instances(const float* v, const int32_t* t, const float* refl, long long nv, long long nt,
+                            const double* aff, const long long* voff, const long long* toff, long long k,
+                            float* out_v, int32_t* out_t, float* out_r, unsigned* bad, hipStream_t stream);
 // Candidate lists hold leaf indices; rewrite them as original triangle indices.
 hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_pulses, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);

@@ -52,6 +52,10 @@ class VoxelDesc(ctypes.Structure):
                 ("pad", P), ("lut", P), ("seed", ctypes.c_uint64)]
 
 
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [("part", i32), ("reserved", i32), ("affine", f64 * 12)]
+
+
 class ScannerDesc(ctypes.Structure):
     _fields_ = [("divergence_rad", f64), ("pattern_extent", f64), ("pulse_width_ns", f64), ("bin_ns", f64),
                 ("window_pre_ns", f64), ("peak_power_w", f64), ("receiver_diameter_m", f64),
@@ -107,6 +111,7 @@ _SIGS = {
     "vls_scene_update_vertices": ([P, P, P], i32),
     "vls_scene_update_reflectance": ([P, P, P], i32),
     "vls_scene_set_voxels": ([P, P, P], i32),
+    "vls_scene_create_instanced": ([P, P, i32, P, i32, P, P], i32),
     "vls_scene_stats_get": ([P, P], i32),
     "vls_scene_export": ([P, P, P, P, P], i32),
     "vls_scene_destroy": ([P], i32),
@@ -205,6 +210,39 @@ def n_subrays(sc):
 
 
 class Scene:
+    @classmethod
+    def instanced(cls, ctx, parts, instances, stream=None):
+        """A scene of parts placed by affine maps: parts = [(vertices, triangles, reflectance)]
+        (host numpy arrays or device tensors), instances = [(part, affine 3 x 4)]."""
+        descs = (MeshDesc * max(len(parts), 1))()
+        keep = []
+        for i, (v, t, r) in enumerate(parts):
+            if isinstance(v, np.ndarray):
+                v = np.ascontiguousarray(v, dtype=np.float32).reshape(-1, 3)
+                t = np.ascontiguousarray(t, dtype=np.int32).reshape(-1, 3)
+                r = np.ascontiguousarray(r, dtype=np.float32).reshape(-1)
+                descs[i] = MeshDesc(v.ctypes.data, t.ctypes.data, r.ctypes.data, v.shape[0], t.shape[0], MEM_HOST, 0)
+            else:
+                v = _dev(v, torch.float32, name="vertices")
+                t = _dev(t, torch.int32, name="triangles")
+                r = _dev(r, torch.float32, name="reflectance")
+                descs[i] = MeshDesc(v.data_ptr(), t.data_ptr(), r.data_ptr(), v.shape[0], t.shape[0], MEM_DEVICE, 0)
+            keep.append((v, t, r))
+        inst = (InstanceDesc * max(len(instances), 1))()
+        for j, (part, aff) in enumerate(instances):
+            a = np.ascontiguousarray(aff, dtype=np.float64).reshape(12)
+            inst[j] = InstanceDesc(int(part), 0, (f64 * 12)(*a.tolist()))
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self._h = P()
+        _check(lib().vls_scene_create_instanced(ctx._h, descs, len(parts), inst, len(instances), _stream(stream),
+                                                ctypes.byref(self._h)))
+        del keep
+        st = self.stats()
+        self.n_vertices = int(st["n_vertices"])
+        self.n_triangles = int(st["n_triangles"])
+        return self
+
     def __init__(self, ctx, vertices, triangles, reflectance, stream=None):
         self.ctx = ctx
         self._h = P()
@@ -313,6 +351,9 @@ class Context:
 
     def scene(self, vertices, triangles, reflectance, stream=None):
         return Scene(self, vertices, triangles, reflectance, stream)
+
+    def scene_instanced(self, parts, instances, stream=None):
+        return Scene.instanced(self, parts, instances, stream)
 
     def set_launch_config(self, block_waves=1, stack_lds=16, persistent_blocks=0, pack=0, cone=1):
         c = LaunchConfig(block_waves, stack_lds, persistent_blocks, pack, cone, 0)

@@ -1,4 +1,4 @@
-"""The six synthetic workloads, as (scene, pulses, scanner) recipes.
+"""The seven synthetic workloads, as (scene, pulses, scanner) recipes.
 
   small_tls      64x64 value-noise DTM at 1 m (7,938 triangles); terrestrial
                  scanner, 100x100 az/el grid; 19 subrays; 256 x 1 ns bins.
@@ -11,6 +11,8 @@
                  triangles (5,952,000), crowns as 0.5 m transmissive voxels of
                  plant area density 0.2-1.6 m^2/m^3 per crown (summed where
                  crowns overlap); Table 2's printed rows.
+  uls_instanced  the uls_trees terrain and flight; its 2,000 trees are instances
+                 of 8 procedural tree models (turned, scaled 0.8-1.2, moved).
   batched_tls    the als_buildings scene; 256 terrestrial positions with
                  log-uniform pulse counts in [1k, 200k]; three scanner types.
   diff_als       the small_tls noise field on 256x256 vertices (130,050
@@ -143,6 +145,45 @@ def uls_voxels(seed=ULS_SEED, strips=4, n_lines=500, per_line=1000, voxel_size=0
     voxels = dict(origin=list(origin), size=float(voxel_size), pad=pad, lut=TABLE2_ROWS, seed=seed)
     _, pulses, sc = uls_trees(seed, strips, n_lines, per_line, mesh=mesh)
     return mesh, voxels, pulses, sc
+
+
+# ---------------------------------------------------------------- uls_instanced
+def tree_models(seed=ULS_SEED, n_models=8, leaves=2000):
+    """Procedural tree models standing at the origin on flat ground."""
+    models = []
+    for m in range(n_models):
+        t = procedural_trees(np.zeros((3, 3)), 10.0, 1, seed=seed + 101 * (m + 1), extent=20.0, leaves=leaves)
+        p = t.info["positions"][0]
+        t.vertices = (t.vertices - np.array([p[0], p[1], 0.0], np.float32)).astype(np.float32)
+        models.append(t)
+    return models
+
+
+def uls_instanced(seed=ULS_SEED, n_models=8, n_trees=2000, strips=4, n_lines=500, per_line=1000, leaves=2000):
+    """The uls_trees terrain and flight with its forest as instances of a few tree
+    models: part 0 is the terrain (placed once, unmoved), parts 1..n_models the
+    models, each tree a model turned about z by a uniform angle, scaled by
+    U(0.8, 1.2) and moved to its position on the ground."""
+    x = np.arange(401, dtype=np.float64) * 0.5
+    X, Y = np.meshgrid(x, x)
+    h = value_noise_field(X, Y, seed=seed, octaves=5, base_wavelength=64.0, amplitude=5.0)
+    parts = [dtm_mesh(h, 0.5, refl_seed=seed)] + tree_models(seed, n_models, leaves)
+    lay = tree_layout(h, 0.5, n_trees, seed=seed, extent=200.0)
+    tid = np.arange(n_trees)
+    model = 1 + np.minimum((uniform01(seed, 60, tid) * n_models).astype(np.int64), n_models - 1)
+    th = 2.0 * np.pi * uniform01(seed, 61, tid)
+    sc_ = 0.8 + 0.4 * uniform01(seed, 62, tid)
+    instances = [(0, np.hstack([np.eye(3), np.zeros((3, 1))]))]
+    for i in range(n_trees):
+        c, s_ = np.cos(th[i]) * sc_[i], np.sin(th[i]) * sc_[i]
+        A = np.array([[c, -s_, 0.0], [s_, c, 0.0], [0.0, 0.0, sc_[i]]])
+        t = np.array([lay["pos"][i, 0], lay["pos"][i, 1], lay["gz"][i]])
+        instances.append((int(model[i]), np.hstack([A, t[:, None]])))
+    info = dict(kind="uls_instanced", heights_mean=float(h.mean()), extent=200.0)
+    mesh_for_pulses = parts[0]
+    mesh_for_pulses.info.update(info)
+    _, pulses, sc = uls_trees(seed, strips, n_lines, per_line, mesh=mesh_for_pulses)
+    return parts, instances, pulses, sc
 
 
 # ---------------------------------------------------------------- batched_tls
