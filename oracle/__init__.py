@@ -106,8 +106,10 @@ def lib():
         L.orc_attribute.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_double]
         L.orc_simulate.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, i64, P] + [P] * 6 + [P] * 7 + [ctypes.c_int]
         L.orc_gradient.argtypes = [P, i64, P, P, i64, P, P, P, i64, P, P, P, P, ctypes.c_int]
-        L.orc_simulate_vox.argtypes = L.orc_simulate.argtypes + [P]
-        L.orc_gradient_vox.argtypes = L.orc_gradient.argtypes + [P]
+        L.orc_simulate_ext.argtypes = L.orc_simulate.argtypes + [P, P, P]
+        L.orc_gradient_ext.argtypes = L.orc_gradient.argtypes + [P, P, P]
+        L.orc_surface_response.argtypes = [ctypes.c_double] * 3
+        L.orc_surface_response.restype = ctypes.c_double
         L.orc_lut_g.argtypes = [P, ctypes.c_double]
         L.orc_lut_g.restype = ctypes.c_double
         L.orc_voxel_hit.argtypes = [P, P, P, ctypes.c_double, ctypes.c_uint64, P, P]
@@ -283,9 +285,22 @@ class OracleResult:
     S: int
 
 
-def simulate(mesh, pulses, sc, select=None, t0=None, threads=0, waveform=True, voxels=None):
+def _specular(specular):
+    if specular is None:
+        return None, None
+    ks, n = specular
+    return np.ascontiguousarray(ks, dtype=np.float32), np.ascontiguousarray(n, dtype=np.float32)
+
+
+def surface_response(ct, ks, n):
+    """(1 - ks) cos + ks max(cos 2 theta, 0)^n of a triangle seen at incidence cos ct."""
+    return lib().orc_surface_response(float(ct), float(ks), float(n))
+
+
+def simulate(mesh, pulses, sc, select=None, t0=None, threads=0, waveform=True, voxels=None, specular=None):
     """Forward over all pulses, or over the pulse indices in ``select``; ``voxels``: an
-    optional transmissive voxel grid (see voxel_struct)."""
+    optional transmissive voxel grid (see voxel_struct); ``specular``: optional per-triangle
+    (specularity, Phong exponent)."""
     mesh.checked()
     st = scanner_struct(sc)
     S = pattern_size(st.n_subrays, st.beam_quality)
@@ -302,14 +317,15 @@ def simulate(mesh, pulses, sc, select=None, t0=None, threads=0, waveform=True, v
     o = np.ascontiguousarray(pulses.origins, dtype=np.float64)
     d = np.ascontiguousarray(pulses.directions, dtype=np.float32)
     vst, keep = voxel_struct(voxels) if voxels is not None else (None, None)
-    got = lib().orc_simulate_vox(_ptr(mesh.vertices), mesh.n_vertices, _ptr(mesh.triangles), _ptr(mesh.reflectance),
+    sk, sn = _specular(specular)
+    got = lib().orc_simulate_ext(_ptr(mesh.vertices), mesh.n_vertices, _ptr(mesh.triangles), _ptr(mesh.reflectance),
                                  mesh.n_triangles, ctypes.byref(st), _ptr(o), _ptr(d), pulses.n,
                                  _ptr(sel), n, _ptr(t0a),
                                  _ptr(r.sub_tri), _ptr(r.sub_range), _ptr(r.sub_cos), _ptr(r.sub_power),
                                  _ptr(r.sub_u), _ptr(r.sub_v),
                                  _ptr(r.waveform), _ptr(r.t0), _ptr(r.n_returns), _ptr(r.ret_range), _ptr(r.ret_amp),
                                  _ptr(r.ret_tri), _ptr(r.ret_bin), int(threads),
-                                 ctypes.byref(vst) if vst is not None else None)
+                                 ctypes.byref(vst) if vst is not None else None, _ptr(sk), _ptr(sn))
     del keep
     if got != S:
         raise RuntimeError("oracle simulate failed")
@@ -336,21 +352,23 @@ def voxel_hit(voxels, O, d, t_limit, pulse, subray):
     return int(vi), t.value, sg.value
 
 
-def gradient(mesh, pulses, sc, t0, grad_wf, threads=0, voxels=None):
+def gradient(mesh, pulses, sc, t0, grad_wf, threads=0, voxels=None, specular=None):
     """(grad_reflectance [T], grad_z [V]) of L with dL/dwf = grad_wf at fixed t0; ``voxels``: an
-    optional transmissive voxel grid (its echoes are constants)."""
+    optional transmissive voxel grid (its echoes are constants); ``specular``: optional
+    per-triangle (specularity, Phong exponent)."""
     st = scanner_struct(sc)
     vst, keep = voxel_struct(voxels) if voxels is not None else (None, None)
+    sk, sn = _specular(specular)
     gr = np.zeros(mesh.n_triangles)
     gz = np.zeros(mesh.n_vertices)
     o = np.ascontiguousarray(pulses.origins, dtype=np.float64)
     d = np.ascontiguousarray(pulses.directions, dtype=np.float32)
     t0 = np.ascontiguousarray(t0, dtype=np.float64)
     G = np.ascontiguousarray(grad_wf, dtype=np.float64)
-    got = lib().orc_gradient_vox(_ptr(mesh.vertices), mesh.n_vertices, _ptr(mesh.triangles),
+    got = lib().orc_gradient_ext(_ptr(mesh.vertices), mesh.n_vertices, _ptr(mesh.triangles),
                                  _ptr(mesh.reflectance), mesh.n_triangles, ctypes.byref(st), _ptr(o), _ptr(d),
                                  pulses.n, _ptr(t0), _ptr(G), _ptr(gr), _ptr(gz), int(threads),
-                                 ctypes.byref(vst) if vst is not None else None)
+                                 ctypes.byref(vst) if vst is not None else None, _ptr(sk), _ptr(sn))
     del keep
     if got < 0:
         raise RuntimeError("oracle gradient failed")

@@ -35,7 +35,9 @@
  *      a voxel of plant area density PAD stops in it at a random depth drawn
  *      from the extinction coefficient (Eq. 5 through a leaf-angle table, Eq. 6),
  *      with the echo power of Eq. 8;
- *  10. scene parts placed by affine maps (Sec. 3.5: a part loaded several
+ *  10. optionally, a Phong-type specular part of each triangle's response
+ *      (Sec. 5.1: materials carry reflectance and specularity);
+ *  11. scene parts placed by affine maps (Sec. 3.5: a part loaded several
  *      times and moved by transforms; Sec. 5.1: primitives rotate, scale and
  *      translate): each instance's vertices mapped to the scene's frame.
  * Everything is FP64 with no truncation of the pulse support.
@@ -373,7 +375,28 @@ typedef struct {
     const float* verts; const int32_t* tris; const float* refl; int64_t n_tri;
     const orc_scanner* sc; int S; const double* alpha; const double* phi; const double* w;
     const orc_voxels* vox;   /* NULL: no voxels */
+    const float* spec_k;     /* per-triangle specularity, or NULL */
+    const float* spec_n;     /* per-triangle Phong exponent */
 } orc_ctx;
+
+/* Surface response of a triangle seen at incidence cos ct (Sec. 5.1: materials
+ * carry reflectance and specularity; the paper gives no formula).  A
+ * Phong-type reading for a scanner whose receiver sits at the emitter: the
+ * mirror direction of the beam makes the angle 2 theta with the way back, so
+ *   f = (1 - ks) cos theta + ks max(cos 2 theta, 0)^n,  cos 2 theta = 2 ct^2 - 1,
+ * which is the Lambertian cos theta for ks = 0 and 1 at normal incidence. */
+double orc_surface_response(double ct, double ks, double n)
+{
+    double c2 = 2.0 * ct * ct - 1.0;
+    return (1.0 - ks) * ct + ks * (c2 > 0.0 ? pow(c2, n) : 0.0);
+}
+
+/* d f / d cos theta */
+double orc_surface_response_dcos(double ct, double ks, double n)
+{
+    double c2 = 2.0 * ct * ct - 1.0;
+    return (1.0 - ks) + (c2 > 0.0 && n != 0.0 ? ks * n * pow(c2, n - 1.0) * 4.0 * ct : 0.0);
+}
 
 uint64_t orc_splitmix64(uint64_t seed, uint64_t c);
 
@@ -505,7 +528,8 @@ static void trace_pulse(const orc_ctx* c, int64_t pulse, const double O[3], cons
         double ct = fabs(dot3(dk, n)) / sqrt(dot3(n, n));
         R[k] = t; cosang[k] = ct; U[k] = u; V[k] = v;
         /* Eq. 7 with a Lambertian extended-target cross-section */
-        P[k] = C * c->w[k] * (double)c->refl[h] * ct / (t * t);
+        double f = c->spec_k ? orc_surface_response(ct, c->spec_k[h], c->spec_n[h]) : ct;
+        P[k] = C * c->w[k] * (double)c->refl[h] * f / (t * t);
     }
 }
 
@@ -552,6 +576,8 @@ static int make_ctx(orc_ctx* c, const float* verts, const int32_t* tris, const f
     c->verts = verts; c->tris = tris; c->refl = refl; c->n_tri = n_tri; c->sc = sc;
     c->alpha = alpha; c->phi = phi; c->w = w;
     c->vox = NULL;
+    c->spec_k = NULL;
+    c->spec_n = NULL;
     c->S = orc_pattern(sc, alpha, phi, w, 4096);
     if (c->S <= 0 || sc->n_bins < 3 || sc->max_returns < 1 || sc->max_returns > 64 || !(sc->bin_ns > 0.0)) return -1;
     return 0;
@@ -561,20 +587,24 @@ static int make_ctx(orc_ctx* c, const float* verts, const int32_t* tris, const f
  * to pulse sel[q].  Per-subray arrays are [n_sel][S]; waveform [n_sel][n_bins];
  * returns [n_sel][K].  t0_in (indexed by pulse, may be NULL) fixes the window
  * origins.  Any per-subray output may be NULL.  Returns S, or -1. */
-/* The same with transmissive voxels (vox may be NULL). */
-int orc_simulate_vox(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
+/* The same with transmissive voxels and specular materials (vox, spec_k and
+ * spec_n may be NULL). */
+int orc_simulate_ext(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
                      const orc_scanner* sc, const double* origins, const float* dirs, int64_t n_pulses,
                      const int64_t* sel, int64_t n_sel, const double* t0_in,
                      int32_t* sub_tri, double* sub_range, double* sub_cos, double* sub_power,
                      double* sub_u, double* sub_v,
                      double* wf, double* t0_out, int32_t* n_ret, double* ret_range, double* ret_amp,
-                     int32_t* ret_tri, int32_t* ret_bin, int n_threads, const orc_voxels* vox)
+                     int32_t* ret_tri, int32_t* ret_bin, int n_threads, const orc_voxels* vox,
+                     const float* spec_k, const float* spec_n)
 {
     (void)n_vert;
     double alpha[4096], phi[4096], w[4096];
     orc_ctx c;
     if (make_ctx(&c, verts, tris, refl, n_tri, sc, alpha, phi, w) < 0) return -1;
     c.vox = vox;
+    c.spec_k = spec_k;
+    c.spec_n = spec_n;
     int S = c.S, nb = sc->n_bins, K = sc->max_returns;
     int64_t n = sel ? n_sel : n_pulses;
 #ifdef _OPENMP
@@ -618,9 +648,9 @@ int orc_simulate(const float* verts, int64_t n_vert, const int32_t* tris, const 
                  double* wf, double* t0_out, int32_t* n_ret, double* ret_range, double* ret_amp,
                  int32_t* ret_tri, int32_t* ret_bin, int n_threads)
 {
-    return orc_simulate_vox(verts, n_vert, tris, refl, n_tri, sc, origins, dirs, n_pulses, sel, n_sel, t0_in, sub_tri,
+    return orc_simulate_ext(verts, n_vert, tris, refl, n_tri, sc, origins, dirs, n_pulses, sel, n_sel, t0_in, sub_tri,
                             sub_range, sub_cos, sub_power, sub_u, sub_v, wf, t0_out, n_ret, ret_range, ret_amp,
-                            ret_tri, ret_bin, n_threads, NULL);
+                            ret_tri, ret_bin, n_threads, NULL, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------ gradient */
@@ -632,17 +662,21 @@ int orc_simulate(const float* verts, int64_t n_vert, const int32_t* tris, const 
  * tau = 2R/c, R = n.(a-O)/(n.d) so dR/dv_i = b_i n/(n.d) (b_i = barycentric
  * weight of vertex i at the hit), cos = |n.d|/|n|.  Accumulated per thread in
  * thread order (deterministic for a fixed thread count). */
-/* The same with transmissive voxels (vox may be NULL): a subray that a voxel
- * stops carries no triangle and so adds nothing to either gradient. */
-int orc_gradient_vox(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
+/* The same with transmissive voxels and specular materials (vox, spec_k and
+ * spec_n may be NULL): a subray that a voxel stops carries no triangle and so
+ * adds nothing to either gradient; the surface response f replaces cos theta
+ * in P and df/dcos carries the incidence derivative. */
+int orc_gradient_ext(const float* verts, int64_t n_vert, const int32_t* tris, const float* refl, int64_t n_tri,
                      const orc_scanner* sc, const double* origins, const float* dirs, int64_t n_pulses,
                      const double* t0, const double* grad_wf, double* grad_refl, double* grad_z, int n_threads,
-                     const orc_voxels* vox)
+                     const orc_voxels* vox, const float* spec_k, const float* spec_n)
 {
     double alpha[4096], phi[4096], w[4096];
     orc_ctx c;
     if (make_ctx(&c, verts, tris, refl, n_tri, sc, alpha, phi, w) < 0) return -1;
     c.vox = vox;
+    c.spec_k = spec_k;
+    c.spec_n = spec_n;
     int S = c.S, nb = sc->n_bins;
     double C = power_const(sc);
 #ifdef _OPENMP
@@ -684,8 +718,10 @@ int orc_gradient_vox(const float* verts, int64_t n_vert, const int32_t* tris, co
                 double gtau = -P[k] * gD;                   /* d wf_j / d tau = -P p'(s) */
                 double gR = gtau * 2.0 / ORC_C_M_PER_NS - gP * 2.0 * P[k] / R[k];
                 double base = C * w[k] / (R[k] * R[k]);
-                double gcos = gP * base * (double)refl[h];
-                gr[h] += gP * base * cs[k];
+                double f = spec_k ? orc_surface_response(cs[k], spec_k[h], spec_n[h]) : cs[k];
+                double df = spec_k ? orc_surface_response_dcos(cs[k], spec_k[h], spec_n[h]) : 1.0;
+                double gcos = gP * base * (double)refl[h] * df;
+                gr[h] += gP * base * f;
                 double dk[3], a[3], b[3], cc[3], e1[3], e2[3], n[3];
                 orc_subray_direction(dp, alpha[k], phi[k], dk);
                 vload(verts, tris[3 * h + 0], a);
@@ -726,8 +762,8 @@ int orc_gradient(const float* verts, int64_t n_vert, const int32_t* tris, const 
                  const orc_scanner* sc, const double* origins, const float* dirs, int64_t n_pulses,
                  const double* t0, const double* grad_wf, double* grad_refl, double* grad_z, int n_threads)
 {
-    return orc_gradient_vox(verts, n_vert, tris, refl, n_tri, sc, origins, dirs, n_pulses, t0, grad_wf, grad_refl,
-                            grad_z, n_threads, NULL);
+    return orc_gradient_ext(verts, n_vert, tris, refl, n_tri, sc, origins, dirs, n_pulses, t0, grad_wf, grad_refl,
+                            grad_z, n_threads, NULL, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------ echo width (Sec. 3.4, optional) */

@@ -23,20 +23,27 @@ def _case(n=12, spacing=1.0, lines=6, per_line=7, S=7, shape="gaussian"):
     return mesh, target, pulses, sc
 
 
-def _loss(orc, mesh, pulses, sc, t0, tgt):
-    r = orc.simulate(mesh, pulses, sc, t0=t0)
+def _loss(orc, mesh, pulses, sc, t0, tgt, spec=None):
+    r = orc.simulate(mesh, pulses, sc, t0=t0, specular=spec)
     return float(np.sum((r.waveform - tgt) ** 2)), r.sub_tri
 
 
-@pytest.mark.parametrize("shape", ["gaussian", "eq3"])
-def test_gradient_matches_finite_differences(orc, shape):
+@pytest.mark.parametrize("shape,specular", [("gaussian", False), ("eq3", False), ("gaussian", True)])
+def test_gradient_matches_finite_differences(orc, shape, specular):
     mesh, target, pulses, sc = _case(shape=shape)
-    base = orc.simulate(mesh, pulses, sc)
+    spec = None
+    if specular:
+        # a Phong-type part on every triangle: specularity 0.2-0.8, exponents 1-8
+        rng = np.random.default_rng(17)
+        spec = (rng.uniform(0.2, 0.8, mesh.n_triangles), rng.uniform(1.0, 8.0, mesh.n_triangles))
+    base = orc.simulate(mesh, pulses, sc, specular=spec)
     t0 = base.t0
     tgt = orc.simulate(target, pulses, sc, t0=t0).waveform
     G = 2.0 * (base.waveform - tgt)
-    gr, gz = orc.gradient(mesh, pulses, sc, t0, G)
-    h = 1e-3
+    gr, gz = orc.gradient(mesh, pulses, sc, t0, G, specular=spec)
+    # the mirror lobe's higher derivatives are larger: a smaller step keeps the
+    # central difference's O(h^2) error under the tolerance
+    h = 2.5e-4 if specular else 1e-3
     scale = max(np.abs(gr).max(), np.abs(gz).max())
     excluded = 0
     compared = 0
@@ -46,8 +53,8 @@ def test_gradient_matches_finite_differences(orc, shape):
         mp.vertices[v, 2] += np.float32(h)
         mm.vertices[v, 2] -= np.float32(h)
         hh = (float(mp.vertices[v, 2]) - float(mm.vertices[v, 2])) / 2
-        lp, tp = _loss(orc, mp, pulses, sc, t0, tgt)
-        lm, tm = _loss(orc, mm, pulses, sc, t0, tgt)
+        lp, tp = _loss(orc, mp, pulses, sc, t0, tgt, spec)
+        lm, tm = _loss(orc, mm, pulses, sc, t0, tgt, spec)
         if not (np.array_equal(tp, base.sub_tri) and np.array_equal(tm, base.sub_tri)):
             excluded += 1
             continue
@@ -59,8 +66,10 @@ def test_gradient_matches_finite_differences(orc, shape):
         rm = rp.copy()
         rp[t] += h
         rm[t] -= h
-        lp, _ = _loss(orc, synth.Mesh(mesh.vertices, mesh.triangles, rp.astype(np.float32)), pulses, sc, t0, tgt)
-        lm, _ = _loss(orc, synth.Mesh(mesh.vertices, mesh.triangles, rm.astype(np.float32)), pulses, sc, t0, tgt)
+        lp, _ = _loss(orc, synth.Mesh(mesh.vertices, mesh.triangles, rp.astype(np.float32)), pulses, sc, t0, tgt,
+                      spec)
+        lm, _ = _loss(orc, synth.Mesh(mesh.vertices, mesh.triangles, rm.astype(np.float32)), pulses, sc, t0, tgt,
+                      spec)
         hh = (float(np.float32(rp[t])) - float(np.float32(rm[t]))) / 2
         fd = (lp - lm) / (2 * hh)
         # L is quadratic in each reflectance: the central difference is exact up to rounding
