@@ -200,6 +200,22 @@ typedef struct {
 
 vls_status vls_scene_set_voxels(vls_scene scene, const vls_voxel_desc* voxels, void* stream);
 
+/* Specular materials (Sec. 5.1: primitives carry reflectance and specularity;
+ * the paper gives no formula).  With them a triangle's surface response,
+ * which takes the place of |cos theta| in the power of Eq. 7, is
+ *   f = (1 - ks) |cos theta| + ks max(cos 2 theta, 0)^n,  cos 2 theta = 2 cos^2 theta - 1:
+ * a Phong-type lobe for a receiver at the emitter, where the beam's mirror
+ * direction makes the angle 2 theta with the way back; ks = 0 is Lambertian and
+ * every ks returns f = 1 at normal incidence.  specularity_dev (ks, in [0, 1])
+ * and exponent_dev (n >= 0) are device arrays [n_triangles] float32 by original
+ * triangle index, copied asynchronously on `stream` into the scene (later calls
+ * overwrite them in place, so graphs captured after the first call see new
+ * values); both NULL turns the term off for later calls and captures.  The
+ * library shades in FP32: the lobe multiplies the FP32 error of cos theta (a
+ * few 2^-24) by about 4n + 3.  vls_waveform_backward differentiates f. */
+vls_status vls_scene_set_specular(vls_scene scene, const float* specularity_dev, const float* exponent_dev,
+                                  void* stream);
+
 /* Synchronous: statistics of the built scene. */
 vls_status vls_scene_stats_get(vls_scene scene, vls_scene_stats* out);
 

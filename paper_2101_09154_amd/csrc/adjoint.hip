@@ -67,7 +67,15 @@ __device__ __forceinline__ bool subray_grads(const SceneDev& scene, const Scanne
     double cosv = fabs(nd) / len;
     double rho = scene.refl[tri];
     double base = sc.power_c * w / (R * R);
-    double P = base * rho * cosv;
+    // surface response f and df/dcos: cos, or the Phong-type specular response
+    double f = cosv, df = 1.0;
+    if (scene.spec_k) {
+        const double ks = scene.spec_k[tri], ns = scene.spec_n[tri];
+        const double c2 = 2.0 * cosv * cosv - 1.0;
+        f = (1.0 - ks) * cosv + ks * (c2 > 0.0 ? pow(c2, ns) : 0.0);
+        df = (1.0 - ks) + (c2 > 0.0 && ns != 0.0 ? ks * ns * pow(c2, ns - 1.0) * 4.0 * cosv : 0.0);
+    }
+    double P = base * rho * f;
     double tau = 2.0 * R / kCmPerNs;
     double rel = tau - t0;
     // bins inside the pulse support around this echo
@@ -96,8 +104,8 @@ __device__ __forceinline__ bool subray_grads(const SceneDev& scene, const Scanne
     }
     double gtau = -P * (double)gD;
     double gR = gtau * 2.0 / kCmPerNs - (double)gP * 2.0 * P / R;
-    double gcos = (double)gP * base * rho;
-    out.grho = (double)gP * base * cosv;
+    double gcos = (double)gP * base * rho * df;
+    out.grho = (double)gP * base * f;
     // through R: dR/dv_i = b_i n / n.d (z component)
     for (int i = 0; i < 3; ++i) out.gz[i] = gR * bw[i] * n[2] / nd;
     // through cos: gradient with respect to n, then to the vertices

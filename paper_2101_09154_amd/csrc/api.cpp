@@ -186,8 +186,11 @@ struct vls_scene_s {
     vls_scene_stats stats{};
     int root = -1;
     VoxDev vox{};              // transmissive voxel grid (n_vox == 0: none); arrays owned here
+    float* spec = nullptr;     // [2][n_tri]: specularity, then Phong exponent (allocated on first use)
+    bool spec_on = false;
     ~vls_scene_s()
     {
+        (void)hipFree(spec);
         (void)hipFree(const_cast<float*>(vox.pad));
         (void)hipFree(const_cast<double*>(vox.lut));
         (void)hipFree(b.nodes);
@@ -294,6 +297,8 @@ SceneDev scene_dev(vls_scene sc)
     s.root = sc->root;
     s.n_tri = (int)sc->b.n_tri;
     s.vox = sc->vox;
+    s.spec_k = sc->spec_on ? sc->spec : nullptr;
+    s.spec_n = sc->spec_on ? sc->spec + sc->b.n_tri : nullptr;
     return s;
 }
 
@@ -875,6 +880,32 @@ vls_status vls_scene_set_voxels(vls_scene scene, const vls_voxel_desc* v, void* 
     } catch (const std::exception& e) {
         return fail(VLS_ERR_INTERNAL, e.what());
     }
+}
+
+vls_status vls_scene_set_specular(vls_scene scene, const float* specularity_dev, const float* exponent_dev,
+                                  void* stream)
+{
+    if (!scene) return fail(VLS_ERR_INVALID_ARG, "scene is NULL");
+    if (!specularity_dev && !exponent_dev) {
+        scene->spec_on = false;
+        return VLS_OK;
+    }
+    if (!specularity_dev || !exponent_dev) return fail(VLS_ERR_INVALID_ARG, "specularity and exponent go together");
+    if (!aligned(specularity_dev, 4) || !aligned(exponent_dev, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned arrays");
+    const int64_t nt = scene->b.n_tri;
+    hipStream_t s = (hipStream_t)stream;
+    if (!scene->spec) {
+        VLS_HIP(hipSetDevice(scene->ctx->device), "hipSetDevice");
+        VLS_HIP(hipMalloc(&scene->spec, sizeof(float) * 2 * (size_t)std::max<int64_t>(nt, 1)), "specular alloc");
+        scene->stats.device_bytes += (int64_t)(sizeof(float) * 2 * nt);
+    }
+    if (nt > 0) {
+        VLS_HIP(hipMemcpyAsync(scene->spec, specularity_dev, 4 * (size_t)nt, hipMemcpyDeviceToDevice, s), "specular copy");
+        VLS_HIP(hipMemcpyAsync(scene->spec + nt, exponent_dev, 4 * (size_t)nt, hipMemcpyDeviceToDevice, s),
+                "specular copy");
+    }
+    scene->spec_on = true;
+    return VLS_OK;
 }
 
 vls_status vls_scene_stats_get(vls_scene scene, vls_scene_stats* out)

@@ -310,9 +310,12 @@ __device__ __forceinline__ void packet_walk(const SceneDev& scene, const Ray& r,
 }
 
 // Incidence and power of the chosen triangle (Sec. 5.2, Eq. 7) in FP32, from
-// its translated FP64 vertices: cos = |d . n| / |n|, P = C w rho cos / R^2.
+// its translated FP64 vertices: cos = |d . n| / |n|, P = C w rho f / R^2 with
+// the surface response f = cos, or, for a scene with specular materials (Sec.
+// 5.1), f = (1 - ks) cos + ks max(cos 2 theta, 0)^n: the mirror direction of a
+// beam whose receiver sits at the emitter makes 2 theta with the way back.
 __device__ __forceinline__ void shade(const Ray& r, const double* a, const double* b, const double* c, double t,
-                                      float cw, float rho, float& cosang, float& P)
+                                      float cw, float rho, const SceneDev& scene, int orig, float& cosang, float& P)
 {
     const float e1x = (float)(b[0] - a[0]), e1y = (float)(b[1] - a[1]), e1z = (float)(b[2] - a[2]);
     const float e2x = (float)(c[0] - a[0]), e2y = (float)(c[1] - a[1]), e2z = (float)(c[2] - a[2]);
@@ -321,7 +324,13 @@ __device__ __forceinline__ void shade(const Ray& r, const double* a, const doubl
     const float cs = nn > 0.0f ? fabsf(r.d32[0] * nx + r.d32[1] * ny + r.d32[2] * nz) / sqrtf(nn) : 0.0f;
     const float R = (float)t;
     cosang = cs;
-    P = cw * rho * cs / (R * R);
+    float f = cs;
+    if (scene.spec_k) {
+        const float ks = scene.spec_k[orig], n = scene.spec_n[orig];
+        const float c2 = 2.0f * cs * cs - 1.0f;
+        f = (1.0f - ks) * cs + ks * (c2 > 0.0f ? powf(c2, n) : 0.0f);
+    }
+    P = cw * rho * f / (R * R);
 }
 
 // Trace one lane's subray: fills tri (original index or -1), R, cos, P.
@@ -441,7 +450,7 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
         translate(r, scene.tris[3 * h.leaf + 1], b);
         translate(r, scene.tris[3 * h.leaf + 2], c);
     }
-    shade(r, a, b, c, h.t, (float)(sc.power_c * pat[4]), scene.refl[h.orig], cosang, P);
+    shade(r, a, b, c, h.t, (float)(sc.power_c * pat[4]), scene.refl[h.orig], scene, h.orig, cosang, P);
     tri = h.orig;
     R = h.t;
 }

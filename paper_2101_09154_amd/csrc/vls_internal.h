@@ -93,6 +93,8 @@ struct SceneDev {
     int root;
     int n_tri;
     VoxDev vox;
+    const float* spec_k;    // per-triangle specularity, or null (Lambertian)
+    const float* spec_n;    // per-triangle Phong exponent
 };
 
 struct PulsesDev {

@@ -111,6 +111,7 @@ _SIGS = {
     "vls_scene_update_vertices": ([P, P, P], i32),
     "vls_scene_update_reflectance": ([P, P, P], i32),
     "vls_scene_set_voxels": ([P, P, P], i32),
+    "vls_scene_set_specular": ([P, P, P, P], i32),
     "vls_scene_create_instanced": ([P, P, i32, P, i32, P, P], i32),
     "vls_scene_stats_get": ([P, P], i32),
     "vls_scene_export": ([P, P, P, P, P], i32),
@@ -275,6 +276,17 @@ class Scene:
     def update_reflectance(self, reflectance, stream=None):
         r = _dev(reflectance, torch.float32, (self.n_triangles,), "reflectance")
         _check(lib().vls_scene_update_reflectance(self._h, _ptr(r), _stream(stream)))
+
+    def set_specular(self, specularity=None, exponent=None, stream=None):
+        """Per-triangle specularity ks and Phong exponent n (device tensors [n_triangles] float32);
+        both None turns the specular term off."""
+        if specularity is None and exponent is None:
+            _check(lib().vls_scene_set_specular(self._h, None, None, _stream(stream)))
+            return
+        k = _dev(specularity, torch.float32, (self.n_triangles,), "specularity")
+        n = _dev(exponent, torch.float32, (self.n_triangles,), "exponent")
+        _check(lib().vls_scene_set_specular(self._h, _ptr(k), _ptr(n), _stream(stream)))
+        self._spec_keep = (k, n)
 
     def set_voxels(self, origin, voxel_size_m, pad, lut, seed=0, stream=None):
         """A transmissive voxel grid: pad [nz, ny, nx] plant area density, lut [n, 2] rows of the
