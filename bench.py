@@ -228,6 +228,36 @@ def bench_voxels(ctx, steps):
     return res
 
 
+def bench_instanced(ctx, steps):
+    """Scene parts placed by affine maps (Sec. 3.5, Sec. 5.1): the uls_instanced
+    forest, 2,000 trees as instances of 8 models, built from the parts on the
+    device, then one step per timed iteration."""
+    import torch
+    from synth import configs
+    import paper_2101_09154_amd as vp
+    parts, inst, pulses, sc = configs.uls_instanced()
+    ps = [(m.vertices, m.triangles, m.reflectance) for m in parts]
+    ctx.scene_instanced(ps, inst).close()       # code objects and first allocations
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    scene = ctx.scene_instanced(ps, inst)
+    build_ms = (time.perf_counter() - t) * 1e3
+    dev = torch.device("cuda", 0)
+    o = torch.from_numpy(pulses.origins).to(dev)
+    d = torch.from_numpy(pulses.directions).to(dev)
+    n = pulses.n
+    S = vp.n_subrays(sc)
+    out = ctx.alloc_outputs(n, S, sc["n_bins"], sc["max_returns"], dev, subrays=False)
+    ms = time_ms(lambda: ctx.simulate(scene, sc, o, d, out=out), steps, 1, torch.cuda.current_stream())
+    res = {"workload": "uls_instanced: uls_trees terrain and flight, 2,000 trees as instances of 8 procedural models "
+                       "(turned, scaled 0.8-1.2, moved); %d placed triangles" % scene.n_triangles,
+           "instances": len(inst), "placed_triangles": scene.n_triangles,
+           "part_triangles": int(sum(m.n_triangles for m in parts)),
+           "build_from_parts_ms": build_ms, "ms": ms, "subrays_per_s": n * S / (ms * 1e-3)}
+    scene.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -439,6 +469,16 @@ def main():
                                "achieved_GBps": 36.0 * n / (gen_ms * 1e-3) / 1e9,
                                "step_with_generation_ms": gstep_ms,
                                "subrays_per_s_with_generation": n * S / (gstep_ms * 1e-3) if gstep_ms else None}
+    # specular materials (Sec. 5.1): the same step with a Phong-type part on every triangle
+    log("specular materials")
+    g = torch.Generator(device="cpu").manual_seed(5)
+    ks = torch.rand(mesh.n_triangles, generator=g).mul_(0.9).to(dev)
+    ne = torch.rand(mesh.n_triangles, generator=g).mul_(7.0).add_(1.0).to(dev)
+    scene.set_specular(ks, ne)
+    spec_ms = time_ms(lambda: ctx.simulate(scene, sc, o, d, out=out), args.steps, 1, stream)
+    scene.set_specular()
+    res["specular"] = {"ms": spec_ms, "step_with_specular_over_step": spec_ms / ms,
+                       "materials": "specularity U(0, 0.9), exponent U(1, 8) per triangle"}
     res["autotune"] = tune
     if not args.only_plain:
         log("batched workload")
@@ -447,6 +487,8 @@ def main():
         res["gradient"] = bench_grad(ctx, max(args.steps // 2, 2))
         log("voxel workload")
         res["voxels"] = bench_voxels(ctx, max(args.steps // 2, 2))
+        log("instanced workload")
+        res["instanced"] = bench_instanced(ctx, max(args.steps // 2, 2))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(mesh, pulses, sc, args.cpu_seconds)
