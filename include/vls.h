@@ -146,6 +146,27 @@ vls_status vls_scene_create_instanced(vls_context ctx, const vls_mesh_desc* part
                                       const vls_instance_desc* instances, int32_t n_instances, void* stream,
                                       vls_scene* out);
 
+/* The same scene kept in two levels: each part built once into its own LBVH in
+ * its own frame, and a top-level LBVH over the instances' boxes in the scene's
+ * frame (the part's box corners mapped in FP64 and rounded outward).  A subray
+ * walks the top level, and in each instance it reaches walks the part's tree
+ * with the ray mapped into the part's frame (A^-1 (O - t), A^-1 D: the ray
+ * parameter stays the world distance), testing each leaf's triangle as placed
+ * (the vertices of vls_scene_create_instanced, then the same world-frame
+ * watertight test).  Hits, ids, distances, powers, waveforms and returns are
+ * therefore those of the expanded scene, bit for bit, while the device holds
+ * each part once.  Traced per subray (no cone pass): only vls_trace and
+ * vls_simulate take such a scene (segments allowed; not in graphs, the
+ * autotuner, the adjoint, vls_trace_counts, vls_cone_candidates or the scene
+ * updates, voxels, specular materials and export, which return
+ * VLS_ERR_UNSUPPORTED).  Maps must be invertible (VLS_ERR_UNSUPPORTED
+ * otherwise); top-level depth <= 47 and part depth <= 63.  vls_simulate keeps
+ * the subray arrays, waveform and window origins the caller leaves NULL in a
+ * context workspace.  Synchronises `stream`. */
+vls_status vls_scene_create_two_level(vls_context ctx, const vls_mesh_desc* parts, int32_t n_parts,
+                                      const vls_instance_desc* instances, int32_t n_instances, void* stream,
+                                      vls_scene* out);
+
 /* New vertex positions (same count and triangles): leaf records and node boxes
  * are refitted, the tree topology is kept.  `vertices_dev` is a device array
  * [n_vertices][3] float32.  Asynchronous on `stream`. */

@@ -155,6 +155,8 @@ struct vls_context_s {
     long long cand_pulses = 0;
     int* ew = nullptr;           // echo-width list of returns + counter, grown on demand
     long long ew_entries = 0;
+    unsigned char* tlw = nullptr;  // two-level simulate: subrays, waveform and t0 not asked for, grown on demand
+    size_t tlw_bytes = 0;
     struct SurveyTab {
         std::vector<double> key;   // the host table it was made from
         double* dev = nullptr;
@@ -174,13 +176,28 @@ struct vls_context_s {
             }
         (void)hipFree(cand);
         (void)hipFree(ew);
+        (void)hipFree(tlw);
         for (auto& t : surveys) (void)hipFree(t.dev);
         for (auto& kv : patterns) (void)hipFree(kv.second);
         for (auto& b : batches) (void)hipFree(b.dev);
     }
 };
 
+struct vls_scene_s;
+
+// A two-level scene: each part's own scene (its LBVH in its own frame), the
+// top-level scene over the instances' boxes, and the device tables.
+struct TwoLevelHost {
+    std::vector<vls_scene_s*> parts;   // by part index (null: unused or empty)
+    vls_scene_s* top = nullptr;
+    InstDev* inst = nullptr;           // [n_inst] in top-level leaf order
+    PartDev* parts_dev = nullptr;
+    TwoLevelDev dev{};
+    ~TwoLevelHost();
+};
+
 struct vls_scene_s {
+    std::unique_ptr<TwoLevelHost> tl;  // set for a two-level scene (b is then empty)
     vls_context ctx = nullptr;
     BvhBuffers b;
     vls_scene_stats stats{};
@@ -208,6 +225,14 @@ struct vls_scene_s {
         (void)hipFree(b.bounds);
     }
 };
+
+TwoLevelHost::~TwoLevelHost()
+{
+    for (vls_scene_s* p : parts) delete p;
+    delete top;
+    (void)hipFree(inst);
+    (void)hipFree(parts_dev);
+}
 
 struct vls_graph_s {
     vls_context ctx = nullptr;
@@ -368,10 +393,15 @@ vls_status prepare(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_
     return VLS_OK;
 }
 
-vls_status check_scene(vls_context ctx, vls_scene scene, const Prepared& pr)
+// allow_tl: the call has a two-level form (vls_trace, vls_simulate).
+vls_status check_scene(vls_context ctx, vls_scene scene, const Prepared& pr, bool allow_tl = false)
 {
     if (!scene) return fail(VLS_ERR_INVALID_ARG, "scene is NULL");
     if (scene->ctx != ctx) return fail(VLS_ERR_INVALID_ARG, "scene belongs to another context");
+    if (scene->tl) {
+        if (!allow_tl) return fail(VLS_ERR_UNSUPPORTED, "a two-level scene is traced by vls_trace and vls_simulate only");
+        return VLS_OK;
+    }
     if (scene->vox.n_vox > 0)
         for (const auto& s : pr.sc)
             if (!(s.vox_c < INFINITY))
@@ -676,6 +706,44 @@ vls_status vls_scene_create(vls_context ctx, const vls_mesh_desc* mesh, void* st
     }
 }
 
+// Checks scene parts and their instances (shared by the expanded and the
+// two-level forms): the placed totals, each instance's first placed vertex and
+// triangle (instance order), and the instances of each part.
+static vls_status check_placement(const vls_mesh_desc* parts, int32_t n_parts, const vls_instance_desc* instances,
+                                  int32_t n_instances, int64_t& V, int64_t& T, std::vector<long long>& voff,
+                                  std::vector<long long>& toff, std::vector<std::vector<int>>& of_part)
+{
+    if ((n_parts > 0 && !parts) || (n_instances > 0 && !instances)) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+    if (n_parts < 0 || n_instances < 0) return fail(VLS_ERR_INVALID_ARG, "negative counts");
+    for (int p = 0; p < n_parts; ++p) {
+        const vls_mesh_desc& m = parts[p];
+        if (m.n_vertices < 0 || m.n_triangles < 0) return fail(VLS_ERR_INVALID_ARG, "negative part sizes");
+        if ((m.n_vertices > 0 && !m.vertices) ||
+            (m.n_triangles > 0 && (!m.triangles || !m.reflectance || m.n_vertices < 1)))
+            return fail(VLS_ERR_INVALID_ARG, "a part lacks vertices, triangles or reflectance");
+        if (m.memory != VLS_MEM_HOST && m.memory != VLS_MEM_DEVICE)
+            return fail(VLS_ERR_INVALID_ARG, "memory must be VLS_MEM_HOST or VLS_MEM_DEVICE");
+    }
+    V = 0;
+    T = 0;
+    of_part.assign(n_parts, {});
+    voff.assign(n_instances, 0);
+    toff.assign(n_instances, 0);
+    for (int j = 0; j < n_instances; ++j) {
+        const vls_instance_desc& d = instances[j];
+        if (d.part < 0 || d.part >= n_parts) return fail(VLS_ERR_INVALID_ARG, "instance part index out of range");
+        for (int i = 0; i < 12; ++i)
+            if (!std::isfinite(d.affine[i])) return fail(VLS_ERR_INVALID_ARG, "non-finite instance map");
+        of_part[d.part].push_back(j);
+        voff[j] = V;
+        toff[j] = T;
+        V += parts[d.part].n_vertices;
+        T += parts[d.part].n_triangles;
+        if (T > 0x3fffffff || V > 0x7fffffff) return fail(VLS_ERR_UNSUPPORTED, "more than 2^30 triangles or 2^31 vertices");
+    }
+    return VLS_OK;
+}
+
 vls_status vls_scene_create_instanced(vls_context ctx, const vls_mesh_desc* parts, int32_t n_parts,
                                       const vls_instance_desc* instances, int32_t n_instances, void* stream,
                                       vls_scene* out)
@@ -695,39 +763,13 @@ vls_status vls_scene_create_instanced(vls_context ctx, const vls_mesh_desc* part
         }
     } tmp;
     try {
-        if (!ctx || !out || (n_parts > 0 && !parts) || (n_instances > 0 && !instances))
-            return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+        if (!ctx || !out) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
         *out = nullptr;
-        if (n_parts < 0 || n_instances < 0) return fail(VLS_ERR_INVALID_ARG, "negative counts");
-        for (int p = 0; p < n_parts; ++p) {
-            const vls_mesh_desc& m = parts[p];
-            if (m.n_vertices < 0 || m.n_triangles < 0) return fail(VLS_ERR_INVALID_ARG, "negative part sizes");
-            if ((m.n_vertices > 0 && !m.vertices) ||
-                (m.n_triangles > 0 && (!m.triangles || !m.reflectance || m.n_vertices < 1)))
-                return fail(VLS_ERR_INVALID_ARG, "a part lacks vertices, triangles or reflectance");
-            if (m.memory != VLS_MEM_HOST && m.memory != VLS_MEM_DEVICE)
-                return fail(VLS_ERR_INVALID_ARG, "memory must be VLS_MEM_HOST or VLS_MEM_DEVICE");
-        }
         int64_t V = 0, T = 0;
-        std::vector<std::vector<int>> of_part(n_parts);
-        for (int j = 0; j < n_instances; ++j) {
-            const vls_instance_desc& d = instances[j];
-            if (d.part < 0 || d.part >= n_parts) return fail(VLS_ERR_INVALID_ARG, "instance part index out of range");
-            for (int i = 0; i < 12; ++i)
-                if (!std::isfinite(d.affine[i])) return fail(VLS_ERR_INVALID_ARG, "non-finite instance map");
-            of_part[d.part].push_back(j);
-            V += parts[d.part].n_vertices;
-            T += parts[d.part].n_triangles;
-            if (T > 0x3fffffff || V > 0x7fffffff) return fail(VLS_ERR_UNSUPPORTED, "more than 2^30 triangles or 2^31 vertices");
-        }
-        // first vertex and triangle of each instance, in instance order
-        std::vector<long long> voff(n_instances), toff(n_instances);
-        for (long long j = 0, v = 0, t = 0; j < n_instances; ++j) {
-            voff[j] = v;
-            toff[j] = t;
-            v += parts[instances[j].part].n_vertices;
-            t += parts[instances[j].part].n_triangles;
-        }
+        std::vector<long long> voff, toff;
+        std::vector<std::vector<int>> of_part;
+        vls_status cst = check_placement(parts, n_parts, instances, n_instances, V, T, voff, toff, of_part);
+        if (cst != VLS_OK) return cst;
         VLS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
         hipStream_t s = (hipStream_t)stream;
         float *wv = nullptr, *wr = nullptr;
@@ -800,8 +842,167 @@ vls_status vls_scene_create_instanced(vls_context ctx, const vls_mesh_desc* part
     }
 }
 
+vls_status vls_scene_create_two_level(vls_context ctx, const vls_mesh_desc* parts, int32_t n_parts,
+                                      const vls_instance_desc* instances, int32_t n_instances, void* stream,
+                                      vls_scene* out)
+{
+    try {
+        if (!ctx || !out) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        int64_t V = 0, T = 0;
+        std::vector<long long> voff, toff;
+        std::vector<std::vector<int>> of_part;
+        vls_status st = check_placement(parts, n_parts, instances, n_instances, V, T, voff, toff, of_part);
+        if (st != VLS_OK) return st;
+        // each map's inverse (the ray goes into the part's frame)
+        std::vector<InstDev> inst(n_instances);
+        for (int j = 0; j < n_instances; ++j) {
+            const double* m = instances[j].affine;
+            const double a = m[0], b = m[1], c = m[2], d = m[4], e = m[5], f = m[6], g = m[8], h = m[9], k = m[10];
+            const double A = e * k - f * h, B = f * g - d * k, C = d * h - e * g;
+            const double det = a * A + b * B + c * C;
+            if (!(std::fabs(det) > 0.0) || !std::isfinite(1.0 / det))
+                return fail(VLS_ERR_UNSUPPORTED, "a two-level scene needs invertible instance maps");
+            const double r = 1.0 / det;
+            const double M[9] = {A * r, (c * h - b * k) * r, (b * f - c * e) * r,
+                                 B * r, (a * k - c * g) * r, (c * d - a * f) * r,
+                                 C * r, (b * g - a * h) * r, (a * e - b * d) * r};
+            InstDev& I = inst[j];
+            memset(&I, 0, sizeof I);
+            memcpy(I.m, m, sizeof I.m);
+            for (int i = 0; i < 3; ++i) {
+                I.inv[4 * i] = M[3 * i];
+                I.inv[4 * i + 1] = M[3 * i + 1];
+                I.inv[4 * i + 2] = M[3 * i + 2];
+                I.inv[4 * i + 3] = -(M[3 * i] * m[3] + M[3 * i + 1] * m[7] + M[3 * i + 2] * m[11]);
+            }
+            I.part = instances[j].part;
+            I.tri_base = (int)toff[j];
+        }
+        hipStream_t s = (hipStream_t)stream;
+        std::unique_ptr<vls_scene_s> sc(new vls_scene_s());
+        sc->ctx = ctx;
+        sc->tl.reset(new TwoLevelHost());
+        TwoLevelHost& tl = *sc->tl;
+        tl.parts.assign(n_parts, nullptr);
+        std::vector<PartDev> pdev(n_parts);
+        memset(pdev.data(), 0, sizeof(PartDev) * pdev.size());
+        int64_t bytes = 0, internal = 0;
+        int part_depth = 0;
+        for (int p = 0; p < n_parts; ++p) {
+            if (of_part[p].empty() || parts[p].n_triangles == 0) continue;
+            vls_scene q = nullptr;
+            if ((st = vls_scene_create(ctx, &parts[p], stream, &q)) != VLS_OK) return st;
+            tl.parts[p] = q;
+            if (q->stats.max_depth > 63) return fail(VLS_ERR_UNSUPPORTED, "a part's tree is deeper than 63");
+            PartDev& P = pdev[p];
+            P.nodes = q->b.nodes;
+            P.tris = q->b.tris;
+            P.refl = q->b.refl;
+            P.root = q->root;
+            P.n_tri = (int)q->b.n_tri;
+            float mag = 0.0f;
+            for (int a = 0; a < 3; ++a) mag = std::max(mag, std::max(std::fabs(q->stats.bounds_lo[a]), std::fabs(q->stats.bounds_hi[a])));
+            P.mag = mag;
+            bytes += q->stats.device_bytes;
+            internal += q->stats.n_internal_nodes;
+            part_depth = std::max(part_depth, (int)q->stats.max_depth);
+        }
+        // the instances' boxes in the scene's frame: the part's box corners mapped
+        // in FP64, rounded outward to FP32 (each placed vertex rounds inside them),
+        // as degenerate triangles (lo, hi, lo) of the top-level tree; instances of
+        // empty parts are left out
+        std::vector<float> tv;
+        std::vector<int32_t> tt;
+        std::vector<InstDev> used;
+        for (int j = 0; j < n_instances; ++j) {
+            const InstDev& I = inst[j];
+            if (!tl.parts[I.part]) continue;
+            const vls_scene_stats& ps = tl.parts[I.part]->stats;
+            double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int corner = 0; corner < 8; ++corner) {
+                const double x = (corner & 1) ? ps.bounds_hi[0] : ps.bounds_lo[0];
+                const double y = (corner & 2) ? ps.bounds_hi[1] : ps.bounds_lo[1];
+                const double z = (corner & 4) ? ps.bounds_hi[2] : ps.bounds_lo[2];
+                for (int i = 0; i < 3; ++i) {
+                    const double w = I.m[4 * i] * x + I.m[4 * i + 1] * y + I.m[4 * i + 2] * z + I.m[4 * i + 3];
+                    lo[i] = std::min(lo[i], w);
+                    hi[i] = std::max(hi[i], w);
+                }
+            }
+            float flo[3], fhi[3];
+            double wmax = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                // one more step outward covers the rounding of the corner arithmetic itself
+                flo[i] = std::nextafter((float)lo[i], -INFINITY);
+                fhi[i] = std::nextafter((float)hi[i], INFINITY);
+                if (!std::isfinite(flo[i]) || !std::isfinite(fhi[i]))
+                    return fail(VLS_ERR_INVALID_ARG, "non-finite placed vertex");
+                wmax = std::max(wmax, std::max(std::fabs((double)flo[i]), std::fabs((double)fhi[i])));
+            }
+            // a placed vertex moves by at most |w| 2^-24 per coordinate when rounded;
+            // through A^-1 that is at most |A^-1|_F |w| 2^-23 in the part's frame
+            double fro = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int c = 0; c < 3; ++c) fro += I.inv[4 * i + c] * I.inv[4 * i + c];
+            InstDev u = I;
+            u.pad_local = (float)(std::sqrt(fro) * wmax * 1.1920928955078125e-07 * 1.01);
+            used.push_back(u);
+            const int32_t base = (int32_t)(tv.size() / 3);
+            for (const float* q : {flo, fhi, flo}) tv.insert(tv.end(), q, q + 3);
+            tt.insert(tt.end(), {base, base + 1, base + 2});
+        }
+        std::vector<float> trefl(tt.size() / 3, 0.0f);
+        vls_mesh_desc top{};
+        top.vertices = tv.data();
+        top.triangles = tt.data();
+        top.reflectance = trefl.data();
+        top.n_vertices = (int64_t)(tv.size() / 3);
+        top.n_triangles = (int64_t)(tt.size() / 3);
+        top.memory = VLS_MEM_HOST;
+        vls_scene q = nullptr;
+        if ((st = vls_scene_create(ctx, &top, stream, &q)) != VLS_OK) return st;
+        tl.top = q;
+        if (q->stats.max_depth > 47) return fail(VLS_ERR_UNSUPPORTED, "the instances' tree is deeper than 47");
+        VLS_HIP(hipMalloc(&tl.inst, sizeof(InstDev) * std::max<size_t>(used.size(), 1)), "instance table");
+        VLS_HIP(hipMalloc(&tl.parts_dev, sizeof(PartDev) * std::max<size_t>(pdev.size(), 1)), "part table");
+        if (!used.empty())
+            VLS_HIP(hipMemcpy(tl.inst, used.data(), sizeof(InstDev) * used.size(), hipMemcpyHostToDevice), "instance table");
+        if (!pdev.empty())
+            VLS_HIP(hipMemcpy(tl.parts_dev, pdev.data(), sizeof(PartDev) * pdev.size(), hipMemcpyHostToDevice), "part table");
+        TwoLevelDev& d = tl.dev;
+        d.nodes = q->b.nodes;
+        d.tris = q->b.tris;
+        d.inst = tl.inst;
+        d.parts = tl.parts_dev;
+        d.root = q->root;
+        d.n_leaves = (int)q->b.n_tri;
+        d.n_inst = (int)used.size();
+        float tmag = 0.0f;
+        for (int a = 0; a < 3; ++a) tmag = std::max(tmag, std::max(std::fabs(q->stats.bounds_lo[a]), std::fabs(q->stats.bounds_hi[a])));
+        d.mag = tmag;
+        vls_scene_stats& ss = sc->stats;
+        ss.n_vertices = V;
+        ss.n_triangles = T;
+        ss.n_internal_nodes = internal + q->stats.n_internal_nodes;
+        ss.device_bytes = bytes + q->stats.device_bytes + (int64_t)(sizeof(InstDev) * used.size() + sizeof(PartDev) * pdev.size());
+        ss.max_depth = q->stats.max_depth + 1 + part_depth;
+        ss.max_supported_depth = 47 + 1 + 63;
+        for (int a = 0; a < 3; ++a) {
+            ss.bounds_lo[a] = q->stats.bounds_lo[a];
+            ss.bounds_hi[a] = q->stats.bounds_hi[a];
+        }
+        VLS_HIP(hipStreamSynchronize(s), "two-level build");
+        *out = sc.release();
+        return VLS_OK;
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
 vls_status vls_scene_update_vertices(vls_scene scene, const float* vertices_dev, void* stream)
 {
+    if (scene && scene->tl) return fail(VLS_ERR_UNSUPPORTED, "a two-level scene keeps its parts as built");
     if (!scene || (!vertices_dev && scene->b.n_vert > 0)) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
     if (!aligned(vertices_dev, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned vertices");
     hipStream_t s = (hipStream_t)stream;
@@ -814,6 +1015,7 @@ vls_status vls_scene_update_vertices(vls_scene scene, const float* vertices_dev,
 
 vls_status vls_scene_update_reflectance(vls_scene scene, const float* reflectance_dev, void* stream)
 {
+    if (scene && scene->tl) return fail(VLS_ERR_UNSUPPORTED, "a two-level scene keeps its parts as built");
     if (!scene || (!reflectance_dev && scene->b.n_tri > 0)) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
     if (scene->b.n_tri > 0)
         VLS_HIP(hipMemcpyAsync(scene->b.refl, reflectance_dev, 4 * (size_t)scene->b.n_tri, hipMemcpyDeviceToDevice,
@@ -825,6 +1027,7 @@ vls_status vls_scene_update_reflectance(vls_scene scene, const float* reflectanc
 vls_status vls_scene_set_voxels(vls_scene scene, const vls_voxel_desc* v, void* stream)
 {
     try {
+        if (scene && scene->tl) return fail(VLS_ERR_UNSUPPORTED, "not available for a two-level scene");
         if (!scene || !v) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
         if (scene->vox.n_vox > 0) return fail(VLS_ERR_INVALID_ARG, "the scene already has a voxel grid");
         if (!v->pad || !v->lut) return fail(VLS_ERR_INVALID_ARG, "pad and lut are required");
@@ -885,6 +1088,7 @@ vls_status vls_scene_set_voxels(vls_scene scene, const vls_voxel_desc* v, void* 
 vls_status vls_scene_set_specular(vls_scene scene, const float* specularity_dev, const float* exponent_dev,
                                   void* stream)
 {
+    if (scene && scene->tl) return fail(VLS_ERR_UNSUPPORTED, "not available for a two-level scene");
     if (!scene) return fail(VLS_ERR_INVALID_ARG, "scene is NULL");
     if (!specularity_dev && !exponent_dev) {
         scene->spec_on = false;
@@ -912,12 +1116,13 @@ vls_status vls_scene_stats_get(vls_scene scene, vls_scene_stats* out)
 {
     if (!scene || !out) return fail(VLS_ERR_INVALID_ARG, "NULL argument");
     *out = scene->stats;
-    out->max_supported_depth = scene->ctx->cfg.stack_lds + kMaxSpill - 1;
+    if (!scene->tl) out->max_supported_depth = scene->ctx->cfg.stack_lds + kMaxSpill - 1;
     return VLS_OK;
 }
 
 vls_status vls_scene_export(vls_scene scene, float* nodes, int32_t* leaf_tri, uint64_t* morton, int32_t* root)
 {
+    if (scene && scene->tl) return fail(VLS_ERR_UNSUPPORTED, "not available for a two-level scene");
     if (!scene) return fail(VLS_ERR_INVALID_ARG, "scene is NULL");
     VLS_HIP(hipDeviceSynchronize(), "sync");
     const int64_t nt = scene->b.n_tri;
@@ -942,12 +1147,20 @@ vls_status vls_trace(vls_context ctx, vls_scene scene, const vls_scanner_desc* s
         Prepared pr;
         vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
         if (st != VLS_OK) return st;
-        if ((st = check_scene(ctx, scene, pr)) != VLS_OK) return st;
+        if ((st = check_scene(ctx, scene, pr, true)) != VLS_OK) return st;
         if ((st = check_outputs(out)) != VLS_OK) return st;
         if (pulses->n_pulses > 0 && !out->subray_tri) return fail(VLS_ERR_INVALID_ARG, "subray_tri is required");
-        if ((st = cone_workspace(ctx, pulses->n_pulses)) != VLS_OK) return st;
         OutDev od = out_dev(out, pr.S_stride);
         PulsesDev pd = pulses_dev(pulses);
+        if (scene->tl) {
+            for (size_t s = 0; s + 1 < pr.off.size(); ++s) {
+                hipError_t e = launch_trace2(scene->tl->dev, pr.sc[pr.seg_sc[s]], pd, od, pr.off[s],
+                                             pr.off[s + 1] - pr.off[s], (hipStream_t)stream);
+                if (e != hipSuccess) return hip_fail(e, "two-level trace launch");
+            }
+            return VLS_OK;
+        }
+        if ((st = cone_workspace(ctx, pulses->n_pulses)) != VLS_OK) return st;
         SceneDev sd = scene_dev(scene);
         if (ctx->cfg.cone && pulses->n_pulses > 0) {
             vls_context_s::Batch* bt = nullptr;
@@ -1139,16 +1352,17 @@ vls_status vls_echo_width(vls_context ctx, const vls_scanner_desc* scanners, int
 
 static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners,
                                    int32_t n_scanners, const vls_pulse_batch* pulses, const vls_outputs* out,
-                                   Prepared& pr, vls_context_s::Batch*& bt, int& blocks)
+                                   Prepared& pr, vls_context_s::Batch*& bt, int& blocks, bool allow_tl = false)
 {
     vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
     if (st != VLS_OK) return st;
-    if ((st = check_scene(ctx, scene, pr)) != VLS_OK) return st;
+    if ((st = check_scene(ctx, scene, pr, allow_tl)) != VLS_OK) return st;
     if ((st = check_outputs(out)) != VLS_OK) return st;
     if (pulses->n_pulses > 0 && (!out->n_returns || !out->ret_range || !out->ret_amplitude || !out->ret_bin))
         return fail(VLS_ERR_INVALID_ARG, "simulate needs n_returns, ret_range, ret_amplitude and ret_bin");
     bt = nullptr;
     blocks = 0;
+    if (scene->tl) return VLS_OK;
     if ((st = cone_workspace(ctx, pulses->n_pulses)) != VLS_OK) return st;
     if (pulses->n_pulses > 0 && pulses->n_segments > 0) {
         if ((st = batch_tables(ctx, pr, bt)) != VLS_OK) return st;
@@ -1227,6 +1441,53 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
     return VLS_OK;
 }
 
+// A two-level scene: per-subray hits (k_trace2), then the waveform and the
+// returns from them; subray arrays, waveform and window origins the caller did
+// not ask for live in a context workspace.
+static vls_status simulate_two_level(vls_context ctx, vls_scene scene, const Prepared& pr,
+                                     const vls_pulse_batch* pulses, const vls_outputs* out, hipStream_t s)
+{
+    const long long n = pulses->n_pulses;
+    if (n == 0) return VLS_OK;
+    OutDev od = out_dev(out, pr.S_stride);
+    const size_t ns = (size_t)n * pr.S_stride;
+    size_t need = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t at = need;
+        need += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_tri = od.sub_tri ? 0 : carve(4 * ns);
+    const size_t o_rng = od.sub_range ? 0 : carve(8 * ns);
+    const size_t o_pow = od.sub_power ? 0 : carve(4 * ns);
+    const size_t o_wf = od.wf ? 0 : carve(4 * (size_t)n * pr.n_bins);
+    const size_t o_t0 = od.t0 ? 0 : carve(8 * (size_t)n);
+    if (need > ctx->tlw_bytes) {
+        VLS_HIP(hipDeviceSynchronize(), "workspace sync");
+        (void)hipFree(ctx->tlw);
+        ctx->tlw = nullptr;
+        ctx->tlw_bytes = 0;
+        VLS_HIP(hipMalloc(&ctx->tlw, need), "two-level workspace");
+        ctx->tlw_bytes = need;
+    }
+    unsigned char* w = ctx->tlw;
+    if (!od.sub_tri) od.sub_tri = reinterpret_cast<int32_t*>(w + o_tri);
+    if (!od.sub_range) od.sub_range = reinterpret_cast<double*>(w + o_rng);
+    if (!od.sub_power) od.sub_power = reinterpret_cast<float*>(w + o_pow);
+    if (!od.wf) od.wf = reinterpret_cast<float*>(w + o_wf);
+    if (!od.t0) od.t0 = reinterpret_cast<double*>(w + o_t0);
+    PulsesDev pd = pulses_dev(pulses);
+    for (size_t q = 0; q + 1 < pr.off.size(); ++q) {
+        const ScannerDev& sc = pr.sc[pr.seg_sc[q]];
+        const long long first = pr.off[q], count = pr.off[q + 1] - pr.off[q];
+        hipError_t e = launch_trace2(scene->tl->dev, sc, pd, od, first, count, s);
+        if (e == hipSuccess) e = launch_waveform(sc, pd, od, first, count, 0, ctx->cfg, s);
+        if (e == hipSuccess) e = launch_waveform(sc, pd, od, first, count, 1, ctx->cfg, s);
+        if (e != hipSuccess) return hip_fail(e, "two-level simulate launch");
+    }
+    return VLS_OK;
+}
+
 vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
                         const vls_pulse_batch* pulses, const vls_outputs* out, void* stream)
 {
@@ -1234,8 +1495,9 @@ vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc
         Prepared pr;
         vls_context_s::Batch* bt = nullptr;
         int blocks = 0;
-        vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, bt, blocks);
+        vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, bt, blocks, true);
         if (st != VLS_OK) return st;
+        if (scene->tl) return simulate_two_level(ctx, scene, pr, pulses, out, (hipStream_t)stream);
         return simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, (hipStream_t)stream, ctx->cand);
     } catch (const std::exception& e) {
         return fail(VLS_ERR_INTERNAL, e.what());
@@ -1295,6 +1557,7 @@ vls_status vls_waveform_backward(vls_context ctx, vls_scene scene, const vls_sca
         vls_status st = prepare(ctx, scanner, 1, pulses, pr);
         if (st != VLS_OK) return st;
         if (!scene || scene->ctx != ctx) return fail(VLS_ERR_INVALID_ARG, "scene is NULL or of another context");
+        if (scene->tl) return fail(VLS_ERR_UNSUPPORTED, "not available for a two-level scene");
         if (pulses->n_segments > 0) return fail(VLS_ERR_INVALID_ARG, "the adjoint takes one scanner and no segments");
         if (pulses->n_pulses > 0 && (!pulses->window_t0_ns || !subray_tri || !grad_waveform))
             return fail(VLS_ERR_INVALID_ARG, "the adjoint needs window_t0_ns, subray_tri and grad_waveform");

@@ -932,6 +932,212 @@ inline size_t sim_lds_bytes(int block, int ring, int wl_bytes)
     return (size_t)wl_bytes * (block / kWave) + sizeof(int) * (size_t)ring * block;
 }
 
+// ------------------------------------------------------------------ two-level scenes
+//
+// Scene parts kept once and placed by instances (Sec. 3.5: a part loaded several
+// times with transforms; Sec. 5.1).  A subray walks the top-level tree of the
+// instances' boxes; in each instance it reached it walks the part's tree with
+// the ray mapped into the part's frame (O' = A^-1 (O - t), D' = A^-1 D, so the
+// ray parameter, and with it every distance and the culling, is the world one),
+// and tests each leaf's triangle as placed: vertices ((A_i0 x + A_i1 y) + A_i2 z)
+// + t_i in FP64 rounded once to FP32, then the world-frame watertight test.
+// These are exactly the triangles and the test of the expanded scene, so hits,
+// distances and powers are the same bit for bit; the device holds the parts
+// once.  Box tests in the part's frame are padded by the instance's pad_local,
+// which covers the rounding of the placed vertices mapped back through A^-1.
+
+// Placed vertex of an instance (the arithmetic of k_instance_verts).
+__device__ __forceinline__ void place(const InstDev& I, float4 v, const Ray& r, double* w)
+{
+#pragma clang fp contract(off)
+    const double x = v.x, y = v.y, z = v.z;
+    for (int i = 0; i < 3; ++i) {
+        const double* a = I.m + 4 * i;
+        double q = a[0] * x;
+        q = q + a[1] * y;
+        q = q + a[2] * z;
+        q = q + a[3];
+        w[i] = (double)(float)q - r.O[i];
+    }
+}
+
+// Box constants of the ray mapped into an instance's part frame.
+__device__ __forceinline__ void local_box(const InstDev& I, const PartDev& P, const Ray& r, RayBox& b)
+{
+#pragma clang fp contract(off)
+    double o[3], d[3];
+    for (int i = 0; i < 3; ++i) {
+        const double* a = I.inv + 4 * i;
+        o[i] = ((a[0] * r.O[0] + a[1] * r.O[1]) + a[2] * r.O[2]) + a[3];
+        d[i] = (a[0] * r.D[0] + a[1] * r.D[1]) + a[2] * r.D[2];
+    }
+    const double omax = fmax(fmax(fabs(o[0]), fabs(o[1])), fabs(o[2]));
+    const double pad = (omax + (double)P.mag + 1.0) * 1.9073486328125e-06 + (double)I.pad_local;
+    for (int i = 0; i < 3; ++i) {
+        float di = (float)d[i];
+        if (fabsf(di) < 1e-30f) di = copysignf(1e-30f, di);
+        const float inv = 1.0f / di;
+        b.inv[i] = inv;
+        b.oim[i] = (float)(o[i] + pad) * inv;
+        b.oip[i] = (float)(o[i] - pad) * inv;
+    }
+}
+
+struct Hit2 {
+    double t;
+    int id;     // scene triangle id (instance's first id + the part's index)
+    int inst;
+    int leaf;   // the part's leaf
+};
+
+constexpr int kTopStack = 48;    // top-level depth limit (checked on the host)
+constexpr int kPartStack = 64;   // part depth limit (checked on the host)
+
+__device__ __forceinline__ void leaf_test2(const InstDev& I, const PartDev& P, int j, int li, const Ray& r, Hit2& h,
+                                           float& tcull)
+{
+    const float4 V0 = P.tris[3 * li], V1 = P.tris[3 * li + 1], V2 = P.tris[3 * li + 2];
+    double a[3], b[3], c[3];
+    place(I, V0, r, a);
+    place(I, V1, r, b);
+    place(I, V2, r, c);
+    const double t = r.kz == 2 ? woop_t<2>(r, a, b, c) : (r.kz == 1 ? woop_t<1>(r, a, b, c) : woop_t<0>(r, a, b, c));
+    const int id = I.tri_base + __float_as_int(V0.w);
+    if (!(t > 0.0 && (t < h.t || (t == h.t && id < h.id)))) return;
+    h.t = t;
+    h.id = id;
+    h.inst = j;
+    h.leaf = li;
+    float tf = (float)t;
+    if ((double)tf < t) tf = nextafterf(tf, INFINITY);
+    tcull = tf;
+}
+
+// Walk of one part (the ray in its frame); budget and range checks as in traverse.
+__device__ __forceinline__ void part_walk(const InstDev& I, const PartDev& P, int j, const Ray& r, Hit2& h,
+                                          float& tcull)
+{
+    if (P.n_tri <= 0) return;
+    RayBox lb;
+    local_box(I, P, r, lb);
+    int stk[kPartStack];
+    int sp = 0;
+    int node = P.root;
+    const int n_int = P.n_tri - 1;
+    for (int budget = 2 * P.n_tri + 64; budget > 0; --budget) {
+        if (node >= n_int || ~node >= P.n_tri) break;
+        if (node >= 0) {
+            const float4* nd = P.nodes + 4 * node;
+            const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+            float tl, tr;
+            const bool hl = box_hit(lb, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl);
+            const bool hr = box_hit(lb, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr);
+            const int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
+            if (hl && hr) {
+                if (sp >= kPartStack) break;
+                stk[sp++] = tl <= tr ? cr : cl;
+                node = tl <= tr ? cl : cr;
+                continue;
+            }
+            if (hl) { node = cl; continue; }
+            if (hr) { node = cr; continue; }
+        } else {
+            leaf_test2(I, P, j, ~node, r, h, tcull);
+        }
+        if (sp == 0) break;
+        node = stk[--sp];
+    }
+}
+
+__device__ __forceinline__ Hit2 walk2(const TwoLevelDev& tl, const Ray& r)
+{
+    Hit2 h;
+    h.t = INFINITY;
+    h.id = 0x7fffffff;
+    h.inst = -1;
+    h.leaf = -1;
+    if (tl.n_leaves <= 0) return h;
+    RayBox rb;
+    setup_box(r, tl.mag, rb);
+    float tcull = INFINITY;
+    int stk[kTopStack];
+    int sp = 0;
+    int node = tl.root;
+    const int n_int = tl.n_leaves - 1;
+    for (int budget = 2 * tl.n_leaves + 64; budget > 0; --budget) {
+        if (node >= n_int || ~node >= tl.n_leaves) break;
+        if (node >= 0) {
+            const float4* nd = tl.nodes + 4 * node;
+            const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+            float tl_, tr_;
+            const bool hl = box_hit(rb, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl_);
+            const bool hr = box_hit(rb, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr_);
+            const int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
+            if (hl && hr) {
+                if (sp >= kTopStack) break;
+                stk[sp++] = tl_ <= tr_ ? cr : cl;
+                node = tl_ <= tr_ ? cl : cr;
+                continue;
+            }
+            if (hl) { node = cl; continue; }
+            if (hr) { node = cr; continue; }
+        } else {
+            // a box reached (a lone root leaf is entered without a test: the
+            // part's own walk culls)
+            const int j = __float_as_int(tl.tris[3 * (~node)].w);
+            if (j >= 0 && j < tl.n_inst) {
+                const InstDev& I = tl.inst[j];
+                part_walk(I, tl.parts[I.part], j, r, h, tcull);
+            }
+        }
+        if (sp == 0) break;
+        node = stk[--sp];
+    }
+    return h;
+}
+
+// One lane per subray, ⌊64/S⌋ pulses per wavefront (as in the fused kernel).
+__global__ __launch_bounds__(256) void k_trace2(TwoLevelDev tl, ScannerDev sc, PulsesDev pulses, OutDev out,
+                                                long long first, long long count)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const long long wave = (long long)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const long long p0 = wave * sc.P_w;
+    if (p0 >= count) return;
+    const int S = sc.S;
+    const int pl = lane / S, k = lane - pl * S;
+    const long long left = count - p0;
+    if (pl >= (left < sc.P_w ? (int)left : sc.P_w)) return;
+    const long long p = first + p0 + pl;
+    Ray r;
+    const bool ok = setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, sc.pattern + 5 * k, r);
+    int tri = -1;
+    double R = INFINITY;
+    float cs = 0.0f, P = 0.0f;
+    if (ok) {
+        const Hit2 h = walk2(tl, r);
+        if (h.inst >= 0) {
+            const InstDev& I = tl.inst[h.inst];
+            const PartDev& Pt = tl.parts[I.part];
+            const float4 V0 = Pt.tris[3 * h.leaf], V1 = Pt.tris[3 * h.leaf + 1], V2 = Pt.tris[3 * h.leaf + 2];
+            double a[3], b[3], c[3];
+            place(I, V0, r, a);
+            place(I, V1, r, b);
+            place(I, V2, r, c);
+            SceneDev none{};
+            shade(r, a, b, c, h.t, (float)(sc.power_c * sc.pattern[5 * k + 4]), Pt.refl[__float_as_int(V0.w)], none,
+                  0, cs, P);
+            tri = h.id;
+            R = h.t;
+        }
+    }
+    const long long o = p * out.sub_stride + k;
+    if (out.sub_tri) out.sub_tri[o] = tri;
+    if (out.sub_range) out.sub_range[o] = R;
+    if (out.sub_cos) out.sub_cos[o] = cs;
+    if (out.sub_power) out.sub_power[o] = P;
+}
+
 }  // namespace
 
 hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
@@ -1062,6 +1268,16 @@ int persistent_occupancy_blocks(int max_bins, int staged_slots, bool vox, const 
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus < 1) cus = 1;
     return per_cu * cus;
+}
+
+hipError_t launch_trace2(const TwoLevelDev& tl, const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
+                         long long first, long long count, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    const long long waves = (count + sc.P_w - 1) / sc.P_w;
+    hipLaunchKernelGGL(k_trace2, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream, tl, sc, pulses, out, first,
+                       count);
+    return hipGetLastError();
 }
 
 }  // namespace vls

@@ -138,6 +138,45 @@ struct BatchDev {
     long long n_tiles;
 };
 
+// Two-level scenes (scene parts kept once, placed by instances; see trace.hip
+// k_trace2).  A part: its own LBVH over its triangles in its own frame.
+struct PartDev {
+    const float4* nodes;
+    const float4* tris;     // leaf records; .w of the first row = the part's triangle index
+    const float* refl;      // by the part's triangle index
+    int root;
+    int n_tri;
+    float mag;              // largest |coordinate| of the part's vertices
+    int pad_;
+};
+
+// An instance: x -> A x + t (m, rows [A_i0 A_i1 A_i2 t_i]) and its inverse
+// (inv, the same layout), the part, the scene id of its first triangle, and the
+// extra box padding in the part's frame that covers the FP32 rounding of the
+// placed vertices.
+struct InstDev {
+    double m[12];
+    double inv[12];
+    int part;
+    int tri_base;
+    float pad_local;
+    int pad_;
+};
+
+// The top level: an LBVH over the instances' boxes in the scene's frame (leaf
+// records hold each box as the degenerate triangle (lo, hi, lo); .w = the
+// instance index).
+struct TwoLevelDev {
+    const float4* nodes;
+    const float4* tris;
+    const InstDev* inst;
+    const PartDev* parts;
+    int root;
+    int n_leaves;
+    int n_inst;
+    float mag;
+};
+
 // A survey as the pulse generator sees it (see survey.hip).
 struct SurveyDev {
     int n_wp;
@@ -217,6 +256,10 @@ hipError_t launch_packets(const SceneDev& scene, const ScannerDev& sc0, const Ba
 hipError_t launch_echo_width(const ScannerDev& sc, const float* wf, const int32_t* n_ret, const int32_t* ret_bin,
                              float s0_bins, long long first, long long count, int* list,
                              unsigned long long* list_ctr, float* width, hipStream_t stream);
+// Per-subray closest hits, power and incidence in a two-level scene (pulses
+// [first, first + count) of one scanner); writes the out.sub_* arrays that are set.
+hipError_t launch_trace2(const TwoLevelDev& tl, const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
+                         long long first, long long count, hipStream_t stream);
 // Pulses [first, first + count) of a survey; tab: per-waypoint table (see survey.hip).
 hipError_t launch_generate(const SurveyDev& sv, const double* tab, long long first, long long count,
                            double* origins, float* dirs, hipStream_t stream);

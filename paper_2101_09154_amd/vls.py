@@ -113,6 +113,7 @@ _SIGS = {
     "vls_scene_set_voxels": ([P, P, P], i32),
     "vls_scene_set_specular": ([P, P, P, P], i32),
     "vls_scene_create_instanced": ([P, P, i32, P, i32, P, P], i32),
+    "vls_scene_create_two_level": ([P, P, i32, P, i32, P, P], i32),
     "vls_scene_stats_get": ([P, P], i32),
     "vls_scene_export": ([P, P, P, P, P], i32),
     "vls_scene_destroy": ([P], i32),
@@ -212,9 +213,10 @@ def n_subrays(sc):
 
 class Scene:
     @classmethod
-    def instanced(cls, ctx, parts, instances, stream=None):
+    def instanced(cls, ctx, parts, instances, stream=None, two_level=False):
         """A scene of parts placed by affine maps: parts = [(vertices, triangles, reflectance)]
-        (host numpy arrays or device tensors), instances = [(part, affine 3 x 4)]."""
+        (host numpy arrays or device tensors), instances = [(part, affine 3 x 4)]; two_level keeps
+        the parts once under a tree of the instances (vls_scene_create_two_level)."""
         descs = (MeshDesc * max(len(parts), 1))()
         keep = []
         for i, (v, t, r) in enumerate(parts):
@@ -236,8 +238,8 @@ class Scene:
         self = cls.__new__(cls)
         self.ctx = ctx
         self._h = P()
-        _check(lib().vls_scene_create_instanced(ctx._h, descs, len(parts), inst, len(instances), _stream(stream),
-                                                ctypes.byref(self._h)))
+        fn = lib().vls_scene_create_two_level if two_level else lib().vls_scene_create_instanced
+        _check(fn(ctx._h, descs, len(parts), inst, len(instances), _stream(stream), ctypes.byref(self._h)))
         del keep
         st = self.stats()
         self.n_vertices = int(st["n_vertices"])
@@ -364,8 +366,8 @@ class Context:
     def scene(self, vertices, triangles, reflectance, stream=None):
         return Scene(self, vertices, triangles, reflectance, stream)
 
-    def scene_instanced(self, parts, instances, stream=None):
-        return Scene.instanced(self, parts, instances, stream)
+    def scene_instanced(self, parts, instances, stream=None, two_level=False):
+        return Scene.instanced(self, parts, instances, stream, two_level)
 
     def set_launch_config(self, block_waves=1, stack_lds=16, persistent_blocks=0, pack=0, cone=1):
         c = LaunchConfig(block_waves, stack_lds, persistent_blocks, pack, cone, 0)

@@ -149,3 +149,84 @@ def test_instanced_forest_sampled(ctx):
     compare(mesh, pulses, sc, g, sel, "uls_instanced")
     tri = out["subray_tri"]
     say("uls_instanced: subrays on trees %.3f" % float((tri >= parts[0].n_triangles).float().mean()))
+
+
+# ------------------------------------------------------------------ two levels
+
+
+def test_two_level_bitwise_equals_expanded(ctx):
+    # the two-level scene tests the same placed triangles with the same
+    # arithmetic: every output equals the expanded scene's bit for bit
+    for seed in (5, 6):
+        parts, inst, pulses, sc = _small_case(seed=seed)
+        flat = ctx.scene_instanced(_parts(parts), inst)
+        two = ctx.scene_instanced(_parts(parts), inst, two_level=True)
+        st = two.stats()
+        say("two-level stats", st)
+        assert two.n_triangles == flat.n_triangles
+        assert st["device_bytes"] < flat.stats()["device_bytes"]
+        o, d = _dev(pulses.origins), _dev(pulses.directions)
+        a = to_np(ctx.simulate(flat, sc, o, d))
+        b = to_np(ctx.simulate(two, sc, o, d))
+        tr = to_np(ctx.trace(two, sc, o, d))
+        torch.cuda.synchronize()
+        for k in a:
+            assert np.array_equal(a[k], b[k], equal_nan=True), (seed, k)
+        for k in tr:
+            assert np.array_equal(a[k], tr[k], equal_nan=True), (seed, k)
+        assert (a["subray_tri"] >= parts[0].n_triangles).mean() > 0.01
+
+
+def test_two_level_batches_and_limits(ctx):
+    import paper_2101_09154_amd as vp
+    parts, inst, pulses, sc = _small_case(seed=8)
+    two = ctx.scene_instanced(_parts(parts), inst, two_level=True)
+    flat = ctx.scene_instanced(_parts(parts), inst)
+    o, d = _dev(pulses.origins), _dev(pulses.directions)
+    # a batch of two scanners, fixed window origins, and outputs without subrays
+    scs = [sc, configs.scanner(1e-3, 7, n_bins=256)]
+    off = np.array([0, 900, pulses.n], np.int64)
+    seg = np.array([1, 0], np.int32)
+    a = to_np(ctx.simulate(flat, scs, o, d, segment_offsets=off, segment_scanner=seg))
+    b = to_np(ctx.simulate(two, scs, o, d, segment_offsets=off, segment_scanner=seg))
+    t0 = _dev(a["window_t0_ns"])
+    c = to_np(ctx.simulate(two, sc, o, d, t0=t0, subrays=False))
+    e = to_np(ctx.simulate(flat, sc, o, d, t0=t0, subrays=False))
+    torch.cuda.synchronize()
+    for k in a:
+        if k.startswith("subray_"):
+            for q in range(2):
+                S = oracle.pattern(scs[seg[q]])[0].size
+                assert np.array_equal(a[k][off[q]:off[q + 1], :S], b[k][off[q]:off[q + 1], :S], equal_nan=True), k
+        else:
+            assert np.array_equal(a[k], b[k], equal_nan=True), k
+    for k in c:
+        assert np.array_equal(c[k], e[k], equal_nan=True), k
+    # no instances, and calls without a two-level form
+    empty = ctx.scene_instanced(_parts(parts), [], two_level=True)
+    assert (to_np(ctx.simulate(empty, sc, o[:5], d[:5]))["subray_tri"] == -1).all()
+    with pytest.raises(vp.VlsError):
+        two.update_reflectance(torch.zeros(two.n_triangles, device="cuda"))
+    with pytest.raises(vp.VlsError):
+        ctx.capture_graph(two, sc, o, d, ctx.alloc_outputs(pulses.n, 19, 256, 8, o.device))
+    sing = inst[1][1].copy()
+    sing[2, :3] = 0.0
+    with pytest.raises(vp.VlsError):
+        ctx.scene_instanced(_parts(parts), [(1, sing)], two_level=True)      # a map that is not invertible
+
+
+def test_two_level_forest_sampled(ctx):
+    parts, inst, pulses, sc = configs.uls_instanced()
+    two = ctx.scene_instanced(_parts(parts), inst, two_level=True)
+    flat = ctx.scene_instanced(_parts(parts), inst)
+    say("uls_instanced two-level stats", two.stats(), "expanded bytes", flat.stats()["device_bytes"])
+    o, d = _dev(pulses.origins), _dev(pulses.directions)
+    rng = np.random.default_rng(11)
+    sel = np.sort(rng.choice(pulses.n, 20000, replace=False))
+    idx = torch.from_numpy(sel).cuda()
+    os_, ds_ = o.index_select(0, idx).contiguous(), d.index_select(0, idx).contiguous()
+    a = to_np(ctx.simulate(flat, sc, os_, ds_))
+    b = to_np(ctx.simulate(two, sc, os_, ds_))
+    torch.cuda.synchronize()
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
