@@ -253,8 +253,19 @@ def bench_instanced(ctx, steps):
                        "(turned, scaled 0.8-1.2, moved); %d placed triangles" % scene.n_triangles,
            "instances": len(inst), "placed_triangles": scene.n_triangles,
            "part_triangles": int(sum(m.n_triangles for m in parts)),
-           "build_from_parts_ms": build_ms, "ms": ms, "subrays_per_s": n * S / (ms * 1e-3)}
+           "build_from_parts_ms": build_ms, "ms": ms, "subrays_per_s": n * S / (ms * 1e-3),
+           "device_bytes": scene.stats()["device_bytes"]}
     scene.close()
+    # the same scene in two levels: the parts once, a tree of the instances
+    ctx.scene_instanced(ps, inst, two_level=True).close()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    two = ctx.scene_instanced(ps, inst, two_level=True)
+    tl_build = (time.perf_counter() - t) * 1e3
+    tl_ms = time_ms(lambda: ctx.simulate(two, sc, o, d, out=out), max(steps // 4, 1), 1, torch.cuda.current_stream())
+    res["two_level"] = {"build_ms": tl_build, "ms": tl_ms, "subrays_per_s": n * S / (tl_ms * 1e-3),
+                        "device_bytes": two.stats()["device_bytes"]}
+    two.close()
     return res
 
 
