@@ -897,6 +897,7 @@ vls_status vls_scene_create_two_level(vls_context ctx, const vls_mesh_desc* part
             if (q->stats.max_depth > 63) return fail(VLS_ERR_UNSUPPORTED, "a part's tree is deeper than 63");
             PartDev& P = pdev[p];
             P.nodes = q->b.nodes;
+            P.nodes4 = q->b.nodes4;
             P.tris = q->b.tris;
             P.refl = q->b.refl;
             P.root = q->root;

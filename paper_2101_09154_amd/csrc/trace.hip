@@ -935,9 +935,9 @@ inline size_t sim_lds_bytes(int block, int ring, int wl_bytes)
 // ------------------------------------------------------------------ two-level scenes
 //
 // Scene parts kept once and placed by instances (Sec. 3.5: a part loaded several
-// times with transforms; Sec. 5.1).  A subray walks the top-level tree of the
-// instances' boxes; in each instance it reached it walks the part's tree with
-// the ray mapped into the part's frame (O' = A^-1 (O - t), D' = A^-1 D, so the
+// times with transforms; Sec. 5.1).  A pulse's subrays walk, as one packet, the
+// top-level tree of the instances' boxes; in each instance reached they walk the
+// part's tree with the ray mapped into the part's frame (O' = A^-1 (O - t), D' = A^-1 D, so the
 // ray parameter, and with it every distance and the culling, is the world one),
 // and tests each leaf's triangle as placed: vertices ((A_i0 x + A_i1 y) + A_i2 z)
 // + t_i in FP64 rounded once to FP32, then the world-frame watertight test.
@@ -991,7 +991,6 @@ struct Hit2 {
 };
 
 constexpr int kTopStack = 48;    // top-level depth limit (checked on the host)
-constexpr int kPartStack = 64;   // part depth limit (checked on the host)
 
 __device__ __forceinline__ void leaf_test2(const InstDev& I, const PartDev& P, int j, int li, const Ray& r, Hit2& h,
                                            float& tcull)
@@ -1013,54 +1012,84 @@ __device__ __forceinline__ void leaf_test2(const InstDev& I, const PartDev& P, i
     tcull = tf;
 }
 
-// Walk of one part (the ray in its frame); budget and range checks as in traverse.
-__device__ __forceinline__ void part_walk(const InstDev& I, const PartDev& P, int j, const Ray& r, Hit2& h,
-                                          float& tcull)
+// One part walked by the wavefront as a packet (as packet_walk does for a
+// scene): the four-wide records, each lane's ray in the part's frame and its
+// own culling distance, a child entered when any lane's box test passes,
+// nearest first by the first lane's entry distance; a uniform stack of `cap`
+// entries at st (3 per four-wide level; the host bounds the part's depth).
+__device__ __forceinline__ void part_packet(const InstDev& I, const PartDev& P, int j, const Ray& r, bool on,
+                                            int leader, Hit2& h, float& tcull, int* __restrict__ st, int cap)
 {
+    const int lane = threadIdx.x & (kWave - 1);
     if (P.n_tri <= 0) return;
     RayBox lb;
     local_box(I, P, r, lb);
-    int stk[kPartStack];
-    int sp = 0;
-    int node = P.root;
     const int n_int = P.n_tri - 1;
-    for (int budget = 2 * P.n_tri + 64; budget > 0; --budget) {
-        if (node >= n_int || ~node >= P.n_tri) break;
+    int node = P.root;
+    int sp = 0;
+    for (int guard = 2 * P.n_tri + 64; guard > 0; --guard) {
         if (node >= 0) {
-            const float4* nd = P.nodes + 4 * node;
-            const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
-            float tl, tr;
-            const bool hl = box_hit(lb, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl);
-            const bool hr = box_hit(lb, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr);
-            const int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
-            if (hl && hr) {
-                if (sp >= kPartStack) break;
-                stk[sp++] = tl <= tr ? cr : cl;
-                node = tl <= tr ? cl : cr;
+            if (node >= n_int) break;  // only a corrupted structure gets here
+            const float4* nd = P.nodes4 + 8 * node;
+            const float4 LX = nd[0], LY = nd[1], LZ = nd[2], HX = nd[3], HY = nd[4], HZ = nd[5], RF = nd[6];
+            int rf[4] = {__float_as_int(RF.x), __float_as_int(RF.y), __float_as_int(RF.z), __float_as_int(RF.w)};
+            float t[4];
+            bool hit[4];
+            hit[0] = on && rf[0] != kEmpty4 && box_hit(lb, LX.x, LY.x, LZ.x, HX.x, HY.x, HZ.x, tcull, t[0]);
+            hit[1] = on && rf[1] != kEmpty4 && box_hit(lb, LX.y, LY.y, LZ.y, HX.y, HY.y, HZ.y, tcull, t[1]);
+            hit[2] = on && rf[2] != kEmpty4 && box_hit(lb, LX.z, LY.z, LZ.z, HX.z, HY.z, HZ.z, tcull, t[2]);
+            hit[3] = on && rf[3] != kEmpty4 && box_hit(lb, LX.w, LY.w, LZ.w, HX.w, HY.w, HZ.w, tcull, t[3]);
+            float key[4];
+            for (int i = 0; i < 4; ++i) {
+                const float lt = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hit[i] ? t[i] : 3e38f), leader));
+                key[i] = __ballot(hit[i]) ? lt : INFINITY;
+            }
+#define VLS_CX(a, b)                                            \
+    if (key[b] < key[a]) {                                      \
+        const float kt = key[a]; key[a] = key[b]; key[b] = kt; \
+        const int rr = rf[a]; rf[a] = rf[b]; rf[b] = rr;       \
+    }
+            VLS_CX(0, 1) VLS_CX(2, 3) VLS_CX(0, 2) VLS_CX(1, 3) VLS_CX(1, 2)
+#undef VLS_CX
+            for (int q = 3; q >= 1; --q) {
+                if (key[q] < INFINITY && sp < cap) {
+                    if (lane == 0) st[sp] = rf[q];
+                    ++sp;
+                }
+            }
+            if (key[0] < INFINITY) {
+                node = rf[0];
                 continue;
             }
-            if (hl) { node = cl; continue; }
-            if (hr) { node = cr; continue; }
         } else {
-            leaf_test2(I, P, j, ~node, r, h, tcull);
+            if (~node >= P.n_tri) break;  // only a corrupted structure gets here
+            if (on) leaf_test2(I, P, j, ~node, r, h, tcull);
         }
         if (sp == 0) break;
-        node = stk[--sp];
+        --sp;
+        node = __builtin_amdgcn_readfirstlane(st[sp]);
     }
 }
 
-__device__ __forceinline__ Hit2 walk2(const TwoLevelDev& tl, const Ray& r)
+// The subrays of one pulse (lanes with `on`) through a two-level scene: the
+// top-level binary tree walked as a packet (a child entered when any lane's
+// box test passes, nearer first by the first lane), and each instance reached
+// walked by part_packet.  top / low: the wavefront's uniform stacks.
+__device__ __forceinline__ Hit2 packet_walk2(const TwoLevelDev& tl, const Ray& r, bool on, int* __restrict__ top,
+                                             int* __restrict__ low)
 {
+    const int lane = threadIdx.x & (kWave - 1);
     Hit2 h;
     h.t = INFINITY;
     h.id = 0x7fffffff;
     h.inst = -1;
     h.leaf = -1;
-    if (tl.n_leaves <= 0) return h;
+    const unsigned long long onm = __ballot(on);
+    if (tl.n_leaves <= 0 || !onm) return h;
+    const int leader = __ffsll((long long)onm) - 1;
     RayBox rb;
     setup_box(r, tl.mag, rb);
     float tcull = INFINITY;
-    int stk[kTopStack];
     int sp = 0;
     int node = tl.root;
     const int n_int = tl.n_leaves - 1;
@@ -1069,67 +1098,68 @@ __device__ __forceinline__ Hit2 walk2(const TwoLevelDev& tl, const Ray& r)
         if (node >= 0) {
             const float4* nd = tl.nodes + 4 * node;
             const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
-            float tl_, tr_;
-            const bool hl = box_hit(rb, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl_);
-            const bool hr = box_hit(rb, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr_);
+            float tl_ = 0.0f, tr_ = 0.0f;
+            const bool hl = on && box_hit(rb, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tcull, tl_);
+            const bool hr = on && box_hit(rb, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tcull, tr_);
             const int cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
-            if (hl && hr) {
-                if (sp >= kTopStack) break;
-                stk[sp++] = tl_ <= tr_ ? cr : cl;
-                node = tl_ <= tr_ ? cl : cr;
+            const float kl = __ballot(hl) ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hl ? tl_ : 3e38f), leader)) : INFINITY;
+            const float kr = __ballot(hr) ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hr ? tr_ : 3e38f), leader)) : INFINITY;
+            if (kl < INFINITY && kr < INFINITY) {
+                if (sp < kTopStack) {
+                    if (lane == 0) top[sp] = kl <= kr ? cr : cl;
+                    ++sp;
+                }
+                node = kl <= kr ? cl : cr;
                 continue;
             }
-            if (hl) { node = cl; continue; }
-            if (hr) { node = cr; continue; }
+            if (kl < INFINITY) { node = cl; continue; }
+            if (kr < INFINITY) { node = cr; continue; }
         } else {
-            // a box reached (a lone root leaf is entered without a test: the
-            // part's own walk culls)
             const int j = __float_as_int(tl.tris[3 * (~node)].w);
             if (j >= 0 && j < tl.n_inst) {
                 const InstDev& I = tl.inst[j];
-                part_walk(I, tl.parts[I.part], j, r, h, tcull);
+                part_packet(I, tl.parts[I.part], j, r, on, leader, h, tcull, low, kPacketCap);
             }
         }
         if (sp == 0) break;
-        node = stk[--sp];
+        --sp;
+        node = __builtin_amdgcn_readfirstlane(top[sp]);
     }
     return h;
 }
 
-// One lane per subray, ⌊64/S⌋ pulses per wavefront (as in the fused kernel).
+// One wavefront per pulse, one lane per subray.
 __global__ __launch_bounds__(256) void k_trace2(TwoLevelDev tl, ScannerDev sc, PulsesDev pulses, OutDev out,
                                                 long long first, long long count)
 {
+    __shared__ int stacks[4][kTopStack + kPacketCap];
     const int lane = threadIdx.x & (kWave - 1);
-    const long long wave = (long long)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const long long p0 = wave * sc.P_w;
-    if (p0 >= count) return;
+    const int w = threadIdx.x / kWave;
+    const long long q = (long long)blockIdx.x * (blockDim.x / kWave) + w;
+    if (q >= count) return;
     const int S = sc.S;
-    const int pl = lane / S, k = lane - pl * S;
-    const long long left = count - p0;
-    if (pl >= (left < sc.P_w ? (int)left : sc.P_w)) return;
-    const long long p = first + p0 + pl;
+    const int k = lane;
+    const long long p = first + q;
     Ray r;
-    const bool ok = setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, sc.pattern + 5 * k, r);
+    const bool on = k < S && setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, sc.pattern + 5 * k, r);
+    const Hit2 h = packet_walk2(tl, r, on, stacks[w], stacks[w] + kTopStack);
+    if (k >= S) return;
     int tri = -1;
     double R = INFINITY;
     float cs = 0.0f, P = 0.0f;
-    if (ok) {
-        const Hit2 h = walk2(tl, r);
-        if (h.inst >= 0) {
-            const InstDev& I = tl.inst[h.inst];
-            const PartDev& Pt = tl.parts[I.part];
-            const float4 V0 = Pt.tris[3 * h.leaf], V1 = Pt.tris[3 * h.leaf + 1], V2 = Pt.tris[3 * h.leaf + 2];
-            double a[3], b[3], c[3];
-            place(I, V0, r, a);
-            place(I, V1, r, b);
-            place(I, V2, r, c);
-            SceneDev none{};
-            shade(r, a, b, c, h.t, (float)(sc.power_c * sc.pattern[5 * k + 4]), Pt.refl[__float_as_int(V0.w)], none,
-                  0, cs, P);
-            tri = h.id;
-            R = h.t;
-        }
+    if (on && h.inst >= 0) {
+        const InstDev& I = tl.inst[h.inst];
+        const PartDev& Pt = tl.parts[I.part];
+        const float4 V0 = Pt.tris[3 * h.leaf], V1 = Pt.tris[3 * h.leaf + 1], V2 = Pt.tris[3 * h.leaf + 2];
+        double a[3], b[3], c[3];
+        place(I, V0, r, a);
+        place(I, V1, r, b);
+        place(I, V2, r, c);
+        SceneDev none{};
+        shade(r, a, b, c, h.t, (float)(sc.power_c * sc.pattern[5 * k + 4]), Pt.refl[__float_as_int(V0.w)], none, 0,
+              cs, P);
+        tri = h.id;
+        R = h.t;
     }
     const long long o = p * out.sub_stride + k;
     if (out.sub_tri) out.sub_tri[o] = tri;
@@ -1274,8 +1304,7 @@ hipError_t launch_trace2(const TwoLevelDev& tl, const ScannerDev& sc, const Puls
                          long long first, long long count, hipStream_t stream)
 {
     if (count <= 0) return hipSuccess;
-    const long long waves = (count + sc.P_w - 1) / sc.P_w;
-    hipLaunchKernelGGL(k_trace2, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream, tl, sc, pulses, out, first,
+    hipLaunchKernelGGL(k_trace2, dim3((unsigned)((count + 3) / 4)), dim3(256), 0, stream, tl, sc, pulses, out, first,
                        count);
     return hipGetLastError();
 }

@@ -142,6 +142,7 @@ struct BatchDev {
 // k_trace2).  A part: its own LBVH over its triangles in its own frame.
 struct PartDev {
     const float4* nodes;
+    const float4* nodes4;   // four-wide records
     const float4* tris;     // leaf records; .w of the first row = the part's triangle index
     const float* refl;      // by the part's triangle index
     int root;
