@@ -617,7 +617,7 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
             bool cand = j >= 1 && j <= nb - 2 && v > left && v >= right && v >= thr;
             unsigned long long mk = __ballot(cand);
             int rt = -1;
-            if (attrib && out.ret_tri) {
+            if (attrib && out.ret_tri && mk) {
                 // each kept return goes to the subray contributing most at its bin
                 // (lowest subray index on ties); subray lanes evaluate their own echo
                 float hi = 0.0f, lo = 0.0f;

@@ -93,3 +93,31 @@ def test_specular_adjoint_matches_oracle(ctx):
     ez = np.linalg.norm(gz.cpu().numpy() - gz_o) / np.linalg.norm(gz_o)
     say("specular adjoint rel L2: reflectance %.2e heights %.2e" % (er, ez))
     assert er <= 1e-4 and ez <= 1e-4
+
+
+def test_specular_als_full_sampled(ctx):
+    # the ALS workload at full size in the launch configuration bench.py times,
+    # a lobe on every triangle; sampled pulses against the oracle
+    mesh, pulses, sc = configs.als_buildings()
+    ks, n = _materials(mesh.n_triangles, 9)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    scene.set_specular(_dev(ks), _dev(n))
+    prev = ctx.launch_config()
+    ctx.set_launch_config(block_waves=2, stack_lds=8)
+    try:
+        out = ctx.simulate(scene, sc, _dev(pulses.origins), _dev(pulses.directions))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_launch_config(**{k: prev[k] for k in ("block_waves", "stack_lds", "persistent_blocks", "pack", "cone")})
+    rng = np.random.default_rng(12)
+    sel = np.sort(rng.choice(pulses.n, 24, replace=False))
+    idx = torch.from_numpy(sel).cuda()
+    g = {k: v.index_select(0, idx).cpu().numpy() for k, v in out.items()}
+    r = oracle.simulate(mesh, pulses, sc, select=sel, specular=(ks, n))
+    rep = {}
+    ok_h = check_hits(mesh, pulses, sc, sel, g, r, rep)
+    ok_w = check_waveforms(g, r, rep)
+    ok_r, tri_bad = check_returns(g, r, sc, rep)
+    left = attribution_excused(mesh, pulses, sc, sel, g, r, tri_bad)
+    say("specular als_buildings", rep)
+    assert ok_h and ok_w and ok_r and not left, rep
