@@ -290,6 +290,8 @@ typedef struct {
     int32_t n_bins;
     int32_t max_returns;
     int32_t reserved;
+    double range_noise_m;   /* ranging error (Sec. 3.7): standard deviation in m, >= 0 (0: none) */
+    uint64_t noise_seed;    /* its SplitMix64 seed */
 } vls_scanner_desc;
 
 /* Number of subrays the description yields (1..64), or an error for an

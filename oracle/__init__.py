@@ -67,7 +67,8 @@ class OrcScanner(ctypes.Structure):
                 ("min_echo_abs", ctypes.c_double), ("min_echo_rel", ctypes.c_double),
                 ("n_subrays", ctypes.c_int32), ("beam_quality", ctypes.c_int32),
                 ("pulse_shape", ctypes.c_int32), ("n_bins", ctypes.c_int32),
-                ("max_returns", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("max_returns", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("range_noise_m", ctypes.c_double), ("noise_seed", ctypes.c_uint64)]
 
 
 _lib = None
@@ -115,6 +116,8 @@ def lib():
         L.orc_voxel_hit.argtypes = [P, P, P, ctypes.c_double, ctypes.c_uint64, P, P]
         L.orc_voxel_hit.restype = i64
         L.orc_instance_vertices.argtypes = [P, i64, P, P]
+        L.orc_range_noise.argtypes = [P, i64, ctypes.c_int]
+        L.orc_range_noise.restype = ctypes.c_double
         L.orc_max_threads.argtypes = []
         _lib = L
     return _lib
@@ -134,7 +137,8 @@ def scanner_struct(sc):
                       min_echo_abs=sc.get("min_echo_abs", 0.0), min_echo_rel=sc.get("min_echo_rel", 1e-3),
                       n_subrays=sc.get("n_subrays", 0), beam_quality=sc.get("beam_quality", 0),
                       pulse_shape=PULSE_EQ3 if shape in ("eq3", PULSE_EQ3) else PULSE_GAUSSIAN,
-                      n_bins=sc["n_bins"], max_returns=sc.get("max_returns", 8), pad_=0)
+                      n_bins=sc["n_bins"], max_returns=sc.get("max_returns", 8), pad_=0,
+                      range_noise_m=sc.get("range_noise_m", 0.0), noise_seed=int(sc.get("noise_seed", 0)) & (2**64 - 1))
 
 
 def ring_layout(n_subrays=0, beam_quality=0):
@@ -290,6 +294,12 @@ def _specular(specular):
         return None, None
     ks, n = specular
     return np.ascontiguousarray(ks, dtype=np.float32), np.ascontiguousarray(n, dtype=np.float32)
+
+
+def range_noise(sc, pulse, ret):
+    """The ranging error of return slot `ret` of pulse `pulse` (0 without noise)."""
+    st = scanner_struct(sc)
+    return lib().orc_range_noise(ctypes.byref(st), int(pulse), int(ret))
 
 
 def surface_response(ct, ks, n):

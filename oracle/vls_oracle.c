@@ -35,6 +35,7 @@
  *      a voxel of plant area density PAD stops in it at a random depth drawn
  *      from the extinction coefficient (Eq. 5 through a leaf-angle table, Eq. 6),
  *      with the echo power of Eq. 8;
+ *   9b. optionally, a ranging error on each return's distance (Sec. 3.7);
  *  10. optionally, a Phong-type specular part of each triangle's response
  *      (Sec. 5.1: materials carry reflectance and specularity);
  *  11. scene parts placed by affine maps (Sec. 3.5: a part loaded several
@@ -94,6 +95,8 @@ typedef struct {
     int32_t n_bins;
     int32_t max_returns;
     int32_t pad_;
+    double range_noise_m;       /* standard deviation of the ranging error (Sec. 3.7); 0: none */
+    uint64_t noise_seed;
 } orc_scanner;
 
 /* ------------------------------------------------------------------ pattern (Sec. 3.4, Fig. 6) */
@@ -534,7 +537,21 @@ static void trace_pulse(const orc_ctx* c, int64_t pulse, const double O[3], cons
 }
 
 /* Waveform + returns for one pulse from its traced subrays. */
-static void waveform_pulse(const orc_ctx* c, const int32_t* tri, const double* R, const double* P,
+/* Ranging error of return r of pulse p (Sec. 3.7: each distance measurement
+ * carries a normally distributed error with the scanner's parameters; mean 0
+ * and standard deviation sigma here): Box-Muller on the uniforms
+ * ((x >> 11) + 1) 2^-53 of SplitMix64 outputs 2 (p K + r) and 2 (p K + r) + 1
+ * of the sequence seeded with the scanner's noise seed. */
+double orc_range_noise(const orc_scanner* sc, int64_t p, int r)
+{
+    if (!(sc->range_noise_m > 0.0)) return 0.0;
+    uint64_t c = 2 * ((uint64_t)p * (uint64_t)sc->max_returns + (uint64_t)r);
+    double u1 = (double)((orc_splitmix64(sc->noise_seed, c) >> 11) + 1) * (1.0 / 9007199254740992.0);
+    double u2 = (double)((orc_splitmix64(sc->noise_seed, c + 1) >> 11) + 1) * (1.0 / 9007199254740992.0);
+    return sc->range_noise_m * sqrt(-2.0 * log(u1)) * cos(2.0 * ORC_PI * u2);
+}
+
+static void waveform_pulse(const orc_ctx* c, int64_t pulse, const int32_t* tri, const double* R, const double* P,
                            const double* t0_in, double* wf, double* t0_out, int32_t* n_ret,
                            double* ret_range, double* ret_amp, int32_t* ret_tri, int32_t* ret_bin)
 {
@@ -565,7 +582,7 @@ static void waveform_pulse(const orc_ctx* c, const int32_t* tri, const double* R
         int bk = orc_attribute(sc, tri, R, P, c->S, tj);
         ret_bin[r] = j;
         ret_amp[r] = wf[j];
-        ret_range[r] = 0.5 * ORC_C_M_PER_NS * (tj - orc_peak_offset(sc));
+        ret_range[r] = 0.5 * ORC_C_M_PER_NS * (tj - orc_peak_offset(sc)) + orc_range_noise(sc, pulse, r);
         ret_tri[r] = bk >= 0 ? tri[bk] : -1;
     }
 }
@@ -630,7 +647,7 @@ int orc_simulate_ext(const float* verts, int64_t n_vert, const int32_t* tris, co
                 if (sub_v) sub_v[q * S + k] = V[k];
             }
             if (wf) {
-                waveform_pulse(&c, tri, R, P, t0_in ? t0_in + p : NULL, wf + q * nb, t0_out + q, n_ret + q,
+                waveform_pulse(&c, p, tri, R, P, t0_in ? t0_in + p : NULL, wf + q * nb, t0_out + q, n_ret + q,
                                ret_range + q * K, ret_amp + q * K, ret_tri + q * K, ret_bin + q * K);
             }
         }

@@ -111,6 +111,7 @@ vls_status check_scanner(const vls_scanner_desc& d, int idx)
         return fail(VLS_ERR_INVALID_ARG, b);
     };
     if (!(d.divergence_rad >= 0.0) || !std::isfinite(d.divergence_rad)) return bad("divergence_rad must be finite and >= 0");
+    if (!(d.range_noise_m >= 0.0) || !std::isfinite(d.range_noise_m)) return bad("range_noise_m must be finite and >= 0");
     if (!(d.pattern_extent >= 0.0) || !std::isfinite(d.pattern_extent)) return bad("pattern_extent must be finite and >= 0");
     if (!finite_pos(d.pulse_width_ns)) return bad("pulse_width_ns must be > 0");
     if (!finite_pos(d.bin_ns)) return bad("bin_ns must be > 0");
@@ -304,6 +305,8 @@ vls_status scanner_dev(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s
     s.power_c = d.peak_power_w * d.efficiency * d.receiver_diameter_m * d.receiver_diameter_m / 4.0;
     s.vox_c = s.power_c / (M_PI * d.divergence_rad * d.divergence_rad);
     s.tan_max = S > 1 ? std::tan(d.pattern_extent * 0.5 * d.divergence_rad) : 0.0;
+    s.range_noise = d.range_noise_m;
+    s.noise_seed = d.noise_seed;
     s.thr_abs = d.min_echo_abs;
     s.thr_rel = d.min_echo_rel;
     return VLS_OK;
@@ -526,6 +529,17 @@ vls_status cone_workspace(vls_context ctx, long long n)
     VLS_HIP(hipMalloc(&ctx->cand, sizeof(int) * cone_ws_ints(n)), "candidate workspace");
     ctx->cand_pulses = n;
     return VLS_OK;
+}
+
+// The ranging error of every segment's returns, once they are found.
+hipError_t range_noise_all(const Prepared& pr, const OutDev& od, hipStream_t s)
+{
+    for (size_t q = 0; q + 1 < pr.off.size(); ++q) {
+        hipError_t e = launch_range_noise(pr.sc[pr.seg_sc[q]], od.n_ret, od.ret_range, pr.off[q],
+                                          pr.off[q + 1] - pr.off[q], s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 double max_tan(const Prepared& pr)
@@ -1212,6 +1226,10 @@ static vls_status wave_common(vls_context ctx, const vls_scanner_desc* scanners,
                                            ctx->cfg, (hipStream_t)stream);
             if (e != hipSuccess) return hip_fail(e, "waveform launch");
         }
+        if (mode == 1) {
+            hipError_t e = range_noise_all(pr, od, (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "ranging error launch");
+        }
         return VLS_OK;
     } catch (const std::exception& e) {
         return fail(VLS_ERR_INTERNAL, e.what());
@@ -1439,6 +1457,7 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
     else e = launch_persistent(sd, bt->bd, pr.n_bins, staged_slots(pr), pd, od, ctx->cfg, blocks, s);
     if (e != hipSuccess) return hip_fail(e, "simulate launch");
     if (prof && (e = prof_end(ctx, s, ev, ctx->prof_fused)) != hipSuccess) return hip_fail(e, "timing event");
+    if ((e = range_noise_all(pr, od, s)) != hipSuccess) return hip_fail(e, "ranging error launch");
     return VLS_OK;
 }
 
@@ -1484,6 +1503,7 @@ static vls_status simulate_two_level(vls_context ctx, vls_scene scene, const Pre
         hipError_t e = launch_trace2(scene->tl->dev, sc, pd, od, first, count, s);
         if (e == hipSuccess) e = launch_waveform(sc, pd, od, first, count, 0, ctx->cfg, s);
         if (e == hipSuccess) e = launch_waveform(sc, pd, od, first, count, 1, ctx->cfg, s);
+        if (e == hipSuccess) e = launch_range_noise(sc, od.n_ret, od.ret_range, first, count, s);
         if (e != hipSuccess) return hip_fail(e, "two-level simulate launch");
     }
     return VLS_OK;

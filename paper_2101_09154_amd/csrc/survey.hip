@@ -99,7 +99,38 @@ __global__ __launch_bounds__(256) void k_generate(SurveyDev sv, const double* __
     w[2] = (float)d2;
 }
 
+// Ranging error (Sec. 3.7: each distance measurement carries a normally
+// distributed error; mean 0 and the scanner's standard deviation here), added
+// to the kept returns of pulses [first, first + count) after they are found:
+// Box-Muller on the uniforms of SplitMix64 outputs 2 (p K + slot) and
+// 2 (p K + slot) + 1 of the scanner's noise seed, so each return's draw is
+// fixed by its pulse and slot alone.  One thread per return slot.
+__global__ __launch_bounds__(256) void k_range_noise(double sigma, uint64_t seed, int K, const int32_t* __restrict__ n_ret,
+                                                     float* __restrict__ ret_range, long long first, long long count)
+{
+#pragma clang fp contract(off)
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count * K) return;
+    const long long p = first + q / K;
+    const int slot = (int)(q - (q / K) * K);
+    if (slot >= n_ret[p]) return;
+    const uint64_t c = 2 * ((uint64_t)p * (uint64_t)K + (uint64_t)slot);
+    const double u1 = sm_uniform(seed, c), u2 = sm_uniform(seed, c + 1);
+    float* r = ret_range + p * K + slot;
+    *r = (float)((double)*r + sigma * sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2));
+}
+
 }  // namespace
+
+hipError_t launch_range_noise(const ScannerDev& sc, const int32_t* n_ret, float* ret_range, long long first,
+                              long long count, hipStream_t stream)
+{
+    if (count <= 0 || !(sc.range_noise > 0.0)) return hipSuccess;
+    const long long n = count * sc.K;
+    hipLaunchKernelGGL(k_range_noise, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sc.range_noise,
+                       (uint64_t)sc.noise_seed, sc.K, n_ret, ret_range, first, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_generate(const SurveyDev& sv, const double* tab, long long first, long long count,
                            double* origins, float* dirs, hipStream_t stream)

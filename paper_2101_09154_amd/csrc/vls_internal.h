@@ -64,6 +64,8 @@ struct ScannerDev {
     double thr_abs;
     double thr_rel;
     double tan_max;         // tan of the largest subray angle (outer ring)
+    double range_noise;     // ranging error's standard deviation (m), 0: none
+    unsigned long long noise_seed;
     double vox_c;           // voxel echoes (Eq. 8): power_c / (pi beta^2), beta the full divergence
 };
 
@@ -261,6 +263,10 @@ hipError_t launch_echo_width(const ScannerDev& sc, const float* wf, const int32_
 // [first, first + count) of one scanner); writes the out.sub_* arrays that are set.
 hipError_t launch_trace2(const TwoLevelDev& tl, const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
                          long long first, long long count, hipStream_t stream);
+// Ranging error on the kept returns of pulses [first, first + count) of one scanner
+// (nothing when its range_noise is 0; see survey.hip).
+hipError_t launch_range_noise(const ScannerDev& sc, const int32_t* n_ret, float* ret_range, long long first,
+                              long long count, hipStream_t stream);
 // Pulses [first, first + count) of a survey; tab: per-waypoint table (see survey.hip).
 hipError_t launch_generate(const SurveyDev& sv, const double* tab, long long first, long long count,
                            double* origins, float* dirs, hipStream_t stream);

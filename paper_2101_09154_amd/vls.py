@@ -61,7 +61,7 @@ class ScannerDesc(ctypes.Structure):
                 ("window_pre_ns", f64), ("peak_power_w", f64), ("receiver_diameter_m", f64),
                 ("efficiency", f64), ("min_echo_abs", f64), ("min_echo_rel", f64), ("n_subrays", i32),
                 ("beam_quality", i32), ("pulse_shape", i32), ("n_bins", i32), ("max_returns", i32),
-                ("reserved", i32)]
+                ("reserved", i32), ("range_noise_m", f64), ("noise_seed", ctypes.c_uint64)]
 
 
 class PulseBatch(ctypes.Structure):
@@ -201,7 +201,9 @@ def scanner_desc(sc):
                        min_echo_abs=sc.get("min_echo_abs", 0.0), min_echo_rel=sc.get("min_echo_rel", 1e-3),
                        n_subrays=sc.get("n_subrays", 0), beam_quality=sc.get("beam_quality", 0),
                        pulse_shape=PULSE_EQ3 if shape in ("eq3", PULSE_EQ3) else PULSE_GAUSSIAN,
-                       n_bins=sc["n_bins"], max_returns=sc.get("max_returns", 8), reserved=0)
+                       n_bins=sc["n_bins"], max_returns=sc.get("max_returns", 8), reserved=0,
+                       range_noise_m=sc.get("range_noise_m", 0.0),
+                       noise_seed=int(sc.get("noise_seed", 0)) & 0xFFFFFFFFFFFFFFFF)
 
 
 def n_subrays(sc):

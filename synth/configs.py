@@ -31,14 +31,16 @@ from .pulses import tls_grid, als_lines, concat_pulses
 def scanner(divergence_rad, n_subrays, *, pulse_shape="gaussian", pulse_width_ns=4.0,
             bin_ns=1.0, n_bins=256, window_pre_ns=-1.0, max_returns=8,
             min_echo_abs=0.0, min_echo_rel=1e-3, peak_power_w=1.0,
-            receiver_diameter_m=1.0, efficiency=1.0, pattern_extent=1.0, beam_quality=0):
+            receiver_diameter_m=1.0, efficiency=1.0, pattern_extent=1.0, beam_quality=0,
+            range_noise_m=0.0, noise_seed=0):
     return dict(divergence_rad=float(divergence_rad), n_subrays=int(n_subrays),
                 beam_quality=int(beam_quality), pattern_extent=float(pattern_extent),
                 pulse_shape=pulse_shape, pulse_width_ns=float(pulse_width_ns),
                 bin_ns=float(bin_ns), n_bins=int(n_bins), window_pre_ns=float(window_pre_ns),
                 peak_power_w=float(peak_power_w), receiver_diameter_m=float(receiver_diameter_m),
                 efficiency=float(efficiency), min_echo_abs=float(min_echo_abs),
-                min_echo_rel=float(min_echo_rel), max_returns=int(max_returns))
+                min_echo_rel=float(min_echo_rel), max_returns=int(max_returns),
+                range_noise_m=float(range_noise_m), noise_seed=int(noise_seed))
 
 
 # ---------------------------------------------------------------- small_tls

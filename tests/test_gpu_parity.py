@@ -834,3 +834,26 @@ def test_cone_candidates_contain_every_hit(ctx):
             listed = set(cand[q, 1:1 + cand[q, 0]])
             for t in hits[q]:
                 assert t < 0 or t in listed, (q, t, listed)
+
+
+def test_ranging_noise_matches_oracle(ctx):
+    # Sec. 3.7 ranging error: the same counter-based draws as the oracle, on the
+    # distances only; the split path (vls_returns) draws the same errors
+    mesh, pulses, sc0 = configs.small_tls()
+    sc = dict(sc0, range_noise_m=0.05, noise_seed=77)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    say("ranging noise")
+    g = run_gpu(ctx, scene, pulses, sc)
+    g0 = run_gpu(ctx, scene, pulses, sc0)
+    compare(mesh, pulses, sc, g, label="ranging noise")
+    assert np.array_equal(g["ret_bin"], g0["ret_bin"]) and np.array_equal(g["waveform"], g0["waveform"])
+    has = np.arange(sc["max_returns"])[None, :] < g0["n_returns"][:, None]
+    e = (g["ret_range"] - g0["ret_range"])[has].astype(np.float64)
+    assert abs(e.std() / 0.05 - 1.0) < 0.05
+    o, d = _dev(pulses.origins), _dev(pulses.directions)
+    out = ctx.trace(scene, sc, o, d)
+    out.update(ctx.alloc_outputs(pulses.n, 19, sc["n_bins"], sc["max_returns"], o.device, subrays=False))
+    ctx.waveform(sc, o, d, out)
+    ctx.returns(sc, o, d, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(out)["ret_range"], g["ret_range"])
