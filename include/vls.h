@@ -373,8 +373,9 @@ vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_
 
 /* ------------------------------------------------------------------ surveys */
 
-/* Scan deflectors (Sec. 3.3, Fig. 7). */
+/* Scan deflectors (Sec. 3.3, Fig. 7) and platforms (Sec. 3.2). */
 enum { VLS_DEFLECT_POLYGON = 0, VLS_DEFLECT_SWING = 1, VLS_DEFLECT_CONIC = 2, VLS_DEFLECT_FIBRE = 3 };
+enum { VLS_PLATFORM_LINEAR = 0, VLS_PLATFORM_MULTICOPTER = 1 };
 
 /* A survey: a platform (Sec. 3.2) carrying a scanner with a deflector (Sec.
  * 3.3).  The paper gives the platforms' and deflectors' behaviour but no
@@ -384,6 +385,13 @@ enum { VLS_DEFLECT_POLYGON = 0, VLS_DEFLECT_SWING = 1, VLS_DEFLECT_CONIC = 2, VL
  *   from the first waypoint at t = 0, level, facing the current leg's
  *   horizontal direction, and stays at the last waypoint afterwards; one
  *   waypoint: static, facing +x;
+ *   Multicopter platform (it also speeds up and slows down; the mode without
+ *   banked turns, which stops and turns at each waypoint): every leg starts
+ *   from rest and ends at rest, accelerating at accel_mps2 up to speed_mps,
+ *   holding it, and slowing down at the same rate (a leg shorter than
+ *   speed^2 / accel speeds up over its first half and slows down over its
+ *   second); turns take no time; level; yaw is the leg's heading, or, with
+ *   leg_yaw, linear in the time on the leg from its start to its end value;
  *   platform frame x forward, y left, z up; with A = scan_angle_rad and
  *   f = scan_freq_hz the beam points along (0, sin a, -cos a) with
  *     POLYGON a = -A + 2A frac(f t)        (parallel lines, even density)
@@ -395,7 +403,8 @@ enum { VLS_DEFLECT_POLYGON = 0, VLS_DEFLECT_SWING = 1, VLS_DEFLECT_CONIC = 2, VL
  *   6k + 2 axis and 6k + 2 axis + 1 of the sequence seeded with `seed`
  *   (Box-Muller), so any range of pulses can be generated on its own.
  * waypoints: [n_waypoints][3] float64 in host memory, finite, consecutive ones
- * distinct; copied (the library caches one device table per distinct survey). */
+ * distinct; copied, as is leg_yaw (the library caches one device table per
+ * distinct survey). */
 typedef struct {
     const double* waypoints;
     int32_t n_waypoints;
@@ -405,10 +414,13 @@ typedef struct {
     double scan_freq_hz;
     double scan_angle_rad;
     int32_t n_fibres;
-    int32_t reserved;
+    int32_t platform;          /* VLS_PLATFORM_*; 0 (LinearPath) for older callers */
     double t0_s;
     double platform_noise_m;
     uint64_t seed;
+    double accel_mps2;         /* Multicopter: > 0 (with speed_mps > 0) when n_waypoints >= 2 */
+    const double* leg_yaw;     /* Multicopter: NULL, or host [n_waypoints - 1][2] start and end
+                                  yaw (rad, finite) of each leg; NULL for LinearPath */
 } vls_survey_desc;
 
 /* Pulses [first, first + count) of a survey, on the device, in the layout

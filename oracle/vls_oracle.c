@@ -28,7 +28,7 @@
  *   7. optionally, the width of each return: a Gaussian fitted by non-linear
  *      least squares to the waveform around the return (Sec. 3.4; its cost is
  *      discussed in Sec. 3.6);
- *   8. pulses generated from a survey: a LinearPath or static platform (Sec.
+ *   8. pulses generated from a survey: a LinearPath, Multicopter or static platform (Sec.
  *      3.2) carrying one of the four scan deflectors of Sec. 3.3, with optional
  *      platform position noise from a counter-based SplitMix64;
  *   9. optionally, transmissive voxels (Sec. 3.5.4, Sec. 5.2): a subray crossing
@@ -950,8 +950,22 @@ void orc_echo_width(const orc_scanner* sc, const double* wf, int n, const int32_
  *            Box-Muller on uniforms u = ((x >> 11) + 1) 2^-53 of SplitMix64
  *            output number c = 6k + 2 axis (+1) of the sequence seeded with
  *            `seed` (Steele, Lea & Flood 2014: output c mixes seed + (c + 1)
- *            times 0x9E3779B97F4A7C15). */
+ *            times 0x9E3779B97F4A7C15).
+ * The Multicopter platform (Sec. 3.2: it also speeds up and slows down; in
+ * the mode without banked turns it stops at each waypoint and turns there;
+ * start and end yaw of every leg may be given) is read as:
+ *   legs     each leg starts from rest at its first waypoint and ends at rest
+ *            at the next: constant acceleration `accel` up to `speed`, then
+ *            that speed, then the same deceleration; a leg too short to reach
+ *            `speed` (length below speed^2 / accel) accelerates over its first
+ *            half and slows down over its second; the turn at a waypoint
+ *            takes no time; afterwards the platform stays at the last one;
+ *   yaw      the leg's heading, or with `leg_yaw` ([n - 1][2]: start and end
+ *            yaw of each leg, rad) linear in the time spent on the leg from
+ *            the start to the end value; the platform stays level (the banked
+ *            turns of the smooth mode are not modelled). */
 enum { ORC_DEFLECT_POLYGON = 0, ORC_DEFLECT_SWING = 1, ORC_DEFLECT_CONIC = 2, ORC_DEFLECT_FIBRE = 3 };
+enum { ORC_PLATFORM_LINEAR = 0, ORC_PLATFORM_MULTICOPTER = 1 };
 
 typedef struct {
     const double* waypoints; /* [n][3] */
@@ -962,10 +976,12 @@ typedef struct {
     double scan_freq;        /* lines (polygon), oscillations (swing), revolutions (conic) per second */
     double scan_angle;       /* A: half the line's angle, or the cone's angle off nadir (rad) */
     int32_t n_fibres;
-    int32_t pad_;
+    int32_t platform;        /* ORC_PLATFORM_* */
     double t0;
     double noise_sigma;      /* m */
     uint64_t seed;
+    double accel;            /* m/s^2, Multicopter */
+    const double* leg_yaw;   /* [n - 1][2] or NULL, Multicopter */
 } orc_survey;
 
 uint64_t orc_splitmix64(uint64_t seed, uint64_t c)
@@ -981,6 +997,28 @@ static double sm_uniform(uint64_t seed, uint64_t c)
     return (double)((orc_splitmix64(seed, c) >> 11) + 1) * (1.0 / 9007199254740992.0);
 }
 
+/* Multicopter leg of length L at cruise speed v and acceleration a: its
+ * duration, and the distance covered tau seconds after it starts. */
+static double copter_leg_duration(double L, double v, double a)
+{
+    if (v * v / a <= L) return L / v + v / a; /* reaches v: two ramps of v / a, cruise over the rest */
+    return 2.0 * sqrt(L / a);                  /* speeds up to sqrt(a L) half way, then slows down */
+}
+
+static double copter_leg_distance(double L, double v, double a, double T, double tau)
+{
+    if (tau <= 0.0) return 0.0;
+    if (tau >= T) return L;
+    double top = v * v / a <= L ? v : sqrt(a * L); /* highest speed on the leg */
+    double ramp = top / a;                          /* time to reach it */
+    if (tau <= ramp) return 0.5 * a * tau * tau;
+    if (tau >= T - ramp) {
+        double r = T - tau;
+        return L - 0.5 * a * r * r;
+    }
+    return 0.5 * a * ramp * ramp + top * (tau - ramp);
+}
+
 /* Pulses [first, first + count): origins [count][3], directions [count][3]
  * (unit, FP64).  Returns 0, or -1 for an invalid survey. */
 int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, double* origins, double* dirs)
@@ -988,13 +1026,21 @@ int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, doub
     int nw = sv->n_waypoints;
     if (nw < 1 || !(sv->prf > 0.0)) return -1;
     if (sv->deflector == ORC_DEFLECT_FIBRE && sv->n_fibres < 2) return -1;
-    double* cum = (double*)malloc(sizeof(double) * (size_t)nw);
+    int copter = sv->platform == ORC_PLATFORM_MULTICOPTER;
+    if (sv->platform != ORC_PLATFORM_LINEAR && !copter) return -1;
+    if (copter && nw >= 2 && !(sv->speed > 0.0 && sv->accel > 0.0)) return -1;
+    if (!copter && sv->leg_yaw) return -1;
+    double* cum = (double*)malloc(sizeof(double) * (size_t)nw);   /* path length at each waypoint */
+    double* start = (double*)malloc(sizeof(double) * (size_t)nw); /* Multicopter: time at each waypoint */
     cum[0] = 0.0;
+    start[0] = 0.0;
     for (int i = 1; i < nw; ++i) {
         const double* a = sv->waypoints + 3 * (i - 1);
         const double* b = sv->waypoints + 3 * i;
         double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
-        cum[i] = cum[i - 1] + sqrt(dx * dx + dy * dy + dz * dz);
+        double len = sqrt(dx * dx + dy * dy + dz * dz);
+        cum[i] = cum[i - 1] + len;
+        start[i] = copter ? start[i - 1] + copter_leg_duration(len, sv->speed, sv->accel) : 0.0;
     }
     for (int64_t q = 0; q < count; ++q) {
         int64_t k = first + q;
@@ -1002,7 +1048,25 @@ int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, doub
         /* position along the path and heading of the current leg */
         double pos[3] = {sv->waypoints[0], sv->waypoints[1], sv->waypoints[2]};
         double yaw = 0.0;
-        if (nw >= 2) {
+        if (nw >= 2 && copter) {
+            int leg = 0;
+            while (leg + 2 < nw && start[leg + 1] <= t) ++leg;
+            const double* a = sv->waypoints + 3 * leg;
+            const double* b = sv->waypoints + 3 * (leg + 1);
+            double L = cum[leg + 1] - cum[leg];
+            double T = start[leg + 1] - start[leg];
+            double tau = t - start[leg];
+            if (tau < 0.0) tau = 0.0;
+            if (tau > T) tau = T;
+            double f = copter_leg_distance(L, sv->speed, sv->accel, T, tau) / L;
+            for (int i = 0; i < 3; ++i) pos[i] = a[i] + f * (b[i] - a[i]);
+            if (sv->leg_yaw) {
+                double y0 = sv->leg_yaw[2 * leg], y1 = sv->leg_yaw[2 * leg + 1];
+                yaw = y0 + (tau / T) * (y1 - y0);
+            } else {
+                yaw = atan2(b[1] - a[1], b[0] - a[0]);
+            }
+        } else if (nw >= 2) {
             double sdist = sv->speed * t;
             int leg = 0;
             while (leg + 2 < nw && cum[leg + 1] <= sdist) ++leg;
@@ -1049,6 +1113,7 @@ int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, doub
         w[2] = d[2];
     }
     free(cum);
+    free(start);
     return 0;
 }
 

@@ -1248,6 +1248,51 @@ vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_
     return wave_common(ctx, scanners, n_scanners, pulses, out, stream, 1);
 }
 
+// Multicopter table (Sec. 3.2): per waypoint (x, y, z, start time of the leg
+// that starts there, its duration, its length, its start yaw, its end yaw).  A
+// leg of length L at cruise speed v and acceleration a lasts L / v + v / a when
+// it reaches v (two ramps of v / a, L - v^2 / a at v), else 2 sqrt(L / a).  The
+// last row repeats the last leg's end yaw (the platform stays there).
+static vls_status copter_table(const vls_survey_desc* sv, std::vector<double>& tab)
+{
+    const int nw = sv->n_waypoints;
+    const double v = sv->speed_mps, a = sv->accel_mps2;
+    tab.assign(8 * (size_t)nw, 0.0);
+    double start = 0.0;
+    for (int i = 0; i < nw; ++i) {
+        const double* p = sv->waypoints + 3 * i;
+        for (int c = 0; c < 3; ++c) {
+            if (!std::isfinite(p[c])) return fail(VLS_ERR_INVALID_ARG, "non-finite waypoint");
+            tab[8 * i + c] = p[c];
+        }
+        tab[8 * i + 3] = start;
+        if (i + 1 < nw) {
+            const double* q = sv->waypoints + 3 * (i + 1);
+            const double dx = q[0] - p[0], dy = q[1] - p[1], dz = q[2] - p[2];
+            const double len = std::sqrt(dx * dx + dy * dy + dz * dz);
+            if (!(len > 0.0)) return fail(VLS_ERR_INVALID_ARG, "consecutive waypoints coincide");
+            const double dur = v * v / a <= len ? len / v + v / a : 2.0 * std::sqrt(len / a);
+            double y0, y1;
+            if (sv->leg_yaw) {
+                y0 = sv->leg_yaw[2 * i];
+                y1 = sv->leg_yaw[2 * i + 1];
+                if (!std::isfinite(y0) || !std::isfinite(y1)) return fail(VLS_ERR_INVALID_ARG, "non-finite leg yaw");
+            } else {
+                y0 = y1 = std::atan2(dy, dx);
+            }
+            tab[8 * i + 4] = dur;
+            tab[8 * i + 5] = len;
+            tab[8 * i + 6] = y0;
+            tab[8 * i + 7] = y1;
+            start = start + dur;
+            if (!std::isfinite(start)) return fail(VLS_ERR_INVALID_ARG, "survey too long");
+        } else if (i > 0) {
+            tab[8 * i + 6] = tab[8 * i + 7] = tab[8 * (i - 1) + 7];
+        }
+    }
+    return VLS_OK;
+}
+
 vls_status vls_generate_pulses(vls_context ctx, const vls_survey_desc* sv, int64_t first, int64_t count,
                                double* origins, float* directions, void* stream)
 {
@@ -1265,13 +1310,25 @@ vls_status vls_generate_pulses(vls_context ctx, const vls_survey_desc* sv, int64
             return fail(VLS_ERR_INVALID_ARG, "survey parameters must be finite (speed and noise >= 0)");
         if (sv->deflector == VLS_DEFLECT_FIBRE && sv->n_fibres < 2)
             return fail(VLS_ERR_INVALID_ARG, "a fibre array needs at least two fibres");
+        if (sv->platform != VLS_PLATFORM_LINEAR && sv->platform != VLS_PLATFORM_MULTICOPTER)
+            return fail(VLS_ERR_INVALID_ARG, "unknown platform");
+        const bool copter = sv->platform == VLS_PLATFORM_MULTICOPTER;
+        if (!copter && sv->leg_yaw) return fail(VLS_ERR_INVALID_ARG, "leg_yaw is for the Multicopter platform");
+        if (copter && sv->n_waypoints >= 2 &&
+            !(sv->speed_mps > 0.0 && sv->accel_mps2 > 0.0 && std::isfinite(sv->accel_mps2)))
+            return fail(VLS_ERR_INVALID_ARG, "a moving Multicopter needs speed_mps > 0 and a finite accel_mps2 > 0");
         if (count == 0) return VLS_OK;
         if (!origins || !directions) return fail(VLS_ERR_INVALID_ARG, "origins and directions are required");
         if (!aligned(origins, 8) || !aligned(directions, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned output");
+        const int nw = sv->n_waypoints;
+        std::vector<double> tab;
+        if (copter) {
+            vls_status st = copter_table(sv, tab);
+            if (st != VLS_OK) return st;
+        } else {
         // per-waypoint table: position, cumulative length, cos and sin of the
         // heading of the leg that starts there (host FP64)
-        const int nw = sv->n_waypoints;
-        std::vector<double> tab(6 * (size_t)nw);
+        tab.resize(6 * (size_t)nw);
         double cum = 0.0;
         for (int i = 0; i < nw; ++i) {
             const double* a = sv->waypoints + 3 * i;
@@ -1295,9 +1352,13 @@ vls_status vls_generate_pulses(vls_context ctx, const vls_survey_desc* sv, int64
             tab[6 * i + 4] = nw >= 2 ? std::cos(yaw) : 1.0;
             tab[6 * i + 5] = nw >= 2 ? std::sin(yaw) : 0.0;
         }
+        }
+        // the cache key: the table and its layout
+        std::vector<double> key = tab;
+        key.push_back((double)sv->platform);
         double* dtab = nullptr;
         for (auto& t : ctx->surveys)
-            if (t.key == tab) dtab = t.dev;
+            if (t.key == key) dtab = t.dev;
         if (!dtab) {
             vls_context_s::SurveyTab t;
             VLS_HIP(hipMalloc(&t.dev, sizeof(double) * tab.size()), "survey table");
@@ -1306,7 +1367,7 @@ vls_status vls_generate_pulses(vls_context ctx, const vls_survey_desc* sv, int64
                 (void)hipFree(t.dev);
                 return hip_fail(e, "survey table upload");
             }
-            t.key = tab;
+            t.key = key;
             dtab = t.dev;
             ctx->surveys.push_back(std::move(t));
         }
@@ -1314,7 +1375,8 @@ vls_status vls_generate_pulses(vls_context ctx, const vls_survey_desc* sv, int64
         d.n_wp = nw;
         d.deflector = sv->deflector;
         d.n_fibres = sv->n_fibres;
-        d.pad_ = 0;
+        d.platform = sv->platform;
+        d.accel = sv->accel_mps2;
         d.speed = sv->speed_mps;
         d.prf = sv->pulse_rate_hz;
         d.freq = sv->scan_freq_hz;

@@ -34,6 +34,22 @@ using dev::sm_uniform;
 
 // tab: per waypoint i, [x, y, z, cumulative length, cos yaw, sin yaw] of the
 // leg that starts there (the last entry's yaw is unused).
+// Multicopter leg (Sec. 3.2: speeds up and slows down, stops at each
+// waypoint): distance covered tau in [0, T] seconds into a leg of length L and
+// duration T, from rest to rest at acceleration a and cruise speed v.
+__device__ __forceinline__ double copter_distance(double L, double T, double v, double a, double tau)
+{
+#pragma clang fp contract(off)
+    if (tau <= 0.0) return 0.0;
+    if (tau >= T) return L;
+    const double vmax = v * v / a <= L ? v : sqrt(a * L);  // speed at the end of the ramp
+    const double ramp = vmax / a;
+    if (tau <= ramp) return 0.5 * a * tau * tau;
+    const double rest = T - tau;
+    if (rest <= ramp) return L - 0.5 * a * rest * rest;
+    return 0.5 * a * ramp * ramp + vmax * (tau - ramp);
+}
+
 __global__ __launch_bounds__(256) void k_generate(SurveyDev sv, const double* __restrict__ tab, long long first,
                                                   long long count, double* __restrict__ origins,
                                                   float* __restrict__ dirs)
@@ -45,7 +61,26 @@ __global__ __launch_bounds__(256) void k_generate(SurveyDev sv, const double* __
     const double t = sv.t0 + (double)k / sv.prf;
     double pos[3] = {tab[0], tab[1], tab[2]};
     double cy = 1.0, sy = 0.0;
-    if (sv.n_wp >= 2) {
+    if (sv.n_wp >= 2 && sv.platform == 1) {
+        // the last leg starting at or before t (the first leg before it)
+        int lo = 0, hi = sv.n_wp - 2;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[8 * mid + 3] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const double* a = tab + 8 * lo;
+        const double* b = tab + 8 * (lo + 1);
+        const double T = a[4], L = a[5];
+        double tau = t - a[3];
+        if (tau < 0.0) tau = 0.0;
+        if (tau > T) tau = T;
+        const double f = copter_distance(L, T, sv.speed, sv.accel, tau) / L;
+        for (int i = 0; i < 3; ++i) pos[i] = a[i] + f * (b[i] - a[i]);
+        const double yaw = a[6] + (tau / T) * (a[7] - a[6]);
+        cy = cos(yaw);
+        sy = sin(yaw);
+    } else if (sv.n_wp >= 2) {
         const double sd = sv.speed * t;
         // the last leg whose start lies at or before sd (the first leg before it)
         int lo = 0, hi = sv.n_wp - 2;

@@ -185,8 +185,10 @@ struct SurveyDev {
     int n_wp;
     int deflector;   // 0 polygon, 1 swing, 2 conic, 3 fibre
     int n_fibres;
-    int pad_;
-    double speed, prf, freq, angle, t0, noise;
+    int platform;    // 0 LinearPath: table rows (x, y, z, path length, cos yaw, sin yaw);
+                     // 1 Multicopter: rows (x, y, z, leg start time, leg duration,
+                     //   leg length, start yaw, end yaw)
+    double speed, prf, freq, angle, t0, noise, accel;
     uint64_t seed;
 };
 

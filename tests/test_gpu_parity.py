@@ -794,6 +794,31 @@ def test_generated_pulses_match_oracle(ctx, deflector, noise, static):
     assert np.allclose(np.linalg.norm(d, axis=1), 1.0, atol=3e-7)
 
 
+@pytest.mark.parametrize("yawed", [False, True])
+def test_generated_multicopter_matches_oracle(ctx, yawed):
+    # Sec. 3.2 Multicopter: ramps at every waypoint, and optionally a yaw that
+    # turns across each leg; the pulses run past the end of the path
+    ly = np.array([[0.2, 1.3], [1.3, -0.4], [3.0, 2.0]])[: len(_WP) - 1] if yawed else None
+    sv = dict(waypoints=_WP, deflector="conic", speed_mps=25.0, pulse_rate_hz=4000.0, scan_freq_hz=37.0,
+              scan_angle_rad=0.45, t0_s=0.125, platform_noise_m=0.0, seed=77, platform="multicopter",
+              accel_mps2=12.0, leg_yaw=ly)               # ramps of 2.1 s; the last leg never cruises
+    first, count = 777, 160001
+    o, d = ctx.generate_pulses(sv, first, count)
+    torch.cuda.synchronize()
+    ro, rd = oracle.generate_pulses(dict(sv, t0=sv["t0_s"]), first, count)
+    o = o.cpu().numpy()
+    d = d.cpu().numpy().astype(np.float64)
+    say("multicopter", yawed, "max |do| %.2e max |dd| %.2e" % (np.abs(o - ro).max(), np.abs(d - rd).max()))
+    assert np.abs(o - ro).max() <= 1e-9
+    assert np.abs(d - rd).max() <= 2e-7
+    assert np.array_equal(o[-10:], np.tile(np.array(_WP[-1], float), (10, 1)))
+    import paper_2101_09154_amd as vp
+    with pytest.raises(vp.VlsError):
+        ctx.generate_pulses(dict(sv, accel_mps2=0.0), 0, 10)
+    with pytest.raises(vp.VlsError):
+        ctx.generate_pulses(dict(sv, platform="linear", leg_yaw=np.zeros((len(_WP) - 1, 2))), 0, 10)
+
+
 def test_simulate_on_generated_pulses(ctx):
     # an airborne survey over the small terrain, generated on the device and
     # simulated there; the oracle simulates the same pulses
