@@ -360,6 +360,45 @@ def _assert_batch_equal(a, b, batch, seg_sc, scs, what=""):
             assert np.array_equal(a[k], b[k], equal_nan=True), (what, k)
 
 
+def test_ranging_noise_batched_and_graph(ctx):
+    # a batch of three scanners with their own ranging errors (one without):
+    # draws addressed by the pulse's index in the batch and the return's slot,
+    # the same in graph replays as eagerly, the oracle's per segment
+    mesh, scs0, batch, seg_sc = _small_batch()
+    noise = [(0.05, 3), (0.0, 0), (0.02, 9)]
+    scs = [dict(sc, range_noise_m=m, noise_seed=sd) for sc, (m, sd) in zip(scs0, noise)]
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = _dev(batch.origins)
+    d = _dev(batch.directions)
+    kw = dict(segment_offsets=batch.segment_offsets, segment_scanner=seg_sc)
+    say("ranging noise: batched", batch.n)
+    eager = to_np(ctx.simulate(scene, scs, o, d, **kw))
+    quiet = to_np(ctx.simulate(scene, scs0, o, d, **kw))
+    off = batch.segment_offsets
+    for s in range(seg_sc.size):
+        sl = slice(off[s], off[s + 1])
+        same = np.array_equal(eager["ret_range"][sl], quiet["ret_range"][sl], equal_nan=True)
+        assert same == (noise[seg_sc[s]][0] == 0.0 or quiet["n_returns"][sl].sum() == 0), s
+        assert np.array_equal(eager["waveform"][sl], quiet["waveform"][sl]), s
+        S = len(oracle.pattern(scs[seg_sc[s]])[0])
+        g = {k: (v[:, :S] if k.startswith("subray") else v) for k, v in eager.items()}
+        sel = np.arange(off[s], off[s + 1])[:: max(1, (off[s + 1] - off[s]) // 30)]
+        compare(mesh, batch, scs[seg_sc[s]], g, sel=sel, label="ranging noise segment %d" % s)
+    out = ctx.alloc_outputs(batch.n, 61, 256, 8, o.device)
+    gr = ctx.capture_graph(scene, scs, o, d, out, **kw)
+    for rep in range(3):
+        for v in out.values():
+            v.fill_(-7)
+        say("ranging noise: graph replay", rep)
+        gr.launch()
+        torch.cuda.synchronize()
+        _assert_batch_equal(eager, to_np(out), batch, seg_sc, scs, rep)
+        other = ctx.simulate(scene, scs[0], o[:100], d[:100])
+        torch.cuda.synchronize()
+        assert other["n_returns"].shape == (100,)
+    gr.close()
+
+
 def test_graph_replays_match_eager(ctx):
     mesh, scs, batch, seg_sc = _small_batch()
     scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
