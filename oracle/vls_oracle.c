@@ -1039,6 +1039,11 @@ int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, doub
         const double* b = sv->waypoints + 3 * i;
         double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
         double len = sqrt(dx * dx + dy * dy + dz * dz);
+        if (!(len > 0.0)) { /* consecutive waypoints must differ */
+            free(cum);
+            free(start);
+            return -1;
+        }
         cum[i] = cum[i - 1] + len;
         start[i] = copter ? start[i - 1] + copter_leg_duration(len, sv->speed, sv->accel) : 0.0;
     }

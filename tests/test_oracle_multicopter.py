@@ -156,6 +156,8 @@ def test_multicopter_rejects(orc):
         orc.generate_pulses(_survey(platform="linear", leg_yaw=np.zeros((3, 2))), 0, 10)
     with pytest.raises(ValueError):
         orc.generate_pulses(_survey(leg_yaw=np.zeros((2, 2))), 0, 10)
+    with pytest.raises(ValueError):
+        orc.generate_pulses(_survey(waypoints=[WP[0], WP[1], WP[1], WP[2]]), 0, 10)   # a leg of length 0
     # one waypoint: static whatever the acceleration
     o, _ = orc.generate_pulses(_survey(waypoints=WP[:1], accel_mps2=0.0), 0, 5)
     assert np.array_equal(o, np.tile(WP[0], (5, 1)))
