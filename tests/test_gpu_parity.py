@@ -360,6 +360,32 @@ def _assert_batch_equal(a, b, batch, seg_sc, scs, what=""):
             assert np.array_equal(a[k], b[k], equal_nan=True), (what, k)
 
 
+def test_sixteen_returns(ctx):
+    # the largest number of kept returns: a field of tiles at random heights
+    # under a wide 64-subray beam gives most pulses 16 or more echoes; K = 16
+    # against the oracle, and its first 8 returns are those of K = 8
+    rng = np.random.default_rng(4)
+    tiles = []
+    for i in range(40):
+        for j in range(40):
+            x0, y0 = -10 + 0.5 * i, -10 + 0.5 * j
+            tiles.append(synth.flat_quad(x0, x0 + 0.5, y0, y0 + 0.5, float(rng.uniform(0, 25)),
+                                         float(rng.uniform(0.2, 0.8))))
+    mesh = synth.merge_meshes(tiles)
+    n = 40
+    o = np.stack([rng.uniform(-3, 3, n), rng.uniform(-3, 3, n), np.full(n, 60.0)], 1)
+    pulses = synth.Pulses(o, np.tile([[0.0, 0.0, -1.0]], (n, 1)).astype(np.float32))
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    say("sixteen returns")
+    g16 = run_gpu(ctx, scene, pulses, configs.scanner(0.1, 64, n_bins=1024, bin_ns=0.25, max_returns=16))
+    g8 = run_gpu(ctx, scene, pulses, configs.scanner(0.1, 64, n_bins=1024, bin_ns=0.25, max_returns=8))
+    compare(mesh, pulses, configs.scanner(0.1, 64, n_bins=1024, bin_ns=0.25, max_returns=16), g16, label="K=16")
+    assert (g16["n_returns"] == 16).mean() > 0.3 and (g8["n_returns"] == 8).all()
+    for k in ("ret_range", "ret_amplitude", "ret_tri", "ret_bin"):
+        assert np.array_equal(g16[k][:, :8], g8[k], equal_nan=True), k
+    assert np.array_equal(g16["waveform"], g8["waveform"])
+
+
 def test_ranging_noise_batched_and_graph(ctx):
     # a batch of three scanners with their own ranging errors (one without):
     # draws addressed by the pulse's index in the batch and the return's slot,
