@@ -480,6 +480,39 @@ def main():
                                "achieved_GBps": 36.0 * n / (gen_ms * 1e-3) / 1e9,
                                "step_with_generation_ms": gstep_ms,
                                "subrays_per_s_with_generation": n * S / (gstep_ms * 1e-3) if gstep_ms else None}
+    if not args.only_plain:   # (kept out of the profiled runs: other surveys and scanners)
+        # a Multicopter (Sec. 3.2) flying three legs 100 m above the terrain with
+        # ramps at every waypoint and turning yaws, a Palmer scanner; and the
+        # step with a 2 cm ranging error on every return (Sec. 3.7)
+        log("multicopter generation, ranging error")
+        zc = mesh.info["heights_mean"] + 100.0
+        mc = dict(waypoints=[[0.1 * ext, 0.1 * ext, zc], [0.9 * ext, 0.1 * ext, zc], [0.9 * ext, 0.2 * ext, zc],
+                             [0.1 * ext, 0.2 * ext, zc]],
+                  platform="multicopter", speed_mps=8.0, accel_mps2=2.0,
+                  leg_yaw=[[0.0, 0.3], [1.57, 1.57], [3.14, 2.9]], deflector="conic", pulse_rate_hz=2.0e4,
+                  scan_freq_hz=50.0, scan_angle_rad=math.radians(15.0), platform_noise_m=0.02, seed=7)
+        ctx.generate_pulses(mc, 0, n, origins=go, directions=gd)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.generate_pulses(mc, 0, n, origins=go, directions=gd)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        mc_ms = e0.elapsed_time(e1) / args.steps
+        res["pulse_generation"]["multicopter"] = {
+            "survey": "Multicopter 100 m above mean ground, three legs from rest to rest (8 m/s, 2 m/s^2, "
+                      "turning yaws), Palmer scanner 15 deg, 2e4 pulses/s, platform noise 2 cm",
+            "ms": mc_ms, "pulses_per_s": n / (mc_ms * 1e-3)}
+        scn = dict(sc, range_noise_m=0.02, noise_seed=11)
+        ctx.simulate(scene, scn, o, d, out=out)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.simulate(scene, scn, o, d, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rn_ms = e0.elapsed_time(e1) / args.steps
+        res["ranging_error"] = {"sigma_m": 0.02, "ms": rn_ms, "step_with_ranging_error_over_step": rn_ms / ms}
     if not args.only_plain:   # (kept out of the profiled runs: the same kernel with the lobe on)
         # specular materials (Sec. 5.1): the same step with a Phong-type part on every triangle
         log("specular materials")
