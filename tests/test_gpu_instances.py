@@ -175,6 +175,14 @@ def test_two_level_bitwise_equals_expanded(ctx):
         for k in tr:
             assert np.array_equal(a[k], tr[k], equal_nan=True), (seed, k)
         assert (a["subray_tri"] >= parts[0].n_triangles).mean() > 0.01
+        # a ranging error (Sec. 3.7) is drawn alike on both forms
+        scn = dict(sc, range_noise_m=0.03, noise_seed=seed)
+        an = to_np(ctx.simulate(flat, scn, o, d))
+        bn = to_np(ctx.simulate(two, scn, o, d))
+        torch.cuda.synchronize()
+        for k in an:
+            assert np.array_equal(an[k], bn[k], equal_nan=True), (seed, "noise", k)
+        assert not np.array_equal(an["ret_range"], a["ret_range"], equal_nan=True)
 
 
 def test_two_level_batches_and_limits(ctx):
