@@ -284,8 +284,8 @@ def main():
                     help="only run a plain device copy of MIB MiB (three times), to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: the path has no multi-GPU form in this build "
-              "(pulses shard with no exchange; see the design notes)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU form "
+              "(pulses would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch

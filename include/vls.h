@@ -43,7 +43,7 @@ typedef enum {
     VLS_ERR_OUT_OF_MEMORY = 2, /* a device or host allocation failed                    */
     VLS_ERR_DEVICE = 3,        /* a HIP runtime call or a kernel failed                  */
     VLS_ERR_NOT_BUILT = 4,     /* reserved                                               */
-    VLS_ERR_UNSUPPORTED = 5,   /* valid request outside what this build handles          */
+    VLS_ERR_UNSUPPORTED = 5,   /* valid request outside what the library handles         */
     VLS_ERR_INTERNAL = 6       /* a C++ exception or an invariant failure inside the lib */
 } vls_status;
 
