@@ -199,7 +199,7 @@ vls_status vls_scene_update_reflectance(vls_scene scene, const float* reflectanc
  *             of the first stop and the closest triangle is the hit (a voxel
  *             stop at the triangle's distance wins);
  *   echo    subray_tri = n_triangles + voxel index, subray_cos = 1,
- *             subray_power = eta sigma P0 w D^2 / (4 pi R^4 beta^2) (Eq. 8 with
+ *             subray_power = eta sigma P0 w D^2 / (4 pi R^4 beta^2) (Eq. 7 with
  *             the proportionality taken as equality; beta the full divergence,
  *             which must then be > 0); waveforms and returns take voxel echoes
  *             like triangle echoes, and ret_tri reports their ids alike.

@@ -408,7 +408,7 @@ vls_status check_scene(vls_context ctx, vls_scene scene, const Prepared& pr, boo
     if (scene->vox.n_vox > 0)
         for (const auto& s : pr.sc)
             if (!(s.vox_c < INFINITY))
-                return fail(VLS_ERR_INVALID_ARG, "a scene with voxels needs scanners of divergence > 0 (Eq. 8)");
+                return fail(VLS_ERR_INVALID_ARG, "a scene with voxels needs scanners of divergence > 0 (Eq. 7)");
     int limit = ctx->cfg.stack_lds + kMaxSpill - 1;
     if (scene->stats.max_depth > limit) {
         char b[128];

@@ -728,7 +728,7 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
                               visits, tests);
         if (VOX && ray_ok) {
             // a voxel that stops the subray before its closest triangle takes the
-            // echo: id n_tri + voxel, cos 1, power by Eq. 8 (proportionality as
+            // echo: id n_tri + voxel, cos 1, power by Eq. 7 (proportionality as
             // equality): P = power_c w sigma / (pi beta^2 R^4)
             double tv, sg;
             const uint64_t c0 = ((uint64_t)p * kWave + (uint64_t)k) * (uint64_t)scene.vox.n_vox;

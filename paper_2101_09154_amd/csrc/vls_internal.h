@@ -66,7 +66,7 @@ struct ScannerDev {
     double tan_max;         // tan of the largest subray angle (outer ring)
     double range_noise;     // ranging error's standard deviation (m), 0: none
     unsigned long long noise_seed;
-    double vox_c;           // voxel echoes (Eq. 8): power_c / (pi beta^2), beta the full divergence
+    double vox_c;           // voxel echoes (Eq. 7): power_c / (pi beta^2), beta the full divergence
 };
 
 // A transmissive voxel grid (see voxels.h); n_vox == 0: none.

@@ -1,6 +1,6 @@
 """GPU parity of transmissive voxels (Sec. 3.5.4, Sec. 5.2) through the C ABI
 against the FP64 oracle, at the tolerances of parity_util (a voxel echo against
-anything else only at a tie in distance; Eq. 8's power to 1e-6 relative).
+anything else only at a tie in distance; Eq. 7's power to 1e-6 relative).
 
 The draws are addressed by (pulse index in the call's batch, subray, voxel), so
 the oracle is always run on the whole batch with a selection, never on a
@@ -232,7 +232,7 @@ def test_voxel_api_errors(ctx):
         scene.set_voxels(vox["origin"], vox["size"], vox["pad"], vox["lut"])        # one grid per scene
     o, d = _dev(pulses.origins[:10]), _dev(pulses.directions[:10])
     with pytest.raises(vp.VlsError):
-        ctx.simulate(scene, dict(SLAB_SC, divergence_rad=0.0, n_subrays=1), o, d)  # Eq. 8 needs beta > 0
+        ctx.simulate(scene, dict(SLAB_SC, divergence_rad=0.0, n_subrays=1), o, d)  # Eq. 7 needs beta > 0
     bad = [dict(pad=-vox["pad"]), dict(pad=np.full_like(vox["pad"], np.nan)),
            dict(lut=[[0.5, 0.4], [0.2, 0.6]]), dict(lut=[[0.0, -0.1]]), dict(size=0.0),
            dict(pad=np.zeros((0, 3, 3), np.float32))]

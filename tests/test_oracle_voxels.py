@@ -1,7 +1,7 @@
 """Pins of the oracle's transmissive voxels (Sec. 3.5.4 and Sec. 5.2: extinction
 from plant area density through a leaf-angle table (Eq. 5, Table 2), a random
 depth s = -ln(u) / sigma (Eq. 6), continuation through the voxels along the ray
-(Sec. 5.1), echo power by Eq. 8)."""
+(Sec. 5.1), echo power by Eq. 7)."""
 import math
 import os
 
@@ -125,7 +125,7 @@ def test_triangle_in_front_wins(orc):
 
 def test_voxel_echo_power_and_ids(orc):
     # a scene of one far plane behind a voxel slab: subrays that stop in a voxel
-    # report id n_tri + voxel, cos 1 and the power of Eq. 8
+    # report id n_tri + voxel, cos 1 and the power of Eq. 7
     plane = synth.flat_quad(-50.0, 50.0, -50.0, 50.0, 0.0, reflectance=0.5)
     pad = np.full((2, 4, 4), 0.4, np.float32)
     vox = _grid(pad, size=2.0, origin=(-4.0, -4.0, 10.0), lut=[[0.0, 0.3], [1.0, 0.7]], seed=11)
