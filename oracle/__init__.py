@@ -99,6 +99,8 @@ def lib():
         L.orc_window_pre.restype = ctypes.c_double
         L.orc_peak_offset.argtypes = [P]
         L.orc_peak_offset.restype = ctypes.c_double
+        L.orc_echo_range.argtypes = [P, ctypes.c_double, ctypes.c_int]
+        L.orc_echo_range.restype = ctypes.c_double
         L.orc_detect_peaks.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, P]
         L.orc_echo_width_bins.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_double, P]
         L.orc_echo_width_bins.restype = ctypes.c_double
@@ -218,9 +220,18 @@ def peak_offset(sc):
     return float(lib().orc_peak_offset(ctypes.byref(st)))
 
 
+def echo_range(sc, t0, j):
+    """Range (m) of a return at bin j of a window starting at t0 (ns), without ranging error."""
+    st = scanner_struct(sc)
+    return float(lib().orc_echo_range(ctypes.byref(st), float(t0), int(j)))
+
+
 def detect_peaks(wf, thr_abs=0.0, thr_rel=1e-3, K=8):
+    """The first K local maxima of a waveform in time order (K >= the number of
+    bins gives all of them)."""
     wf = np.ascontiguousarray(wf, dtype=np.float64)
-    bins = np.zeros(64, np.int32)
+    K = max(0, min(int(K), wf.size))
+    bins = np.zeros(max(K, 1), np.int32)
     n = lib().orc_detect_peaks(_ptr(wf), wf.size, float(thr_abs), float(thr_rel), int(K), _ptr(bins))
     return bins[:n].copy()
 

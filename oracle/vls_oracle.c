@@ -34,7 +34,7 @@
  *   9. optionally, transmissive voxels (Sec. 3.5.4, Sec. 5.2): a subray crossing
  *      a voxel of plant area density PAD stops in it at a random depth drawn
  *      from the extinction coefficient (Eq. 5 through a leaf-angle table, Eq. 6),
- *      with the echo power of Eq. 8;
+ *      with the echo power of Eq. 7;
  *   9b. optionally, a ranging error on each return's distance (Sec. 3.7);
  *  10. optionally, a Phong-type specular part of each triangle's response
  *      (Sec. 5.1: materials carry reflectance and specularity);
@@ -304,6 +304,15 @@ double orc_window_pre(const orc_scanner* sc)
 
 double orc_peak_offset(const orc_scanner* sc) { return sc->pulse_shape == ORC_PULSE_EQ3 ? 2.0 * eq3_tau(sc) : 0.0; }
 
+/* Range of a return at bin j of a window starting at t0 (Sec. 3.4: the point's
+ * position along the range axis comes from the local maximum): half the
+ * two-way time of the bin, less the pulse's own peak offset, times c. */
+double orc_echo_range(const orc_scanner* sc, double t0, int j)
+{
+    double tj = t0 + (double)j * sc->bin_ns;
+    return 0.5 * ORC_C_M_PER_NS * (tj - orc_peak_offset(sc));
+}
+
 /* ------------------------------------------------------------------ returns (Sec. 3.4) */
 
 int orc_detect_peaks(const double* wf, int n, double thr_abs, double thr_rel, int K, int32_t* bins)
@@ -361,7 +370,7 @@ static double power_const(const orc_scanner* sc)
  *            1987) in FP64; the nearest of the first stopping voxel and the
  *            closest triangle is the hit (Sec. 5.1: consecutive intersections
  *            along the ray);
- *   power    Eq. 8 with the proportionality taken as equality:
+ *   power    Eq. 7 with the proportionality taken as equality:
  *            P = eta * sigma * P0 w D^2 / (4 pi R^4 beta^2), beta the full
  *            divergence, R the hit distance; cos is reported as 1;
  *   id       a voxel hit is reported as triangle id n_tri + voxel index. */
@@ -508,7 +517,7 @@ static void trace_pulse(const orc_ctx* c, int64_t pulse, const double O[3], cons
                           (uint64_t)((int64_t)c->vox->nx * c->vox->ny * c->vox->nz);
             int64_t vi = orc_voxel_hit(c->vox, O, dk, h >= 0 ? t : INFINITY, c0, &tv, &sg);
             if (vi >= 0) {
-                /* Eq. 8, proportionality taken as equality */
+                /* Eq. 7, proportionality taken as equality */
                 double beta = c->sc->divergence_rad;
                 double Dm = c->sc->receiver_diameter_m;
                 tri[k] = (int32_t)(c->n_tri + vi);
@@ -582,7 +591,7 @@ static void waveform_pulse(const orc_ctx* c, int64_t pulse, const int32_t* tri, 
         int bk = orc_attribute(sc, tri, R, P, c->S, tj);
         ret_bin[r] = j;
         ret_amp[r] = wf[j];
-        ret_range[r] = 0.5 * ORC_C_M_PER_NS * (tj - orc_peak_offset(sc)) + orc_range_noise(sc, pulse, r);
+        ret_range[r] = orc_echo_range(sc, t0, j) + orc_range_noise(sc, pulse, r);
         ret_tri[r] = bk >= 0 ? tri[bk] : -1;
     }
 }

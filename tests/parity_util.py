@@ -6,12 +6,14 @@ within 1e-6 (barycentric) of an edge of either triangle, or the two hit
 distances agree to 1e-6 relative (a depth tie).  A miss against a hit is
 excused only at an edge of the hit triangle.  A voxel echo (id >= n_triangles)
 against anything else is excused only where the two distances agree to 1e-6
-relative; equal voxel echoes carry Eq. 8's power to 1e-6 relative and cos 1.
+relative; equal voxel echoes carry Eq. 7's power to 1e-6 relative and cos 1.
 Range: <= 1e-4 m on equal ids.
 Waveform: per-pulse relative L2 <= 1e-5 for pulses whose ids all match;
 all-miss pulses are all zero.
-Returns: equal counts and bins except where the oracle's waveform has a near
-tie (|wf[j] - wf[j +- 1]| or |wf[j] - thr| <= 1e-5 max wf) at a differing bin.
+Returns: the GPU's bins are the oracle's first bins in time order (all of them
+when the GPU kept fewer than K) except where the oracle's waveform has a near
+tie (|wf[j] - wf[j +- 1]| or |wf[j] - thr| <= 1e-5 max wf) at a differing bin;
+range, amplitude and attribution on every bin both sides report.
 """
 import numpy as np
 
@@ -93,7 +95,7 @@ def check_hits(mesh, pulses, sc, sel, g, r, report):
     power_ok = True
     vm = eq & (r.sub_tri >= nt)
     if vm.any() and "subray_power" in g:
-        # voxel echoes: Eq. 8's power, rounded once to FP32 by the GPU
+        # voxel echoes: Eq. 7's power, rounded once to FP32 by the GPU
         rel = np.abs(g["subray_power"][:, :S][vm] - r.sub_power[vm]) / r.sub_power[vm]
         report["voxel_echoes"] = int(vm.sum())
         report["voxel_power_rel_err"] = float(rel.max())
@@ -129,45 +131,85 @@ def _near_tie(w, j, thr, scale):
 
 
 def check_returns(g, r, sc, report):
+    """Returns of every pulse whose subray ids all match the oracle's.
+
+    The oracle's complete list of local maxima comes from its own FP64
+    waveform (its peak rule with no cap on the count); its K-limited returns
+    must be the prefix of that list (first K in time order).  The GPU keeps
+    the first K in time order too, so its bins must equal the oracle's bins up
+    to the GPU's last kept bin (all of them when it kept fewer than K), except
+    at near ties of the oracle's waveform.  Every GPU return whose bin the
+    oracle also has is compared, whether or not either side reached K: range
+    (1e-4 m), amplitude (1e-5 of the waveform's maximum) and attribution.  With
+    a ranging error only slots drawn alike on both sides compare ranges.
+    """
     S = r.S
     K = sc.get("max_returns", 8)
+    thr_abs, thr_rel = sc.get("min_echo_abs", 0.0), sc.get("min_echo_rel", 1e-3)
+    noisy = sc.get("range_noise_m", 0.0) > 0.0
     allmatch = np.all(g["subray_tri"][:, :S] == r.sub_tri, axis=1)
     bad = []
     tri_bad = []
+    n_sat = n_cmp = n_pulses = 0
     for q in np.nonzero(allmatch)[0]:
+        n_pulses += 1
         ng, no = int(g["n_returns"][q]), int(r.n_returns[q])
-        bg = list(g["ret_bin"][q, :ng])
-        bo = list(r.ret_bin[q, :no])
         w = r.waveform[q]
         mx = w.max() if w.size else 0.0
-        thr = max(sc.get("min_echo_abs", 0.0), sc.get("min_echo_rel", 1e-3) * mx)
-        if bg != bo:
-            diff = set(bg) ^ set(bo)
-            if not all(_near_tie(w, j, thr, mx) for j in diff) and not (ng == K or no == K):
-                bad.append(int(q))
+        thr = max(thr_abs, thr_rel * mx)
+        full = [int(b) for b in oracle.detect_peaks(w, thr_abs, thr_rel, K=w.size)]
+        if [int(b) for b in r.ret_bin[q, :no]] != full[:K] or no != min(len(full), K):
+            bad.append(int(q))  # the oracle's K-limited list is not its prefix
             continue
-        if ng:
-            if np.max(np.abs(g["ret_range"][q, :ng] - r.ret_range[q, :ng])) > RANGE_TOL:
+        bg = [int(b) for b in g["ret_bin"][q, :ng]]
+        if ng < 0 or ng > K or any(bg[i] >= bg[i + 1] for i in range(ng - 1)):
+            bad.append(int(q))
+            continue
+        if ng == K or no == K:
+            n_sat += 1
+        ref = full if ng < K else [b for b in full if b <= bg[-1]]
+        diff = set(bg) ^ set(ref)
+        if not all(_near_tie(w, j, thr, mx) for j in diff):
+            bad.append(int(q))
+        pos = {b: i for i, b in enumerate(full)}
+        for s in range(ng):
+            j = bg[s]
+            so = pos.get(j)
+            if so is None:
+                continue  # a near-tie bin the oracle does not have
+            n_cmp += 1
+            if abs(float(g["ret_amplitude"][q, s]) - w[j]) > 1e-5 * mx:
                 bad.append(int(q))
-            if np.max(np.abs(g["ret_amplitude"][q, :ng] - r.ret_amp[q, :ng])) > 1e-5 * mx:
+            if so < no:
+                rr = None if noisy and so != s else float(r.ret_range[q, so])
+            else:
+                rr = None if noisy else oracle.echo_range(sc, r.t0[q], j)
+            if rr is not None and abs(float(g["ret_range"][q, s]) - rr) > RANGE_TOL:
                 bad.append(int(q))
-            for s in range(ng):
-                if g["ret_tri"][q, s] != r.ret_tri[q, s]:
-                    tri_bad.append((int(q), s))
+            if so < no:
+                to = int(r.ret_tri[q, so])
+            else:
+                kb = oracle.attribute(sc, r.sub_tri[q], r.sub_range[q], r.sub_power[q], r.t0[q] + j * sc["bin_ns"])
+                to = int(r.sub_tri[q, kb]) if kb >= 0 else -1
+            if int(g["ret_tri"][q, s]) != to:
+                tri_bad.append((int(q), s, j))
         if np.any(g["ret_bin"][q, ng:K] != -1) or np.any(g["ret_tri"][q, ng:K] != -1):
             bad.append(int(q))
-    report["returns_bad"] = bad[:20]
-    report["returns_bad_n"] = len(bad)
+    report["returns_pulses"] = n_pulses
+    report["returns_saturated"] = n_sat
+    report["returns_compared"] = n_cmp
+    report["returns_bad"] = sorted(set(bad))[:20]
+    report["returns_bad_n"] = len(set(bad))
     report["ret_tri_mismatch"] = len(tri_bad)
     return not bad, tri_bad
 
 
 def attribution_excused(mesh, pulses, sc, sel, g, r, tri_bad):
     """A differing return attribution is excused when the GPU's triangle carries a
-    subray whose contribution at the bin is within 1e-5 of the largest."""
+    subray whose contribution at the bin is within 1e-5 of the largest.
+    tri_bad: (row, GPU slot, bin) of each differing attribution."""
     left = []
-    for q, s in tri_bad:
-        j = int(r.ret_bin[q, s])
+    for q, s, j in tri_bad:
         tj = r.t0[q] + j * sc["bin_ns"]
         contrib = np.array([r.sub_power[q, k] * oracle.pulse_value(sc, tj - 2 * r.sub_range[q, k] / C)
                             if r.sub_tri[q, k] >= 0 else -1.0 for k in range(r.S)])

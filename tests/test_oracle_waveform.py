@@ -200,3 +200,44 @@ def test_attribution_rule(orc):
     assert orc.attribute(sc, [-1, -1, -1, -1], R, [3.0, 3.0, 3.0, 0.0], tj) == -1
     # far in time from its own echo a strong subray loses to a weak one on time
     assert orc.attribute(sc, [5, 6, 7, 8], R, [1.0, 0.0, 0.0, 100.0], tj) == 0
+
+
+def test_returns_are_prefix_of_larger_k(orc):
+    # Sec. 3.4: the first K local maxima in time order are kept, so the returns
+    # of a K-limited run are the first ones of any run with a larger K
+    rng = np.random.default_rng(4)
+    tiles = []
+    for i in range(12):
+        for j in range(12):
+            x0, y0 = -3 + 0.5 * i, -3 + 0.5 * j
+            tiles.append(synth.flat_quad(x0, x0 + 0.5, y0, y0 + 0.5, float(rng.uniform(0, 25)),
+                                         float(rng.uniform(0.2, 0.8))))
+    m = synth.merge_meshes(tiles)
+    n = 6
+    o = np.stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), np.full(n, 60.0)], 1)
+    p = synth.Pulses(o, np.tile([[0.0, 0.0, -1.0]], (n, 1)).astype(np.float32))
+    kw = dict(n_bins=1024, bin_ns=0.25)
+    r4 = orc.simulate(m, p, configs.scanner(0.1, 64, max_returns=4, **kw))
+    r16 = orc.simulate(m, p, configs.scanner(0.1, 64, max_returns=16, **kw))
+    assert (r4.n_returns == 4).all() and (r16.n_returns > 4).all()
+    for a, b in ((r4.ret_bin, r16.ret_bin), (r4.ret_range, r16.ret_range), (r4.ret_amp, r16.ret_amp),
+                 (r4.ret_tri, r16.ret_tri)):
+        assert np.array_equal(a, b[:, :4])
+    assert np.array_equal(r4.waveform, r16.waveform)
+    # the uncapped list of the waveform's maxima starts with the kept ones
+    for q in range(n):
+        full = orc.detect_peaks(r16.waveform[q], K=r16.waveform.shape[1])
+        assert list(full[:r16.n_returns[q]]) == list(r16.ret_bin[q, :r16.n_returns[q]])
+        # ranges of returns past the kept ones come from the same rule
+        assert orc.echo_range(configs.scanner(0.1, 64, max_returns=16, **kw), r16.t0[q], int(full[0])) == \
+            r16.ret_range[q, 0]
+
+
+def test_echo_range_of_bin(orc):
+    # a return at bin j lies at half the two-way time of the bin, less the
+    # pulse's peak offset (0 for the Gaussian, 2 tau for Eq. 3)
+    sc = configs.scanner(0.5e-3, 1, bin_ns=0.5)
+    assert orc.echo_range(sc, 1000.0, 10) == pytest.approx(0.5 * C * 1005.0, rel=1e-15)
+    L = 4.0
+    sc3 = configs.scanner(0.5e-3, 1, bin_ns=0.5, pulse_shape="eq3", pulse_width_ns=L)
+    assert orc.echo_range(sc3, 1000.0, 10) == pytest.approx(0.5 * C * (1005.0 - 2 * L / 1.75), rel=1e-15)
