@@ -1,12 +1,18 @@
-"""Compile the HIP library (gfx950) in-tree: paper_2101_09154_amd/libvls.so."""
+"""Compile the HIP library (gfx950) in-tree: paper_2101_09154_amd/libvls.so.
+
+Each source is compiled to its own object in parallel (no device code crosses
+translation units), then the objects are linked into the shared library.
+"""
 import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libvls.so")
+OBJ_DIR = os.path.join(ROOT, "_build", "vls")
 ARCH = os.environ.get("VLS_OFFLOAD_ARCH", "gfx950")
 
 
@@ -14,19 +20,42 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) + glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
 
 
-def build(verbose=False):
+def _flags():
+    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+            "-I" + os.path.join(ROOT, "include"),
+            # packed FP32 instructions are disabled on purpose for every HIP source
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def build(verbose=False, jobs=None):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    srcs = sources()
+    objs = [os.path.join(OBJ_DIR, os.path.basename(s) + ".o") for s in srcs]
+
+    def compile_one(pair):
+        src, obj = pair
+        cmd = [hipcc] + _flags() + ["-c", "-o", obj + ".tmp", src]
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            return src, r.stderr[-8000:]
+        os.replace(obj + ".tmp", obj)
+        return src, None
+
+    jobs = jobs or min(len(srcs), max(1, min(os.cpu_count() or 1, 16)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for src, err in ex.map(compile_one, zip(srcs, objs)):
+            if err is not None:
+                raise RuntimeError("hipcc failed on %s:\n%s" % (os.path.basename(src), err))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-I" + os.path.join(ROOT, "include"),
-           # packed FP32 instructions are disabled on purpose for every HIP source
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-o", tmp] + sources()
+    cmd = [hipcc, "--offload-arch=" + ARCH, "-fPIC", "-shared", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + r.stderr[-8000:])
+        raise RuntimeError("link failed:\n" + r.stderr[-8000:])
     os.replace(tmp, LIB)
     return LIB
 
