@@ -80,7 +80,10 @@ vls_status vls_context_destroy(vls_context ctx);
  *               by vls_scene_create)
  *   reflectance [n_triangles] float32
  *   memory      where the three arrays live: VLS_MEM_HOST or VLS_MEM_DEVICE.
- * n_triangles may be 0 (every subray misses). */
+ * n_triangles may be 0 (every subray misses).
+ * There is no per-triangle object id: returns carry the index of the triangle
+ * they are attributed to (ret_tri, an index into `triangles`), so a caller that
+ * groups triangles into objects looks the object up as object_id[ret_tri]. */
 typedef struct {
     const float* vertices;
     const int32_t* triangles;

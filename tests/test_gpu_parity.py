@@ -12,6 +12,7 @@ import pytest
 import oracle
 import synth
 from synth import configs
+import parity_summary
 from parity_util import (attribution_excused, check_hits, check_returns, check_waveforms, to_np)
 
 torch = pytest.importorskip("torch")
@@ -54,6 +55,7 @@ def compare(mesh, pulses, sc, g, sel=None, label=""):
     left = attribution_excused(mesh, pulses, sc, sel, gs, r, tri_bad)
     rep["attribution_unexcused"] = left[:10]
     say(label, rep)
+    parity_summary.record(label, sel.size, r.S, rep)
     assert ok_h, rep
     assert ok_w, rep
     assert ok_r, rep
@@ -320,7 +322,10 @@ def test_als_buildings_sampled(ctx):
     say("als_buildings stats", scene.stats())
     g = run_gpu(ctx, scene, pulses, sc)
     rng = np.random.default_rng(11)
-    sel = np.sort(rng.choice(pulses.n, 48, replace=False))
+    # 2,000 pulses (62,000 subrays): one unexcused id mismatch already reads
+    # below 99.99 %, and the oracle's brute force over 2.33M triangles stays
+    # near a minute on 16 host threads
+    sel = np.sort(rng.choice(pulses.n, 2000, replace=False))
     # a few pulses at the swath edges (partial and total misses)
     sel = np.unique(np.concatenate([sel, [0, 999, 500500, 999999]]))
     compare(mesh, pulses, sc, g, sel=sel, label="als_buildings")
@@ -636,7 +641,7 @@ def test_uls_trees_sampled(ctx):
     rng = np.random.default_rng(5)
     x_land = pulses.origins[:, 0] - pulses.directions[:, 0] / pulses.directions[:, 2] * 60.0
     inside = np.nonzero((x_land > 10) & (x_land < 190))[0]
-    sel = np.sort(rng.choice(inside, 12, replace=False))
+    sel = np.sort(rng.choice(inside, 200, replace=False))
     g = _rows(out, sel)
     sub = pulses.subset(sel)
     rep = compare(mesh, sub, sc, g, label="uls_trees")
@@ -665,9 +670,9 @@ def test_batched_full_sampled(ctx):
         torch.cuda.synchronize()
         for k in out:
             assert torch.equal(out[k][a:b].nan_to_num(-1), alone[k].nan_to_num(-1)), (s, k)
-        sel = np.sort(rng.choice(np.arange(a, b), 3, replace=False))
+        sel = np.sort(rng.choice(np.arange(a, b), 100, replace=False))
         g = _rows(alone, sel - a)
-        compare(mesh, pulses.subset(sel), scs[typ], g, label="batched segment %d" % s)
+        compare(mesh, pulses.subset(sel), scs[typ], g, label="batched_tls S=%d seg %d" % (len(oracle.pattern(scs[typ])[0]), s))
 
 
 def test_gradient_full_sampled(ctx):
