@@ -48,9 +48,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_hash):
-    """HBM bytes per launch from the committed PMC summary, if it was taken on this source."""
-    path = os.path.join(ROOT, "profiles", "simulate_als_buildings_pmc.md")
+def traffic_record(workload, kernel_hash):
+    """The traffic-json record of the committed PMC summary of a workload, if it
+    was taken on this device code (else None)."""
+    path = os.path.join(ROOT, "profiles", "simulate_%s_pmc.md" % workload)
     if not os.path.exists(path):
         return None
     rec = None
@@ -59,7 +60,126 @@ def measured_traffic(kernel_hash):
             rec = json.loads(line.split(":", 1)[1])
     if not rec or rec.get("source_hash") != kernel_hash:
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def measured_traffic(kernel_hash):
+    """HBM bytes per launch of the fused kernel on the ALS workload, from its PMC summary."""
+    rec = traffic_record("als_buildings", kernel_hash)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def input_digest(mesh, pulses, sc, seed):
+    """SHA-256 of the arrays a step reads (scene, pulses, segments) and of the
+    scanner descriptions, with the generator seed they came from."""
+    h = hashlib.sha256()
+    arrays = [mesh.vertices, mesh.triangles, mesh.reflectance, pulses.origins, pulses.directions]
+    if getattr(pulses, "segment_offsets", None) is not None:
+        arrays += [pulses.segment_offsets, pulses.segment_scanner]
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    h.update(json.dumps(sc, sort_keys=True).encode())
+    return {"sha256": h.hexdigest(), "seed": seed}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def copy_bandwidth(mib=1024, reps=5):
+    """A plain device-to-device copy of `mib` MiB, timed with events: bytes read
+    plus bytes written per second (the measured counterpart of the 8 TB/s peak)."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = time_ms(lambda: dst.copy_(src), reps, 2, torch.cuda.current_stream())
+    del src, dst
+    return {"bytes_per_copy": 2 * 4 * n, "ms": ms, "GBps": 2 * 4 * n / (ms * 1e-3) / 1e9,
+            "what": "torch copy_ of %d MiB on the device, read + write, mean of %d" % (mib, reps)}
+
+
+def candidate_census(ctx, scene, sc, o, d, chunk=131072):
+    """Per-pulse candidate lists of the cone pass, in chunks: (candidates summed
+    over the pulses with a list, pulses whose list overflowed)."""
+    import torch
+    total = 0
+    over = 0
+    rows = None
+    for a in range(0, o.shape[0], chunk):
+        b = min(a + chunk, o.shape[0])
+        if rows is None or rows.shape[0] != b - a:
+            rows = torch.empty((b - a, 256), dtype=torch.int32, device=o.device)
+        ctx.cone_candidates(scene, sc, o[a:b], d[a:b], out=rows)
+        c = rows[:, 0]
+        total += int(c.clamp(min=0).sum().item())
+        over += int((c < 0).sum().item())
+    return total, over
+
+
+def bench_plain(ctx, name, label, mesh, pulses, sc, steps, seed, hbm=True):
+    """One scanner's step on a whole workload: step time and rates, the kernels'
+    times, the fused kernel's algorithmic bytes (candidate records once per
+    pulse), and, when a PMC summary of this workload was taken on this device
+    code, each kernel's measured HBM traffic and rate."""
+    import torch
+    import paper_2101_09154_amd as vp
+    dev = torch.device("cuda", 0)
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    o = torch.from_numpy(pulses.origins).to(dev)
+    d = torch.from_numpy(pulses.directions).to(dev)
+    n = pulses.n
+    S = vp.n_subrays(sc)
+    K = sc["max_returns"]
+    nb = sc["n_bins"]
+    out = ctx.alloc_outputs(n, S, nb, K, dev, subrays=False)
+    stream = torch.cuda.current_stream()
+    cand, n_over = candidate_census(ctx, scene, sc, o, d)
+    ms = time_ms(lambda: ctx.simulate(scene, sc, o, d, out=out), steps, 2, stream)
+    ctx.profile(True)
+    for _ in range(steps):
+        ctx.simulate(scene, sc, o, d, out=out)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    fused_ms = prof["fused_ms"] / max(prof["fused_launches"], 1)
+    cone_ms = prof["cone_ms"] / max(prof["cone_launches"], 1)
+    packet_ms = prof["packet_ms"] / max(prof["packet_launches"], 1)
+    per_pulse_io = 36.0 + 4.0 * nb + 8.0 + 4.0 + 16.0 * K
+    # fused kernel: pulse in, count, each listed candidate's id and 48 B record
+    # once per pulse; a pulse that overflowed reads one leaf per subray (the
+    # packet walk's result); a reflectance per subray; outputs out
+    fused_bytes = n * (per_pulse_io + 4.0) + 52.0 * cand + 52.0 * S * n_over + 4.0 * n * S
+    scene_bytes = 112.0 * max(mesh.n_triangles - 1, 1) + 52.0 * mesh.n_triangles
+    res = {"workload": label, "pulses": n, "subrays_per_pulse": S, "n_bins": nb, "max_returns": K,
+           "triangles": mesh.n_triangles, "inputs": input_digest(mesh, pulses, sc, seed),
+           "ms": ms, "subrays_per_s": n * S / (ms * 1e-3), "pulses_per_s": n / (ms * 1e-3),
+           "candidates_per_listed_pulse": cand / max(n - n_over, 1), "overflowed_pulses": n_over,
+           "kernels": {"cone_ms": cone_ms, "packet_ms": packet_ms, "fused_ms": fused_ms},
+           "fused": {"algorithmic_bytes_per_launch": fused_bytes,
+                     "achieved_GBps": fused_bytes / (fused_ms * 1e-3) / 1e9},
+           "scene_bytes": scene_bytes,
+           "timing": "HIP events: step = mean of %d simulate calls; kernels recorded by the library around "
+                     "each launch on its stream" % steps}
+    if hbm:
+        res["fused"]["frac"] = res["fused"]["achieved_GBps"] / HBM_PEAK_GBS
+        rec = traffic_record(name, source_hash())
+        if rec:
+            for kern, t in (("fused", fused_ms), ("cone", cone_ms), ("packet", packet_ms)):
+                b = rec.get(kern + "_bytes_per_launch")
+                if b:
+                    res.setdefault("traffic", {})[kern] = {
+                        "bytes_per_launch": b, "GBps": b / (t * 1e-3) / 1e9,
+                        "frac": b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    else:
+        res["fused"]["level"] = "L2: the scene and the candidate records stay in the caches"
+    scene.close()
+    return res
 
 
 def cpu_baseline(mesh, pulses, sc, target_s):
@@ -269,6 +389,42 @@ def bench_instanced(ctx, steps):
     return res
 
 
+def run_leg(ctx, leg, steps, tune=True):
+    """The vegetation workload (2,000 trees, ~10M triangles, 2M ULS pulses, 61
+    subrays, K = 8; scene larger than the caches, so HBM-level figures) or the
+    small terrestrial one (7,938 triangles, 10,000 pulses, 19 subrays; the scene
+    stays in L2, so L2-level figures), each with its own tuned launch."""
+    import torch
+    from synth import configs
+    import paper_2101_09154_amd as vp
+    cfg0 = ctx.launch_config()
+    if leg == "uls_trees":
+        mesh, pulses, sc = configs.uls_trees()
+        label = ("uls_trees: 2,000 procedural trees on a 200 x 200 m fBm DTM (%d triangles), 2,000,000 ULS "
+                 "pulses at 60 m AGL, 61 subrays, 512 x 0.5 ns bins, K=8" % mesh.n_triangles)
+        seed, hbm = configs.ULS_SEED, True
+    else:
+        mesh, pulses, sc = configs.small_tls()
+        label = ("small_tls: 64 x 64 value-noise DTM at 1 m (7,938 triangles), 10,000 TLS pulses on a 100 x 100 "
+                 "grid, 19 subrays, 256 x 1 ns bins, K=8")
+        seed, hbm = configs.SMALL_SEED, False
+    tuned = None
+    if tune:
+        scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+        o = torch.from_numpy(pulses.origins).cuda()
+        d = torch.from_numpy(pulses.directions).cuda()
+        out = ctx.alloc_outputs(pulses.n, vp.n_subrays(sc), sc["n_bins"], sc["max_returns"], o.device,
+                                subrays=False)
+        tuned = ctx.autotune(scene, sc, o, d, out)
+        scene.close()
+        del o, d, out
+    res = bench_plain(ctx, leg, label, mesh, pulses, sc, steps, seed, hbm=hbm)
+    res["launch"] = ctx.launch_config()
+    res["autotune"] = tuned
+    ctx.set_launch_config(**cfg0)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +438,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (three times), to scale HBM counters")
+    ap.add_argument("--leg", choices=["uls_trees", "small_tls"], default=None,
+                    help="only run this workload's leg and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU form "
@@ -301,6 +459,12 @@ def main():
     from synth import configs
     import paper_2101_09154_amd as vp
 
+    if args.leg:
+        ctx = vp.Context(0)
+        if not args.no_tune:
+            log("autotune (%s)" % args.leg)
+        print(json.dumps(run_leg(ctx, args.leg, args.steps, tune=not args.no_tune)), flush=True)
+        return
     log("generating scene and pulses")
     mesh, pulses, sc = configs.als_buildings()
     dev = torch.device("cuda", 0)
@@ -534,9 +698,17 @@ def main():
         res["voxels"] = bench_voxels(ctx, max(args.steps // 2, 2))
         log("instanced workload")
         res["instanced"] = bench_instanced(ctx, max(args.steps // 2, 2))
+    if not args.only_plain:
+        for leg in ("uls_trees", "small_tls"):
+            log("%s workload" % leg)
+            res[leg] = run_leg(ctx, leg, max(args.steps // 2, 2), tune=not args.no_tune)
+        log("copy bandwidth")
+        res["copy_bandwidth"] = copy_bandwidth()
+    res["inputs"] = input_digest(mesh, pulses, sc, configs.ALS_SEED)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(mesh, pulses, sc, args.cpu_seconds)
+        res["cpu_baseline"]["cpu_model"] = cpu_model()
     print(json.dumps(res), flush=True)
 
 
