@@ -465,6 +465,35 @@ vls_status vls_echo_width(vls_context ctx, const vls_scanner_desc* scanners, int
 vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
                         const vls_pulse_batch* pulses, const vls_outputs* out, void* stream);
 
+/* vls_simulate for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same kernels as vls_simulate on one scanner (results equal to its own), but
+ * every workspace lives in a fixed device array of the library's, which each
+ * GPU the library runs on holds until the process ends: the scanner's subray
+ * table (stored by a small kernel, the table travelling as its argument) and
+ * the cone pass's candidate lists, overflow list, counters and pulse bases
+ * (VLS_NOALLOC_SCRATCH_BYTES bytes).  The call makes no hipMalloc, hipFree or
+ * other allocating call and records no timing events; the caller still passes
+ * the inputs and outputs.
+ *   scanner   one description (no segments: pulses->n_segments must be 0)
+ *   pulses    n_pulses <= VLS_NOALLOC_MAX_PULSES; larger batches are split by
+ *             the caller
+ *   scene     a scene from vls_scene_create or vls_scene_create_instanced (not
+ *             two-level)
+ * Every call on a GPU shares that GPU's array, and each call rewrites what it
+ * reads there before reading it (the counters with a fill kernel), so
+ * consecutive calls on one stream are independent.  Calls that overlap on one
+ * GPU (other streams, other contexts or threads) race on the array and must be
+ * ordered by the caller.
+ * Errors: as vls_simulate; VLS_ERR_INVALID_ARG for more than
+ * VLS_NOALLOC_MAX_PULSES pulses; VLS_ERR_UNSUPPORTED for segments or a
+ * two-level scene; VLS_ERR_DEVICE if the array's address could not be found
+ * when the context was created. */
+#define VLS_NOALLOC_MAX_PULSES 32768
+#define VLS_NOALLOC_SCRATCH_BYTES (2560 + 4 * (267 * 32768 + 4))
+vls_status vls_simulate_noalloc(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanner,
+                                const vls_pulse_batch* pulses, const vls_outputs* out, void* stream);
+
 /* ------------------------------------------------------------------ adjoint */
 
 /* Gradient of a waveform loss L with respect to per-triangle reflectance and

@@ -3,6 +3,6 @@ arXiv 2101.09154): HIP kernels for gfx950 behind the C ABI of include/vls.h,
 with a thin ctypes binding."""
 from . import vls
 from .autograd import WaveformFn
-from .vls import Context, Scene, VlsError, n_subrays, scanner_desc
+from .vls import NOALLOC_MAX_PULSES, Context, Scene, VlsError, n_subrays, scanner_desc
 
-__all__ = ["vls", "WaveformFn", "Context", "Scene", "VlsError", "n_subrays", "scanner_desc"]
+__all__ = ["vls", "WaveformFn", "NOALLOC_MAX_PULSES", "Context", "Scene", "VlsError", "n_subrays", "scanner_desc"]

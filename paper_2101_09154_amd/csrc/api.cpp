@@ -163,6 +163,8 @@ struct vls_context_s {
         double* dev = nullptr;
     };
     std::vector<SurveyTab> surveys;  // device waypoint tables, one per distinct survey
+    void* noalloc_ptr = nullptr;     // this device's scratch of vls_simulate_noalloc
+    hipError_t noalloc_status = hipSuccess;
     // kernel timing (vls_profile_*): event pairs recorded around the cone pass
     // and the fused kernel of eager vls_simulate calls, and a pool of spares
     bool prof = false;
@@ -252,28 +254,13 @@ struct vls_graph_s {
 
 namespace {
 
-vls_status scanner_dev(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s)
+// Everything of a scanner's device description but its subray table's device
+// copy (s.pattern stays null); the table itself goes to `table`.
+vls_status scanner_params(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s, std::vector<double>& table)
 {
-    std::vector<double> table;
     int S = subray_table(d, table);
     if (S <= 0) return fail(VLS_ERR_UNSUPPORTED, "subray pattern too large");
-    char key[160];
-    snprintf(key, sizeof key, "%d|%a|%a", S, d.divergence_rad, d.pattern_extent);
-    double* dev = nullptr;
-    auto it = ctx->patterns.find(key);
-    if (it == ctx->patterns.end()) {
-        VLS_HIP(hipMalloc(&dev, sizeof(double) * table.size()), "pattern alloc");
-        hipError_t e = hipMemcpy(dev, table.data(), sizeof(double) * table.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(dev);
-            return hip_fail(e, "pattern upload");
-        }
-        ctx->patterns[key] = dev;
-    } else {
-        dev = it->second;
-    }
     memset(&s, 0, sizeof s);
-    s.pattern = dev;
     s.S = S;
     s.P_w = ctx->cfg.pack ? 1 : kWave / S;
     s.n_bins = d.n_bins;
@@ -309,6 +296,32 @@ vls_status scanner_dev(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s
     s.noise_seed = d.noise_seed;
     s.thr_abs = d.min_echo_abs;
     s.thr_rel = d.min_echo_rel;
+    return VLS_OK;
+}
+
+// The scanner's device description with its subray table uploaded once per
+// context and distinct table.
+vls_status scanner_dev(vls_context ctx, const vls_scanner_desc& d, ScannerDev& s)
+{
+    std::vector<double> table;
+    vls_status st = scanner_params(ctx, d, s, table);
+    if (st != VLS_OK) return st;
+    char key[160];
+    snprintf(key, sizeof key, "%d|%a|%a", s.S, d.divergence_rad, d.pattern_extent);
+    double* dev = nullptr;
+    auto it = ctx->patterns.find(key);
+    if (it == ctx->patterns.end()) {
+        VLS_HIP(hipMalloc(&dev, sizeof(double) * table.size()), "pattern alloc");
+        hipError_t e = hipMemcpy(dev, table.data(), sizeof(double) * table.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(dev);
+            return hip_fail(e, "pattern upload");
+        }
+        ctx->patterns[key] = dev;
+    } else {
+        dev = it->second;
+    }
+    s.pattern = dev;
     return VLS_OK;
 }
 
@@ -348,8 +361,10 @@ int staged_slots(const Prepared& pr)
     return m;
 }
 
+// tables: when not null, the scanners' subray tables are left on the host
+// (appended here, one per scanner) and no device table is uploaded.
 vls_status prepare(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_scanners, const vls_pulse_batch* pulses,
-                   Prepared& pr)
+                   Prepared& pr, std::vector<std::vector<double>>* tables = nullptr)
 {
     if (!ctx) return fail(VLS_ERR_INVALID_ARG, "context is NULL");
     if (!scanners || n_scanners < 1 || n_scanners > VLS_MAX_SCANNERS)
@@ -364,7 +379,12 @@ vls_status prepare(vls_context ctx, const vls_scanner_desc* scanners, int32_t n_
     for (int i = 0; i < n_scanners; ++i) {
         vls_status st = check_scanner(scanners[i], i);
         if (st != VLS_OK) return st;
-        st = scanner_dev(ctx, scanners[i], pr.sc[i]);
+        if (tables) {
+            tables->emplace_back();
+            st = scanner_params(ctx, scanners[i], pr.sc[i], tables->back());
+        } else {
+            st = scanner_dev(ctx, scanners[i], pr.sc[i]);
+        }
         if (st != VLS_OK) return st;
     }
     pr.n_bins = pr.sc[0].n_bins;
@@ -596,6 +616,9 @@ vls_status vls_context_create(int32_t hip_device, vls_context* out)
         VLS_HIP(hipSetDevice(hip_device), "hipSetDevice");
         auto* c = new vls_context_s();
         c->device = hip_device;
+        // the allocation-free entry point's scratch on this device (its status is
+        // kept and reported by that entry point; other calls do not need it)
+        c->noalloc_status = noalloc_scratch(hip_device, &c->noalloc_ptr);
         *out = c;
         return VLS_OK;
     } catch (const std::exception& e) {
@@ -1483,9 +1506,11 @@ static hipError_t prof_end(vls_context ctx, hipStream_t s, std::pair<hipEvent_t,
 }
 
 // cand: candidate workspace of at least n_pulses entries (the context's, or a graph's own)
+// allow_prof: timing events may be recorded (not for the allocation-free entry
+// point, whose caller may forbid creating them)
 static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepared& pr, const vls_pulse_batch* pulses,
                                    const vls_outputs* out, vls_context_s::Batch* bt, int blocks, hipStream_t s,
-                                   int* cand)
+                                   int* cand, bool allow_prof = true)
 {
     if (pulses->n_pulses == 0) return VLS_OK;
     OutDev od = out_dev(out, pr.S_stride);
@@ -1494,8 +1519,8 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
     hipError_t e;
     // timing events only on eager calls (not while a graph is being captured)
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (ctx->prof && hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
-    const bool prof = ctx->prof && cap == hipStreamCaptureStatusNone;
+    if (allow_prof && ctx->prof && hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
+    const bool prof = allow_prof && ctx->prof && cap == hipStreamCaptureStatusNone;
     std::pair<hipEvent_t, hipEvent_t> ev{};
     if (ctx->cfg.cone) {
         if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
@@ -1582,6 +1607,48 @@ vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc
         if (st != VLS_OK) return st;
         if (scene->tl) return simulate_two_level(ctx, scene, pr, pulses, out, (hipStream_t)stream);
         return simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, (hipStream_t)stream, ctx->cand);
+    } catch (const std::exception& e) {
+        return fail(VLS_ERR_INTERNAL, e.what());
+    }
+}
+
+static_assert(VLS_NOALLOC_MAX_PULSES == kNoAllocMaxPulses, "vls.h and the library agree on the pulse limit");
+static_assert(VLS_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes, "vls.h and the library agree on the scratch size");
+
+vls_status vls_simulate_noalloc(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanner,
+                                const vls_pulse_batch* pulses, const vls_outputs* out, void* stream)
+{
+    try {
+        if (!ctx) return fail(VLS_ERR_INVALID_ARG, "context is NULL");
+        if (!pulses) return fail(VLS_ERR_INVALID_ARG, "pulse batch is NULL");
+        if (pulses->n_segments != 0)
+            return fail(VLS_ERR_UNSUPPORTED, "vls_simulate_noalloc takes one scanner and no segments");
+        if (pulses->n_pulses > kNoAllocMaxPulses) {
+            char b[160];
+            snprintf(b, sizeof b, "vls_simulate_noalloc handles at most %lld pulses per call (got %lld)",
+                     (long long)kNoAllocMaxPulses, (long long)pulses->n_pulses);
+            return fail(VLS_ERR_INVALID_ARG, b);
+        }
+        if (scene && scene->tl) return fail(VLS_ERR_UNSUPPORTED, "vls_simulate_noalloc does not take two-level scenes");
+        Prepared pr;
+        std::vector<std::vector<double>> tables;
+        vls_status st = prepare(ctx, scanner, 1, pulses, pr, &tables);
+        if (st != VLS_OK) return st;
+        if ((st = check_scene(ctx, scene, pr)) != VLS_OK) return st;
+        if ((st = check_outputs(out)) != VLS_OK) return st;
+        if (pulses->n_pulses > 0 && (!out->n_returns || !out->ret_range || !out->ret_amplitude || !out->ret_bin))
+            return fail(VLS_ERR_INVALID_ARG, "simulate needs n_returns, ret_range, ret_amplitude and ret_bin");
+        if (ctx->noalloc_status != hipSuccess) return hip_fail(ctx->noalloc_status, "scratch address");
+        if (pulses->n_pulses == 0) return VLS_OK;
+        hipStream_t s = (hipStream_t)stream;
+        // scratch: the subray table, then the cone-pass workspace of this call's pulses
+        unsigned char* base = static_cast<unsigned char*>(ctx->noalloc_ptr);
+        double* pattern = reinterpret_cast<double*>(base);
+        int* cand = reinterpret_cast<int*>(base + kNoAllocPatternBytes);
+        hipError_t e = launch_store_pattern(tables[0].data(), (int)tables[0].size(), pattern, s);
+        if (e != hipSuccess) return hip_fail(e, "subray table store");
+        pr.sc[0].pattern = pattern;
+        return simulate_enqueue(ctx, scene, pr, pulses, out, nullptr, 0, s, cand, false);
     } catch (const std::exception& e) {
         return fail(VLS_ERR_INTERNAL, e.what());
     }

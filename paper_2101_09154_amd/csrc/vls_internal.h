@@ -23,7 +23,7 @@ constexpr int kPacketCap = 128;          // stack entries of a packet walk (3 pe
 // Cone-pass workspace for n pulses: candidate rows [n][kCandMax + 1], then the
 // list of pulses that overflowed [n], then two counters (overflow count, work),
 // then each pulse's basis [n][5] doubles (see dev::Basis).
-inline size_t cone_ws_ints(long long n) { return (size_t)(kCandMax + 1) * n + n + (n & 1) + 4 + 10 * (size_t)n; }
+constexpr size_t cone_ws_ints(long long n) { return (size_t)(kCandMax + 1) * n + n + (n & 1) + 4 + 10 * (size_t)n; }
 inline int* cone_ws_list(int* ws, long long n) { return ws + (size_t)(kCandMax + 1) * n; }
 inline unsigned long long* cone_ws_ctr(int* ws, long long n)
 {
@@ -33,6 +33,13 @@ inline double* cone_ws_basis(int* ws, long long n)
 {
     return reinterpret_cast<double*>(ws + (size_t)(kCandMax + 1) * n + n + (n & 1) + 4);
 }
+// The allocation-free simulate entry point keeps its workspace in a fixed device
+// array: the subray table of its one scanner (5 doubles per subray), then the
+// cone-pass workspace above for at most kNoAllocMaxPulses pulses.
+constexpr long long kNoAllocMaxPulses = 32768;
+constexpr size_t kNoAllocPatternBytes = 5 * kWave * sizeof(double);
+constexpr size_t kNoAllocScratchBytes = kNoAllocPatternBytes + sizeof(int) * cone_ws_ints(kNoAllocMaxPulses);
+static_assert(kNoAllocPatternBytes % 256 == 0, "the candidate workspace starts 256-byte aligned");
 constexpr int kMaxLevel = 4096;          // depth cap of the build's level lists
 constexpr int kCandStaged = 16;          // of which the first ones are staged in LDS by the fused kernel
 // Candidates staged per pulse: one per lane of the wavefront, so 64 for one pulse
@@ -282,5 +289,11 @@ hipError_t launch_instances(const float* v, const int32_t* t, const float* refl,
 hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_pulses, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t stream);
 int persistent_occupancy_blocks(int max_bins, int staged_slots, bool vox, const LaunchCfg& cfg);
+// The allocation-free entry point's device scratch (kNoAllocScratchBytes) on
+// `device`: its address, looked up once per device (see noalloc.hip).
+hipError_t noalloc_scratch(int device, void** ptr);
+// Writes a subray table (n doubles, n <= 5 * kWave) to device memory dst with one
+// small kernel; the table travels as the kernel's argument.
+hipError_t launch_store_pattern(const double* table, int n, double* dst, hipStream_t stream);
 
 }  // namespace vls

@@ -19,6 +19,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "device error",
           5: "unsupported", 6: "internal error"}
 MEM_HOST = 0
 MAX_CANDIDATES = 255  # VLS_MAX_CANDIDATES: triangles the cone pass lists per pulse
+NOALLOC_MAX_PULSES = 32768  # VLS_NOALLOC_MAX_PULSES: pulses per vls_simulate_noalloc call
 MEM_DEVICE = 1
 PULSE_GAUSSIAN = 0
 PULSE_EQ3 = 1
@@ -126,6 +127,7 @@ _SIGS = {
     "vls_echo_width": ([P, P, i32, P, P, P, P], i32),
     "vls_generate_pulses": ([P, P, ctypes.c_int64, ctypes.c_int64, P, P, P], i32),
     "vls_simulate": ([P, P, P, i32, P, P, P], i32),
+    "vls_simulate_noalloc": ([P, P, P, P, P, P], i32),
     "vls_set_launch_config": ([P, P], i32),
     "vls_get_launch_config": ([P, P], i32),
     "vls_synchronize": ([P, P], i32),
@@ -451,6 +453,15 @@ class Context:
         b, keep = self._batch(origins, directions, t0, segment_offsets, segment_scanner)
         o = self._outputs(out)
         _check(lib().vls_simulate(self._h, scene._h, arr, ns, ctypes.byref(b), ctypes.byref(o), _stream(stream)))
+        return out
+
+    def simulate_noalloc(self, scene, scanner, origins, directions, out, *, t0=None, stream=None):
+        """vls_simulate_noalloc: the fused path on one scanner with the library's
+        fixed device scratch; `out` (from alloc_outputs) is required."""
+        arr, ns = self._scanners([scanner])
+        b, keep = self._batch(origins, directions, t0, None, None)
+        o = self._outputs(out)
+        _check(lib().vls_simulate_noalloc(self._h, scene._h, arr, ctypes.byref(b), ctypes.byref(o), _stream(stream)))
         return out
 
     def trace(self, scene, scanners, origins, directions, *, out=None, segment_offsets=None, segment_scanner=None,
