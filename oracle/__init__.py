@@ -37,11 +37,11 @@ class OrcSurvey(ctypes.Structure):
                 ("speed", ctypes.c_double), ("prf", ctypes.c_double), ("scan_freq", ctypes.c_double),
                 ("scan_angle", ctypes.c_double), ("n_fibres", ctypes.c_int32), ("platform", ctypes.c_int32),
                 ("t0", ctypes.c_double), ("noise_sigma", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("accel", ctypes.c_double), ("leg_yaw", ctypes.c_void_p)]
+                ("accel", ctypes.c_double), ("leg_yaw", ctypes.c_void_p), ("bank", ctypes.c_double)]
 
 
 DEFLECTORS = {"polygon": 0, "swing": 1, "conic": 2, "fibre": 3}
-PLATFORMS = {"linear": 0, "multicopter": 1}
+PLATFORMS = {"linear": 0, "multicopter": 1, "multicopter_smooth": 2}
 
 
 class OrcVoxels(ctypes.Structure):
@@ -263,8 +263,9 @@ def splitmix64(seed, c):
 def generate_pulses(sv, first, count):
     """Pulses [first, first + count) of a survey (Sec. 3.2-3.3 readings):
     origins and unit directions, both float64 [count, 3].  `platform` is
-    "linear" (default) or "multicopter" (with `accel_mps2` and optionally
-    `leg_yaw`, [n_waypoints - 1, 2] start and end yaw of each leg)."""
+    "linear" (default), "multicopter" (with `accel_mps2` and optionally
+    `leg_yaw`, [n_waypoints - 1, 2] start and end yaw of each leg) or
+    "multicopter_smooth" (banked turns: `accel_mps2` and `bank_angle_rad`)."""
     wp = np.ascontiguousarray(sv["waypoints"], dtype=np.float64).reshape(-1, 3)
     ly = sv.get("leg_yaw")
     ly = None if ly is None else np.ascontiguousarray(ly, dtype=np.float64).reshape(-1, 2)
@@ -275,7 +276,8 @@ def generate_pulses(sv, first, count):
                    float(sv.get("scan_angle_rad", 0.0)), int(sv.get("n_fibres", 0)),
                    PLATFORMS[sv.get("platform", "linear")], float(sv.get("t0", 0.0)),
                    float(sv.get("platform_noise_m", 0.0)), int(sv.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF,
-                   float(sv.get("accel_mps2", 0.0)), None if ly is None else ly.ctypes.data)
+                   float(sv.get("accel_mps2", 0.0)), None if ly is None else ly.ctypes.data,
+                   float(sv.get("bank_angle_rad", 0.0)))
     o = np.zeros((count, 3))
     d = np.zeros((count, 3))
     if lib().orc_generate_pulses(ctypes.byref(st), int(first), int(count), _ptr(o), _ptr(d)) != 0:

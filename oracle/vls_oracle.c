@@ -971,10 +971,31 @@ void orc_echo_width(const orc_scanner* sc, const double* wf, int n, const int32_
  *            takes no time; afterwards the platform stays at the last one;
  *   yaw      the leg's heading, or with `leg_yaw` ([n - 1][2]: start and end
  *            yaw of each leg, rad) linear in the time spent on the leg from
- *            the start to the end value; the platform stays level (the banked
- *            turns of the smooth mode are not modelled). */
+ *            the start to the end value; the platform stays level.
+ * The Multicopter's smooth turn mode (Sec. 3.2: the platform banks to turn
+ * smoothly at the waypoints instead of stopping and turning on the spot, as
+ * the banked turns of drone flight protocols do) is read as a coordinated turn:
+ *   path     every interior waypoint W is cut by a circular arc tangent to
+ *            both of its legs, of radius r = v^2 / (g tan b) (speed v, bank
+ *            angle b, g = 9.80665 m/s^2): with u, w the unit directions into
+ *            and out of W and theta = acos(u . w) the turn angle, the arc runs
+ *            from W - s u to W + s w, s = r tan(theta / 2), in the plane of the
+ *            two legs; the legs' straight parts join the arcs;
+ *   speed    from rest at the first waypoint the platform speeds up at
+ *            `accel` to v, keeps v along the straight parts and through every
+ *            arc, and slows down at `accel` to rest at the last waypoint,
+ *            where it stays; every leg must hold its arcs and ramps (the arc
+ *            lengths s at both ends, plus v^2 / (2 accel) on the first and the
+ *            last leg), and no turn may reverse a leg (theta < 179 deg);
+ *   attitude heading along the horizontal direction of motion; level on the
+ *            straight parts; on an arc banked by b toward the turn's centre
+ *            (left when the horizontal turn is anticlockwise), the bank taken
+ *            and released at the arc's ends: a platform-frame direction
+ *            (x, y, z) becomes (x, y cos l + z sin l, -y sin l + z cos l) with
+ *            l = +b to the left, -b to the right, then turns by the heading. */
 enum { ORC_DEFLECT_POLYGON = 0, ORC_DEFLECT_SWING = 1, ORC_DEFLECT_CONIC = 2, ORC_DEFLECT_FIBRE = 3 };
-enum { ORC_PLATFORM_LINEAR = 0, ORC_PLATFORM_MULTICOPTER = 1 };
+enum { ORC_PLATFORM_LINEAR = 0, ORC_PLATFORM_MULTICOPTER = 1, ORC_PLATFORM_MULTICOPTER_SMOOTH = 2 };
+#define ORC_G 9.80665
 
 typedef struct {
     const double* waypoints; /* [n][3] */
@@ -991,6 +1012,7 @@ typedef struct {
     uint64_t seed;
     double accel;            /* m/s^2, Multicopter */
     const double* leg_yaw;   /* [n - 1][2] or NULL, Multicopter */
+    double bank;             /* rad, Multicopter smooth turns: bank angle in (0, pi/2) */
 } orc_survey;
 
 uint64_t orc_splitmix64(uint64_t seed, uint64_t c)
@@ -1028,6 +1050,138 @@ static double copter_leg_distance(double L, double v, double a, double T, double
     return 0.5 * a * ramp * ramp + top * (tau - ramp);
 }
 
+/* The smooth turn path: its pieces in order, a straight part of each leg and an
+ * arc at each interior waypoint. */
+typedef struct {
+    int arc;              /* 0 straight, 1 arc */
+    double len;           /* arc length of the piece */
+    double p0[3], dir[3]; /* straight: start point and unit direction */
+    double c[3], u[3], n[3], r, lean; /* arc: centre, tangent at its start, unit vector toward the centre, radius, bank */
+} orc_piece;
+
+/* Pieces of a smooth survey; returns their number, or -1 when a leg cannot hold
+ * its arcs and ramps or a turn reverses a leg.  *total gets the path length. */
+static int smooth_pieces(const orc_survey* sv, orc_piece* pc, double* total)
+{
+    const int nw = sv->n_waypoints;
+    const double v = sv->speed, r = v * v / (ORC_G * tan(sv->bank)), ramp = v * v / (2.0 * sv->accel);
+    double s_at[nw > 0 ? nw : 1]; /* tangent length of the arc at each waypoint (0 at the ends) */
+    double u_in[3], u_out[3];
+    int np = 0;
+    for (int i = 0; i < nw; ++i) s_at[i] = 0.0;
+    for (int i = 1; i + 1 < nw; ++i) {
+        const double *a = sv->waypoints + 3 * (i - 1), *w = sv->waypoints + 3 * i, *b = sv->waypoints + 3 * (i + 1);
+        double li = 0.0, lo = 0.0, dot = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            u_in[k] = w[k] - a[k];
+            u_out[k] = b[k] - w[k];
+            li += u_in[k] * u_in[k];
+            lo += u_out[k] * u_out[k];
+        }
+        li = sqrt(li);
+        lo = sqrt(lo);
+        for (int k = 0; k < 3; ++k) {
+            u_in[k] /= li;
+            u_out[k] /= lo;
+            dot += u_in[k] * u_out[k];
+        }
+        if (dot > 1.0) dot = 1.0;
+        if (dot < -1.0) dot = -1.0;
+        const double theta = acos(dot);
+        if (theta > 179.0 * ORC_PI / 180.0) return -1;
+        s_at[i] = r * tan(0.5 * theta);
+    }
+    double tot = 0.0;
+    for (int j = 0; j + 1 < nw; ++j) {
+        const double *a = sv->waypoints + 3 * j, *b = sv->waypoints + 3 * (j + 1);
+        double d[3], L = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            d[k] = b[k] - a[k];
+            L += d[k] * d[k];
+        }
+        L = sqrt(L);
+        for (int k = 0; k < 3; ++k) d[k] /= L;
+        const double need = s_at[j] + s_at[j + 1] + (j == 0 ? ramp : 0.0) + (j + 2 == nw ? ramp : 0.0);
+        if (!(need <= L)) return -1;
+        /* the straight part of leg j */
+        orc_piece* q = &pc[np++];
+        q->arc = 0;
+        q->len = L - s_at[j] - s_at[j + 1];
+        for (int k = 0; k < 3; ++k) {
+            q->p0[k] = a[k] + s_at[j] * d[k];
+            q->dir[k] = d[k];
+        }
+        tot += q->len;
+        if (j + 2 < nw) {
+            /* the arc at waypoint j + 1 */
+            const double* c2 = sv->waypoints + 3 * (j + 2);
+            double w2[3], lw = 0.0, dot = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                w2[k] = c2[k] - b[k];
+                lw += w2[k] * w2[k];
+            }
+            lw = sqrt(lw);
+            for (int k = 0; k < 3; ++k) {
+                w2[k] /= lw;
+                dot += d[k] * w2[k];
+            }
+            if (dot > 1.0) dot = 1.0;
+            if (dot < -1.0) dot = -1.0;
+            const double theta = acos(dot);
+            if (theta > 0.0) {
+                orc_piece* g = &pc[np++];
+                g->arc = 1;
+                g->r = r;
+                g->len = r * theta;
+                double nrm = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    g->n[k] = w2[k] - dot * d[k];
+                    nrm += g->n[k] * g->n[k];
+                }
+                nrm = sqrt(nrm);
+                for (int k = 0; k < 3; ++k) {
+                    g->n[k] /= nrm;
+                    g->u[k] = d[k];
+                    g->c[k] = b[k] - s_at[j + 1] * d[k] + r * g->n[k];
+                }
+                /* bank toward the centre: left for an anticlockwise horizontal turn */
+                const double turn_z = d[0] * w2[1] - d[1] * w2[0];
+                g->lean = turn_z > 0.0 ? sv->bank : (turn_z < 0.0 ? -sv->bank : 0.0);
+                tot += g->len;
+            }
+        }
+    }
+    *total = tot;
+    return np;
+}
+
+/* Position, unit direction of motion and bank of the smooth path at path length
+ * sigma (0 <= sigma <= total). */
+static void smooth_at(const orc_piece* pc, int np, double sigma, double* pos, double* dir, double* lean)
+{
+    int i = 0;
+    while (i + 1 < np && sigma > pc[i].len) {
+        sigma -= pc[i].len;
+        ++i;
+    }
+    const orc_piece* q = &pc[i];
+    if (sigma > q->len) sigma = q->len;
+    if (!q->arc) {
+        for (int k = 0; k < 3; ++k) {
+            pos[k] = q->p0[k] + sigma * q->dir[k];
+            dir[k] = q->dir[k];
+        }
+        *lean = 0.0;
+        return;
+    }
+    const double ph = sigma / q->r;
+    for (int k = 0; k < 3; ++k) {
+        pos[k] = q->c[k] - q->r * cos(ph) * q->n[k] + q->r * sin(ph) * q->u[k];
+        dir[k] = cos(ph) * q->u[k] + sin(ph) * q->n[k];
+    }
+    *lean = q->lean;
+}
+
 /* Pulses [first, first + count): origins [count][3], directions [count][3]
  * (unit, FP64).  Returns 0, or -1 for an invalid survey. */
 int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, double* origins, double* dirs)
@@ -1036,9 +1190,30 @@ int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, doub
     if (nw < 1 || !(sv->prf > 0.0)) return -1;
     if (sv->deflector == ORC_DEFLECT_FIBRE && sv->n_fibres < 2) return -1;
     int copter = sv->platform == ORC_PLATFORM_MULTICOPTER;
-    if (sv->platform != ORC_PLATFORM_LINEAR && !copter) return -1;
-    if (copter && nw >= 2 && !(sv->speed > 0.0 && sv->accel > 0.0)) return -1;
+    int smooth = sv->platform == ORC_PLATFORM_MULTICOPTER_SMOOTH;
+    if (sv->platform != ORC_PLATFORM_LINEAR && !copter && !smooth) return -1;
+    if ((copter || smooth) && nw >= 2 && !(sv->speed > 0.0 && sv->accel > 0.0)) return -1;
     if (!copter && sv->leg_yaw) return -1;
+    if (smooth && !(sv->bank > 0.0 && sv->bank < 0.5 * ORC_PI)) return -1;
+    orc_piece* pc = NULL;
+    int np = 0;
+    double total = 0.0, T_end = 0.0;
+    if (smooth && nw >= 2) {
+        pc = (orc_piece*)malloc(sizeof(orc_piece) * (size_t)(2 * nw));
+        for (int i = 1; i < nw; ++i) {
+            const double *a = sv->waypoints + 3 * (i - 1), *b = sv->waypoints + 3 * i;
+            if (!((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) + (b[2] - a[2]) * (b[2] - a[2]) > 0.0)) {
+                free(pc);
+                return -1;
+            }
+        }
+        np = smooth_pieces(sv, pc, &total);
+        if (np < 0) {
+            free(pc);
+            return -1;
+        }
+        T_end = total / sv->speed + sv->speed / sv->accel;
+    }
     double* cum = (double*)malloc(sizeof(double) * (size_t)nw);   /* path length at each waypoint */
     double* start = (double*)malloc(sizeof(double) * (size_t)nw); /* Multicopter: time at each waypoint */
     cum[0] = 0.0;
@@ -1061,8 +1236,20 @@ int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, doub
         double t = sv->t0 + (double)k / sv->prf;
         /* position along the path and heading of the current leg */
         double pos[3] = {sv->waypoints[0], sv->waypoints[1], sv->waypoints[2]};
-        double yaw = 0.0;
-        if (nw >= 2 && copter) {
+        double yaw = 0.0, lean = 0.0;
+        if (nw >= 2 && smooth) {
+            /* path length covered: ramp up, cruise, ramp down (Sec. 3.2 reading above) */
+            const double v = sv->speed, acc = sv->accel, tr = v / acc;
+            double sigma;
+            if (t <= 0.0) sigma = 0.0;
+            else if (t <= tr) sigma = 0.5 * acc * t * t;
+            else if (t < T_end - tr) sigma = 0.5 * acc * tr * tr + v * (t - tr);
+            else if (t < T_end) sigma = total - 0.5 * acc * (T_end - t) * (T_end - t);
+            else sigma = total;
+            double dir[3];
+            smooth_at(pc, np, sigma, pos, dir, &lean);
+            yaw = atan2(dir[1], dir[0]);
+        } else if (nw >= 2 && copter) {
             int leg = 0;
             while (leg + 2 < nw && start[leg + 1] <= t) ++leg;
             const double* a = sv->waypoints + 3 * leg;
@@ -1118,6 +1305,13 @@ int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, doub
             d[1] = sin(ang);
             d[2] = -cos(ang);
         }
+        if (lean != 0.0) {
+            /* banked toward the turn's centre */
+            double cl = cos(lean), sl = sin(lean);
+            double y = d[1] * cl + d[2] * sl, z = -d[1] * sl + d[2] * cl;
+            d[1] = y;
+            d[2] = z;
+        }
         double cy = cos(yaw), sy = sin(yaw);
         double* o = origins + 3 * q;
         double* w = dirs + 3 * q;
@@ -1128,6 +1322,7 @@ int orc_generate_pulses(const orc_survey* sv, int64_t first, int64_t count, doub
     }
     free(cum);
     free(start);
+    free(pc);
     return 0;
 }
 
