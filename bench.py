@@ -300,11 +300,29 @@ def bench_grad(ctx, steps):
             bwd += ev[1].elapsed_time(ev[2])
     fwd /= steps
     bwd /= steps
+    # the adjoint in its fixed summation order (bitwise repeatable)
+    ctx.set_deterministic(True)
+    bwd_det = 0.0
+    for it in range(steps + 2):
+        heights.grad = None
+        refl.grad = None
+        wf = vp.WaveformFn.apply(refl, heights, ctx, scene, sc, o, d, t0, base_xy)
+        loss = ((wf - tgt) ** 2).sum()
+        torch.cuda.synchronize()
+        ev[1].record(stream)
+        loss.backward()
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        if it >= 2:
+            bwd_det += ev[1].elapsed_time(ev[2])
+    ctx.set_deterministic(False)
+    bwd_det /= steps
     S = vp.n_subrays(sc)
     return {"workload": "diff_als: 256x256 value-noise DTM (130,050 triangles), 100,000 ALS pulses at 200 m, "
                         "31 subrays, 512 x 0.5 ns bins; L2 loss to a target with heights +-0.2 m and "
                         "reflectance +-0.05",
             "forward_ms": fwd, "backward_ms": bwd, "bwd_fwd_ratio": bwd / fwd,
+            "backward_deterministic_ms": bwd_det, "bwd_fwd_ratio_deterministic": bwd_det / fwd,
             "forward_subrays_per_s": pulses.n * S / (fwd * 1e-3), "loss": float(loss.item()),
             "grad_norm_reflectance": float(refl.grad.norm().item()),
             "grad_norm_heights": float(heights.grad.norm().item())}

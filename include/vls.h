@@ -26,7 +26,17 @@
  *   - device faults surface at the next synchronising call, e.g. vls_synchronize;
  *   - the caller owns every array it passes; the library owns contexts,
  *     scenes and graphs, freed by their *_destroy call;
- *   - a context (and everything created from it) is not thread-safe.
+ *   - a context (and everything created from it) is not thread-safe: calls on
+ *     it come from one host thread at a time;
+ *   - a context may be used with several streams: each stream gets its own
+ *     workspaces (candidate lists, counters, echo-width and adjoint scratch),
+ *     grown when a call needs more by stream-ordered allocation on that stream
+ *     (hipMallocAsync / hipFreeAsync), so calls on different streams share no
+ *     scratch memory and growing one does not synchronise the device; a
+ *     stream must outlive the calls made on it until they have completed;
+ *   - calls documented as synchronous (scene creation, statistics, the first
+ *     upload of a scanner's subray table or of a batch's segment table, which
+ *     are shared read-only by every stream) wait for their own copies.
  */
 #ifndef VLS_H
 #define VLS_H
@@ -508,11 +518,22 @@ vls_status vls_simulate_noalloc(vls_context ctx, vls_scene scene, const vls_scan
  *   grad_waveform      [n_pulses][n_bins] float32 device
  *   grad_reflectance   [n_triangles] float32 device, overwritten (may be NULL)
  *   grad_vertex_z      [n_vertices] float32 device, overwritten (may be NULL)
- * Float atomics make the summation order, and so the last bits, vary between
- * runs.  Asynchronous on `stream`. */
+ * By default each wavefront sums the contributions of its subrays that share a
+ * triangle and adds them with float atomics, so the summation order, and the
+ * last bits, vary between runs.  With vls_set_deterministic(ctx, 1) every
+ * subray's contributions are written as entries keyed by their parameter
+ * (triangle or vertex), stably sorted by key, and each parameter's entries
+ * summed in subray order in FP64: bitwise repeatable, at the cost of a
+ * workspace of 112 B per subray (grown on the stream) and a radix sort.
+ * Asynchronous on `stream`. */
 vls_status vls_waveform_backward(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanner,
                                  const vls_pulse_batch* pulses, const int32_t* subray_tri, const float* grad_waveform,
                                  float* grad_reflectance, float* grad_vertex_z, void* stream);
+
+/* Summation order of vls_waveform_backward: 0 (default) wavefront sums and
+ * float atomics; 1 a fixed order (sort by parameter, sums in subray order), so
+ * two runs on the same inputs give bitwise equal gradients. */
+vls_status vls_set_deterministic(vls_context ctx, int32_t on);
 
 /* ------------------------------------------------------------------ launch configuration */
 

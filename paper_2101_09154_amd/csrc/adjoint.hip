@@ -177,7 +177,129 @@ __global__ __launch_bounds__(256) void k_backward(SceneDev scene, ScannerDev sc,
     }
 }
 
+// Deterministic form: instead of atomics, every subray slot e (pulse p, subray
+// k: e = p S + k) writes four entries, 4 e + c: c = 0 its reflectance
+// contribution keyed by its triangle, c = 1..3 its height contributions keyed
+// by the triangle's vertices (key = kind << id_bits | id, kind 0 reflectance,
+// 1 height; slots without a hit or an unrequested gradient get the key
+// `none`).  A stable sort by key then puts each parameter's contributions
+// together in entry order, and one thread per run sums them in that order.
+__global__ __launch_bounds__(256) void k_backward_entries(SceneDev scene, ScannerDev sc, PulsesDev pulses,
+                                                          const int32_t* __restrict__ sub_tri, int sub_stride,
+                                                          const float* __restrict__ grad_wf, bool want_refl,
+                                                          bool want_z, int id_bits, unsigned long long none,
+                                                          unsigned long long* __restrict__ keys,
+                                                          int32_t* __restrict__ vals, float* __restrict__ contrib,
+                                                          long long count)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int waves = blockDim.x / kWave;
+    long long wave = (long long)blockIdx.x * waves + threadIdx.x / kWave;
+    long long p0 = wave * sc.P_w;
+    if (p0 >= count) return;
+    long long left = count - p0;
+    const int npw = left < sc.P_w ? (int)left : sc.P_w;
+    const int S = sc.S;
+    const int pl = lane / S, k = lane - pl * S;
+    if (pl >= npw) return;
+    const long long p = p0 + pl;
+    int tri = -1;
+    Grads g;
+    g.grho = g.gz[0] = g.gz[1] = g.gz[2] = 0.0;
+    int t = sub_tri[p * sub_stride + k];
+    double t0 = pulses.t0_in[p];
+    if (t >= 0 && t < scene.n_tri && !isnan(t0)) {
+        Ray r;
+        const double* pat = sc.pattern + 5 * k;
+        if (setup_ray(pulses.origins + 3 * p, pulses.dirs + 3 * p, pat, r) &&
+            subray_grads(scene, sc, r, t, pat[4], t0, grad_wf + p * sc.n_bins, g))
+            tri = t;
+    }
+    const long long e = 4 * (p * S + k);
+    const int32_t* ti = scene.tri_idx + 3 * (long long)(tri >= 0 ? tri : 0);
+    keys[e] = tri >= 0 && want_refl ? (unsigned long long)tri : none;
+    vals[e] = (int32_t)e;
+    contrib[e] = (float)g.grho;
+    for (int c = 0; c < 3; ++c) {
+        keys[e + 1 + c] = tri >= 0 && want_z ? (1ull << id_bits) | (unsigned long long)ti[c] : none;
+        vals[e + 1 + c] = (int32_t)(e + 1 + c);
+        contrib[e + 1 + c] = (float)g.gz[c];
+    }
+}
+
+// One thread per sorted entry; the first entry of each run of equal keys sums
+// the run's contributions in entry order (FP64) and writes the parameter.
+__global__ __launch_bounds__(256) void k_segment_sums(const unsigned long long* __restrict__ keys,
+                                                      const int32_t* __restrict__ vals,
+                                                      const float* __restrict__ contrib, long long n, int id_bits,
+                                                      unsigned long long none, float* grad_refl, float* grad_z)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long key = keys[i];
+    if (key == none || (i > 0 && keys[i - 1] == key)) return;
+    double sum = 0.0;
+    for (long long j = i; j < n && keys[j] == key; ++j) sum += (double)contrib[vals[j]];
+    const unsigned long long id = key & ((1ull << id_bits) - 1);
+    if ((key >> id_bits) == 0) grad_refl[id] = (float)sum;
+    else grad_z[id] = (float)sum;
+}
+
 }  // namespace
+
+// Bits of a parameter index in the deterministic form's keys (ids below
+// max(n_tri, n_vert)), and the sort passes (8 bits each) that cover the kind bit
+// and the `none` key.
+static int backward_id_bits(long long n_tri, long long n_vert)
+{
+    long long m = n_tri > n_vert ? n_tri : n_vert;
+    int b = 1;
+    while ((1ll << b) < m) ++b;
+    return b;
+}
+
+size_t backward_det_bytes(long long n_pulses, int S)
+{
+    const long long n = 4 * n_pulses * (long long)S;
+    const size_t a = (size_t)n;
+    return 2 * 8 * a + 2 * 4 * a + 4 * a + 4 * (size_t)radix_sort_hist_words(n) + 4 * 256;
+}
+
+hipError_t launch_backward_det(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
+                               const int32_t* sub_tri, int sub_stride, const float* grad_wf, float* grad_refl,
+                               float* grad_z, long long n_vert, const LaunchCfg& cfg, void* ws, hipStream_t stream)
+{
+    if (grad_refl && scene.n_tri > 0)
+        hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((scene.n_tri + 255) / 256)), dim3(256), 0, stream, grad_refl,
+                           (long long)scene.n_tri);
+    if (grad_z && n_vert > 0)
+        hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n_vert + 255) / 256)), dim3(256), 0, stream, grad_z, n_vert);
+    if (pulses.n <= 0 || scene.n_tri <= 0) return hipGetLastError();
+    const long long n = 4 * pulses.n * (long long)sc.S;
+    const int id_bits = backward_id_bits(scene.n_tri, n_vert);
+    const unsigned long long none = (2ull << id_bits) | ((1ull << id_bits) - 1);  // kind 2: after every real key
+    int passes = (id_bits + 2 + 7) / 8;
+    if (passes & 1) ++passes;  // an even count leaves the result in the first arrays
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    auto* keys = reinterpret_cast<unsigned long long*>(w);
+    auto* keys2 = keys + n;
+    auto* vals = reinterpret_cast<int32_t*>(keys2 + n);
+    int32_t* vals2 = vals + n;
+    float* contrib = reinterpret_cast<float*>(vals2 + n);
+    unsigned* hist = reinterpret_cast<unsigned*>(contrib + n);
+    const int block = cfg.block_waves * kWave;
+    long long waves = (pulses.n + sc.P_w - 1) / sc.P_w;
+    unsigned grid = (unsigned)((waves + cfg.block_waves - 1) / cfg.block_waves);
+    // every entry is written: each slot (p < n_pulses, k < S) is one lane of one wavefront
+    hipLaunchKernelGGL(k_backward_entries, dim3(grid), dim3(block), 0, stream, scene, sc, pulses, sub_tri, sub_stride,
+                       grad_wf, grad_refl != nullptr, grad_z != nullptr, id_bits, none, keys, vals, contrib, pulses.n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = radix_sort_pairs(keys, vals, keys2, vals2, hist, n, passes, stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_segment_sums, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, keys, vals, contrib, n,
+                       id_bits, none, grad_refl, grad_z);
+    return hipGetLastError();
+}
 
 hipError_t launch_backward(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
                            const int32_t* sub_tri, int sub_stride, const float* grad_wf, float* grad_refl,

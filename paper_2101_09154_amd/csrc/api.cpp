@@ -151,13 +151,26 @@ struct vls_context_s {
         BatchDev bd;
         int max_bins = 0;
     };
-    std::vector<Batch> batches;  // uploaded segment tables, reused by content
-    int* cand = nullptr;         // cone-pass candidate lists, grown on demand
-    long long cand_pulses = 0;
-    int* ew = nullptr;           // echo-width list of returns + counter, grown on demand
-    long long ew_entries = 0;
-    unsigned char* tlw = nullptr;  // two-level simulate: subrays, waveform and t0 not asked for, grown on demand
-    size_t tlw_bytes = 0;
+    std::vector<Batch> batches;  // uploaded segment tables (read-only), reused by content
+    // Per-stream workspaces: every stream the context is used with gets its own,
+    // grown on demand by stream-ordered allocations on that stream, so calls on
+    // different streams never share scratch memory and growing one waits for
+    // nothing but earlier work on its own stream.
+    struct Workspace {
+        hipStream_t stream = nullptr;
+        int* cand = nullptr;                // cone-pass workspace (cone_ws_*)
+        size_t cand_bytes = 0;
+        int* ew = nullptr;                  // echo-width list of returns + counter
+        size_t ew_bytes = 0;
+        unsigned char* tlw = nullptr;       // two-level simulate: subrays, waveform and t0 not asked for
+        size_t tlw_bytes = 0;
+        unsigned char* adw = nullptr;       // adjoint in fixed summation order: entries and sort buffers
+        size_t adw_bytes = 0;
+        unsigned long long* ctr = nullptr;  // the batched launch's work counter
+        size_t ctr_bytes = 0;
+    };
+    std::vector<std::unique_ptr<Workspace>> workspaces;
+    bool deterministic = false;  // the adjoint sums in a fixed order (vls_set_deterministic)
     struct SurveyTab {
         std::vector<double> key;   // the host table it was made from
         double* dev = nullptr;
@@ -177,9 +190,10 @@ struct vls_context_s {
                 (void)hipEventDestroy(e.first);
                 (void)hipEventDestroy(e.second);
             }
-        (void)hipFree(cand);
-        (void)hipFree(ew);
-        (void)hipFree(tlw);
+        for (auto& w : workspaces)
+            for (void* q : {(void*)w->cand, (void*)w->ew, (void*)w->tlw, (void*)w->adw, (void*)w->ctr})
+                if (q) (void)hipFreeAsync(q, nullptr);
+        (void)hipDeviceSynchronize();
         for (auto& t : surveys) (void)hipFree(t.dev);
         for (auto& kv : patterns) (void)hipFree(kv.second);
         for (auto& b : batches) (void)hipFree(b.dev);
@@ -242,13 +256,15 @@ struct vls_graph_s {
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int* cand = nullptr;
+    int* cand = nullptr;                // the graph's own cone-pass workspace
+    unsigned long long* ctr = nullptr;  // and its own work counter for a batched launch
     ~vls_graph_s()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cs) (void)hipStreamDestroy(cs);
         (void)hipFree(cand);
+        (void)hipFree(ctr);
     }
 };
 
@@ -538,17 +554,50 @@ vls_status batch_tables(vls_context ctx, const Prepared& pr, vls_context_s::Batc
     return VLS_OK;
 }
 
-// Candidate workspace for n pulses (allocated outside any capture).
-vls_status cone_workspace(vls_context ctx, long long n)
+// Grow a workspace block to `need` bytes in stream order: the old block is
+// freed after the work already queued on s (its only user) and the new one is
+// usable by work queued after this call.
+template <class T>
+vls_status ws_grow(T*& p, size_t& have, size_t need, hipStream_t s, const char* what)
 {
-    if (!ctx->cfg.cone || n <= ctx->cand_pulses) return VLS_OK;
-    VLS_HIP(hipDeviceSynchronize(), "workspace sync");
-    (void)hipFree(ctx->cand);
-    ctx->cand = nullptr;
-    ctx->cand_pulses = 0;
-    VLS_HIP(hipMalloc(&ctx->cand, sizeof(int) * cone_ws_ints(n)), "candidate workspace");
-    ctx->cand_pulses = n;
+    if (p && need <= have) return VLS_OK;
+    if (p) {
+        VLS_HIP(hipFreeAsync(p, s), what);
+        p = nullptr;
+        have = 0;
+    }
+    void* q = nullptr;
+    VLS_HIP(hipMallocAsync(&q, need < 256 ? 256 : need, s), what);
+    p = static_cast<T*>(q);
+    have = need < 256 ? 256 : need;
     return VLS_OK;
+}
+
+// The workspace of stream s (made on first use).
+vls_status stream_ws(vls_context ctx, hipStream_t s, vls_context_s::Workspace*& out)
+{
+    for (auto& w : ctx->workspaces)
+        if (w->stream == s) {
+            out = w.get();
+            return VLS_OK;
+        }
+    std::unique_ptr<vls_context_s::Workspace> w(new vls_context_s::Workspace());
+    w->stream = s;
+    vls_status st = ws_grow(w->ctr, w->ctr_bytes, 64, s, "counter workspace");
+    if (st != VLS_OK) return st;
+    out = w.get();
+    ctx->workspaces.push_back(std::move(w));
+    return VLS_OK;
+}
+
+// Stream s's workspace with room for the cone pass of n pulses (eager calls only:
+// a captured graph brings its own).
+vls_status cone_workspace(vls_context ctx, long long n, hipStream_t s, vls_context_s::Workspace*& w)
+{
+    vls_status st = stream_ws(ctx, s, w);
+    if (st != VLS_OK) return st;
+    if (!ctx->cfg.cone || n <= 0) return VLS_OK;
+    return ws_grow(w->cand, w->cand_bytes, sizeof(int) * cone_ws_ints(n), s, "candidate workspace");
 }
 
 // The ranging error of every segment's returns, once they are found.
@@ -1198,22 +1247,23 @@ vls_status vls_trace(vls_context ctx, vls_scene scene, const vls_scanner_desc* s
             }
             return VLS_OK;
         }
-        if ((st = cone_workspace(ctx, pulses->n_pulses)) != VLS_OK) return st;
+        vls_context_s::Workspace* ws = nullptr;
+        if ((st = cone_workspace(ctx, pulses->n_pulses, (hipStream_t)stream, ws)) != VLS_OK) return st;
         SceneDev sd = scene_dev(scene);
         if (ctx->cfg.cone && pulses->n_pulses > 0) {
             vls_context_s::Batch* bt = nullptr;
             if (pr.seg_sc.size() > 1 && (st = batch_tables(ctx, pr, bt)) != VLS_OK) return st;
             const long long n = pulses->n_pulses;
-            int* list = cone_ws_list(ctx->cand, n);
-            unsigned long long* ctr = cone_ws_ctr(ctx->cand, n);
-            double* basis = cone_ws_basis(ctx->cand, n);
-            hipError_t e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, n, ctx->cfg, nullptr, list, ctr, basis,
+            int* list = cone_ws_list(ws->cand, n);
+            unsigned long long* ctr = cone_ws_ctr(ws->cand, n);
+            double* basis = cone_ws_basis(ws->cand, n);
+            hipError_t e = launch_cone(sd, max_tan(pr), pd, ws->cand, 0, n, ctx->cfg, nullptr, list, ctr, basis,
                                        (hipStream_t)stream);
             if (e != hipSuccess) return hip_fail(e, "cone launch");
-            e = launch_packets(sd, pr.sc[0], bt ? bt->bd : BatchDev{}, pd, ctx->cand, list, ctr, 0,
+            e = launch_packets(sd, pr.sc[0], bt ? bt->bd : BatchDev{}, pd, ws->cand, list, ctr, 0,
                                (hipStream_t)stream);
             if (e != hipSuccess) return hip_fail(e, "packet launch");
-            pd.cand = ctx->cand;
+            pd.cand = ws->cand;
             pd.basis = basis;
         }
         for (size_t s = 0; s + 1 < pr.off.size(); ++s) {
@@ -1430,21 +1480,19 @@ vls_status vls_echo_width(vls_context ctx, const vls_scanner_desc* scanners, int
         if (!aligned(width_ns, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned width_ns");
         // workspace: one list entry per return slot, then a 64-bit counter
         const long long entries = n * (long long)pr.K;
-        if (entries > ctx->ew_entries) {
-            (void)hipFree(ctx->ew);
-            ctx->ew = nullptr;
-            ctx->ew_entries = 0;
-            VLS_HIP(hipMalloc(&ctx->ew, sizeof(int) * (size_t)(entries + (entries & 1) + 2)), "echo-width workspace");
-            ctx->ew_entries = entries;
-        }
-        unsigned long long* ctr = reinterpret_cast<unsigned long long*>(ctx->ew + entries + (entries & 1));
+        vls_context_s::Workspace* ws = nullptr;
+        if ((st = stream_ws(ctx, (hipStream_t)stream, ws)) != VLS_OK) return st;
+        if ((st = ws_grow(ws->ew, ws->ew_bytes, sizeof(int) * (size_t)(entries + (entries & 1) + 2), (hipStream_t)stream,
+                          "echo-width workspace")) != VLS_OK)
+            return st;
+        unsigned long long* ctr = reinterpret_cast<unsigned long long*>(ws->ew + entries + (entries & 1));
         for (size_t g = 0; g + 1 < pr.off.size(); ++g) {
             const vls_scanner_desc& d = scanners[pr.seg_sc[g]];
             // start width: the pulse's standard deviation (for Eq. 3 that of a
             // Gaussian of the same width parameter), in bins
             const float s0 = (float)(d.pulse_width_ns / (2.0 * std::sqrt(2.0 * std::log(2.0))) / d.bin_ns);
             hipError_t e = launch_echo_width(pr.sc[pr.seg_sc[g]], out->waveform, out->n_returns, out->ret_bin, s0,
-                                             pr.off[g], pr.off[g + 1] - pr.off[g], ctx->ew, ctr, width_ns,
+                                             pr.off[g], pr.off[g + 1] - pr.off[g], ws->ew, ctr, width_ns,
                                              (hipStream_t)stream);
             if (e != hipSuccess) return hip_fail(e, "echo-width launch");
         }
@@ -1454,9 +1502,12 @@ vls_status vls_echo_width(vls_context ctx, const vls_scanner_desc* scanners, int
     }
 }
 
+// ws: when not null, gets stream s's workspace, grown for the call (eager
+// calls; a graph capture passes null and brings its own).
 static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners,
                                    int32_t n_scanners, const vls_pulse_batch* pulses, const vls_outputs* out,
-                                   Prepared& pr, vls_context_s::Batch*& bt, int& blocks, bool allow_tl = false)
+                                   Prepared& pr, vls_context_s::Batch*& bt, int& blocks, hipStream_t s,
+                                   vls_context_s::Workspace** ws, bool allow_tl = false)
 {
     vls_status st = prepare(ctx, scanners, n_scanners, pulses, pr);
     if (st != VLS_OK) return st;
@@ -1466,8 +1517,9 @@ static vls_status simulate_prepare(vls_context ctx, vls_scene scene, const vls_s
         return fail(VLS_ERR_INVALID_ARG, "simulate needs n_returns, ret_range, ret_amplitude and ret_bin");
     bt = nullptr;
     blocks = 0;
+    if (ws && (st = stream_ws(ctx, s, *ws)) != VLS_OK) return st;
     if (scene->tl) return VLS_OK;
-    if ((st = cone_workspace(ctx, pulses->n_pulses)) != VLS_OK) return st;
+    if (ws && (st = cone_workspace(ctx, pulses->n_pulses, s, *ws)) != VLS_OK) return st;
     if (pulses->n_pulses > 0 && pulses->n_segments > 0) {
         if ((st = batch_tables(ctx, pr, bt)) != VLS_OK) return st;
         blocks = ctx->cfg.persistent_blocks > 0 ? ctx->cfg.persistent_blocks
@@ -1508,9 +1560,11 @@ static hipError_t prof_end(vls_context ctx, hipStream_t s, std::pair<hipEvent_t,
 // cand: candidate workspace of at least n_pulses entries (the context's, or a graph's own)
 // allow_prof: timing events may be recorded (not for the allocation-free entry
 // point, whose caller may forbid creating them)
+// cand, ctr: the cone-pass workspace and the batched launch's work counter (a
+// stream's workspace, a graph's own, or the allocation-free entry point's array)
 static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepared& pr, const vls_pulse_batch* pulses,
                                    const vls_outputs* out, vls_context_s::Batch* bt, int blocks, hipStream_t s,
-                                   int* cand, bool allow_prof = true)
+                                   int* cand, unsigned long long* batch_ctr, bool allow_prof = true)
 {
     if (pulses->n_pulses == 0) return VLS_OK;
     OutDev od = out_dev(out, pr.S_stride);
@@ -1522,6 +1576,11 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
     if (allow_prof && ctx->prof && hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
     const bool prof = allow_prof && ctx->prof && cap == hipStreamCaptureStatusNone;
     std::pair<hipEvent_t, hipEvent_t> ev{};
+    BatchDev bd{};
+    if (bt) {
+        bd = bt->bd;
+        bd.counter = batch_ctr;
+    }
     if (ctx->cfg.cone) {
         if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
         const long long n = pulses->n_pulses;
@@ -1533,7 +1592,7 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
         if (prof && (e = prof_end(ctx, s, ev, ctx->prof_cone)) != hipSuccess) return hip_fail(e, "timing event");
         // pulses whose candidate list overflowed: one wavefront walks each pulse's subrays together
         if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
-        e = launch_packets(sd, pr.sc[0], bt ? bt->bd : BatchDev{}, pd, cand, list, ctr, 0, s);
+        e = launch_packets(sd, pr.sc[0], bd, pd, cand, list, ctr, 0, s);
         if (e != hipSuccess) return hip_fail(e, "packet launch");
         if (prof && (e = prof_end(ctx, s, ev, ctx->prof_packets)) != hipSuccess) return hip_fail(e, "timing event");
         pd.cand = cand;
@@ -1541,7 +1600,7 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
     }
     if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
     if (!bt) e = launch_simulate(sd, pr.sc[0], pd, od, 0, pulses->n_pulses, 1, ctx->cfg, s);
-    else e = launch_persistent(sd, bt->bd, pr.n_bins, staged_slots(pr), pd, od, ctx->cfg, blocks, s);
+    else e = launch_persistent(sd, bd, pr.n_bins, staged_slots(pr), pd, od, ctx->cfg, blocks, s);
     if (e != hipSuccess) return hip_fail(e, "simulate launch");
     if (prof && (e = prof_end(ctx, s, ev, ctx->prof_fused)) != hipSuccess) return hip_fail(e, "timing event");
     if ((e = range_noise_all(pr, od, s)) != hipSuccess) return hip_fail(e, "ranging error launch");
@@ -1552,7 +1611,8 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
 // returns from them; subray arrays, waveform and window origins the caller did
 // not ask for live in a context workspace.
 static vls_status simulate_two_level(vls_context ctx, vls_scene scene, const Prepared& pr,
-                                     const vls_pulse_batch* pulses, const vls_outputs* out, hipStream_t s)
+                                     const vls_pulse_batch* pulses, const vls_outputs* out, hipStream_t s,
+                                     vls_context_s::Workspace* ws)
 {
     const long long n = pulses->n_pulses;
     if (n == 0) return VLS_OK;
@@ -1569,15 +1629,11 @@ static vls_status simulate_two_level(vls_context ctx, vls_scene scene, const Pre
     const size_t o_pow = od.sub_power ? 0 : carve(4 * ns);
     const size_t o_wf = od.wf ? 0 : carve(4 * (size_t)n * pr.n_bins);
     const size_t o_t0 = od.t0 ? 0 : carve(8 * (size_t)n);
-    if (need > ctx->tlw_bytes) {
-        VLS_HIP(hipDeviceSynchronize(), "workspace sync");
-        (void)hipFree(ctx->tlw);
-        ctx->tlw = nullptr;
-        ctx->tlw_bytes = 0;
-        VLS_HIP(hipMalloc(&ctx->tlw, need), "two-level workspace");
-        ctx->tlw_bytes = need;
+    if (need > 0) {
+        vls_status st = ws_grow(ws->tlw, ws->tlw_bytes, need, s, "two-level workspace");
+        if (st != VLS_OK) return st;
     }
-    unsigned char* w = ctx->tlw;
+    unsigned char* w = ws->tlw;
     if (!od.sub_tri) od.sub_tri = reinterpret_cast<int32_t*>(w + o_tri);
     if (!od.sub_range) od.sub_range = reinterpret_cast<double*>(w + o_rng);
     if (!od.sub_power) od.sub_power = reinterpret_cast<float*>(w + o_pow);
@@ -1603,10 +1659,12 @@ vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc
         Prepared pr;
         vls_context_s::Batch* bt = nullptr;
         int blocks = 0;
-        vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, bt, blocks, true);
+        vls_context_s::Workspace* ws = nullptr;
+        const hipStream_t s = (hipStream_t)stream;
+        vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, bt, blocks, s, &ws, true);
         if (st != VLS_OK) return st;
-        if (scene->tl) return simulate_two_level(ctx, scene, pr, pulses, out, (hipStream_t)stream);
-        return simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, (hipStream_t)stream, ctx->cand);
+        if (scene->tl) return simulate_two_level(ctx, scene, pr, pulses, out, s, ws);
+        return simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, s, ws->cand, ws->ctr);
     } catch (const std::exception& e) {
         return fail(VLS_ERR_INTERNAL, e.what());
     }
@@ -1648,7 +1706,7 @@ vls_status vls_simulate_noalloc(vls_context ctx, vls_scene scene, const vls_scan
         hipError_t e = launch_store_pattern(tables[0].data(), (int)tables[0].size(), pattern, s);
         if (e != hipSuccess) return hip_fail(e, "subray table store");
         pr.sc[0].pattern = pattern;
-        return simulate_enqueue(ctx, scene, pr, pulses, out, nullptr, 0, s, cand, false);
+        return simulate_enqueue(ctx, scene, pr, pulses, out, nullptr, 0, s, cand, nullptr, false);
     } catch (const std::exception& e) {
         return fail(VLS_ERR_INTERNAL, e.what());
     }
@@ -1673,15 +1731,16 @@ vls_status vls_trace_counts(vls_context ctx, vls_scene scene, const vls_scanner_
         od.counts = dc;
         PulsesDev pd = pulses_dev(pulses);
         SceneDev sd = scene_dev(scene);
-        if ((st = cone_workspace(ctx, pulses->n_pulses)) != VLS_OK) {
+        vls_context_s::Workspace* ws = nullptr;
+        if ((st = cone_workspace(ctx, pulses->n_pulses, s, ws)) != VLS_OK) {
             (void)hipFree(dc);
             return st;
         }
         if (e == hipSuccess && ctx->cfg.cone && pulses->n_pulses > 0) {
-            double* basis = cone_ws_basis(ctx->cand, pulses->n_pulses);
-            e = launch_cone(sd, max_tan(pr), pd, ctx->cand, 0, pulses->n_pulses, ctx->cfg, dc, nullptr, nullptr, basis,
+            double* basis = cone_ws_basis(ws->cand, pulses->n_pulses);
+            e = launch_cone(sd, max_tan(pr), pd, ws->cand, 0, pulses->n_pulses, ctx->cfg, dc, nullptr, nullptr, basis,
                             s);
-            pd.cand = ctx->cand;
+            pd.cand = ws->cand;
             pd.basis = basis;
         }
         for (size_t g = 0; e == hipSuccess && g + 1 < pr.off.size(); ++g)
@@ -1715,13 +1774,34 @@ vls_status vls_waveform_backward(vls_context ctx, vls_scene scene, const vls_sca
         if (!aligned(subray_tri, 4) || !aligned(grad_waveform, 4) || !aligned(grad_reflectance, 4) ||
             !aligned(grad_vertex_z, 4))
             return fail(VLS_ERR_INVALID_ARG, "misaligned array");
-        hipError_t e = launch_backward(scene_dev(scene), pr.sc[0], pulses_dev(pulses), subray_tri, pr.S_stride,
-                                       grad_waveform, grad_reflectance, grad_vertex_z, scene->b.n_vert, ctx->cfg,
-                                       (hipStream_t)stream);
+        const hipStream_t s = (hipStream_t)stream;
+        hipError_t e;
+        if (ctx->deterministic) {
+            vls_context_s::Workspace* ws = nullptr;
+            if ((st = stream_ws(ctx, s, ws)) != VLS_OK) return st;
+            if (pulses->n_pulses > 0 &&
+                (st = ws_grow(ws->adw, ws->adw_bytes, backward_det_bytes(pulses->n_pulses, pr.sc[0].S), s,
+                              "adjoint workspace")) != VLS_OK)
+                return st;
+            e = launch_backward_det(scene_dev(scene), pr.sc[0], pulses_dev(pulses), subray_tri, pr.S_stride,
+                                    grad_waveform, grad_reflectance, grad_vertex_z, scene->b.n_vert, ctx->cfg, ws->adw,
+                                    s);
+        } else {
+            e = launch_backward(scene_dev(scene), pr.sc[0], pulses_dev(pulses), subray_tri, pr.S_stride, grad_waveform,
+                                grad_reflectance, grad_vertex_z, scene->b.n_vert, ctx->cfg, s);
+        }
         return e == hipSuccess ? VLS_OK : hip_fail(e, "backward launch");
     } catch (const std::exception& e) {
         return fail(VLS_ERR_INTERNAL, e.what());
     }
+}
+
+vls_status vls_set_deterministic(vls_context ctx, int32_t on)
+{
+    if (!ctx) return fail(VLS_ERR_INVALID_ARG, "context is NULL");
+    if (on != 0 && on != 1) return fail(VLS_ERR_INVALID_ARG, "on must be 0 or 1");
+    ctx->deterministic = on != 0;
+    return VLS_OK;
 }
 
 vls_status vls_graph_capture(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
@@ -1733,16 +1813,19 @@ vls_status vls_graph_capture(vls_context ctx, vls_scene scene, const vls_scanner
         Prepared pr;
         vls_context_s::Batch* bt = nullptr;
         int blocks = 0;
-        vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, bt, blocks);
+        vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, bt, blocks, nullptr,
+                                         nullptr);
         if (st != VLS_OK) return st;
         std::unique_ptr<vls_graph_s> g(new vls_graph_s());
         g->ctx = ctx;
-        // the graph owns its candidate workspace: the context's may be reallocated later
+        // the graph owns its candidate workspace and work counter: graphs and eager
+        // calls replayed on other streams must not share them
         if (ctx->cfg.cone && pulses->n_pulses > 0)
             VLS_HIP(hipMalloc(&g->cand, sizeof(int) * cone_ws_ints(pulses->n_pulses)), "graph workspace");
+        if (bt) VLS_HIP(hipMalloc(&g->ctr, 64), "graph counter");
         VLS_HIP(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking), "capture stream");
         VLS_HIP(hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal), "begin capture");
-        st = simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, g->cs, g->cand);
+        st = simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, g->cs, g->cand, g->ctr);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(g->cs, &gr);
         if (st != VLS_OK) {
@@ -1822,10 +1905,11 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
         Prepared pr0;
         vls_context_s::Batch* bt = nullptr;
         int blocks = 0;
-        vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr0, bt, blocks);
+        hipStream_t s = (hipStream_t)stream;
+        vls_context_s::Workspace* ws = nullptr;
+        vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr0, bt, blocks, s, &ws);
         if (st != VLS_OK) return st;
         const std::string key = tune_key(scene, pr0, pulses);
-        hipStream_t s = (hipStream_t)stream;
         const LaunchCfg entry = ctx->cfg;
         hipEvent_t e0, e1;
         VLS_HIP(hipEventCreate(&e0), "event");
@@ -1835,16 +1919,17 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             Prepared pr;
             vls_context_s::Batch* b2 = nullptr;
             int bl = 0;
-            vls_status r = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, b2, bl);
+            vls_status r = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, b2, bl, s, &ws);
             if (r != VLS_OK) return r;
-            if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s, ctx->cand)) != VLS_OK) return r;
+            if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s, ws->cand, ws->ctr)) != VLS_OK) return r;
             // the fastest of three pairs of launches: single timings vary by a few
             // per cent, as much as the configurations differ
             ms = INFINITY;
             for (int g = 0; g < 3; ++g) {
                 VLS_HIP(hipEventRecord(e0, s), "event");
                 for (int i = 0; i < 2; ++i)
-                    if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s, ctx->cand)) != VLS_OK) return r;
+                    if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s, ws->cand, ws->ctr)) != VLS_OK)
+                        return r;
                 VLS_HIP(hipEventRecord(e1, s), "event");
                 VLS_HIP(hipEventSynchronize(e1), "event");
                 float f = 0.0f;

@@ -533,6 +533,27 @@ hipError_t mesh_check(const BvhBuffers& b, hipStream_t stream, unsigned& bad)
     return hipStreamSynchronize(stream);
 }
 
+long long radix_sort_hist_words(long long n) { return 256ll * ((n + kSortTile - 1) / kSortTile); }
+
+hipError_t radix_sort_pairs(unsigned long long* keys, int32_t* vals, unsigned long long* keys2, int32_t* vals2,
+                            unsigned* hist, long long n, int passes, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const int n_tiles = (int)((n + kSortTile - 1) / kSortTile);
+    unsigned long long *kin = keys, *kout = keys2;
+    int32_t *vin = vals, *vout = vals2;
+    for (int pass = 0; pass < passes; ++pass) {
+        int shift = 8 * pass;
+        hipLaunchKernelGGL(k_hist, dim3(n_tiles), dim3(kSortThreads), 0, stream, kin, n, shift, hist, n_tiles);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, stream, hist, 256ll * n_tiles);
+        hipLaunchKernelGGL(k_scatter, dim3(n_tiles), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n, shift,
+                           hist, n_tiles);
+        unsigned long long* tk = kin; kin = kout; kout = tk;
+        int32_t* tv = vin; vin = vout; vout = tv;
+    }
+    return hipGetLastError();
+}
+
 hipError_t bvh_build(BvhBuffers& b, hipStream_t stream, std::string& err)
 {
     const long long n = b.n_tri;
@@ -556,19 +577,8 @@ hipError_t bvh_build(BvhBuffers& b, hipStream_t stream, std::string& err)
         if ((e = bounds_pass(b, ub, stream)) != hipSuccess) { (void)fail(e, "bounds"); break; }
         hipLaunchKernelGGL(k_morton, dim3(grid_for(n, 256)), dim3(256), 0, stream, b.verts, b.tri_idx, n, b.bounds,
                            b.morton, vals);
-        unsigned long long *kin = b.morton, *kout = keys2;
-        int32_t *vin = vals, *vout = vals2;
-        for (int pass = 0; pass < 8; ++pass) {
-            int shift = 8 * pass;
-            hipLaunchKernelGGL(k_hist, dim3(n_tiles), dim3(kSortThreads), 0, stream, kin, n, shift, hist, n_tiles);
-            hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, stream, hist, 256ll * n_tiles);
-            hipLaunchKernelGGL(k_scatter, dim3(n_tiles), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n, shift,
-                               hist, n_tiles);
-            unsigned long long* tk = kin; kin = kout; kout = tk;
-            int32_t* tv = vin; vin = vout; vout = tv;
-        }
         // 8 passes: the sorted data is back in b.morton / vals
-        if ((e = hipGetLastError()) != hipSuccess) { (void)fail(e, "sort"); break; }
+        if ((e = radix_sort_pairs(b.morton, vals, keys2, vals2, hist, n, 8, stream)) != hipSuccess) { (void)fail(e, "sort"); break; }
         if (n > 1) {
             hipLaunchKernelGGL(k_karras, dim3(grid_for(n - 1, 256)), dim3(256), 0, stream, b.morton, n, b.nodes,
                                b.leaf_parent, b.node_parent);

@@ -232,6 +232,12 @@ struct BvhBuffers {
 // 0 for an index out of range, bit 1 for a non-finite coordinate.  Synchronises.
 hipError_t mesh_check(const BvhBuffers& b, hipStream_t stream, unsigned& bad);
 hipError_t bvh_build(BvhBuffers& b, hipStream_t stream, std::string& err);
+// Stable LSD radix sort of (key, value) pairs by the low 8 * passes bits of the
+// keys (passes even: the result ends in keys / vals; the second pair of arrays
+// is the ping-pong buffer); hist holds radix_sort_hist_words(n) words.
+long long radix_sort_hist_words(long long n);
+hipError_t radix_sort_pairs(unsigned long long* keys, int32_t* vals, unsigned long long* keys2, int32_t* vals2,
+                            unsigned* hist, long long n, int passes, hipStream_t stream);
 hipError_t bvh_refit(BvhBuffers& b, hipStream_t stream);
 hipError_t bvh_update_vertices(BvhBuffers& b, hipStream_t stream);
 
@@ -248,6 +254,13 @@ hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int m
 hipError_t launch_backward(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
                            const int32_t* sub_tri, int sub_stride, const float* grad_wf, float* grad_refl,
                            float* grad_z, long long n_vert, const LaunchCfg& cfg, hipStream_t stream);
+// The adjoint with sums in a fixed order (per-entry contributions, a stable sort
+// by parameter, sums of each run in entry order): bitwise repeatable.  ws holds
+// backward_det_bytes(n_pulses, S) bytes.
+size_t backward_det_bytes(long long n_pulses, int S);
+hipError_t launch_backward_det(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
+                               const int32_t* sub_tri, int sub_stride, const float* grad_wf, float* grad_refl,
+                               float* grad_z, long long n_vert, const LaunchCfg& cfg, void* ws, hipStream_t stream);
 // Cone pass: pulses [first, first + count), cone slope tan_max (largest over the
 // scanners in use).  Writes cand[p * (kCandMax + 1) ...]; counts (optional)
 // accumulates node visits into counts[1].

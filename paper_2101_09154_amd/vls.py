@@ -128,6 +128,7 @@ _SIGS = {
     "vls_generate_pulses": ([P, P, ctypes.c_int64, ctypes.c_int64, P, P, P], i32),
     "vls_simulate": ([P, P, P, i32, P, P, P], i32),
     "vls_simulate_noalloc": ([P, P, P, P, P, P], i32),
+    "vls_set_deterministic": ([P, i32], i32),
     "vls_set_launch_config": ([P, P], i32),
     "vls_get_launch_config": ([P, P], i32),
     "vls_synchronize": ([P, P], i32),
@@ -378,6 +379,10 @@ class Context:
     def set_launch_config(self, block_waves=1, stack_lds=16, persistent_blocks=0, pack=0, cone=1):
         c = LaunchConfig(block_waves, stack_lds, persistent_blocks, pack, cone, 0)
         _check(lib().vls_set_launch_config(self._h, ctypes.byref(c)))
+
+    def set_deterministic(self, on=True):
+        """Fixed summation order for the adjoint (bitwise repeatable gradients)."""
+        _check(lib().vls_set_deterministic(self._h, 1 if on else 0))
 
     def launch_config(self):
         c = LaunchConfig()
