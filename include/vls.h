@@ -388,7 +388,7 @@ vls_status vls_returns(vls_context ctx, const vls_scanner_desc* scanners, int32_
 
 /* Scan deflectors (Sec. 3.3, Fig. 7) and platforms (Sec. 3.2). */
 enum { VLS_DEFLECT_POLYGON = 0, VLS_DEFLECT_SWING = 1, VLS_DEFLECT_CONIC = 2, VLS_DEFLECT_FIBRE = 3 };
-enum { VLS_PLATFORM_LINEAR = 0, VLS_PLATFORM_MULTICOPTER = 1 };
+enum { VLS_PLATFORM_LINEAR = 0, VLS_PLATFORM_MULTICOPTER = 1, VLS_PLATFORM_MULTICOPTER_SMOOTH = 2 };
 
 /* A survey: a platform (Sec. 3.2) carrying a scanner with a deflector (Sec.
  * 3.3).  The paper gives the platforms' and deflectors' behaviour but no
@@ -405,6 +405,21 @@ enum { VLS_PLATFORM_LINEAR = 0, VLS_PLATFORM_MULTICOPTER = 1 };
  *   speed^2 / accel speeds up over its first half and slows down over its
  *   second); turns take no time; level; yaw is the leg's heading, or, with
  *   leg_yaw, linear in the time on the leg from its start to its end value;
+ *   Multicopter platform with smooth turns (it banks to turn at the
+ *   waypoints instead of stopping there): a coordinated turn at each interior
+ *   waypoint on the circular arc tangent to both legs, of radius
+ *   r = v^2 / (g tan b) (v = speed_mps, b = bank_angle_rad, g = 9.80665 m/s^2),
+ *   from W - s u to W + s w (u, w the unit directions into and out of W,
+ *   s = r tan(theta / 2), theta = acos(u . w)), in the plane of the two legs;
+ *   from rest at the first waypoint it speeds up at accel_mps2 to v, keeps v
+ *   along the straight parts and the arcs, and slows down to rest at the last
+ *   waypoint, where it stays; heading along the horizontal direction of
+ *   motion; level on the straight parts, banked by b toward the turn's centre
+ *   on an arc (a platform direction (x, y, z) becomes
+ *   (x, y cos l + z sin l, -y sin l + z cos l), l = +b for a turn to the left,
+ *   -b to the right, before the heading); every leg must hold its arcs (s at
+ *   each end) and, on the first and the last leg, the ramp v^2 / (2 accel),
+ *   no turn may exceed 179 degrees, and leg_yaw must be NULL;
  *   platform frame x forward, y left, z up; with A = scan_angle_rad and
  *   f = scan_freq_hz the beam points along (0, sin a, -cos a) with
  *     POLYGON a = -A + 2A frac(f t)        (parallel lines, even density)
@@ -433,7 +448,8 @@ typedef struct {
     uint64_t seed;
     double accel_mps2;         /* Multicopter: > 0 (with speed_mps > 0) when n_waypoints >= 2 */
     const double* leg_yaw;     /* Multicopter: NULL, or host [n_waypoints - 1][2] start and end
-                                  yaw (rad, finite) of each leg; NULL for LinearPath */
+                                  yaw (rad, finite) of each leg; NULL for the other platforms */
+    double bank_angle_rad;     /* Multicopter with smooth turns: bank angle in (0, pi/2) */
 } vls_survey_desc;
 
 /* Pulses [first, first + count) of a survey, on the device, in the layout

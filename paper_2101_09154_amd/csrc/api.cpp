@@ -1366,6 +1366,86 @@ static vls_status copter_table(const vls_survey_desc* sv, std::vector<double>& t
     return VLS_OK;
 }
 
+// Pieces of a Multicopter path with smooth turns (Sec. 3.2 banked turns, read as
+// coordinated turns): each leg's straight part, and at each interior waypoint
+// the circular arc of radius v^2 / (g tan b) tangent to both legs; rows of
+// kSmoothRow doubles (see vls_internal.h).  total: the path's length.
+static vls_status smooth_table(const vls_survey_desc* sv, std::vector<double>& tab, int& n_piece, double& total)
+{
+    const int nw = sv->n_waypoints;
+    const double v = sv->speed_mps, g = 9.80665;
+    const double r = v * v / (g * std::tan(sv->bank_angle_rad));
+    const double ramp = v * v / (2.0 * sv->accel_mps2);
+    std::vector<double> len(nw > 1 ? nw - 1 : 1), s_at(nw, 0.0);
+    std::vector<double> dir(3 * (size_t)std::max(nw - 1, 1));
+    for (int j = 0; j + 1 < nw; ++j) {
+        const double* a = sv->waypoints + 3 * j;
+        const double* b = sv->waypoints + 3 * (j + 1);
+        for (int c = 0; c < 3; ++c)
+            if (!std::isfinite(a[c]) || !std::isfinite(b[c])) return fail(VLS_ERR_INVALID_ARG, "non-finite waypoint");
+        const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+        len[j] = std::sqrt(dx * dx + dy * dy + dz * dz);
+        if (!(len[j] > 0.0)) return fail(VLS_ERR_INVALID_ARG, "consecutive waypoints coincide");
+        dir[3 * j] = dx / len[j];
+        dir[3 * j + 1] = dy / len[j];
+        dir[3 * j + 2] = dz / len[j];
+    }
+    std::vector<double> theta(nw, 0.0);
+    for (int i = 1; i + 1 < nw; ++i) {
+        const double* u = &dir[3 * (i - 1)];
+        const double* w = &dir[3 * i];
+        double dot = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+        dot = std::min(1.0, std::max(-1.0, dot));
+        theta[i] = std::acos(dot);
+        if (theta[i] > 179.0 * M_PI / 180.0) return fail(VLS_ERR_INVALID_ARG, "a smooth turn may not exceed 179 degrees");
+        s_at[i] = r * std::tan(0.5 * theta[i]);
+    }
+    tab.clear();
+    n_piece = 0;
+    total = 0.0;
+    for (int j = 0; j + 1 < nw; ++j) {
+        const double need = s_at[j] + s_at[j + 1] + (j == 0 ? ramp : 0.0) + (j + 2 == nw ? ramp : 0.0);
+        if (!(need <= len[j]))
+            return fail(VLS_ERR_INVALID_ARG, "a leg is too short for its turns and ramps (smooth Multicopter)");
+        const double* a = sv->waypoints + 3 * j;
+        const double* d = &dir[3 * j];
+        double row[kSmoothRow] = {0.0};
+        row[0] = total;
+        row[1] = len[j] - s_at[j] - s_at[j + 1];
+        for (int c = 0; c < 3; ++c) {
+            row[5 + c] = a[c] + s_at[j] * d[c];
+            row[8 + c] = d[c];
+        }
+        tab.insert(tab.end(), row, row + kSmoothRow);
+        ++n_piece;
+        total = total + row[1];
+        if (j + 2 < nw && theta[j + 1] > 0.0) {
+            const double* b = sv->waypoints + 3 * (j + 1);
+            const double* w = &dir[3 * (j + 1)];
+            const double dot = std::min(1.0, std::max(-1.0, d[0] * w[0] + d[1] * w[1] + d[2] * w[2]));
+            double nv[3] = {w[0] - dot * d[0], w[1] - dot * d[1], w[2] - dot * d[2]};
+            const double nn = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            double arc[kSmoothRow] = {0.0};
+            arc[0] = total;
+            arc[1] = r * theta[j + 1];
+            arc[2] = 1.0;
+            arc[3] = r;
+            const double turn_z = d[0] * w[1] - d[1] * w[0];
+            arc[4] = turn_z > 0.0 ? sv->bank_angle_rad : (turn_z < 0.0 ? -sv->bank_angle_rad : 0.0);
+            for (int c = 0; c < 3; ++c) {
+                arc[11 + c] = nv[c] / nn;
+                arc[8 + c] = d[c];
+                arc[5 + c] = b[c] - s_at[j + 1] * d[c] + r * arc[11 + c];
+            }
+            tab.insert(tab.end(), arc, arc + kSmoothRow);
+            ++n_piece;
+            total = total + arc[1];
+        }
+    }
+    if (!std::isfinite(total)) return fail(VLS_ERR_INVALID_ARG, "survey too long");
+    return VLS_OK;
+}
+
 vls_status vls_generate_pulses(vls_context ctx, const vls_survey_desc* sv, int64_t first, int64_t count,
                                double* origins, float* directions, void* stream)
 {
@@ -1383,19 +1463,29 @@ vls_status vls_generate_pulses(vls_context ctx, const vls_survey_desc* sv, int64
             return fail(VLS_ERR_INVALID_ARG, "survey parameters must be finite (speed and noise >= 0)");
         if (sv->deflector == VLS_DEFLECT_FIBRE && sv->n_fibres < 2)
             return fail(VLS_ERR_INVALID_ARG, "a fibre array needs at least two fibres");
-        if (sv->platform != VLS_PLATFORM_LINEAR && sv->platform != VLS_PLATFORM_MULTICOPTER)
+        if (sv->platform != VLS_PLATFORM_LINEAR && sv->platform != VLS_PLATFORM_MULTICOPTER &&
+            sv->platform != VLS_PLATFORM_MULTICOPTER_SMOOTH)
             return fail(VLS_ERR_INVALID_ARG, "unknown platform");
         const bool copter = sv->platform == VLS_PLATFORM_MULTICOPTER;
-        if (!copter && sv->leg_yaw) return fail(VLS_ERR_INVALID_ARG, "leg_yaw is for the Multicopter platform");
-        if (copter && sv->n_waypoints >= 2 &&
+        const bool smooth = sv->platform == VLS_PLATFORM_MULTICOPTER_SMOOTH;
+        if (!copter && sv->leg_yaw)
+            return fail(VLS_ERR_INVALID_ARG, "leg_yaw is for the Multicopter platform without smooth turns");
+        if ((copter || smooth) && sv->n_waypoints >= 2 &&
             !(sv->speed_mps > 0.0 && sv->accel_mps2 > 0.0 && std::isfinite(sv->accel_mps2)))
             return fail(VLS_ERR_INVALID_ARG, "a moving Multicopter needs speed_mps > 0 and a finite accel_mps2 > 0");
+        if (smooth && !(sv->bank_angle_rad > 0.0 && sv->bank_angle_rad < 0.5 * M_PI))
+            return fail(VLS_ERR_INVALID_ARG, "smooth turns need a bank_angle_rad in (0, pi/2)");
         if (count == 0) return VLS_OK;
         if (!origins || !directions) return fail(VLS_ERR_INVALID_ARG, "origins and directions are required");
         if (!aligned(origins, 8) || !aligned(directions, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned output");
         const int nw = sv->n_waypoints;
         std::vector<double> tab;
-        if (copter) {
+        int n_piece = 0;
+        double path_len = 0.0;
+        if (smooth && nw >= 2) {
+            vls_status st = smooth_table(sv, tab, n_piece, path_len);
+            if (st != VLS_OK) return st;
+        } else if (copter) {
             vls_status st = copter_table(sv, tab);
             if (st != VLS_OK) return st;
         } else {
@@ -1457,6 +1547,9 @@ vls_status vls_generate_pulses(vls_context ctx, const vls_survey_desc* sv, int64
         d.t0 = sv->t0_s;
         d.noise = sv->platform_noise_m;
         d.seed = sv->seed;
+        d.n_piece = n_piece;
+        d.path_len = path_len;
+        d.t_end = smooth && nw >= 2 ? path_len / sv->speed_mps + sv->speed_mps / sv->accel_mps2 : 0.0;
         hipError_t e = launch_generate(d, dtab, first, count, origins, directions, (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(e, "pulse generation launch");
         return VLS_OK;

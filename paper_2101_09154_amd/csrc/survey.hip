@@ -2,7 +2,10 @@
 // deflectors), so that a scan needs no host arrays of origins and directions.
 //
 // The paper describes the platforms and deflectors and their patterns but gives
-// no formulas; the model here: pulse k leaves at t = t0 + k / prf; a LinearPath
+// no formulas; the model here: pulse k leaves at t = t0 + k / prf; a Multicopter
+// with smooth turns flies coordinated turns on arcs tangent to its legs (radius
+// v^2 / (g tan b)), banked toward each turn's centre, at its cruise speed
+// between the ramps from and to rest at the ends of the path; a LinearPath
 // platform covers its polyline of waypoints at constant speed from t = 0, stays
 // level, faces the current leg's horizontal direction, and stays at the last
 // waypoint afterwards (one waypoint: static, facing +x).  In the platform frame
@@ -60,8 +63,47 @@ __global__ __launch_bounds__(256) void k_generate(SurveyDev sv, const double* __
     const long long k = first + q;
     const double t = sv.t0 + (double)k / sv.prf;
     double pos[3] = {tab[0], tab[1], tab[2]};
-    double cy = 1.0, sy = 0.0;
-    if (sv.n_wp >= 2 && sv.platform == 1) {
+    double cy = 1.0, sy = 0.0, lean = 0.0;
+    if (sv.n_wp >= 2 && sv.platform == 2) {
+        // smooth turns: path length covered (ramp up, cruise, ramp down), then
+        // the piece that holds it (the last piece starting at or before it)
+        const double v = sv.speed, acc = sv.accel, tr = v / acc;
+        double sg;
+        if (t <= 0.0) sg = 0.0;
+        else if (t <= tr) sg = 0.5 * acc * t * t;
+        else if (t < sv.t_end - tr) sg = 0.5 * acc * tr * tr + v * (t - tr);
+        else if (t < sv.t_end) sg = sv.path_len - 0.5 * acc * (sv.t_end - t) * (sv.t_end - t);
+        else sg = sv.path_len;
+        int lo = 0, hi = sv.n_piece - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[kSmoothRow * mid] < sg) lo = mid;
+            else hi = mid - 1;
+        }
+        const double* pc = tab + kSmoothRow * lo;
+        double l = sg - pc[0];
+        if (l > pc[1]) l = pc[1];
+        if (l < 0.0) l = 0.0;
+        double dir[3];
+        if (pc[2] == 0.0) {
+            for (int i = 0; i < 3; ++i) {
+                pos[i] = pc[5 + i] + l * pc[8 + i];
+                dir[i] = pc[8 + i];
+            }
+        } else {
+            // on the arc: angle l / r from its start, centre pc[5..7], tangent
+            // at the start pc[8..10], toward the centre pc[11..13]
+            const double ph = l / pc[3], c = cos(ph), s = sin(ph);
+            for (int i = 0; i < 3; ++i) {
+                pos[i] = pc[5 + i] - pc[3] * c * pc[11 + i] + pc[3] * s * pc[8 + i];
+                dir[i] = c * pc[8 + i] + s * pc[11 + i];
+            }
+            lean = pc[4];
+        }
+        const double yaw = atan2(dir[1], dir[0]);
+        cy = cos(yaw);
+        sy = sin(yaw);
+    } else if (sv.n_wp >= 2 && sv.platform == 1) {
         // the last leg starting at or before t (the first leg before it)
         int lo = 0, hi = sv.n_wp - 2;
         while (lo < hi) {
@@ -123,6 +165,13 @@ __global__ __launch_bounds__(256) void k_generate(SurveyDev sv, const double* __
         d0 = 0.0;
         d1 = sin(ang);
         d2 = -cos(ang);
+    }
+    if (lean != 0.0) {
+        // banked toward the turn's centre
+        const double cl = cos(lean), sl = sin(lean);
+        const double y = d1 * cl + d2 * sl, z = -d1 * sl + d2 * cl;
+        d1 = y;
+        d2 = z;
     }
     double* o = origins + 3 * q;
     float* w = dirs + 3 * q;

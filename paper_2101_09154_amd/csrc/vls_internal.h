@@ -194,10 +194,20 @@ struct SurveyDev {
     int n_fibres;
     int platform;    // 0 LinearPath: table rows (x, y, z, path length, cos yaw, sin yaw);
                      // 1 Multicopter: rows (x, y, z, leg start time, leg duration,
-                     //   leg length, start yaw, end yaw)
+                     //   leg length, start yaw, end yaw);
+                     // 2 Multicopter with smooth turns: one row of kSmoothRow per
+                     //   piece of the path (see survey.hip), n_piece rows
     double speed, prf, freq, angle, t0, noise, accel;
     uint64_t seed;
+    int n_piece;         // smooth turns: pieces of the path
+    double path_len;     // smooth turns: length of the whole path
+    double t_end;        // smooth turns: arrival at the last waypoint
 };
+// A piece of a smooth-turn path: path length at its start, its length, 1 for an
+// arc (0 straight), radius, bank, start point (straight) or centre (arc),
+// direction (straight) or tangent at the start (arc), unit vector toward the
+// centre (arc), two unused.
+constexpr int kSmoothRow = 16;
 
 struct LaunchCfg {
     int block_waves = 1;

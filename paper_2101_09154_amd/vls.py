@@ -85,11 +85,11 @@ class SurveyDesc(ctypes.Structure):
     _fields_ = [("waypoints", P), ("n_waypoints", i32), ("deflector", i32), ("speed_mps", f64),
                 ("pulse_rate_hz", f64), ("scan_freq_hz", f64), ("scan_angle_rad", f64), ("n_fibres", i32),
                 ("platform", i32), ("t0_s", f64), ("platform_noise_m", f64), ("seed", ctypes.c_uint64),
-                ("accel_mps2", f64), ("leg_yaw", P)]
+                ("accel_mps2", f64), ("leg_yaw", P), ("bank_angle_rad", f64)]
 
 
 DEFLECTORS = {"polygon": 0, "swing": 1, "conic": 2, "fibre": 3}
-PLATFORMS = {"linear": 0, "multicopter": 1}
+PLATFORMS = {"linear": 0, "multicopter": 1, "multicopter_smooth": 2}
 
 
 class Profile(ctypes.Structure):
@@ -581,8 +581,9 @@ class Context:
     def generate_pulses(self, survey, first, count, *, origins=None, directions=None, device=0, stream=None):
         """Pulses [first, first + count) of a survey (dict: waypoints, deflector, speed_mps,
         pulse_rate_hz, scan_freq_hz, scan_angle_rad, n_fibres, t0_s, platform_noise_m, seed;
-        platform "linear" (default) or "multicopter" with accel_mps2 and optionally leg_yaw,
-        [n_waypoints - 1, 2]) generated on the device: (origins float64 [count, 3],
+        platform "linear" (default), "multicopter" with accel_mps2 and optionally leg_yaw,
+        [n_waypoints - 1, 2], or "multicopter_smooth" with accel_mps2 and bank_angle_rad)
+        generated on the device: (origins float64 [count, 3],
         directions float32 [count, 3])."""
         wp = np.ascontiguousarray(survey["waypoints"], dtype=np.float64).reshape(-1, 3)
         ly = survey.get("leg_yaw")
@@ -596,7 +597,7 @@ class Context:
                           int(survey.get("n_fibres", 0)), PLATFORMS[survey.get("platform", "linear")],
                           float(survey.get("t0_s", 0.0)), float(survey.get("platform_noise_m", 0.0)),
                           int(survey.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF, float(survey.get("accel_mps2", 0.0)),
-                          None if ly is None else ly.ctypes.data)
+                          None if ly is None else ly.ctypes.data, float(survey.get("bank_angle_rad", 0.0)))
         dev = torch.device("cuda", device) if isinstance(device, int) else device
         if origins is None:
             origins = torch.empty((count, 3), dtype=torch.float64, device=dev)
