@@ -185,45 +185,70 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const unsigned long long*
     hist[(long long)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of `total` counts in one block (sizes here are <= 256 * tiles):
-// tiles of 4 * kScanThreads consecutive counts, four per thread, read and
+// Exclusive scan of the counts [base, base + 4 * kScanThreads) of a (those below
+// total), plus carry, by one block: four consecutive counts per thread, read and
 // written coalesced; wavefront scans by lane shifts, then one scan of the
-// wavefront sums, and a carry from tile to tile.
-__global__ __launch_bounds__(kScanThreads) void k_scan(unsigned* __restrict__ a, long long total)
+// wavefront sums.  Returns the tile's sum (to every thread).
+__device__ __forceinline__ unsigned scan_tile(unsigned* __restrict__ a, long long base, long long total, unsigned carry,
+                                              unsigned* wsum)
 {
     constexpr int W = kScanThreads / kWave;
-    __shared__ unsigned wsum[W];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    unsigned carry = 0;
-    for (long long base = 0; base < total; base += 4 * kScanThreads) {
-        const long long i0 = base + 4 * (long long)threadIdx.x;
-        unsigned v[4];
-        for (int q = 0; q < 4; ++q) v[q] = i0 + q < total ? a[i0 + q] : 0u;
-        const unsigned t = v[0] + v[1] + v[2] + v[3];
-        unsigned x = t;  // inclusive scan over the wavefront
-        for (int off = 1; off < kWave; off <<= 1) {
-            const unsigned y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
-        if (lane == kWave - 1) wsum[w] = x;
-        __syncthreads();
-        if (w == 0) {
-            unsigned ws = lane < W ? wsum[lane] : 0u;
-            for (int off = 1; off < W; off <<= 1) {
-                const unsigned y = __shfl_up(ws, off);
-                if (lane >= off) ws += y;
-            }
-            if (lane < W) wsum[lane] = ws;
-        }
-        __syncthreads();
-        unsigned run = carry + (w > 0 ? wsum[w - 1] : 0u) + x - t;
-        for (int q = 0; q < 4; ++q) {
-            if (i0 + q < total) a[i0 + q] = run;
-            run += v[q];
-        }
-        carry += wsum[W - 1];
-        __syncthreads();
+    const long long i0 = base + 4 * (long long)threadIdx.x;
+    unsigned v[4];
+    for (int q = 0; q < 4; ++q) v[q] = i0 + q < total ? a[i0 + q] : 0u;
+    const unsigned t = v[0] + v[1] + v[2] + v[3];
+    unsigned x = t;  // inclusive scan over the wavefront
+    for (int off = 1; off < kWave; off <<= 1) {
+        const unsigned y = __shfl_up(x, off);
+        if (lane >= off) x += y;
     }
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        unsigned ws = lane < W ? wsum[lane] : 0u;
+        for (int off = 1; off < W; off <<= 1) {
+            const unsigned y = __shfl_up(ws, off);
+            if (lane >= off) ws += y;
+        }
+        if (lane < W) wsum[lane] = ws;
+    }
+    __syncthreads();
+    unsigned run = carry + (w > 0 ? wsum[w - 1] : 0u) + x - t;
+    for (int q = 0; q < 4; ++q) {
+        if (i0 + q < total) a[i0 + q] = run;
+        run += v[q];
+    }
+    const unsigned sum = wsum[W - 1];
+    __syncthreads();
+    return sum;
+}
+
+// Exclusive scan of `total` counts in one block: tile after tile with a carry.
+__global__ __launch_bounds__(kScanThreads) void k_scan(unsigned* __restrict__ a, long long total)
+{
+    __shared__ unsigned wsum[kScanThreads / kWave];
+    unsigned carry = 0;
+    for (long long base = 0; base < total; base += 4 * kScanThreads) carry += scan_tile(a, base, total, carry, wsum);
+}
+
+// Larger scans: each block scans its own tile and writes the tile's sum; the
+// sums are scanned by k_scan; k_scan_add then adds each tile's offset.
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(unsigned* __restrict__ a, long long total,
+                                                             unsigned* __restrict__ sums)
+{
+    __shared__ unsigned wsum[kScanThreads / kWave];
+    const unsigned s = scan_tile(a, (long long)blockIdx.x * 4 * kScanThreads, total, 0u, wsum);
+    if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(unsigned* __restrict__ a, long long total,
+                                                           const unsigned* __restrict__ sums)
+{
+    const unsigned add = sums[blockIdx.x];
+    const long long i0 = (long long)blockIdx.x * 4 * kScanThreads + 4 * (long long)threadIdx.x;
+    for (int q = 0; q < 4; ++q)
+        if (i0 + q < total) a[i0 + q] += add;
 }
 
 __device__ __forceinline__ unsigned lanes_below(unsigned long long m)
@@ -533,7 +558,12 @@ hipError_t mesh_check(const BvhBuffers& b, hipStream_t stream, unsigned& bad)
     return hipStreamSynchronize(stream);
 }
 
-long long radix_sort_hist_words(long long n) { return 256ll * ((n + kSortTile - 1) / kSortTile); }
+// Histogram words of a sort of n keys, plus room for the tile sums of their scan.
+long long radix_sort_hist_words(long long n)
+{
+    const long long words = 256ll * ((n + kSortTile - 1) / kSortTile);
+    return words + (words + 4 * kScanThreads - 1) / (4 * kScanThreads);
+}
 
 hipError_t radix_sort_pairs(unsigned long long* keys, int32_t* vals, unsigned long long* keys2, int32_t* vals2,
                             unsigned* hist, long long n, int passes, hipStream_t stream)
@@ -545,7 +575,16 @@ hipError_t radix_sort_pairs(unsigned long long* keys, int32_t* vals, unsigned lo
     for (int pass = 0; pass < passes; ++pass) {
         int shift = 8 * pass;
         hipLaunchKernelGGL(k_hist, dim3(n_tiles), dim3(kSortThreads), 0, stream, kin, n, shift, hist, n_tiles);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, stream, hist, 256ll * n_tiles);
+        const long long words = 256ll * n_tiles;
+        const long long scan_tiles = (words + 4 * kScanThreads - 1) / (4 * kScanThreads);
+        if (scan_tiles <= 8) {
+            hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, stream, hist, words);
+        } else {
+            unsigned* sums = hist + words;
+            hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)scan_tiles), dim3(kScanThreads), 0, stream, hist, words, sums);
+            hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, stream, sums, scan_tiles);
+            hipLaunchKernelGGL(k_scan_add, dim3((unsigned)scan_tiles), dim3(kScanThreads), 0, stream, hist, words, sums);
+        }
         hipLaunchKernelGGL(k_scatter, dim3(n_tiles), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n, shift,
                            hist, n_tiles);
         unsigned long long* tk = kin; kin = kout; kout = tk;
@@ -572,7 +611,7 @@ hipError_t bvh_build(BvhBuffers& b, hipStream_t stream, std::string& err)
         if ((e = hipMalloc(&keys2, sizeof(unsigned long long) * n)) != hipSuccess) { (void)fail(e, "alloc keys"); break; }
         if ((e = hipMalloc(&vals, sizeof(int32_t) * n)) != hipSuccess) { (void)fail(e, "alloc vals"); break; }
         if ((e = hipMalloc(&vals2, sizeof(int32_t) * n)) != hipSuccess) { (void)fail(e, "alloc vals"); break; }
-        if ((e = hipMalloc(&hist, sizeof(unsigned) * 256 * (size_t)n_tiles)) != hipSuccess) { (void)fail(e, "alloc hist"); break; }
+        if ((e = hipMalloc(&hist, sizeof(unsigned) * (size_t)radix_sort_hist_words(n))) != hipSuccess) { (void)fail(e, "alloc hist"); break; }
         if ((e = hipMalloc(&ub, sizeof(unsigned) * 16)) != hipSuccess) { (void)fail(e, "alloc bounds"); break; }
         if ((e = bounds_pass(b, ub, stream)) != hipSuccess) { (void)fail(e, "bounds"); break; }
         hipLaunchKernelGGL(k_morton, dim3(grid_for(n, 256)), dim3(256), 0, stream, b.verts, b.tri_idx, n, b.bounds,

@@ -78,6 +78,37 @@ __device__ __forceinline__ double wave_min_d(double v)
     return __hiloint2double(wave_bcast63_i(__double2hiint(v)), wave_bcast63_i(__double2loint(v)));
 }
 
+// Half-wavefront reductions: the same steps without the last broadcast, so lane
+// 31 ends with the result over lanes 0-31 and lane 63 with that over lanes
+// 32-63; each lane gets its own half's result.
+#define VLS_DPP_HALF_STEPS(STEP) STEP(0xB1, 0xF) STEP(0x4E, 0xF) STEP(0x141, 0xF) STEP(0x140, 0xF) STEP(0x142, 0xA)
+
+__device__ __forceinline__ int half_pick_i(int v)
+{
+    const int a = __builtin_amdgcn_readlane(v, 31), b = __builtin_amdgcn_readlane(v, 63);
+    return (threadIdx.x & 32) ? b : a;
+}
+
+__device__ __forceinline__ float half_max_f(float v)
+{
+    const int id = __float_as_int(-INFINITY);
+#define VLS_STEP(C, M) v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(id, __float_as_int(v), C, M, 0xF, false)));
+    VLS_DPP_HALF_STEPS(VLS_STEP)
+#undef VLS_STEP
+    return __int_as_float(half_pick_i(__float_as_int(v)));
+}
+
+__device__ __forceinline__ double half_min_d(double v)
+{
+    const int id_lo = __double2loint(INFINITY), id_hi = __double2hiint(INFINITY);
+#define VLS_STEP(C, M)                                                                         \
+    v = fmin(v, __hiloint2double(__builtin_amdgcn_update_dpp(id_hi, __double2hiint(v), C, M, 0xF, false), \
+                                 __builtin_amdgcn_update_dpp(id_lo, __double2loint(v), C, M, 0xF, false)));
+    VLS_DPP_HALF_STEPS(VLS_STEP)
+#undef VLS_STEP
+    return __hiloint2double(half_pick_i(__double2hiint(v)), half_pick_i(__double2loint(v)));
+}
+
 // Value of lane l - 1 (lane 0 gets `edge`) and of lane l + 1 (lane 63 gets `edge`).
 __device__ __forceinline__ float lane_prev_f(float v, float edge)
 {

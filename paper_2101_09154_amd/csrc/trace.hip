@@ -657,6 +657,215 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
     if (lane == 0) out.n_ret[p] = nret;
 }
 
+// Waveform and returns of the two pulses of a wavefront at once, pulse h in
+// lanes 32 h .. 32 h + 31 (its subray k in lane 32 h + k, S <= 32), with the same
+// results, bit for bit, as pulse_phase on each in turn: the same chunks of 64
+// bins from the same window start, each lane holding bins jb + 64 c + l and
+// jb + 64 c + 32 + l of its pulse (l = lane & 31), the same offsets from the
+// chunk's centre bin and the same sums in subray order.  Reductions run over
+// half wavefronts, so the two pulses share every reduction, neighbour exchange
+// and ballot, and each subray record read from LDS serves two bins.
+template <int MAXCH, int SHAPE>
+__device__ __forceinline__ void pulse_pair(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
+                                           long long first, float4* sub, double my_tau, float my_pw, int my_tri,
+                                           bool sub_lane)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int h = lane >> 5, l = lane & 31, hb = lane & 32;
+    const int S = sc.S, nb = sc.n_bins, K = sc.K;
+    const long long p = first + h;
+    const bool mine = sub_lane && my_tri >= 0;
+    const double tmin = half_min_d(mine ? my_tau : INFINITY);
+    const bool any = tmin < INFINITY;
+    double t0;
+    if (pulses.t0_in) t0 = pulses.t0_in[p];
+    else t0 = any ? tmin - sc.t_pre : (double)NAN;
+    const bool have = any && !isnan(t0);
+    const double rel = my_tau - t0;  // used on `mine` lanes only
+    const float x0 = (float)((double)(l - 32) * sc.bin_d), x1 = (float)((double)l * sc.bin_d);
+    int jb = 0, nch = 0;
+    {
+        const float lo = (float)(tmin - t0);
+        const float hi = half_max_f(mine ? (float)rel : -INFINITY);
+        if (have) {
+            const int jl = (int)fminf(fmaxf(floorf((lo - sc.cut_lo) * sc.inv_bin) - 1.0f, 0.0f), 1e9f);
+            const int jh = (int)fminf(fmaxf(ceilf((hi + sc.cut_hi) * sc.inv_bin) + 1.0f, -1.0f), (float)(nb - 1));
+            if (jl <= jh) {
+                jb = jl & ~3;
+                nch = ((jh - jb) >> 6) + 1;
+            }
+        }
+    }
+    const int nch_max = max(__builtin_amdgcn_readlane(nch, 0), __builtin_amdgcn_readlane(nch, 32));
+    float wa[MAXCH], wb[MAXCH];
+#pragma unroll
+    for (int c = 0; c < MAXCH; ++c) {
+        wa[c] = 0.0f;
+        wb[c] = 0.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < MAXCH; ++c) {
+        if (c >= nch_max) continue;
+        if (sub_lane) {
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (mine && c < nch) {
+                echo_offset(sc, rel, jb + c * kWave + 32, v.x, v.y);
+                v.z = my_pw;
+            }
+            sub[lane] = v;
+        }
+        wave_sync();
+        float acc0 = 0.0f, acc1 = 0.0f;
+#pragma unroll 4
+        for (int kk = 0; kk < S; ++kk) {
+            const float4 u = sub[hb + kk];
+            acc0 = fmaf(u.z, pulse_shape<SHAPE>(sc, (x0 - u.x) - u.y), acc0);
+            acc1 = fmaf(u.z, pulse_shape<SHAPE>(sc, (x1 - u.x) - u.y), acc1);
+        }
+        const int j0 = jb + c * kWave + l;
+        if (c < nch) {
+            wa[c] = j0 < nb ? acc0 : 0.0f;
+            wb[c] = j0 + 32 < nb ? acc1 : 0.0f;
+        }
+        wave_sync();
+    }
+    if (out.wf) {
+        float* row = out.wf + p * nb;
+        const int jend = jb + nch * kWave;
+        if ((nb & 3) == 0 && (reinterpret_cast<unsigned long long>(out.wf) & 15) == 0) {
+            float4* row4 = reinterpret_cast<float4*>(row);
+#pragma unroll
+            for (int m = 0; m < (MAXCH + 1) / 2; ++m) {
+                const int g = m * 32 + l, j = 4 * g;
+                if (j < nb && (j < jb || j >= jend)) stream_zero4(&row4[g]);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 2 * MAXCH; ++m) {
+                const int j = m * 32 + l;
+                if (j < nb && (j < jb || j >= jend)) stream_store(&row[j], 0.0f);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < MAXCH; ++c) {
+            const int j = jb + c * kWave + l;
+            if (c < nch && j < nb) stream_store(&row[j], wa[c]);
+            if (c < nch && j + 32 < nb) stream_store(&row[j + 32], wb[c]);
+        }
+    }
+    if (l == 0 && out.t0) out.t0[p] = t0;
+    // returns (Sec. 3.4 local maxima), as in pulse_phase, per half
+    int count = 0;
+    float m = 0.0f;
+#pragma unroll
+    for (int c = 0; c < MAXCH; ++c)
+        if (c < nch) m = fmaxf(m, fmaxf(wa[c], wb[c]));
+    m = half_max_f(m);
+    const float thr = fmaxf((float)sc.thr_abs, (float)(sc.thr_rel * (double)m));
+    float hi_off = 0.0f, lo_off = 0.0f;
+    const unsigned long long half_bits = h ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull;
+#pragma unroll
+    for (int c = 0; c < MAXCH; ++c) {
+        if (c >= nch_max) continue;
+        const bool act = have && c < nch && count < K;
+        if (__ballot(act) == 0) continue;
+        const float v0 = wa[c], v1 = wb[c];
+        // neighbours in bin order: bin jb + 64 c + l has v0 of lane l - 1 and l + 1,
+        // the last bin of the previous chunk at l = 0 and v1 of l = 0 at l = 31;
+        // bin jb + 64 c + 32 + l likewise, with v0 of l = 31 at l = 0 and the first
+        // bin of the next chunk at l = 31 (zero beyond the pulse's chunks)
+        const float prev_last = c > 0 ? __int_as_float(half_pick_i(__float_as_int(wb[c > 0 ? c - 1 : 0]))) : 0.0f;
+        const float v0_last = __int_as_float(half_pick_i(__float_as_int(v0)));
+        const float v1_first = __int_as_float(h ? __builtin_amdgcn_readlane(__float_as_int(v1), 32)
+                                                 : __builtin_amdgcn_readlane(__float_as_int(v1), 0));
+        float next_first = 0.0f;
+        if (c + 1 < MAXCH) {
+            const int wn = __float_as_int(wa[c + 1 < MAXCH ? c + 1 : c]);
+            const float f = __int_as_float(h ? __builtin_amdgcn_readlane(wn, 32) : __builtin_amdgcn_readlane(wn, 0));
+            next_first = c + 1 < nch ? f : 0.0f;
+        }
+        float left0 = lane_prev_f(v0, 0.0f), right0 = lane_next_f(v0, 0.0f);
+        float left1 = lane_prev_f(v1, 0.0f), right1 = lane_next_f(v1, 0.0f);
+        if (l == 0) {
+            left0 = prev_last;
+            left1 = v0_last;
+        }
+        if (l == 31) {
+            right0 = v1_first;
+            right1 = next_first;
+        }
+        const int j0 = jb + c * kWave + l, j1 = j0 + 32;
+        const bool cand0 = act && j0 >= 1 && j0 <= nb - 2 && v0 > left0 && v0 >= right0 && v0 >= thr;
+        const bool cand1 = act && j1 >= 1 && j1 <= nb - 2 && v1 > left1 && v1 >= right1 && v1 >= thr;
+        const unsigned long long mk0 = __ballot(cand0), mk1 = __ballot(cand1);
+        const unsigned long long my0 = mk0 & half_bits, my1 = mk1 & half_bits;
+        const int n0 = __popcll(my0), n1 = __popcll(my1);
+        int rt0 = -1, rt1 = -1;
+        if (out.ret_tri && (mk0 | mk1)) {
+            // each kept return goes to the subray contributing most at its bin
+            // (lowest subray index on ties): both halves walk their returns in
+            // bin order together, one half-wavefront maximum per step
+            if (mine) echo_offset(sc, rel, jb + c * kWave + 32, hi_off, lo_off);
+            const int left_h = max(0, min(n0 + n1, K - count));
+            const int steps = max(__builtin_amdgcn_readlane(left_h, 0), __builtin_amdgcn_readlane(left_h, 32));
+            unsigned long long t0m = my0, t1m = my1;
+            for (int s2 = 0; s2 < steps; ++s2) {
+                // this half's next return: position b in the chunk (0..63), or none
+                int b = -1;
+                if (s2 < left_h) {
+                    if (t0m) {
+                        b = (__ffsll((long long)t0m) - 1) & 31;
+                        t0m &= t0m - 1;
+                    } else if (t1m) {
+                        b = 32 + ((__ffsll((long long)t1m) - 1) & 31);
+                        t1m &= t1m - 1;
+                    }
+                }
+                const float xb = (float)((double)(b - 32) * sc.bin_d);
+                const float val = mine && b >= 0 ? echo_value<SHAPE>(sc, xb, hi_off, lo_off, my_pw) : -1.0f;
+                const float best = half_max_f(val);
+                // each half's winner: the lowest of its lanes at the maximum
+                // (read with lane numbers that are the same for the whole wavefront)
+                const unsigned long long w = __ballot(mine && b >= 0 && val == best);
+                const unsigned w_lo = (unsigned)w, w_hi = (unsigned)(w >> 32);
+                const int t_lo = w_lo ? __builtin_amdgcn_readlane(my_tri, __ffs((int)w_lo) - 1) : -1;
+                const int t_hi = w_hi ? __builtin_amdgcn_readlane(my_tri, 32 + __ffs((int)w_hi) - 1) : -1;
+                const int t = h ? t_hi : t_lo;
+                if (b >= 0 && l == (b & 31)) {
+                    if (b < 32) rt0 = t;
+                    else rt1 = t;
+                }
+            }
+        }
+        const int slot0 = count + (int)lanes_below(my0);
+        const int slot1 = count + n0 + (int)lanes_below(my1);
+        if (cand0 && slot0 < K) {
+            const long long o = p * K + slot0;
+            out.ret_range[o] = (float)(0.5 * kCmPerNs * (t0 + (double)j0 * sc.bin_d - sc.s_peak));
+            out.ret_amp[o] = v0;
+            out.ret_bin[o] = j0;
+            if (out.ret_tri) out.ret_tri[o] = rt0;
+        }
+        if (cand1 && slot1 < K) {
+            const long long o = p * K + slot1;
+            out.ret_range[o] = (float)(0.5 * kCmPerNs * (t0 + (double)j1 * sc.bin_d - sc.s_peak));
+            out.ret_amp[o] = v1;
+            out.ret_bin[o] = j1;
+            if (out.ret_tri) out.ret_tri[o] = rt1;
+        }
+        count += n0 + n1;
+    }
+    const int nret = count < K ? count : K;
+    if (l >= nret && l < K) {
+        const long long o = p * K + l;
+        out.ret_range[o] = 0.0f;
+        out.ret_amp[o] = 0.0f;
+        out.ret_bin[o] = -1;
+        if (out.ret_tri) out.ret_tri[o] = -1;
+    }
+    if (l == 0) out.n_ret[p] = nret;
+}
+
 // One wavefront: pulses [first, first + npw) of one scanner.
 // MODE 0: trace only.  MODE 1: trace + waveform + returns (fused).
 // MODE 2: trace only, adding subrays / node visits / triangle tests to out.counts.
@@ -669,9 +878,12 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int S = sc.S;
-    const int pl = lane / S;
-    const int k = lane - pl * S;
-    const bool active = pl < npw;
+    // two pulses per wavefront in the fused launch: pulse h's subrays in lanes
+    // 32 h + k, so that its waveform phase runs on half a wavefront (pulse_pair)
+    const bool pair = MODE == 1 && !CHUNK && sc.P_w == 2 && npw == 2;
+    const int pl = pair ? lane >> 5 : lane / S;
+    const int k = pair ? lane & 31 : lane - pl * S;
+    const bool active = pl < npw && k < S;
     // stage the first candidate triangles of up to 4 pulses, one per lane (64 for
     // one pulse per wavefront, else 16 per pulse), translated to their pulse's
     // origin
@@ -766,7 +978,10 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     // the staged records are dead: the same LDS now carries the waveform inputs
     wave_sync();
     float4* sub = reinterpret_cast<float4*>(wl);
-    if (sc.shape == 0) {
+    if (pair) {
+        if (sc.shape == 0) pulse_pair<MAXCH, 0>(sc, pulses, out, first, sub, tau, P, tri, active);
+        else pulse_pair<MAXCH, 1>(sc, pulses, out, first, sub, tau, P, tri, active);
+    } else if (sc.shape == 0) {
         for (int q = 0; q < npw; ++q)
             pulse_phase<MAXCH, true, true, 0>(sc, pulses, out, first + q, q * S, sub, true, tau, P, tri);
     } else {
