@@ -31,6 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# launch configurations the autotuner chose on MI355X for these workloads (JSON
+# lines keyed by scene size, subrays, bins, pulse count and segments); a key not
+# in the file is tuned on the spot (and appended when the file is writable)
+TUNE_CACHE = os.path.join(ROOT, "paper_2101_09154_amd", "tuning", "mi355x.jsonl")
 
 
 def log(*a):
@@ -216,7 +220,7 @@ def time_ms(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def bench_batched(ctx, scene, mesh, steps):
+def bench_batched(ctx, scene, mesh, steps, tune_cache=None):
     """256 terrestrial positions on the same scene: per-segment launches vs one
     persistent launch vs a replayed HIP graph of it (autotuned)."""
     import torch
@@ -246,7 +250,7 @@ def bench_batched(ctx, scene, mesh, steps):
     cfg0 = ctx.launch_config()
     t_seg = time_ms(per_segment, max(1, steps // 4), 1, stream)
     t_pers = time_ms(lambda: ctx.simulate(scene, scs, o, d, out=out, **kw), steps, 1, stream)
-    tune = ctx.autotune(scene, scs, o, d, out, **kw)
+    tune = ctx.autotune(scene, scs, o, d, out, cache_path=tune_cache, **kw)
     t_tuned = time_ms(lambda: ctx.simulate(scene, scs, o, d, out=out, **kw), steps, 1, stream)
     g = ctx.capture_graph(scene, scs, o, d, out, **kw)
     t_graph = time_ms(lambda: g.launch(), steps, 1, stream)
@@ -407,7 +411,7 @@ def bench_instanced(ctx, steps):
     return res
 
 
-def run_leg(ctx, leg, steps, tune=True):
+def run_leg(ctx, leg, steps, tune=True, tune_cache=None):
     """The vegetation workload (2,000 trees, ~10M triangles, 2M ULS pulses, 61
     subrays, K = 8; scene larger than the caches, so HBM-level figures) or the
     small terrestrial one (7,938 triangles, 10,000 pulses, 19 subrays; the scene
@@ -433,7 +437,7 @@ def run_leg(ctx, leg, steps, tune=True):
         d = torch.from_numpy(pulses.directions).cuda()
         out = ctx.alloc_outputs(pulses.n, vp.n_subrays(sc), sc["n_bins"], sc["max_returns"], o.device,
                                 subrays=False)
-        tuned = ctx.autotune(scene, sc, o, d, out)
+        tuned = ctx.autotune(scene, sc, o, d, out, cache_path=tune_cache)
         scene.close()
         del o, d, out
     res = bench_plain(ctx, leg, label, mesh, pulses, sc, steps, seed, hbm=hbm)
@@ -456,9 +460,12 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (three times), to scale HBM counters")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuner cache (JSON lines); '' tunes every workload afresh")
     ap.add_argument("--leg", choices=["uls_trees", "small_tls"], default=None,
                     help="only run this workload's leg and print its record (for profiling)")
     args = ap.parse_args()
+    args.tune_cache = args.tune_cache or None
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU form "
               "(pulses would shard across GPUs with no exchange)", file=sys.stderr)
@@ -481,7 +488,8 @@ def main():
         ctx = vp.Context(0)
         if not args.no_tune:
             log("autotune (%s)" % args.leg)
-        print(json.dumps(run_leg(ctx, args.leg, args.steps, tune=not args.no_tune)), flush=True)
+        print(json.dumps(run_leg(ctx, args.leg, args.steps, tune=not args.no_tune, tune_cache=args.tune_cache)),
+              flush=True)
         return
     log("generating scene and pulses")
     mesh, pulses, sc = configs.als_buildings()
@@ -519,7 +527,7 @@ def main():
     tune = None
     if not args.no_tune:
         log("autotune (plain)")
-        tune = ctx.autotune(scene, sc, o, d, out)
+        tune = ctx.autotune(scene, sc, o, d, out, cache_path=args.tune_cache)
     for _ in range(args.warmup):
         ctx.simulate(scene, sc, o, d, out=out)
     torch.cuda.synchronize()
@@ -709,7 +717,8 @@ def main():
     res["autotune"] = tune
     if not args.only_plain:
         log("batched workload")
-        res["batched"] = bench_batched(ctx, scene, mesh, args.steps // 2 if args.steps > 2 else 1)
+        res["batched"] = bench_batched(ctx, scene, mesh, args.steps // 2 if args.steps > 2 else 1,
+                                       tune_cache=args.tune_cache)
         log("gradient workload")
         res["gradient"] = bench_grad(ctx, max(args.steps // 2, 2))
         log("voxel workload")
@@ -719,7 +728,7 @@ def main():
     if not args.only_plain:
         for leg in ("uls_trees", "small_tls"):
             log("%s workload" % leg)
-            res[leg] = run_leg(ctx, leg, max(args.steps // 2, 2), tune=not args.no_tune)
+            res[leg] = run_leg(ctx, leg, max(args.steps // 2, 2), tune=not args.no_tune, tune_cache=args.tune_cache)
         log("copy bandwidth")
         res["copy_bandwidth"] = copy_bandwidth()
     res["inputs"] = input_digest(mesh, pulses, sc, configs.ALS_SEED)
