@@ -76,7 +76,7 @@ __device__ __forceinline__ bool subray_grads(const SceneDev& scene, const Scanne
         df = (1.0 - ks) + (c2 > 0.0 && ns != 0.0 ? ks * ns * pow(c2, ns - 1.0) * 4.0 * cosv : 0.0);
     }
     double P = base * rho * f;
-    double tau = 2.0 * R / kCmPerNs;
+    double tau = round_trip_ns(R);
     double rel = tau - t0;
     // bins inside the pulse support around this echo
     double lo = ceil((rel - sc.cut_lo) / sc.bin_d), hi = floor((rel + sc.cut_hi) / sc.bin_d);

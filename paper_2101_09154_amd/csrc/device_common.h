@@ -265,6 +265,11 @@ __device__ __forceinline__ double sm_uniform(uint64_t seed, uint64_t c)
     return (double)((sm64(seed, c) >> 11) + 1) * (1.0 / 9007199254740992.0);
 }
 
+// Round-trip time in ns of a range R in m, 2 R / c (Sec. 3.4), as a product with
+// the double nearest to 2 / c (a division would cost an FP64 divide sequence).
+constexpr double kNsPerRoundTripM = 2.0 / kCmPerNs;
+__device__ __forceinline__ double round_trip_ns(double R) { return R * kNsPerRoundTripM; }
+
 // Outgoing pulse at offset s (ns): unit-peak Gaussian (SHAPE 0), or Eq. 3
 // (s/tau)^2 exp(-s/tau) (SHAPE 1).  exp2 is the hardware instruction: results
 // below 2^-126 flush to zero, far under any bin that matters.

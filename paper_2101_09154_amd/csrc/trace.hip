@@ -56,10 +56,15 @@ struct CandRec {
 
 // Per-wavefront LDS, used in turn by the two phases: the staged candidates of the
 // wavefront's pulses (slot = pulse * staged_per_pulse + candidate) while tracing,
-// then the subrays' waveform inputs (offset hi, offset lo, power, unused) per lane.
+// then the subrays' waveform inputs (offset hi, offset lo, power, unused) per lane,
+// followed by the kept returns of the two pulses of a paired wavefront (16 bytes
+// per slot, VLS_MAX_RETURNS slots per pulse).
+constexpr int kWaveInBytes = kWave * 16;
+constexpr int kRetStageBytes = 2 * 16 * 16;
 __host__ __device__ constexpr int wave_lds_bytes(int staged_slots)
 {
-    return staged_slots * (int)sizeof(CandRec) > kWave * 16 ? staged_slots * (int)sizeof(CandRec) : kWave * 16;
+    return staged_slots * (int)sizeof(CandRec) > kWaveInBytes + kRetStageBytes ? staged_slots * (int)sizeof(CandRec)
+                                                                               : kWaveInBytes + kRetStageBytes;
 }
 
 __device__ __forceinline__ bool box_hit(const RayBox& r, float lx, float ly, float lz, float hx, float hy, float hz,
@@ -85,9 +90,15 @@ struct Hit {
 // triangle is sheared so the ray runs along +kz; the 2-D edge functions U, V, W
 // are then evaluated from the same operands for both triangles of a shared edge,
 // so no ray slips between them.  Returns t = T / det for a hit with t > 0, else
-// a value that is not > 0 (NaN or <= 0).
+// a value that is not > 0 (NaN or <= 0).  tmax: the lane's closest distance so
+// far; a hit provably beyond it is reported as a miss without the division
+// (|T| above |det| tmax with a relative margin of 2^-40, far more than the
+// rounding of the two products, means the quotient rounds above tmax, which
+// the caller would reject; equal distances still take the division, since the
+// caller breaks those ties by triangle index).
 template <int KZ>
-__device__ __forceinline__ double woop_t(const Ray& r, const double* a, const double* b, const double* c)
+__device__ __forceinline__ double woop_t(const Ray& r, const double* a, const double* b, const double* c,
+                                         double tmax)
 {
 #pragma clang fp contract(off)
     constexpr int KX = KZ == 2 ? 0 : KZ + 1;
@@ -101,10 +112,17 @@ __device__ __forceinline__ double woop_t(const Ray& r, const double* a, const do
     const double W = Bx * Ay - By * Ax;
     const bool out = (U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0);
     const double det = U + V + W;
-    const double T = U * (r.Sz * Az) + V * (r.Sz * Bz) + W * (r.Sz * Cz);
-    // the division only where some lane can hit (most candidates miss every lane)
+    // branches on the wavefront's votes: the scaled distance only where some
+    // lane is inside the edges (most candidates miss every lane), the division
+    // only where some lane can still hit closer
     double t = -1.0;
-    if (!out && det != 0.0) t = T / det;
+    const bool inside = !out && det != 0.0;
+    if (__ballot(inside)) {
+        const double T = U * (r.Sz * Az) + V * (r.Sz * Bz) + W * (r.Sz * Cz);
+        const double lim = (fabs(det) * tmax) * (1.0 + 0x1p-40);
+        const bool go = inside && !(fabs(T) > lim && lim >= 0x1p-1000);
+        if (__ballot(go)) t = go ? T / det : -1.0;
+    }
     return t;
 }
 
@@ -129,7 +147,8 @@ __device__ __forceinline__ bool leaf_test(const Ray& r, const float4* __restrict
     translate(r, P0, a);
     translate(r, P1, b);
     translate(r, P2, c);
-    const double t = r.kz == 2 ? woop_t<2>(r, a, b, c) : (r.kz == 1 ? woop_t<1>(r, a, b, c) : woop_t<0>(r, a, b, c));
+    const double t = r.kz == 2 ? woop_t<2>(r, a, b, c, h.t)
+                               : (r.kz == 1 ? woop_t<1>(r, a, b, c, h.t) : woop_t<0>(r, a, b, c, h.t));
     const int orig = __float_as_int(P0.w);
     if (!closer(t, orig, h)) return false;
     h.t = t;
@@ -147,7 +166,7 @@ __device__ __forceinline__ int cand_loop(const Ray& r, const CandRec* __restrict
     for (int i = 0; i < nc; ++i) {
         const CandRec& c = rec[i];
         double a[3] = {c.a[0], c.a[1], c.a[2]}, b[3] = {c.b[0], c.b[1], c.b[2]}, e[3] = {c.c[0], c.c[1], c.c[2]};
-        const double t = woop_t<KZ>(r, a, b, e);
+        const double t = woop_t<KZ>(r, a, b, e, h.t);
         const int orig = c.orig;
         if (closer(t, orig, h)) {
             h.t = t;
@@ -754,73 +773,89 @@ __device__ __forceinline__ void pulse_pair(const ScannerDev& sc, const PulsesDev
         }
     }
     if (l == 0 && out.t0) out.t0[p] = t0;
-    // returns (Sec. 3.4 local maxima), as in pulse_phase, per half
-    int count = 0;
+    // returns (Sec. 3.4 local maxima), as in pulse_phase, per half.  The kept
+    // returns go to LDS slots first (bin order, as found), then lanes l < K of
+    // each half write the pulse's K output slots once, zeros past its count.
     float m = 0.0f;
 #pragma unroll
-    for (int c = 0; c < MAXCH; ++c)
-        if (c < nch) m = fmaxf(m, fmaxf(wa[c], wb[c]));
+    for (int c = 0; c < MAXCH; ++c) {
+        if (c >= nch_max) break;
+        m = fmaxf(m, fmaxf(wa[c], wb[c]));
+    }
     m = half_max_f(m);
     const float thr = fmaxf((float)sc.thr_abs, (float)(sc.thr_rel * (double)m));
+    float4* ret_st = reinterpret_cast<float4*>(reinterpret_cast<unsigned char*>(sub) + kWaveInBytes) + 16 * h;
+    // kept so far in each half (wave-uniform values)
+    int cnt_lo = 0, cnt_hi = 0;
+    const unsigned long long lo_lanes = 0x00000000FFFFFFFFull;
     float hi_off = 0.0f, lo_off = 0.0f;
-    const unsigned long long half_bits = h ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull;
 #pragma unroll
     for (int c = 0; c < MAXCH; ++c) {
-        if (c >= nch_max) continue;
+        if (c >= nch_max) break;
+        if (cnt_lo >= K && cnt_hi >= K) break;
+        const int count = h ? cnt_hi : cnt_lo;
         const bool act = have && c < nch && count < K;
-        if (__ballot(act) == 0) continue;
         const float v0 = wa[c], v1 = wb[c];
         // neighbours in bin order: bin jb + 64 c + l has v0 of lane l - 1 and l + 1,
         // the last bin of the previous chunk at l = 0 and v1 of l = 0 at l = 31;
         // bin jb + 64 c + 32 + l likewise, with v0 of l = 31 at l = 0 and the first
         // bin of the next chunk at l = 31 (zero beyond the pulse's chunks)
-        const float prev_last = c > 0 ? __int_as_float(half_pick_i(__float_as_int(wb[c > 0 ? c - 1 : 0]))) : 0.0f;
-        const float v0_last = __int_as_float(half_pick_i(__float_as_int(v0)));
-        const float v1_first = __int_as_float(h ? __builtin_amdgcn_readlane(__float_as_int(v1), 32)
-                                                 : __builtin_amdgcn_readlane(__float_as_int(v1), 0));
-        float next_first = 0.0f;
-        if (c + 1 < MAXCH) {
-            const int wn = __float_as_int(wa[c + 1 < MAXCH ? c + 1 : c]);
-            const float f = __int_as_float(h ? __builtin_amdgcn_readlane(wn, 32) : __builtin_amdgcn_readlane(wn, 0));
-            next_first = c + 1 < nch ? f : 0.0f;
-        }
         float left0 = lane_prev_f(v0, 0.0f), right0 = lane_next_f(v0, 0.0f);
         float left1 = lane_prev_f(v1, 0.0f), right1 = lane_next_f(v1, 0.0f);
         if (l == 0) {
-            left0 = prev_last;
-            left1 = v0_last;
+            left0 = c > 0 ? __int_as_float(half_pick_i(__float_as_int(wb[c > 0 ? c - 1 : 0]))) : 0.0f;
+            left1 = __int_as_float(half_pick_i(__float_as_int(v0)));
         }
         if (l == 31) {
-            right0 = v1_first;
-            right1 = next_first;
+            right0 = __int_as_float(h ? __builtin_amdgcn_readlane(__float_as_int(v1), 32)
+                                      : __builtin_amdgcn_readlane(__float_as_int(v1), 0));
+            float f = 0.0f;
+            if (c + 1 < MAXCH && c + 1 < nch_max) {
+                const int wn = __float_as_int(wa[c + 1 < MAXCH ? c + 1 : c]);
+                f = __int_as_float(h ? __builtin_amdgcn_readlane(wn, 32) : __builtin_amdgcn_readlane(wn, 0));
+            }
+            right1 = c + 1 < nch ? f : 0.0f;
         }
         const int j0 = jb + c * kWave + l, j1 = j0 + 32;
-        const bool cand0 = act && j0 >= 1 && j0 <= nb - 2 && v0 > left0 && v0 >= right0 && v0 >= thr;
-        const bool cand1 = act && j1 >= 1 && j1 <= nb - 2 && v1 > left1 && v1 >= right1 && v1 >= thr;
+        const bool cand0 = act && (unsigned)(j0 - 1) <= (unsigned)(nb - 3) && v0 > left0 && v0 >= right0 && v0 >= thr;
+        const bool cand1 = act && (unsigned)(j1 - 1) <= (unsigned)(nb - 3) && v1 > left1 && v1 >= right1 && v1 >= thr;
         const unsigned long long mk0 = __ballot(cand0), mk1 = __ballot(cand1);
-        const unsigned long long my0 = mk0 & half_bits, my1 = mk1 & half_bits;
-        const int n0 = __popcll(my0), n1 = __popcll(my1);
+        if ((mk0 | mk1) == 0) continue;
+        // per half: candidates of the first and second 32 bins (wave-uniform)
+        const unsigned a_lo = (unsigned)mk0, b_lo = (unsigned)mk1;
+        const unsigned a_hi = (unsigned)(mk0 >> 32), b_hi = (unsigned)(mk1 >> 32);
+        const int n_lo = __popc(a_lo) + __popc(b_lo), n_hi = __popc(a_hi) + __popc(b_hi);
+        const int take_lo = max(0, min(n_lo, K - cnt_lo)), take_hi = max(0, min(n_hi, K - cnt_hi));
         int rt0 = -1, rt1 = -1;
-        if (out.ret_tri && (mk0 | mk1)) {
+        if (out.ret_tri) {
             // each kept return goes to the subray contributing most at its bin
             // (lowest subray index on ties): both halves walk their returns in
             // bin order together, one half-wavefront maximum per step
             if (mine) echo_offset(sc, rel, jb + c * kWave + 32, hi_off, lo_off);
-            const int left_h = max(0, min(n0 + n1, K - count));
-            const int steps = max(__builtin_amdgcn_readlane(left_h, 0), __builtin_amdgcn_readlane(left_h, 32));
-            unsigned long long t0m = my0, t1m = my1;
+            const int steps = max(take_lo, take_hi);
+            unsigned ra_lo = a_lo, rb_lo = b_lo, ra_hi = a_hi, rb_hi = b_hi;
             for (int s2 = 0; s2 < steps; ++s2) {
-                // this half's next return: position b in the chunk (0..63), or none
-                int b = -1;
-                if (s2 < left_h) {
-                    if (t0m) {
-                        b = (__ffsll((long long)t0m) - 1) & 31;
-                        t0m &= t0m - 1;
-                    } else if (t1m) {
-                        b = 32 + ((__ffsll((long long)t1m) - 1) & 31);
-                        t1m &= t1m - 1;
+                // each half's next return: position in the chunk (0..63), or -1
+                int bl = -1, bh = -1;
+                if (s2 < take_lo) {
+                    if (ra_lo) {
+                        bl = __ffs((int)ra_lo) - 1;
+                        ra_lo &= ra_lo - 1;
+                    } else {
+                        bl = 32 + __ffs((int)rb_lo) - 1;
+                        rb_lo &= rb_lo - 1;
                     }
                 }
+                if (s2 < take_hi) {
+                    if (ra_hi) {
+                        bh = __ffs((int)ra_hi) - 1;
+                        ra_hi &= ra_hi - 1;
+                    } else {
+                        bh = 32 + __ffs((int)rb_hi) - 1;
+                        rb_hi &= rb_hi - 1;
+                    }
+                }
+                const int b = h ? bh : bl;
                 const float xb = (float)((double)(b - 32) * sc.bin_d);
                 const float val = mine && b >= 0 ? echo_value<SHAPE>(sc, xb, hi_off, lo_off, my_pw) : -1.0f;
                 const float best = half_max_f(val);
@@ -837,31 +872,33 @@ __device__ __forceinline__ void pulse_pair(const ScannerDev& sc, const PulsesDev
                 }
             }
         }
-        const int slot0 = count + (int)lanes_below(my0);
-        const int slot1 = count + n0 + (int)lanes_below(my1);
+        // slots: this half's count, then the first 32 bins' candidates below the
+        // lane, then the second 32 bins' below it
+        const unsigned a_h = h ? a_hi : a_lo, b_h = h ? b_hi : b_lo;
+        const unsigned below = (1u << l) - 1u;
+        const int slot0 = count + __popc(a_h & below);
+        const int slot1 = count + __popc(a_h) + __popc(b_h & below);
         if (cand0 && slot0 < K) {
-            const long long o = p * K + slot0;
-            out.ret_range[o] = (float)(0.5 * kCmPerNs * (t0 + (double)j0 * sc.bin_d - sc.s_peak));
-            out.ret_amp[o] = v0;
-            out.ret_bin[o] = j0;
-            if (out.ret_tri) out.ret_tri[o] = rt0;
+            const float rg = (float)(0.5 * kCmPerNs * (t0 + (double)j0 * sc.bin_d - sc.s_peak));
+            ret_st[slot0] = make_float4(rg, v0, __int_as_float(j0), __int_as_float(rt0));
         }
         if (cand1 && slot1 < K) {
-            const long long o = p * K + slot1;
-            out.ret_range[o] = (float)(0.5 * kCmPerNs * (t0 + (double)j1 * sc.bin_d - sc.s_peak));
-            out.ret_amp[o] = v1;
-            out.ret_bin[o] = j1;
-            if (out.ret_tri) out.ret_tri[o] = rt1;
+            const float rg = (float)(0.5 * kCmPerNs * (t0 + (double)j1 * sc.bin_d - sc.s_peak));
+            ret_st[slot1] = make_float4(rg, v1, __int_as_float(j1), __int_as_float(rt1));
         }
-        count += n0 + n1;
+        cnt_lo += n_lo;
+        cnt_hi += n_hi;
     }
-    const int nret = count < K ? count : K;
-    if (l >= nret && l < K) {
+    wave_sync();
+    const int nret = min(h ? cnt_hi : cnt_lo, K);
+    if (l < K) {
+        float4 r = make_float4(0.0f, 0.0f, __int_as_float(-1), __int_as_float(-1));
+        if (l < nret) r = ret_st[l];
         const long long o = p * K + l;
-        out.ret_range[o] = 0.0f;
-        out.ret_amp[o] = 0.0f;
-        out.ret_bin[o] = -1;
-        if (out.ret_tri) out.ret_tri[o] = -1;
+        out.ret_range[o] = r.x;
+        out.ret_amp[o] = r.y;
+        out.ret_bin[o] = __float_as_int(r.z);
+        if (out.ret_tri) out.ret_tri[o] = __float_as_int(r.w);
     }
     if (l == 0) out.n_ret[p] = nret;
 }
@@ -974,7 +1011,7 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
         return;
     }
     if (MODE == 0) return;
-    const double tau = (active && tri >= 0) ? 2.0 * R / kCmPerNs : (double)INFINITY;
+    const double tau = (active && tri >= 0) ? round_trip_ns(R) : (double)INFINITY;
     // the staged records are dead: the same LDS now carries the waveform inputs
     wave_sync();
     float4* sub = reinterpret_cast<float4*>(wl);
@@ -1035,7 +1072,7 @@ __global__ __launch_bounds__(256) void k_wave(ScannerDev sc, PulsesDev pulses, O
             P = out.sub_power[o];
         }
     }
-    const double tau = tri >= 0 ? 2.0 * R / kCmPerNs : (double)INFINITY;
+    const double tau = tri >= 0 ? round_trip_ns(R) : (double)INFINITY;
     for (int q = 0; q < npw; ++q) {
         const long long p = first + p0 + q;
         if (KIND == 0) {
@@ -1215,7 +1252,8 @@ __device__ __forceinline__ void leaf_test2(const InstDev& I, const PartDev& P, i
     place(I, V0, r, a);
     place(I, V1, r, b);
     place(I, V2, r, c);
-    const double t = r.kz == 2 ? woop_t<2>(r, a, b, c) : (r.kz == 1 ? woop_t<1>(r, a, b, c) : woop_t<0>(r, a, b, c));
+    const double t = r.kz == 2 ? woop_t<2>(r, a, b, c, h.t)
+                               : (r.kz == 1 ? woop_t<1>(r, a, b, c, h.t) : woop_t<0>(r, a, b, c, h.t));
     const int id = I.tri_base + __float_as_int(V0.w);
     if (!(t > 0.0 && (t < h.t || (t == h.t && id < h.id)))) return;
     h.t = t;
@@ -1431,8 +1469,11 @@ hipError_t launch_packets(const SceneDev& scene, const ScannerDev& sc0, const Ba
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    // eight wavefronts per SIMD: the walks wait on dependent node fetches, and
+    // more resident walks hide more of that latency (measured: 4 per SIMD is
+    // 11 % slower on a vegetation scene, 16 per SIMD 5 % slower)
     const int block = 4 * kWave;
-    const unsigned grid = (unsigned)(cus > 0 ? 4 * cus : 1024);
+    const unsigned grid = (unsigned)(cus > 0 ? 8 * cus : 2048);
     const size_t lds = sizeof(int) * (size_t)kPacketCap * block / kWave;
     hipLaunchKernelGGL(k_packets, dim3(grid), dim3(block), lds, stream, scene, sc0, batch, pulses, cand, ovf_list,
                        ovf_ctr, first);
