@@ -177,6 +177,27 @@ __device__ __forceinline__ int cand_loop(const Ray& r, const CandRec* __restrict
     return best;
 }
 
+// The staged records whose bits are set in `mask` (a wave-uniform 64-bit set).
+template <int KZ>
+__device__ __forceinline__ int cand_loop_mask(const Ray& r, const CandRec* __restrict__ rec, unsigned long long mask,
+                                              Hit& h)
+{
+    int best = -1;
+    for (; mask; mask &= mask - 1) {
+        const int i = __ffsll((long long)mask) - 1;
+        const CandRec& c = rec[i];
+        double a[3] = {c.a[0], c.a[1], c.a[2]}, b[3] = {c.b[0], c.b[1], c.b[2]}, e[3] = {c.c[0], c.c[1], c.c[2]};
+        const double t = woop_t<KZ>(r, a, b, e, h.t);
+        const int orig = c.orig;
+        if (closer(t, orig, h)) {
+            h.t = t;
+            h.orig = orig;
+            best = i;
+        }
+    }
+    return best;
+}
+
 // Closest hit of one ray.  ring: this block's LDS ring, stride = blockDim.x.
 // COUNT: also count internal-node visits and triangle tests.
 template <bool COUNT>
@@ -352,13 +373,82 @@ __device__ __forceinline__ void shade(const Ray& r, const double* a, const doubl
     P = cw * rho * f / (R * R);
 }
 
+// Can any subray of a pulse meet this triangle (vertices translated to the
+// pulse origin)?  In the pulse's basis (x = X.u, y = X.v, z = X.n) every subray
+// direction lies in the square pyramid |x| <= k z, |y| <= k z with k the tangent
+// of the largest subray angle, so a triangle whose three vertices all lie
+// outside one of its four side planes, or all behind the origin, is met by no
+// subray (its points are convex combinations of the vertices).  Only a cull
+// test, in FP32: k is widened by 1e-5 relative and every comparison carries a
+// margin of 1e-6 of the vertex's size (L1), several times the rounding of the
+// vertex, the basis and the dot products, so a triangle some subray meets is
+// never dropped.
+struct CullBasis {
+    float n[3], u[3], v[3];
+    float k;
+};
+
+__device__ __forceinline__ CullBasis cull_basis(const Basis& Bs, double tan_max)
+{
+    CullBasis c;
+    const double* n = Bs.n;
+    const double sgn = copysign(1.0, n[2]);
+    const double u[3] = {1.0 + sgn * n[0] * n[0] * Bs.a, sgn * Bs.b, -sgn * n[0]};
+    const double v[3] = {Bs.b, sgn + n[1] * n[1] * Bs.a, -n[1]};
+    for (int i = 0; i < 3; ++i) {
+        c.n[i] = (float)n[i];
+        c.u[i] = (float)u[i];
+        c.v[i] = (float)v[i];
+    }
+    c.k = (float)(tan_max * (1.0 + 1e-5) + 1e-12);
+    return c;
+}
+
+__device__ __forceinline__ bool cone_may_hit(const double* A, const double* B, const double* C, const CullBasis& cb)
+{
+    bool px = true, nx = true, py = true, ny = true, bz = true;
+    const double* X[3] = {A, B, C};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float w0 = (float)X[i][0], w1 = (float)X[i][1], w2 = (float)X[i][2];
+        const float z = fmaf(w0, cb.n[0], fmaf(w1, cb.n[1], w2 * cb.n[2]));
+        const float x = fmaf(w0, cb.u[0], fmaf(w1, cb.u[1], w2 * cb.u[2]));
+        const float y = fmaf(w0, cb.v[0], fmaf(w1, cb.v[1], w2 * cb.v[2]));
+        const float m = 1e-6f * (fabsf(w0) + fabsf(w1) + fabsf(w2));
+        const float kz = fmaf(cb.k, z, m);
+        px = px && x > kz;
+        nx = nx && -x > kz;
+        py = py && y > kz;
+        ny = ny && -y > kz;
+        bz = bz && z < -m;
+    }
+    return !(px || nx || py || ny || bz);
+}
+
+__device__ __forceinline__ void stage_rec(CandRec& w, float4 P0, float4 P1, float4 P2, const double* o, int li)
+{
+    w.a[0] = (double)P0.x - o[0];
+    w.a[1] = (double)P0.y - o[1];
+    w.a[2] = (double)P0.z - o[2];
+    w.b[0] = (double)P1.x - o[0];
+    w.b[1] = (double)P1.y - o[1];
+    w.b[2] = (double)P1.z - o[2];
+    w.c[0] = (double)P2.x - o[0];
+    w.c[1] = (double)P2.y - o[1];
+    w.c[2] = (double)P2.z - o[2];
+    w.orig = __float_as_int(P0.w);
+    w.leaf = li;
+}
+
 // Trace one lane's subray: fills tri (original index or -1), R, cos, P.
-// staged: the pulse's first candidate records sit in rec[q * 16, q * 16 + min(nc, 16)).
+// staged: the pulse's first min(nc, per) candidates sit in rec[q * per, ...)
+// (per = staged_per_pulse); in a CHUNK launch only the n_kept of them that may
+// meet one of its subrays, in rec[0, n_kept).
 template <bool COUNT, bool CHUNK>
 __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
-                                           long long p, int k, int q, const Ray& r, bool ray_ok, bool staged,
-                                           CandRec* rec, int* ring, int ring_mask, int& tri, double& R,
-                                           float& cosang, float& P, int& visits, int& tests)
+                                           long long p, int k, int q, const Ray& r, const Basis& B, bool ray_ok,
+                                           bool staged, int n_kept, CandRec* rec, int* ring, int ring_mask,
+                                           int& tri, double& R, float& cosang, float& P, int& visits, int& tests)
 {
     tri = -1;
     R = INFINITY;
@@ -379,16 +469,17 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
         const int per = staged_per_pulse(sc.P_w);
         const CandRec* mine = rec + q * per;
         const int ns = nc < per ? nc : per;
+        const int nk = CHUNK ? n_kept : ns;
         const int kz0 = __builtin_amdgcn_readfirstlane(r.kz);
         int best;
         if (__ballot(r.kz != kz0) == 0) {
-            if (kz0 == 2) best = cand_loop<2>(r, mine, ns, h);
-            else if (kz0 == 1) best = cand_loop<1>(r, mine, ns, h);
-            else best = cand_loop<0>(r, mine, ns, h);
+            if (kz0 == 2) best = cand_loop<2>(r, mine, nk, h);
+            else if (kz0 == 1) best = cand_loop<1>(r, mine, nk, h);
+            else best = cand_loop<0>(r, mine, nk, h);
         } else {
-            if (r.kz == 2) best = cand_loop<2>(r, mine, ns, h);
-            else if (r.kz == 1) best = cand_loop<1>(r, mine, ns, h);
-            else best = cand_loop<0>(r, mine, ns, h);
+            if (r.kz == 2) best = cand_loop<2>(r, mine, nk, h);
+            else if (r.kz == 1) best = cand_loop<1>(r, mine, nk, h);
+            else best = cand_loop<0>(r, mine, nk, h);
         }
         const int* cand = pulses.cand + p * (kCandMax + 1);
         if (CHUNK && sc.P_w == 1 && nc > ns) {
@@ -397,30 +488,29 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
             // subray lanes (all of them take this branch together, k = 0..S-1)
             int best_leaf = best >= 0 ? mine[best].leaf : -1;
             const double* o = pulses.origins + 3 * p;
+            const CullBasis cb = cull_basis(B, sc.tan_max);
             for (int base = ns; base < nc; base += kWave) {
                 const int m = nc - base < kWave ? nc - base : kWave;
                 wave_sync();  // the previous chunk has been read
-                for (int j = k; j < m; j += sc.S) {
-                    const int li = min(max(cand[1 + base + j], 0), scene.n_tri - 1);
-                    const float4 P0 = scene.tris[3 * li], P1 = scene.tris[3 * li + 1], P2 = scene.tris[3 * li + 2];
-                    CandRec& w = rec[j];
-                    w.a[0] = (double)P0.x - o[0];
-                    w.a[1] = (double)P0.y - o[1];
-                    w.a[2] = (double)P0.z - o[2];
-                    w.b[0] = (double)P1.x - o[0];
-                    w.b[1] = (double)P1.y - o[1];
-                    w.b[2] = (double)P1.z - o[2];
-                    w.c[0] = (double)P2.x - o[0];
-                    w.c[1] = (double)P2.y - o[1];
-                    w.c[2] = (double)P2.z - o[2];
-                    w.orig = __float_as_int(P0.w);
-                    w.leaf = li;
+                // record j of the chunk in slot j; bit j of `keep` set when it
+                // may meet a subray (lane k stages j = k, k + S, ...)
+                unsigned long long keep = 0;
+                for (int j0 = 0; j0 < m; j0 += sc.S) {
+                    const int j = j0 + k;
+                    bool kp = false;
+                    if (j < m) {
+                        const int li = min(max(cand[1 + base + j], 0), scene.n_tri - 1);
+                        CandRec& w = rec[j];
+                        stage_rec(w, scene.tris[3 * li], scene.tris[3 * li + 1], scene.tris[3 * li + 2], o, li);
+                        kp = cone_may_hit(w.a, w.b, w.c, cb);
+                    }
+                    keep |= __ballot(kp) << j0;
                 }
                 wave_sync();
                 int b2;
-                if (r.kz == 2) b2 = cand_loop<2>(r, rec, m, h);
-                else if (r.kz == 1) b2 = cand_loop<1>(r, rec, m, h);
-                else b2 = cand_loop<0>(r, rec, m, h);
+                if (r.kz == 2) b2 = cand_loop_mask<2>(r, rec, keep, h);
+                else if (r.kz == 1) b2 = cand_loop_mask<1>(r, rec, keep, h);
+                else b2 = cand_loop_mask<0>(r, rec, keep, h);
                 if (b2 >= 0) best_leaf = rec[b2].leaf;
             }
             if (COUNT) tests += nc;
@@ -486,8 +576,12 @@ __device__ __forceinline__ void stream_zero4(float4* p)
 
 // Contribution of one echo to a bin: offsets are taken from the centre bin jc of
 // the bin's chunk, so x = (l - 32) bin (lane l) and the echo offset
-// r = (tau - t0) - jc bin (FP64, split into FP32 hi + lo) are both small, and
-// s = (x - hi) - lo keeps FP64 accuracy in FP32 arithmetic.
+// r = (tau - t0) - jc bin (FP64, split into FP32 hi + lo) are both small.  The
+// waveform sums take s = x - hi: |r| stays within a chunk's reach (tens of ns),
+// so dropping lo moves s by at most half an FP32 ulp of r (~1e-6 ns) and a bin's
+// value by ~1e-6 relative at the pulse's flanks, a tenth of the waveform bound;
+// the attribution of returns, which compares subrays at one bin, takes
+// s = (x - hi) - lo with FP64 accuracy.
 __device__ __forceinline__ void echo_offset(const ScannerDev& sc, double rel, int jc, float& hi, float& lo)
 {
     const double r = rel - (double)jc * sc.bin_d;
@@ -575,7 +669,7 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
 #pragma unroll 4
             for (int kk = 0; kk < S; ++kk) {
                 const float4 u = sub[k0 + kk];
-                acc = fmaf(u.z, pulse_shape<SHAPE>(sc, (x - u.x) - u.y), acc);
+                acc = fmaf(u.z, pulse_shape<SHAPE>(sc, x - u.x), acc);
             }
             wf[c] = jb + c * kWave + lane < nb ? acc : 0.0f;
             wave_sync();
@@ -738,8 +832,8 @@ __device__ __forceinline__ void pulse_pair(const ScannerDev& sc, const PulsesDev
 #pragma unroll 4
         for (int kk = 0; kk < S; ++kk) {
             const float4 u = sub[hb + kk];
-            acc0 = fmaf(u.z, pulse_shape<SHAPE>(sc, (x0 - u.x) - u.y), acc0);
-            acc1 = fmaf(u.z, pulse_shape<SHAPE>(sc, (x1 - u.x) - u.y), acc1);
+            acc0 = fmaf(u.z, pulse_shape<SHAPE>(sc, x0 - u.x), acc0);
+            acc1 = fmaf(u.z, pulse_shape<SHAPE>(sc, x1 - u.x), acc1);
         }
         const int j0 = jb + c * kWave + l;
         if (c < nch) {
@@ -934,6 +1028,8 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     const int sq = lane >> per_shift, sc16 = lane & ((1 << per_shift) - 1);
     int nq = -1, li = 0;
     float4 P0, P1, P2;
+    Basis Bq;  // the staged pulse's basis (for the cull test)
+    bool bq_ok = false;
     if (staged && sq < npw && scene.n_tri > 0) {
         const int* row = pulses.cand + (first + sq) * (kCandMax + 1);
         nq = row[0];
@@ -941,6 +1037,9 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
         P0 = scene.tris[3 * li];
         P1 = scene.tris[3 * li + 1];
         P2 = scene.tris[3 * li + 2];
+        if (CHUNK)
+            bq_ok = pulses.basis ? load_basis(pulses.basis + 5 * (first + sq), Bq)
+                                 : pulse_basis(pulses.dirs + 3 * (first + sq), Bq);
     }
     Ray r;
     // the pulse's basis comes from the cone pass when it ran (same values)
@@ -949,21 +1048,25 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
                         (pulses.basis ? load_basis(pulses.basis + 5 * (first + pl), B)
                                       : pulse_basis(pulses.dirs + 3 * (first + pl), B)) &&
                         setup_ray_b(pulses.origins + 3 * (first + pl), B, sc.pattern + 5 * k, r);
+    // With one pulse per wavefront (long candidate lists), the staged
+    // candidates that may meet one of its subrays, packed in list order (a
+    // pulse without a valid direction keeps all: its subrays trace nothing);
+    // with several, all of them (short lists, where the test costs more than
+    // it saves).
+    int n_kept = 0;
     if (staged) {
-        if (sc16 < nq) {
-            const double* o = pulses.origins + 3 * (first + sq);
-            CandRec& w = rec[lane];
-            w.a[0] = (double)P0.x - o[0];
-            w.a[1] = (double)P0.y - o[1];
-            w.a[2] = (double)P0.z - o[2];
-            w.b[0] = (double)P1.x - o[0];
-            w.b[1] = (double)P1.y - o[1];
-            w.b[2] = (double)P1.z - o[2];
-            w.c[0] = (double)P2.x - o[0];
-            w.c[1] = (double)P2.y - o[1];
-            w.c[2] = (double)P2.z - o[2];
-            w.orig = __float_as_int(P0.w);
-            w.leaf = li;
+        if (CHUNK) {
+            CandRec w;
+            bool keep = false;
+            if (sc16 < nq) {
+                stage_rec(w, P0, P1, P2, pulses.origins + 3 * (first + sq), li);
+                keep = !bq_ok || cone_may_hit(w.a, w.b, w.c, cull_basis(Bq, sc.tan_max));
+            }
+            const unsigned long long kept = __ballot(keep);
+            if (keep) rec[lanes_below(kept)] = w;
+            n_kept = __popcll(kept);
+        } else if (sc16 < nq) {
+            stage_rec(rec[lane], P0, P1, P2, pulses.origins + 3 * (first + sq), li);
         }
         wave_sync();
     }
@@ -973,7 +1076,8 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     int visits = 0, tests = 0;
     if (active) {
         long long p = first + pl;
-        trace_lane<MODE == 2, CHUNK>(scene, sc, pulses, p, k, pl, r, ray_ok, staged, rec, ring, ring_mask, tri, R, cs, P,
+        trace_lane<MODE == 2, CHUNK>(scene, sc, pulses, p, k, pl, r, B, ray_ok, staged, n_kept, rec, ring, ring_mask,
+                                     tri, R, cs, P,
                               visits, tests);
         if (VOX && ray_ok) {
             // a voxel that stops the subray before its closest triangle takes the
