@@ -173,6 +173,7 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
                                          int ring_mask, int& visits)
 {
     int n = 0;
+    int b0 = 0, b1 = 0, b2 = 0, b3 = 0;  // the row's current group of four entries
     float tcull = INFINITY;
     const int stride = blockDim.x;
     // stack entries carry their entry distance, so nodes pushed before a cull
@@ -226,7 +227,15 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
                 n = -1;
                 busy = false;
             } else {
-                out[1 + n] = ~node;
+                // row entry 1 + n goes to the lane's four-entry buffer; a full,
+                // 16-byte aligned group of four is stored at once (entry 0, the
+                // count, is stored after the walk)
+                const int e = 1 + n, id = ~node;
+                b0 = (e & 3) == 0 ? id : b0;
+                b1 = (e & 3) == 1 ? id : b1;
+                b2 = (e & 3) == 2 ? id : b2;
+                b3 = (e & 3) == 3 ? id : b3;
+                if ((e & 3) == 3) *reinterpret_cast<int4*>(out + (e - 3)) = make_int4(b0, b1, b2, b3);
                 ++n;
                 if (pend < 0) pend = ~node;
                 pop = true;
@@ -266,6 +275,13 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
                 pend = -1;
             }
         }
+    }
+    // the last, partial group: entries (1 + n) & ~3 .. n (entry 0 is the count)
+    if (n > 0) {
+        const int e = (1 + n) & ~3, r = (1 + n) & 3;
+        if (e > 0 && r > 0) out[e] = b0;
+        if (r > 1) out[e + 1] = b1;
+        if (r > 2) out[e + 2] = b2;
     }
     return n;
 }

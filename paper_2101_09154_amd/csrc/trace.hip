@@ -1028,8 +1028,6 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     const int sq = lane >> per_shift, sc16 = lane & ((1 << per_shift) - 1);
     int nq = -1, li = 0;
     float4 P0, P1, P2;
-    Basis Bq;  // the staged pulse's basis (for the cull test)
-    bool bq_ok = false;
     if (staged && sq < npw && scene.n_tri > 0) {
         const int* row = pulses.cand + (first + sq) * (kCandMax + 1);
         nq = row[0];
@@ -1037,17 +1035,16 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
         P0 = scene.tris[3 * li];
         P1 = scene.tris[3 * li + 1];
         P2 = scene.tris[3 * li + 2];
-        if (CHUNK)
-            bq_ok = pulses.basis ? load_basis(pulses.basis + 5 * (first + sq), Bq)
-                                 : pulse_basis(pulses.dirs + 3 * (first + sq), Bq);
     }
     Ray r;
     // the pulse's basis comes from the cone pass when it ran (same values)
+    // (one pulse per wavefront: every lane loads it, the staging lanes beyond
+    // the subrays test candidates against it)
     Basis B;
-    const bool ray_ok = active &&
-                        (pulses.basis ? load_basis(pulses.basis + 5 * (first + pl), B)
-                                      : pulse_basis(pulses.dirs + 3 * (first + pl), B)) &&
-                        setup_ray_b(pulses.origins + 3 * (first + pl), B, sc.pattern + 5 * k, r);
+    const long long pb = CHUNK ? first : first + pl;
+    const bool b_ok = (CHUNK || active) && (pulses.basis ? load_basis(pulses.basis + 5 * pb, B)
+                                                         : pulse_basis(pulses.dirs + 3 * pb, B));
+    const bool ray_ok = active && b_ok && setup_ray_b(pulses.origins + 3 * (first + pl), B, sc.pattern + 5 * k, r);
     // With one pulse per wavefront (long candidate lists), the staged
     // candidates that may meet one of its subrays, packed in list order (a
     // pulse without a valid direction keeps all: its subrays trace nothing);
@@ -1060,7 +1057,7 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
             bool keep = false;
             if (sc16 < nq) {
                 stage_rec(w, P0, P1, P2, pulses.origins + 3 * (first + sq), li);
-                keep = !bq_ok || cone_may_hit(w.a, w.b, w.c, cull_basis(Bq, sc.tan_max));
+                keep = !b_ok || cone_may_hit(w.a, w.b, w.c, cull_basis(B, sc.tan_max));
             }
             const unsigned long long kept = __ballot(keep);
             if (keep) rec[lanes_below(kept)] = w;
@@ -1132,9 +1129,9 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
 }
 
 template <int MAXCH, int MODE, bool CHUNK, bool VOX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_simulate(SceneDev scene, ScannerDev sc, PulsesDev pulses,
-                                                  OutDev out, long long first, long long count, int ring_mask,
-                                                  int wl_bytes)
+__device__ __forceinline__ void simulate_body(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
+                                              const OutDev& out, long long first, long long count, int ring_mask,
+                                              int wl_bytes)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int waves = blockDim.x / kWave;
@@ -1146,6 +1143,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     long long left = count - p0;
     int npw = left < sc.P_w ? (int)left : sc.P_w;
     process_wave<MAXCH, MODE, CHUNK, VOX>(scene, sc, pulses, out, first + p0, npw, ring, ring_mask, wl);
+}
+
+// Several pulses per wavefront: six wavefronts per SIMD (80 registers).
+template <int MAXCH, int MODE, bool VOX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_simulate(SceneDev scene,
+    ScannerDev sc, PulsesDev pulses, OutDev out, long long first, long long count, int ring_mask, int wl_bytes)
+{
+    simulate_body<MAXCH, MODE, false, VOX>(scene, sc, pulses, out, first, count, ring_mask, wl_bytes);
+}
+
+// One pulse per wavefront (candidate lists staged in chunks and culled): five
+// wavefronts per SIMD, whose 96 registers hold the chunk loop without spills.
+template <int MAXCH, int MODE, bool VOX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_simulate1(SceneDev scene,
+    ScannerDev sc, PulsesDev pulses, OutDev out, long long first, long long count, int ring_mask, int wl_bytes)
+{
+    simulate_body<MAXCH, MODE, true, VOX>(scene, sc, pulses, out, first, count, ring_mask, wl_bytes);
 }
 
 // Waveform from stored subrays (KIND 0) or returns from stored waveforms (KIND 1).
@@ -1542,10 +1556,10 @@ hipError_t launch_simulate(const SceneDev& scene, const ScannerDev& sc, const Pu
 #define VLS_SIM_LAUNCH_V(CH, MODE, VOX)                                                                       \
     do {                                                                                                     \
         if (sc.P_w == 1 && MODE != 2)                                                                        \
-            hipLaunchKernelGGL((k_simulate<CH, MODE, true, VOX>), dim3(grid), dim3(block), lds, stream, scene, sc, \
+            hipLaunchKernelGGL((k_simulate1<CH, MODE, VOX>), dim3(grid), dim3(block), lds, stream, scene, sc, \
                                pulses, out, first, count, mask, wl);                                         \
         else                                                                                                 \
-            hipLaunchKernelGGL((k_simulate<CH, MODE, false, VOX>), dim3(grid), dim3(block), lds, stream, scene, sc, \
+            hipLaunchKernelGGL((k_simulate<CH, MODE, VOX>), dim3(grid), dim3(block), lds, stream, scene, sc, \
                                pulses, out, first, count, mask, wl);                                         \
     } while (0)
 #define VLS_SIM_LAUNCH(CH, MODE)               \
