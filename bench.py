@@ -145,6 +145,10 @@ def bench_plain(ctx, name, label, mesh, pulses, sc, steps, seed, hbm=True):
     out = ctx.alloc_outputs(n, S, nb, K, dev, subrays=False)
     stream = torch.cuda.current_stream()
     cand, n_over = candidate_census(ctx, scene, sc, o, d)
+    visits = None
+    if hbm:
+        # the cone pass's four-wide records visited (a counting pass, untimed)
+        _, visits, _ = ctx.trace_counts(scene, sc, o, d)
     ms = time_ms(lambda: ctx.simulate(scene, sc, o, d, out=out), steps, 2, stream)
     ctx.profile(True)
     for _ in range(steps):
@@ -172,6 +176,14 @@ def bench_plain(ctx, name, label, mesh, pulses, sc, steps, seed, hbm=True):
                      "each launch on its stream" % steps}
     if hbm:
         res["fused"]["frac"] = res["fused"]["achieved_GBps"] / HBM_PEAK_GBS
+        # cone pass: 112 B per four-wide record visited, pulse in (36 B), count
+        # and basis out (4 + 40 B), 52 B per listed candidate (id out, triangle
+        # read by the cover test)
+        cone_bytes = 112.0 * visits + n * (36.0 + 4.0 + 40.0) + 52.0 * cand
+        res["cone"] = {"node_visits_per_pulse": visits / n, "algorithmic_bytes_per_launch": cone_bytes,
+                       "achieved_GBps": cone_bytes / (cone_ms * 1e-3) / 1e9,
+                       "level": "records re-read by neighbouring pulses are served by L2 and the last-level "
+                                "cache: the counters' traffic (below) is what reaches HBM"}
         rec = traffic_record(name, source_hash())
         if rec:
             for kern, t in (("fused", fused_ms), ("cone", cone_ms), ("packet", packet_ms)):
