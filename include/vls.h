@@ -487,7 +487,14 @@ vls_status vls_echo_width(vls_context ctx, const vls_scanner_desc* scanners, int
 /* The whole path fused in one launch: trace, power, waveform, returns.
  * waveform may be NULL (returns are still found from the in-register
  * waveform, Sec. 5.4: binning runs even when no waveform is written).
- * With segments, one persistent launch covers every segment. */
+ * With segments, one persistent launch covers every segment.  Before it, a
+ * cone pass lists each pulse's candidate triangles (Sec. 3.4: every subray of
+ * a pulse leaves its origin within the beam's divergence): up to
+ * VLS_MAX_CANDIDATES per pulse in the stream's workspace (1 KiB per pulse);
+ * a pulse with more gets a second walk into a long list of up to 2,048
+ * (8 KiB each, for the first 65,536 such pulses of a call); a pulse past
+ * that is walked by one wavefront, all its subrays together.  The results do
+ * not depend on which of these a pulse takes. */
 vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
                         const vls_pulse_batch* pulses, const vls_outputs* out, void* stream);
 

@@ -160,6 +160,8 @@ struct vls_context_s {
         hipStream_t stream = nullptr;
         int* cand = nullptr;                // cone-pass workspace (cone_ws_*)
         size_t cand_bytes = 0;
+        int* longw = nullptr;               // long candidate lists (long_ws_*)
+        size_t long_bytes = 0;
         int* ew = nullptr;                  // echo-width list of returns + counter
         size_t ew_bytes = 0;
         unsigned char* tlw = nullptr;       // two-level simulate: subrays, waveform and t0 not asked for
@@ -191,7 +193,7 @@ struct vls_context_s {
                 (void)hipEventDestroy(e.second);
             }
         for (auto& w : workspaces)
-            for (void* q : {(void*)w->cand, (void*)w->ew, (void*)w->tlw, (void*)w->adw, (void*)w->ctr})
+            for (void* q : {(void*)w->cand, (void*)w->longw, (void*)w->ew, (void*)w->tlw, (void*)w->adw, (void*)w->ctr})
                 if (q) (void)hipFreeAsync(q, nullptr);
         (void)hipDeviceSynchronize();
         for (auto& t : surveys) (void)hipFree(t.dev);
@@ -499,6 +501,7 @@ PulsesDev pulses_dev(const vls_pulse_batch* p)
     d.n = p->n_pulses;
     d.basis = nullptr;
     d.cand = nullptr;
+    d.cand_long = nullptr;
     return d;
 }
 
@@ -597,7 +600,9 @@ vls_status cone_workspace(vls_context ctx, long long n, hipStream_t s, vls_conte
     vls_status st = stream_ws(ctx, s, w);
     if (st != VLS_OK) return st;
     if (!ctx->cfg.cone || n <= 0) return VLS_OK;
-    return ws_grow(w->cand, w->cand_bytes, sizeof(int) * cone_ws_ints(n), s, "candidate workspace");
+    st = ws_grow(w->cand, w->cand_bytes, sizeof(int) * cone_ws_ints(n), s, "candidate workspace");
+    if (st != VLS_OK) return st;
+    return ws_grow(w->longw, w->long_bytes, sizeof(int) * long_ws_ints(n), s, "long candidate workspace");
 }
 
 // The ranging error of every segment's returns, once they are found.
@@ -1655,9 +1660,12 @@ static hipError_t prof_end(vls_context ctx, hipStream_t s, std::pair<hipEvent_t,
 // point, whose caller may forbid creating them)
 // cand, ctr: the cone-pass workspace and the batched launch's work counter (a
 // stream's workspace, a graph's own, or the allocation-free entry point's array)
+// longw: the long-list workspace, or null (overflowed pulses then all take the
+// packet walk; the results are the same)
 static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepared& pr, const vls_pulse_batch* pulses,
                                    const vls_outputs* out, vls_context_s::Batch* bt, int blocks, hipStream_t s,
-                                   int* cand, unsigned long long* batch_ctr, bool allow_prof = true)
+                                   int* cand, unsigned long long* batch_ctr, bool allow_prof = true,
+                                   int* longw = nullptr)
 {
     if (pulses->n_pulses == 0) return VLS_OK;
     OutDev od = out_dev(out, pr.S_stride);
@@ -1682,6 +1690,15 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
         double* basis = cone_ws_basis(cand, n);
         e = launch_cone(sd, max_tan(pr), pd, cand, 0, n, ctx->cfg, nullptr, list, ctr, basis, s);
         if (e != hipSuccess) return hip_fail(e, "cone launch");
+        if (longw) {
+            // pulses whose row overflowed: a second walk into the long rows
+            pd.basis = basis;
+            e = launch_cone_long(sd, max_tan(pr), pd, cand, list, ctr, n, longw, ctx->cfg, s);
+            if (e != hipSuccess) return hip_fail(e, "long-list cone launch");
+            list = long_ws_list(longw, n);
+            ctr = long_ws_ctr(longw, n);
+            pd.cand_long = longw;
+        }
         if (prof && (e = prof_end(ctx, s, ev, ctx->prof_cone)) != hipSuccess) return hip_fail(e, "timing event");
         // pulses whose candidate list overflowed: one wavefront walks each pulse's subrays together
         if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
@@ -1757,7 +1774,7 @@ vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc
         vls_status st = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, bt, blocks, s, &ws, true);
         if (st != VLS_OK) return st;
         if (scene->tl) return simulate_two_level(ctx, scene, pr, pulses, out, s, ws);
-        return simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, s, ws->cand, ws->ctr);
+        return simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, s, ws->cand, ws->ctr, true, ws->longw);
     } catch (const std::exception& e) {
         return fail(VLS_ERR_INTERNAL, e.what());
     }
@@ -2014,14 +2031,14 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             int bl = 0;
             vls_status r = simulate_prepare(ctx, scene, scanners, n_scanners, pulses, out, pr, b2, bl, s, &ws);
             if (r != VLS_OK) return r;
-            if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s, ws->cand, ws->ctr)) != VLS_OK) return r;
+            if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s, ws->cand, ws->ctr, true, ws->longw)) != VLS_OK) return r;
             // the fastest of three pairs of launches: single timings vary by a few
             // per cent, as much as the configurations differ
             ms = INFINITY;
             for (int g = 0; g < 3; ++g) {
                 VLS_HIP(hipEventRecord(e0, s), "event");
                 for (int i = 0; i < 2; ++i)
-                    if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s, ws->cand, ws->ctr)) != VLS_OK)
+                    if ((r = simulate_enqueue(ctx, scene, pr, pulses, out, b2, bl, s, ws->cand, ws->ctr, true, ws->longw)) != VLS_OK)
                         return r;
                 VLS_HIP(hipEventRecord(e1, s), "event");
                 VLS_HIP(hipEventSynchronize(e1), "event");

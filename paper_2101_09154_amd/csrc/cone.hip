@@ -159,8 +159,9 @@ __device__ __forceinline__ double cover_distance(const Cone& c, const float4* __
     return (fabs(tn) / dmin) * (1.0 + 1e-9) + 1e-9;
 }
 
-// One lane's cone traversal: writes the candidate leaves to out[1..] and returns
-// their count (-1: more than kCandMax, or a corrupted structure).
+// One lane's cone traversal: writes the candidate leaves to out[e0..] and
+// returns their count (-1: more than cap, or a corrupted structure).  out is
+// 16-byte aligned; entries below e0 (a row's count) are left to the caller.
 //
 // A leaf is recorded and the walk moves on at once; the cover test (the
 // expensive part, and only an aid to culling) runs on a lane's first untested
@@ -168,9 +169,9 @@ __device__ __forceinline__ double cover_distance(const Cone& c, const float4* __
 // one waiting, so that the wavefront does not pay for it in every step in which
 // some lane sits at a leaf.  A later or skipped cover test only culls less; the
 // list still holds every leaf the cone reaches before the cull that applies.
-template <bool COUNT, bool MIXED>
-__device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, int* __restrict__ out, int2* my,
-                                         int ring_mask, int& visits)
+template <bool COUNT, bool MIXED, bool COVER = true>
+__device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, int* __restrict__ out, int e0, int cap,
+                                         int2* my, int ring_mask, int& visits)
 {
     int n = 0;
     int b0 = 0, b1 = 0, b2 = 0, b3 = 0;  // the row's current group of four entries
@@ -223,21 +224,21 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
                         ++sp;
                     }
                 }
-            } else if (n == kCandMax) {  // too many: the subrays traverse on their own
+            } else if (n == cap) {  // too many: a longer list or the subrays' own walks
                 n = -1;
                 busy = false;
             } else {
-                // row entry 1 + n goes to the lane's four-entry buffer; a full,
-                // 16-byte aligned group of four is stored at once (entry 0, the
-                // count, is stored after the walk)
-                const int e = 1 + n, id = ~node;
+                // entry e0 + n goes to the lane's four-entry buffer; a full,
+                // 16-byte aligned group of four is stored at once (a row's
+                // entry 0, the count, is stored after the walk)
+                const int e = e0 + n, id = ~node;
                 b0 = (e & 3) == 0 ? id : b0;
                 b1 = (e & 3) == 1 ? id : b1;
                 b2 = (e & 3) == 2 ? id : b2;
                 b3 = (e & 3) == 3 ? id : b3;
                 if ((e & 3) == 3) *reinterpret_cast<int4*>(out + (e - 3)) = make_int4(b0, b1, b2, b3);
                 ++n;
-                if (pend < 0) pend = ~node;
+                if (COVER && pend < 0) pend = ~node;
                 pop = true;
             }
             if (pop) {
@@ -276,12 +277,13 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
             }
         }
     }
-    // the last, partial group: entries (1 + n) & ~3 .. n (entry 0 is the count)
+    // the last, partial group: entries (e0 + n) & ~3 .. e0 + n - 1, those below
+    // e0 excepted
     if (n > 0) {
-        const int e = (1 + n) & ~3, r = (1 + n) & 3;
-        if (e > 0 && r > 0) out[e] = b0;
-        if (r > 1) out[e + 1] = b1;
-        if (r > 2) out[e + 2] = b2;
+        const int e = (e0 + n) & ~3, r = (e0 + n) & 3;
+        if (r > 0 && e >= e0) out[e] = b0;
+        if (r > 1 && e + 1 >= e0) out[e + 1] = b1;
+        if (r > 2 && e + 2 >= e0) out[e + 2] = b2;
     }
     return n;
 }
@@ -315,9 +317,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     int2* my = reinterpret_cast<int2*>(smem) + threadIdx.x;
     // the cheaper slab test serves every wavefront without a mixed-sign axis
     if (__ballot(ok && c.mixed) == 0) {
-        if (ok) n = cone_walk<COUNT, false>(scene, c, out, my, ring_mask, visits);
+        if (ok) n = cone_walk<COUNT, false>(scene, c, out, 1, kCandMax, my, ring_mask, visits);
     } else {
-        if (ok) n = cone_walk<COUNT, true>(scene, c, out, my, ring_mask, visits);
+        if (ok) n = cone_walk<COUNT, true>(scene, c, out, 1, kCandMax, my, ring_mask, visits);
     }
     if (active) out[0] = n;
     if (ovf_list) {
@@ -341,6 +343,68 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
 }
 
+// Second pass over the overflowed pulses: list[i] (i < *ctr) is a pulse index
+// relative to the launch.  Pulse i of the list walks again with room for
+// kLongMax candidates in long row i (while i < rows); a list that fits makes
+// the pulse's row (count, long row index); the others go to list2 for the packet
+// walk, one counter update per wavefront.  A grid-stride loop covers the list.
+// COVER: cover tests as in the first pass.  The long pass runs without them:
+// pulses that overflow are the ones no triangle covers (a canopy's leaves), so
+// the tests would only cost time (8.1 against 8.9 ms for both passes on the
+// vegetation workload, the same lists' worth of fused time).
+template <bool COVER>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_cone_long(
+    SceneDev scene, double tana, PulsesDev pulses, int* __restrict__ cand, const int* __restrict__ list,
+    const unsigned long long* ctr, long long rows, int* __restrict__ long_rows, int* list2,
+    unsigned long long* ctr2, int ring_mask)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const long long n_ovf = (long long)__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    int2* my = reinterpret_cast<int2*>(smem) + threadIdx.x;
+    const long long start = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // every lane of a wavefront takes the same number of turns (the ballot
+    // below needs the whole wavefront)
+    const long long wave0 = start - (threadIdx.x & (kWave - 1));
+    for (long long base = wave0; base < n_ovf; base += stride) {
+        const long long i = base + (threadIdx.x & (kWave - 1));
+        const bool active = i < n_ovf;
+        const long long q = active ? list[i] : 0;
+        int n = -1;
+        if (active && i < rows) {
+            dev::Basis B;
+            Cone c;
+            const bool ok = scene.n_tri > 0 && dev::load_basis(pulses.basis + 5 * q, B) &&
+                            setup_cone(pulses.origins + 3 * q, B, tana, scene.bounds[12], c);
+            int visits = 0;
+            int* out = long_rows + (size_t)i * kLongMax;
+            if (ok) n = c.mixed ? cone_walk<false, true, COVER>(scene, c, out, 0, kLongMax, my, ring_mask, visits)
+                                : cone_walk<false, false, COVER>(scene, c, out, 0, kLongMax, my, ring_mask, visits);
+            if (n > kCandMax) {
+                int* row = cand + q * (kCandMax + 1);
+                row[0] = n;
+                row[1] = (int)i;
+            } else if (n >= 0) {
+                // the second walk's culls came at other times and it fits a row
+                int* row = cand + q * (kCandMax + 1);
+                for (int j = 0; j < n; ++j) row[1 + j] = out[j];
+                row[0] = n;
+            }
+        }
+        const unsigned long long m = __ballot(active && n < 0);
+        if (m) {
+            const int lane = threadIdx.x & (kWave - 1);
+            const int leader = __ffsll((long long)m) - 1;
+            unsigned long long b = 0;
+            if (lane == leader) b = atomicAdd(ctr2, (unsigned long long)__popcll(m));
+            const unsigned b_lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, leader);
+            const unsigned b_hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), leader);
+            const unsigned long long bb = ((unsigned long long)b_hi << 32) | b_lo;
+            if (active && n < 0) list2[bb + dev::lanes_below(m)] = (int)q;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_leaf_to_orig(const int32_t* __restrict__ leaf_tri, int* __restrict__ cand,
                                                       long long n)
 {
@@ -357,6 +421,26 @@ hipError_t launch_leaf_to_orig(const int32_t* leaf_tri, int* cand, long long n_p
 {
     hipLaunchKernelGGL(k_leaf_to_orig, dim3((unsigned)((n_pulses + 255) / 256)), dim3(256), 0, stream, leaf_tri, cand,
                        n_pulses);
+    return hipGetLastError();
+}
+
+hipError_t launch_cone_long(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand,
+                            const int* list, const unsigned long long* ctr, long long n, int* longw,
+                            const LaunchCfg& cfg, hipStream_t stream)
+{
+    int* list2 = long_ws_list(longw, n);
+    unsigned long long* ctr2 = long_ws_ctr(longw, n);
+    hipError_t e = launch_fill_u64(ctr2, 2, 0ull, stream);
+    if (e != hipSuccess) return e;
+    if (n <= 0) return hipSuccess;
+    // one lane per long row at most; the list's count is read on the device
+    const int block = kWave;
+    const long long rows = long_rows(n);
+    const unsigned grid = (unsigned)((rows + block - 1) / block);
+    const size_t lds = sizeof(int2) * (size_t)kConeRing * block;
+    (void)cfg;
+    hipLaunchKernelGGL(k_cone_long<false>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, list,
+                       ctr, rows, longw, list2, ctr2, kConeRing - 1);
     return hipGetLastError();
 }
 

@@ -481,7 +481,7 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
             else if (r.kz == 1) best = cand_loop<1>(r, mine, nk, h);
             else best = cand_loop<0>(r, mine, nk, h);
         }
-        const int* cand = pulses.cand + p * (kCandMax + 1);
+        const int* cand = cand_ids(pulses.cand + p * (kCandMax + 1), nc, pulses.cand_long);
         if (CHUNK && sc.P_w == 1 && nc > ns) {
             // one pulse per wavefront: the rest are staged in chunks of 64 as
             // well, each triangle loaded and translated once for the pulse by the
@@ -499,7 +499,7 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
                     const int j = j0 + k;
                     bool kp = false;
                     if (j < m) {
-                        const int li = min(max(cand[1 + base + j], 0), scene.n_tri - 1);
+                        const int li = min(max(cand[base + j], 0), scene.n_tri - 1);
                         CandRec& w = rec[j];
                         stage_rec(w, scene.tris[3 * li], scene.tris[3 * li + 1], scene.tris[3 * li + 2], o, li);
                         kp = cone_may_hit(w.a, w.b, w.c, cb);
@@ -520,7 +520,7 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
             h.leaf = best_leaf;
         } else {
             // candidates beyond the staged ones come from the leaf records
-            for (int i = ns; i < nc; ++i) leaf_test(r, scene.tris, cand[1 + i], h);
+            for (int i = ns; i < nc; ++i) leaf_test(r, scene.tris, cand[i], h);
             if (COUNT) tests += nc;
         }
         if (h.leaf >= 0) {
@@ -541,6 +541,7 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
             // the pulse's candidates, or the one leaf a packet walk found for
             // this subray (-1: none)
             const int* ids = pulses.cand + p * (kCandMax + 1) + 1;
+            if (nc > kCandMax) ids = cand_ids(ids - 1, nc, pulses.cand_long);
             int cnt = nc;
             if (nc == kWalked) {
                 cnt = 1;
@@ -1031,7 +1032,9 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     if (staged && sq < npw && scene.n_tri > 0) {
         const int* row = pulses.cand + (first + sq) * (kCandMax + 1);
         nq = row[0];
-        li = min(max(row[1 + sc16], 0), scene.n_tri - 1);
+        int id = row[1 + sc16];  // loaded with the count; a long list's ids come after it
+        if (nq > kCandMax && sc16 < nq) id = cand_ids(row, nq, pulses.cand_long)[sc16];
+        li = min(max(id, 0), scene.n_tri - 1);
         P0 = scene.tris[3 * li];
         P1 = scene.tris[3 * li + 1];
         P2 = scene.tris[3 * li + 2];

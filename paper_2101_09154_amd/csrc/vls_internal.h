@@ -33,6 +33,21 @@ inline double* cone_ws_basis(int* ws, long long n)
 {
     return reinterpret_cast<double*>(ws + (size_t)(kCandMax + 1) * n + n + (n & 1) + 4);
 }
+// Long candidate lists: a pulse that overflows its row is walked again by a
+// second cone pass with room for kLongMax candidates, in one of at most
+// kLongPulses rows of a separate workspace; its row then holds the count (past
+// kCandMax) and the long row's index.  Long-list workspace for n pulses: the
+// rows [min(n, kLongPulses)][kLongMax], then the list of pulses left for the
+// packet walk [n], then two 64-bit counters (long-list count, packet-list count).
+constexpr int kLongMax = 2048;
+constexpr long long kLongPulses = 65536;
+__host__ __device__ constexpr long long long_rows(long long n) { return n < kLongPulses ? n : kLongPulses; }
+constexpr size_t long_ws_ints(long long n) { return (size_t)kLongMax * long_rows(n) + n + (n & 1) + 4; }
+inline int* long_ws_list(int* w, long long n) { return w + (size_t)kLongMax * long_rows(n); }
+inline unsigned long long* long_ws_ctr(int* w, long long n)
+{
+    return reinterpret_cast<unsigned long long*>(w + (size_t)kLongMax * long_rows(n) + n + (n & 1));
+}
 // The allocation-free simulate entry point keeps its workspace in a fixed device
 // array: the subray table of its one scanner (5 doubles per subray), then the
 // cone-pass workspace above for at most kNoAllocMaxPulses pulses.
@@ -114,8 +129,16 @@ struct PulsesDev {
     const double* basis;    // [n][5] each pulse's basis from the cone pass (n, a, b), or null
     const int* cand;        // [n][kCandMax + 1] candidate leaves from the cone pass, or null:
                             // entry 0 = count (-1 = overflow, use full traversal; kWalked:
-                            // one leaf per subray from a packet walk), then leaf ids
+                            // one leaf per subray from a packet walk), then leaf ids; a
+                            // count past kCandMax: entry 1 is a row of cand_long
+    const int* cand_long;   // [rows][kLongMax] long candidate lists, or null
 };
+
+// The leaf ids of a pulse's candidate row (count nc > 0 read from row[0]).
+__host__ __device__ inline const int* cand_ids(const int* row, int nc, const int* cand_long)
+{
+    return nc > kCandMax ? cand_long + (size_t)row[1] * kLongMax : row + 1;
+}
 
 struct OutDev {
     int32_t* sub_tri;
@@ -281,6 +304,13 @@ hipError_t launch_backward_det(const SceneDev& scene, const ScannerDev& sc, cons
 hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
                        long long count, const LaunchCfg& cfg, unsigned long long* counts, int* ovf_list,
                        unsigned long long* ovf_ctr, double* basis_out, hipStream_t stream);
+// Second cone pass over the pulses that overflowed their rows (list, ctr from
+// launch_cone): each gets a long row while rows last (its candidate row then
+// holds the count and the long row's index), else it goes to list2 / ctr2 for
+// the packet walk, as do pulses whose long list overflows too.
+hipError_t launch_cone_long(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand,
+                            const int* list, const unsigned long long* ctr, long long n, int* longw,
+                            const LaunchCfg& cfg, hipStream_t stream);
 // Packet walks of the overflowed pulses (see k_packets); batch.n_seg == 0: every
 // pulse uses sc0.
 hipError_t launch_packets(const SceneDev& scene, const ScannerDev& sc0, const BatchDev& batch, const PulsesDev& pulses,
