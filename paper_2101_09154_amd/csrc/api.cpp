@@ -258,7 +258,8 @@ struct vls_graph_s {
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int* cand = nullptr;                // the graph's own cone-pass workspace
+    int* cand = nullptr;                // the graph's own cone-pass workspace,
+    int* longw = nullptr;               // long candidate lists
     unsigned long long* ctr = nullptr;  // and its own work counter for a batched launch
     ~vls_graph_s()
     {
@@ -266,6 +267,7 @@ struct vls_graph_s {
         if (graph) (void)hipGraphDestroy(graph);
         if (cs) (void)hipStreamDestroy(cs);
         (void)hipFree(cand);
+        (void)hipFree(longw);
         (void)hipFree(ctr);
     }
 };
@@ -1265,6 +1267,15 @@ vls_status vls_trace(vls_context ctx, vls_scene scene, const vls_scanner_desc* s
             hipError_t e = launch_cone(sd, max_tan(pr), pd, ws->cand, 0, n, ctx->cfg, nullptr, list, ctr, basis,
                                        (hipStream_t)stream);
             if (e != hipSuccess) return hip_fail(e, "cone launch");
+            if (ws->longw) {
+                pd.basis = basis;
+                e = launch_cone_long(sd, max_tan(pr), pd, ws->cand, list, ctr, n, ws->longw, ctx->cfg,
+                                     (hipStream_t)stream);
+                if (e != hipSuccess) return hip_fail(e, "long-list cone launch");
+                list = long_ws_list(ws->longw, n);
+                ctr = long_ws_ctr(ws->longw, n);
+                pd.cand_long = ws->longw;
+            }
             e = launch_packets(sd, pr.sc[0], bt ? bt->bd : BatchDev{}, pd, ws->cand, list, ctr, 0,
                                (hipStream_t)stream);
             if (e != hipSuccess) return hip_fail(e, "packet launch");
@@ -1930,12 +1941,14 @@ vls_status vls_graph_capture(vls_context ctx, vls_scene scene, const vls_scanner
         g->ctx = ctx;
         // the graph owns its candidate workspace and work counter: graphs and eager
         // calls replayed on other streams must not share them
-        if (ctx->cfg.cone && pulses->n_pulses > 0)
+        if (ctx->cfg.cone && pulses->n_pulses > 0) {
             VLS_HIP(hipMalloc(&g->cand, sizeof(int) * cone_ws_ints(pulses->n_pulses)), "graph workspace");
+            VLS_HIP(hipMalloc(&g->longw, sizeof(int) * long_ws_ints(pulses->n_pulses)), "graph workspace");
+        }
         if (bt) VLS_HIP(hipMalloc(&g->ctr, 64), "graph counter");
         VLS_HIP(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking), "capture stream");
         VLS_HIP(hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal), "begin capture");
-        st = simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, g->cs, g->cand, g->ctr);
+        st = simulate_enqueue(ctx, scene, pr, pulses, out, bt, blocks, g->cs, g->cand, g->ctr, true, g->longw);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(g->cs, &gr);
         if (st != VLS_OK) {
