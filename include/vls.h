@@ -491,10 +491,10 @@ vls_status vls_echo_width(vls_context ctx, const vls_scanner_desc* scanners, int
  * cone pass lists each pulse's candidate triangles (Sec. 3.4: every subray of
  * a pulse leaves its origin within the beam's divergence): up to
  * VLS_MAX_CANDIDATES per pulse in the stream's workspace (1 KiB per pulse);
- * a pulse with more gets a second walk into a long list of up to 2,048
- * (8 KiB each, for the first 65,536 such pulses of a call); a pulse past
- * that is walked by one wavefront, all its subrays together.  The results do
- * not depend on which of these a pulse takes. */
+ * a pulse whose walk reaches more than 159 gets a second walk into a long list
+ * of up to 1,024 (4 KiB each, for the first 262,144 such pulses of a call);
+ * a pulse past that is walked by one wavefront, all its subrays together.
+ * The results do not depend on which of these a pulse takes. */
 vls_status vls_simulate(vls_context ctx, vls_scene scene, const vls_scanner_desc* scanners, int32_t n_scanners,
                         const vls_pulse_batch* pulses, const vls_outputs* out, void* stream);
 

@@ -1265,7 +1265,7 @@ vls_status vls_trace(vls_context ctx, vls_scene scene, const vls_scanner_desc* s
             unsigned long long* ctr = cone_ws_ctr(ws->cand, n);
             double* basis = cone_ws_basis(ws->cand, n);
             hipError_t e = launch_cone(sd, max_tan(pr), pd, ws->cand, 0, n, ctx->cfg, nullptr, list, ctr, basis,
-                                       (hipStream_t)stream);
+                                       (hipStream_t)stream, ws->longw ? kCandFirst : kCandMax);
             if (e != hipSuccess) return hip_fail(e, "cone launch");
             if (ws->longw) {
                 pd.basis = basis;
@@ -1699,7 +1699,8 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
         int* list = cone_ws_list(cand, n);
         unsigned long long* ctr = cone_ws_ctr(cand, n);
         double* basis = cone_ws_basis(cand, n);
-        e = launch_cone(sd, max_tan(pr), pd, cand, 0, n, ctx->cfg, nullptr, list, ctr, basis, s);
+        e = launch_cone(sd, max_tan(pr), pd, cand, 0, n, ctx->cfg, nullptr, list, ctr, basis, s,
+                        longw ? kCandFirst : kCandMax);
         if (e != hipSuccess) return hip_fail(e, "cone launch");
         if (longw) {
             // pulses whose row overflowed: a second walk into the long rows

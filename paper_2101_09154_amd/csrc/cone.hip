@@ -292,7 +292,7 @@ template <bool COUNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_cone(SceneDev scene, double tana, PulsesDev pulses, int* __restrict__ cand,
                                               long long first, long long count, int ring_mask,
                                               unsigned long long* counts, int* ovf_list, unsigned long long* ovf_ctr,
-                                              double* basis_out)
+                                              double* basis_out, int cap)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -317,9 +317,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     int2* my = reinterpret_cast<int2*>(smem) + threadIdx.x;
     // the cheaper slab test serves every wavefront without a mixed-sign axis
     if (__ballot(ok && c.mixed) == 0) {
-        if (ok) n = cone_walk<COUNT, false>(scene, c, out, 1, kCandMax, my, ring_mask, visits);
+        if (ok) n = cone_walk<COUNT, false>(scene, c, out, 1, cap, my, ring_mask, visits);
     } else {
-        if (ok) n = cone_walk<COUNT, true>(scene, c, out, 1, kCandMax, my, ring_mask, visits);
+        if (ok) n = cone_walk<COUNT, true>(scene, c, out, 1, cap, my, ring_mask, visits);
     }
     if (active) out[0] = n;
     if (ovf_list) {
@@ -446,7 +446,7 @@ hipError_t launch_cone_long(const SceneDev& scene, double tan_max, const PulsesD
 
 hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
                        long long count, const LaunchCfg& cfg, unsigned long long* counts, int* ovf_list,
-                       unsigned long long* ovf_ctr, double* basis_out, hipStream_t stream)
+                       unsigned long long* ovf_ctr, double* basis_out, hipStream_t stream, int cap)
 {
     if (ovf_list) {
         hipError_t e = launch_fill_u64(ovf_ctr, 2, 0ull, stream);
@@ -461,10 +461,10 @@ hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& p
     int mask = kConeRing - 1;
     if (counts)
         hipLaunchKernelGGL(k_cone<true>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, first,
-                           count, mask, counts, ovf_list, ovf_ctr, basis_out);
+                           count, mask, counts, ovf_list, ovf_ctr, basis_out, cap);
     else
         hipLaunchKernelGGL(k_cone<false>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, first,
-                           count, mask, counts, ovf_list, ovf_ctr, basis_out);
+                           count, mask, counts, ovf_list, ovf_ctr, basis_out, cap);
     return hipGetLastError();
 }
 

@@ -35,12 +35,17 @@ inline double* cone_ws_basis(int* ws, long long n)
 }
 // Long candidate lists: a pulse that overflows its row is walked again by a
 // second cone pass with room for kLongMax candidates, in one of at most
-// kLongPulses rows of a separate workspace; its row then holds the count (past
+// kLongPulses rows of a separate workspace (4 KiB each); its row then holds the count (past
 // kCandMax) and the long row's index.  Long-list workspace for n pulses: the
 // rows [min(n, kLongPulses)][kLongMax], then the list of pulses left for the
 // packet walk [n], then two 64-bit counters (long-list count, packet-list count).
-constexpr int kLongMax = 2048;
-constexpr long long kLongPulses = 65536;
+constexpr int kLongMax = 1024;
+constexpr long long kLongPulses = 262144;
+// With long lists at hand the first pass stops a pulse's walk at kCandFirst
+// candidates: the long walkers then run together in the second pass instead of
+// holding up the wavefronts of the first (measured on the vegetation workload:
+// 19.2 ms per step against 21.0 ms at 255, 20.1 at 127, 20.3 at 191 and 223).
+constexpr int kCandFirst = 159;
 __host__ __device__ constexpr long long long_rows(long long n) { return n < kLongPulses ? n : kLongPulses; }
 constexpr size_t long_ws_ints(long long n) { return (size_t)kLongMax * long_rows(n) + n + (n & 1) + 4; }
 inline int* long_ws_list(int* w, long long n) { return w + (size_t)kLongMax * long_rows(n); }
@@ -303,7 +308,8 @@ hipError_t launch_backward_det(const SceneDev& scene, const ScannerDev& sc, cons
 // basis_out (optional): each pulse's basis, [p][5] doubles.
 hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
                        long long count, const LaunchCfg& cfg, unsigned long long* counts, int* ovf_list,
-                       unsigned long long* ovf_ctr, double* basis_out, hipStream_t stream);
+                       unsigned long long* ovf_ctr, double* basis_out, hipStream_t stream,
+                       int cap = kCandMax);
 // Second cone pass over the pulses that overflowed their rows (list, ctr from
 // launch_cone): each gets a long row while rows last (its candidate row then
 // holds the count and the long row's index), else it goes to list2 / ctr2 for
