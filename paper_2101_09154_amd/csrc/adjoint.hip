@@ -182,15 +182,15 @@ __global__ __launch_bounds__(256) void k_backward(SceneDev scene, ScannerDev sc,
 // contribution keyed by its triangle, c = 1..3 its height contributions keyed
 // by the triangle's vertices (key = kind << id_bits | id, kind 0 reflectance,
 // 1 height; slots without a hit or an unrequested gradient get the key
-// `none`).  A stable sort by key then puts each parameter's contributions
-// together in entry order, and one thread per run sums them in that order.
+// `none`), with the contribution's FP32 bits as the entry's value.  A stable
+// sort by key then puts each parameter's contributions together in entry
+// order, and one thread per run sums them in that order.
 __global__ __launch_bounds__(256) void k_backward_entries(SceneDev scene, ScannerDev sc, PulsesDev pulses,
                                                           const int32_t* __restrict__ sub_tri, int sub_stride,
                                                           const float* __restrict__ grad_wf, bool want_refl,
                                                           bool want_z, int id_bits, unsigned long long none,
                                                           unsigned long long* __restrict__ keys,
-                                                          int32_t* __restrict__ vals, float* __restrict__ contrib,
-                                                          long long count)
+                                                          int32_t* __restrict__ vals, long long count)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int waves = blockDim.x / kWave;
@@ -218,20 +218,17 @@ __global__ __launch_bounds__(256) void k_backward_entries(SceneDev scene, Scanne
     const long long e = 4 * (p * S + k);
     const int32_t* ti = scene.tri_idx + 3 * (long long)(tri >= 0 ? tri : 0);
     keys[e] = tri >= 0 && want_refl ? (unsigned long long)tri : none;
-    vals[e] = (int32_t)e;
-    contrib[e] = (float)g.grho;
+    vals[e] = __float_as_int((float)g.grho);
     for (int c = 0; c < 3; ++c) {
         keys[e + 1 + c] = tri >= 0 && want_z ? (1ull << id_bits) | (unsigned long long)ti[c] : none;
-        vals[e + 1 + c] = (int32_t)(e + 1 + c);
-        contrib[e + 1 + c] = (float)g.gz[c];
+        vals[e + 1 + c] = __float_as_int((float)g.gz[c]);
     }
 }
 
 // One thread per sorted entry; the first entry of each run of equal keys sums
 // the run's contributions in entry order (FP64) and writes the parameter.
 __global__ __launch_bounds__(256) void k_segment_sums(const unsigned long long* __restrict__ keys,
-                                                      const int32_t* __restrict__ vals,
-                                                      const float* __restrict__ contrib, long long n, int id_bits,
+                                                      const int32_t* __restrict__ vals, long long n, int id_bits,
                                                       unsigned long long none, float* grad_refl, float* grad_z)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -239,7 +236,7 @@ __global__ __launch_bounds__(256) void k_segment_sums(const unsigned long long* 
     const unsigned long long key = keys[i];
     if (key == none || (i > 0 && keys[i - 1] == key)) return;
     double sum = 0.0;
-    for (long long j = i; j < n && keys[j] == key; ++j) sum += (double)contrib[vals[j]];
+    for (long long j = i; j < n && keys[j] == key; ++j) sum += (double)__int_as_float(vals[j]);
     const unsigned long long id = key & ((1ull << id_bits) - 1);
     if ((key >> id_bits) == 0) grad_refl[id] = (float)sum;
     else grad_z[id] = (float)sum;
@@ -262,7 +259,7 @@ size_t backward_det_bytes(long long n_pulses, int S)
 {
     const long long n = 4 * n_pulses * (long long)S;
     const size_t a = (size_t)n;
-    return 2 * 8 * a + 2 * 4 * a + 4 * a + 4 * (size_t)radix_sort_hist_words(n) + 4 * 256;
+    return 2 * 8 * a + 2 * 4 * a + 4 * (size_t)radix_sort_hist_words(n) + 4 * 256;
 }
 
 hipError_t launch_backward_det(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
@@ -278,26 +275,28 @@ hipError_t launch_backward_det(const SceneDev& scene, const ScannerDev& sc, cons
     const long long n = 4 * pulses.n * (long long)sc.S;
     const int id_bits = backward_id_bits(scene.n_tri, n_vert);
     const unsigned long long none = (2ull << id_bits) | ((1ull << id_bits) - 1);  // kind 2: after every real key
-    int passes = (id_bits + 2 + 7) / 8;
-    if (passes & 1) ++passes;  // an even count leaves the result in the first arrays
+    const int passes = (id_bits + 2 + 7) / 8;
     unsigned char* w = static_cast<unsigned char*>(ws);
     auto* keys = reinterpret_cast<unsigned long long*>(w);
     auto* keys2 = keys + n;
     auto* vals = reinterpret_cast<int32_t*>(keys2 + n);
     int32_t* vals2 = vals + n;
-    float* contrib = reinterpret_cast<float*>(vals2 + n);
-    unsigned* hist = reinterpret_cast<unsigned*>(contrib + n);
+    unsigned* hist = reinterpret_cast<unsigned*>(vals2 + n);
     const int block = cfg.block_waves * kWave;
     long long waves = (pulses.n + sc.P_w - 1) / sc.P_w;
     unsigned grid = (unsigned)((waves + cfg.block_waves - 1) / cfg.block_waves);
     // every entry is written: each slot (p < n_pulses, k < S) is one lane of one wavefront
     hipLaunchKernelGGL(k_backward_entries, dim3(grid), dim3(block), 0, stream, scene, sc, pulses, sub_tri, sub_stride,
-                       grad_wf, grad_refl != nullptr, grad_z != nullptr, id_bits, none, keys, vals, contrib, pulses.n);
+                       grad_wf, grad_refl != nullptr, grad_z != nullptr, id_bits, none, keys, vals, pulses.n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = radix_sort_pairs(keys, vals, keys2, vals2, hist, n, passes, stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_segment_sums, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, keys, vals, contrib, n,
-                       id_bits, none, grad_refl, grad_z);
+    // the sort alternates between the two pairs of arrays: an odd number of
+    // passes leaves the result in the second
+    const unsigned long long* ks = passes & 1 ? keys2 : keys;
+    const int32_t* vs = passes & 1 ? vals2 : vals;
+    hipLaunchKernelGGL(k_segment_sums, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, ks, vs, n, id_bits,
+                       none, grad_refl, grad_z);
     return hipGetLastError();
 }
 
