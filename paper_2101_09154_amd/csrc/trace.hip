@@ -54,6 +54,17 @@ struct CandRec {
     int leaf;
 };
 
+// A candidate staged for a pulse alone in its wavefront (long candidate lists):
+// its vertices as loaded (w: the original index, the leaf index, and the last
+// component of the subrays' vote below), and the vote's other eight components.
+// The FP64 translation to the pulse origin is redone, with the same operations
+// as for a CandRec, only for candidates some subray may meet.
+struct ChunkRec {
+    float4 P0, P1, P2;
+    float4 e0, e1;  // n0x n0y n0z n1x | n1y n1z n2x n2y (n2z in P2.w)
+};
+static_assert(sizeof(ChunkRec) == sizeof(CandRec), "a chunk slot is a staged slot");
+
 // Per-wavefront LDS, used in turn by the two phases: the staged candidates of the
 // wavefront's pulses (slot = pulse * staged_per_pulse + candidate) while tracing,
 // then the subrays' waveform inputs (offset hi, offset lo, power, unused) per lane,
@@ -404,13 +415,13 @@ __device__ __forceinline__ CullBasis cull_basis(const Basis& Bs, double tan_max)
     return c;
 }
 
-__device__ __forceinline__ bool cone_may_hit(const double* A, const double* B, const double* C, const CullBasis& cb)
+__device__ __forceinline__ bool cone_may_hit(const float* A, const float* B, const float* C, const CullBasis& cb)
 {
     bool px = true, nx = true, py = true, ny = true, bz = true;
-    const double* X[3] = {A, B, C};
+    const float* X[3] = {A, B, C};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const float w0 = (float)X[i][0], w1 = (float)X[i][1], w2 = (float)X[i][2];
+        const float w0 = X[i][0], w1 = X[i][1], w2 = X[i][2];
         const float z = fmaf(w0, cb.n[0], fmaf(w1, cb.n[1], w2 * cb.n[2]));
         const float x = fmaf(w0, cb.u[0], fmaf(w1, cb.u[1], w2 * cb.u[2]));
         const float y = fmaf(w0, cb.v[0], fmaf(w1, cb.v[1], w2 * cb.v[2]));
@@ -440,10 +451,146 @@ __device__ __forceinline__ void stage_rec(CandRec& w, float4 P0, float4 P1, floa
     w.leaf = li;
 }
 
+// The subrays' vote on a candidate, a cheap pre-test of the watertight test's
+// edge functions.  With the vertices a, b, c translated to the pulse origin,
+// the watertight test's U, V, W for a subray of direction d are d.(c x b),
+// d.(a x c) and d.(b x a) divided by one common factor, d's dominant component
+// (the edge functions as scalar triple products, the Pluecker form of the edge
+// test).  Since c x b = c x (b - c), each normal is formed in FP32 from one
+// vertex relative to the origin and one edge of the triangle, n_i = p_i x e_i,
+// so the FP32 products lose no digits to cancellation; its error is below
+// 2^-22 |p_i|1 |e_i|1.  The normals are oriented so that a subray inside the
+// edges has all three d.n_i >= 0: their sum d.N, N = (c - a) x (b - a), keeps
+// one sign over the pulse's subrays when N.w - k |N|1 clears its margin (w the
+// pulse axis, k the tangent of the largest subray angle); otherwise (the
+// triangle's plane passes within the subrays' pyramid) every subray passes.
+// Each normal then gets a margin m_i = 2^-17 |p_i|1 |e_i|1 + 2^-40 |p_i|1 |q_i|1
+// (q_i the edge's other vertex; the FP64 rounding of U, V, W is below 2^-46 of
+// that), folded in as m_i kc w with kc >= 1 / cos(largest subray angle), so that
+// d.(n_i + m_i kc w) >= d.n_i + m_i for every subray.  The vote's FP32
+// evaluation (direction rounded to FP32, three rounded products) errs by less
+// than 2^-21 |p_i|1 |e_i|1.  So a subray the watertight test finds inside the
+// edges always votes yes, and a candidate no subray of the wavefront votes for
+// would change no decision and is skipped.
+// t: the FP32 vertices relative to the origin; e: n0 n1 n2 (9 floats).
+__device__ __forceinline__ void edge_vote_normals(const float4& P0, const float4& P1, const float4& P2,
+                                                  const float* ta, const float* tb, const float* tc,
+                                                  const CullBasis& cb, float* e)
+{
+    float eb[3] = {P1.x - P2.x, P1.y - P2.y, P1.z - P2.z};  // b - c
+    float ec[3] = {P2.x - P0.x, P2.y - P0.y, P2.z - P0.z};  // c - a
+    float ea[3] = {P0.x - P1.x, P0.y - P1.y, P0.z - P1.z};  // a - b
+    // N = (c - a) x (b - a), b - a = -ea
+    const float Nx = fmaf(ec[2], ea[1], -(ec[1] * ea[2]));
+    const float Ny = fmaf(ec[0], ea[2], -(ec[2] * ea[0]));
+    const float Nz = fmaf(ec[1], ea[0], -(ec[0] * ea[1]));
+    const float Nw = fmaf(Nx, cb.n[0], fmaf(Ny, cb.n[1], Nz * cb.n[2]));
+    const float N1 = fabsf(Nx) + fabsf(Ny) + fabsf(Nz);
+    const float la = fabsf(ta[0]) + fabsf(ta[1]) + fabsf(ta[2]);
+    const float lb = fabsf(tb[0]) + fabsf(tb[1]) + fabsf(tb[2]);
+    const float lc = fabsf(tc[0]) + fabsf(tc[1]) + fabsf(tc[2]);
+    const float lea = fabsf(ea[0]) + fabsf(ea[1]) + fabsf(ea[2]);
+    const float leb = fabsf(eb[0]) + fabsf(eb[1]) + fabsf(eb[2]);
+    const float lec = fabsf(ec[0]) + fabsf(ec[1]) + fabsf(ec[2]);
+    // one bound for the three edges: L = max |p|1, E = max |e|1
+    const float L = fmaxf(la, fmaxf(lb, lc)), E = fmaxf(lea, fmaxf(leb, lec));
+    const float mg = L * fmaf(0x1p-17f, E, 0x1p-40f * L);
+    const float marg = fmaf(0x1p-18f * lec, lea, 0x1p-38f * 3.0f * L * L);
+    const float spread = cb.k * N1;
+    // beyond FP32's reach (also NaN): no orientation, a unit margin
+    const bool fits = L * fmaxf(L, E) < 1e30f;
+    float sg = Nw - spread > marg ? 1.0f : (-Nw - spread > marg ? -1.0f : 0.0f);
+    sg = fits ? sg : 0.0f;
+    // kc >= 1 / cos(largest subray angle) with room for the rounded axis
+    const float mk = (fits ? fmaxf(mg, 0x1p-100f) : 1.0f) * (1.001f * sqrtf(fmaf(cb.k, cb.k, 1.0f)));
+    // oriented normals n_i = p_i x (sg e_i) plus the folded margin; with sg = 0
+    // only the margin is left and every subray votes yes
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        eb[j] *= sg;
+        ec[j] *= sg;
+        ea[j] *= sg;
+    }
+    const float* const pv[3] = {tc, ta, tb};
+    const float* const ev[3] = {eb, ec, ea};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float* x = pv[i];
+        const float* y = ev[i];
+        e[3 * i] = fmaf(mk, cb.n[0], fmaf(x[1], y[2], -(x[2] * y[1])));
+        e[3 * i + 1] = fmaf(mk, cb.n[1], fmaf(x[2], y[0], -(x[0] * y[2])));
+        e[3 * i + 2] = fmaf(mk, cb.n[2], fmaf(x[0], y[1], -(x[1] * y[0])));
+    }
+}
+
+// Stage candidate li for the chunk loop: the FP32 vertices relative to the
+// origin (for the cull and the vote; the watertight test redoes the FP64
+// translation), the cull against the pulse's pyramid, the vote's normals.
+// Returns whether the candidate may be met.
+__device__ __forceinline__ bool stage_chunk(ChunkRec& w, float4 P0, float4 P1, float4 P2,
+                                            const double* o, int li, bool b_ok, const CullBasis& cb)
+{
+    const float ta[3] = {(float)((double)P0.x - o[0]), (float)((double)P0.y - o[1]), (float)((double)P0.z - o[2])};
+    const float tb[3] = {(float)((double)P1.x - o[0]), (float)((double)P1.y - o[1]), (float)((double)P1.z - o[2])};
+    const float tc[3] = {(float)((double)P2.x - o[0]), (float)((double)P2.y - o[1]), (float)((double)P2.z - o[2])};
+    float e[9];
+    edge_vote_normals(P0, P1, P2, ta, tb, tc, cb, e);
+    w.P0 = P0;
+    w.P1 = make_float4(P1.x, P1.y, P1.z, __int_as_float(li));
+    w.P2 = make_float4(P2.x, P2.y, P2.z, e[8]);
+    w.e0 = make_float4(e[0], e[1], e[2], e[3]);
+    w.e1 = make_float4(e[4], e[5], e[6], e[7]);
+    return !b_ok || cone_may_hit(ta, tb, tc, cb);
+}
+
+// The chunk's records whose bits are set in `mask` (wave-uniform): the vote
+// first (on the lane's FP32 direction), the watertight test only where some
+// subray votes yes.  Returns the winning slot or -1.
+template <int KZ>
+__device__ __forceinline__ int chunk_loop(const Ray& r, const ChunkRec* __restrict__ rec, unsigned long long mask,
+                                          Hit& h)
+{
+    const float dx = r.d32[0], dy = r.d32[1], dz = r.d32[2];
+    int best = -1;
+    for (; mask; mask &= mask - 1) {
+        const int i = __ffsll((long long)mask) - 1;
+        const float4 e0 = rec[i].e0, e1 = rec[i].e1;
+        const float n2z = rec[i].P2.w;
+        const float E0 = fmaf(e0.x, dx, fmaf(e0.y, dy, e0.z * dz));
+        const float E1 = fmaf(e0.w, dx, fmaf(e1.x, dy, e1.y * dz));
+        const float E2 = fmaf(e1.z, dx, fmaf(e1.w, dy, n2z * dz));
+        if (__ballot(fminf(E0, fminf(E1, E2)) >= 0.0f)) {
+            const ChunkRec& cr = rec[i];
+            double a[3], b[3], c[3];
+            translate(r, cr.P0, a);
+            translate(r, cr.P1, b);
+            translate(r, cr.P2, c);
+            const double t = woop_t<KZ>(r, a, b, c, h.t);
+            const int orig = __float_as_int(cr.P0.w);
+            if (closer(t, orig, h)) {
+                h.t = t;
+                h.orig = orig;
+                best = i;
+            }
+        }
+    }
+    return best;
+}
+
+__device__ __forceinline__ int chunk_loop_any(const Ray& r, const ChunkRec* rec, unsigned long long mask, Hit& h)
+{
+    // the mask is the wavefront's: keep it in scalar registers
+    mask = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(mask >> 32)) << 32) |
+           (unsigned)__builtin_amdgcn_readfirstlane((int)mask);
+    if (r.kz == 2) return chunk_loop<2>(r, rec, mask, h);
+    if (r.kz == 1) return chunk_loop<1>(r, rec, mask, h);
+    return chunk_loop<0>(r, rec, mask, h);
+}
+
 // Trace one lane's subray: fills tri (original index or -1), R, cos, P.
 // staged: the pulse's first min(nc, per) candidates sit in rec[q * per, ...)
 // (per = staged_per_pulse); in a CHUNK launch only the n_kept of them that may
-// meet one of its subrays, in rec[0, n_kept).
+// meet one of its subrays, as ChunkRec slots [0, n_kept).
 template <bool COUNT, bool CHUNK>
 __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerDev& sc, const PulsesDev& pulses,
                                            long long p, int k, int q, const Ray& r, const Basis& B, bool ray_ok,
@@ -462,67 +609,72 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
     h.orig = 0x7fffffff;
     const int nc = pulses.cand ? pulses.cand[p * (kCandMax + 1)] : -1;
     double a[3], b[3], c[3];
-    if (nc >= 0 && staged) {
-        // the cone pass found every triangle any subray of this pulse can hit;
-        // the dominant axis is the same for the whole wavefront almost always, so
-        // the test of the staged ones is specialised for it behind a uniform branch
-        const int per = staged_per_pulse(sc.P_w);
-        const CandRec* mine = rec + q * per;
-        const int ns = nc < per ? nc : per;
-        const int nk = CHUNK ? n_kept : ns;
-        const int kz0 = __builtin_amdgcn_readfirstlane(r.kz);
-        int best;
-        if (__ballot(r.kz != kz0) == 0) {
-            if (kz0 == 2) best = cand_loop<2>(r, mine, nk, h);
-            else if (kz0 == 1) best = cand_loop<1>(r, mine, nk, h);
-            else best = cand_loop<0>(r, mine, nk, h);
-        } else {
-            if (r.kz == 2) best = cand_loop<2>(r, mine, nk, h);
-            else if (r.kz == 1) best = cand_loop<1>(r, mine, nk, h);
-            else best = cand_loop<0>(r, mine, nk, h);
-        }
-        const int* cand = cand_ids(pulses.cand + p * (kCandMax + 1), nc, pulses.cand_long);
-        if (CHUNK && sc.P_w == 1 && nc > ns) {
-            // one pulse per wavefront: the rest are staged in chunks of 64 as
-            // well, each triangle loaded and translated once for the pulse by the
-            // subray lanes (all of them take this branch together, k = 0..S-1)
-            int best_leaf = best >= 0 ? mine[best].leaf : -1;
+    if (CHUNK && nc >= 0 && staged) {
+        // one pulse per wavefront: its first min(nc, 64) candidates were staged
+        // by the whole wavefront, the n_kept of them that may meet a subray
+        // packed in slots [0, n_kept); the rest are staged here in chunks of
+        // S floor(64 / S), each triangle loaded by one subray lane (all of them
+        // take this branch together, k = 0..S-1), culled, and marked in a
+        // 64-bit mask
+        ChunkRec* crec = reinterpret_cast<ChunkRec*>(rec);
+        const unsigned long long m0 = n_kept >= kWave ? ~0ull : ((1ull << n_kept) - 1ull);
+        const int b0 = chunk_loop_any(r, crec, m0, h);
+        int best_leaf = b0 >= 0 ? __float_as_int(crec[b0].P1.w) : -1;
+        if (nc > kWave) {
+            const int* cand = cand_ids(pulses.cand + p * (kCandMax + 1), nc, pulses.cand_long);
             const double* o = pulses.origins + 3 * p;
             const CullBasis cb = cull_basis(B, sc.tan_max);
-            for (int base = ns; base < nc; base += kWave) {
-                const int m = nc - base < kWave ? nc - base : kWave;
+            const int step = sc.S * (kWave / sc.S);
+            for (int base = kWave; base < nc; base += step) {
+                const int m = nc - base < step ? nc - base : step;
                 wave_sync();  // the previous chunk has been read
-                // record j of the chunk in slot j; bit j of `keep` set when it
-                // may meet a subray (lane k stages j = k, k + S, ...)
                 unsigned long long keep = 0;
                 for (int j0 = 0; j0 < m; j0 += sc.S) {
                     const int j = j0 + k;
                     bool kp = false;
                     if (j < m) {
                         const int li = min(max(cand[base + j], 0), scene.n_tri - 1);
-                        CandRec& w = rec[j];
-                        stage_rec(w, scene.tris[3 * li], scene.tris[3 * li + 1], scene.tris[3 * li + 2], o, li);
-                        kp = cone_may_hit(w.a, w.b, w.c, cb);
+                        ChunkRec w;
+                        kp = stage_chunk(w, scene.tris[3 * li], scene.tris[3 * li + 1], scene.tris[3 * li + 2], o, li,
+                                         true, cb);
+                        if (kp) crec[j] = w;
                     }
                     keep |= __ballot(kp) << j0;
                 }
                 wave_sync();
-                int b2;
-                if (r.kz == 2) b2 = cand_loop_mask<2>(r, rec, keep, h);
-                else if (r.kz == 1) b2 = cand_loop_mask<1>(r, rec, keep, h);
-                else b2 = cand_loop_mask<0>(r, rec, keep, h);
-                if (b2 >= 0) best_leaf = rec[b2].leaf;
+                const int b2 = chunk_loop_any(r, crec, keep, h);
+                if (b2 >= 0) best_leaf = __float_as_int(crec[b2].P1.w);
             }
-            if (COUNT) tests += nc;
-            if (best_leaf < 0) return;
-            // the winner's vertices come again from its leaf record below (the
-            // same FP64 translation as when it was staged)
-            h.leaf = best_leaf;
-        } else {
-            // candidates beyond the staged ones come from the leaf records
-            for (int i = ns; i < nc; ++i) leaf_test(r, scene.tris, cand[i], h);
-            if (COUNT) tests += nc;
         }
+        if (best_leaf < 0) return;
+        // the winner's vertices come again from its leaf record (the same FP64
+        // translation as in the test)
+        h.leaf = best_leaf;
+        translate(r, scene.tris[3 * h.leaf], a);
+        translate(r, scene.tris[3 * h.leaf + 1], b);
+        translate(r, scene.tris[3 * h.leaf + 2], c);
+    } else if (nc >= 0 && staged) {
+        // the cone pass found every triangle any subray of this pulse can hit;
+        // the dominant axis is the same for the whole wavefront almost always, so
+        // the test of the staged ones is specialised for it behind a uniform branch
+        const int per = staged_per_pulse(sc.P_w);
+        const CandRec* mine = rec + q * per;
+        const int ns = nc < per ? nc : per;
+        const int kz0 = __builtin_amdgcn_readfirstlane(r.kz);
+        int best;
+        if (__ballot(r.kz != kz0) == 0) {
+            if (kz0 == 2) best = cand_loop<2>(r, mine, ns, h);
+            else if (kz0 == 1) best = cand_loop<1>(r, mine, ns, h);
+            else best = cand_loop<0>(r, mine, ns, h);
+        } else {
+            if (r.kz == 2) best = cand_loop<2>(r, mine, ns, h);
+            else if (r.kz == 1) best = cand_loop<1>(r, mine, ns, h);
+            else best = cand_loop<0>(r, mine, ns, h);
+        }
+        // candidates beyond the staged ones come from the leaf records
+        const int* cand = cand_ids(pulses.cand + p * (kCandMax + 1), nc, pulses.cand_long);
+        for (int i = ns; i < nc; ++i) leaf_test(r, scene.tris, cand[i], h);
+        if (COUNT) tests += nc;
         if (h.leaf >= 0) {
             translate(r, scene.tris[3 * h.leaf], a);
             translate(r, scene.tris[3 * h.leaf + 1], b);
@@ -1056,14 +1208,13 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
     int n_kept = 0;
     if (staged) {
         if (CHUNK) {
-            CandRec w;
+            ChunkRec w;
             bool keep = false;
-            if (sc16 < nq) {
-                stage_rec(w, P0, P1, P2, pulses.origins + 3 * (first + sq), li);
-                keep = !b_ok || cone_may_hit(w.a, w.b, w.c, cull_basis(B, sc.tan_max));
-            }
+            if (sc16 < nq)
+                keep = stage_chunk(w, P0, P1, P2, pulses.origins + 3 * (first + sq), li, b_ok,
+                                   cull_basis(B, sc.tan_max));
             const unsigned long long kept = __ballot(keep);
-            if (keep) rec[lanes_below(kept)] = w;
+            if (keep) reinterpret_cast<ChunkRec*>(wl)[lanes_below(kept)] = w;
             n_kept = __popcll(kept);
         } else if (sc16 < nq) {
             stage_rec(rec[lane], P0, P1, P2, pulses.origins + 3 * (first + sq), li);
