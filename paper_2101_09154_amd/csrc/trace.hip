@@ -804,24 +804,28 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
     float wf[MAXCH];
 #pragma unroll
     for (int c = 0; c < MAXCH; ++c) wf[c] = 0.0f;
+    // a chunk's bins lie within [-33, 32] bins of its centre (one bin of slack),
+    // so an echo whose offset from the centre is outside [-33 bin - cut_hi,
+    // 32 bin + cut_lo] adds less than the cut's 1e-9 of its peak to every bin
+    // of the chunk (the same bound that delimits the window) and is left out
+    const float reach_lo = -33.0f * sc.bin_ns - sc.cut_hi, reach_hi = 32.0f * sc.bin_ns + sc.cut_lo;
     if (COMPUTE) {
 #pragma unroll
         for (int c = 0; c < MAXCH; ++c) {
             if (c >= nch) continue;
-            if (sub_lane) {
-                // a missed subray carries power 0 and offset 0: it adds exactly 0
-                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (mine) {
-                    echo_offset(sc, rel, jb + c * kWave + 32, v.x, v.y);
-                    v.z = my_pw;
-                }
-                sub[lane] = v;
-            }
+            // the echoes that reach the chunk, packed in subray order (missed
+            // subrays add nothing and are left out too)
+            float hi = 0.0f, lo = 0.0f;
+            if (mine) echo_offset(sc, rel, jb + c * kWave + 32, hi, lo);
+            const bool reach = mine && hi >= reach_lo && hi <= reach_hi;
+            const unsigned long long rm = __ballot(reach);
+            if (reach) sub[lanes_below(rm)] = make_float4(hi, 0.0f, my_pw, 0.0f);
+            const int nr = __popcll(rm);
             wave_sync();
             float acc = 0.0f;
 #pragma unroll 4
-            for (int kk = 0; kk < S; ++kk) {
-                const float4 u = sub[k0 + kk];
+            for (int kk = 0; kk < nr; ++kk) {
+                const float4 u = sub[kk];
                 acc = fmaf(u.z, pulse_shape<SHAPE>(sc, x - u.x), acc);
             }
             wf[c] = jb + c * kWave + lane < nb ? acc : 0.0f;
