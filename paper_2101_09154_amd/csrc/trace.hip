@@ -61,7 +61,7 @@ struct CandRec {
 // as for a CandRec, only for candidates some subray may meet.
 struct ChunkRec {
     float4 P0, P1, P2;
-    float4 e0, e1;  // n0x n0y n0z n1x | n1y n1z n2x n2y (n2z in P2.w)
+    float4 e0, e1;  // A0 B0 C0 A1 | B1 C1 A2 B2 (C2 in P2.w)
 };
 static_assert(sizeof(ChunkRec) == sizeof(CandRec), "a chunk slot is a staged slot");
 
@@ -397,6 +397,8 @@ __device__ __forceinline__ void shade(const Ray& r, const double* a, const doubl
 struct CullBasis {
     float n[3], u[3], v[3];
     float k;
+    float kc;  // >= 1 / cos(largest subray angle), with room for the FP32 axis
+    float k2;  // k^2 (1 + 2^-18)
 };
 
 __device__ __forceinline__ CullBasis cull_basis(const Basis& Bs, double tan_max)
@@ -411,7 +413,10 @@ __device__ __forceinline__ CullBasis cull_basis(const Basis& Bs, double tan_max)
         c.u[i] = (float)u[i];
         c.v[i] = (float)v[i];
     }
-    c.k = (float)(tan_max * (1.0 + 1e-5) + 1e-12);
+    const double k = tan_max * (1.0 + 1e-5) + 1e-12;
+    c.k = (float)k;
+    c.kc = (float)(1.001 * sqrt(1.0 + k * k));
+    c.k2 = (float)(k * k * (1.0 + 0x1p-18));
     return c;
 }
 
@@ -467,15 +472,24 @@ __device__ __forceinline__ void stage_rec(CandRec& w, float4 P0, float4 P1, floa
 // Each normal then gets a margin m_i = 2^-17 |p_i|1 |e_i|1 + 2^-40 |p_i|1 |q_i|1
 // (q_i the edge's other vertex; the FP64 rounding of U, V, W is below 2^-46 of
 // that), folded in as m_i kc w with kc >= 1 / cos(largest subray angle), so that
-// d.(n_i + m_i kc w) >= d.n_i + m_i for every subray.  The vote's FP32
-// evaluation (direction rounded to FP32, three rounded products) errs by less
-// than 2^-21 |p_i|1 |e_i|1.  So a subray the watertight test finds inside the
-// edges always votes yes, and a candidate no subray of the wavefront votes for
-// would change no decision and is skipped.
-// t: the FP32 vertices relative to the origin; e: n0 n1 n2 (9 floats).
-__device__ __forceinline__ void edge_vote_normals(const float4& P0, const float4& P1, const float4& P2,
-                                                  const float* ta, const float* tb, const float* tc,
-                                                  const CullBasis& cb, float* e)
+// d.(n_i + m_i kc w) >= d.n_i + m_i for every subray.  Each margin-carrying
+// normal is then taken to the pulse's basis (u, v, w): with d / (d.w) =
+// x u + y v + w, (x, y) fixed per subray and x^2 + y^2 <= k^2, the vote of a
+// subray on edge i is A_i x + B_i y + C_i >= 0, six fused multiply-adds for the
+// three edges; its FP32 evaluation (basis, coefficients and x, y rounded to
+// FP32) errs by less than 2^-20 |n_i|1, far inside the margin.  So a subray
+// the watertight test finds inside the edges always votes yes, and a
+// candidate no subray of the wavefront votes for would change no decision and
+// is skipped.  A candidate for which some edge has C_i + k sqrt(A_i^2 + B_i^2)
+// below -2^-20 (|A_i| + |B_i| + |C_i|) has every subray of the pulse outside
+// that edge (the maximum of the vote over the disk of radius k), so no subray
+// can vote for it and it is dropped at staging (the projected triangle and the
+// beam's disk are separated along that edge's normal).
+// t: the FP32 vertices relative to the origin; e: A0 B0 C0 A1 B1 C1 A2 B2 C2.
+// Returns false for a candidate so dropped.
+__device__ __forceinline__ bool edge_vote_coeffs(const float4& P0, const float4& P1, const float4& P2,
+                                                 const float* ta, const float* tb, const float* tc,
+                                                 const CullBasis& cb, float* e)
 {
     float eb[3] = {P1.x - P2.x, P1.y - P2.y, P1.z - P2.z};  // b - c
     float ec[3] = {P2.x - P0.x, P2.y - P0.y, P2.z - P0.z};  // c - a
@@ -501,8 +515,7 @@ __device__ __forceinline__ void edge_vote_normals(const float4& P0, const float4
     const bool fits = L * fmaxf(L, E) < 1e30f;
     float sg = Nw - spread > marg ? 1.0f : (-Nw - spread > marg ? -1.0f : 0.0f);
     sg = fits ? sg : 0.0f;
-    // kc >= 1 / cos(largest subray angle) with room for the rounded axis
-    const float mk = (fits ? fmaxf(mg, 0x1p-100f) : 1.0f) * (1.001f * sqrtf(fmaf(cb.k, cb.k, 1.0f)));
+    const float mk = (fits ? fmaxf(mg, 0x1p-100f) : 1.0f) * cb.kc;
     // oriented normals n_i = p_i x (sg e_i) plus the folded margin; with sg = 0
     // only the margin is left and every subray votes yes
 #pragma unroll
@@ -513,20 +526,33 @@ __device__ __forceinline__ void edge_vote_normals(const float4& P0, const float4
     }
     const float* const pv[3] = {tc, ta, tb};
     const float* const ev[3] = {eb, ec, ea};
+    bool may = true;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const float* x = pv[i];
         const float* y = ev[i];
-        e[3 * i] = fmaf(mk, cb.n[0], fmaf(x[1], y[2], -(x[2] * y[1])));
-        e[3 * i + 1] = fmaf(mk, cb.n[1], fmaf(x[2], y[0], -(x[0] * y[2])));
-        e[3 * i + 2] = fmaf(mk, cb.n[2], fmaf(x[0], y[1], -(x[1] * y[0])));
+        const float n0 = fmaf(mk, cb.n[0], fmaf(x[1], y[2], -(x[2] * y[1])));
+        const float n1 = fmaf(mk, cb.n[1], fmaf(x[2], y[0], -(x[0] * y[2])));
+        const float n2 = fmaf(mk, cb.n[2], fmaf(x[0], y[1], -(x[1] * y[0])));
+        const float A = fmaf(n0, cb.u[0], fmaf(n1, cb.u[1], n2 * cb.u[2]));
+        const float B = fmaf(n0, cb.v[0], fmaf(n1, cb.v[1], n2 * cb.v[2]));
+        const float C = fmaf(n0, cb.n[0], fmaf(n1, cb.n[1], n2 * cb.n[2]));
+        e[3 * i] = A;
+        e[3 * i + 1] = B;
+        e[3 * i + 2] = C;
+        // C + k sqrt(A^2 + B^2) < -eps  <=>  t = -C - eps > 0 and t^2 > k^2 (A^2 + B^2),
+        // squared (k2 carries the squares' rounding): a product that flushes
+        // to zero can only keep a candidate, never drop one wrongly
+        const float t = fmaf(-0x1p-20f, fabsf(A) + fabsf(B) + fabsf(C), -C);
+        may = may && !(t > 0.0f && t * t > cb.k2 * fmaf(A, A, B * B));
     }
+    return may;
 }
 
 // Stage candidate li for the chunk loop: the FP32 vertices relative to the
-// origin (for the cull and the vote; the watertight test redoes the FP64
-// translation), the cull against the pulse's pyramid, the vote's normals.
-// Returns whether the candidate may be met.
+// origin (for the culls and the vote; the watertight test redoes the FP64
+// translation), the cull against the pulse's pyramid and the beam's disk, the
+// vote's coefficients.  Returns whether the candidate may be met.
 __device__ __forceinline__ bool stage_chunk(ChunkRec& w, float4 P0, float4 P1, float4 P2,
                                             const double* o, int li, bool b_ok, const CullBasis& cb)
 {
@@ -534,31 +560,31 @@ __device__ __forceinline__ bool stage_chunk(ChunkRec& w, float4 P0, float4 P1, f
     const float tb[3] = {(float)((double)P1.x - o[0]), (float)((double)P1.y - o[1]), (float)((double)P1.z - o[2])};
     const float tc[3] = {(float)((double)P2.x - o[0]), (float)((double)P2.y - o[1]), (float)((double)P2.z - o[2])};
     float e[9];
-    edge_vote_normals(P0, P1, P2, ta, tb, tc, cb, e);
+    const bool may = edge_vote_coeffs(P0, P1, P2, ta, tb, tc, cb, e);
     w.P0 = P0;
     w.P1 = make_float4(P1.x, P1.y, P1.z, __int_as_float(li));
     w.P2 = make_float4(P2.x, P2.y, P2.z, e[8]);
     w.e0 = make_float4(e[0], e[1], e[2], e[3]);
     w.e1 = make_float4(e[4], e[5], e[6], e[7]);
-    return !b_ok || cone_may_hit(ta, tb, tc, cb);
+    return !b_ok || (may && cone_may_hit(ta, tb, tc, cb));
 }
 
 // The chunk's records whose bits are set in `mask` (wave-uniform): the vote
-// first (on the lane's FP32 direction), the watertight test only where some
-// subray votes yes.  Returns the winning slot or -1.
+// first ((x, y): the lane's subray in the pulse's basis, d / (d.w) = x u + y v
+// + w), the watertight test only where some subray votes yes.  Returns the
+// winning slot or -1.
 template <int KZ>
-__device__ __forceinline__ int chunk_loop(const Ray& r, const ChunkRec* __restrict__ rec, unsigned long long mask,
-                                          Hit& h)
+__device__ __forceinline__ int chunk_loop(const Ray& r, float x, float y, const ChunkRec* __restrict__ rec,
+                                          unsigned long long mask, Hit& h)
 {
-    const float dx = r.d32[0], dy = r.d32[1], dz = r.d32[2];
     int best = -1;
     for (; mask; mask &= mask - 1) {
         const int i = __ffsll((long long)mask) - 1;
         const float4 e0 = rec[i].e0, e1 = rec[i].e1;
-        const float n2z = rec[i].P2.w;
-        const float E0 = fmaf(e0.x, dx, fmaf(e0.y, dy, e0.z * dz));
-        const float E1 = fmaf(e0.w, dx, fmaf(e1.x, dy, e1.y * dz));
-        const float E2 = fmaf(e1.z, dx, fmaf(e1.w, dy, n2z * dz));
+        const float c2 = rec[i].P2.w;
+        const float E0 = fmaf(e0.x, x, fmaf(e0.y, y, e0.z));
+        const float E1 = fmaf(e0.w, x, fmaf(e1.x, y, e1.y));
+        const float E2 = fmaf(e1.z, x, fmaf(e1.w, y, c2));
         if (__ballot(fminf(E0, fminf(E1, E2)) >= 0.0f)) {
             const ChunkRec& cr = rec[i];
             double a[3], b[3], c[3];
@@ -577,14 +603,15 @@ __device__ __forceinline__ int chunk_loop(const Ray& r, const ChunkRec* __restri
     return best;
 }
 
-__device__ __forceinline__ int chunk_loop_any(const Ray& r, const ChunkRec* rec, unsigned long long mask, Hit& h)
+__device__ __forceinline__ int chunk_loop_any(const Ray& r, float x, float y, const ChunkRec* rec,
+                                              unsigned long long mask, Hit& h)
 {
     // the mask is the wavefront's: keep it in scalar registers
     mask = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(mask >> 32)) << 32) |
            (unsigned)__builtin_amdgcn_readfirstlane((int)mask);
-    if (r.kz == 2) return chunk_loop<2>(r, rec, mask, h);
-    if (r.kz == 1) return chunk_loop<1>(r, rec, mask, h);
-    return chunk_loop<0>(r, rec, mask, h);
+    if (r.kz == 2) return chunk_loop<2>(r, x, y, rec, mask, h);
+    if (r.kz == 1) return chunk_loop<1>(r, x, y, rec, mask, h);
+    return chunk_loop<0>(r, x, y, rec, mask, h);
 }
 
 // Trace one lane's subray: fills tri (original index or -1), R, cos, P.
@@ -617,8 +644,12 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
         // take this branch together, k = 0..S-1), culled, and marked in a
         // 64-bit mask
         ChunkRec* crec = reinterpret_cast<ChunkRec*>(rec);
+        // the subray in the pulse's basis (from the subray table: d = cos a w +
+        // sin a (cos phi u + sin phi v))
+        const double ta = pat[1] / pat[0];
+        const float x = (float)(ta * pat[2]), y = (float)(ta * pat[3]);
         const unsigned long long m0 = n_kept >= kWave ? ~0ull : ((1ull << n_kept) - 1ull);
-        const int b0 = chunk_loop_any(r, crec, m0, h);
+        const int b0 = chunk_loop_any(r, x, y, crec, m0, h);
         int best_leaf = b0 >= 0 ? __float_as_int(crec[b0].P1.w) : -1;
         if (nc > kWave) {
             const int* cand = cand_ids(pulses.cand + p * (kCandMax + 1), nc, pulses.cand_long);
@@ -642,7 +673,7 @@ __device__ __forceinline__ void trace_lane(const SceneDev& scene, const ScannerD
                     keep |= __ballot(kp) << j0;
                 }
                 wave_sync();
-                const int b2 = chunk_loop_any(r, crec, keep, h);
+                const int b2 = chunk_loop_any(r, x, y, crec, keep, h);
                 if (b2 >= 0) best_leaf = __float_as_int(crec[b2].P1.w);
             }
         }
