@@ -788,7 +788,10 @@ __device__ __forceinline__ float echo_value(const ScannerDev& sc, float x, float
 // so it is computed as nch chunks of 64 bins starting at jb = jl (lane l of chunk
 // c owns bin jb + 64 c + l); a loaded one as the aligned chunks of the whole row.
 // Bins outside the chunks are zero.
-template <int MAXCH, bool COMPUTE, bool RET, int SHAPE>
+// PACK: each chunk sums only the echoes that reach it (one pulse per wavefront,
+// where echoes spread over several chunks; elsewhere the plain loop over all
+// subrays is kept, which measured faster there).
+template <int MAXCH, bool COMPUTE, bool RET, int SHAPE, bool PACK = false>
 __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
                                             long long p, int k0, float4* sub, bool attrib, double my_tau,
                                             float my_pw, int my_tri)
@@ -844,20 +847,38 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
 #pragma unroll
         for (int c = 0; c < MAXCH; ++c) {
             if (c >= nch) continue;
-            // the echoes that reach the chunk, packed in subray order (missed
-            // subrays add nothing and are left out too)
-            float hi = 0.0f, lo = 0.0f;
-            if (mine) echo_offset(sc, rel, jb + c * kWave + 32, hi, lo);
-            const bool reach = mine && hi >= reach_lo && hi <= reach_hi;
-            const unsigned long long rm = __ballot(reach);
-            if (reach) sub[lanes_below(rm)] = make_float4(hi, 0.0f, my_pw, 0.0f);
-            const int nr = __popcll(rm);
-            wave_sync();
             float acc = 0.0f;
+            if (PACK) {
+                // the echoes that reach the chunk, packed in subray order (missed
+                // subrays add nothing and are left out too)
+                float hi = 0.0f, lo = 0.0f;
+                if (mine) echo_offset(sc, rel, jb + c * kWave + 32, hi, lo);
+                const bool reach = mine && hi >= reach_lo && hi <= reach_hi;
+                const unsigned long long rm = __ballot(reach);
+                if (reach) sub[lanes_below(rm)] = make_float4(hi, 0.0f, my_pw, 0.0f);
+                const int nr = __popcll(rm);
+                wave_sync();
 #pragma unroll 4
-            for (int kk = 0; kk < nr; ++kk) {
-                const float4 u = sub[kk];
-                acc = fmaf(u.z, pulse_shape<SHAPE>(sc, x - u.x), acc);
+                for (int kk = 0; kk < nr; ++kk) {
+                    const float4 u = sub[kk];
+                    acc = fmaf(u.z, pulse_shape<SHAPE>(sc, x - u.x), acc);
+                }
+            } else {
+                if (sub_lane) {
+                    // a missed subray carries power 0 and offset 0: it adds exactly 0
+                    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (mine) {
+                        echo_offset(sc, rel, jb + c * kWave + 32, v.x, v.y);
+                        v.z = my_pw;
+                    }
+                    sub[lane] = v;
+                }
+                wave_sync();
+#pragma unroll 4
+                for (int kk = 0; kk < S; ++kk) {
+                    const float4 u = sub[k0 + kk];
+                    acc = fmaf(u.z, pulse_shape<SHAPE>(sc, x - u.x), acc);
+                }
             }
             wf[c] = jb + c * kWave + lane < nb ? acc : 0.0f;
             wave_sync();
@@ -1310,10 +1331,10 @@ __device__ __forceinline__ void process_wave(const SceneDev& scene, const Scanne
         else pulse_pair<MAXCH, 1>(sc, pulses, out, first, sub, tau, P, tri, active);
     } else if (sc.shape == 0) {
         for (int q = 0; q < npw; ++q)
-            pulse_phase<MAXCH, true, true, 0>(sc, pulses, out, first + q, q * S, sub, true, tau, P, tri);
+            pulse_phase<MAXCH, true, true, 0, CHUNK>(sc, pulses, out, first + q, q * S, sub, true, tau, P, tri);
     } else {
         for (int q = 0; q < npw; ++q)
-            pulse_phase<MAXCH, true, true, 1>(sc, pulses, out, first + q, q * S, sub, true, tau, P, tri);
+            pulse_phase<MAXCH, true, true, 1, CHUNK>(sc, pulses, out, first + q, q * S, sub, true, tau, P, tri);
     }
 }
 
