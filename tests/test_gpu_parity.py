@@ -756,6 +756,38 @@ def test_packet_walk_bitwise_on_trees(ctx, S):
         assert np.array_equal(res[0][k], res[1][k], equal_nan=True), k
 
 
+
+def test_vote_on_shared_edges(ctx):
+    # one pulse per wavefront (61 subrays: the chunked kernel, whose subrays vote
+    # on each candidate before the watertight test) aimed straight down at grid
+    # vertices, edge midpoints and cell centres of the terrain, so the central
+    # subray meets shared vertices and edges with edge functions exactly zero.
+    # The vote and the staging culls may drop no candidate the watertight test
+    # would take: every output equals the per-subray traversal's bit for bit,
+    # and the ids the oracle's.
+    mesh, _, _ = configs.small_tls()
+    scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+    xy = []
+    for i in range(6, 58, 3):
+        for j in range(6, 58, 3):
+            xy += [(i, j), (i + 0.5, j), (i, j + 0.5), (i + 0.5, j + 0.5)]
+    xy = np.array(xy, dtype=np.float64)
+    o = np.concatenate([xy, np.full((xy.shape[0], 1), 40.0)], 1)
+    d = np.tile(np.array([[0.0, 0.0, -1.0]], dtype=np.float32), (xy.shape[0], 1))
+    pulses = synth.Pulses(o, d)
+    sc = configs.scanner(2e-3, 61, n_bins=256)
+    say("vote on shared edges: pulses", pulses.n)
+    res = []
+    for cone in (1, 0):
+        ctx.set_launch_config(cone=cone)
+        res.append(run_gpu(ctx, scene, pulses, sc))
+    ctx.set_launch_config()
+    for k in res[0]:
+        assert np.array_equal(res[0][k], res[1][k], equal_nan=True), k
+    assert np.all(res[0]["subray_tri"][:, 0] >= 0)
+    compare(mesh, pulses, sc, res[0], label="vote on shared edges")
+
+
 # ------------------------------------------------------------------ echo width (Sec. 3.4, optional)
 
 # FP32 fit against the FP64 one on the same waveform: sums over <= 63 bins
