@@ -569,7 +569,11 @@ typedef struct {
     int32_t cone;              /* 1 (default): one cone traversal per pulse collects the triangles
                                   its subrays can hit (same results, less work); 0: every subray
                                   traverses the LBVH on its own                                    */
-    int32_t reserved;
+    int32_t cover_off;         /* 0 (default): the cone traversal culls the triangles behind one
+                                  that covers the whole beam (an FP64 test of leaves on its way);
+                                  1: it does not (shorter walks, longer candidate lists, the same
+                                  results): faster where candidates are cheap to test, as for
+                                  vegetation scanned with one pulse per wavefront               */
 } vls_launch_config;
 
 vls_status vls_set_launch_config(vls_context ctx, const vls_launch_config* cfg);
@@ -604,7 +608,7 @@ typedef struct {
 
 /* Times vls_simulate on this batch for launch configurations (block shape,
  * LDS stack depth, pulses per wavefront, persistent grid size, cone pass on or
- * off) by coordinate descent with HIP events on `stream` (a configuration's
+ * off, its cover tests on or off) by coordinate descent with HIP events on `stream` (a configuration's
  * time: the fastest of three pairs of calls after one warm-up call), keeps the
  * fastest in `ctx`, and appends
  * it to `cache_path` (JSON lines, may be NULL) keyed by scene size, subray

@@ -625,6 +625,7 @@ double max_tan(const Prepared& pr)
     return t;
 }
 
+
 }  // namespace
 
 // ------------------------------------------------------------------ ABI
@@ -699,11 +700,13 @@ vls_status vls_set_launch_config(vls_context ctx, const vls_launch_config* cfg)
     if (cfg->persistent_blocks < 0) return fail(VLS_ERR_INVALID_ARG, "persistent_blocks must be >= 0");
     if (cfg->pack != 0 && cfg->pack != 1) return fail(VLS_ERR_INVALID_ARG, "pack must be 0 or 1");
     if (cfg->cone != 0 && cfg->cone != 1) return fail(VLS_ERR_INVALID_ARG, "cone must be 0 or 1");
+    if (cfg->cover_off != 0 && cfg->cover_off != 1) return fail(VLS_ERR_INVALID_ARG, "cover_off must be 0 or 1");
     ctx->cfg.block_waves = cfg->block_waves;
     ctx->cfg.stack_lds = r;
     ctx->cfg.persistent_blocks = cfg->persistent_blocks;
     ctx->cfg.pack = cfg->pack;
     ctx->cfg.cone = cfg->cone;
+    ctx->cfg.cover_off = cfg->cover_off;
     return VLS_OK;
 }
 
@@ -715,7 +718,7 @@ vls_status vls_get_launch_config(vls_context ctx, vls_launch_config* cfg)
     cfg->persistent_blocks = ctx->cfg.persistent_blocks;
     cfg->pack = ctx->cfg.pack;
     cfg->cone = ctx->cfg.cone;
-    cfg->reserved = 0;
+    cfg->cover_off = ctx->cfg.cover_off;
     return VLS_OK;
 }
 
@@ -1265,7 +1268,7 @@ vls_status vls_trace(vls_context ctx, vls_scene scene, const vls_scanner_desc* s
             unsigned long long* ctr = cone_ws_ctr(ws->cand, n);
             double* basis = cone_ws_basis(ws->cand, n);
             hipError_t e = launch_cone(sd, max_tan(pr), pd, ws->cand, 0, n, ctx->cfg, nullptr, list, ctr, basis,
-                                       (hipStream_t)stream, ws->longw ? kCandFirst : kCandMax);
+                                       (hipStream_t)stream, ws->longw ? kCandFirst : kCandMax, !ctx->cfg.cover_off);
             if (e != hipSuccess) return hip_fail(e, "cone launch");
             if (ws->longw) {
                 pd.basis = basis;
@@ -1700,7 +1703,7 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
         unsigned long long* ctr = cone_ws_ctr(cand, n);
         double* basis = cone_ws_basis(cand, n);
         e = launch_cone(sd, max_tan(pr), pd, cand, 0, n, ctx->cfg, nullptr, list, ctr, basis, s,
-                        longw ? kCandFirst : kCandMax);
+                        longw ? kCandFirst : kCandMax, !ctx->cfg.cover_off);
         if (e != hipSuccess) return hip_fail(e, "cone launch");
         if (longw) {
             // pulses whose row overflowed: a second walk into the long rows
@@ -1861,7 +1864,7 @@ vls_status vls_trace_counts(vls_context ctx, vls_scene scene, const vls_scanner_
         if (e == hipSuccess && ctx->cfg.cone && pulses->n_pulses > 0) {
             double* basis = cone_ws_basis(ws->cand, pulses->n_pulses);
             e = launch_cone(sd, max_tan(pr), pd, ws->cand, 0, pulses->n_pulses, ctx->cfg, dc, nullptr, nullptr, basis,
-                            s);
+                            s, kCandMax, !ctx->cfg.cover_off);
             pd.cand = ws->cand;
             pd.basis = basis;
         }
@@ -2012,6 +2015,7 @@ static bool tune_cache_find(const char* path, const std::string& key, vls_launch
         if ((p = strstr(line, "\"persistent_blocks\": "))) t.persistent_blocks = atoi(p + 21);
         if ((p = strstr(line, "\"pack\": "))) t.pack = atoi(p + 8);
         if ((p = strstr(line, "\"cone\": "))) t.cone = atoi(p + 8);
+        if ((p = strstr(line, "\"cover_off\": "))) t.cover_off = atoi(p + 13);
         c = t;
         found = true;
     }
@@ -2074,6 +2078,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             c.persistent_blocks = cached.persistent_blocks;
             c.pack = cached.pack;
             c.cone = cached.cone;
+            c.cover_off = cached.cover_off;
             double ms = 0.0;
             if ((st = timed(c, ms)) != VLS_OK) { ctx->cfg = entry; return st; }
             best = c;
@@ -2083,7 +2088,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             int tried = 1;
             const bool seg = pulses->n_segments > 0;
             int auto_blocks = seg ? persistent_occupancy_blocks(pr0.n_bins, staged_slots(pr0), scene->vox.n_vox > 0, entry) : 0;
-            for (int dim = 0; dim < 5; ++dim) {
+            for (int dim = 0; dim < 6; ++dim) {
                 std::vector<LaunchCfg> cand;
                 for (int v = 0; v < 4; ++v) {
                     LaunchCfg c = best;
@@ -2092,12 +2097,14 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
                     if (dim == 2) { if (v > 1) break; c.pack = v; }
                     if (dim == 3) { if (!seg || v > 2) break; c.persistent_blocks = v == 0 ? 0 : (v == 1 ? auto_blocks / 2 : 2 * auto_blocks); }
                     if (dim == 4) { if (v > 1) break; c.cone = v; }
+                    if (dim == 5) { if (v > 1 || !c.cone) break; c.cover_off = v; }
                     if (c.stack_lds + kMaxSpill - 1 < scene->stats.max_depth) continue;
                     cand.push_back(c);
                 }
                 for (auto& c : cand) {
                     if (c.block_waves == best.block_waves && c.stack_lds == best.stack_lds && c.pack == best.pack &&
-                        c.persistent_blocks == best.persistent_blocks && c.cone == best.cone)
+                        c.persistent_blocks == best.persistent_blocks && c.cone == best.cone &&
+                        c.cover_off == best.cover_off)
                         continue;
                     double ms = 0.0;
                     if ((st = timed(c, ms)) != VLS_OK) { ctx->cfg = entry; return st; }
@@ -2109,9 +2116,9 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             if (cache_path) {
                 FILE* f = fopen(cache_path, "a");
                 if (f) {
-                    fprintf(f, "{\"key\": \"%s\", \"block_waves\": %d, \"stack_lds\": %d, \"persistent_blocks\": %d, \"pack\": %d, \"cone\": %d, \"ms\": %.6f}\n",
+                    fprintf(f, "{\"key\": \"%s\", \"block_waves\": %d, \"stack_lds\": %d, \"persistent_blocks\": %d, \"pack\": %d, \"cone\": %d, \"cover_off\": %d, \"ms\": %.6f}\n",
                             key.c_str(), best.block_waves, best.stack_lds, best.persistent_blocks, best.pack, best.cone,
-                            best_ms);
+                            best.cover_off, best_ms);
                     fclose(f);
                 }
             }
@@ -2124,6 +2131,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
         result->best.persistent_blocks = best.persistent_blocks;
         result->best.pack = best.pack;
         result->best.cone = best.cone;
+        result->best.cover_off = best.cover_off;
         result->best_ms = best_ms;
         return VLS_OK;
     } catch (const std::exception& e) {
@@ -2143,7 +2151,7 @@ vls_status vls_cone_candidates(vls_context ctx, vls_scene scene, const vls_scann
         if (!aligned(candidates, 4)) return fail(VLS_ERR_INVALID_ARG, "misaligned candidates");
         hipStream_t s = (hipStream_t)stream;
         hipError_t e = launch_cone(scene_dev(scene), max_tan(pr), pulses_dev(pulses), candidates, 0, pulses->n_pulses,
-                                   ctx->cfg, nullptr, nullptr, nullptr, nullptr, s);
+                                   ctx->cfg, nullptr, nullptr, nullptr, nullptr, s, kCandMax, !ctx->cfg.cover_off);
         if (e != hipSuccess) return hip_fail(e, "cone launch");
         if (pulses->n_pulses > 0) {
             e = launch_leaf_to_orig(scene->b.leaf_tri, candidates, pulses->n_pulses, s);

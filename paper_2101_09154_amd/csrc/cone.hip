@@ -288,7 +288,8 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
     return n;
 }
 
-template <bool COUNT>
+// COVER: run the cover tests (see cone_walk).
+template <bool COUNT, bool COVER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_cone(SceneDev scene, double tana, PulsesDev pulses, int* __restrict__ cand,
                                               long long first, long long count, int ring_mask,
                                               unsigned long long* counts, int* ovf_list, unsigned long long* ovf_ctr,
@@ -317,9 +318,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     int2* my = reinterpret_cast<int2*>(smem) + threadIdx.x;
     // the cheaper slab test serves every wavefront without a mixed-sign axis
     if (__ballot(ok && c.mixed) == 0) {
-        if (ok) n = cone_walk<COUNT, false>(scene, c, out, 1, cap, my, ring_mask, visits);
+        if (ok) n = cone_walk<COUNT, false, COVER>(scene, c, out, 1, cap, my, ring_mask, visits);
     } else {
-        if (ok) n = cone_walk<COUNT, true>(scene, c, out, 1, cap, my, ring_mask, visits);
+        if (ok) n = cone_walk<COUNT, true, COVER>(scene, c, out, 1, cap, my, ring_mask, visits);
     }
     if (active) out[0] = n;
     if (ovf_list) {
@@ -446,7 +447,7 @@ hipError_t launch_cone_long(const SceneDev& scene, double tan_max, const PulsesD
 
 hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
                        long long count, const LaunchCfg& cfg, unsigned long long* counts, int* ovf_list,
-                       unsigned long long* ovf_ctr, double* basis_out, hipStream_t stream, int cap)
+                       unsigned long long* ovf_ctr, double* basis_out, hipStream_t stream, int cap, bool cover)
 {
     if (ovf_list) {
         hipError_t e = launch_fill_u64(ovf_ctr, 2, 0ull, stream);
@@ -459,12 +460,17 @@ hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& p
     // entries, and 16 entries per lane still fit 4 wavefronts per SIMD
     size_t lds = sizeof(int2) * (size_t)kConeRing * block;
     int mask = kConeRing - 1;
-    if (counts)
-        hipLaunchKernelGGL(k_cone<true>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, first,
-                           count, mask, counts, ovf_list, ovf_ctr, basis_out, cap);
-    else
-        hipLaunchKernelGGL(k_cone<false>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, first,
-                           count, mask, counts, ovf_list, ovf_ctr, basis_out, cap);
+#define VLS_CONE_LAUNCH(COUNT, COVER)                                                                          \
+    hipLaunchKernelGGL((k_cone<COUNT, COVER>), dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, \
+                       first, count, mask, counts, ovf_list, ovf_ctr, basis_out, cap)
+    if (counts) {
+        if (cover) VLS_CONE_LAUNCH(true, true);
+        else VLS_CONE_LAUNCH(true, false);
+    } else {
+        if (cover) VLS_CONE_LAUNCH(false, true);
+        else VLS_CONE_LAUNCH(false, false);
+    }
+#undef VLS_CONE_LAUNCH
     return hipGetLastError();
 }
 

@@ -790,7 +790,8 @@ __device__ __forceinline__ float echo_value(const ScannerDev& sc, float x, float
 // Bins outside the chunks are zero.
 // PACK: each chunk sums only the echoes that reach it (one pulse per wavefront,
 // where echoes spread over several chunks; elsewhere the plain loop over all
-// subrays is kept, which measured faster there).
+// subrays is kept, which measured faster there).  The echoes left out add
+// exactly zero to every bin of the chunk, so both loops give the same bits.
 template <int MAXCH, bool COMPUTE, bool RET, int SHAPE, bool PACK = false>
 __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDev& pulses, const OutDev& out,
                                             long long p, int k0, float4* sub, bool attrib, double my_tau,
@@ -838,11 +839,17 @@ __device__ __forceinline__ void pulse_phase(const ScannerDev& sc, const PulsesDe
     float wf[MAXCH];
 #pragma unroll
     for (int c = 0; c < MAXCH; ++c) wf[c] = 0.0f;
-    // a chunk's bins lie within [-33, 32] bins of its centre (one bin of slack),
-    // so an echo whose offset from the centre is outside [-33 bin - cut_hi,
-    // 32 bin + cut_lo] adds less than the cut's 1e-9 of its peak to every bin
-    // of the chunk (the same bound that delimits the window) and is left out
-    const float reach_lo = -33.0f * sc.bin_ns - sc.cut_hi, reach_hi = 32.0f * sc.bin_ns + sc.cut_lo;
+    // an echo reaches a chunk if its pulse is non-zero at one of the chunk's
+    // bins, whose offsets from the centre lie within [-33, 32] bins (one bin of
+    // slack).  pulse_shape is exactly zero where its exp2 argument is below
+    // -160 (the result is far below the smallest FP32 subnormal): the Gaussian
+    // beyond |s| = sqrt(160 / -neg_k), Eq. 3 at s <= 0 and beyond s = 160 /
+    // (-neg_k inv_tau); widened by 1e-3 against the FP32 rounding of s and of
+    // the exponent, an echo outside [-33 bin - z_pos, 32 bin + z_neg] adds
+    // exactly zero to each of the chunk's bins
+    const float z_pos = 1.001f * (SHAPE == 0 ? sqrtf(-160.0f / sc.neg_k) : -160.0f / (sc.neg_k * sc.inv_tau));
+    const float z_neg = SHAPE == 0 ? z_pos : 0.0f;
+    const float reach_lo = -33.0f * sc.bin_ns - z_pos, reach_hi = 32.0f * sc.bin_ns + z_neg;
     if (COMPUTE) {
 #pragma unroll
         for (int c = 0; c < MAXCH; ++c) {

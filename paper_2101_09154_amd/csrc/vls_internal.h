@@ -243,6 +243,7 @@ struct LaunchCfg {
     int persistent_blocks = 0;
     int pack = 0;  // 0: floor(64/S) pulses per wavefront; 1: one pulse per wavefront
     int cone = 1;  // 1: one cone traversal per pulse collects candidate triangles for its subrays
+    int cover_off = 0;  // 1: the cone traversal runs no cover tests
 };
 
 // ---- host-side launchers (defined in the .hip files) ----
@@ -309,7 +310,7 @@ hipError_t launch_backward_det(const SceneDev& scene, const ScannerDev& sc, cons
 hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& pulses, int* cand, long long first,
                        long long count, const LaunchCfg& cfg, unsigned long long* counts, int* ovf_list,
                        unsigned long long* ovf_ctr, double* basis_out, hipStream_t stream,
-                       int cap = kCandMax);
+                       int cap = kCandMax, bool cover = true);
 // Second cone pass over the pulses that overflowed their rows (list, ctr from
 // launch_cone): each gets a long row while rows last (its candidate row then
 // holds the count and the long row's index), else it goes to list2 / ctr2 for

@@ -504,9 +504,12 @@ def test_autotune_and_cache(ctx, tmp_path):
     ctx.set_launch_config()
     r2 = ctx.autotune(scene, scs, o, d, out, cache_path=cache, **kw)
     assert r2["from_cache"] and r2["best"] == r1["best"]
-    # packing one pulse per wavefront changes nothing but speed
+    # packing one pulse per wavefront, or a cone pass without cover tests,
+    # changes nothing but speed
     ctx.set_launch_config(pack=1)
     _assert_batch_equal(eager, to_np(ctx.simulate(scene, scs, o, d, **kw)), batch, seg_sc, scs, "pack")
+    ctx.set_launch_config(cover_off=1)
+    _assert_batch_equal(eager, to_np(ctx.simulate(scene, scs, o, d, **kw)), batch, seg_sc, scs, "cover_off")
     ctx.set_launch_config()
 
 
@@ -718,15 +721,16 @@ def test_cone_pass_bitwise_on_buildings(ctx):
         o = _dev(pulses.origins)
         d = _dev(pulses.directions)
         res = []
-        for cone in (1, 0):
-            ctx.set_launch_config(cone=cone)
-            say("cone", cone, pulses.n)
+        for cfg in (dict(cone=1), dict(cone=0), dict(cone=1, cover_off=1)):
+            ctx.set_launch_config(**cfg)
+            say("cone", cfg, pulses.n)
             res.append(to_np(ctx.simulate(scene, scn, o, d, **kw)))
-        for k in res[0]:
-            a, b = res[0][k], res[1][k]
-            if k.startswith("subray") and kw:
-                continue
-            assert np.array_equal(a, b, equal_nan=True), k
+        for r in res[1:]:
+            for k in res[0]:
+                a, b = res[0][k], r[k]
+                if k.startswith("subray") and kw:
+                    continue
+                assert np.array_equal(a, b, equal_nan=True), k
     ctx.set_launch_config()
 
 
@@ -778,12 +782,13 @@ def test_vote_on_shared_edges(ctx):
     sc = configs.scanner(2e-3, 61, n_bins=256)
     say("vote on shared edges: pulses", pulses.n)
     res = []
-    for cone in (1, 0):
-        ctx.set_launch_config(cone=cone)
+    for cfg in (dict(cone=1), dict(cone=0), dict(cone=1, cover_off=1)):
+        ctx.set_launch_config(**cfg)
         res.append(run_gpu(ctx, scene, pulses, sc))
     ctx.set_launch_config()
-    for k in res[0]:
-        assert np.array_equal(res[0][k], res[1][k], equal_nan=True), k
+    for r in res[1:]:
+        for k in res[0]:
+            assert np.array_equal(res[0][k], r[k], equal_nan=True), k
     assert np.all(res[0]["subray_tri"][:, 0] >= 0)
     compare(mesh, pulses, sc, res[0], label="vote on shared edges")
 
