@@ -234,7 +234,8 @@ def time_ms(fn, steps, warmup, stream):
 
 def bench_batched(ctx, scene, mesh, steps, tune_cache=None):
     """256 terrestrial positions on the same scene: per-segment launches vs one
-    persistent launch vs a replayed HIP graph of it (autotuned)."""
+    persistent launch vs one launch per scanner over its segments (grouped) vs a
+    replayed HIP graph of the autotuned choice."""
     import torch
     from synth import configs
     import paper_2101_09154_amd as vp
@@ -261,7 +262,11 @@ def bench_batched(ctx, scene, mesh, steps, tune_cache=None):
     kw = dict(segment_offsets=off, segment_scanner=seg)
     cfg0 = ctx.launch_config()
     t_seg = time_ms(per_segment, max(1, steps // 4), 1, stream)
+    ctx.set_launch_config(**dict(cfg0, grouped=0))
     t_pers = time_ms(lambda: ctx.simulate(scene, scs, o, d, out=out, **kw), steps, 1, stream)
+    ctx.set_launch_config(**dict(cfg0, grouped=1))
+    t_grp = time_ms(lambda: ctx.simulate(scene, scs, o, d, out=out, **kw), steps, 1, stream)
+    ctx.set_launch_config(**cfg0)
     tune = ctx.autotune(scene, scs, o, d, out, cache_path=tune_cache, **kw)
     t_tuned = time_ms(lambda: ctx.simulate(scene, scs, o, d, out=out, **kw), steps, 1, stream)
     g = ctx.capture_graph(scene, scs, o, d, out, **kw)
@@ -272,7 +277,7 @@ def bench_batched(ctx, scene, mesh, steps, tune_cache=None):
     return {"workload": "batched_tls: %d positions on the als_buildings scene, %d pulses, %d subrays, "
                         "scanners S=19/31/61, 256 x 1 ns bins" % (seg.size, n, subrays),
             "pulses": n, "subrays": subrays,
-            "per_segment_launches_ms": t_seg, "persistent_ms": t_pers, "persistent_tuned_ms": t_tuned,
+            "per_segment_launches_ms": t_seg, "persistent_ms": t_pers, "grouped_ms": t_grp, "tuned_ms": t_tuned,
             "graph_tuned_ms": t_graph, "subrays_per_s_graph": subrays / (t_graph * 1e-3),
             "pulses_per_s_graph": n / (t_graph * 1e-3),
             "subrays_per_s_per_segment": subrays / (t_seg * 1e-3),

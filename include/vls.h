@@ -574,6 +574,11 @@ typedef struct {
                                   1: it does not (shorter walks, longer candidate lists, the same
                                   results): faster where candidates are cheap to test, as for
                                   vegetation scanned with one pulse per wavefront               */
+    int32_t grouped;           /* batches (segments): 1 (default) one launch per scanner over its
+                                  segments' wavefront tiles, each the fused kernel of that
+                                  scanner's layout; 0 one persistent launch for all segments,
+                                  whose wavefronts take tiles from a work counter (same results)  */
+    int32_t reserved;
 } vls_launch_config;
 
 vls_status vls_set_launch_config(vls_context ctx, const vls_launch_config* cfg);
@@ -608,7 +613,7 @@ typedef struct {
 
 /* Times vls_simulate on this batch for launch configurations (block shape,
  * LDS stack depth, pulses per wavefront, persistent grid size, cone pass on or
- * off, its cover tests on or off) by coordinate descent with HIP events on `stream` (a configuration's
+ * off, its cover tests on or off, grouped or persistent batches) by coordinate descent with HIP events on `stream` (a configuration's
  * time: the fastest of three pairs of calls after one warm-up call), keeps the
  * fastest in `ctx`, and appends
  * it to `cache_path` (JSON lines, may be NULL) keyed by scene size, subray

@@ -149,6 +149,7 @@ struct vls_context_s {
         std::vector<unsigned char> key;
         unsigned char* dev = nullptr;
         BatchDev bd;
+        std::vector<GroupDev> groups;  // per scanner: its segments, for grouped launches
         int max_bins = 0;
     };
     std::vector<Batch> batches;  // uploaded segment tables (read-only), reused by content
@@ -522,16 +523,44 @@ vls_status batch_tables(vls_context ctx, const Prepared& pr, vls_context_s::Batc
         pulse_end[s] = pr.off[s + 1];
         seg[s] = pr.seg_sc[s];
     }
-    // layout: tile_off | pulse_off | pulse_end | seg | scanners | counter
+    // the same segments grouped by scanner (in segment order within a scanner)
+    // with their own tile numbering, for one launch per scanner
+    const int nsc = (int)pr.sc.size();
+    std::vector<long long> g_tile(ns), g_po(ns), g_pe(ns);
+    std::vector<int> g_first(nsc + 1, 0);
+    std::vector<long long> g_t0(nsc + 1, 0);
+    {
+        int k = 0;
+        long long t = 0;
+        for (int c = 0; c < nsc; ++c) {
+            g_first[c] = k;
+            g_t0[c] = t;
+            for (int s = 0; s < ns; ++s) {
+                if (pr.seg_sc[s] != c) continue;
+                g_tile[k] = t;
+                g_po[k] = pulse_off[s];
+                g_pe[k] = pulse_end[s];
+                t += tile_off[s + 1] - tile_off[s];
+                ++k;
+            }
+        }
+        g_first[nsc] = k;
+        g_t0[nsc] = t;
+    }
+    // layout: tile_off | pulse_off | pulse_end | seg | scanners | counter | grouped tile_off | pulse_off | pulse_end
     size_t o_tile = 0, o_po = o_tile + 8 * (ns + 1), o_pe = o_po + 8 * ns, o_seg = o_pe + 8 * ns;
     size_t o_sc = (o_seg + 4 * ns + 63) / 64 * 64, o_ctr = o_sc + sizeof(ScannerDev) * pr.sc.size();
-    size_t bytes = o_ctr + 64;
+    size_t o_gt = o_ctr + 64, o_gpo = o_gt + 8 * ns, o_gpe = o_gpo + 8 * ns;
+    size_t bytes = o_gpe + 8 * ns;
     std::vector<unsigned char> blob(bytes, 0);
     memcpy(&blob[o_tile], tile_off.data(), 8 * (ns + 1));
     memcpy(&blob[o_po], pulse_off.data(), 8 * ns);
     memcpy(&blob[o_pe], pulse_end.data(), 8 * ns);
     memcpy(&blob[o_seg], seg.data(), 4 * ns);
     memcpy(&blob[o_sc], pr.sc.data(), sizeof(ScannerDev) * pr.sc.size());
+    memcpy(&blob[o_gt], g_tile.data(), 8 * ns);
+    memcpy(&blob[o_gpo], g_po.data(), 8 * ns);
+    memcpy(&blob[o_gpe], g_pe.data(), 8 * ns);
     for (auto& b : ctx->batches)
         if (b.key == blob) {
             out = &b;
@@ -553,6 +582,16 @@ vls_status batch_tables(vls_context ctx, const Prepared& pr, vls_context_s::Batc
     b.bd.counter = reinterpret_cast<unsigned long long*>(b.dev + o_ctr);
     b.bd.n_seg = ns;
     b.bd.n_tiles = tile_off[ns];
+    for (int c = 0; c < nsc; ++c) {
+        GroupDev g;
+        g.tile_off = reinterpret_cast<const long long*>(b.dev + o_gt) + g_first[c];
+        g.pulse_off = reinterpret_cast<const long long*>(b.dev + o_gpo) + g_first[c];
+        g.pulse_end = reinterpret_cast<const long long*>(b.dev + o_gpe) + g_first[c];
+        g.n_seg = g_first[c + 1] - g_first[c];
+        g.tile0 = g_t0[c];
+        g.tile1 = g_t0[c + 1];
+        b.groups.push_back(g);
+    }
     b.max_bins = pr.n_bins;
     ctx->batches.push_back(std::move(b));
     out = &ctx->batches.back();
@@ -701,12 +740,14 @@ vls_status vls_set_launch_config(vls_context ctx, const vls_launch_config* cfg)
     if (cfg->pack != 0 && cfg->pack != 1) return fail(VLS_ERR_INVALID_ARG, "pack must be 0 or 1");
     if (cfg->cone != 0 && cfg->cone != 1) return fail(VLS_ERR_INVALID_ARG, "cone must be 0 or 1");
     if (cfg->cover_off != 0 && cfg->cover_off != 1) return fail(VLS_ERR_INVALID_ARG, "cover_off must be 0 or 1");
+    if (cfg->grouped != 0 && cfg->grouped != 1) return fail(VLS_ERR_INVALID_ARG, "grouped must be 0 or 1");
     ctx->cfg.block_waves = cfg->block_waves;
     ctx->cfg.stack_lds = r;
     ctx->cfg.persistent_blocks = cfg->persistent_blocks;
     ctx->cfg.pack = cfg->pack;
     ctx->cfg.cone = cfg->cone;
     ctx->cfg.cover_off = cfg->cover_off;
+    ctx->cfg.grouped = cfg->grouped;
     return VLS_OK;
 }
 
@@ -719,6 +760,8 @@ vls_status vls_get_launch_config(vls_context ctx, vls_launch_config* cfg)
     cfg->pack = ctx->cfg.pack;
     cfg->cone = ctx->cfg.cone;
     cfg->cover_off = ctx->cfg.cover_off;
+    cfg->grouped = ctx->cfg.grouped;
+    cfg->reserved = 0;
     return VLS_OK;
 }
 
@@ -1724,8 +1767,15 @@ static vls_status simulate_enqueue(vls_context ctx, vls_scene scene, const Prepa
         pd.basis = basis;
     }
     if (prof && (e = prof_begin(ctx, s, ev)) != hipSuccess) return hip_fail(e, "timing event");
-    if (!bt) e = launch_simulate(sd, pr.sc[0], pd, od, 0, pulses->n_pulses, 1, ctx->cfg, s);
-    else e = launch_persistent(sd, bd, pr.n_bins, staged_slots(pr), pd, od, ctx->cfg, blocks, s);
+    if (!bt) {
+        e = launch_simulate(sd, pr.sc[0], pd, od, 0, pulses->n_pulses, 1, ctx->cfg, s);
+    } else if (ctx->cfg.grouped) {
+        e = hipSuccess;
+        for (size_t c = 0; c < bt->groups.size() && e == hipSuccess; ++c)
+            e = launch_grouped(sd, pr.sc[c], bt->groups[c], pd, od, ctx->cfg, s);
+    } else {
+        e = launch_persistent(sd, bd, pr.n_bins, staged_slots(pr), pd, od, ctx->cfg, blocks, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "simulate launch");
     if (prof && (e = prof_end(ctx, s, ev, ctx->prof_fused)) != hipSuccess) return hip_fail(e, "timing event");
     if ((e = range_noise_all(pr, od, s)) != hipSuccess) return hip_fail(e, "ranging error launch");
@@ -2016,6 +2066,7 @@ static bool tune_cache_find(const char* path, const std::string& key, vls_launch
         if ((p = strstr(line, "\"pack\": "))) t.pack = atoi(p + 8);
         if ((p = strstr(line, "\"cone\": "))) t.cone = atoi(p + 8);
         if ((p = strstr(line, "\"cover_off\": "))) t.cover_off = atoi(p + 13);
+        if ((p = strstr(line, "\"grouped\": "))) t.grouped = atoi(p + 11);
         c = t;
         found = true;
     }
@@ -2079,6 +2130,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             c.pack = cached.pack;
             c.cone = cached.cone;
             c.cover_off = cached.cover_off;
+            c.grouped = cached.grouped;
             double ms = 0.0;
             if ((st = timed(c, ms)) != VLS_OK) { ctx->cfg = entry; return st; }
             best = c;
@@ -2088,7 +2140,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             int tried = 1;
             const bool seg = pulses->n_segments > 0;
             int auto_blocks = seg ? persistent_occupancy_blocks(pr0.n_bins, staged_slots(pr0), scene->vox.n_vox > 0, entry) : 0;
-            for (int dim = 0; dim < 6; ++dim) {
+            for (int dim = 0; dim < 7; ++dim) {
                 std::vector<LaunchCfg> cand;
                 for (int v = 0; v < 4; ++v) {
                     LaunchCfg c = best;
@@ -2098,13 +2150,14 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
                     if (dim == 3) { if (!seg || v > 2) break; c.persistent_blocks = v == 0 ? 0 : (v == 1 ? auto_blocks / 2 : 2 * auto_blocks); }
                     if (dim == 4) { if (v > 1) break; c.cone = v; }
                     if (dim == 5) { if (v > 1 || !c.cone) break; c.cover_off = v; }
+                    if (dim == 6) { if (v > 1 || !seg) break; c.grouped = v; }
                     if (c.stack_lds + kMaxSpill - 1 < scene->stats.max_depth) continue;
                     cand.push_back(c);
                 }
                 for (auto& c : cand) {
                     if (c.block_waves == best.block_waves && c.stack_lds == best.stack_lds && c.pack == best.pack &&
                         c.persistent_blocks == best.persistent_blocks && c.cone == best.cone &&
-                        c.cover_off == best.cover_off)
+                        c.cover_off == best.cover_off && c.grouped == best.grouped)
                         continue;
                     double ms = 0.0;
                     if ((st = timed(c, ms)) != VLS_OK) { ctx->cfg = entry; return st; }
@@ -2116,9 +2169,9 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
             if (cache_path) {
                 FILE* f = fopen(cache_path, "a");
                 if (f) {
-                    fprintf(f, "{\"key\": \"%s\", \"block_waves\": %d, \"stack_lds\": %d, \"persistent_blocks\": %d, \"pack\": %d, \"cone\": %d, \"cover_off\": %d, \"ms\": %.6f}\n",
+                    fprintf(f, "{\"key\": \"%s\", \"block_waves\": %d, \"stack_lds\": %d, \"persistent_blocks\": %d, \"pack\": %d, \"cone\": %d, \"cover_off\": %d, \"grouped\": %d, \"ms\": %.6f}\n",
                             key.c_str(), best.block_waves, best.stack_lds, best.persistent_blocks, best.pack, best.cone,
-                            best.cover_off, best_ms);
+                            best.cover_off, best.grouped, best_ms);
                     fclose(f);
                 }
             }
@@ -2132,6 +2185,7 @@ vls_status vls_autotune(vls_context ctx, vls_scene scene, const vls_scanner_desc
         result->best.pack = best.pack;
         result->best.cone = best.cone;
         result->best.cover_off = best.cover_off;
+        result->best.grouped = best.grouped;
         result->best_ms = best_ms;
         return VLS_OK;
     } catch (const std::exception& e) {

@@ -1420,6 +1420,46 @@ __global__ __launch_bounds__(256) void k_wave(ScannerDev sc, PulsesDev pulses, O
     }
 }
 
+// Batched, grouped by scanner: one launch per scanner of a batch over its
+// segments' wave-tiles, one wavefront per tile.  The segment holding a tile is
+// found by a wave-uniform binary search; the wavefront then runs exactly as in
+// a launch of that segment alone (same kernel layout, same results).
+template <int MAXCH, bool CHUNK, bool VOX>
+__device__ __forceinline__ void grouped_body(const SceneDev& scene, const ScannerDev& sc, const GroupDev& g,
+                                             const PulsesDev& pulses, const OutDev& out, int ring_mask, int wl_bytes)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int waves = blockDim.x / kWave;
+    unsigned char* wl = smem + (threadIdx.x / kWave) * wl_bytes;
+    int* ring = reinterpret_cast<int*>(smem + wl_bytes * waves);
+    const long long tile = g.tile0 + (long long)blockIdx.x * waves + threadIdx.x / kWave;
+    if (tile >= g.tile1) return;
+    int lo = 0, hi = g.n_seg - 1;
+    while (lo < hi) {  // last segment whose first tile <= tile
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.tile_off[mid] <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const long long p = g.pulse_off[lo] + (tile - g.tile_off[lo]) * sc.P_w;
+    const long long left = g.pulse_end[lo] - p;
+    const int npw = left < sc.P_w ? (int)left : sc.P_w;
+    process_wave<MAXCH, 1, CHUNK, VOX>(scene, sc, pulses, out, p, npw, ring, ring_mask, wl);
+}
+
+template <int MAXCH, bool VOX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_grouped(SceneDev scene,
+    ScannerDev sc, GroupDev g, PulsesDev pulses, OutDev out, int ring_mask, int wl_bytes)
+{
+    grouped_body<MAXCH, false, VOX>(scene, sc, g, pulses, out, ring_mask, wl_bytes);
+}
+
+template <int MAXCH, bool VOX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_grouped1(SceneDev scene,
+    ScannerDev sc, GroupDev g, PulsesDev pulses, OutDev out, int ring_mask, int wl_bytes)
+{
+    grouped_body<MAXCH, true, VOX>(scene, sc, g, pulses, out, ring_mask, wl_bytes);
+}
+
 // Persistent batched kernel: wavefronts take chunks of wave-tiles from a global counter.
 template <int MAXCH, bool VOX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_persistent(SceneDev scene, BatchDev batch, PulsesDev pulses,
@@ -1834,6 +1874,39 @@ hipError_t launch_waveform(const ScannerDev& sc, const PulsesDev& pulses, const 
     else if (sc.n_bins <= 512) VLS_WAVE_LAUNCH(8);
     else VLS_WAVE_LAUNCH(16);
 #undef VLS_WAVE_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_grouped(const SceneDev& scene, const ScannerDev& sc, const GroupDev& g, const PulsesDev& pulses,
+                          const OutDev& out, const LaunchCfg& cfg, hipStream_t stream)
+{
+    const long long tiles = g.tile1 - g.tile0;
+    if (tiles <= 0 || g.n_seg <= 0) return hipSuccess;
+    const int block = cfg.block_waves * kWave;
+    const unsigned grid = (unsigned)((tiles + cfg.block_waves - 1) / cfg.block_waves);
+    const int wl = wave_lds_bytes(pulses.cand ? sc.P_w * staged_per_pulse(sc.P_w) : 0);
+    const size_t lds = sim_lds_bytes(block, cfg.stack_lds, wl);
+    const int mask = cfg.stack_lds - 1;
+    const bool vox = scene.vox.n_vox > 0;
+#define VLS_GROUPED_V(CH, VOX)                                                                                     \
+    do {                                                                                                          \
+        if (sc.P_w == 1)                                                                                          \
+            hipLaunchKernelGGL((k_grouped1<CH, VOX>), dim3(grid), dim3(block), lds, stream, scene, sc, g, pulses, out, \
+                               mask, wl);                                                                         \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_grouped<CH, VOX>), dim3(grid), dim3(block), lds, stream, scene, sc, g, pulses, out,  \
+                               mask, wl);                                                                         \
+    } while (0)
+#define VLS_GROUPED(CH)                   \
+    do {                                  \
+        if (vox) VLS_GROUPED_V(CH, true); \
+        else VLS_GROUPED_V(CH, false);    \
+    } while (0)
+    if (sc.n_bins <= 256) VLS_GROUPED(4);
+    else if (sc.n_bins <= 512) VLS_GROUPED(8);
+    else VLS_GROUPED(16);
+#undef VLS_GROUPED
+#undef VLS_GROUPED_V
     return hipGetLastError();
 }
 

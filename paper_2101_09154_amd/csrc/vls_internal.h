@@ -175,6 +175,17 @@ struct BatchDev {
     long long n_tiles;
 };
 
+// One scanner's segments of a batch, numbered in the batch's scanner-grouped
+// tile order: a launch covers tiles [tile0, tile1), segment i starting at tile
+// tile_off[i] with pulses [pulse_off[i], pulse_end[i]).
+struct GroupDev {
+    const long long* tile_off;
+    const long long* pulse_off;
+    const long long* pulse_end;
+    int n_seg = 0;
+    long long tile0 = 0, tile1 = 0;
+};
+
 // Two-level scenes (scene parts kept once, placed by instances; see trace.hip
 // k_trace2).  A part: its own LBVH over its triangles in its own frame.
 struct PartDev {
@@ -244,6 +255,7 @@ struct LaunchCfg {
     int pack = 0;  // 0: floor(64/S) pulses per wavefront; 1: one pulse per wavefront
     int cone = 1;  // 1: one cone traversal per pulse collects candidate triangles for its subrays
     int cover_off = 0;  // 1: the cone traversal runs no cover tests
+    int grouped = 1;    // batches: 1 one launch per scanner over its segments' tiles, 0 the persistent kernel
 };
 
 // ---- host-side launchers (defined in the .hip files) ----
@@ -287,6 +299,10 @@ hipError_t launch_waveform(const ScannerDev& sc, const PulsesDev& pulses, const 
                            long long first, long long count, int mode, const LaunchCfg& cfg, hipStream_t stream);
 // staged_slots: the most candidate records any of the batch's scanners stages per
 // wavefront (pulses per wavefront * staged_per_pulse): it sizes that LDS.
+// One launch over one scanner's segments of a batch (the fused kernel of its
+// layout, one wavefront per tile, the segment found by a binary search).
+hipError_t launch_grouped(const SceneDev& scene, const ScannerDev& sc, const GroupDev& g, const PulsesDev& pulses,
+                          const OutDev& out, const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_persistent(const SceneDev& scene, const BatchDev& batch, int max_bins, int staged_slots,
                              const PulsesDev& pulses, const OutDev& out, const LaunchCfg& cfg, int blocks,
                              hipStream_t stream);

@@ -78,7 +78,7 @@ class Outputs(ctypes.Structure):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("block_waves", i32), ("stack_lds", i32), ("persistent_blocks", i32), ("pack", i32),
-                ("cone", i32), ("cover_off", i32)]
+                ("cone", i32), ("cover_off", i32), ("grouped", i32), ("reserved", i32)]
 
 
 class SurveyDesc(ctypes.Structure):
@@ -376,8 +376,9 @@ class Context:
     def scene_instanced(self, parts, instances, stream=None, two_level=False):
         return Scene.instanced(self, parts, instances, stream, two_level)
 
-    def set_launch_config(self, block_waves=1, stack_lds=16, persistent_blocks=0, pack=0, cone=1, cover_off=0):
-        c = LaunchConfig(block_waves, stack_lds, persistent_blocks, pack, cone, cover_off)
+    def set_launch_config(self, block_waves=1, stack_lds=16, persistent_blocks=0, pack=0, cone=1, cover_off=0,
+                          grouped=1):
+        c = LaunchConfig(block_waves, stack_lds, persistent_blocks, pack, cone, cover_off, grouped, 0)
         _check(lib().vls_set_launch_config(self._h, ctypes.byref(c)))
 
     def set_deterministic(self, on=True):
@@ -388,7 +389,7 @@ class Context:
         c = LaunchConfig()
         _check(lib().vls_get_launch_config(self._h, ctypes.byref(c)))
         return {"block_waves": c.block_waves, "stack_lds": c.stack_lds, "persistent_blocks": c.persistent_blocks,
-                "pack": c.pack, "cone": c.cone, "cover_off": c.cover_off}
+                "pack": c.pack, "cone": c.cone, "cover_off": c.cover_off, "grouped": c.grouped}
 
     def synchronize(self, stream=None):
         _check(lib().vls_synchronize(self._h, _stream(stream)))
@@ -532,7 +533,7 @@ class Context:
                                   ctypes.byref(r)))
         return {"best": {"block_waves": r.best.block_waves, "stack_lds": r.best.stack_lds,
                          "persistent_blocks": r.best.persistent_blocks, "pack": r.best.pack,
-                         "cone": r.best.cone, "cover_off": r.best.cover_off},
+                         "cone": r.best.cone, "cover_off": r.best.cover_off, "grouped": r.best.grouped},
                 "best_ms": r.best_ms, "default_ms": r.default_ms, "n_tried": r.n_tried,
                 "from_cache": bool(r.from_cache)}
 

@@ -294,7 +294,12 @@ def test_batched_matches_per_segment(ctx):
     say("batched", batch.n, batch.segment_offsets)
     o = _dev(batch.origins)
     d = _dev(batch.directions)
-    gb = to_np(ctx.simulate(scene, scs, o, d, segment_offsets=batch.segment_offsets, segment_scanner=seg_sc))
+    # one launch per scanner over its segments (default) and the persistent kernel
+    gbs = []
+    for grouped in (1, 0):
+        ctx.set_launch_config(grouped=grouped)
+        gbs.append(to_np(ctx.simulate(scene, scs, o, d, segment_offsets=batch.segment_offsets, segment_scanner=seg_sc)))
+    ctx.set_launch_config()
     torch.cuda.synchronize()
     off = batch.segment_offsets
     for s in range(len(parts)):
@@ -303,11 +308,12 @@ def test_batched_matches_per_segment(ctx):
         sc = scs[seg_sc[s]]
         gs = to_np(ctx.simulate(scene, sc, o[off[s]:off[s + 1]], d[off[s]:off[s + 1]]))
         S = gs["subray_tri"].shape[1]
-        for k in gs:
-            a = gb[k][off[s]:off[s + 1]]
-            if k.startswith("subray"):
-                a = a[:, :S]
-            assert np.array_equal(a, gs[k], equal_nan=True), (s, k)
+        for gb in gbs:
+            for k in gs:
+                a = gb[k][off[s]:off[s + 1]]
+                if k.startswith("subray"):
+                    a = a[:, :S]
+                assert np.array_equal(a, gs[k], equal_nan=True), (s, k)
         sel = np.arange(parts[s].n)[:: max(1, parts[s].n // 40)]
         compare(mesh, parts[s], sc, {k: v for k, v in gs.items()}, sel=sel, label="segment %d" % s)
 
