@@ -2059,6 +2059,7 @@ static bool tune_cache_find(const char* path, const std::string& key, vls_launch
     while (fgets(line, sizeof line, f)) {
         if (!strstr(line, pat.c_str())) continue;
         vls_launch_config t{};
+        t.grouped = 1;  // the default for entries written before the field existed
         const char* p;
         if ((p = strstr(line, "\"block_waves\": "))) t.block_waves = atoi(p + 15);
         if ((p = strstr(line, "\"stack_lds\": "))) t.stack_lds = atoi(p + 13);
