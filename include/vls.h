@@ -487,7 +487,9 @@ vls_status vls_echo_width(vls_context ctx, const vls_scanner_desc* scanners, int
 /* The whole path fused in one launch: trace, power, waveform, returns.
  * waveform may be NULL (returns are still found from the in-register
  * waveform, Sec. 5.4: binning runs even when no waveform is written).
- * With segments, one persistent launch covers every segment.  Before it, a
+ * With segments, one launch per scanner covers its segments (or, with the
+ * launch configuration's grouped = 0, one persistent launch covers them all).
+ * Before it, a
  * cone pass lists each pulse's candidate triangles (Sec. 3.4: every subray of
  * a pulse leaves its origin within the beam's divergence): up to
  * VLS_MAX_CANDIDATES per pulse in the stream's workspace (1 KiB per pulse);
@@ -613,9 +615,10 @@ typedef struct {
 
 /* Times vls_simulate on this batch for launch configurations (block shape,
  * LDS stack depth, pulses per wavefront, persistent grid size, cone pass on or
- * off, its cover tests on or off, grouped or persistent batches) by coordinate descent with HIP events on `stream` (a configuration's
- * time: the fastest of three pairs of calls after one warm-up call), keeps the
- * fastest in `ctx`, and appends
+ * off, its cover tests on or off, grouped or persistent batches) by
+ * coordinate descent with HIP events on `stream` (a configuration's time: the
+ * fastest of three pairs of calls after one warm-up call), keeps the fastest in
+ * `ctx`, and appends
  * it to `cache_path` (JSON lines, may be NULL) keyed by scene size, subray
  * counts, bins, pulse count and segments.  A matching cache entry is used
  * without timing.  Writes the outputs as vls_simulate does.  Synchronous. */
@@ -634,8 +637,8 @@ vls_status vls_cone_candidates(vls_context ctx, vls_scene scene, const vls_scann
 /* Kernel timing for measurement (no passage of the paper: it instruments the
  * calls above).  While enabled, every eager vls_simulate call records a pair of
  * HIP events on its stream around the cone pass, around the packet walk of the
- * pulses whose candidate list overflowed, and around the fused (or persistent)
- * kernel; nothing is recorded while the stream is being captured
+ * pulses whose candidate list overflowed, and around the fused kernel (or the
+ * batch's launches); nothing is recorded while the stream is being captured
  * into a graph.  vls_profile_read waits for the recorded events, returns the
  * summed elapsed times and launch counts since the previous read, and clears
  * them.  The events are owned by the context.  Errors: VLS_ERR_INVALID_ARG for
