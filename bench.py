@@ -19,6 +19,7 @@ library (vls_trace_counts).
 """
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -42,13 +43,18 @@ def log(*a):
 
 
 def source_hash():
-    """Hash of the device code (the .hip sources and the headers they include)."""
+    """Hash of the device code (the .hip sources and the headers they include),
+    comments left out and white space collapsed: an edit of a comment does not
+    change the code the profiles were taken on."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2101_09154_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(csrc, f), "r") as fh:
+                text = fh.read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+            h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

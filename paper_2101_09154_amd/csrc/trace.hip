@@ -7,14 +7,19 @@
 // sin phi v), (u, v) the orthonormal basis of Duff et al. (2017).
 //
 // Closest hit (Sec. 3.4: a hit ends the subray; Sec. 5.1: minimum-distance
-// intersection): LBVH traversal, near child first, boxes tested in FP32 against
-// a per-ray padding that covers the rounding of the FP32 ray, so no box that
-// holds the FP64 closest hit is culled.  Leaves are tested in FP64 with the
-// watertight test of Woop, Benthin & Wald (2013) (two-sided, inclusive edges,
-// t > 0), so no subray slips through a shared edge and hit selection is the
-// exact-arithmetic result up to FP64 rounding.  Equal distances go to the lower triangle index.  The
-// traversal stack is a per-lane ring in LDS that spills its oldest entries to
-// per-lane scratch when it is full.
+// intersection): the triangles a pulse's subrays can meet come from the cone
+// pass (cone.hip); otherwise each subray walks the LBVH, near child first,
+// boxes tested in FP32 against a per-ray padding that covers the rounding of
+// the FP32 ray, so no box that holds the FP64 closest hit is culled.
+// Triangles are tested in FP64 with the watertight test of Woop, Benthin &
+// Wald (2013) (two-sided, inclusive edges, t > 0), so no subray slips through
+// a shared edge and hit selection is the exact-arithmetic result up to FP64
+// rounding; equal distances go to the lower triangle index.  A pulse alone in
+// its wavefront first culls its candidates at staging and puts each survivor
+// to its subrays' FP32 vote (edge_vote_coeffs), whose margins guarantee that
+// only candidates no subray can be inside skip the FP64 test.  The traversal
+// stack is a per-lane ring in LDS that spills its oldest entries to per-lane
+// scratch when it is full.
 //
 // Power (Sec. 5.2, Eq. 7 with a Lambertian extended target):
 //   P_k = P0 w_k (eta D^2 / 4) rho cos(theta) / R^2,  cos(theta) = |d_k . n|.
@@ -23,8 +28,9 @@
 // before the pulse's first two-way travel time tau = 2R/c; lane l owns bins
 // l + 64 m; each bin sums P_k p(t0 + j bin - tau_k) over the pulse's subrays,
 // read from LDS, in fixed k order (deterministic).  Offsets are formed in FP64
-// and split into two FP32 parts so the FP32 pulse argument keeps FP64 accuracy.
-// Only chunks of 64 bins that some subray's pulse support reaches are summed.
+// from the chunk's centre and split into two FP32 parts: the sums take the
+// head, the attribution of returns both.  Only chunks of 64 bins that some
+// subray's pulse support reaches are summed.
 //
 // Returns (Sec. 3.4 local maxima): bin j in [1, n-2] is a return if
 // wf[j] > wf[j-1], wf[j] >= wf[j+1] and wf[j] >= max(abs, rel * max wf);
