@@ -39,7 +39,8 @@ struct Cone {
     float U[3];
     float V[3];
     float i1[3], i2[3], c1[3], c2[3];
-    bool mixed;   // some axis has d_a - k < 0 < d_a + k
+    bool mixed;      // some axis has d_a - k < 0 < d_a + k
+    int mixed_axes;  // bit a set for each such axis
 };
 
 // The pulse's cone from its basis (the subrays' own basis, computed the same
@@ -67,12 +68,16 @@ __device__ __forceinline__ bool setup_cone(const double* __restrict__ o, const d
     // slope: tan(a_max), the FP32 rounding of the axis (~2^-23 rad) and slack
     float k = (float)(tana * (1.0 + 1e-6) + 4e-7);
     c.mixed = false;
+    c.mixed_axes = 0;
     for (int i = 0; i < 3; ++i) {
         float da = (float)n[i];
         float s1 = da + k, s2 = da - k;
         if (s1 == 0.0f) s1 = 1e-30f;
         if (s2 == 0.0f) s2 = -1e-30f;
-        if (s1 > 0.0f && s2 < 0.0f) c.mixed = true;
+        if (s1 > 0.0f && s2 < 0.0f) {
+            c.mixed = true;
+            c.mixed_axes |= 1 << i;
+        }
         c.i1[i] = 1.0f / s1;
         c.i2[i] = 1.0f / s2;
         c.c1[i] = (float)(c.O[i] + pad) * c.i1[i];
@@ -104,14 +109,17 @@ __device__ __forceinline__ void cone_axis(const Cone& c, int a, float lo, float 
     }
 }
 
-template <bool MIXED>
+// MA: the axes (bit a for axis a) that take the mixed-sign form; it must
+// include every mixed axis of every lane that uses it (the form is also right
+// for an axis whose slopes have one sign, only dearer).
+template <int MA>
 __device__ __forceinline__ bool cone_box(const Cone& c, float lx, float ly, float lz, float hx, float hy, float hz,
                                          float tcull, float& tn)
 {
     float l0, u0, l1, u1, l2, u2;
-    cone_axis<MIXED>(c, 0, lx, hx, l0, u0);
-    cone_axis<MIXED>(c, 1, ly, hy, l1, u1);
-    cone_axis<MIXED>(c, 2, lz, hz, l2, u2);
+    cone_axis<(MA & 1) != 0>(c, 0, lx, hx, l0, u0);
+    cone_axis<(MA & 2) != 0>(c, 1, ly, hy, l1, u1);
+    cone_axis<(MA & 4) != 0>(c, 2, lz, hz, l2, u2);
     float n0 = fmaxf(fmaxf(l0, l1), fmaxf(l2, 0.0f));
     float f0 = fminf(fminf(u0, u1), fminf(u2, tcull));
     tn = n0;
@@ -169,7 +177,7 @@ __device__ __forceinline__ double cover_distance(const Cone& c, const float4* __
 // one waiting, so that the wavefront does not pay for it in every step in which
 // some lane sits at a leaf.  A later or skipped cover test only culls less; the
 // list still holds every leaf the cone reaches before the cull that applies.
-template <bool COUNT, bool MIXED, bool COVER = true>
+template <bool COUNT, int MA, bool COVER = true>
 __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, int* __restrict__ out, int e0, int cap,
                                          int2* my, int ring_mask, int& visits)
 {
@@ -199,10 +207,10 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
                 const float4 LX = nd[0], LY = nd[1], LZ = nd[2], HX = nd[3], HY = nd[4], HZ = nd[5], RF = nd[6];
                 float t[4];
                 int r[4] = {__float_as_int(RF.x), __float_as_int(RF.y), __float_as_int(RF.z), __float_as_int(RF.w)};
-                t[0] = cone_box<MIXED>(c, LX.x, LY.x, LZ.x, HX.x, HY.x, HZ.x, tcull, t[0]) && r[0] != kEmpty4 ? t[0] : INFINITY;
-                t[1] = cone_box<MIXED>(c, LX.y, LY.y, LZ.y, HX.y, HY.y, HZ.y, tcull, t[1]) && r[1] != kEmpty4 ? t[1] : INFINITY;
-                t[2] = cone_box<MIXED>(c, LX.z, LY.z, LZ.z, HX.z, HY.z, HZ.z, tcull, t[2]) && r[2] != kEmpty4 ? t[2] : INFINITY;
-                t[3] = cone_box<MIXED>(c, LX.w, LY.w, LZ.w, HX.w, HY.w, HZ.w, tcull, t[3]) && r[3] != kEmpty4 ? t[3] : INFINITY;
+                t[0] = cone_box<MA>(c, LX.x, LY.x, LZ.x, HX.x, HY.x, HZ.x, tcull, t[0]) && r[0] != kEmpty4 ? t[0] : INFINITY;
+                t[1] = cone_box<MA>(c, LX.y, LY.y, LZ.y, HX.y, HY.y, HZ.y, tcull, t[1]) && r[1] != kEmpty4 ? t[1] : INFINITY;
+                t[2] = cone_box<MA>(c, LX.z, LY.z, LZ.z, HX.z, HY.z, HZ.z, tcull, t[2]) && r[2] != kEmpty4 ? t[2] : INFINITY;
+                t[3] = cone_box<MA>(c, LX.w, LY.w, LZ.w, HX.w, HY.w, HZ.w, tcull, t[3]) && r[3] != kEmpty4 ? t[3] : INFINITY;
                 // nearest first: sort the four (distance, ref) pairs, misses (inf) last
 #define VLS_CX(a, b)                                  \
     if (t[b] < t[a]) {                                \
@@ -316,11 +324,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     int n = 0;
     int* out = cand + p * (kCandMax + 1);
     int2* my = reinterpret_cast<int2*>(smem) + threadIdx.x;
-    // the cheaper slab test serves every wavefront without a mixed-sign axis
-    if (__ballot(ok && c.mixed) == 0) {
-        if (ok) n = cone_walk<COUNT, false, COVER>(scene, c, out, 1, cap, my, ring_mask, visits);
+    // the cheaper slab test serves every axis no lane of the wavefront has with
+    // slopes of both signs: none, only x or only y (scan lines along an axis),
+    // else all three take the mixed form
+    const unsigned long long mx = __ballot(ok && (c.mixed_axes & 1)), my_ = __ballot(ok && (c.mixed_axes & 2)),
+                             mz = __ballot(ok && (c.mixed_axes & 4));
+    if ((mx | my_ | mz) == 0) {
+        if (ok) n = cone_walk<COUNT, 0, COVER>(scene, c, out, 1, cap, my, ring_mask, visits);
+    } else if ((my_ | mz) == 0) {
+        if (ok) n = cone_walk<COUNT, 1, COVER>(scene, c, out, 1, cap, my, ring_mask, visits);
+    } else if ((mx | mz) == 0) {
+        if (ok) n = cone_walk<COUNT, 2, COVER>(scene, c, out, 1, cap, my, ring_mask, visits);
     } else {
-        if (ok) n = cone_walk<COUNT, true, COVER>(scene, c, out, 1, cap, my, ring_mask, visits);
+        if (ok) n = cone_walk<COUNT, 7, COVER>(scene, c, out, 1, cap, my, ring_mask, visits);
     }
     if (active) out[0] = n;
     if (ovf_list) {
@@ -379,8 +395,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                             setup_cone(pulses.origins + 3 * q, B, tana, scene.bounds[12], c);
             int visits = 0;
             int* out = long_rows + (size_t)i * kLongMax;
-            if (ok) n = c.mixed ? cone_walk<false, true, COVER>(scene, c, out, 0, kLongMax, my, ring_mask, visits)
-                                : cone_walk<false, false, COVER>(scene, c, out, 0, kLongMax, my, ring_mask, visits);
+            // the slab test's form by the wavefront's mixed-sign axes, as in k_cone
+            const unsigned long long mx = __ballot(ok && (c.mixed_axes & 1)),
+                                     my_ = __ballot(ok && (c.mixed_axes & 2)), mz = __ballot(ok && (c.mixed_axes & 4));
+            if ((mx | my_ | mz) == 0) {
+                if (ok) n = cone_walk<false, 0, COVER>(scene, c, out, 0, kLongMax, my, ring_mask, visits);
+            } else if ((my_ | mz) == 0) {
+                if (ok) n = cone_walk<false, 1, COVER>(scene, c, out, 0, kLongMax, my, ring_mask, visits);
+            } else if ((mx | mz) == 0) {
+                if (ok) n = cone_walk<false, 2, COVER>(scene, c, out, 0, kLongMax, my, ring_mask, visits);
+            } else {
+                if (ok) n = cone_walk<false, 7, COVER>(scene, c, out, 0, kLongMax, my, ring_mask, visits);
+            }
             if (n > kCandMax) {
                 int* row = cand + q * (kCandMax + 1);
                 row[0] = n;
