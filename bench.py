@@ -355,9 +355,10 @@ def bench_grad(ctx, steps):
             "grad_norm_heights": float(heights.grad.norm().item())}
 
 
-def bench_voxels(ctx, steps):
+def bench_voxels(ctx, steps, tune_cache=None):
     """Transmissive voxels (Sec. 3.5.4, Sec. 5.2): the uls_voxels forest, crowns
-    as a voxel grid of plant area density over woody trees and terrain."""
+    as a voxel grid of plant area density over woody trees and terrain (launch
+    configuration from the autotuner's cache)."""
     import torch
     from synth import configs
     import paper_2101_09154_amd as vp
@@ -371,6 +372,8 @@ def bench_voxels(ctx, steps):
     S = vp.n_subrays(sc)
     out = ctx.alloc_outputs(n, S, sc["n_bins"], sc["max_returns"], dev)
     stream = torch.cuda.current_stream()
+    cfg0 = ctx.launch_config()
+    tune = ctx.autotune(scene, sc, o, d, out, cache_path=tune_cache)
     ctx.simulate(scene, sc, o, d, out=out)
     torch.cuda.synchronize()
     vfrac = float((out["subray_tri"] >= mesh.n_triangles).float().mean().item())
@@ -388,7 +391,9 @@ def bench_voxels(ctx, steps):
            "voxel_echo_fraction": vfrac,
            "fused_ms": prof["fused_ms"] / max(prof["fused_launches"], 1),
            "cone_ms": prof["cone_ms"] / max(prof["cone_launches"], 1),
-           "packet_ms": prof["packet_ms"] / max(prof["packet_launches"], 1)}
+           "packet_ms": prof["packet_ms"] / max(prof["packet_launches"], 1),
+           "launch": ctx.launch_config(), "autotune": tune}
+    ctx.set_launch_config(**cfg0)
     scene.close()
     return res
 
@@ -745,7 +750,7 @@ def main():
         log("gradient workload")
         res["gradient"] = bench_grad(ctx, max(args.steps // 2, 2))
         log("voxel workload")
-        res["voxels"] = bench_voxels(ctx, max(args.steps // 2, 2))
+        res["voxels"] = bench_voxels(ctx, max(args.steps // 2, 2), tune_cache=args.tune_cache)
         log("instanced workload")
         res["instanced"] = bench_instanced(ctx, max(args.steps // 2, 2))
     if not args.only_plain:
