@@ -127,44 +127,62 @@ __device__ __forceinline__ bool cone_box(const Cone& c, float lx, float ly, floa
 }
 
 // Largest axial distance at which the whole pyramid around the cone meets the
-// triangle, or +inf if some corner ray misses it.  Each corner ray O + t d,
-// d = D +- U +- V, must hit the triangle inside all three edges with a margin
-// (Moller-Trumbore in FP64; a sufficient condition only: a miss just means no
-// cull).  With s = O - a, n = e1 x e2, w = e2 x s and q = s x e1, the
+// triangle (an upper bound), or +inf if some corner ray may miss it.  Each
+// corner ray O + t d, d = D +- U +- V, must hit the triangle strictly inside
+// all three edges (Moller-Trumbore; a sufficient condition only: a miss just
+// means no cull).  With s = O - a, n = e1 x e2, w = e2 x s and q = s x e1, the
 // unnormalised determinant and barycentrics are triple products:
 // det = -d . n, u det = d . w, v det = d . q, t det = e2 . q, so each corner
-// costs three dot products.
-__device__ __forceinline__ double cover_distance(const Cone& c, const float4* __restrict__ tris, int li)
+// costs three dot products.  In FP32: e1, e2 and s are rounded once (s from
+// FP64), a cross product by fused multiply-adds and a dot product with the
+// exact corner direction err by less than 8 u |x|1 |y|1 |z|1 for the triple
+// product of x, y, z (u = 2^-24); each test is taken with twice that bound
+// against it, so a pass holds in exact arithmetic, and the distance is the
+// bound's largest quotient rounded up.
+__device__ __forceinline__ float cover_distance(const Cone& c, const float4* __restrict__ tris, int li)
 {
     const float4 A = tris[3 * li], B = tris[3 * li + 1], C = tris[3 * li + 2];
-    const double e1[3] = {(double)B.x - A.x, (double)B.y - A.y, (double)B.z - A.z};
-    const double e2[3] = {(double)C.x - A.x, (double)C.y - A.y, (double)C.z - A.z};
-    const double s3[3] = {c.O[0] - A.x, c.O[1] - A.y, c.O[2] - A.z};
-    const double q[3] = {s3[1] * e1[2] - s3[2] * e1[1], s3[2] * e1[0] - s3[0] * e1[2], s3[0] * e1[1] - s3[1] * e1[0]};
-    const double w[3] = {e2[1] * s3[2] - e2[2] * s3[1], e2[2] * s3[0] - e2[0] * s3[2], e2[0] * s3[1] - e2[1] * s3[0]};
-    const double nv[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
-    const double tn = e2[0] * q[0] + e2[1] * q[1] + e2[2] * q[2];
-    const double m = 1e-9;
-    double dmin = INFINITY;  // smallest |det| over the corners (largest t = tn / det)
+    const float e1[3] = {B.x - A.x, B.y - A.y, B.z - A.z};
+    const float e2[3] = {C.x - A.x, C.y - A.y, C.z - A.z};
+    const float s3[3] = {(float)(c.O[0] - A.x), (float)(c.O[1] - A.y), (float)(c.O[2] - A.z)};
+    const float q[3] = {fmaf(s3[1], e1[2], -(s3[2] * e1[1])), fmaf(s3[2], e1[0], -(s3[0] * e1[2])),
+                        fmaf(s3[0], e1[1], -(s3[1] * e1[0]))};
+    const float w[3] = {fmaf(e2[1], s3[2], -(e2[2] * s3[1])), fmaf(e2[2], s3[0], -(e2[0] * s3[2])),
+                        fmaf(e2[0], s3[1], -(e2[1] * s3[0]))};
+    const float nv[3] = {fmaf(e1[1], e2[2], -(e1[2] * e2[1])), fmaf(e1[2], e2[0], -(e1[0] * e2[2])),
+                         fmaf(e1[0], e2[1], -(e1[1] * e2[0]))};
+    const float tn = fmaf(e2[0], q[0], fmaf(e2[1], q[1], e2[2] * q[2]));
+    const float l1 = fabsf(e1[0]) + fabsf(e1[1]) + fabsf(e1[2]);
+    const float l2 = fabsf(e2[0]) + fabsf(e2[1]) + fabsf(e2[2]);
+    const float ls = fabsf(s3[0]) + fabsf(s3[1]) + fabsf(s3[2]);
+    // |d|1 of every corner is at most |D|1 + |U|1 + |V|1
+    const float dl = (fabsf(c.D[0]) + fabsf(c.D[1]) + fabsf(c.D[2])) + (fabsf(c.U[0]) + fabsf(c.U[1]) + fabsf(c.U[2])) +
+                     (fabsf(c.V[0]) + fabsf(c.V[1]) + fabsf(c.V[2]));
+    const float Ed = 0x1p-20f * dl * l1 * l2, Eu = 0x1p-20f * dl * l2 * ls, Ev = 0x1p-20f * dl * ls * l1;
+    const float Et = 0x1p-20f * l2 * ls * l1;
+    // beyond FP32's comfortable range (or not finite): no cull
+    if (!(Ed + Eu + Ev + Et < 1e30f)) return INFINITY;
+    float dmin = INFINITY;  // smallest determinant bound over the corners
     for (int k = 0; k < 4; ++k) {
         const float su = (k & 1) ? 1.0f : -1.0f, sv = (k & 2) ? 1.0f : -1.0f;
-        const double d[3] = {(double)fmaf(sv, c.V[0], fmaf(su, c.U[0], c.D[0])),
-                             (double)fmaf(sv, c.V[1], fmaf(su, c.U[1], c.D[1])),
-                             (double)fmaf(sv, c.V[2], fmaf(su, c.U[2], c.D[2]))};
-        double det = -(d[0] * nv[0] + d[1] * nv[1] + d[2] * nv[2]);
-        double un = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
-        double vn = d[0] * q[0] + d[1] * q[1] + d[2] * q[2];
-        double t = tn;
-        if (det < 0.0) {  // same tests with det > 0
+        const float d[3] = {fmaf(sv, c.V[0], fmaf(su, c.U[0], c.D[0])), fmaf(sv, c.V[1], fmaf(su, c.U[1], c.D[1])),
+                            fmaf(sv, c.V[2], fmaf(su, c.U[2], c.D[2]))};
+        float det = -fmaf(d[0], nv[0], fmaf(d[1], nv[1], d[2] * nv[2]));
+        float un = fmaf(d[0], w[0], fmaf(d[1], w[1], d[2] * w[2]));
+        float vn = fmaf(d[0], q[0], fmaf(d[1], q[1], d[2] * q[2]));
+        float t = tn;
+        if (det < 0.0f) {  // same tests with det > 0
             det = -det;
             un = -un;
             vn = -vn;
             t = -t;
         }
-        if (!(det > 0.0 && un > m * det && vn > m * det && un + vn < (1.0 - m) * det && t > 0.0)) return INFINITY;
-        dmin = fmin(dmin, det);
+        const float dlo = det - Ed;
+        if (!(dlo > 0.0f && un > Eu && vn > Ev && (un + vn) * (1.0f + 0x1p-22f) + (Eu + Ev) < dlo && t > Et))
+            return INFINITY;
+        dmin = fminf(dmin, dlo);
     }
-    return (fabs(tn) / dmin) * (1.0 + 1e-9) + 1e-9;
+    return (fabsf(tn) + Et) / dmin * (1.0f + 0x1p-20f);
 }
 
 // One lane's cone traversal: writes the candidate leaves to out[e0..] and
@@ -275,12 +293,8 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
         const int nw = __popcll(waiting);
         if (nw >= 16 || 4 * nw >= __popcll(walking)) {
             if (busy && pend >= 0) {
-                double tc = cover_distance(c, scene.tris, pend);
-                if (tc < INFINITY) {
-                    float tf = (float)tc;
-                    if ((double)tf < tc) tf = nextafterf(tf, INFINITY);
-                    tcull = fminf(tcull, tf);
-                }
+                const float tc = cover_distance(c, scene.tris, pend);
+                if (tc < INFINITY) tcull = fminf(tcull, tc);
                 pend = -1;
             }
         }
