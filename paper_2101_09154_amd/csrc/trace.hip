@@ -194,27 +194,6 @@ __device__ __forceinline__ int cand_loop(const Ray& r, const CandRec* __restrict
     return best;
 }
 
-// The staged records whose bits are set in `mask` (a wave-uniform 64-bit set).
-template <int KZ>
-__device__ __forceinline__ int cand_loop_mask(const Ray& r, const CandRec* __restrict__ rec, unsigned long long mask,
-                                              Hit& h)
-{
-    int best = -1;
-    for (; mask; mask &= mask - 1) {
-        const int i = __ffsll((long long)mask) - 1;
-        const CandRec& c = rec[i];
-        double a[3] = {c.a[0], c.a[1], c.a[2]}, b[3] = {c.b[0], c.b[1], c.b[2]}, e[3] = {c.c[0], c.c[1], c.c[2]};
-        const double t = woop_t<KZ>(r, a, b, e, h.t);
-        const int orig = c.orig;
-        if (closer(t, orig, h)) {
-            h.t = t;
-            h.orig = orig;
-            best = i;
-        }
-    }
-    return best;
-}
-
 // Closest hit of one ray.  ring: this block's LDS ring, stride = blockDim.x.
 // COUNT: also count internal-node visits and triangle tests.
 template <bool COUNT>
