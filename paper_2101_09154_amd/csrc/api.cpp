@@ -457,7 +457,8 @@ vls_status check_scene(vls_context ctx, vls_scene scene, const Prepared& pr, boo
         return fail(VLS_ERR_UNSUPPORTED, b);
     }
     // the cone pass pushes up to three entries per four-wide level
-    if (ctx->cfg.cone && 3 * ((scene->stats.max_depth + 1) / 2) > kConeRing + kMaxSpill - 1) {
+    const int cone_ring = ctx->cfg.cover_off ? kConeRing : kConeRingCover;
+    if (ctx->cfg.cone && 3 * ((scene->stats.max_depth + 1) / 2) > cone_ring + kMaxSpill - 1) {
         char b[128];
         snprintf(b, sizeof b, "scene depth %d exceeds the cone-pass stack; use cone = 0", scene->stats.max_depth);
         return fail(VLS_ERR_UNSUPPORTED, b);

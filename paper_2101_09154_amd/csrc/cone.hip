@@ -497,9 +497,13 @@ hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& p
     const int block = 64 * cfg.block_waves;
     unsigned grid = (unsigned)((count + block - 1) / block);
     // the cone pass keeps its own ring depth: a four-wide visit can push three
-    // entries, and 16 entries per lane still fit 4 wavefronts per SIMD
-    size_t lds = sizeof(int2) * (size_t)kConeRing * block;
-    int mask = kConeRing - 1;
+    // entries.  With cover tests the walks stop behind covering triangles and
+    // stay shallow, and 8 entries per lane leave LDS for more wavefronts (ALS
+    // workload 0.72 -> 0.69 ms); without them (deep canopy walks) 8 entries
+    // spill to scratch too often (vegetation 5.5 -> 6.0 ms), so they keep 16
+    const int ring = cover ? kConeRingCover : kConeRing;
+    size_t lds = sizeof(int2) * (size_t)ring * block;
+    int mask = ring - 1;
 #define VLS_CONE_LAUNCH(COUNT, COVER)                                                                          \
     hipLaunchKernelGGL((k_cone<COUNT, COVER>), dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, \
                        first, count, mask, counts, ovf_list, ovf_ctr, basis_out, cap)

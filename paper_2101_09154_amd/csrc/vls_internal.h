@@ -17,6 +17,7 @@ constexpr int kCandMax = 255;            // candidate leaves kept per pulse by t
 static_assert(kCandMax >= kWave, "a packet walk writes one leaf per subray into the row");
 constexpr int kEmpty4 = 0x7fffffff;       // unused slot of a four-wide record
 constexpr int kConeRing = 16;            // LDS stack entries per lane of the cone pass
+constexpr int kConeRingCover = 8;        // the same with cover tests (walks culled behind a cover stay shallow)
 constexpr int kWalked = -2;              // count word kWalked: the row holds one leaf per subray
 constexpr int kPacketCap = 128;          // stack entries of a packet walk (3 per four-wide level)
 
