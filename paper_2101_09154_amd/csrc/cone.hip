@@ -185,6 +185,29 @@ __device__ __forceinline__ float cover_distance(const Cone& c, const float4* __r
     return (fabsf(tn) + Et) / dmin * (1.0f + 0x1p-20f);
 }
 
+// A stack entry of the cone walk: the node and, with cover tests, its entry
+// distance (an entry pushed before a cull distance was known is dropped when
+// popped beyond it).  Without cover tests the cull distance stays infinite, so
+// the node alone is kept: half the LDS per entry, more wavefronts per CU.
+template <bool COVER>
+struct ConeEnt;
+template <>
+struct ConeEnt<true> {
+    using T = int2;
+    static __device__ __forceinline__ T make(int node, float t) { return make_int2(node, __float_as_int(t)); }
+    static __device__ __forceinline__ T none() { return make_int2(-1, 0); }
+    static __device__ __forceinline__ int node(T e) { return e.x; }
+    static __device__ __forceinline__ bool live(T e, float tcull) { return __int_as_float(e.y) <= tcull; }
+};
+template <>
+struct ConeEnt<false> {
+    using T = int;
+    static __device__ __forceinline__ T make(int node, float) { return node; }
+    static __device__ __forceinline__ T none() { return -1; }
+    static __device__ __forceinline__ int node(T e) { return e; }
+    static __device__ __forceinline__ bool live(T, float) { return true; }
+};
+
 // One lane's cone traversal: writes the candidate leaves to out[e0..] and
 // returns their count (-1: more than cap, or a corrupted structure).  out is
 // 16-byte aligned; entries below e0 (a row's count) are left to the caller.
@@ -197,7 +220,7 @@ __device__ __forceinline__ float cover_distance(const Cone& c, const float4* __r
 // list still holds every leaf the cone reaches before the cull that applies.
 template <bool COUNT, int MA, bool COVER = true>
 __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, int* __restrict__ out, int e0, int cap,
-                                         int2* my, int ring_mask, int& visits)
+                                         typename ConeEnt<COVER>::T* my, int ring_mask, int& visits)
 {
     int n = 0;
     int b0 = 0, b1 = 0, b2 = 0, b3 = 0;  // the row's current group of four entries
@@ -205,7 +228,8 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
     const int stride = blockDim.x;
     // stack entries carry their entry distance, so nodes pushed before a cull
     // distance was known are dropped when popped
-    int2 spill[kMaxSpill];
+    using E = ConeEnt<COVER>;
+    typename E::T spill[kMaxSpill];
     int sp = 0, nlow = 0;
     int node = scene.root;
     const int n_int = scene.n_tri - 1;
@@ -246,7 +270,7 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
                             if (nlow < kMaxSpill) spill[nlow] = my[(nlow & ring_mask) * stride];
                             ++nlow;
                         }
-                        my[(sp & ring_mask) * stride] = make_int2(r[q], __float_as_int(t[q]));
+                        my[(sp & ring_mask) * stride] = E::make(r[q], t[q]);
                         ++sp;
                     }
                 }
@@ -272,15 +296,15 @@ __device__ __forceinline__ int cone_walk(const SceneDev& scene, const Cone& c, i
                 busy = false;
                 while (sp > 0) {
                     --sp;
-                    int2 e;
+                    typename E::T e;
                     if (sp < nlow) {
-                        e = sp < kMaxSpill ? spill[sp] : make_int2(-1, 0);
+                        e = sp < kMaxSpill ? spill[sp] : E::none();
                         nlow = sp;
                     } else {
                         e = my[(sp & ring_mask) * stride];
                     }
-                    if (__int_as_float(e.y) <= tcull) {
-                        node = e.x;
+                    if (E::live(e, tcull)) {
+                        node = E::node(e);
                         busy = true;
                         break;
                     }
@@ -337,7 +361,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const bool ok = bok && scene.n_tri > 0 && setup_cone(pulses.origins + 3 * p, B, tana, scene.bounds[12], c);
     int n = 0;
     int* out = cand + p * (kCandMax + 1);
-    int2* my = reinterpret_cast<int2*>(smem) + threadIdx.x;
+    auto* my = reinterpret_cast<typename ConeEnt<COVER>::T*>(smem) + threadIdx.x;
     // the cheaper slab test serves every axis no lane of the wavefront has with
     // slopes of both signs: none, only x or only y (scan lines along an axis),
     // else all three take the mixed form
@@ -392,7 +416,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     extern __shared__ __align__(16) unsigned char smem[];
     const long long n_ovf = (long long)__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const long long stride = (long long)gridDim.x * blockDim.x;
-    int2* my = reinterpret_cast<int2*>(smem) + threadIdx.x;
+    auto* my = reinterpret_cast<typename ConeEnt<COVER>::T*>(smem) + threadIdx.x;
     const long long start = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     // every lane of a wavefront takes the same number of turns (the ballot
     // below needs the whole wavefront)
@@ -478,7 +502,7 @@ hipError_t launch_cone_long(const SceneDev& scene, double tan_max, const PulsesD
     const int block = kWave;
     const long long rows = long_rows(n);
     const unsigned grid = (unsigned)((rows + block - 1) / block);
-    const size_t lds = sizeof(int2) * (size_t)kConeRing * block;
+    const size_t lds = sizeof(ConeEnt<false>::T) * (size_t)kConeRing * block;
     (void)cfg;
     hipLaunchKernelGGL(k_cone_long<false>, dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, list,
                        ctr, rows, longw, list2, ctr2, kConeRing - 1);
@@ -502,7 +526,7 @@ hipError_t launch_cone(const SceneDev& scene, double tan_max, const PulsesDev& p
     // workload 0.72 -> 0.69 ms); without them (deep canopy walks) 8 entries
     // spill to scratch too often (vegetation 5.5 -> 6.0 ms), so they keep 16
     const int ring = cover ? kConeRingCover : kConeRing;
-    size_t lds = sizeof(int2) * (size_t)ring * block;
+    size_t lds = (cover ? sizeof(ConeEnt<true>::T) : sizeof(ConeEnt<false>::T)) * (size_t)ring * block;
     int mask = ring - 1;
 #define VLS_CONE_LAUNCH(COUNT, COVER)                                                                          \
     hipLaunchKernelGGL((k_cone<COUNT, COVER>), dim3(grid), dim3(block), lds, stream, scene, tan_max, pulses, cand, \
