@@ -490,7 +490,7 @@ def main():
                     help="only run a plain device copy of MIB MiB (three times), to scale HBM counters")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
                     help="autotuner cache (JSON lines); '' tunes every workload afresh")
-    ap.add_argument("--leg", choices=["uls_trees", "small_tls"], default=None,
+    ap.add_argument("--leg", choices=["uls_trees", "small_tls", "batched_tls", "uls_voxels"], default=None,
                     help="only run this workload's leg and print its record (for profiling)")
     args = ap.parse_args()
     args.tune_cache = args.tune_cache or None
@@ -514,10 +514,20 @@ def main():
 
     if args.leg:
         ctx = vp.Context(0)
-        if not args.no_tune:
-            log("autotune (%s)" % args.leg)
-        print(json.dumps(run_leg(ctx, args.leg, args.steps, tune=not args.no_tune, tune_cache=args.tune_cache)),
-              flush=True)
+        if args.leg == "batched_tls":
+            # the 256 positions on the als_buildings scene, launch from the cache
+            log("batched workload")
+            mesh, _, _ = configs.als_buildings()
+            scene = ctx.scene(mesh.vertices, mesh.triangles, mesh.reflectance)
+            rec = bench_batched(ctx, scene, mesh, args.steps, tune_cache=args.tune_cache)
+        elif args.leg == "uls_voxels":
+            log("voxel workload")
+            rec = bench_voxels(ctx, args.steps, tune_cache=args.tune_cache)
+        else:
+            if not args.no_tune:
+                log("autotune (%s)" % args.leg)
+            rec = run_leg(ctx, args.leg, args.steps, tune=not args.no_tune, tune_cache=args.tune_cache)
+        print(json.dumps(rec), flush=True)
         return
     log("generating scene and pulses")
     mesh, pulses, sc = configs.als_buildings()
