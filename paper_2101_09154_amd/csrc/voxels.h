@@ -18,7 +18,10 @@
 //               reaches the limit (the closest triangle): consecutive
 //               intersections along one ray (Sec. 5.1), without an epsilon step.
 // All arithmetic in FP64 with contraction off, so every boundary decision is
-// rounded as written.
+// rounded as written.  The stop test s <= L equals u >= exp(-sigma L); an FP32
+// estimate of that exponential settles, without the FP64 log and divide, the
+// voxels whose draw lies clearly below it (no stop); every other voxel, every
+// stop among them, takes the FP64 test as written.
 #pragma once
 
 #include "device_common.h"
@@ -116,6 +119,9 @@ __device__ __forceinline__ long long voxel_stop(const VoxDev& v, const double* O
     VoxAxis Z = vox_axis(O[2], D[2], t_in, v.origin[2], s, v.nz);
     const double g = vox_lut(v, D[2]);
     const long long plane = (long long)v.nx * v.ny;
+    // the cell's index, moved by one cell along the axis of each step
+    long long vi = (long long)X.i + (long long)v.nx * Y.i + plane * Z.i;
+    const long long dx = X.step, dy = (long long)Y.step * v.nx, dz = (long long)Z.step * plane;
     double t = t_in;
     const int max_steps = v.nx + v.ny + v.nz + 1;
     for (int it = 0; it < max_steps && t < t_out; ++it) {
@@ -124,14 +130,26 @@ __device__ __forceinline__ long long voxel_stop(const VoxDev& v, const double* O
         const double tb = ax == 0 ? X.tmax : (ax == 1 ? Y.tmax : Z.tmax);
         double t_exit = tb < t_out ? tb : t_out;
         if (t_exit < t) t_exit = t;
-        const long long vi = (long long)X.i + (long long)v.nx * Y.i + plane * Z.i;
-        const double sg = (double)v.pad[vi] * g;
+        const float pd = v.pad[vi];
+        const double sg = pd > 0.0f ? (double)pd * g : 0.0;
         if (sg > 0.0) {
-            const double sd = -log(sm_uniform(v.seed, c0 + (uint64_t)vi)) / sg;
-            if (sd <= t_exit - t) {
-                t_hit = t + sd;
-                sigma = sg;
-                return vi;
+            const double u = sm_uniform(v.seed, c0 + (uint64_t)vi);
+            // y = 2^(-x log2 e) for x = sigma L <= 64: rounding the exponent to
+            // FP32 (at most 92.4 in magnitude, so y stays normal) and the 1-ulp
+            // v_exp_f32 keep y within a factor 1 +- 2^-17 of exp(-x); then
+            // u < y (1 - 2^-12) gives -ln u > x + 2^-13, and the FP64 s (log and
+            // divide within 2^-50 relative) exceeds L for any x below 2^36.
+            const double x = sg * (t_exit - t);
+            const bool below = x <= 64.0 &&
+                               u < (double)__builtin_amdgcn_exp2f((float)(x * -1.4426950408889634)) *
+                                       (1.0 - 0x1p-12);
+            if (!below) {
+                const double sd = -log(u) / sg;
+                if (sd <= t_exit - t) {
+                    t_hit = t + sd;
+                    sigma = sg;
+                    return vi;
+                }
             }
         }
         t = t_exit;
@@ -139,14 +157,17 @@ __device__ __forceinline__ long long voxel_stop(const VoxDev& v, const double* O
             X.i += X.step;
             if (X.i < 0 || X.i >= v.nx) break;
             X.tmax += X.tdel;
+            vi += dx;
         } else if (ax == 1) {
             Y.i += Y.step;
             if (Y.i < 0 || Y.i >= v.ny) break;
             Y.tmax += Y.tdel;
+            vi += dy;
         } else {
             Z.i += Z.step;
             if (Z.i < 0 || Z.i >= v.nz) break;
             Z.tmax += Z.tdel;
+            vi += dz;
         }
     }
     return -1;
