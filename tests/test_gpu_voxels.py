@@ -97,6 +97,22 @@ def test_voxel_slab_matches_oracle(ctx):
     assert (out["subray_tri"][-2:, :19] == -1).all()
 
 
+def test_voxel_densities_over_seven_decades(ctx):
+    """The slab with densities from 1e-4 to 1e3 per metre: sigma L from far
+    below 1 (the FP32 pre-test of the draw rejects nearly every cell) to far
+    above 64 (beyond its range: the FP64 test alone), on the same pulses."""
+    mesh, vox, pulses = _slab_case(seed=5)
+    rng = np.random.default_rng(5)
+    pad = (10.0 ** rng.uniform(-4.0, 3.0, vox["pad"].shape)).astype(np.float32)
+    pad[vox["pad"] == 0.0] = 0.0
+    vox = dict(vox, pad=pad)
+    scene = _scene(ctx, mesh, vox)
+    say("voxel slab, densities 1e-4..1e3: pulses", pulses.n)
+    out = to_np(ctx.simulate(scene, SLAB_SC, _dev(pulses.origins), _dev(pulses.directions)))
+    torch.cuda.synchronize()
+    compare_vox(mesh, vox, pulses, SLAB_SC, out, np.arange(pulses.n), "voxel slab decades", min_voxel_frac=0.3)
+
+
 def test_voxels_without_triangles(ctx):
     mesh, vox, pulses = _slab_case(seed=4)
     empty = synth.Mesh(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32), np.zeros(0, np.float32))
